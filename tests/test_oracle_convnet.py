@@ -1,0 +1,65 @@
+"""Pins of the FP64 network oracle: convolution vs scipy's correlate2d, gradients vs central
+finite differences, Adam vs its first-step closed form."""
+import numpy as np
+from scipy import signal
+
+from oracle import convnet as cn
+
+
+def test_conv3x3_matches_scipy_correlate():
+    rng = np.random.default_rng(0)
+    B, C, O, H, W = 2, 3, 4, 7, 9
+    x = rng.standard_normal((B, C, H, W))
+    Wt = rng.standard_normal((O, C, 3, 3))
+    b = rng.standard_normal(O)
+    y = cn.conv3x3(x, Wt, b)
+    for bb in range(B):
+        for o in range(O):
+            ref = b[o] + sum(signal.correlate2d(x[bb, c], Wt[o, c], mode="same", boundary="fill")
+                             for c in range(C))
+            assert np.abs(y[bb, o] - ref).max() < 1e-13
+
+
+def test_net_gradients_finite_differences():
+    rng = np.random.default_rng(1)
+    B, C, Hd, H, W = 2, 2, 3, 6, 5
+    params = [(0.4 * rng.standard_normal((Hd, C, 3, 3)), 0.1 * rng.standard_normal(Hd)),
+              (0.4 * rng.standard_normal((Hd, Hd, 3, 3)), 0.1 * rng.standard_normal(Hd)),
+              (0.4 * rng.standard_normal((C, Hd, 3, 3)), 0.1 * rng.standard_normal(C))]
+    r = rng.standard_normal((B, C, H, W))
+    e = rng.standard_normal((B, C, H, W))
+    loss, grads = cn.pc_loss(r, e, params)
+    eps = 1e-6
+    for li in range(3):
+        for which in (0, 1):
+            arr = params[li][which]
+            flat = arr.reshape(-1)
+            for idx in rng.choice(flat.size, size=min(6, flat.size), replace=False):
+                old = flat[idx]
+                flat[idx] = old + eps
+                lp, _ = cn.pc_loss(r, e, params)
+                flat[idx] = old - eps
+                lm, _ = cn.pc_loss(r, e, params)
+                flat[idx] = old
+                fd = (lp - lm) / (2 * eps)
+                an = grads[li][which].reshape(-1)[idx]
+                assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd))
+    # input gradient
+    out, cache = cn.net_forward(r, params)
+    g = rng.standard_normal(out.shape)
+    _, gx = cn.net_backward(g, params, cache)
+    for _ in range(5):
+        idx = tuple(rng.integers(0, s) for s in r.shape)
+        rp = r.copy(); rp[idx] += eps
+        rm = r.copy(); rm[idx] -= eps
+        fd = (np.sum(g * cn.net_forward(rp, params)[0]) - np.sum(g * cn.net_forward(rm, params)[0])) / (2 * eps)
+        assert abs(fd - gx[idx]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_adam_first_step_is_signed_lr():
+    """After one bias-corrected step, Adam moves each weight by lr * g/(|g| + eps)."""
+    rng = np.random.default_rng(2)
+    p = rng.standard_normal(10)
+    g = rng.standard_normal(10)
+    p1, m, v = cn.adam_step(p, g, np.zeros(10), np.zeros(10), 1, lr=1e-2)
+    assert np.abs((p - p1) - 1e-2 * g / (np.abs(g) + 1e-8)).max() < 1e-12
