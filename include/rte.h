@@ -1,0 +1,169 @@
+/*
+ * rte.h -- C ABI of the MI355X (gfx950) solver for the steady-state radiative transfer equation
+ * in a homogeneous medium, in the angularly reduced Fredholm form of Fan, An and Ying,
+ * "Fast algorithms for integral formulations of steady-state radiative transfer equation".
+ *
+ * The discrete problem (Sec. 3.3, eq. ani_discretization and eq. ani_AU; the isotropic u-form
+ * of eq. iso_Fredholm discretised per Sec. 2.3) is
+ *
+ *     A u = (I - K~ D) u = K~ g,      g_{j,k} = f(x_j) delta_{k0},   D = diag_k(mu_s sigma_hat_k)
+ *
+ * on the cell centres x_j of a uniform grid of square (cubic) cells of side h.  K~ couples output
+ * mode k at x_i to input mode k' at x_j by h^d kappa(|x_i-x_j|) exp(i (k'-k) theta_ij), with
+ * kappa(r) = exp(-mu_t r)/(2 pi r) in 2D and exp(-mu_t r)/(4 pi r^2) in 3D and theta_ij the polar
+ * angle of x_i - x_j (eq. ani_2d_operator); the diagonal entry is the exact cell integral of the
+ * singular kernel (Sec. 2.3, "the integral of K~ at the i-th cell").  The operator is applied by
+ * zero-padded FFT convolution (Sec. 2.3.1 and 3.3.1) and the system is solved by GMRES.
+ *
+ * Conventions shared by every entry point
+ *   - All arrays are device pointers (hipMalloc'd or torch CUDA tensors) owned by the caller and
+ *     borrowed for the duration of the call; all work is enqueued on the context's stream.
+ *   - Grids: 2D arrays are [ny][nx] (x fastest), 3D arrays [nz][ny][nx].
+ *   - RTE_LAYOUT_MODES: complex128 (interleaved re,im doubles) [M][ny][nx], mode k = -L..L at
+ *     index k+L (M = 2L+1).  Any complex vector is accepted.  3D: M = 1, [1][nz][ny][nx].
+ *   - RTE_LAYOUT_CHANNELS: real float64 [C][ny][nx], C = 2L+1, the image of a real angular flux
+ *     (u_{-k} = conj u_k): channel 0 = Re u_0, channel 2k-1 = sqrt(2) Re u_k,
+ *     channel 2k = sqrt(2) Im u_k (k = 1..L).  With the sqrt(2) the Euclidean norm of the channel
+ *     vector equals the norm of the full mode vector.  3D: C = 1, [nz][ny][nx].
+ *   - Status: every int-returning function returns RTE_OK (0) on success, a positive value for a
+ *     completed call with a caveat, a negative value on error; it never throws or aborts.
+ *     rte_last_error() gives a thread-local message for the last non-OK status.
+ */
+#ifndef RTE_H
+#define RTE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rte_ctx rte_ctx;
+
+typedef struct {
+    int dim;        /* 2 or 3 */
+    int n[3];       /* cells along x, y, z (n[2] ignored in 2D); each >= 2 */
+    double h;       /* cell side > 0; the domain is [0, n_x h] x [0, n_y h] (x [0, n_z h]) */
+} rte_grid;
+
+enum {
+    RTE_OK = 0,
+    RTE_NOT_CONVERGED = 1,   /* solve stopped at max_iter / max_cycles; output holds best iterate */
+    RTE_EINVAL = -1,         /* bad argument; nothing was enqueued */
+    RTE_ENOMEM = -2,         /* device allocation failed */
+    RTE_EDEVICE = -3,        /* HIP runtime error */
+    RTE_ENUMERIC = -4,       /* NaN or Inf in the residual */
+    RTE_EUNSUPPORTED = -5    /* valid request outside what this build implements */
+};
+
+enum { RTE_PREC_FP32 = 0,    /* FFT apply in FP32/complex64 (FP32 accumulation); Krylov in FP64 */
+       RTE_PREC_FP64 = 1 };  /* everything in FP64 */
+
+enum { RTE_OP_A = 0,         /* y = x - K~ D x        (eq. ani_AU) */
+       RTE_OP_KT = 1 };      /* y = K~ x              (step T.1 when x = g) */
+
+enum { RTE_LAYOUT_MODES = 0, RTE_LAYOUT_CHANNELS = 1 };
+
+typedef struct {
+    int iterations;      /* inner (F)GMRES iterations, all cycles */
+    int applies;         /* operator applies, all precisions */
+    int cycles;          /* refinement cycles (true-residual checks) */
+    int pc_used;         /* 1 if the attached preconditioner was used */
+    int pc_fallback;     /* 1 if the solve fell back to plain GMRES */
+    double relres_est;   /* last Arnoldi estimate of the relative residual */
+    double relres_true;  /* ||b - A x|| / ||b|| with the FP64 apply, at exit */
+    double t_setup_ms;   /* time of rte_setup for this context */
+    double t_solve_ms;   /* wall time of this solve */
+} rte_solve_info;
+
+typedef struct {
+    int restart;         /* Krylov dimension per cycle, 1..RTE_MAX_RESTART (default 64) */
+    int max_cycles;      /* refinement cycles (default 8) */
+    double inner_tol;    /* per-cycle relative reduction for the FP32 inner solve (default 1e-5;
+                            ignored for RTE_PREC_FP64, whose cycles run to the requested tol) */
+    int always_reorth;   /* 0: classical Gram-Schmidt with a second pass only when the norm drops
+                            below 1/sqrt(2) of its value (default); 1: always two passes */
+    int use_pc;          /* 1: flexible GMRES with the attached preconditioner (default 1 if one
+                            is attached) */
+} rte_solve_opts;
+
+#define RTE_MAX_L 8
+#define RTE_MAX_RESTART 128
+
+/* Create a context: validates the problem, allocates the device state and precomputes the
+ * kernel spectra in FP64 on the device (the T_pre step of Sec. 2.4).
+ *   g          grid (2D: any n_x, n_y in [2, 512]; 3D: n in [2, 256], L must be 0)
+ *   mu_a, mu_s absorption and scattering coefficients, >= 0, mu_a + mu_s > 0 (assumption C2)
+ *   sigma_hat  host array of L+1 real Fourier coefficients of the phase function (Sec. 3.1.1,
+ *              eq. ani_Fouriermode; sigma_hat_{-k} = sigma_hat_k), sigma_hat[0] == 1 (C3) and
+ *              |sigma_hat[k]| <= 1; may be NULL when L == 0
+ *   L          number of retained modes on each side, 0..RTE_MAX_L (M = 2L+1)
+ *   prec       RTE_PREC_FP32 or RTE_PREC_FP64
+ *   hip_stream hipStream_t to enqueue on (NULL = default stream)
+ * Errors: RTE_EINVAL (before any device work), RTE_EUNSUPPORTED (3D with L > 0, oversize grid),
+ * RTE_ENOMEM, RTE_EDEVICE.  On error *out is NULL. */
+int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s,
+              const double* sigma_hat, int L, int prec, void* hip_stream);
+
+/* y = op(x) in the given layout.  prec selects the apply precision: RTE_PREC_FP64 is always
+ * available; RTE_PREC_FP32 needs a context created with RTE_PREC_FP32.  x and y are FP64
+ * (complex128 or float64 per layout) and may not alias.  Asynchronous on the context stream. */
+int rte_apply(rte_ctx* ctx, int op, int layout, int prec, const void* x_dev, void* y_dev);
+
+/* b = K~ g for g = f delta_{k0} (step T.1).  f_dev: float64 [ny][nx] ([nz][ny][nx]);
+ * b_dev: FP64 in the given layout.  Uses the FP64 apply.  Asynchronous. */
+int rte_rhs(rte_ctx* ctx, const double* f_dev, int layout, void* b_dev);
+
+/* Replace the solver options (NULL restores the defaults). */
+int rte_set_solve_opts(rte_ctx* ctx, const rte_solve_opts* opts);
+
+/* Solve A u = K~ g to ||b - A u||_2 / ||b||_2 <= tol (true residual, FP64 apply) with
+ * GMRES from u = 0, FP32 or FP64 inner applies per the context precision and FP64
+ * iterative refinement.  f_dev: float64 source at the cell centres; u_dev: complex128 modes
+ * (RTE_LAYOUT_MODES).  max_iter bounds the total inner iterations.  Synchronises the stream.
+ * Returns RTE_OK, RTE_NOT_CONVERGED (u holds the best iterate), RTE_ENUMERIC or an error.
+ * f = 0 gives u = 0 and RTE_OK.  info may be NULL. */
+int rte_solve(rte_ctx* ctx, const double* f_dev, double tol, int max_iter, void* u_dev,
+              rte_solve_info* info);
+
+/* Solve A x = b for a right-hand side b given in RTE_LAYOUT_CHANNELS (float64), x in the same
+ * layout.  If x_iterates is not NULL, the first inner cycle's iterates are recorded there
+ * (x_iterates[j] = the iterate after j+1 inner iterations, up to max_record vectors of the
+ * channel size) for generating preconditioner training pairs; *n_recorded gets their count. */
+int rte_solve_rhs(rte_ctx* ctx, const double* b_dev, double tol, int max_iter, double* x_dev,
+                  rte_solve_info* info, double* x_iterates, int max_record, int* n_recorded);
+
+/* Solve `count` independent problems (contexts may differ in grid and coefficients; all must be
+ * 2D isotropic (L = 0) contexts created on the same device and stream).  All problems advance
+ * together: every pass is one launch over the tiles of all unconverged problems, and one inner
+ * iteration is captured once into a HIP graph and replayed.  f_dev[i], u_dev[i] as in rte_solve;
+ * tol[i] per problem; infos may be NULL.  Returns RTE_OK if all converged, RTE_NOT_CONVERGED if
+ * some did not, or an error. */
+int rte_solve_batched(int count, rte_ctx* const* ctxs, const double* const* f_dev,
+                      const double* tol, int max_iter, void* const* u_dev, rte_solve_info* infos);
+
+/* Attach a learned right preconditioner z = v + ||v|| N(v / ||v||) for flexible GMRES.
+ * weights_dev: float32 parameters of `layers` 3x3 convolutions packed as
+ * [W0 (hidden x C x 3 x 3), b0 (hidden), W1 (hidden x hidden x 3 x 3), b1, ..., W_last
+ * (C x hidden x 3 x 3), b_last] with C = 2L+1 channels; ReLU after every layer but the last.
+ * The context keeps a BF16 copy of the weights.  NULL detaches.  2D contexts only. */
+int rte_pc_attach(rte_ctx* ctx, const float* weights_dev, int hidden, int layers);
+
+/* Time `reps` back-to-back applies (op, RTE_LAYOUT_CHANNELS, prec) on the context stream with
+ * HIP events.  ms_total: whole apply; ms_pass[0..4]: per kernel of the apply (2D: passes A, B, C;
+ * 3D: five passes; unused entries 0).  Input/output are internal buffers. */
+int rte_time_apply(rte_ctx* ctx, int op, int prec, int reps, double* ms_total, double* ms_pass);
+
+/* Sizes: *channels = 2L+1 (3D: 1), *modes = 2L+1, *cells = n_x n_y (n_z). */
+int rte_query(const rte_ctx* ctx, int* channels, int* modes, long long* cells);
+
+/* Pack complex modes (must be conjugate-symmetric) into channels, and back. FP64, asynchronous. */
+int rte_modes_to_channels(rte_ctx* ctx, const void* modes_dev, double* channels_dev);
+int rte_channels_to_modes(rte_ctx* ctx, const double* channels_dev, void* modes_dev);
+
+void rte_destroy(rte_ctx* ctx);
+const char* rte_last_error(void);
+const char* rte_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTE_H */

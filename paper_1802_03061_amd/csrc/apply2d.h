@@ -1,0 +1,40 @@
+// Host-side interface of the 2D FFT apply kernels.
+#pragma once
+#include "common.h"
+
+namespace rte {
+
+enum { APPLY_A = 0, APPLY_KT = 1, APPLY_RESID = 2 };
+
+struct ChanScale {
+    double s[2 * 8 + 1];   // per-channel factor applied in pass A (D for operator A, 1 for K~)
+};
+
+template <typename T>
+struct Apply2DArgs {
+    int nx, ny, PX, PY, L, C;
+    cx<T>* work;               // work buffer [nbatch][C][PX/2+1][ny]
+    cx<T>* work2;              // split pass B only: [nbatch][C][PX/2+1][PY] (may be null otherwise)
+    const cx<T>* Q;            // quarter spectra [2L+1][PX/2+1][PY/2+1], scaled by 1/(PX PY)
+    const cx<T>* twx;          // exp(-2 pi i q/PX), q < PX
+    const cx<T>* twy;          // exp(-2 pi i q/PY), q < PY
+    hipStream_t stream;
+};
+
+// y = x - K~ D x (APPLY_A), K~ x (APPLY_KT) or b - (x - K~ D x) (APPLY_RESID) on nbatch channel
+// vectors [nbatch][C][ny][nx] of float64, computed with FFTs in precision T.
+template <typename T>
+int apply2d(const Apply2DArgs<T>& a, const double* x, const double* b, double* y, int mode,
+            const ChanScale& sc, int nbatch);
+template <typename T>
+int apply2d_pass_a(const Apply2DArgs<T>& a, const double* x, const ChanScale& sc, int nbatch);
+template <typename T>
+int apply2d_pass_b(const Apply2DArgs<T>& a, int nbatch);
+// True when pass B for (L, PY) in precision T needs the work2 buffer.
+template <typename T>
+bool apply2d_needs_work2(int L, int PY);
+template <typename T>
+int apply2d_pass_c(const Apply2DArgs<T>& a, const double* x, const double* b, double* y, int mode,
+                   int nbatch);
+
+}  // namespace rte

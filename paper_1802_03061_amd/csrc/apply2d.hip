@@ -1,0 +1,210 @@
+// 2D FFT apply of the angularly reduced operator (Sec. 3.3.1, "Homogeneous media and FFT-based
+// algorithm"; isotropic: Sec. 2.3.1).
+//
+// The kernel of K~ depends only on x_i - x_j and on k' - k, so K~ w is, per output mode k, a sum
+// over input modes k' of 2D convolutions with K_{k'-k}.  Zero-padding each field to a
+// PY x PX periodic grid (P >= 2n - 1) makes every convolution circulant and
+//     FFT(K~ w)_k(xi) = sum_{k'} Khat_{k'-k}(xi) FFT(w_{k'})(xi),
+// a (2L+1)x(2L+1) Toeplitz-in-mode product per frequency.
+//
+// Data are kept as real channels of a real angular flux (u_{-k} = conj u_k): channel 0 = u_0,
+// channel 2k-1 = sqrt2 Re u_k, channel 2k = sqrt2 Im u_k.  Real fields let the x-transform be a
+// real-to-complex FFT (frequencies 0..PX/2 only), which halves the work and traffic of the complex
+// mode form; the complex modes are recombined per frequency inside pass B.
+//
+//   pass A  per (channel, tile of TR rows): scale by the channel's D entry, zero-pad to PX, FFT
+//           along x (two real rows per complex FFT), store transposed T[c][kx][y]
+//   pass B  per column kx: FFT along y for every channel (zero-padded to PY), couple the modes at
+//           every frequency with the kernel spectra, inverse FFT along y, store back in place
+//   pass C  per (channel, tile of rows): inverse FFT along x (complex-to-real), crop to nx, and
+//           finalise y = x - v (operator A), y = v (K~), or y = b - x + v (residual)
+//
+// The kernel spectra are read from a quarter table Q[m][kx][ky], m = 0..2L, kx <= PX/2,
+// ky <= PY/2, using Khat_m(kx, -ky) = (-1)^m conj Khat_m(kx, ky) (mirror symmetry of the square
+// grid) and Khat_{-m} = (-1)^m conj Khat_m; the 1/(PX PY) of the inverse FFT is folded into Q.
+#include "apply2d.h"
+#include "apply2d_b.h"
+#include "fft.h"
+
+namespace rte {
+
+// ---------------------------------------------------------------------------- pass A --------
+template <typename T, int PX, int TR, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_pass_a(const double* __restrict__ x, cx<T>* __restrict__ Tb,
+                                                 const cx<T>* __restrict__ tw, int nx, int ny, int C,
+                                                 ChanScale sc) {
+    constexpr int NP = TR / 2;        // complex FFTs per block (two real rows each)
+    constexpr int LD = PX;
+    constexpr int NK = PX / 2 + 1;    // stored x-frequencies
+    __shared__ cx<T> buf[NP * LD];
+    const int tid = threadIdx.x;
+    const int bc = blockIdx.y;
+    const int c = bc % C;
+    const int y0 = blockIdx.x * TR;
+    const T s = (T)sc.s[c];
+    const double* xin = x + (size_t)bc * ny * nx;
+    for (int idx = tid; idx < NP * PX; idx += NTHR) {
+        const int p = idx / PX, m = idx % PX;
+        const int ya = y0 + 2 * p, yb = ya + 1;
+        T re = 0, im = 0;
+        if (m < nx) {
+            if (ya < ny) re = s * (T)xin[(size_t)ya * nx + m];
+            if (yb < ny) im = s * (T)xin[(size_t)yb * nx + m];
+        }
+        buf[p * LD + m] = mk(re, im);
+    }
+    __syncthreads();
+    block_fft<T, PX, NP, LD, NTHR, false>(buf, tw, tid);
+    cx<T>* out = Tb + (size_t)bc * NK * ny;
+    for (int idx = tid; idx < NK * TR; idx += NTHR) {
+        const int yl = idx % TR, k = idx / TR;
+        const int y = y0 + yl;
+        if (y < ny) {
+            const int p = yl >> 1;
+            const cx<T> z = buf[p * LD + k];
+            const cx<T> zc = conj(buf[p * LD + ((PX - k) & (PX - 1))]);
+            // X_a = (Z + conj Z(-k))/2,  X_b = (Z - conj Z(-k))/(2i)
+            const cx<T> X = (yl & 1) ? scale(mul_mi(z - zc), (T)0.5) : scale(z + zc, (T)0.5);
+            out[(size_t)k * ny + y] = X;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------- pass C --------
+template <typename T, int PX, int TR, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_pass_c(const cx<T>* __restrict__ Tb, const double* __restrict__ xin,
+                                                 const double* __restrict__ bin, double* __restrict__ yout,
+                                                 const cx<T>* __restrict__ tw, int nx, int ny, int mode) {
+    constexpr int NP = TR / 2;
+    constexpr int LD = PX;
+    constexpr int NK = PX / 2 + 1;
+    __shared__ cx<T> buf[NP * LD];
+    const int tid = threadIdx.x;
+    const int bc = blockIdx.y;
+    const int y0 = blockIdx.x * TR;
+    const cx<T>* src = Tb + (size_t)bc * NK * ny;
+    for (int idx = tid; idx < NK * NP; idx += NTHR) {
+        const int p = idx % NP, k = idx / NP;
+        const int ya = y0 + 2 * p, yb = ya + 1;
+        cx<T> Xa = ya < ny ? src[(size_t)k * ny + ya] : mk((T)0, (T)0);
+        cx<T> Xb = yb < ny ? src[(size_t)k * ny + yb] : mk((T)0, (T)0);
+        if (k == 0 || k == PX / 2) { Xa.im = 0; Xb.im = 0; }
+        buf[p * LD + k] = Xa + mul_i(Xb);
+        if (k > 0 && k < PX / 2) buf[p * LD + PX - k] = conj(Xa) + mul_i(conj(Xb));
+    }
+    __syncthreads();
+    block_fft<T, PX, NP, LD, NTHR, true>(buf, tw, tid);
+    const size_t base = (size_t)bc * ny * nx;
+    for (int idx = tid; idx < TR * nx; idx += NTHR) {
+        const int yl = idx / nx, m = idx % nx;
+        const int y = y0 + yl;
+        if (y < ny) {
+            const cx<T> z = buf[(yl >> 1) * LD + m];
+            const double v = (double)((yl & 1) ? z.im : z.re);
+            const size_t o = base + (size_t)y * nx + m;
+            double r;
+            if (mode == APPLY_A) r = xin[o] - v;
+            else if (mode == APPLY_KT) r = v;
+            else r = bin[o] - xin[o] + v;       // APPLY_RESID: b - A x
+            yout[o] = r;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------- dispatch -------
+template <typename T> constexpr int tile_rows() { return sizeof(T) == 4 ? 16 : 8; }
+template <typename T, int PX>
+static void launch_a(const Apply2DArgs<T>& a, const double* x, const ChanScale& sc, int nchan_total) {
+    constexpr int TR = tile_rows<T>();
+    dim3 grid((a.ny + TR - 1) / TR, nchan_total);
+    hipLaunchKernelGGL((k_pass_a<T, PX, TR, 256>), grid, dim3(256), 0, a.stream, x, a.work, a.twx, a.nx,
+                       a.ny, a.C, sc);
+}
+
+template <typename T, int PX>
+static void launch_c(const Apply2DArgs<T>& a, const double* x, const double* b, double* y, int mode,
+                     int nchan_total) {
+    constexpr int TR = tile_rows<T>();
+    dim3 grid((a.ny + TR - 1) / TR, nchan_total);
+    hipLaunchKernelGGL((k_pass_c<T, PX, TR, 256>), grid, dim3(256), 0, a.stream, a.work, x, b, y, a.twx,
+                       a.nx, a.ny, mode);
+}
+
+#define RTE_P_SWITCH(P, FN, ...)                  \
+    switch (P) {                                  \
+        case 16: FN<T, 16>(__VA_ARGS__); break;   \
+        case 32: FN<T, 32>(__VA_ARGS__); break;   \
+        case 64: FN<T, 64>(__VA_ARGS__); break;   \
+        case 128: FN<T, 128>(__VA_ARGS__); break; \
+        case 256: FN<T, 256>(__VA_ARGS__); break; \
+        case 512: FN<T, 512>(__VA_ARGS__); break; \
+        case 1024: FN<T, 1024>(__VA_ARGS__); break; \
+        default: return -1;                       \
+    }
+
+template <typename T>
+int apply2d_pass_a(const Apply2DArgs<T>& a, const double* x, const ChanScale& sc, int nbatch) {
+    RTE_P_SWITCH(a.PX, launch_a, a, x, sc, nbatch * a.C);
+    return 0;
+}
+template <typename T>
+int apply2d_pass_b(const Apply2DArgs<T>& a, int nbatch) {
+    switch (a.L) {
+        case 0: return pass_b_L0<T>(a, nbatch);
+        case 1: return pass_b_L1<T>(a, nbatch);
+        case 2: return pass_b_L2<T>(a, nbatch);
+        case 3: return pass_b_L3<T>(a, nbatch);
+        case 4: return pass_b_L4<T>(a, nbatch);
+        case 5: return pass_b_L5<T>(a, nbatch);
+        case 6: return pass_b_L6<T>(a, nbatch);
+        case 7: return pass_b_L7<T>(a, nbatch);
+        case 8: return pass_b_L8<T>(a, nbatch);
+    }
+    return -1;
+}
+template <typename T>
+bool apply2d_needs_work2(int L, int PY) {
+    switch (L) {
+        case 0: return pass_b_split_L0<T>(PY);
+        case 1: return pass_b_split_L1<T>(PY);
+        case 2: return pass_b_split_L2<T>(PY);
+        case 3: return pass_b_split_L3<T>(PY);
+        case 4: return pass_b_split_L4<T>(PY);
+        case 5: return pass_b_split_L5<T>(PY);
+        case 6: return pass_b_split_L6<T>(PY);
+        case 7: return pass_b_split_L7<T>(PY);
+        case 8: return pass_b_split_L8<T>(PY);
+    }
+    return true;
+}
+template bool apply2d_needs_work2<float>(int, int);
+template bool apply2d_needs_work2<double>(int, int);
+template <typename T>
+int apply2d_pass_c(const Apply2DArgs<T>& a, const double* x, const double* b, double* y, int mode,
+                   int nbatch) {
+    RTE_P_SWITCH(a.PX, launch_c, a, x, b, y, mode, nbatch * a.C);
+    return 0;
+}
+
+template <typename T>
+int apply2d(const Apply2DArgs<T>& a, const double* x, const double* b, double* y, int mode,
+            const ChanScale& sc, int nbatch) {
+    if (apply2d_pass_a<T>(a, x, sc, nbatch)) return -1;
+    if (apply2d_pass_b<T>(a, nbatch)) return -1;
+    return apply2d_pass_c<T>(a, x, b, y, mode, nbatch);
+}
+
+template int apply2d<float>(const Apply2DArgs<float>&, const double*, const double*, double*, int,
+                            const ChanScale&, int);
+template int apply2d<double>(const Apply2DArgs<double>&, const double*, const double*, double*, int,
+                             const ChanScale&, int);
+template int apply2d_pass_a<float>(const Apply2DArgs<float>&, const double*, const ChanScale&, int);
+template int apply2d_pass_a<double>(const Apply2DArgs<double>&, const double*, const ChanScale&, int);
+template int apply2d_pass_b<float>(const Apply2DArgs<float>&, int);
+template int apply2d_pass_b<double>(const Apply2DArgs<double>&, int);
+template int apply2d_pass_c<float>(const Apply2DArgs<float>&, const double*, const double*, double*, int,
+                                   int);
+template int apply2d_pass_c<double>(const Apply2DArgs<double>&, const double*, const double*, double*,
+                                    int, int);
+
+}  // namespace rte

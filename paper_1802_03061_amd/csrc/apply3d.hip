@@ -1,0 +1,132 @@
+// 3D isotropic FFT apply (Sec. 2.3.1 with d = 3; the M = {0} case of Sec. 3.1.2).
+//
+// u is one real field [nz][ny][nx]; the kernel h^3 exp(-mu_t r)/(4 pi r^2) has a real, even
+// spectrum, stored as the octant Q3[kx][ky][kz] (scaled by 1/(PX PY PZ)).  Five passes:
+//   A  x-FFT (real-to-complex) of every row, per z-slab, stored T1[z][kx][y]   (2D pass A)
+//   B  y-FFT of every (z, kx) column, stored transposed T2[kx][ky][z]
+//   C  z-FFT of every (kx, ky) column, multiply by the spectrum, inverse z-FFT, in place
+//   D  inverse y-FFT, stored back to T1[z][kx][y]
+//   E  inverse x-FFT (complex-to-real), crop, y = u - mu_s v / v / residual   (2D pass C)
+// Each pass reads and writes HBM in 128-byte runs: B and D move tiles of TZ consecutive z.
+#include "apply3d.h"
+#include "fft.h"
+
+namespace rte {
+
+template <typename T, int PY, int TZ, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_pass3_b(const cx<T>* __restrict__ T1, cx<T>* __restrict__ T2,
+                                                  const cx<T>* __restrict__ tw, int ny, int nz, int nkx) {
+    __shared__ cx<T> buf[TZ * PY];
+    const int tid = threadIdx.x;
+    const int kx = blockIdx.x, z0 = blockIdx.y * TZ;
+    for (int idx = tid; idx < TZ * PY; idx += NTHR) {
+        const int zl = idx / PY, y = idx % PY;
+        const int z = z0 + zl;
+        buf[idx] = (z < nz && y < ny) ? T1[((size_t)z * nkx + kx) * ny + y] : mk((T)0, (T)0);
+    }
+    __syncthreads();
+    block_fft<T, PY, TZ, PY, NTHR, false>(buf, tw, tid);
+    for (int idx = tid; idx < TZ * PY; idx += NTHR) {
+        const int zl = idx % TZ, ky = idx / TZ;
+        const int z = z0 + zl;
+        if (z < nz) T2[((size_t)kx * PY + ky) * nz + z] = buf[zl * PY + ky];
+    }
+}
+
+template <typename T, int PZ, int NC, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_pass3_c(cx<T>* __restrict__ T2, const T* __restrict__ Q3,
+                                                  const cx<T>* __restrict__ tw, int nz, int PY, size_t ncol) {
+    __shared__ cx<T> buf[NC * PZ];
+    const int tid = threadIdx.x;
+    const size_t c0 = (size_t)blockIdx.x * NC;
+    const int HY = PY / 2 + 1, HZ = PZ / 2 + 1;
+    for (int idx = tid; idx < NC * PZ; idx += NTHR) {
+        const int c = idx / PZ, z = idx % PZ;
+        const size_t col = c0 + c;
+        buf[idx] = (col < ncol && z < nz) ? T2[col * nz + z] : mk((T)0, (T)0);
+    }
+    __syncthreads();
+    block_fft<T, PZ, NC, PZ, NTHR, false>(buf, tw, tid);
+    for (int idx = tid; idx < NC * PZ; idx += NTHR) {
+        const int c = idx / PZ, kz = idx % PZ;
+        const size_t col = c0 + c;
+        if (col < ncol) {
+            const int kx = (int)(col / PY), ky = (int)(col % PY);
+            const int fy = ky <= PY / 2 ? ky : PY - ky;
+            const int fz = kz <= PZ / 2 ? kz : PZ - kz;
+            buf[idx] = scale(buf[idx], Q3[((size_t)kx * HY + fy) * HZ + fz]);
+        }
+    }
+    __syncthreads();
+    block_fft<T, PZ, NC, PZ, NTHR, true>(buf, tw, tid);
+    for (int idx = tid; idx < NC * PZ; idx += NTHR) {
+        const int c = idx / PZ, z = idx % PZ;
+        const size_t col = c0 + c;
+        if (col < ncol && z < nz) T2[col * nz + z] = buf[idx];
+    }
+}
+
+template <typename T, int PY, int TZ, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_pass3_d(cx<T>* __restrict__ T1, const cx<T>* __restrict__ T2,
+                                                  const cx<T>* __restrict__ tw, int ny, int nz, int nkx) {
+    __shared__ cx<T> buf[TZ * PY];
+    const int tid = threadIdx.x;
+    const int kx = blockIdx.x, z0 = blockIdx.y * TZ;
+    for (int idx = tid; idx < TZ * PY; idx += NTHR) {
+        const int zl = idx % TZ, ky = idx / TZ;
+        const int z = z0 + zl;
+        buf[zl * PY + ky] = z < nz ? T2[((size_t)kx * PY + ky) * nz + z] : mk((T)0, (T)0);
+    }
+    __syncthreads();
+    block_fft<T, PY, TZ, PY, NTHR, true>(buf, tw, tid);
+    for (int idx = tid; idx < TZ * ny; idx += NTHR) {
+        const int zl = idx / ny, y = idx % ny;
+        const int z = z0 + zl;
+        if (z < nz) T1[((size_t)z * nkx + kx) * ny + y] = buf[zl * PY + y];
+    }
+}
+
+template <typename T> constexpr int tz_rows() { return sizeof(T) == 4 ? 16 : 8; }
+
+template <typename T, int PY>
+static void launch3_bd(const Apply3DArgs<T>& a, bool inverse) {
+    constexpr int TZ = tz_rows<T>();
+    const int nkx = a.PX / 2 + 1;
+    dim3 grid(nkx, (a.nz + TZ - 1) / TZ);
+    if (!inverse)
+        hipLaunchKernelGGL((k_pass3_b<T, PY, TZ, 256>), grid, dim3(256), 0, a.stream, a.T1, a.T2, a.twy, a.ny, a.nz,
+                           nkx);
+    else
+        hipLaunchKernelGGL((k_pass3_d<T, PY, TZ, 256>), grid, dim3(256), 0, a.stream, a.T1, a.T2, a.twy, a.ny, a.nz,
+                           nkx);
+}
+
+template <typename T, int PZ>
+static void launch3_c(const Apply3DArgs<T>& a) {
+    constexpr int NC = PZ >= 2048 ? 1 : 2048 / PZ;
+    const size_t ncol = (size_t)(a.PX / 2 + 1) * a.PY;
+    dim3 grid((unsigned)((ncol + NC - 1) / NC));
+    hipLaunchKernelGGL((k_pass3_c<T, PZ, NC, 256>), grid, dim3(256), 0, a.stream, a.T2, a.Q3, a.twz, a.nz, a.PY,
+                       ncol);
+}
+
+template <typename T>
+int apply3d_pass(const Apply3DArgs<T>& a, int which) {
+    const int P = which == 2 ? a.PZ : a.PY;
+    switch (P) {
+#define RTE_C3(PP)                                              \
+    case PP:                                                    \
+        if (which == 1) launch3_bd<T, PP>(a, false);            \
+        else if (which == 3) launch3_bd<T, PP>(a, true);        \
+        else launch3_c<T, PP>(a);                               \
+        return 0;
+        RTE_C3(16) RTE_C3(32) RTE_C3(64) RTE_C3(128) RTE_C3(256) RTE_C3(512)
+#undef RTE_C3
+    }
+    return -1;
+}
+
+template int apply3d_pass<float>(const Apply3DArgs<float>&, int);
+template int apply3d_pass<double>(const Apply3DArgs<double>&, int);
+
+}  // namespace rte

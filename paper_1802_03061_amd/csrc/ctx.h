@@ -1,0 +1,66 @@
+// The opaque context behind rte_ctx (one problem: grid, coefficients, spectra, work buffers,
+// Krylov basis and the optional learned preconditioner).
+#pragma once
+#include <vector>
+
+#include "../../include/rte.h"
+#include "common.h"
+
+struct rte_ctx {
+    int dim = 2, nx = 0, ny = 0, nz = 1, L = 0, C = 1, M = 1, prec = RTE_PREC_FP64;
+    double h = 0, mu_a = 0, mu_s = 0, mu_t = 0;
+    std::vector<double> sigma;
+    int PX = 0, PY = 0, PZ = 1;
+    size_t ncell = 0, nvec = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    double t_setup_ms = 0;
+    // kernel spectra: 2D quarter [C][PX/2+1][PY/2+1]; 3D octant [PX/2+1][PY/2+1][PZ/2+1]
+    rte::cx<float>* Qf = nullptr;
+    rte::cx<double>* Qd = nullptr;
+    float* Q3f = nullptr;
+    double* Q3d = nullptr;
+    rte::cx<float>* twf[3] = {nullptr, nullptr, nullptr};
+    rte::cx<double>* twd[3] = {nullptr, nullptr, nullptr};
+    // FFT work buffers (2D: T and the split pass-B buffer; 3D: T1 and T2)
+    rte::cx<float>* wf = nullptr;
+    rte::cx<float>* wf2 = nullptr;
+    rte::cx<double>* wd = nullptr;
+    rte::cx<double>* wd2 = nullptr;
+    // solver vectors (channel layout, FP64)
+    double* xv = nullptr;
+    double* rv = nullptr;
+    double* bv = nullptr;
+    double* t0 = nullptr;   // 2 vectors
+    double* t1 = nullptr;   // 2 vectors
+    int* dflag = nullptr;
+    // Krylov basis
+    int krylov_m = 0;
+    bool krylov_z = false;
+    double* V = nullptr;
+    double* Z = nullptr;
+    double* partial = nullptr;
+    double* dsmall = nullptr;
+    double* hsmall = nullptr;   // pinned
+    rte_solve_opts opts{};
+    // learned preconditioner (see nn.hip)
+    bool pc_attached = false;
+    int pc_hidden = 0, pc_layers = 0;
+    void* pc_w = nullptr;       // BF16 weights, device
+    float* pc_b = nullptr;      // FP32 biases, device
+    float* pc_act0 = nullptr;   // activation ping-pong buffers
+    float* pc_act1 = nullptr;
+    double* pc_partial = nullptr;
+};
+
+namespace rte {
+int ensure_krylov(rte_ctx* c, int m, bool need_z);
+int apply_channels(rte_ctx* c, int mode, int prec, const double* x, const double* b, double* y, int nbatch);
+int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
+               double* rec, int max_rec, int* nrec);
+}  // namespace rte
+
+namespace rte {
+int solve_batched_impl(int count, rte_ctx* const* ctxs, const double* const* f, const double* tol, int max_iter,
+                       void* const* u, rte_solve_info* infos);
+}  // namespace rte

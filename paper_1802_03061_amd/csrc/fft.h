@@ -1,0 +1,123 @@
+// Workgroup-cooperative FFTs staged through LDS (gfx950, 64-wide waves).
+//
+// A transform of length P (a power of two) is computed by the Stockham autosort scheme: stage s
+// combines R sub-transforms of length Ns into transforms of length Ns*R, reading R values spaced
+// P/R apart, applying the twiddles exp(-+2 pi i r (j mod Ns)/(Ns R)), an R-point DFT in
+// registers, and writing the R results spaced Ns apart.  The result comes out in natural order.
+// Stages run in place in LDS: every thread first reads and transforms all its butterflies into
+// registers, a barrier, then writes.  Radices are 8 (with one leading 2 or 4 stage when
+// log2 P is not a multiple of 3).  Twiddles come from a table tw[q] = exp(-2 pi i q / P)
+// computed in FP64 on the host and rounded to the working precision.
+#pragma once
+#include "common.h"
+
+namespace rte {
+
+constexpr int fft_radix(int P, int Ns) {
+    // log2 of what remains to be combined
+    return (ilog2(P) - ilog2(Ns)) % 3 == 1 ? 2 : ((ilog2(P) - ilog2(Ns)) % 3 == 2 ? 4 : 8);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> rot_mi(cx<T> a) {  // multiply by -i (forward) or +i (inverse)
+    return INV ? mul_i(a) : mul_mi(a);
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_small(cx<T>* v) {
+    if constexpr (R == 2) {
+        cx<T> a = v[0], b = v[1];
+        v[0] = a + b;
+        v[1] = a - b;
+    } else if constexpr (R == 4) {
+        cx<T> t0 = v[0] + v[2], t1 = v[0] - v[2];
+        cx<T> t2 = v[1] + v[3], t3 = rot_mi<T, INV>(v[1] - v[3]);
+        v[0] = t0 + t2;
+        v[2] = t0 - t2;
+        v[1] = t1 + t3;
+        v[3] = t1 - t3;
+    } else {  // R == 8: two 4-point DFTs on the even and odd samples, then W8^q
+        cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+        cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+        dft_small<T, 4, INV>(e);
+        dft_small<T, 4, INV>(o);
+        const T s = (T)0.70710678118654752440084436210485;
+        // W8^1 = (1 -+ i)/sqrt2, W8^2 = -+i, W8^3 = (-1 -+ i)/sqrt2  (upper sign forward)
+        cx<T> o1 = INV ? mk(s * (o[1].re - o[1].im), s * (o[1].re + o[1].im))
+                       : mk(s * (o[1].re + o[1].im), s * (o[1].im - o[1].re));
+        cx<T> o2 = rot_mi<T, INV>(o[2]);
+        cx<T> o3 = INV ? mk(-s * (o[3].re + o[3].im), s * (o[3].re - o[3].im))
+                       : mk(s * (o[3].im - o[3].re), -s * (o[3].re + o[3].im));
+        v[0] = e[0] + o[0];
+        v[4] = e[0] - o[0];
+        v[1] = e[1] + o1;
+        v[5] = e[1] - o1;
+        v[2] = e[2] + o2;
+        v[6] = e[2] - o2;
+        v[3] = e[3] + o3;
+        v[7] = e[3] - o3;
+    }
+}
+
+// One in-place Stockham stage over NFFT transforms of length P at buf + f*LD.
+template <typename T, int P, int NFFT, int LD, int NTHR, int R, int NS, bool INV>
+__device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
+    constexpr int NB = P / R;
+    constexpr int TOTAL = NB * NFFT;
+    constexpr int ITEMS = (TOTAL + NTHR - 1) / NTHR;
+    constexpr int S = NS * R;
+    constexpr int TWSTEP = P / S;
+    cx<T> v[ITEMS][R];
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int idx = tid + it * NTHR;
+        if ((TOTAL % NTHR == 0) || idx < TOTAL) {
+            const int f = idx / NB, j = idx % NB;
+            const cx<T>* src = buf + f * LD + j;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[it][r] = src[r * NB];
+            if constexpr (NS > 1) {
+                const int k = j % NS;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    cx<T> w = tw[k * r * TWSTEP];
+                    if (INV) w.im = -w.im;
+                    v[it][r] = v[it][r] * w;
+                }
+            }
+            dft_small<T, R, INV>(v[it]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int idx = tid + it * NTHR;
+        if ((TOTAL % NTHR == 0) || idx < TOTAL) {
+            const int f = idx / NB, j = idx % NB;
+            const int k = j % NS;
+            cx<T>* dst = buf + f * LD + (j / NS) * S + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[r * NS] = v[it][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int P, int NFFT, int LD, int NTHR, bool INV, int NS>
+__device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
+    if constexpr (NS < P) {
+        constexpr int R = fft_radix(P, NS);
+        fft_stage<T, P, NFFT, LD, NTHR, R, NS, INV>(buf, tw, tid);
+        fft_stages<T, P, NFFT, LD, NTHR, INV, NS * R>(buf, tw, tid);
+    }
+}
+
+// Unnormalised DFT (INV=false: exp(-2 pi i jk/P); INV=true: exp(+2 pi i jk/P)) of NFFT
+// transforms held in LDS.  Must be called by all NTHR threads; ends with a barrier.
+template <typename T, int P, int NFFT, int LD, int NTHR, bool INV>
+__device__ __forceinline__ void block_fft(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
+    static_assert(is_pow2(P) && P >= 2, "FFT length must be a power of two");
+    fft_stages<T, P, NFFT, LD, NTHR, INV, 1>(buf, tw, tid);
+}
+
+}  // namespace rte

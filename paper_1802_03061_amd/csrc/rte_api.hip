@@ -1,0 +1,664 @@
+// C ABI of the RTE library: context set-up, operator apply, right-hand side, GMRES solve.
+//
+// The solve follows steps T.1/T.2 of Sec. 3.3 (S.1/S.2 of Sec. 2.3 for the isotropic case):
+// b = K~ g by one FFT apply, then GMRES on (I - K~ D) u = b from u = 0.  Unknowns are held as real
+// channel vectors (see apply2d.hip); for a real angular flux their Euclidean inner product equals
+// the complex inner product of the full mode vector, so GMRES runs in real FP64 arithmetic.
+// With RTE_PREC_FP32 the inner applies use FP32 FFTs and each restart cycle ends with an FP64
+// true-residual apply (iterative refinement); orthogonalisation, the Hessenberg least squares and
+// the residual check are FP64 throughout.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/rte.h"
+#include "apply2d.h"
+#include "apply3d.h"
+#include "ctx.h"
+#include "krylov.h"
+#include "nn.h"
+#include "spectra.h"
+
+namespace rte {
+
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int set_hip_error(hipError_t e, const char* what, const char* file, int line) {
+    const int code = (e == hipErrorOutOfMemory) ? RTE_ENOMEM : RTE_EDEVICE;
+    return set_error(code, "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+}
+
+static double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename P>
+static int dalloc(P** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) return RTE_OK;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(P));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return set_error(e == hipErrorOutOfMemory ? RTE_ENOMEM : RTE_EDEVICE, "hipMalloc of %zu bytes failed: %s",
+                         count * sizeof(P), hipGetErrorString(e));
+    }
+    return RTE_OK;
+}
+
+template <typename P>
+static void dfree(P*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+// ------------------------------------------------------------------ context lifetime ----------
+
+static void free_krylov(rte_ctx* c) {
+    dfree(c->V);
+    dfree(c->Z);
+    dfree(c->partial);
+    dfree(c->dsmall);
+    if (c->hsmall) (void)hipHostFree(c->hsmall);
+    c->hsmall = nullptr;
+    c->krylov_m = 0;
+    c->krylov_z = false;
+}
+
+static void free_ctx(rte_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_krylov(c);
+    dfree(c->Qf);
+    dfree(c->Qd);
+    dfree(c->Q3f);
+    dfree(c->Q3d);
+    for (int a = 0; a < 3; ++a) {
+        dfree(c->twf[a]);
+        dfree(c->twd[a]);
+    }
+    dfree(c->wf);
+    dfree(c->wf2);
+    dfree(c->wd);
+    dfree(c->wd2);
+    dfree(c->xv);
+    dfree(c->rv);
+    dfree(c->bv);
+    dfree(c->t0);
+    dfree(c->t1);
+    dfree(c->dflag);
+    pc_free(c);
+    delete c;
+}
+
+int ensure_krylov(rte_ctx* c, int m, bool need_z) {
+    if (c->krylov_m >= m && (!need_z || c->krylov_z)) return RTE_OK;
+    free_krylov(c);
+    const size_t n = c->nvec;
+    int rc;
+    if ((rc = dalloc(&c->V, (size_t)(m + 1) * n))) return rc;
+    if (need_z && (rc = dalloc(&c->Z, (size_t)m * n))) return rc;
+    if ((rc = dalloc(&c->partial, (size_t)(m + 3) * RTE_KRYLOV_NBLK))) return rc;
+    if ((rc = dalloc(&c->dsmall, (size_t)(2 * m + 16)))) return rc;
+    hipError_t e = hipHostMalloc((void**)&c->hsmall, (size_t)(2 * m + 16) * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) return set_hip_error(e, "hipHostMalloc", __FILE__, __LINE__);
+    c->krylov_m = m;
+    c->krylov_z = need_z;
+    return RTE_OK;
+}
+
+// ------------------------------------------------------------------ apply ---------------------
+
+static ChanScale channel_scale(const rte_ctx* c, int mode) {
+    ChanScale s;
+    for (int i = 0; i < 2 * RTE_MAX_L + 1; ++i) s.s[i] = 1.0;
+    if (mode != APPLY_KT) {
+        s.s[0] = c->mu_s * c->sigma[0];
+        for (int k = 1; k <= c->L; ++k) s.s[2 * k - 1] = s.s[2 * k] = c->mu_s * c->sigma[k];
+    }
+    return s;
+}
+
+template <typename T>
+static Apply2DArgs<T> args2d(const rte_ctx* c);
+template <>
+Apply2DArgs<float> args2d<float>(const rte_ctx* c) {
+    Apply2DArgs<float> a{c->nx, c->ny, c->PX, c->PY, c->L, c->C, c->wf, c->wf2, c->Qf, c->twf[0], c->twf[1], c->stream};
+    return a;
+}
+template <>
+Apply2DArgs<double> args2d<double>(const rte_ctx* c) {
+    Apply2DArgs<double> a{c->nx, c->ny, c->PX, c->PY, c->L, c->C, c->wd, c->wd2, c->Qd, c->twd[0], c->twd[1], c->stream};
+    return a;
+}
+
+template <typename T>
+static int apply_t(rte_ctx* c, int mode, const double* x, const double* b, double* y, int nbatch, hipEvent_t* ev) {
+    const ChanScale sc = channel_scale(c, mode);
+    if (c->dim == 2) {
+        Apply2DArgs<T> a = args2d<T>(c);
+        if (ev) (void)hipEventRecord(ev[0], c->stream);
+        if (apply2d_pass_a<T>(a, x, sc, nbatch)) return set_error(RTE_EUNSUPPORTED, "pass A: unsupported size");
+        if (ev) (void)hipEventRecord(ev[1], c->stream);
+        if (apply2d_pass_b<T>(a, nbatch)) return set_error(RTE_EUNSUPPORTED, "pass B: unsupported size");
+        if (ev) (void)hipEventRecord(ev[2], c->stream);
+        if (apply2d_pass_c<T>(a, x, b, y, mode, nbatch)) return set_error(RTE_EUNSUPPORTED, "pass C: unsupported size");
+        if (ev) (void)hipEventRecord(ev[3], c->stream);
+    } else {
+        // x-passes treat every z-slab of every batch entry as one channel of a 2D apply
+        Apply2DArgs<T> a = args2d<T>(c);
+        a.C = 1;
+        a.L = 0;
+        Apply3DArgs<T> a3;
+        a3.nx = c->nx; a3.ny = c->ny; a3.nz = c->nz; a3.PX = c->PX; a3.PY = c->PY; a3.PZ = c->PZ;
+        a3.stream = c->stream;
+        const size_t t1sz = (size_t)c->nz * (c->PX / 2 + 1) * c->ny;
+        if constexpr (sizeof(T) == 4) {
+            a3.T1 = c->wf; a3.T2 = c->wf2; a3.Q3 = c->Q3f; a3.twy = c->twf[1]; a3.twz = c->twf[2];
+        } else {
+            a3.T1 = c->wd; a3.T2 = c->wd2; a3.Q3 = c->Q3d; a3.twy = c->twd[1]; a3.twz = c->twd[2];
+        }
+        if (ev) (void)hipEventRecord(ev[0], c->stream);
+        if (apply2d_pass_a<T>(a, x, sc, nbatch * c->nz)) return set_error(RTE_EUNSUPPORTED, "3D pass A: unsupported size");
+        if (ev) (void)hipEventRecord(ev[1], c->stream);
+        cx<T>* T1base = a3.T1;
+        for (int bi = 0; bi < nbatch; ++bi) {
+            a3.T1 = T1base + (size_t)bi * t1sz;
+            if (apply3d_pass<T>(a3, 1)) return set_error(RTE_EUNSUPPORTED, "3D pass B: unsupported size");
+            if (ev && bi == nbatch - 1) (void)hipEventRecord(ev[2], c->stream);
+            if (apply3d_pass<T>(a3, 2)) return set_error(RTE_EUNSUPPORTED, "3D pass C: unsupported size");
+            if (ev && bi == nbatch - 1) (void)hipEventRecord(ev[3], c->stream);
+            if (apply3d_pass<T>(a3, 3)) return set_error(RTE_EUNSUPPORTED, "3D pass D: unsupported size");
+        }
+        if (ev) (void)hipEventRecord(ev[4], c->stream);
+        if (apply2d_pass_c<T>(a, x, b, y, mode, nbatch * c->nz)) return set_error(RTE_EUNSUPPORTED, "3D pass E: unsupported size");
+        if (ev) (void)hipEventRecord(ev[5], c->stream);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_hip_error(e, "apply launch", __FILE__, __LINE__);
+    return RTE_OK;
+}
+
+int apply_channels(rte_ctx* c, int mode, int prec, const double* x, const double* b, double* y, int nbatch) {
+    if (prec == RTE_PREC_FP32) return apply_t<float>(c, mode, x, b, y, nbatch, nullptr);
+    return apply_t<double>(c, mode, x, b, y, nbatch, nullptr);
+}
+
+// ------------------------------------------------------------------ small host helpers ---------
+
+static int dot_host(rte_ctx* c, const double* a, const double* b, double* out) {
+    krylov_dots(a, c->nvec, 1, b, c->nvec, c->partial, c->dsmall, false, c->stream);
+    RTE_HIP_TRY(hipMemcpyAsync(c->hsmall, c->dsmall, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    RTE_HIP_TRY(hipStreamSynchronize(c->stream));
+    *out = c->hsmall[0];
+    return RTE_OK;
+}
+
+// Solve the upper-triangular k x k system R y = g (R column-major with leading dimension ld).
+static void back_solve(const std::vector<double>& R, int ld, const std::vector<double>& g, int k, std::vector<double>& y) {
+    y.assign(k, 0.0);
+    for (int i = k - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int j = i + 1; j < k; ++j) s -= R[(size_t)j * ld + i] * y[j];
+        y[i] = s / R[(size_t)i * ld + i];
+    }
+}
+
+// ------------------------------------------------------------------ GMRES ---------------------
+
+int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
+               double* rec, int max_rec, int* nrec) {
+    const double t_start = now_ms();
+    hipStream_t st = c->stream;
+    const size_t n = c->nvec;
+    const int m = c->opts.restart;
+    const bool use_pc = c->pc_attached && c->opts.use_pc;
+    const bool mixed = c->prec == RTE_PREC_FP32;
+    int rc = ensure_krylov(c, m, use_pc);
+    if (rc) return rc;
+    if (nrec) *nrec = 0;
+    rte_solve_info inf;
+    memset(&inf, 0, sizeof(inf));
+    inf.t_setup_ms = c->t_setup_ms;
+    inf.pc_used = use_pc ? 1 : 0;
+
+    double bn2;
+    if ((rc = dot_host(c, b, b, &bn2))) return rc;
+    vec_fill(x, 0.0, n, st);
+    if (!std::isfinite(bn2)) {
+        if (info) *info = inf;
+        return set_error(RTE_ENUMERIC, "non-finite right-hand side");
+    }
+    if (bn2 == 0.0) {
+        RTE_HIP_TRY(hipStreamSynchronize(st));
+        inf.t_solve_ms = now_ms() - t_start;
+        if (info) *info = inf;
+        return RTE_OK;
+    }
+    const double bn = std::sqrt(bn2);
+    RTE_HIP_TRY(hipMemcpyAsync(c->rv, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    double rn = bn;
+    int it = 0, cycles = 0, status = RTE_NOT_CONVERGED;
+    double est = bn;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), yv;
+    bool pc_live = use_pc;
+
+    while (true) {
+        if (rn <= tol * bn) { status = RTE_OK; break; }
+        if (cycles >= c->opts.max_cycles || it >= max_iter) { status = RTE_NOT_CONVERGED; break; }
+        ++cycles;
+        double target = 0.5 * tol * bn;
+        if (mixed) target = std::max(target, c->opts.inner_tol * rn);
+        vec_scale(c->V, c->rv, 1.0 / rn, n, st);
+        std::fill(g.begin(), g.end(), 0.0);
+        std::fill(H.begin(), H.end(), 0.0);
+        g[0] = rn;
+        est = rn;
+        const double cycle_start_rn = rn;
+        int jd = 0;
+        for (int j = 0; j < m && it < max_iter; ++j) {
+            double* vj = c->V + (size_t)j * n;
+            double* w = c->V + (size_t)(j + 1) * n;
+            const double* zj = vj;
+            if (pc_live) {
+                double* z = c->Z + (size_t)j * n;
+                if ((rc = pc_apply(c, vj, z))) return rc;
+                zj = z;
+            } else if (use_pc) {
+                double* z = c->Z + (size_t)j * n;   // keep Z = V once the PC is dropped
+                RTE_HIP_TRY(hipMemcpyAsync(z, vj, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+                zj = z;
+            }
+            if ((rc = apply_channels(c, APPLY_A, c->prec, zj, nullptr, w, 1))) return rc;
+            ++inf.applies;
+            // classical Gram-Schmidt; a second pass when the norm dropped below 1/sqrt2 of its value
+            krylov_dots(c->V, n, j + 1, w, n, c->partial, c->dsmall, true, st);
+            krylov_update(w, c->V, n, j + 1, c->dsmall, n, c->partial, c->dsmall + j + 2, st);
+            RTE_HIP_TRY(hipMemcpyAsync(c->hsmall, c->dsmall, (j + 3) * sizeof(double), hipMemcpyDeviceToHost, st));
+            RTE_HIP_TRY(hipStreamSynchronize(st));
+            double* Hj = &H[(size_t)j * (m + 1)];
+            for (int i = 0; i <= j; ++i) Hj[i] = c->hsmall[i];
+            const double w0 = c->hsmall[j + 1];
+            double w1 = c->hsmall[j + 2];
+            if (c->opts.always_reorth || w1 < 0.5 * w0) {
+                krylov_dots(c->V, n, j + 1, w, n, c->partial, c->dsmall, false, st);
+                krylov_update(w, c->V, n, j + 1, c->dsmall, n, c->partial, c->dsmall + j + 2, st);
+                RTE_HIP_TRY(hipMemcpyAsync(c->hsmall, c->dsmall, (j + 3) * sizeof(double), hipMemcpyDeviceToHost, st));
+                RTE_HIP_TRY(hipStreamSynchronize(st));
+                for (int i = 0; i <= j; ++i) Hj[i] += c->hsmall[i];
+                w1 = c->hsmall[j + 2];
+            }
+            const double hn = std::sqrt(std::max(w1, 0.0));
+            Hj[j + 1] = hn;
+            // Givens rotations (real)
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * Hj[i] + sn[i] * Hj[i + 1];
+                Hj[i + 1] = -sn[i] * Hj[i] + cs[i] * Hj[i + 1];
+                Hj[i] = t;
+            }
+            const double den = std::hypot(Hj[j], Hj[j + 1]);
+            if (den == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
+            else { cs[j] = Hj[j] / den; sn[j] = Hj[j + 1] / den; }
+            Hj[j] = den;
+            Hj[j + 1] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            est = std::fabs(g[j + 1]);
+            ++it;
+            jd = j + 1;
+            if (!std::isfinite(est) || !std::isfinite(den)) {
+                if (pc_live) {   // a broken preconditioner: restart this cycle without it
+                    pc_live = false;
+                    inf.pc_fallback = 1;
+                    jd = 0;
+                    break;
+                }
+                inf.iterations = it;
+                inf.cycles = cycles;
+                if (info) *info = inf;
+                return set_error(RTE_ENUMERIC, "non-finite value in the Arnoldi process");
+            }
+            if (rec && cycles == 1 && j < max_rec) {
+                back_solve(H, m + 1, g, jd, yv);
+                RTE_HIP_TRY(hipMemcpyAsync(c->dsmall, yv.data(), jd * sizeof(double), hipMemcpyHostToDevice, st));
+                double* xr = rec + (size_t)j * n;
+                vec_fill(xr, 0.0, n, st);
+                krylov_combine(xr, use_pc ? c->Z : c->V, n, jd, c->dsmall, n, st);
+                if (nrec) *nrec = j + 1;
+            }
+            if (hn <= 1e-14 * std::sqrt(std::max(w0, 0.0)) || est <= target) break;
+            vec_scale(w, w, 1.0 / hn, n, st);
+        }
+        if (jd > 0) {
+            back_solve(H, m + 1, g, jd, yv);
+            RTE_HIP_TRY(hipMemcpyAsync(c->dsmall, yv.data(), jd * sizeof(double), hipMemcpyHostToDevice, st));
+            krylov_combine(x, use_pc ? c->Z : c->V, n, jd, c->dsmall, n, st);
+        }
+        // true residual with the FP64 apply
+        if ((rc = apply_channels(c, APPLY_RESID, RTE_PREC_FP64, x, b, c->rv, 1))) return rc;
+        ++inf.applies;
+        double rn2;
+        if ((rc = dot_host(c, c->rv, c->rv, &rn2))) return rc;
+        if (!std::isfinite(rn2)) {
+            inf.iterations = it;
+            inf.cycles = cycles;
+            if (info) *info = inf;
+            return set_error(RTE_ENUMERIC, "non-finite true residual");
+        }
+        rn = std::sqrt(rn2);
+        // the preconditioned cycle must cut the residual at least 10x, else continue without it
+        if (pc_live && rn > 0.1 * cycle_start_rn) {
+            pc_live = false;
+            inf.pc_fallback = 1;
+        }
+    }
+    RTE_HIP_TRY(hipStreamSynchronize(st));
+    inf.iterations = it;
+    inf.cycles = cycles;
+    inf.relres_est = est / bn;
+    inf.relres_true = rn / bn;
+    inf.t_solve_ms = now_ms() - t_start;
+    if (info) *info = inf;
+    if (status == RTE_NOT_CONVERGED)
+        set_error(RTE_NOT_CONVERGED, "not converged: relative residual %.3e after %d iterations", rn / bn, it);
+    return status;
+}
+
+}  // namespace rte
+
+using namespace rte;
+
+// ------------------------------------------------------------------ C ABI --------------------
+
+extern "C" {
+
+const char* rte_last_error(void) { return g_err; }
+const char* rte_version(void) { return "rte-mi355x 0.1 (gfx950)"; }
+
+static int validate_setup(const rte_grid* g, double mu_a, double mu_s, const double* sigma_hat, int L, int prec) {
+    if (!g) return set_error(RTE_EINVAL, "grid is NULL");
+    if (g->dim != 2 && g->dim != 3) return set_error(RTE_EINVAL, "dim must be 2 or 3 (got %d)", g->dim);
+    for (int a = 0; a < g->dim; ++a)
+        if (g->n[a] < 2) return set_error(RTE_EINVAL, "n[%d] = %d must be >= 2", a, g->n[a]);
+    if (!(g->h > 0.0) || !std::isfinite(g->h)) return set_error(RTE_EINVAL, "h must be finite and > 0");
+    if (!(mu_a >= 0.0) || !std::isfinite(mu_a)) return set_error(RTE_EINVAL, "mu_a must be finite and >= 0");
+    if (!(mu_s >= 0.0) || !std::isfinite(mu_s)) return set_error(RTE_EINVAL, "mu_s must be finite and >= 0");
+    if (!(mu_a + mu_s > 0.0)) return set_error(RTE_EINVAL, "mu_t = mu_a + mu_s must be > 0");
+    if (L < 0 || L > RTE_MAX_L) return set_error(RTE_EINVAL, "L = %d outside 0..%d", L, RTE_MAX_L);
+    if (prec != RTE_PREC_FP32 && prec != RTE_PREC_FP64) return set_error(RTE_EINVAL, "prec must be FP32 or FP64");
+    if (L > 0 && !sigma_hat) return set_error(RTE_EINVAL, "sigma_hat is NULL with L > 0");
+    if (sigma_hat) {
+        if (std::fabs(sigma_hat[0] - 1.0) > 1e-12) return set_error(RTE_EINVAL, "sigma_hat[0] must be 1 (normalised phase function)");
+        for (int k = 1; k <= L; ++k)
+            if (!(std::fabs(sigma_hat[k]) <= 1.0)) return set_error(RTE_EINVAL, "|sigma_hat[%d]| must be <= 1", k);
+    }
+    if (g->dim == 3 && L > 0) return set_error(RTE_EUNSUPPORTED, "3D is isotropic only (L must be 0)");
+    const int nmax = g->dim == 2 ? 512 : 256;
+    for (int a = 0; a < g->dim; ++a)
+        if (g->n[a] > nmax) return set_error(RTE_EUNSUPPORTED, "n[%d] = %d exceeds %d", a, g->n[a], nmax);
+    return RTE_OK;
+}
+
+int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const double* sigma_hat, int L, int prec,
+              void* hip_stream) {
+    if (!out) return set_error(RTE_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_setup(g, mu_a, mu_s, sigma_hat, L, prec);
+    if (rc) return rc;
+    const double t0 = now_ms();
+    rte_ctx* c = new (std::nothrow) rte_ctx();
+    if (!c) return set_error(RTE_ENOMEM, "host allocation failed");
+    c->dim = g->dim;
+    c->nx = g->n[0];
+    c->ny = g->n[1];
+    c->nz = g->dim == 3 ? g->n[2] : 1;
+    c->h = g->h;
+    c->L = L;
+    c->C = 2 * L + 1;
+    c->M = 2 * L + 1;
+    c->prec = prec;
+    c->mu_a = mu_a;
+    c->mu_s = mu_s;
+    c->mu_t = mu_a + mu_s;
+    c->sigma.assign(L + 1, 1.0);
+    for (int k = 0; k <= L && sigma_hat; ++k) c->sigma[k] = sigma_hat[k];
+    c->stream = (hipStream_t)hip_stream;
+    c->PX = next_pow2(std::max(2 * c->nx - 1, 16));
+    c->PY = next_pow2(std::max(2 * c->ny - 1, 16));
+    c->PZ = c->dim == 3 ? next_pow2(std::max(2 * c->nz - 1, 16)) : 1;
+    c->ncell = (size_t)c->nx * c->ny * c->nz;
+    c->nvec = (size_t)c->C * c->ncell;
+    c->opts.restart = 64;
+    c->opts.max_cycles = 8;
+    c->opts.inner_tol = 1e-5;
+    c->opts.always_reorth = 0;
+    c->opts.use_pc = 1;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) { free_ctx(c); return set_hip_error(e, "hipGetDevice", __FILE__, __LINE__); }
+
+    // twiddles
+    const int Ps[3] = {c->PX, c->PY, c->PZ};
+    for (int a = 0; a < c->dim; ++a) {
+        std::vector<double> re, im;
+        twiddles(Ps[a], re, im);
+        std::vector<cx<double>> td(Ps[a]);
+        std::vector<cx<float>> tf(Ps[a]);
+        for (int q = 0; q < Ps[a]; ++q) {
+            td[q] = mk(re[q], im[q]);
+            tf[q] = mk((float)re[q], (float)im[q]);
+        }
+        if ((rc = dalloc(&c->twd[a], Ps[a])) || (rc = dalloc(&c->twf[a], Ps[a]))) { free_ctx(c); return rc; }
+        e = hipMemcpy(c->twd[a], td.data(), Ps[a] * sizeof(cx<double>), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(c->twf[a], tf.data(), Ps[a] * sizeof(cx<float>), hipMemcpyHostToDevice);
+        if (e != hipSuccess) { free_ctx(c); return set_hip_error(e, "twiddle upload", __FILE__, __LINE__); }
+    }
+    const bool f32 = prec == RTE_PREC_FP32;
+    const int NK = c->PX / 2 + 1;
+    // spectra (FP64 on the device)
+    {
+        const size_t np = (size_t)c->PX * c->PY * c->PZ;
+        cx<double>*b0 = nullptr, *b1 = nullptr;
+        if ((rc = dalloc(&b0, np)) || (rc = dalloc(&b1, np))) { dfree(b0); dfree(b1); free_ctx(c); return rc; }
+        if (c->dim == 2) {
+            const size_t nq = (size_t)c->C * NK * (c->PY / 2 + 1);
+            if ((rc = dalloc(&c->Qd, nq)) || (f32 && (rc = dalloc(&c->Qf, nq)))) { dfree(b0); dfree(b1); free_ctx(c); return rc; }
+            SpectraArgs2D a{c->nx, c->ny, c->PX, c->PY, c->L, c->h, c->mu_t, b0, b1, c->twd[0], c->twd[1],
+                            c->Qf, c->Qd, c->stream};
+            rc = build_spectra_2d(a);
+        } else {
+            const size_t no = (size_t)NK * (c->PY / 2 + 1) * (c->PZ / 2 + 1);
+            if ((rc = dalloc(&c->Q3d, no)) || (f32 && (rc = dalloc(&c->Q3f, no)))) { dfree(b0); dfree(b1); free_ctx(c); return rc; }
+            SpectraArgs3D a{c->nx, c->ny, c->nz, c->PX, c->PY, c->PZ, c->h, c->mu_t, b0, b1,
+                            c->twd[0], c->twd[1], c->twd[2], c->Q3f, c->Q3d, c->stream};
+            rc = build_spectrum_3d(a);
+        }
+        e = hipStreamSynchronize(c->stream);
+        dfree(b0);
+        dfree(b1);
+        if (rc || e != hipSuccess) { free_ctx(c); return rc ? set_error(RTE_EDEVICE, "spectrum build failed") : set_hip_error(e, "spectra", __FILE__, __LINE__); }
+    }
+    // work buffers, sized for two right-hand sides (the general complex apply)
+    const int nb = 2;
+    if (c->dim == 2) {
+        const size_t nt = (size_t)nb * c->C * NK * c->ny;
+        const size_t nt2 = (size_t)nb * c->C * NK * c->PY;
+        if ((rc = dalloc(&c->wd, nt))) { free_ctx(c); return rc; }
+        if (apply2d_needs_work2<double>(c->L, c->PY) && (rc = dalloc(&c->wd2, nt2))) { free_ctx(c); return rc; }
+        if (f32) {
+            if ((rc = dalloc(&c->wf, nt))) { free_ctx(c); return rc; }
+            if (apply2d_needs_work2<float>(c->L, c->PY) && (rc = dalloc(&c->wf2, nt2))) { free_ctx(c); return rc; }
+        }
+    } else {
+        const size_t n1 = (size_t)nb * c->nz * NK * c->ny;
+        const size_t n2 = (size_t)NK * c->PY * c->nz;
+        if ((rc = dalloc(&c->wd, n1)) || (rc = dalloc(&c->wd2, n2))) { free_ctx(c); return rc; }
+        if (f32 && ((rc = dalloc(&c->wf, n1)) || (rc = dalloc(&c->wf2, n2)))) { free_ctx(c); return rc; }
+    }
+    const size_t n = c->nvec;
+    if ((rc = dalloc(&c->xv, n)) || (rc = dalloc(&c->rv, n)) || (rc = dalloc(&c->bv, n)) ||
+        (rc = dalloc(&c->t0, 2 * n)) || (rc = dalloc(&c->t1, 2 * n)) || (rc = dalloc(&c->dflag, 4))) {
+        free_ctx(c);
+        return rc;
+    }
+    if ((rc = ensure_krylov(c, c->opts.restart, false))) { free_ctx(c); return rc; }
+    c->t_setup_ms = now_ms() - t0;
+    *out = c;
+    return RTE_OK;
+}
+
+void rte_destroy(rte_ctx* ctx) { free_ctx(ctx); }
+
+int rte_query(const rte_ctx* c, int* channels, int* modes, long long* cells) {
+    if (!c) return set_error(RTE_EINVAL, "ctx is NULL");
+    if (channels) *channels = c->C;
+    if (modes) *modes = c->M;
+    if (cells) *cells = (long long)c->ncell;
+    return RTE_OK;
+}
+
+int rte_set_solve_opts(rte_ctx* c, const rte_solve_opts* o) {
+    if (!c) return set_error(RTE_EINVAL, "ctx is NULL");
+    rte_solve_opts d;
+    d.restart = 64;
+    d.max_cycles = 8;
+    d.inner_tol = 1e-5;
+    d.always_reorth = 0;
+    d.use_pc = 1;
+    if (o) {
+        if (o->restart < 1 || o->restart > RTE_MAX_RESTART) return set_error(RTE_EINVAL, "restart must be in 1..%d", RTE_MAX_RESTART);
+        if (o->max_cycles < 1) return set_error(RTE_EINVAL, "max_cycles must be >= 1");
+        if (!(o->inner_tol > 0.0 && o->inner_tol < 1.0)) return set_error(RTE_EINVAL, "inner_tol must be in (0, 1)");
+        d = *o;
+    }
+    c->opts = d;
+    return RTE_OK;
+}
+
+int rte_apply(rte_ctx* c, int op, int layout, int prec, const void* x, void* y) {
+    if (!c) return set_error(RTE_EINVAL, "ctx is NULL");
+    if (op != RTE_OP_A && op != RTE_OP_KT) return set_error(RTE_EINVAL, "op must be RTE_OP_A or RTE_OP_KT");
+    if (layout != RTE_LAYOUT_MODES && layout != RTE_LAYOUT_CHANNELS) return set_error(RTE_EINVAL, "bad layout");
+    if (prec != RTE_PREC_FP32 && prec != RTE_PREC_FP64) return set_error(RTE_EINVAL, "bad prec");
+    if (prec == RTE_PREC_FP32 && c->prec != RTE_PREC_FP32) return set_error(RTE_EINVAL, "FP32 apply needs an FP32 context");
+    if (!x || !y) return set_error(RTE_EINVAL, "x or y is NULL");
+    if (x == y) return set_error(RTE_EINVAL, "x and y may not alias");
+    const int mode = op == RTE_OP_A ? APPLY_A : APPLY_KT;
+    if (layout == RTE_LAYOUT_CHANNELS) return apply_channels(c, mode, prec, (const double*)x, nullptr, (double*)y, 1);
+    modes_to_channels(x, c->t0, c->L, c->ncell, false, c->stream);
+    int rc = apply_channels(c, mode, prec, c->t0, nullptr, c->t1, 2);
+    if (rc) return rc;
+    channels_to_modes(c->t1, y, c->L, c->ncell, false, c->stream);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RTE_OK : set_hip_error(e, "rte_apply", __FILE__, __LINE__);
+}
+
+int rte_modes_to_channels(rte_ctx* c, const void* modes, double* ch) {
+    if (!c || !modes || !ch) return set_error(RTE_EINVAL, "NULL argument");
+    modes_to_channels(modes, ch, c->L, c->ncell, true, c->stream);
+    return RTE_OK;
+}
+
+int rte_channels_to_modes(rte_ctx* c, const double* ch, void* modes) {
+    if (!c || !modes || !ch) return set_error(RTE_EINVAL, "NULL argument");
+    channels_to_modes(ch, modes, c->L, c->ncell, true, c->stream);
+    return RTE_OK;
+}
+
+// b = K~ g with g = f delta_{k0}: channel 0 carries f, the others are zero.
+static int rhs_channels(rte_ctx* c, const double* f, double* b) {
+    vec_fill(c->t0, 0.0, c->nvec, c->stream);
+    hipError_t e = hipMemcpyAsync(c->t0, f, c->ncell * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return set_hip_error(e, "rhs copy", __FILE__, __LINE__);
+    return apply_channels(c, APPLY_KT, RTE_PREC_FP64, c->t0, nullptr, b, 1);
+}
+
+int rte_rhs(rte_ctx* c, const double* f, int layout, void* b) {
+    if (!c || !f || !b) return set_error(RTE_EINVAL, "NULL argument");
+    if (layout != RTE_LAYOUT_MODES && layout != RTE_LAYOUT_CHANNELS) return set_error(RTE_EINVAL, "bad layout");
+    if (layout == RTE_LAYOUT_CHANNELS) return rhs_channels(c, f, (double*)b);
+    int rc = rhs_channels(c, f, c->bv);
+    if (rc) return rc;
+    channels_to_modes(c->bv, b, c->L, c->ncell, true, c->stream);
+    return RTE_OK;
+}
+
+int rte_solve(rte_ctx* c, const double* f, double tol, int max_iter, void* u, rte_solve_info* info) {
+    if (!c || !f || !u) return set_error(RTE_EINVAL, "NULL argument");
+    if (!(tol > 0.0) || !(tol < 1.0)) return set_error(RTE_EINVAL, "tol must be in (0, 1)");
+    if (max_iter < 1) return set_error(RTE_EINVAL, "max_iter must be >= 1");
+    int rc = rhs_channels(c, f, c->bv);
+    if (rc) return rc;
+    rc = solve_core(c, c->bv, tol, max_iter, c->xv, info, nullptr, 0, nullptr);
+    if (rc < 0) return rc;
+    channels_to_modes(c->xv, u, c->L, c->ncell, true, c->stream);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return set_hip_error(e, "rte_solve", __FILE__, __LINE__);
+    if (rc == RTE_NOT_CONVERGED)
+        set_error(RTE_NOT_CONVERGED, "not converged: relative residual %.3e", info ? info->relres_true : -1.0);
+    return rc;
+}
+
+int rte_solve_rhs(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
+                  double* x_iterates, int max_record, int* n_recorded) {
+    if (!c || !b || !x) return set_error(RTE_EINVAL, "NULL argument");
+    if (!(tol > 0.0) || !(tol < 1.0)) return set_error(RTE_EINVAL, "tol must be in (0, 1)");
+    if (max_iter < 1) return set_error(RTE_EINVAL, "max_iter must be >= 1");
+    if (x_iterates && max_record < 0) return set_error(RTE_EINVAL, "max_record must be >= 0");
+    return solve_core(c, b, tol, max_iter, x, info, x_iterates, max_record, n_recorded);
+}
+
+int rte_time_apply(rte_ctx* c, int op, int prec, int reps, double* ms_total, double* ms_pass) {
+    if (!c || reps < 1) return set_error(RTE_EINVAL, "bad argument");
+    if (prec == RTE_PREC_FP32 && c->prec != RTE_PREC_FP32) return set_error(RTE_EINVAL, "FP32 apply needs an FP32 context");
+    const int mode = op == RTE_OP_A ? APPLY_A : APPLY_KT;
+    const int nev = c->dim == 2 ? 4 : 6;
+    hipEvent_t ev[6];
+    for (int i = 0; i < nev; ++i) RTE_HIP_TRY(hipEventCreate(&ev[i]));
+    std::vector<double> acc(nev, 0.0);
+    vec_fill(c->t0, 1.0, c->nvec, c->stream);
+    int rc = RTE_OK;
+    for (int r = 0; r < reps && !rc; ++r) {
+        rc = prec == RTE_PREC_FP32 ? apply_t<float>(c, mode, c->t0, nullptr, c->t1, 1, ev)
+                                   : apply_t<double>(c, mode, c->t0, nullptr, c->t1, 1, ev);
+        if (rc) break;
+        RTE_HIP_TRY(hipEventSynchronize(ev[nev - 1]));
+        for (int i = 1; i < nev; ++i) {
+            float ms = 0.f;
+            RTE_HIP_TRY(hipEventElapsedTime(&ms, ev[i - 1], ev[i]));
+            acc[i] += ms;
+        }
+    }
+    for (int i = 0; i < nev; ++i) (void)hipEventDestroy(ev[i]);
+    if (rc) return rc;
+    double tot = 0.0;
+    for (int i = 1; i < nev; ++i) tot += acc[i];
+    if (ms_total) *ms_total = tot / reps;
+    if (ms_pass) {
+        for (int i = 0; i < 5; ++i) ms_pass[i] = 0.0;
+        for (int i = 1; i < nev; ++i) ms_pass[i - 1] = acc[i] / reps;
+    }
+    return RTE_OK;
+}
+
+}  // extern "C"
+
+extern "C" int rte_solve_batched(int count, rte_ctx* const* ctxs, const double* const* f, const double* tol,
+                                 int max_iter, void* const* u, rte_solve_info* infos) {
+    return rte::solve_batched_impl(count, ctxs, f, tol, max_iter, u, infos);
+}

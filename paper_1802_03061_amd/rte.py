@@ -1,0 +1,262 @@
+"""ctypes binding of the C ABI in include/rte.h (argument marshalling only).
+
+Every computation runs in librte.so (HIP, gfx950).  PyTorch supplies device memory and the
+stream: tensors are passed by data pointer and the context enqueues on torch's current stream
+at creation time.  There is no fallback: if the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librte.so")
+
+RTE_OK, RTE_NOT_CONVERGED = 0, 1
+RTE_EINVAL, RTE_ENOMEM, RTE_EDEVICE, RTE_ENUMERIC, RTE_EUNSUPPORTED = -1, -2, -3, -4, -5
+PREC_FP32, PREC_FP64 = 0, 1
+OP_A, OP_KT = 0, 1
+LAYOUT_MODES, LAYOUT_CHANNELS = 0, 1
+MAX_L = 8
+
+
+class RteError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rte error {code}: {msg}")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("applies", C.c_int), ("cycles", C.c_int),
+                ("pc_used", C.c_int), ("pc_fallback", C.c_int),
+                ("relres_est", C.c_double), ("relres_true", C.c_double),
+                ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("restart", C.c_int), ("max_cycles", C.c_int), ("inner_tol", C.c_double),
+                ("always_reorth", C.c_int), ("use_pc", C.c_int)]
+
+
+_lib = None
+
+
+def load():
+    """Load librte.so (built in-tree by paper_1802_03061_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_1802_03061_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    P, I, D = C.c_void_p, C.c_int, C.c_double
+    sig = {
+        "rte_setup": (I, [C.POINTER(P), C.POINTER(Grid), D, D, C.POINTER(D), I, I, P]),
+        "rte_apply": (I, [P, I, I, I, P, P]),
+        "rte_rhs": (I, [P, P, I, P]),
+        "rte_set_solve_opts": (I, [P, C.POINTER(SolveOpts)]),
+        "rte_solve": (I, [P, P, D, I, P, C.POINTER(SolveInfo)]),
+        "rte_solve_rhs": (I, [P, P, D, I, P, C.POINTER(SolveInfo), P, I, C.POINTER(I)]),
+        "rte_solve_batched": (I, [I, C.POINTER(P), C.POINTER(P), C.POINTER(D), I, C.POINTER(P),
+                                  C.POINTER(SolveInfo)]),
+        "rte_pc_attach": (I, [P, P, I, I]),
+        "rte_time_apply": (I, [P, I, I, I, C.POINTER(D), C.POINTER(D)]),
+        "rte_query": (I, [P, C.POINTER(I), C.POINTER(I), C.POINTER(C.c_longlong)]),
+        "rte_modes_to_channels": (I, [P, P, P]),
+        "rte_channels_to_modes": (I, [P, P, P]),
+        "rte_destroy": (None, [P]),
+        "rte_last_error": (C.c_char_p, []),
+        "rte_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().rte_last_error().decode()
+
+
+def _check(rc, allow=(RTE_OK,)):
+    if rc not in allow:
+        raise RteError(rc, last_error())
+    return rc
+
+
+def _ptr(t: torch.Tensor, dtype, numel=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One problem: grid, coefficients, precision; owns its device state."""
+
+    def __init__(self, n, h=None, mu_a=0.1, mu_s=1.0, sigma_hat=None, L=0, prec=PREC_FP64, dim=None,
+                 device=None):
+        lib = load()
+        if isinstance(n, int):
+            n = (n, n) if (dim or 2) == 2 else (n, n, n)
+        n = tuple(int(v) for v in n)
+        dim = len(n)
+        self.dim, self.shape_xyz, self.L, self.prec = dim, n, int(L), int(prec)
+        self.h = float(h if h is not None else 1.0 / n[0])
+        self.mu_a, self.mu_s = float(mu_a), float(mu_s)
+        g = Grid()
+        g.dim = dim
+        for a in range(3):
+            g.n[a] = n[a] if a < dim else 1
+        g.h = self.h
+        sh = None
+        if sigma_hat is not None:
+            arr = (C.c_double * len(sigma_hat))(*[float(s) for s in sigma_hat])
+            sh = C.cast(arr, C.POINTER(C.c_double))
+            self._sigma = arr
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib.rte_setup(C.byref(h), C.byref(g), self.mu_a, self.mu_s, sh, self.L, self.prec,
+                             C.c_void_p(stream.cuda_stream)))
+        self._h = h
+        ch, md, cells = C.c_int(), C.c_int(), C.c_longlong()
+        _check(lib.rte_query(h, C.byref(ch), C.byref(md), C.byref(cells)))
+        self.channels, self.modes, self.cells = ch.value, md.value, cells.value
+        # array shapes: 2D [..][ny][nx], 3D [nz][ny][nx]
+        self.grid_shape = tuple(reversed(n))
+
+    # ---- shapes
+    @property
+    def mode_shape(self):
+        return (self.modes,) + self.grid_shape
+
+    @property
+    def channel_shape(self):
+        return (self.channels,) + self.grid_shape
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().rte_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- operations
+    def apply(self, x, op=OP_A, layout=LAYOUT_MODES, prec=None, out=None):
+        prec = self.prec if prec is None else prec
+        if layout == LAYOUT_MODES:
+            xp = _ptr(x, torch.complex128, self.modes * self.cells)
+            out = torch.empty_like(x) if out is None else out
+            yp = _ptr(out, torch.complex128, self.modes * self.cells)
+        else:
+            xp = _ptr(x, torch.float64, self.channels * self.cells)
+            out = torch.empty_like(x) if out is None else out
+            yp = _ptr(out, torch.float64, self.channels * self.cells)
+        _check(load().rte_apply(self._h, op, layout, prec, xp, yp))
+        return out
+
+    def rhs(self, f, layout=LAYOUT_MODES):
+        fp = _ptr(f, torch.float64, self.cells)
+        if layout == LAYOUT_MODES:
+            out = torch.empty(self.mode_shape, dtype=torch.complex128, device=f.device)
+        else:
+            out = torch.empty(self.channel_shape, dtype=torch.float64, device=f.device)
+        _check(load().rte_rhs(self._h, fp, layout, C.c_void_p(out.data_ptr())))
+        return out
+
+    def set_opts(self, restart=64, max_cycles=8, inner_tol=1e-5, always_reorth=0, use_pc=1):
+        o = SolveOpts(restart, max_cycles, inner_tol, always_reorth, use_pc)
+        _check(load().rte_set_solve_opts(self._h, C.byref(o)))
+
+    def solve(self, f, tol=1e-8, max_iter=1000, allow_not_converged=False):
+        fp = _ptr(f, torch.float64, self.cells)
+        u = torch.empty(self.mode_shape, dtype=torch.complex128, device=f.device)
+        info = SolveInfo()
+        allow = (RTE_OK, RTE_NOT_CONVERGED) if allow_not_converged else (RTE_OK,)
+        rc = _check(load().rte_solve(self._h, fp, float(tol), int(max_iter), C.c_void_p(u.data_ptr()),
+                                     C.byref(info)), allow)
+        d = info.as_dict()
+        d["status"] = rc
+        return u, d
+
+    def solve_rhs(self, b, tol=1e-8, max_iter=1000, record=0, allow_not_converged=False):
+        bp = _ptr(b, torch.float64, self.channels * self.cells)
+        x = torch.empty_like(b)
+        info = SolveInfo()
+        rec = None
+        nrec = C.c_int(0)
+        if record:
+            rec = torch.zeros((record,) + tuple(b.shape), dtype=torch.float64, device=b.device)
+        allow = (RTE_OK, RTE_NOT_CONVERGED) if allow_not_converged else (RTE_OK,)
+        rc = _check(load().rte_solve_rhs(self._h, bp, float(tol), int(max_iter), C.c_void_p(x.data_ptr()),
+                                         C.byref(info),
+                                         C.c_void_p(rec.data_ptr()) if rec is not None else None,
+                                         int(record), C.byref(nrec)), allow)
+        d = info.as_dict()
+        d["status"] = rc
+        if rec is not None:
+            return x, d, rec[:nrec.value]
+        return x, d
+
+    def time_apply(self, op=OP_A, prec=None, reps=20):
+        prec = self.prec if prec is None else prec
+        tot = C.c_double()
+        passes = (C.c_double * 5)()
+        _check(load().rte_time_apply(self._h, op, prec, reps, C.byref(tot), passes))
+        return tot.value, list(passes)
+
+    def attach_pc(self, weights, hidden, layers):
+        if weights is None:
+            _check(load().rte_pc_attach(self._h, None, 0, 0))
+            return
+        wp = _ptr(weights, torch.float32)
+        _check(load().rte_pc_attach(self._h, wp, int(hidden), int(layers)))
+
+    def modes_to_channels(self, x):
+        out = torch.empty(self.channel_shape, dtype=torch.float64, device=x.device)
+        _check(load().rte_modes_to_channels(self._h, _ptr(x, torch.complex128, self.modes * self.cells),
+                                            C.c_void_p(out.data_ptr())))
+        return out
+
+    def channels_to_modes(self, ch):
+        out = torch.empty(self.mode_shape, dtype=torch.complex128, device=ch.device)
+        _check(load().rte_channels_to_modes(self._h, _ptr(ch, torch.float64, self.channels * self.cells),
+                                            C.c_void_p(out.data_ptr())))
+        return out
+
+
+def solve_batched(ctxs, fs, tols, max_iter=1000, allow_not_converged=False):
+    """Solve several isotropic 2D problems together (rte_solve_batched)."""
+    lib = load()
+    n = len(ctxs)
+    hs = (C.c_void_p * n)(*[c._h for c in ctxs])
+    fp = (C.c_void_p * n)(*[_ptr(f, torch.float64, c.cells) for f, c in zip(fs, ctxs)])
+    us = [torch.empty(c.mode_shape, dtype=torch.complex128, device=f.device) for c, f in zip(ctxs, fs)]
+    up = (C.c_void_p * n)(*[C.c_void_p(u.data_ptr()) for u in us])
+    tl = (C.c_double * n)(*[float(t) for t in tols])
+    infos = (SolveInfo * n)()
+    allow = (RTE_OK, RTE_NOT_CONVERGED) if allow_not_converged else (RTE_OK,)
+    rc = _check(lib.rte_solve_batched(n, hs, fp, tl, int(max_iter), up, infos), allow)
+    return us, [i.as_dict() for i in infos], rc

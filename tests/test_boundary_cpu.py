@@ -1,0 +1,93 @@
+"""The C ABI without a GPU: the library loads, exports every function declared in include/rte.h,
+and rejects invalid arguments before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rte.h")
+LIB = os.path.join(ROOT, "paper_1802_03061_amd", "librte.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rte_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("librte.so is not built (python -m paper_1802_03061_amd.build)")
+    from paper_1802_03061_amd import rte
+    return rte.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("rte_setup", "rte_apply", "rte_solve", "rte_solve_batched", "rte_destroy",
+                 "rte_last_error", "rte_pc_attach"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def _grid(rte, dim=2, n=(16, 16, 1), h=1 / 16):
+    g = rte.Grid()
+    g.dim = dim
+    for a in range(3):
+        g.n[a] = n[a]
+    g.h = h
+    return g
+
+
+@pytest.mark.parametrize("case", [
+    dict(dim=4), dict(n=(1, 16, 1)), dict(h=0.0), dict(h=-1.0), dict(mu_a=-0.1), dict(mu_s=-1.0),
+    dict(mu_a=0.0, mu_s=0.0), dict(L=-1), dict(L=9), dict(prec=7), dict(sigma=[0.5, 0.2], L=1),
+    dict(sigma=[1.0, 1.5], L=1), dict(sigma=None, L=2),
+])
+def test_setup_rejects_invalid_arguments(lib, case):
+    from paper_1802_03061_amd import rte
+    g = _grid(rte, dim=case.get("dim", 2), n=case.get("n", (16, 16, 1)), h=case.get("h", 1 / 16))
+    L = case.get("L", 0)
+    sigma = case.get("sigma", [1.0] * (max(L, 0) + 1))
+    arr = None if sigma is None else (C.c_double * len(sigma))(*sigma)
+    out = C.c_void_p(123)
+    rc = lib.rte_setup(C.byref(out), C.byref(g), case.get("mu_a", 0.1), case.get("mu_s", 1.0),
+                       C.cast(arr, C.POINTER(C.c_double)) if arr is not None else None, L,
+                       case.get("prec", 1), None)
+    assert rc == rte.RTE_EINVAL
+    assert out.value is None
+    assert len(lib.rte_last_error()) > 0
+
+
+def test_setup_3d_anisotropic_is_unsupported(lib):
+    from paper_1802_03061_amd import rte
+    g = _grid(rte, dim=3, n=(8, 8, 8), h=1 / 8)
+    arr = (C.c_double * 2)(1.0, 0.3)
+    out = C.c_void_p()
+    rc = lib.rte_setup(C.byref(out), C.byref(g), 0.1, 1.0, C.cast(arr, C.POINTER(C.c_double)), 1, 1, None)
+    assert rc == rte.RTE_EUNSUPPORTED
+
+
+def test_setup_oversize_is_unsupported(lib):
+    from paper_1802_03061_amd import rte
+    g = _grid(rte, n=(1024, 16, 1))
+    out = C.c_void_p()
+    assert lib.rte_setup(C.byref(out), C.byref(g), 0.1, 1.0, None, 0, 1, None) == rte.RTE_EUNSUPPORTED
+
+
+def test_null_context_calls_fail_cleanly(lib):
+    from paper_1802_03061_amd import rte
+    assert lib.rte_apply(None, 0, 0, 1, None, None) == rte.RTE_EINVAL
+    assert lib.rte_solve(None, None, 1e-8, 10, None, None) == rte.RTE_EINVAL
+    assert lib.rte_rhs(None, None, 0, None) == rte.RTE_EINVAL
+    assert lib.rte_set_solve_opts(None, None) == rte.RTE_EINVAL
+    assert lib.rte_query(None, None, None, None) == rte.RTE_EINVAL
+    lib.rte_destroy(None)
+    assert b"gfx950" in lib.rte_version()

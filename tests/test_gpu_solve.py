@@ -1,0 +1,148 @@
+"""GPU parity of the GMRES solve against the CPU oracle (through the C ABI), plus the solver's
+edge cases (zero source, non-finite source, iteration cap)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import dev, host, relerr, say
+from oracle import krylov as kr
+from oracle import operator2d as op2
+from oracle import operator3d as op3
+from paper_1802_03061_amd import inputs
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def rte():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1802_03061_amd import rte as r
+    r.load()
+    return r
+
+
+def _lu(f, L, ny, nx, h, mu_a, mu_s, sh):
+    mu_t = mu_a + mu_s
+    A = op2.dense_A(ny, nx, L, h, mu_t, mu_s, sh)
+    b = op2.rhs(f, L, h, mu_t, method="direct")
+    return kr.solve_dense(A, b.reshape(-1)).reshape(b.shape)
+
+
+def test_solve_iso32_fp64_vs_lu(rte):
+    """32x32 isotropic, mu_a = 0.1, mu_s = 1, centred Gaussian, FP64, GMRES to 1e-10."""
+    say("solve iso32 fp64")
+    w = inputs.workload("iso32")
+    ctx = rte.Context(32, mu_a=w["mu_a"], mu_s=w["mu_s"], L=0, prec=rte.PREC_FP64)
+    u, info = ctx.solve(dev(w["f"]), tol=1e-10)
+    say("  info", info)
+    ref = _lu(w["f"], 0, 32, 32, 1 / 32, w["mu_a"], w["mu_s"], w["sigma_hat"])
+    e = relerr(host(u), ref)
+    say("  relerr vs LU", e)
+    assert e <= 1e-10
+    assert info["relres_true"] <= 1e-10
+    with open(os.path.join(GOLDEN, "iso32_summary.json")) as fh:
+        gold = json.load(fh)
+    uu = host(u)[0].real
+    for (iy, ix), val in zip(gold["cells"], gold["values"]):
+        assert abs(uu[iy, ix] - val) <= 1e-9 * abs(val)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec,tol_err", [(1, 1e-10), (0, 1e-6)])
+@pytest.mark.parametrize("L,ny,nx,mu_s", [(3, 12, 12, 2.0), (1, 10, 14, 5.0), (8, 8, 8, 10.0)])
+def test_solve_aniso_small_vs_lu(rte, prec, tol_err, L, ny, nx, mu_s):
+    say("solve small", L, ny, nx, mu_s, "prec", prec)
+    rng = np.random.default_rng(L + ny)
+    h = 1.0 / max(nx, ny)
+    mu_a = 0.1
+    sh = inputs.hg_sigma_hat(0.5, L)
+    f = rng.random((ny, nx))
+    ctx = rte.Context((nx, ny), h=h, mu_a=mu_a, mu_s=mu_s, sigma_hat=sh, L=L, prec=prec)
+    u, info = ctx.solve(dev(f), tol=1e-11)
+    say("  info", info)
+    ref = _lu(f, L, ny, nx, h, mu_a, mu_s, sh)
+    e = relerr(host(u), ref)
+    say("  relerr vs LU", e)
+    assert e <= tol_err
+    ctx.close()
+
+
+def test_solve_hg512_full_size_residual(rte):
+    """512^2, HG g = 0.5, L = 8, mu_s = 10, FP32 apply + FP64 Krylov, tol 1e-8: the oracle's FP64
+    FFT apply confirms the true residual of the GPU solution."""
+    say("solve hg512 L8 mu_s 10")
+    w = inputs.workload("hg512", seed=0, mu_s=10.0)
+    n, L = w["n"], w["L"]
+    ctx = rte.Context(n, mu_a=w["mu_a"], mu_s=w["mu_s"], sigma_hat=w["sigma_hat"], L=L, prec=rte.PREC_FP32)
+    u, info = ctx.solve(dev(w["f"]), tol=1e-8)
+    say("  info", info)
+    uu = host(u)
+    h, mu_t = 1.0 / n, w["mu_a"] + w["mu_s"]
+    spectra = op2.kernel_spectra(n, n, L, h, mu_t)
+    b = op2.rhs(w["f"], L, h, mu_t, spectra=spectra)
+    r = b - op2.apply_fft(uu, L, h, mu_t, w["mu_s"], w["sigma_hat"], "A", spectra=spectra)
+    rr = np.linalg.norm(r) / np.linalg.norm(b)
+    say("  oracle true residual", rr)
+    assert rr <= 1.5e-8
+    # conjugate symmetry of the output modes
+    assert np.abs(uu[L + 3] - np.conj(uu[L - 3])).max() <= 1e-12 * np.abs(uu).max()
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_solve_3d_small_vs_lu(rte, prec):
+    say("solve 3d small prec", prec)
+    n, h, mu_a, mu_s = 8, 1.0 / 8, 0.05, 4.0
+    f = inputs.gaussian_mixture_source(n, inputs.gaussian_mixture_params(np.random.default_rng(2), 3), 3)
+    ctx = rte.Context(n, dim=3, h=h, mu_a=mu_a, mu_s=mu_s, L=0, prec=prec)
+    u, info = ctx.solve(dev(f), tol=1e-11)
+    say("  info", info)
+    A = op3.dense_A(n, n, n, h, mu_a + mu_s, mu_s)
+    b = op3.dense_Ktilde(n, n, n, h, mu_a + mu_s) @ f.reshape(-1)
+    ref = np.linalg.solve(A, b).reshape(f.shape)
+    e = relerr(host(u)[0].real, ref)
+    say("  relerr vs LU", e)
+    assert e <= (1e-10 if prec == 1 else 1e-6)
+    ctx.close()
+
+
+def test_solve_zero_source_gives_zero(rte):
+    ctx = rte.Context(16, mu_a=0.1, mu_s=1.0, L=2, sigma_hat=[1, .5, .25], prec=0)
+    u, info = ctx.solve(torch.zeros((16, 16), dtype=torch.float64, device="cuda"), tol=1e-8)
+    assert info["status"] == rte.RTE_OK
+    assert float(u.abs().max()) == 0.0
+    ctx.close()
+
+
+def test_solve_nonfinite_source_is_enumeric(rte):
+    ctx = rte.Context(16, mu_a=0.1, mu_s=1.0, L=0, prec=1)
+    f = torch.ones((16, 16), dtype=torch.float64, device="cuda")
+    f[3, 4] = float("nan")
+    with pytest.raises(rte.RteError) as ei:
+        ctx.solve(f, tol=1e-8)
+    assert ei.value.code == rte.RTE_ENUMERIC
+    ctx.close()
+
+
+def test_solve_iteration_cap_reports_not_converged(rte):
+    ctx = rte.Context(32, mu_a=0.01, mu_s=20.0, L=0, prec=1)
+    f = dev(inputs.centred_gaussian_source(32))
+    u, info = ctx.solve(f, tol=1e-12, max_iter=1, allow_not_converged=True)
+    assert info["status"] == rte.RTE_NOT_CONVERGED
+    assert info["iterations"] == 1
+    assert 0 < info["relres_true"] < 1
+    ctx.close()
+
+
+def test_solve_bad_tolerance_is_einval(rte):
+    ctx = rte.Context(16, mu_a=0.1, mu_s=1.0, L=0, prec=1)
+    f = torch.ones((16, 16), dtype=torch.float64, device="cuda")
+    for tol in (0.0, -1.0, 1.5):
+        with pytest.raises(rte.RteError) as ei:
+            ctx.solve(f, tol=tol)
+        assert ei.value.code == rte.RTE_EINVAL
+    ctx.close()
