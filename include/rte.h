@@ -79,8 +79,9 @@ typedef struct {
     int max_cycles;      /* refinement cycles (default 8) */
     double inner_tol;    /* per-cycle relative reduction for the FP32 inner solve (default 1e-5;
                             ignored for RTE_PREC_FP64, whose cycles run to the requested tol) */
-    int always_reorth;   /* 0: classical Gram-Schmidt with a second pass only when the norm drops
-                            below 1/sqrt(2) of its value (default); 1: always two passes */
+    int reorth;          /* classical Gram-Schmidt passes: 0 = one pass (default; each restart
+                            cycle ends with an FP64 true-residual check), 1 = a second pass when
+                            the norm drops below 1/sqrt(2) of its value, 2 = always two passes */
     int use_pc;          /* 1: flexible GMRES with the attached preconditioner (default 1 if one
                             is attached) */
 } rte_solve_opts;

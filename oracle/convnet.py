@@ -84,6 +84,36 @@ def pc_loss(r: np.ndarray, e: np.ndarray, params):
     return loss, grads
 
 
+def coarse_loss(x: np.ndarray, t: np.ndarray, w: np.ndarray, params):
+    """Mean over the batch of w_b ||N(x_b) - t_b||^2 and its parameter gradients.
+
+    This is the training objective of the coarse-grid correction z = v + s P N(R v / s) (R: F x F
+    block average, P: piecewise-constant prolongation, s: RMS of R v): with x = R r / s and
+    t = R(e - r) / s, ||r + s P N(x) - e||^2 = ||(I - P R)(r - e)||^2 + F^2 s^2 ||N(x) - t||^2
+    because P R is the orthogonal projector onto block-constant fields, so the fine-grid relative
+    loss ||r + s P N(x) - e||^2 / ||e||^2 differs from w ||N(x) - t||^2 (w = F^2 s^2 / ||e||^2)
+    only by a term independent of the network."""
+    out, cache = net_forward(x, params)
+    diff = out - t
+    B = x.shape[0]
+    per = np.array([np.sum(diff[b] ** 2) for b in range(B)])
+    loss = float(np.sum(w * per) / B)
+    gout = 2.0 * diff * (w / B)[:, None, None, None]
+    grads, _ = net_backward(gout, params, cache)
+    return loss, grads
+
+
+def restrict(v: np.ndarray, F: int) -> np.ndarray:
+    """F x F block average of [..., H, W] (H, W multiples of F)."""
+    *lead, H, W = v.shape
+    return v.reshape(*lead, H // F, F, W // F, F).mean(axis=(-3, -1))
+
+
+def prolong(vc: np.ndarray, F: int) -> np.ndarray:
+    """Piecewise-constant prolongation: each coarse value fills its F x F block."""
+    return np.repeat(np.repeat(vc, F, axis=-2), F, axis=-1)
+
+
 def adam_step(param, grad, m, v, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     """One Adam update (Kingma and Ba), bias-corrected; returns new (param, m, v)."""
     m = beta1 * m + (1 - beta1) * grad

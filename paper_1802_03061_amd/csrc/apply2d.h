@@ -13,12 +13,13 @@ struct ChanScale {
 template <typename T>
 struct Apply2DArgs {
     int nx, ny, PX, PY, L, C;
-    cx<T>* work;               // work buffer [nbatch][C][PX/2+1][ny]
-    cx<T>* work2;              // split pass B only: [nbatch][C][PX/2+1][PY] (may be null otherwise)
+    cx<T>* work;               // work buffer [nbatch][C][NKS][ny], NKS = pack ? PX/2 : PX/2+1
+    cx<T>* work2;              // split pass B only: [nbatch][C][NKS][PY] (may be null otherwise)
     const cx<T>* Q;            // quarter spectra [2L+1][PX/2+1][PY/2+1], scaled by 1/(PX PY)
     const cx<T>* twx;          // exp(-2 pi i q/PX), q < PX
     const cx<T>* twy;          // exp(-2 pi i q/PY), q < PY
     hipStream_t stream;
+    int pack;                  // 1: x-frequencies 0 and PX/2 share column 0 of the work buffer
 };
 
 // y = x - K~ D x (APPLY_A), K~ x (APPLY_KT) or b - (x - K~ D x) (APPLY_RESID) on nbatch channel

@@ -19,6 +19,9 @@
 //   pass C  per (channel, tile of rows): inverse FFT along x (complex-to-real), crop to nx, and
 //           finalise y = x - v (operator A), y = v (K~), or y = b - x + v (residual)
 //
+// In 2D the x-frequencies 0 and PX/2 (real for real rows) share one complex column, so T has
+// exactly PX/2 columns and pass B an even number of blocks.
+//
 // The kernel spectra are read from a quarter table Q[m][kx][ky], m = 0..2L, kx <= PX/2,
 // ky <= PY/2, using Khat_m(kx, -ky) = (-1)^m conj Khat_m(kx, ky) (mirror symmetry of the square
 // grid) and Khat_{-m} = (-1)^m conj Khat_m; the 1/(PX PY) of the inverse FFT is folded into Q.
@@ -29,42 +32,65 @@
 namespace rte {
 
 // ---------------------------------------------------------------------------- pass A --------
+// With pack != 0 the x-frequencies 0 and PX/2, whose values are real for real rows, share
+// column 0 of T as (X[0], X[PX/2]); T then has PX/2 columns.
 template <typename T, int PX, int TR, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_pass_a(const double* __restrict__ x, cx<T>* __restrict__ Tb,
                                                  const cx<T>* __restrict__ tw, int nx, int ny, int C,
-                                                 ChanScale sc) {
+                                                 ChanScale sc, int pack) {
     constexpr int NP = TR / 2;        // complex FFTs per block (two real rows each)
-    constexpr int LD = PX;
-    constexpr int NK = PX / 2 + 1;    // stored x-frequencies
+    constexpr int LD = padded(PX) + 1;   // odd row pitch: the NP transforms start on different banks
+    constexpr int H = PX / 2;
     __shared__ cx<T> buf[NP * LD];
+    __shared__ cx<T> tws[PX];
     const int tid = threadIdx.x;
     const int bc = blockIdx.y;
     const int c = bc % C;
     const int y0 = blockIdx.x * TR;
-    const T s = (T)sc.s[c];
+    const double s = sc.s[c];
     const double* xin = x + (size_t)bc * ny * nx;
-    for (int idx = tid; idx < NP * PX; idx += NTHR) {
-        const int p = idx / PX, m = idx % PX;
+    stage_twiddles<T, PX, NTHR>(tws, tw, tid);
+    // rows y0+2p (real part) and y0+2p+1 (imaginary part); only m < nx <= PX/2 is non-zero
+    constexpr int NL = NP * H;
+    constexpr int IT = (NL + NTHR - 1) / NTHR;
+    double ra[IT], rb[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int idx = tid + it * NTHR;
+        const int p = idx / H, m = idx % H;
         const int ya = y0 + 2 * p, yb = ya + 1;
-        T re = 0, im = 0;
-        if (m < nx) {
-            if (ya < ny) re = s * (T)xin[(size_t)ya * nx + m];
-            if (yb < ny) im = s * (T)xin[(size_t)yb * nx + m];
+        const bool ok = (NL % NTHR == 0 || idx < NL) && m < nx;
+        ra[it] = (ok && ya < ny) ? xin[(size_t)ya * nx + m] : 0.0;
+        rb[it] = (ok && yb < ny) ? xin[(size_t)yb * nx + m] : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int idx = tid + it * NTHR;
+        if (NL % NTHR == 0 || idx < NL) {
+            const int p = idx / H, m = idx % H;
+            buf[p * LD + sw(m)] = mk((T)(s * ra[it]), (T)(s * rb[it]));
+            buf[p * LD + sw(m + H)] = mk((T)0, (T)0);
         }
-        buf[p * LD + m] = mk(re, im);
     }
     __syncthreads();
-    block_fft<T, PX, NP, LD, NTHR, false>(buf, tw, tid);
-    cx<T>* out = Tb + (size_t)bc * NK * ny;
-    for (int idx = tid; idx < NK * TR; idx += NTHR) {
+    block_fft<T, PX, NP, LD, NTHR, false>(buf, tws, tid);
+    const int NKS = pack ? H : H + 1;
+    cx<T>* out = Tb + (size_t)bc * NKS * ny;
+    for (int idx = tid; idx < NKS * TR; idx += NTHR) {
         const int yl = idx % TR, k = idx / TR;
         const int y = y0 + yl;
         if (y < ny) {
             const int p = yl >> 1;
-            const cx<T> z = buf[p * LD + k];
-            const cx<T> zc = conj(buf[p * LD + ((PX - k) & (PX - 1))]);
-            // X_a = (Z + conj Z(-k))/2,  X_b = (Z - conj Z(-k))/(2i)
-            const cx<T> X = (yl & 1) ? scale(mul_mi(z - zc), (T)0.5) : scale(z + zc, (T)0.5);
+            cx<T> X;
+            if (pack && k == 0) {
+                const cx<T> z0 = buf[p * LD + sw(0)], zh = buf[p * LD + sw(H)];
+                X = (yl & 1) ? mk(z0.im, zh.im) : mk(z0.re, zh.re);
+            } else {
+                const cx<T> z = buf[p * LD + sw(k)];
+                const cx<T> zc = conj(buf[p * LD + sw((PX - k) & (PX - 1))]);
+                // X_a = (Z + conj Z(-k))/2,  X_b = (Z - conj Z(-k))/(2i)
+                X = (yl & 1) ? scale(mul_mi(z - zc), (T)0.5) : scale(z + zc, (T)0.5);
+            }
             out[(size_t)k * ny + y] = X;
         }
     }
@@ -74,39 +100,79 @@ __global__ __launch_bounds__(NTHR) void k_pass_a(const double* __restrict__ x, c
 template <typename T, int PX, int TR, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_pass_c(const cx<T>* __restrict__ Tb, const double* __restrict__ xin,
                                                  const double* __restrict__ bin, double* __restrict__ yout,
-                                                 const cx<T>* __restrict__ tw, int nx, int ny, int mode) {
+                                                 const cx<T>* __restrict__ tw, int nx, int ny, int mode, int pack) {
     constexpr int NP = TR / 2;
-    constexpr int LD = PX;
-    constexpr int NK = PX / 2 + 1;
+    constexpr int LD = padded(PX) + 1;   // odd row pitch: the NP transforms start on different banks
+    constexpr int H = PX / 2;
     __shared__ cx<T> buf[NP * LD];
+    __shared__ cx<T> tws[PX];
     const int tid = threadIdx.x;
     const int bc = blockIdx.y;
     const int y0 = blockIdx.x * TR;
-    const cx<T>* src = Tb + (size_t)bc * NK * ny;
-    for (int idx = tid; idx < NK * NP; idx += NTHR) {
+    const int NKS = pack ? H : H + 1;
+    const cx<T>* src = Tb + (size_t)bc * NKS * ny;
+    stage_twiddles<T, PX, NTHR>(tws, tw, tid);
+    constexpr int NL = (H + 1) * NP;
+    constexpr int IT = (NL + NTHR - 1) / NTHR;
+    cx<T> xa[IT], xb[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int idx = tid + it * NTHR;
         const int p = idx % NP, k = idx / NP;
         const int ya = y0 + 2 * p, yb = ya + 1;
-        cx<T> Xa = ya < ny ? src[(size_t)k * ny + ya] : mk((T)0, (T)0);
-        cx<T> Xb = yb < ny ? src[(size_t)k * ny + yb] : mk((T)0, (T)0);
-        if (k == 0 || k == PX / 2) { Xa.im = 0; Xb.im = 0; }
-        buf[p * LD + k] = Xa + mul_i(Xb);
-        if (k > 0 && k < PX / 2) buf[p * LD + PX - k] = conj(Xa) + mul_i(conj(Xb));
+        const bool ok = k < NKS;
+        xa[it] = (ok && ya < ny) ? src[(size_t)k * ny + ya] : mk((T)0, (T)0);
+        xb[it] = (ok && yb < ny) ? src[(size_t)k * ny + yb] : mk((T)0, (T)0);
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int idx = tid + it * NTHR;
+        const int p = idx % NP, k = idx / NP;
+        if (k < NKS) {
+            cx<T> Xa = xa[it], Xb = xb[it];
+            if (pack && k == 0) {   // (X[0], X[PX/2]) of rows a and b
+                buf[p * LD + sw(0)] = mk(Xa.re, Xb.re);
+                buf[p * LD + sw(H)] = mk(Xa.im, Xb.im);
+            } else {
+                if (k == 0 || k == H) { Xa.im = 0; Xb.im = 0; }
+                buf[p * LD + sw(k)] = Xa + mul_i(Xb);
+                if (k > 0 && k < H) buf[p * LD + sw(PX - k)] = conj(Xa) + mul_i(conj(Xb));
+            }
+        }
     }
     __syncthreads();
-    block_fft<T, PX, NP, LD, NTHR, true>(buf, tw, tid);
+    block_fft<T, PX, NP, LD, NTHR, true>(buf, tws, tid);
     const size_t base = (size_t)bc * ny * nx;
-    for (int idx = tid; idx < TR * nx; idx += NTHR) {
-        const int yl = idx / nx, m = idx % nx;
-        const int y = y0 + yl;
-        if (y < ny) {
-            const cx<T> z = buf[(yl >> 1) * LD + m];
-            const double v = (double)((yl & 1) ? z.im : z.re);
+    // finalise in chunks of CH iterations so the batched loads stay in a modest register budget
+    constexpr int NO = TR * H;
+    constexpr int IO = (NO + NTHR - 1) / NTHR;
+    constexpr int CH = IO < 8 ? IO : 8;
+    for (int i0 = 0; i0 < IO; i0 += CH) {
+        double xv[CH], bv[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int idx = tid + (i0 + u) * NTHR;
+            const int yl = idx / H, m = idx % H;
+            const int y = y0 + yl;
+            const bool ok = idx < NO && m < nx && y < ny;
             const size_t o = base + (size_t)y * nx + m;
-            double r;
-            if (mode == APPLY_A) r = xin[o] - v;
-            else if (mode == APPLY_KT) r = v;
-            else r = bin[o] - xin[o] + v;       // APPLY_RESID: b - A x
-            yout[o] = r;
+            xv[u] = (ok && mode != APPLY_KT) ? xin[o] : 0.0;
+            bv[u] = (ok && mode == APPLY_RESID) ? bin[o] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int idx = tid + (i0 + u) * NTHR;
+            const int yl = idx / H, m = idx % H;
+            const int y = y0 + yl;
+            if (idx < NO && m < nx && y < ny) {
+                const cx<T> z = buf[(yl >> 1) * LD + sw(m)];
+                const double v = (double)((yl & 1) ? z.im : z.re);
+                double r;
+                if (mode == APPLY_A) r = xv[u] - v;
+                else if (mode == APPLY_KT) r = v;
+                else r = bv[u] - xv[u] + v;       // APPLY_RESID: b - A x
+                yout[base + (size_t)y * nx + m] = r;
+            }
         }
     }
 }
@@ -118,7 +184,7 @@ static void launch_a(const Apply2DArgs<T>& a, const double* x, const ChanScale& 
     constexpr int TR = tile_rows<T>();
     dim3 grid((a.ny + TR - 1) / TR, nchan_total);
     hipLaunchKernelGGL((k_pass_a<T, PX, TR, 256>), grid, dim3(256), 0, a.stream, x, a.work, a.twx, a.nx,
-                       a.ny, a.C, sc);
+                       a.ny, a.C, sc, a.pack);
 }
 
 template <typename T, int PX>
@@ -127,7 +193,7 @@ static void launch_c(const Apply2DArgs<T>& a, const double* x, const double* b, 
     constexpr int TR = tile_rows<T>();
     dim3 grid((a.ny + TR - 1) / TR, nchan_total);
     hipLaunchKernelGGL((k_pass_c<T, PX, TR, 256>), grid, dim3(256), 0, a.stream, a.work, x, b, y, a.twx,
-                       a.nx, a.ny, mode);
+                       a.nx, a.ny, mode, a.pack);
 }
 
 #define RTE_P_SWITCH(P, FN, ...)                  \

@@ -62,74 +62,198 @@ __device__ __forceinline__ void couple_modes(cx<T>* v /* C values, in/out */, co
     }
 }
 
+// The same coupling reading the C channel values at base[c * stride] and writing the result back
+// in place, one output pair (V_k, V_{-k}) at a time; only W and the 2L+1 kernel values stay live.
+template <typename T, int L>
+__device__ __forceinline__ void couple_inplace(cx<T>* base, int stride, const cx<T>* __restrict__ Q,
+                                               size_t qstride_m, size_t qoff, bool flip) {
+    constexpr int C = 2 * L + 1;
+    const T r2 = (T)0.70710678118654752440084436210485;
+    cx<T> Kp[2 * L + 1];
+#pragma unroll
+    for (int m = 0; m <= 2 * L; ++m) {
+        cx<T> K = Q[m * qstride_m + qoff];
+        if (flip) { K.im = -K.im; if (m & 1) { K.re = -K.re; K.im = -K.im; } }
+        Kp[m] = K;
+    }
+    cx<T> W[C];
+    W[L] = base[0];
+#pragma unroll
+    for (int k = 1; k <= L; ++k) {
+        const cx<T> a = base[(2 * k - 1) * stride], bb = base[2 * k * stride];
+        W[L + k] = scale(a + mul_i(bb), r2);
+        W[L - k] = scale(a - mul_i(bb), r2);
+    }
+#pragma unroll
+    for (int k = 0; k <= L; ++k) {
+        cx<T> Vp = mk((T)0, (T)0), Vm = mk((T)0, (T)0);
+#pragma unroll
+        for (int kp = -L; kp <= L; ++kp) {
+            const int mp = kp - k;           // Khat_{kp-k} multiplies W_kp in V_k
+            cx<T> Ka = mp >= 0 ? Kp[mp] : conj(Kp[-mp]);
+            if (mp < 0 && ((-mp) & 1)) { Ka.re = -Ka.re; Ka.im = -Ka.im; }
+            cmac(Vp, Ka, W[kp + L]);
+            if (k > 0) {
+                const int mm = kp + k;       // Khat_{kp+k} multiplies W_kp in V_{-k}
+                cx<T> Kb = mm >= 0 ? Kp[mm] : conj(Kp[-mm]);
+                if (mm < 0 && ((-mm) & 1)) { Kb.re = -Kb.re; Kb.im = -Kb.im; }
+                cmac(Vm, Kb, W[kp + L]);
+            }
+        }
+        if (k == 0) {
+            base[0] = Vp;
+        } else {
+            base[(2 * k - 1) * stride] = scale(Vp + Vm, r2);
+            base[2 * k * stride] = scale(mul_mi(Vp - Vm), r2);
+        }
+    }
+}
+
+// Column 0 of a packed work buffer holds z = d + i q with d, q the (real) x-frequency-0 and
+// x-frequency-PX/2 sequences in y.  At y-frequency f (and its mirror -f):
+// D = (Z(f) + conj Z(-f))/2 and Q = (Z(f) - conj Z(-f))/(2i) are their spectra; each is coupled
+// with its own kernel column and Z(f) = D' + i Q', Z(-f) = conj D' + i conj Q' recombined
+// (D' and Q' are spectra of real sequences).  p(c) addresses Z(f) of channel c, pm(c) Z(-f); the
+// coupled D' is parked in the Z(f) slot while Q is coupled, to keep few values live.
+template <typename T, int L, typename PF, typename PM>
+__device__ __forceinline__ void couple_packed_pair(PF p, PM pm, const cx<T>* __restrict__ Q, size_t qstride_m,
+                                                   size_t qoff_dc, size_t qoff_ny, bool self) {
+    constexpr int C = 2 * L + 1;
+    cx<T> v[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const cx<T> z = *p(c), w = conj(*pm(c));
+        v[c] = scale(z + w, (T)0.5);
+    }
+    couple_modes<T, L>(v, Q, qstride_m, qoff_dc, false);
+    cx<T> q[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const cx<T> z = *p(c), w = conj(*pm(c));
+        q[c] = scale(mul_mi(z - w), (T)0.5);
+        *p(c) = v[c];                       // park D'
+    }
+    couple_modes<T, L>(q, Q, qstride_m, qoff_ny, false);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const cx<T> d = *p(c);
+        *p(c) = d + mul_i(q[c]);
+        if (!self) *pm(c) = conj(d) + mul_i(conj(q[c]));
+    }
+}
+
 // Fused pass B: NCOL columns x C channels per block, spectra resident in LDS.
+// nkx = columns of the work buffer, nkq = columns of the kernel table (PX/2 + 1).
 template <typename T, int PY, int L, int NCOL, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_pass_b_lds(cx<T>* __restrict__ Tb, const cx<T>* __restrict__ Q,
-                                                     const cx<T>* __restrict__ tw, int ny, int nkx) {
+                                                     const cx<T>* __restrict__ tw, int ny, int nkx, int nkq,
+                                                     int pack) {
     constexpr int C = 2 * L + 1;
     constexpr int NF = NCOL * C;
-    constexpr int LD = PY;
+    constexpr int LD = padded(PY);
     constexpr int KH = PY / 2 + 1;
+    constexpr int HY = PY / 2;
     __shared__ cx<T> spec[NF * LD];
+    __shared__ cx<T> tws[PY];
+    __shared__ cx<T> pairtmp[2 * C];   // Q of the two self-mirrored frequencies of a packed column
     const int tid = threadIdx.x;
     const int kx0 = blockIdx.x * NCOL;
     const int b = blockIdx.y;
     const size_t cstride = (size_t)nkx * ny;
     cx<T>* base = Tb + (size_t)b * C * cstride;
-    // spec[(col * C + c) * LD + y]
-    for (int idx = tid; idx < NF * PY; idx += NTHR) {
-        const int y = idx % PY, fc = idx / PY;
+    stage_twiddles<T, PY, NTHR>(tws, tw, tid);
+    // spec[(col * C + c) * LD + sw(y)]; rows y < ny <= PY/2 come from memory, the rest is zero
+    constexpr int NL = NF * HY;
+    constexpr int IT = (NL + NTHR - 1) / NTHR;
+    cx<T> r[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int idx = tid + it * NTHR;
+        const int y = idx % HY, fc = idx / HY;
         const int col = fc / C, c = fc % C;
         const int kx = kx0 + col;
-        cx<T> v = mk((T)0, (T)0);
-        if (y < ny && kx < nkx) v = base[c * cstride + (size_t)kx * ny + y];
-        spec[fc * LD + y] = v;
+        const bool ok = (NL % NTHR == 0 || idx < NL) && y < ny && kx < nkx;
+        r[it] = ok ? base[c * cstride + (size_t)kx * ny + y] : mk((T)0, (T)0);
     }
-    __syncthreads();
-    block_fft<T, PY, NF, LD, NTHR, false>(spec, tw, tid);
-    for (int idx = tid; idx < NCOL * PY; idx += NTHR) {
-        const int f = idx % PY, col = idx / PY;
-        const int kx = kx0 + col;
-        if (kx < nkx) {
-            const bool flip = f > PY / 2;
-            const int fy = flip ? PY - f : f;
-            cx<T> v[C];
 #pragma unroll
-            for (int c = 0; c < C; ++c) v[c] = spec[(col * C + c) * LD + f];
-            couple_modes<T, L>(v, Q, (size_t)nkx * KH, (size_t)kx * KH + fy, flip);
-#pragma unroll
-            for (int c = 0; c < C; ++c) spec[(col * C + c) * LD + f] = v[c];
+    for (int it = 0; it < IT; ++it) {
+        const int idx = tid + it * NTHR;
+        if (NL % NTHR == 0 || idx < NL) {
+            const int y = idx % HY, fc = idx / HY;
+            spec[fc * LD + sw(y)] = r[it];
+            spec[fc * LD + sw(y + HY)] = mk((T)0, (T)0);
         }
     }
     __syncthreads();
-    block_fft<T, PY, NF, LD, NTHR, true>(spec, tw, tid);
-    for (int idx = tid; idx < NF * ny; idx += NTHR) {
-        const int y = idx % ny, fc = idx / ny;
+    // at most ~3 radix-8 butterflies per thread and stage
+    constexpr int G = (3 * NTHR * 8) / PY >= NF ? NF : ((3 * NTHR * 8) / PY < 1 ? 1 : (3 * NTHR * 8) / PY);
+    block_fft_grouped<T, PY, NF, G, LD, NTHR, false>(spec, tws, tid);
+    const size_t qs = (size_t)nkq * KH;
+#pragma unroll 1
+    for (int idx = tid; idx < NCOL * PY; idx += NTHR) {
+        const int f = idx % PY, col = idx / PY;
+        const int kx = kx0 + col;
+        if (kx >= nkx) continue;
+        cx<T>* sp = spec + col * C * LD;
+        if (pack && kx == 0) {
+            if (f > HY) continue;
+            const int fm = (PY - f) & (PY - 1);
+            const bool self = fm == f;
+            cx<T>* zf = sp + sw(f);
+            cx<T>* zq = self ? pairtmp + (f == 0 ? 0 : C) : sp + sw(fm);   // where Q is coupled
+            // split into the spectra D (kept at f) and Q of the two real sequences
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const cx<T> z = zf[c * LD], w = conj(self ? z : zq[c * LD]);
+                zf[c * LD] = scale(z + w, (T)0.5);
+                zq[c * (self ? 1 : LD)] = scale(mul_mi(z - w), (T)0.5);
+            }
+            couple_inplace<T, L>(zf, LD, Q, qs, (size_t)f, false);
+            couple_inplace<T, L>(zq, self ? 1 : LD, Q, qs, (size_t)(nkq - 1) * KH + f, false);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const cx<T> d = zf[c * LD], q = zq[c * (self ? 1 : LD)];
+                zf[c * LD] = d + mul_i(q);
+                if (!self) zq[c * LD] = conj(d) + mul_i(conj(q));
+            }
+        } else {
+            const bool flip = f > HY;
+            const int fy = flip ? PY - f : f;
+            couple_inplace<T, L>(sp + sw(f), LD, Q, qs, (size_t)kx * KH + fy, flip);
+        }
+    }
+    __syncthreads();
+    block_fft_grouped<T, PY, NF, G, LD, NTHR, true>(spec, tws, tid);
+    for (int idx = tid; idx < NL; idx += NTHR) {
+        const int y = idx % HY, fc = idx / HY;
         const int col = fc / C, c = fc % C;
         const int kx = kx0 + col;
-        if (kx < nkx) base[c * cstride + (size_t)kx * ny + y] = spec[fc * LD + y];
+        if (y < ny && kx < nkx) base[c * cstride + (size_t)kx * ny + y] = spec[fc * LD + sw(y)];
     }
 }
 
 // Split form, step 1/3: forward y-FFT of one (channel, column) into a full-length buffer.
 template <typename T, int PY, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_pass_b_fwd(const cx<T>* __restrict__ Tb, cx<T>* __restrict__ T2,
-                                                     const cx<T>* __restrict__ tw, int ny, int nkx, int C) {
-    __shared__ cx<T> buf[PY];
+                                                     const cx<T>* __restrict__ tw, int ny, int nkx) {
+    constexpr int LD = padded(PY);
+    __shared__ cx<T> buf[LD];
+    __shared__ cx<T> tws[PY];
     const int tid = threadIdx.x;
     const int kx = blockIdx.x, bc = blockIdx.y;
+    stage_twiddles<T, PY, NTHR>(tws, tw, tid);
     const cx<T>* src = Tb + ((size_t)bc * nkx + kx) * ny;
-    for (int y = tid; y < PY; y += NTHR) buf[y] = y < ny ? src[y] : mk((T)0, (T)0);
+    for (int y = tid; y < PY; y += NTHR) buf[sw(y)] = y < ny ? src[y] : mk((T)0, (T)0);
     __syncthreads();
-    block_fft<T, PY, 1, PY, NTHR, false>(buf, tw, tid);
+    block_fft<T, PY, 1, LD, NTHR, false>(buf, tws, tid);
     cx<T>* dst = T2 + ((size_t)bc * nkx + kx) * PY;
-    for (int y = tid; y < PY; y += NTHR) dst[y] = buf[y];
+    for (int y = tid; y < PY; y += NTHR) dst[y] = buf[sw(y)];
 }
 
 // Split form, step 2/3: pointwise coupling over all (kx, ky).
 template <typename T, int PY, int L>
 __global__ __launch_bounds__(256) void k_pass_b_couple(cx<T>* __restrict__ T2, const cx<T>* __restrict__ Q,
-                                                       int nkx) {
+                                                       int nkx, int nkq, int pack) {
     constexpr int C = 2 * L + 1;
     constexpr int KH = PY / 2 + 1;
     const int b = blockIdx.y;
@@ -137,33 +261,44 @@ __global__ __launch_bounds__(256) void k_pass_b_couple(cx<T>* __restrict__ T2, c
     if (idx >= (size_t)nkx * PY) return;
     const int kx = (int)(idx / PY), f = (int)(idx % PY);
     const size_t cstride = (size_t)nkx * PY;
-    cx<T>* p = T2 + (size_t)b * C * cstride + idx;
+    const size_t qs = (size_t)nkq * KH;
+    cx<T>* p = T2 + (size_t)b * C * cstride + (size_t)kx * PY;
+    if (pack && kx == 0) {
+        if (f > PY / 2) return;
+        const int fm = (PY - f) & (PY - 1);
+        couple_packed_pair<T, L>([&](int c) { return p + c * cstride + f; }, [&](int c) { return p + c * cstride + fm; },
+                                 Q, qs, (size_t)f, (size_t)(nkq - 1) * KH + f, fm == f);
+        return;
+    }
     const bool flip = f > PY / 2;
     const int fy = flip ? PY - f : f;
     cx<T> v[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) v[c] = p[c * cstride];
-    couple_modes<T, L>(v, Q, (size_t)nkx * KH, (size_t)kx * KH + fy, flip);
+    for (int c = 0; c < C; ++c) v[c] = p[c * cstride + f];
+    couple_modes<T, L>(v, Q, qs, (size_t)kx * KH + fy, flip);
 #pragma unroll
-    for (int c = 0; c < C; ++c) p[c * cstride] = v[c];
+    for (int c = 0; c < C; ++c) p[c * cstride + f] = v[c];
 }
 
 // Split form, step 3/3: inverse y-FFT and crop back into the work buffer.
 template <typename T, int PY, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_pass_b_inv(cx<T>* __restrict__ Tb, const cx<T>* __restrict__ T2,
                                                      const cx<T>* __restrict__ tw, int ny, int nkx) {
-    __shared__ cx<T> buf[PY];
+    constexpr int LD = padded(PY);
+    __shared__ cx<T> buf[LD];
+    __shared__ cx<T> tws[PY];
     const int tid = threadIdx.x;
     const int kx = blockIdx.x, bc = blockIdx.y;
+    stage_twiddles<T, PY, NTHR>(tws, tw, tid);
     const cx<T>* src = T2 + ((size_t)bc * nkx + kx) * PY;
-    for (int y = tid; y < PY; y += NTHR) buf[y] = src[y];
+    for (int y = tid; y < PY; y += NTHR) buf[sw(y)] = src[y];
     __syncthreads();
-    block_fft<T, PY, 1, PY, NTHR, true>(buf, tw, tid);
+    block_fft<T, PY, 1, LD, NTHR, true>(buf, tws, tid);
     cx<T>* dst = Tb + ((size_t)bc * nkx + kx) * ny;
-    for (int y = tid; y < ny; y += NTHR) dst[y] = buf[y];
+    for (int y = tid; y < ny; y += NTHR) dst[y] = buf[sw(y)];
 }
 
-constexpr int lds_budget() { return 150 * 1024; }
+constexpr int lds_budget() { return 160 * 1024; }
 
 template <typename T, int PY, int L>
 constexpr int ncol_for() {
@@ -171,13 +306,16 @@ constexpr int ncol_for() {
 }
 template <typename T, int PY, int L>
 constexpr bool fused_fits() {
-    // FP64 with L > 4 holds too many complex values per thread for the fused coupling
-    return (long)ncol_for<T, PY, L>() * (2 * L + 1) * PY * (long)sizeof(cx<T>) <= lds_budget() &&
+    // LDS: column spectra, twiddle table, and the pair scratch; FP64 with L > 4 is left to the
+    // split form (the fused FP64 coupling does not fit the register budget)
+    return ((long)ncol_for<T, PY, L>() * (2 * L + 1) * padded(PY) + PY + 2 * (2 * L + 1)) * (long)sizeof(cx<T>) <=
+               lds_budget() &&
            (sizeof(T) == 4 || L <= 4);
 }
 template <typename T, int NFPY>
 constexpr int nthr_for() {
-    // about 8 elements per thread, at most 512 threads (256 VGPRs per lane)
+    // about 8 elements per thread, at most 512 threads: the mode coupling keeps 2(2L+1) complex
+    // values per thread live, which does not fit the 128-VGPR budget of 1024-thread blocks
     return NFPY / 8 >= 512 ? 512 : (NFPY / 8 >= 256 ? 256 : (NFPY / 8 >= 128 ? 128 : 64));
 }
 
@@ -185,22 +323,24 @@ template <typename T, int PY>
 static int launch_py(const Apply2DArgs<T>& a, int nbatch) {
     constexpr int L = RTE_PASSB_L;
     constexpr int C = 2 * L + 1;
-    const int nkx = a.PX / 2 + 1;
+    const int nkq = a.PX / 2 + 1;
+    const int nkx = a.pack ? a.PX / 2 : nkq;
     if constexpr (fused_fits<T, PY, L>()) {
         constexpr int NCOL = ncol_for<T, PY, L>();
         constexpr int NT = nthr_for<T, NCOL * C * PY>();
         dim3 grid((nkx + NCOL - 1) / NCOL, nbatch);
         hipLaunchKernelGGL((k_pass_b_lds<T, PY, L, NCOL, NT>), grid, dim3(NT), 0, a.stream, a.work, a.Q,
-                           a.twy, a.ny, nkx);
+                           a.twy, a.ny, nkx, nkq, a.pack);
         return 0;
     } else {
         if (!a.work2) return -2;
         constexpr int NT = PY >= 256 ? 256 : (PY < 64 ? 64 : PY);
         dim3 g1(nkx, nbatch * C);
         hipLaunchKernelGGL((k_pass_b_fwd<T, PY, NT>), g1, dim3(NT), 0, a.stream, a.work, a.work2, a.twy, a.ny,
-                           nkx, C);
+                           nkx);
         dim3 g2((unsigned)(((size_t)nkx * PY + 255) / 256), nbatch);
-        hipLaunchKernelGGL((k_pass_b_couple<T, PY, L>), g2, dim3(256), 0, a.stream, a.work2, a.Q, nkx);
+        hipLaunchKernelGGL((k_pass_b_couple<T, PY, L>), g2, dim3(256), 0, a.stream, a.work2, a.Q, nkx, nkq,
+                           a.pack);
         hipLaunchKernelGGL((k_pass_b_inv<T, PY, NT>), g1, dim3(NT), 0, a.stream, a.work, a.work2, a.twy, a.ny,
                            nkx);
         return 0;

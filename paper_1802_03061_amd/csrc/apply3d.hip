@@ -16,37 +16,43 @@ namespace rte {
 template <typename T, int PY, int TZ, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_pass3_b(const cx<T>* __restrict__ T1, cx<T>* __restrict__ T2,
                                                   const cx<T>* __restrict__ tw, int ny, int nz, int nkx) {
-    __shared__ cx<T> buf[TZ * PY];
+    constexpr int LD = padded(PY) + 1;   // odd row pitch: the TZ transforms start on different banks
+    __shared__ cx<T> buf[TZ * LD];
+    __shared__ cx<T> tws[PY];
     const int tid = threadIdx.x;
     const int kx = blockIdx.x, z0 = blockIdx.y * TZ;
+    stage_twiddles<T, PY, NTHR>(tws, tw, tid);
     for (int idx = tid; idx < TZ * PY; idx += NTHR) {
         const int zl = idx / PY, y = idx % PY;
         const int z = z0 + zl;
-        buf[idx] = (z < nz && y < ny) ? T1[((size_t)z * nkx + kx) * ny + y] : mk((T)0, (T)0);
+        buf[zl * LD + sw(y)] = (z < nz && y < ny) ? T1[((size_t)z * nkx + kx) * ny + y] : mk((T)0, (T)0);
     }
     __syncthreads();
-    block_fft<T, PY, TZ, PY, NTHR, false>(buf, tw, tid);
+    block_fft<T, PY, TZ, LD, NTHR, false>(buf, tws, tid);
     for (int idx = tid; idx < TZ * PY; idx += NTHR) {
         const int zl = idx % TZ, ky = idx / TZ;
         const int z = z0 + zl;
-        if (z < nz) T2[((size_t)kx * PY + ky) * nz + z] = buf[zl * PY + ky];
+        if (z < nz) T2[((size_t)kx * PY + ky) * nz + z] = buf[zl * LD + sw(ky)];
     }
 }
 
 template <typename T, int PZ, int NC, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_pass3_c(cx<T>* __restrict__ T2, const T* __restrict__ Q3,
                                                   const cx<T>* __restrict__ tw, int nz, int PY, size_t ncol) {
-    __shared__ cx<T> buf[NC * PZ];
+    constexpr int LD = padded(PZ) + 1;
+    __shared__ cx<T> buf[NC * LD];
+    __shared__ cx<T> tws[PZ];
     const int tid = threadIdx.x;
     const size_t c0 = (size_t)blockIdx.x * NC;
     const int HY = PY / 2 + 1, HZ = PZ / 2 + 1;
+    stage_twiddles<T, PZ, NTHR>(tws, tw, tid);
     for (int idx = tid; idx < NC * PZ; idx += NTHR) {
         const int c = idx / PZ, z = idx % PZ;
         const size_t col = c0 + c;
-        buf[idx] = (col < ncol && z < nz) ? T2[col * nz + z] : mk((T)0, (T)0);
+        buf[c * LD + sw(z)] = (col < ncol && z < nz) ? T2[col * nz + z] : mk((T)0, (T)0);
     }
     __syncthreads();
-    block_fft<T, PZ, NC, PZ, NTHR, false>(buf, tw, tid);
+    block_fft<T, PZ, NC, LD, NTHR, false>(buf, tws, tid);
     for (int idx = tid; idx < NC * PZ; idx += NTHR) {
         const int c = idx / PZ, kz = idx % PZ;
         const size_t col = c0 + c;
@@ -54,35 +60,38 @@ __global__ __launch_bounds__(NTHR) void k_pass3_c(cx<T>* __restrict__ T2, const 
             const int kx = (int)(col / PY), ky = (int)(col % PY);
             const int fy = ky <= PY / 2 ? ky : PY - ky;
             const int fz = kz <= PZ / 2 ? kz : PZ - kz;
-            buf[idx] = scale(buf[idx], Q3[((size_t)kx * HY + fy) * HZ + fz]);
+            buf[c * LD + sw(kz)] = scale(buf[c * LD + sw(kz)], Q3[((size_t)kx * HY + fy) * HZ + fz]);
         }
     }
     __syncthreads();
-    block_fft<T, PZ, NC, PZ, NTHR, true>(buf, tw, tid);
+    block_fft<T, PZ, NC, LD, NTHR, true>(buf, tws, tid);
     for (int idx = tid; idx < NC * PZ; idx += NTHR) {
         const int c = idx / PZ, z = idx % PZ;
         const size_t col = c0 + c;
-        if (col < ncol && z < nz) T2[col * nz + z] = buf[idx];
+        if (col < ncol && z < nz) T2[col * nz + z] = buf[c * LD + sw(z)];
     }
 }
 
 template <typename T, int PY, int TZ, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_pass3_d(cx<T>* __restrict__ T1, const cx<T>* __restrict__ T2,
                                                   const cx<T>* __restrict__ tw, int ny, int nz, int nkx) {
-    __shared__ cx<T> buf[TZ * PY];
+    constexpr int LD = padded(PY) + 1;   // odd row pitch: the TZ transforms start on different banks
+    __shared__ cx<T> buf[TZ * LD];
+    __shared__ cx<T> tws[PY];
     const int tid = threadIdx.x;
     const int kx = blockIdx.x, z0 = blockIdx.y * TZ;
+    stage_twiddles<T, PY, NTHR>(tws, tw, tid);
     for (int idx = tid; idx < TZ * PY; idx += NTHR) {
         const int zl = idx % TZ, ky = idx / TZ;
         const int z = z0 + zl;
-        buf[zl * PY + ky] = z < nz ? T2[((size_t)kx * PY + ky) * nz + z] : mk((T)0, (T)0);
+        buf[zl * LD + sw(ky)] = z < nz ? T2[((size_t)kx * PY + ky) * nz + z] : mk((T)0, (T)0);
     }
     __syncthreads();
-    block_fft<T, PY, TZ, PY, NTHR, true>(buf, tw, tid);
+    block_fft<T, PY, TZ, LD, NTHR, true>(buf, tws, tid);
     for (int idx = tid; idx < TZ * ny; idx += NTHR) {
         const int zl = idx / ny, y = idx % ny;
         const int z = z0 + zl;
-        if (z < nz) T1[((size_t)z * nkx + kx) * ny + y] = buf[zl * PY + y];
+        if (z < nz) T1[((size_t)z * nkx + kx) * ny + y] = buf[zl * LD + sw(y)];
     }
 }
 

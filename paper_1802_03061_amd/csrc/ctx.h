@@ -42,6 +42,11 @@ struct rte_ctx {
     double* partial = nullptr;
     double* dsmall = nullptr;
     double* hsmall = nullptr;   // pinned
+    double* arn = nullptr;      // device Arnoldi state (H, Givens, g, estimates)
+    int* arn_flags = nullptr;   // [second pass, breakdown, non-finite, spare]
+    double* hpipe = nullptr;    // pinned per-iteration residual estimates
+    int* hpipe_flags = nullptr; // pinned per-iteration (breakdown, non-finite)
+    std::vector<hipEvent_t> ev_iter;
     rte_solve_opts opts{};
     // learned preconditioner (see nn.hip)
     bool pc_attached = false;

@@ -7,11 +7,18 @@
 // Stages run in place in LDS: every thread first reads and transforms all its butterflies into
 // registers, a barrier, then writes.  Radices are 8 (with one leading 2 or 4 stage when
 // log2 P is not a multiple of 3).  Twiddles come from a table tw[q] = exp(-2 pi i q / P)
-// computed in FP64 on the host and rounded to the working precision.
+// computed in FP64 on the host, rounded to the working precision and staged into LDS.
+//
+// LDS layout: element i of a transform lives at sw(i) = i + i/16, i.e. one pad slot per 16
+// elements.  The strided writes of the early stages (stride R or Ns elements) then fall on
+// different banks instead of repeating the same few.
 #pragma once
 #include "common.h"
 
 namespace rte {
+
+__device__ __forceinline__ int sw(int i) { return i + (i >> 4); }
+constexpr int padded(int P) { return P + P / 16; }
 
 constexpr int fft_radix(int P, int Ns) {
     // log2 of what remains to be combined
@@ -59,9 +66,9 @@ __device__ __forceinline__ void dft_small(cx<T>* v) {
     }
 }
 
-// One in-place Stockham stage over NFFT transforms of length P at buf + f*LD.
+// One in-place Stockham stage over NFFT transforms of length P at buf + f*LD (swizzled).
 template <typename T, int P, int NFFT, int LD, int NTHR, int R, int NS, bool INV>
-__device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* tw, int tid) {
     constexpr int NB = P / R;
     constexpr int TOTAL = NB * NFFT;
     constexpr int ITEMS = (TOTAL + NTHR - 1) / NTHR;
@@ -73,9 +80,9 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
         const int idx = tid + it * NTHR;
         if ((TOTAL % NTHR == 0) || idx < TOTAL) {
             const int f = idx / NB, j = idx % NB;
-            const cx<T>* src = buf + f * LD + j;
+            const cx<T>* src = buf + f * LD;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[it][r] = src[r * NB];
+            for (int r = 0; r < R; ++r) v[it][r] = src[sw(j + r * NB)];
             if constexpr (NS > 1) {
                 const int k = j % NS;
 #pragma unroll
@@ -95,16 +102,17 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* __restrict__ 
         if ((TOTAL % NTHR == 0) || idx < TOTAL) {
             const int f = idx / NB, j = idx % NB;
             const int k = j % NS;
-            cx<T>* dst = buf + f * LD + (j / NS) * S + k;
+            cx<T>* dst = buf + f * LD;
+            const int base = (j / NS) * S + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[r * NS] = v[it][r];
+            for (int r = 0; r < R; ++r) dst[sw(base + r * NS)] = v[it][r];
         }
     }
     __syncthreads();
 }
 
 template <typename T, int P, int NFFT, int LD, int NTHR, bool INV, int NS>
-__device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* tw, int tid) {
     if constexpr (NS < P) {
         constexpr int R = fft_radix(P, NS);
         fft_stage<T, P, NFFT, LD, NTHR, R, NS, INV>(buf, tw, tid);
@@ -113,11 +121,31 @@ __device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* __restrict__
 }
 
 // Unnormalised DFT (INV=false: exp(-2 pi i jk/P); INV=true: exp(+2 pi i jk/P)) of NFFT
-// transforms held in LDS.  Must be called by all NTHR threads; ends with a barrier.
+// transforms held in LDS at buf + f*LD, element i at sw(i); LD >= padded(P).  tw is the
+// twiddle table (LDS or global).  Must be called by all NTHR threads; ends with a barrier.
 template <typename T, int P, int NFFT, int LD, int NTHR, bool INV>
-__device__ __forceinline__ void block_fft(cx<T>* buf, const cx<T>* __restrict__ tw, int tid) {
+__device__ __forceinline__ void block_fft(cx<T>* buf, const cx<T>* tw, int tid) {
     static_assert(is_pow2(P) && P >= 2, "FFT length must be a power of two");
+    static_assert(LD >= P + P / 16, "LD must hold the padded transform");
     fft_stages<T, P, NFFT, LD, NTHR, INV, 1>(buf, tw, tid);
+}
+
+// The same over NFFT transforms processed in groups of at most G (fewer butterflies held in
+// registers per stage, at the price of more barriers).
+template <typename T, int P, int NFFT, int G, int LD, int NTHR, bool INV>
+__device__ __forceinline__ void block_fft_grouped(cx<T>* buf, const cx<T>* tw, int tid) {
+    if constexpr (NFFT <= G) {
+        block_fft<T, P, NFFT, LD, NTHR, INV>(buf, tw, tid);
+    } else {
+        block_fft<T, P, G, LD, NTHR, INV>(buf, tw, tid);
+        block_fft_grouped<T, P, NFFT - G, G, LD, NTHR, INV>(buf + G * LD, tw, tid);
+    }
+}
+
+// Copy the P-entry twiddle table into LDS (all threads; followed by the caller's barrier).
+template <typename T, int P, int NTHR>
+__device__ __forceinline__ void stage_twiddles(cx<T>* tws, const cx<T>* __restrict__ tw, int tid) {
+    for (int q = tid; q < P; q += NTHR) tws[q] = tw[q];
 }
 
 }  // namespace rte

@@ -35,8 +35,10 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // v = nvec holds sum w[i]^2 when with_norm.
 __global__ __launch_bounds__(KT) void k_dot_partial(const double* __restrict__ V, size_t ld, int nvec,
                                                     const double* __restrict__ w, size_t n,
-                                                    double* __restrict__ partial, int with_norm) {
+                                                    double* __restrict__ partial, int with_norm,
+                                                    const int* __restrict__ active) {
     __shared__ double sh[KT / 64];
+    if (active && *active == 0) return;
     const int nblk = gridDim.x;
     const int v0 = blockIdx.y * VB;
     const int nv = min(VB, nvec - v0);
@@ -65,8 +67,9 @@ __global__ __launch_bounds__(KT) void k_dot_partial(const double* __restrict__ V
 
 // out[v] = sum_b partial[v * nblk + b] in a fixed order.
 __global__ __launch_bounds__(KT) void k_reduce_partials(const double* __restrict__ partial, int nblk,
-                                                        double* __restrict__ out) {
+                                                        double* __restrict__ out, const int* __restrict__ active) {
     __shared__ double sh[KT / 64];
+    if (active && *active == 0) return;
     const int v = blockIdx.x;
     double s = 0.0;
     for (int b = threadIdx.x; b < nblk; b += KT) s += partial[(size_t)v * nblk + b];
@@ -77,9 +80,10 @@ __global__ __launch_bounds__(KT) void k_reduce_partials(const double* __restrict
 // w[i] -= sum_v V[v][i] h[v]; partial_norm[blk] = sum over the slice of w_new[i]^2.
 __global__ __launch_bounds__(KT) void k_cgs_update(double* __restrict__ w, const double* __restrict__ V, size_t ld,
                                                    int nvec, const double* __restrict__ h, size_t n,
-                                                   double* __restrict__ partial_norm) {
+                                                   double* __restrict__ partial_norm, const int* __restrict__ active) {
     __shared__ double sh[KT / 64];
     __shared__ double hs[RTE_KRYLOV_MAXVEC];
+    if (active && *active == 0) return;
     for (int v = threadIdx.x; v < nvec; v += KT) hs[v] = h[v];
     __syncthreads();
     double nrm = 0.0;
@@ -106,6 +110,58 @@ __global__ __launch_bounds__(KT) void k_combine(double* __restrict__ x, const do
         for (int v = 0; v < nvec; ++v) s += Z[(size_t)v * ld + i] * ys[v];
         x[i] = s;
     }
+}
+
+// dst[i] = (*a) * src[i] with the factor read from device memory
+__global__ __launch_bounds__(KT) void k_scale_dev(double* __restrict__ dst, const double* __restrict__ src,
+                                                  const double* __restrict__ a, size_t n) {
+    const double s = *a;
+    const size_t stride = (size_t)gridDim.x * KT;
+    for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) dst[i] = s * src[i];
+}
+
+// One Arnoldi column on the device.  stage 0: after the first Gram-Schmidt pass, decide whether
+// a second pass runs (reorth 2: always; 1: when the norm fell below 1/sqrt2 of its value; 0: never)
+// and store h into H[:, j].
+// stage 1: add the second pass, form H[j+1, j], apply the previous Givens rotations and a new
+// one, update the residual vector g, and write the estimate |g[j+1]| and 1/H[j+1, j].
+// st layout: [0..m] h pass 1 | [m+1] |w|^2 | [m+2] |w1|^2 | [m+4..2m+4] h pass 2
+__global__ void k_arnoldi(int stage, int j, int m, double* __restrict__ st, double* __restrict__ H,
+                          double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
+                          double* __restrict__ est, double* __restrict__ inv, int* __restrict__ flags, int reorth) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double* Hj = H + (size_t)j * (m + 1);
+    const double* h1 = st;
+    const double* h2 = st + m + 4;
+    if (stage == 0) {
+        for (int i = 0; i <= j; ++i) Hj[i] = h1[i];
+        flags[0] = (reorth == 2 || (reorth == 1 && st[j + 2] < 0.5 * st[j + 1])) ? 1 : 0;
+        st[m + 3] = st[j + 1];   // |w|^2 before orthogonalisation
+        return;
+    }
+    if (flags[0])
+        for (int i = 0; i <= j; ++i) Hj[i] += h2[i];
+    const double w0 = st[m + 3];
+    const double w1 = st[j + 2] > 0.0 ? st[j + 2] : 0.0;
+    const double hn = sqrt(w1);
+    Hj[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * Hj[i] + sn[i] * Hj[i + 1];
+        Hj[i + 1] = -sn[i] * Hj[i] + cs[i] * Hj[i + 1];
+        Hj[i] = t;
+    }
+    const double den = hypot(Hj[j], Hj[j + 1]);
+    if (den == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
+    else { cs[j] = Hj[j] / den; sn[j] = Hj[j + 1] / den; }
+    Hj[j] = den;
+    Hj[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    est[j] = fabs(g[j + 1]);
+    const bool breakdown = !(hn > 1e-14 * sqrt(w0 > 0.0 ? w0 : 0.0));
+    inv[j + 1] = breakdown ? 0.0 : 1.0 / hn;
+    flags[1] = breakdown ? 1 : 0;
+    if (!isfinite(den) || !isfinite(est[j])) flags[2] = 1;
 }
 
 // dst[i] = a * src[i]
@@ -181,20 +237,29 @@ static inline unsigned grid_for(size_t n, unsigned cap) {
 }
 
 void krylov_dots(const double* V, size_t ld, int nvec, const double* w, size_t n, double* partial,
-                 double* out, bool with_norm, hipStream_t st) {
+                 double* out, bool with_norm, hipStream_t st, const int* active) {
     const unsigned nblk = grid_for(n, RTE_KRYLOV_NBLK);
     dim3 grid(nblk, (nvec + VB - 1) / VB);
     if (nvec == 0) grid.y = 1;
-    hipLaunchKernelGGL(k_dot_partial, grid, dim3(KT), 0, st, V, ld, nvec, w, n, partial, with_norm ? 1 : 0);
+    hipLaunchKernelGGL(k_dot_partial, grid, dim3(KT), 0, st, V, ld, nvec, w, n, partial, with_norm ? 1 : 0, active);
     const int nout = nvec + (with_norm ? 1 : 0);
-    if (nout > 0) hipLaunchKernelGGL(k_reduce_partials, dim3(nout), dim3(KT), 0, st, partial, (int)nblk, out);
+    if (nout > 0) hipLaunchKernelGGL(k_reduce_partials, dim3(nout), dim3(KT), 0, st, partial, (int)nblk, out, active);
 }
 
 void krylov_update(double* w, const double* V, size_t ld, int nvec, const double* h, size_t n, double* partial,
-                   double* norm_out, hipStream_t st) {
+                   double* norm_out, hipStream_t st, const int* active) {
     const unsigned nblk = grid_for(n, RTE_KRYLOV_NBLK);
-    hipLaunchKernelGGL(k_cgs_update, dim3(nblk), dim3(KT), 0, st, w, V, ld, nvec, h, n, partial);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(KT), 0, st, partial, (int)nblk, norm_out);
+    hipLaunchKernelGGL(k_cgs_update, dim3(nblk), dim3(KT), 0, st, w, V, ld, nvec, h, n, partial, active);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(KT), 0, st, partial, (int)nblk, norm_out, active);
+}
+
+void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_dev, dim3(grid_for(n, 4096)), dim3(KT), 0, st, dst, src, a, n);
+}
+
+void arnoldi_step(int stage, int j, int m, double* st, double* H, double* cs, double* sn, double* g, double* est,
+                  double* inv, int* flags, int reorth, hipStream_t s) {
+    hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), 0, s, stage, j, m, st, H, cs, sn, g, est, inv, flags, reorth);
 }
 
 void krylov_combine(double* x, const double* Z, size_t ld, int nvec, const double* y, size_t n, hipStream_t st) {

@@ -75,8 +75,16 @@ static void free_krylov(rte_ctx* c) {
     dfree(c->Z);
     dfree(c->partial);
     dfree(c->dsmall);
+    dfree(c->arn);
+    dfree(c->arn_flags);
     if (c->hsmall) (void)hipHostFree(c->hsmall);
     c->hsmall = nullptr;
+    if (c->hpipe) (void)hipHostFree(c->hpipe);
+    c->hpipe = nullptr;
+    if (c->hpipe_flags) (void)hipHostFree(c->hpipe_flags);
+    c->hpipe_flags = nullptr;
+    for (auto& e : c->ev_iter) if (e) (void)hipEventDestroy(e);
+    c->ev_iter.clear();
     c->krylov_m = 0;
     c->krylov_z = false;
 }
@@ -116,8 +124,21 @@ int ensure_krylov(rte_ctx* c, int m, bool need_z) {
     if (need_z && (rc = dalloc(&c->Z, (size_t)m * n))) return rc;
     if ((rc = dalloc(&c->partial, (size_t)(m + 3) * RTE_KRYLOV_NBLK))) return rc;
     if ((rc = dalloc(&c->dsmall, (size_t)(2 * m + 16)))) return rc;
+    // device Arnoldi state: H [(m+1) x m] | cs [m] | sn [m] | g [m+1] | est [m] | inv [m+1]
+    if ((rc = dalloc(&c->arn, (size_t)(m + 1) * m + 4 * (size_t)m + 2))) return rc;
+    if ((rc = dalloc(&c->arn_flags, 4))) return rc;
     hipError_t e = hipHostMalloc((void**)&c->hsmall, (size_t)(2 * m + 16) * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) return set_hip_error(e, "hipHostMalloc", __FILE__, __LINE__);
+    // per-iteration pinned slots: estimate; (breakdown, non-finite) flags
+    e = hipHostMalloc((void**)&c->hpipe, (size_t)m * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) return set_hip_error(e, "hipHostMalloc", __FILE__, __LINE__);
+    e = hipHostMalloc((void**)&c->hpipe_flags, (size_t)2 * m * sizeof(int), hipHostMallocDefault);
+    if (e != hipSuccess) return set_hip_error(e, "hipHostMalloc", __FILE__, __LINE__);
+    c->ev_iter.assign(m, nullptr);
+    for (int i = 0; i < m; ++i) {
+        e = hipEventCreateWithFlags(&c->ev_iter[i], hipEventDisableTiming);
+        if (e != hipSuccess) return set_hip_error(e, "hipEventCreate", __FILE__, __LINE__);
+    }
     c->krylov_m = m;
     c->krylov_z = need_z;
     return RTE_OK;
@@ -153,6 +174,7 @@ static int apply_t(rte_ctx* c, int mode, const double* x, const double* b, doubl
     const ChanScale sc = channel_scale(c, mode);
     if (c->dim == 2) {
         Apply2DArgs<T> a = args2d<T>(c);
+        a.pack = 1;
         if (ev) (void)hipEventRecord(ev[0], c->stream);
         if (apply2d_pass_a<T>(a, x, sc, nbatch)) return set_error(RTE_EUNSUPPORTED, "pass A: unsupported size");
         if (ev) (void)hipEventRecord(ev[1], c->stream);
@@ -165,6 +187,7 @@ static int apply_t(rte_ctx* c, int mode, const double* x, const double* b, doubl
         Apply2DArgs<T> a = args2d<T>(c);
         a.C = 1;
         a.L = 0;
+        a.pack = 0;
         Apply3DArgs<T> a3;
         a3.nx = c->nx; a3.ny = c->ny; a3.nz = c->nz; a3.PX = c->PX; a3.PY = c->PY; a3.PZ = c->PZ;
         a3.stream = c->stream;
@@ -256,9 +279,18 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
     double rn = bn;
     int it = 0, cycles = 0, status = RTE_NOT_CONVERGED;
     double est = bn;
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), yv;
+    std::vector<double> H((size_t)(m + 1) * m), g(m + 1), yv;
     bool pc_live = use_pc;
 
+    double* dH = c->arn;
+    double* dcs = dH + (size_t)(m + 1) * m;
+    double* dsn = dcs + m;
+    double* dg = dsn + m;
+    double* dest = dg + m + 1;
+    double* dinv = dest + m;
+    int* dfl = c->arn_flags;
+    double* hp = c->hpipe;          // per-iteration residual estimates
+    int* hfl = c->hpipe_flags;      // per-iteration (breakdown, non-finite)
     while (true) {
         if (rn <= tol * bn) { status = RTE_OK; break; }
         if (cycles >= c->opts.max_cycles || it >= max_iter) { status = RTE_NOT_CONVERGED; break; }
@@ -267,85 +299,93 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
         if (mixed) target = std::max(target, c->opts.inner_tol * rn);
         vec_scale(c->V, c->rv, 1.0 / rn, n, st);
         std::fill(g.begin(), g.end(), 0.0);
-        std::fill(H.begin(), H.end(), 0.0);
         g[0] = rn;
+        RTE_HIP_TRY(hipMemcpyAsync(dg, g.data(), (m + 1) * sizeof(double), hipMemcpyHostToDevice, st));
+        RTE_HIP_TRY(hipMemsetAsync(dfl, 0, 4 * sizeof(int), st));
         est = rn;
         const double cycle_start_rn = rn;
-        int jd = 0;
-        for (int j = 0; j < m && it < max_iter; ++j) {
+        // Iterations are enqueued one ahead of the convergence check: when iteration j is queued the
+        // host reads the estimate of iteration j-1, so the device never waits for the host.
+        int jd = 0;           // columns of this cycle that are valid
+        int launched = 0;
+        bool stop = false, bad = false;
+        for (int j = 0; j < m && it + launched < max_iter && !stop; ++j) {
             double* vj = c->V + (size_t)j * n;
             double* w = c->V + (size_t)(j + 1) * n;
             const double* zj = vj;
-            if (pc_live) {
+            if (use_pc) {
                 double* z = c->Z + (size_t)j * n;
-                if ((rc = pc_apply(c, vj, z))) return rc;
-                zj = z;
-            } else if (use_pc) {
-                double* z = c->Z + (size_t)j * n;   // keep Z = V once the PC is dropped
-                RTE_HIP_TRY(hipMemcpyAsync(z, vj, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+                if (pc_live) {
+                    if ((rc = pc_apply(c, vj, z))) return rc;
+                } else {
+                    RTE_HIP_TRY(hipMemcpyAsync(z, vj, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+                }
                 zj = z;
             }
             if ((rc = apply_channels(c, APPLY_A, c->prec, zj, nullptr, w, 1))) return rc;
             ++inf.applies;
-            // classical Gram-Schmidt; a second pass when the norm dropped below 1/sqrt2 of its value
-            krylov_dots(c->V, n, j + 1, w, n, c->partial, c->dsmall, true, st);
-            krylov_update(w, c->V, n, j + 1, c->dsmall, n, c->partial, c->dsmall + j + 2, st);
-            RTE_HIP_TRY(hipMemcpyAsync(c->hsmall, c->dsmall, (j + 3) * sizeof(double), hipMemcpyDeviceToHost, st));
-            RTE_HIP_TRY(hipStreamSynchronize(st));
-            double* Hj = &H[(size_t)j * (m + 1)];
-            for (int i = 0; i <= j; ++i) Hj[i] = c->hsmall[i];
-            const double w0 = c->hsmall[j + 1];
-            double w1 = c->hsmall[j + 2];
-            if (c->opts.always_reorth || w1 < 0.5 * w0) {
-                krylov_dots(c->V, n, j + 1, w, n, c->partial, c->dsmall, false, st);
-                krylov_update(w, c->V, n, j + 1, c->dsmall, n, c->partial, c->dsmall + j + 2, st);
-                RTE_HIP_TRY(hipMemcpyAsync(c->hsmall, c->dsmall, (j + 3) * sizeof(double), hipMemcpyDeviceToHost, st));
-                RTE_HIP_TRY(hipStreamSynchronize(st));
-                for (int i = 0; i <= j; ++i) Hj[i] += c->hsmall[i];
-                w1 = c->hsmall[j + 2];
+            double* sd = c->dsmall;
+            krylov_dots(c->V, n, j + 1, w, n, c->partial, sd, true, st);
+            krylov_update(w, c->V, n, j + 1, sd, n, c->partial, sd + j + 2, st);
+            arnoldi_step(0, j, m, sd, dH, dcs, dsn, dg, dest, dinv, dfl, c->opts.reorth, st);
+            if (c->opts.reorth > 0) {   // second pass, skipped on the device unless flagged
+                krylov_dots(c->V, n, j + 1, w, n, c->partial, sd + m + 4, false, st, dfl);
+                krylov_update(w, c->V, n, j + 1, sd + m + 4, n, c->partial, sd + j + 2, st, dfl);
             }
-            const double hn = std::sqrt(std::max(w1, 0.0));
-            Hj[j + 1] = hn;
-            // Givens rotations (real)
-            for (int i = 0; i < j; ++i) {
-                const double t = cs[i] * Hj[i] + sn[i] * Hj[i + 1];
-                Hj[i + 1] = -sn[i] * Hj[i] + cs[i] * Hj[i + 1];
-                Hj[i] = t;
+            arnoldi_step(1, j, m, sd, dH, dcs, dsn, dg, dest, dinv, dfl, c->opts.reorth, st);
+            vec_scale_dev(w, w, dinv + j + 1, n, st);
+            RTE_HIP_TRY(hipMemcpyAsync(hp + j, dest + j, sizeof(double), hipMemcpyDeviceToHost, st));
+            RTE_HIP_TRY(hipMemcpyAsync(hfl + 2 * j, dfl + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+            RTE_HIP_TRY(hipEventRecord(c->ev_iter[j], st));
+            ++launched;
+            // check the previous iteration
+            if (j >= 1) {
+                RTE_HIP_TRY(hipEventSynchronize(c->ev_iter[j - 1]));
+                const double e1 = hp[j - 1];
+                if (hfl[2 * (j - 1) + 1] != 0 || !std::isfinite(e1)) { bad = true; stop = true; break; }
+                if (hfl[2 * (j - 1)] != 0) { est = e1; jd = j; stop = true; break; }   // breakdown: drop column j
+                est = e1;
+                jd = j;
+                if (e1 <= target) stop = true;                                  // column j is kept too
             }
-            const double den = std::hypot(Hj[j], Hj[j + 1]);
-            if (den == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
-            else { cs[j] = Hj[j] / den; sn[j] = Hj[j + 1] / den; }
-            Hj[j] = den;
-            Hj[j + 1] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            est = std::fabs(g[j + 1]);
-            ++it;
-            jd = j + 1;
-            if (!std::isfinite(est) || !std::isfinite(den)) {
-                if (pc_live) {   // a broken preconditioner: restart this cycle without it
-                    pc_live = false;
-                    inf.pc_fallback = 1;
-                    jd = 0;
-                    break;
-                }
-                inf.iterations = it;
-                inf.cycles = cycles;
-                if (info) *info = inf;
-                return set_error(RTE_ENUMERIC, "non-finite value in the Arnoldi process");
+        }
+        // settle the last enqueued iteration
+        RTE_HIP_TRY(hipStreamSynchronize(st));
+        if (!bad && launched > 0) {
+            const int jl = launched - 1;
+            const bool prev_brk = jl >= 1 && hfl[2 * (jl - 1)] != 0;
+            if (!prev_brk && jd == jl) {
+                if (hfl[2 * jl + 1] != 0 || !std::isfinite(hp[jl])) bad = true;
+                else { est = hp[jl]; jd = jl + 1; }
             }
-            if (rec && cycles == 1 && j < max_rec) {
-                back_solve(H, m + 1, g, jd, yv);
-                RTE_HIP_TRY(hipMemcpyAsync(c->dsmall, yv.data(), jd * sizeof(double), hipMemcpyHostToDevice, st));
-                double* xr = rec + (size_t)j * n;
-                vec_fill(xr, 0.0, n, st);
-                krylov_combine(xr, use_pc ? c->Z : c->V, n, jd, c->dsmall, n, st);
-                if (nrec) *nrec = j + 1;
+        }
+        it += launched;
+        if (bad) {
+            if (pc_live) {   // a broken preconditioner: restart this cycle without it
+                pc_live = false;
+                inf.pc_fallback = 1;
+                continue;
             }
-            if (hn <= 1e-14 * std::sqrt(std::max(w0, 0.0)) || est <= target) break;
-            vec_scale(w, w, 1.0 / hn, n, st);
+            inf.iterations = it;
+            inf.cycles = cycles;
+            if (info) *info = inf;
+            return set_error(RTE_ENUMERIC, "non-finite value in the Arnoldi process");
         }
         if (jd > 0) {
+            RTE_HIP_TRY(hipMemcpy(H.data(), dH, (size_t)(m + 1) * jd * sizeof(double), hipMemcpyDeviceToHost));
+            RTE_HIP_TRY(hipMemcpy(g.data(), dg, (m + 1) * sizeof(double), hipMemcpyDeviceToHost));
+            if (rec && cycles == 1) {
+                const int nr = std::min(jd, max_rec);
+                for (int k = 1; k <= nr; ++k) {
+                    back_solve(H, m + 1, g, k, yv);
+                    RTE_HIP_TRY(hipMemcpyAsync(c->dsmall, yv.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+                    double* xr = rec + (size_t)(k - 1) * n;
+                    vec_fill(xr, 0.0, n, st);
+                    krylov_combine(xr, use_pc ? c->Z : c->V, n, k, c->dsmall, n, st);
+                    RTE_HIP_TRY(hipStreamSynchronize(st));
+                }
+                if (nrec) *nrec = nr;
+            }
             back_solve(H, m + 1, g, jd, yv);
             RTE_HIP_TRY(hipMemcpyAsync(c->dsmall, yv.data(), jd * sizeof(double), hipMemcpyHostToDevice, st));
             krylov_combine(x, use_pc ? c->Z : c->V, n, jd, c->dsmall, n, st);
@@ -447,7 +487,7 @@ int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const 
     c->opts.restart = 64;
     c->opts.max_cycles = 8;
     c->opts.inner_tol = 1e-5;
-    c->opts.always_reorth = 0;
+    c->opts.reorth = 0;
     c->opts.use_pc = 1;
     hipError_t e = hipGetDevice(&c->device);
     if (e != hipSuccess) { free_ctx(c); return set_hip_error(e, "hipGetDevice", __FILE__, __LINE__); }
@@ -538,12 +578,13 @@ int rte_set_solve_opts(rte_ctx* c, const rte_solve_opts* o) {
     d.restart = 64;
     d.max_cycles = 8;
     d.inner_tol = 1e-5;
-    d.always_reorth = 0;
+    d.reorth = 0;
     d.use_pc = 1;
     if (o) {
         if (o->restart < 1 || o->restart > RTE_MAX_RESTART) return set_error(RTE_EINVAL, "restart must be in 1..%d", RTE_MAX_RESTART);
         if (o->max_cycles < 1) return set_error(RTE_EINVAL, "max_cycles must be >= 1");
         if (!(o->inner_tol > 0.0 && o->inner_tol < 1.0)) return set_error(RTE_EINVAL, "inner_tol must be in (0, 1)");
+        if (o->reorth < 0 || o->reorth > 2) return set_error(RTE_EINVAL, "reorth must be 0, 1 or 2");
         d = *o;
     }
     c->opts = d;

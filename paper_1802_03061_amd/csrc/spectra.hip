@@ -166,18 +166,21 @@ template <typename T, int P, bool INV>
 __global__ __launch_bounds__(256) void k_fft_rows(cx<T>* __restrict__ data, const cx<T>* __restrict__ tw,
                                                   size_t rows) {
     constexpr int RPB = P >= 2048 ? 1 : 2048 / P;
-    __shared__ cx<T> buf[RPB * P];
+    constexpr int LD = padded(P) + 1;
+    __shared__ cx<T> buf[RPB * LD];
+    __shared__ cx<T> tws[P];
     const size_t r0 = (size_t)blockIdx.x * RPB;
     const int tid = threadIdx.x;
+    stage_twiddles<T, P, 256>(tws, tw, tid);
     for (int idx = tid; idx < RPB * P; idx += 256) {
         const size_t r = r0 + idx / P;
-        buf[idx] = r < rows ? data[r * P + idx % P] : mk((T)0, (T)0);
+        buf[(idx / P) * LD + sw(idx % P)] = r < rows ? data[r * P + idx % P] : mk((T)0, (T)0);
     }
     __syncthreads();
-    block_fft<T, P, RPB, P, 256, INV>(buf, tw, tid);
+    block_fft<T, P, RPB, LD, 256, INV>(buf, tws, tid);
     for (int idx = tid; idx < RPB * P; idx += 256) {
         const size_t r = r0 + idx / P;
-        if (r < rows) data[r * P + idx % P] = buf[idx];
+        if (r < rows) data[r * P + idx % P] = buf[(idx / P) * LD + sw(idx % P)];
     }
 }
 

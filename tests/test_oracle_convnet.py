@@ -63,3 +63,35 @@ def test_adam_first_step_is_signed_lr():
     g = rng.standard_normal(10)
     p1, m, v = cn.adam_step(p, g, np.zeros(10), np.zeros(10), 1, lr=1e-2)
     assert np.abs((p - p1) - 1e-2 * g / (np.abs(g) + 1e-8)).max() < 1e-12
+
+
+def test_coarse_loss_gradient_and_decomposition():
+    """Finite-difference check of the coarse loss, and the identity
+    ||r + s P y - e||^2 = ||(I - P R)(r - e)||^2 + F^2 s^2 ||y - R(e - r)/s||^2."""
+    rng = np.random.default_rng(3)
+    C, Hd, F, B = 3, 4, 4, 2
+    params = [(0.3 * rng.standard_normal((Hd, C, 3, 3)), 0.1 * rng.standard_normal(Hd)),
+              (0.3 * rng.standard_normal((C, Hd, 3, 3)), 0.1 * rng.standard_normal(C))]
+    x = rng.standard_normal((B, C, 5, 6))
+    t = rng.standard_normal((B, C, 5, 6))
+    w = rng.random(B) + 0.5
+    loss, grads = cn.coarse_loss(x, t, w, params)
+    eps = 1e-6
+    for li in range(2):
+        arr = params[li][0].reshape(-1)
+        for idx in rng.choice(arr.size, 5, replace=False):
+            old = arr[idx]
+            arr[idx] = old + eps
+            lp, _ = cn.coarse_loss(x, t, w, params)
+            arr[idx] = old - eps
+            lm, _ = cn.coarse_loss(x, t, w, params)
+            arr[idx] = old
+            assert abs((lp - lm) / (2 * eps) - grads[li][0].reshape(-1)[idx]) <= 1e-6 * max(1, abs(lp))
+    r = rng.standard_normal((C, 8, 12))
+    e = rng.standard_normal((C, 8, 12))
+    y = rng.standard_normal((C, 2, 3))
+    s = 0.7
+    lhs = np.sum((r + s * cn.prolong(y, F) - e) ** 2)
+    rhs = np.sum(((r - e) - cn.prolong(cn.restrict(r - e, F), F)) ** 2) + \
+        F * F * s * s * np.sum((y - cn.restrict(e - r, F) / s) ** 2)
+    assert abs(lhs - rhs) <= 1e-12 * lhs
