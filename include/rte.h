@@ -141,12 +141,14 @@ int rte_solve_rhs(rte_ctx* ctx, const double* b_dev, double tol, int max_iter, d
 int rte_solve_batched(int count, rte_ctx* const* ctxs, const double* const* f_dev,
                       const double* tol, int max_iter, void* const* u_dev, rte_solve_info* infos);
 
-/* Attach a learned right preconditioner z = v + ||v|| N(v / ||v||) for flexible GMRES.
- * weights_dev: float32 parameters of `layers` 3x3 convolutions packed as
- * [W0 (hidden x C x 3 x 3), b0 (hidden), W1 (hidden x hidden x 3 x 3), b1, ..., W_last
- * (C x hidden x 3 x 3), b_last] with C = 2L+1 channels; ReLU after every layer but the last.
- * The context keeps a BF16 copy of the weights.  NULL detaches.  2D contexts only. */
-int rte_pc_attach(rte_ctx* ctx, const float* weights_dev, int hidden, int layers);
+/* Attach a learned right preconditioner for flexible GMRES: the coarse-grid correction
+ * z = v + s P N(R v / s) of rte_nn.h (R: factor x factor block average, P: piecewise-constant
+ * prolongation, s: RMS of R v, N: `layers` 3x3 convolutions C -> hidden -> ... -> C with ReLU
+ * between, C = 2L+1).  weights_dev: packed float32 parameters (layout in rte_nn.h); the context
+ * keeps a BF16 copy.  factor must divide n_x and n_y.  NULL detaches.  2D contexts only.
+ * A preconditioned cycle that fails to cut the true residual 10x, or produces a non-finite value,
+ * is followed by plain GMRES (info.pc_fallback = 1). */
+int rte_pc_attach(rte_ctx* ctx, const float* weights_dev, int hidden, int layers, int factor);
 
 /* Time `reps` back-to-back applies (op, RTE_LAYOUT_CHANNELS, prec) on the context stream with
  * HIP events.  ms_total: whole apply; ms_pass[0..4]: per kernel of the apply (2D: passes A, B, C;

@@ -1,0 +1,67 @@
+/*
+ * rte_nn.h -- the learned right preconditioner of the RTE library (a component the paper does not
+ * have).  A stack of 3x3 convolutions (zero "same" padding, bias, ReLU after every layer but the
+ * last) maps C = 2L+1 channels through `hidden` channels back to C channels.  As a
+ * preconditioner it acts on a coarse grid:
+ *
+ *     z = v + s P N(R v / s),   R: F x F block average, P: piecewise-constant prolongation,
+ *                               s: root-mean-square of R v,
+ *
+ * and flexible GMRES uses z_j for the Arnoldi vector v_j.  It is trained on pairs (residual r,
+ * error e = x* - x) of plain GMRES iterates: with x = R r / s and t = R(e - r) / s the objective
+ * ||r + s P N(x) - e||^2 / ||e||^2 equals w ||N(x) - t||^2 + const with w = F^2 s^2 / ||e||^2
+ * (P R is the orthogonal projector onto block-constant fields), so training runs on coarse data.
+ *
+ * Packed parameters (float32): for each layer l = 0..layers-1 the weights W_l[Cout][Cin][3][3]
+ * followed by the bias b_l[Cout]; layer 0 is C -> hidden, the last hidden -> C.  Activations are
+ * float32 [batch][channels][H][W].  Convolutions run on MFMA with BF16 operands and FP32
+ * accumulation (forward and data gradient); weight gradients and Adam are FP32.
+ * All pointers are device pointers; calls are asynchronous on the given stream unless noted.
+ * Status codes are those of rte.h.
+ */
+#ifndef RTE_NN_H
+#define RTE_NN_H
+
+#include "rte.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rte_nn rte_nn;
+
+/* channels in 1..17 (odd: 2L+1), hidden 16 or 32, layers in 2..8.  Weights are drawn with a
+ * seeded He-normal initialiser on the host, biases are zero; Adam moments start at zero. */
+int rte_nn_create(rte_nn** out, int channels, int hidden, int layers, unsigned long long seed,
+                  void* hip_stream);
+void rte_nn_destroy(rte_nn* nn);
+int rte_nn_param_count(const rte_nn* nn, long long* count);
+int rte_nn_get_params(rte_nn* nn, float* dst_dev);
+int rte_nn_set_params(rte_nn* nn, const float* src_dev);
+
+/* y = N(x) with the BF16 MFMA kernels; x, y: [batch][channels][H][W]. */
+int rte_nn_forward(rte_nn* nn, const float* x_dev, int batch, int H, int W, float* y_dev);
+
+/* loss = mean_b w_b ||N(x_b) - t_b||^2 and its parameter gradient (kept inside the object for
+ * rte_nn_adam_step, and copied to grad_dev in the packed layout if not NULL).  Synchronises the
+ * stream to return the loss. */
+int rte_nn_loss_grad(rte_nn* nn, const float* x_dev, const float* t_dev, const float* w_dev, int batch,
+                     int H, int W, double* loss, float* grad_dev);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the last gradient. */
+int rte_nn_adam_step(rte_nn* nn, float lr);
+
+/* Training pairs from `count` iterates x_j of a solve of A x = b with solution x_star (all FP64
+ * channel vectors of the context): r_j = b - A x_j (FP64 apply), e_j = x_star - x_j, written as
+ * coarse inputs x_out[j] = R r_j / s_j, targets t_out[j] = R (e_j - r_j) / s_j ([count][C][Hc][Wc],
+ * Hc = ny / factor, Wc = nx / factor; factor must divide both) and weights
+ * w_out[j] = factor^2 s_j^2 / ||e_j||^2. */
+int rte_pc_make_pairs(rte_ctx* ctx, const double* b_dev, const double* x_star_dev, const double* x_iters_dev,
+                      int count, int factor, float* x_out, float* t_out, float* w_out);
+
+/* The network is attached to a solver context with rte_pc_attach (rte.h). */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTE_NN_H */

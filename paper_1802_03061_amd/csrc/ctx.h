@@ -50,12 +50,13 @@ struct rte_ctx {
     rte_solve_opts opts{};
     // learned preconditioner (see nn.hip)
     bool pc_attached = false;
-    int pc_hidden = 0, pc_layers = 0;
-    void* pc_w = nullptr;       // BF16 weights, device
-    float* pc_b = nullptr;      // FP32 biases, device
-    float* pc_act0 = nullptr;   // activation ping-pong buffers
+    int pc_hidden = 0, pc_layers = 0, pc_factor = 1;
+    void* pc_w = nullptr;       // BF16 weight packs, device
+    float* pc_b = nullptr;      // FP32 parameter copy (biases read from it), device
+    float* pc_act0 = nullptr;   // activation ping-pong buffers (coarse grid)
     float* pc_act1 = nullptr;
-    double* pc_partial = nullptr;
+    float* pc_coarse = nullptr; // restricted input
+    float* pc_st = nullptr;     // [s, 1/s]
 };
 
 namespace rte {

@@ -1,16 +1,618 @@
-// Learned right preconditioner (3x3 convolution network).  The network kernels are added in a
-// separate step; until then attaching a network reports RTE_EUNSUPPORTED.
+// Learned right preconditioner: a coarse-grid 3x3 convolution network (see include/rte_nn.h).
+//
+// Convolution as an implicit GEMM on MFMA: out[o][p] = sum_k W[o][k] X[k][p] with k = c*9 + tap
+// (tap = 3*(dy+1) + (dx+1)) and X[k][p] the input at p + (dy, dx).  Each 64-lane wave computes a
+// 32 (output channels) x 32 (pixels of one row) tile with v_mfma_f32_32x32x8_bf16, K in steps of
+// 8; BF16 operands, FP32 accumulation.  The input tile with its one-cell halo is staged in LDS as
+// BF16.  The data gradient is the same convolution with the weights flipped in space and
+// transposed in channels, masked by the ReLU derivative of the previous layer.  Weight and bias
+// gradients are FP32 reductions over the batch, one block per (output, input) channel pair, in a
+// fixed order.
+#include <algorithm>
+#include <cmath>
+#include <random>
+#include <vector>
+
+#include "../../include/rte_nn.h"
+#include "apply2d.h"
+#include "ctx.h"
+#include "krylov.h"
 #include "nn.h"
 
 namespace rte {
-int pc_apply(rte_ctx* c, const double* v, double* z) {
-    (void)c; (void)v; (void)z;
-    return set_error(RTE_EUNSUPPORTED, "learned preconditioner not available");
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ unsigned short f2bf(float f) {   // round to nearest even
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
 }
-void pc_free(rte_ctx* c) { c->pc_attached = false; }
+
+constexpr int kpad(int cin) { return (cin * 9 + 7) / 8 * 8; }
+
+// ------------------------------------------------------------------ convolution (MFMA) --------
+// in [B][CIN][H][W] (times *in_scale if given); Wp [32][KP] bf16; out/preact [B][Cout][H][W].
+// mask (optional, same shape as out): the output is zeroed where mask <= 0.
+template <int CIN>
+__global__ __launch_bounds__(256) void k_conv3x3(const float* __restrict__ in, const unsigned short* __restrict__ Wp,
+                                                 const float* __restrict__ bias, int Cout, float* __restrict__ out,
+                                                 float* __restrict__ preact, const float* __restrict__ mask, int relu,
+                                                 const float* __restrict__ in_scale, int B, int H, int W) {
+    constexpr int K = CIN * 9;
+    constexpr int KP = kpad(CIN);
+    constexpr int ROWS = 4, TW = 32;
+    __shared__ unsigned short patch[CIN][ROWS + 2][TW + 2];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + ROWS - 1) / ROWS;
+    int bid = blockIdx.x;
+    const int tx = bid % tiles_x;
+    bid /= tiles_x;
+    const int ty = bid % tiles_y;
+    const int b = bid / tiles_y;
+    const int x0 = tx * TW, y0 = ty * ROWS;
+    const float sc = in_scale ? *in_scale : 1.0f;
+    for (int idx = threadIdx.x; idx < CIN * (ROWS + 2) * (TW + 2); idx += 256) {
+        const int c = idx / ((ROWS + 2) * (TW + 2));
+        const int rem = idx % ((ROWS + 2) * (TW + 2));
+        const int r = rem / (TW + 2), q = rem % (TW + 2);
+        const int y = y0 + r - 1, x = x0 + q - 1;
+        float v = 0.f;
+        if (y >= 0 && y < H && x >= 0 && x < W) v = in[((size_t)(b * CIN + c) * H + y) * W + x] * sc;
+        patch[c][r][q] = f2bf(v);
+    }
+    __syncthreads();
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    const int ai = lane & 31;          // A row (output channel) held by this lane
+    const int kq = (lane >> 5) * 4;    // K offset of this lane within a step of 8
+    const int j = lane & 31;           // pixel column within the tile
+#pragma unroll 4
+    for (int kb = 0; kb < KP / 8; ++kb) {
+        const bf16x4 a = *reinterpret_cast<const bf16x4*>(Wp + (size_t)ai * KP + kb * 8 + kq);
+        bf16x4 bv;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int k = kb * 8 + kq + r;
+            unsigned short val = 0;
+            if (k < K) {
+                const int c = k / 9, t = k % 9;
+                val = patch[c][wave + t / 3][j + t % 3];
+            }
+            bv[r] = (short)val;
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bv, acc, 0, 0, 0);
+    }
+    const int x = x0 + j, y = y0 + wave;
+    if (x < W && y < H) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);   // output channel of acc[r]
+            if (i < Cout) {
+                const size_t o = ((size_t)(b * Cout + i) * H + y) * W + x;
+                float v = acc[r] + (bias ? bias[i] : 0.f);
+                if (preact) preact[o] = v;
+                if (mask && !(mask[o] > 0.f)) v = 0.f;
+                if (relu) v = fmaxf(v, 0.f);
+                out[o] = v;
+            }
+        }
+    }
+}
+
+// gW[o][c][t] = sum_{b,p} gy[b][o][p] x[b][c][p + off_t]; gb[o] = sum gy[b][o][p] (block c == 0).
+__global__ __launch_bounds__(256) void k_conv3x3_wgrad(const float* __restrict__ x, const float* __restrict__ gy,
+                                                       float* __restrict__ gW, float* __restrict__ gb, int B,
+                                                       int Cin, int Cout, int H, int W) {
+    __shared__ float sh[4][10];
+    const int o = blockIdx.x / Cin, c = blockIdx.x % Cin;
+    float acc[10];
+#pragma unroll
+    for (int t = 0; t < 10; ++t) acc[t] = 0.f;
+    const int HW = H * W;
+    for (int p = threadIdx.x; p < B * HW; p += 256) {
+        const int b = p / HW, yx = p % HW;
+        const int y = yx / W, xx = yx % W;
+        const float g = gy[(size_t)(b * Cout + o) * HW + yx];
+        const float* xc = x + (size_t)(b * Cin + c) * HW;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int yy = y + t / 3 - 1, xq = xx + t % 3 - 1;
+            if (yy >= 0 && yy < H && xq >= 0 && xq < W) acc[t] += g * xc[yy * W + xq];
+        }
+        acc[9] += g;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int t = 0; t < 10; ++t) {
+        float v = acc[t];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) sh[wid][t] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 10) {
+        const int t = threadIdx.x;
+        const float v = sh[0][t] + sh[1][t] + sh[2][t] + sh[3][t];
+        if (t < 9) gW[((size_t)o * Cin + c) * 9 + t] = v;
+        else if (c == 0 && gb) gb[o] = v;
+    }
+}
+
+// diff = y - t; gout = 2 w_b diff / B; lossb[b] = w_b ||diff||^2 / B.  One block per sample.
+__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ y, const float* __restrict__ t,
+                                              const float* __restrict__ w, float* __restrict__ gout,
+                                              double* __restrict__ lossb, int per, int B) {
+    __shared__ double sh[4];
+    const int b = blockIdx.x;
+    const float wb = w[b];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < per; i += 256) {
+        const size_t o = (size_t)b * per + i;
+        const float d = y[o] - t[o];
+        s += (double)d * d;
+        gout[o] = 2.f * wb * d / (float)B;
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) lossb[b] = (double)wb * (sh[0] + sh[1] + sh[2] + sh[3]) / B;
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       size_t n, float lr, float b1, float b2, float c1, float c2, float eps) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Forward pack: Wf[i][k] = W[i][c][t] (k = c*9 + t) for i < Cout, zero elsewhere (32 x KP(Cin)).
+// Backward pack: Wb[c][k'] = W[o][c][8 - t] (k' = o*9 + t) for c < Cin (32 x KP(Cout)).
+__global__ void k_pack(const float* __restrict__ W, int Cin, int Cout, unsigned short* __restrict__ Wf,
+                       unsigned short* __restrict__ Wb) {
+    const int KPf = kpad(Cin), KPb = kpad(Cout);
+    const int n1 = 32 * KPf, n2 = 32 * KPb;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n1 + n2; idx += gridDim.x * blockDim.x) {
+        if (idx < n1) {
+            const int i = idx / KPf, k = idx % KPf;
+            float v = 0.f;
+            if (i < Cout && k < Cin * 9) v = W[((size_t)i * Cin + k / 9) * 9 + k % 9];
+            Wf[idx] = f2bf(v);
+        } else if (Wb) {
+            const int q = idx - n1;
+            const int cc = q / KPb, k = q % KPb;
+            float v = 0.f;
+            if (cc < Cin && k < Cout * 9) {
+                const int o = k / 9, t = k % 9;
+                v = W[((size_t)o * Cin + cc) * 9 + (8 - t)];
+            }
+            Wb[q] = f2bf(v);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ coarse grid helpers ------
+// out[c][I][J] = mean over the F x F block of (a - b - d) (b, d optional), FP64 in, FP32 out.
+__global__ void k_pool(const double* __restrict__ a, const double* __restrict__ bsub, const double* __restrict__ dsub,
+                       float* __restrict__ out, int C, int ny, int nx, int F) {
+    const int Hc = ny / F, Wc = nx / F;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= C * Hc * Wc) return;
+    const int c = idx / (Hc * Wc), rem = idx % (Hc * Wc);
+    const int I = rem / Wc, J = rem % Wc;
+    double s = 0.0;
+    for (int u = 0; u < F; ++u) {
+        const size_t row = ((size_t)c * ny + I * F + u) * nx + J * F;
+        for (int v = 0; v < F; ++v) {
+            double val = a[row + v];
+            if (bsub) val -= bsub[row + v];
+            if (dsub) val -= dsub[row + v];
+            s += val;
+        }
+    }
+    out[idx] = (float)(s / ((double)F * F));
+}
+
+// Single block: s = sqrt(mean(x^2)) over n values; st[0] = s, st[1] = 1/s (0 if s == 0).
+__global__ __launch_bounds__(256) void k_rms(const float* __restrict__ x, int n, float* __restrict__ st) {
+    __shared__ double sh[4];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += (double)x[i] * x[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double r = sqrt((sh[0] + sh[1] + sh[2] + sh[3]) / n);
+        st[0] = (float)r;
+        st[1] = r > 0.0 ? (float)(1.0 / r) : 0.f;
+    }
+}
+
+// z = v + s * y[c][i/F][j/F]
+__global__ void k_prolong_add(const double* __restrict__ v, const float* __restrict__ y, const float* __restrict__ st,
+                              double* __restrict__ z, int C, int ny, int nx, int F) {
+    const size_t n = (size_t)C * ny * nx;
+    const double s = st[0];
+    const int Hc = ny / F, Wc = nx / F;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int xx = (int)(i % nx);
+        const int yy = (int)((i / nx) % ny);
+        const int c = (int)(i / ((size_t)nx * ny));
+        z[i] = v[i] + s * (double)y[((size_t)c * Hc + yy / F) * Wc + xx / F];
+    }
+}
+
+// Training pair normalisation (single block): s^2 = mean(xr^2); x = xr/s, t = xt/s,
+// w = F^2 s^2 / |e|^2 (e2 on the device).
+__global__ __launch_bounds__(256) void k_pair_finish(float* __restrict__ xr, float* __restrict__ xt, int n,
+                                                     const double* __restrict__ e2, float* __restrict__ w, int F) {
+    __shared__ double sh[4];
+    __shared__ double sc;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += (double)xr[i] * xr[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double ms = (sh[0] + sh[1] + sh[2] + sh[3]) / n;
+        sc = ms > 0.0 ? 1.0 / sqrt(ms) : 0.0;
+        w[0] = (e2[0] > 0.0) ? (float)((double)F * F * ms / e2[0]) : 0.f;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += 256) {
+        xr[i] = (float)(xr[i] * sc);
+        xt[i] = (float)(xt[i] * sc);
+    }
+}
+
+// d = a - b (FP64)
+__global__ void k_sub(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ d, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        d[i] = a[i] - b[i];
+}
+
+// ------------------------------------------------------------------ host dispatch ------------
+static int conv_launch(int Cin, const float* in, const unsigned short* Wp, const float* bias, int Cout, float* out,
+                       float* preact, const float* mask, bool relu, const float* in_scale, int B, int H, int W,
+                       hipStream_t st) {
+    const int tiles = B * ((H + 3) / 4) * ((W + 31) / 32);
+    dim3 g(tiles), blk(256);
+    switch (Cin) {
+#define RTE_CV(CI)                                                                                         \
+    case CI:                                                                                               \
+        hipLaunchKernelGGL((k_conv3x3<CI>), g, blk, 0, st, in, Wp, bias, Cout, out, preact, mask, relu ? 1 : 0, \
+                           in_scale, B, H, W);                                                             \
+        return 0;
+        RTE_CV(1) RTE_CV(3) RTE_CV(5) RTE_CV(7) RTE_CV(9) RTE_CV(11) RTE_CV(13) RTE_CV(15) RTE_CV(16) RTE_CV(17)
+        RTE_CV(32)
+#undef RTE_CV
+    }
+    return -1;
+}
+
+struct NetShape {
+    int C = 0, hidden = 0, layers = 0;
+    std::vector<int> cin, cout;
+    std::vector<size_t> woff, boff;    // offsets of W_l and b_l in the packed parameters
+    size_t nparam = 0;
+    size_t pf_off_total = 0, pb_off_total = 0;
+    std::vector<size_t> pf_off, pb_off;  // offsets of the bf16 packs
+    void init(int C_, int hidden_, int layers_) {
+        C = C_; hidden = hidden_; layers = layers_;
+        cin.resize(layers); cout.resize(layers); woff.resize(layers); boff.resize(layers);
+        pf_off.resize(layers); pb_off.resize(layers);
+        size_t off = 0, pf = 0, pb = 0;
+        for (int l = 0; l < layers; ++l) {
+            cin[l] = l == 0 ? C : hidden;
+            cout[l] = l == layers - 1 ? C : hidden;
+            woff[l] = off; off += (size_t)cout[l] * cin[l] * 9;
+            boff[l] = off; off += cout[l];
+            pf_off[l] = pf; pf += (size_t)32 * kpad(cin[l]);
+            pb_off[l] = pb; pb += (size_t)32 * kpad(cout[l]);
+        }
+        nparam = off; pf_off_total = pf; pb_off_total = pb;
+    }
+};
+
+static bool valid_net(int C, int hidden, int layers) {
+    return C >= 1 && C <= 17 && (C & 1) && (hidden == 16 || hidden == 32) && layers >= 2 && layers <= 8;
+}
+
 }  // namespace rte
 
-extern "C" int rte_pc_attach(rte_ctx* ctx, const float* weights_dev, int hidden, int layers) {
-    (void)ctx; (void)weights_dev; (void)hidden; (void)layers;
-    return rte::set_error(RTE_EUNSUPPORTED, "learned preconditioner not available");
+struct rte_nn {
+    rte::NetShape sh;
+    hipStream_t stream = nullptr;
+    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+    unsigned short *wf = nullptr, *wb = nullptr;
+    int step = 0;
+    size_t cap = 0;                    // activation capacity in floats per tensor
+    std::vector<float*> act, pre;      // act[l]: input of layer l (act[0] unused), pre[l]: pre-activation
+    float *gA = nullptr, *gB = nullptr;
+    double* lossb = nullptr;
+    int lossb_cap = 0;
+};
+
+namespace rte {
+
+template <typename P>
+static int nalloc(P** p, size_t count) {
+    *p = nullptr;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(P));
+    if (e != hipSuccess) { *p = nullptr; (void)hipGetLastError(); return set_error(RTE_ENOMEM, "hipMalloc failed"); }
+    return RTE_OK;
 }
+template <typename P>
+static void nfree(P*& p) { if (p) (void)hipFree((void*)p); p = nullptr; }
+
+static void pack_all(const NetShape& sh, const float* params, unsigned short* wf, unsigned short* wb, hipStream_t st) {
+    for (int l = 0; l < sh.layers; ++l)
+        hipLaunchKernelGGL(k_pack, dim3(64), dim3(256), 0, st, params + sh.woff[l], sh.cin[l], sh.cout[l],
+                           wf + sh.pf_off[l], wb ? wb + sh.pb_off[l] : (unsigned short*)nullptr);
+}
+
+static int ensure_acts(rte_nn* nn, size_t per_tensor, int B) {
+    if (per_tensor <= nn->cap && B <= nn->lossb_cap) return RTE_OK;
+    for (auto& a : nn->act) nfree(a);
+    for (auto& a : nn->pre) nfree(a);
+    nfree(nn->gA); nfree(nn->gB); nfree(nn->lossb);
+    const int L = nn->sh.layers;
+    nn->act.assign(L + 1, nullptr);
+    nn->pre.assign(L, nullptr);
+    int rc;
+    for (int l = 1; l <= L; ++l) if ((rc = nalloc(&nn->act[l], per_tensor))) return rc;
+    for (int l = 0; l < L; ++l) if ((rc = nalloc(&nn->pre[l], per_tensor))) return rc;
+    if ((rc = nalloc(&nn->gA, per_tensor)) || (rc = nalloc(&nn->gB, per_tensor))) return rc;
+    if ((rc = nalloc(&nn->lossb, (size_t)B))) return rc;
+    nn->cap = per_tensor;
+    nn->lossb_cap = B;
+    return RTE_OK;
+}
+
+// Forward through all layers; act[l+1] = layer l output, pre[l] = its pre-activation.
+static int net_forward(const NetShape& sh, const unsigned short* wf, const float* params_bias_base,
+                       const std::vector<size_t>& boff, const float* x, const float* in_scale, float* const* act,
+                       float* const* pre, int B, int H, int W, hipStream_t st) {
+    const float* a = x;
+    for (int l = 0; l < sh.layers; ++l) {
+        const bool last = l == sh.layers - 1;
+        if (conv_launch(sh.cin[l], a, wf + sh.pf_off[l], params_bias_base + boff[l], sh.cout[l], act[l + 1],
+                        pre ? pre[l] : nullptr, nullptr, !last, l == 0 ? in_scale : nullptr, B, H, W, st))
+            return set_error(RTE_EUNSUPPORTED, "unsupported convolution width");
+        a = act[l + 1];
+    }
+    return RTE_OK;
+}
+
+// ------------------------------------------------------------------ preconditioner on ctx -----
+void pc_free(rte_ctx* c) {
+    if (c->pc_w) (void)hipFree(c->pc_w);
+    c->pc_w = nullptr;
+    nfree(c->pc_b);
+    nfree(c->pc_act0);
+    nfree(c->pc_act1);
+    nfree(c->pc_coarse);
+    nfree(c->pc_st);
+    c->pc_attached = false;
+}
+
+int pc_apply(rte_ctx* c, const double* v, double* z) {
+    NetShape sh;
+    sh.init(c->C, c->pc_hidden, c->pc_layers);
+    const int F = c->pc_factor;
+    const int Hc = c->ny / F, Wc = c->nx / F;
+    const int nco = c->C * Hc * Wc;
+    hipStream_t st = c->stream;
+    hipLaunchKernelGGL(k_pool, dim3((nco + 255) / 256), dim3(256), 0, st, v, (const double*)nullptr,
+                       (const double*)nullptr, c->pc_coarse, c->C, c->ny, c->nx, F);
+    hipLaunchKernelGGL(k_rms, dim3(1), dim3(256), 0, st, c->pc_coarse, nco, c->pc_st);
+    // ping-pong activations: layer l writes act[(l % 2)]
+    float* bufs[2] = {c->pc_act0, c->pc_act1};
+    const float* a = c->pc_coarse;
+    const unsigned short* wf = (const unsigned short*)c->pc_w;
+    for (int l = 0; l < sh.layers; ++l) {
+        const bool last = l == sh.layers - 1;
+        float* o = bufs[l & 1];
+        if (conv_launch(sh.cin[l], a, wf + sh.pf_off[l], c->pc_b + sh.boff[l], sh.cout[l], o, nullptr, nullptr, !last,
+                        l == 0 ? c->pc_st + 1 : nullptr, 1, Hc, Wc, st))
+            return set_error(RTE_EUNSUPPORTED, "unsupported convolution width");
+        a = o;
+    }
+    const size_t n = c->nvec;
+    hipLaunchKernelGGL(k_prolong_add, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, st, v, a,
+                       c->pc_st, z, c->C, c->ny, c->nx, F);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RTE_OK : set_hip_error(e, "pc_apply", __FILE__, __LINE__);
+}
+
+}  // namespace rte
+
+using namespace rte;
+
+extern "C" {
+
+int rte_pc_attach(rte_ctx* c, const float* weights, int hidden, int layers, int factor) {
+    if (!c) return set_error(RTE_EINVAL, "ctx is NULL");
+    pc_free(c);
+    if (!weights) return RTE_OK;
+    if (c->dim != 2) return set_error(RTE_EUNSUPPORTED, "the learned preconditioner is 2D only");
+    if (!valid_net(c->C, hidden, layers)) return set_error(RTE_EINVAL, "bad network shape");
+    if (factor < 1 || c->nx % factor || c->ny % factor) return set_error(RTE_EINVAL, "factor must divide n_x and n_y");
+    NetShape sh;
+    sh.init(c->C, hidden, layers);
+    const int Hc = c->ny / factor, Wc = c->nx / factor;
+    const size_t per = (size_t)std::max(hidden, c->C) * Hc * Wc;
+    unsigned short* wf = nullptr;
+    int rc;
+    if ((rc = nalloc(&wf, sh.pf_off_total))) return rc;
+    c->pc_w = wf;
+    if ((rc = nalloc(&c->pc_b, sh.nparam)) || (rc = nalloc(&c->pc_act0, per)) || (rc = nalloc(&c->pc_act1, per)) ||
+        (rc = nalloc(&c->pc_coarse, (size_t)c->C * Hc * Wc)) || (rc = nalloc(&c->pc_st, 4))) {
+        pc_free(c);
+        return rc;
+    }
+    // biases are read from a full FP32 copy of the parameters (only the bias slices are used)
+    hipError_t e = hipMemcpyAsync(c->pc_b, weights, sh.nparam * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) { pc_free(c); return set_hip_error(e, "pc weights", __FILE__, __LINE__); }
+    pack_all(sh, weights, wf, nullptr, c->stream);
+    c->pc_hidden = hidden;
+    c->pc_layers = layers;
+    c->pc_factor = factor;
+    c->pc_attached = true;
+    e = hipGetLastError();
+    return e == hipSuccess ? RTE_OK : set_hip_error(e, "rte_pc_attach", __FILE__, __LINE__);
+}
+
+int rte_nn_create(rte_nn** out, int C, int hidden, int layers, unsigned long long seed, void* stream) {
+    if (!out) return set_error(RTE_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!valid_net(C, hidden, layers)) return set_error(RTE_EINVAL, "bad network shape");
+    rte_nn* nn = new rte_nn();
+    nn->sh.init(C, hidden, layers);
+    nn->stream = (hipStream_t)stream;
+    const size_t np = nn->sh.nparam;
+    int rc;
+    if ((rc = nalloc(&nn->p, np)) || (rc = nalloc(&nn->g, np)) || (rc = nalloc(&nn->m, np)) || (rc = nalloc(&nn->v, np)) ||
+        (rc = nalloc(&nn->wf, nn->sh.pf_off_total)) || (rc = nalloc(&nn->wb, nn->sh.pb_off_total))) {
+        rte_nn_destroy(nn);
+        return rc;
+    }
+    // He-normal weights (std = sqrt(2 / fan_in)), zero biases, seeded
+    std::vector<float> h(np, 0.f);
+    std::mt19937_64 gen(seed);
+    for (int l = 0; l < layers; ++l) {
+        std::normal_distribution<double> nd(0.0, std::sqrt(2.0 / (9.0 * nn->sh.cin[l])) * (l == layers - 1 ? 0.1 : 1.0));
+        for (size_t i = 0; i < (size_t)nn->sh.cout[l] * nn->sh.cin[l] * 9; ++i) h[nn->sh.woff[l] + i] = (float)nd(gen);
+    }
+    hipError_t e = hipMemcpy(nn->p, h.data(), np * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(nn->m, 0, np * sizeof(float));
+    if (e == hipSuccess) e = hipMemset(nn->v, 0, np * sizeof(float));
+    if (e != hipSuccess) { rte_nn_destroy(nn); return set_hip_error(e, "rte_nn_create", __FILE__, __LINE__); }
+    *out = nn;
+    return RTE_OK;
+}
+
+void rte_nn_destroy(rte_nn* nn) {
+    if (!nn) return;
+    if (nn->stream) (void)hipStreamSynchronize(nn->stream);
+    nfree(nn->p); nfree(nn->g); nfree(nn->m); nfree(nn->v); nfree(nn->wf); nfree(nn->wb);
+    for (auto& a : nn->act) nfree(a);
+    for (auto& a : nn->pre) nfree(a);
+    nfree(nn->gA); nfree(nn->gB); nfree(nn->lossb);
+    delete nn;
+}
+
+int rte_nn_param_count(const rte_nn* nn, long long* count) {
+    if (!nn || !count) return set_error(RTE_EINVAL, "NULL argument");
+    *count = (long long)nn->sh.nparam;
+    return RTE_OK;
+}
+
+int rte_nn_get_params(rte_nn* nn, float* dst) {
+    if (!nn || !dst) return set_error(RTE_EINVAL, "NULL argument");
+    RTE_HIP_TRY(hipMemcpyAsync(dst, nn->p, nn->sh.nparam * sizeof(float), hipMemcpyDeviceToDevice, nn->stream));
+    return RTE_OK;
+}
+
+int rte_nn_set_params(rte_nn* nn, const float* src) {
+    if (!nn || !src) return set_error(RTE_EINVAL, "NULL argument");
+    RTE_HIP_TRY(hipMemcpyAsync(nn->p, src, nn->sh.nparam * sizeof(float), hipMemcpyDeviceToDevice, nn->stream));
+    return RTE_OK;
+}
+
+int rte_nn_forward(rte_nn* nn, const float* x, int B, int H, int W, float* y) {
+    if (!nn || !x || !y || B < 1 || H < 1 || W < 1) return set_error(RTE_EINVAL, "bad argument");
+    int rc = ensure_acts(nn, (size_t)B * std::max(nn->sh.hidden, nn->sh.C) * H * W, B);
+    if (rc) return rc;
+    pack_all(nn->sh, nn->p, nn->wf, nullptr, nn->stream);
+    std::vector<float*> act = nn->act;
+    act[nn->sh.layers] = y;
+    rc = net_forward(nn->sh, nn->wf, nn->p, nn->sh.boff, x, nullptr, act.data(), nullptr, B, H, W, nn->stream);
+    if (rc) return rc;
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RTE_OK : set_hip_error(e, "rte_nn_forward", __FILE__, __LINE__);
+}
+
+int rte_nn_loss_grad(rte_nn* nn, const float* x, const float* t, const float* w, int B, int H, int W, double* loss,
+                     float* grad) {
+    if (!nn || !x || !t || !w || B < 1 || H < 1 || W < 1) return set_error(RTE_EINVAL, "bad argument");
+    const NetShape& sh = nn->sh;
+    int rc = ensure_acts(nn, (size_t)B * std::max(sh.hidden, sh.C) * H * W, B);
+    if (rc) return rc;
+    hipStream_t st = nn->stream;
+    pack_all(sh, nn->p, nn->wf, nn->wb, st);
+    if ((rc = net_forward(sh, nn->wf, nn->p, sh.boff, x, nullptr, nn->act.data(), nn->pre.data(), B, H, W, st)))
+        return rc;
+    const int per = sh.C * H * W;
+    hipLaunchKernelGGL(k_loss, dim3(B), dim3(256), 0, st, nn->act[sh.layers], t, w, nn->gA, nn->lossb, per, B);
+    // backward: gA holds dLoss/d(output of layer l)
+    float* gcur = nn->gA;
+    float* gnext = nn->gB;
+    for (int l = sh.layers - 1; l >= 0; --l) {
+        const float* a_in = l == 0 ? x : nn->act[l];
+        hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(sh.cout[l] * sh.cin[l]), dim3(256), 0, st, a_in, gcur,
+                           nn->g + sh.woff[l], nn->g + sh.boff[l], B, sh.cin[l], sh.cout[l], H, W);
+        if (l > 0) {   // data gradient, masked by the ReLU of layer l-1
+            if (conv_launch(sh.cout[l], gcur, nn->wb + sh.pb_off[l], nullptr, sh.cin[l], gnext, nullptr, nn->pre[l - 1],
+                            false, nullptr, B, H, W, st))
+                return set_error(RTE_EUNSUPPORTED, "unsupported convolution width");
+            std::swap(gcur, gnext);
+        }
+    }
+    std::vector<double> lb(B);
+    RTE_HIP_TRY(hipMemcpyAsync(lb.data(), nn->lossb, B * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (grad) RTE_HIP_TRY(hipMemcpyAsync(grad, nn->g, sh.nparam * sizeof(float), hipMemcpyDeviceToDevice, st));
+    RTE_HIP_TRY(hipStreamSynchronize(st));
+    double s = 0.0;
+    for (int b = 0; b < B; ++b) s += lb[b];
+    if (loss) *loss = s;
+    return RTE_OK;
+}
+
+int rte_nn_adam_step(rte_nn* nn, float lr) {
+    if (!nn || !(lr > 0.f)) return set_error(RTE_EINVAL, "bad argument");
+    nn->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - std::pow(b1, (float)nn->step), c2 = 1.f - std::pow(b2, (float)nn->step);
+    const size_t n = nn->sh.nparam;
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, nn->stream, nn->p, nn->g, nn->m, nn->v, n,
+                       lr, b1, b2, c1, c2, 1e-8f);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RTE_OK : set_hip_error(e, "rte_nn_adam_step", __FILE__, __LINE__);
+}
+
+int rte_pc_make_pairs(rte_ctx* c, const double* b, const double* xs, const double* xit, int count, int F, float* xo,
+                      float* to, float* wo) {
+    if (!c || !b || !xs || !xit || !xo || !to || !wo || count < 0) return set_error(RTE_EINVAL, "bad argument");
+    if (c->dim != 2 || F < 1 || c->nx % F || c->ny % F) return set_error(RTE_EINVAL, "factor must divide n_x and n_y");
+    const size_t n = c->nvec;
+    const int Hc = c->ny / F, Wc = c->nx / F;
+    const int nco = c->C * Hc * Wc;
+    hipStream_t st = c->stream;
+    for (int j = 0; j < count; ++j) {
+        const double* xj = xit + (size_t)j * n;
+        // r = b - A x_j into rv; e = x_star - x_j into t1
+        int rc = apply_channels(c, APPLY_RESID, RTE_PREC_FP64, xj, b, c->rv, 1);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_sub, dim3(2048), dim3(256), 0, st, xs, xj, c->t1, n);
+        krylov_dots(c->t1, n, 1, c->t1, n, c->partial, c->dsmall, false, st);
+        float* xr = xo + (size_t)j * nco;
+        float* xt = to + (size_t)j * nco;
+        hipLaunchKernelGGL(k_pool, dim3((nco + 255) / 256), dim3(256), 0, st, c->rv, (const double*)nullptr,
+                           (const double*)nullptr, xr, c->C, c->ny, c->nx, F);
+        hipLaunchKernelGGL(k_pool, dim3((nco + 255) / 256), dim3(256), 0, st, c->t1, c->rv, (const double*)nullptr, xt,
+                           c->C, c->ny, c->nx, F);
+        hipLaunchKernelGGL(k_pair_finish, dim3(1), dim3(256), 0, st, xr, xt, nco, c->dsmall, wo + j, F);
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RTE_OK : set_hip_error(e, "rte_pc_make_pairs", __FILE__, __LINE__);
+}
+
+}  // extern "C"

@@ -68,7 +68,16 @@ def load():
         "rte_solve_rhs": (I, [P, P, D, I, P, C.POINTER(SolveInfo), P, I, C.POINTER(I)]),
         "rte_solve_batched": (I, [I, C.POINTER(P), C.POINTER(P), C.POINTER(D), I, C.POINTER(P),
                                   C.POINTER(SolveInfo)]),
-        "rte_pc_attach": (I, [P, P, I, I]),
+        "rte_pc_attach": (I, [P, P, I, I, I]),
+        "rte_nn_create": (I, [C.POINTER(P), I, I, I, C.c_ulonglong, P]),
+        "rte_nn_destroy": (None, [P]),
+        "rte_nn_param_count": (I, [P, C.POINTER(C.c_longlong)]),
+        "rte_nn_get_params": (I, [P, P]),
+        "rte_nn_set_params": (I, [P, P]),
+        "rte_nn_forward": (I, [P, P, I, I, I, P]),
+        "rte_nn_loss_grad": (I, [P, P, P, P, I, I, I, C.POINTER(D), P]),
+        "rte_nn_adam_step": (I, [P, C.c_float]),
+        "rte_pc_make_pairs": (I, [P, P, P, P, I, I, P, P, P]),
         "rte_time_apply": (I, [P, I, I, I, C.POINTER(D), C.POINTER(D)]),
         "rte_query": (I, [P, C.POINTER(I), C.POINTER(I), C.POINTER(C.c_longlong)]),
         "rte_modes_to_channels": (I, [P, P, P]),
@@ -227,12 +236,28 @@ class Context:
         _check(load().rte_time_apply(self._h, op, prec, reps, C.byref(tot), passes))
         return tot.value, list(passes)
 
-    def attach_pc(self, weights, hidden, layers):
+    def attach_pc(self, weights, hidden=32, layers=5, factor=8):
+        """Attach the coarse-grid network (packed float32 parameters) as the FGMRES right
+        preconditioner; None detaches."""
         if weights is None:
-            _check(load().rte_pc_attach(self._h, None, 0, 0))
+            _check(load().rte_pc_attach(self._h, None, 0, 0, 1))
             return
         wp = _ptr(weights, torch.float32)
-        _check(load().rte_pc_attach(self._h, wp, int(hidden), int(layers)))
+        _check(load().rte_pc_attach(self._h, wp, int(hidden), int(layers), int(factor)))
+
+    def make_pairs(self, b, x_star, x_iters, factor):
+        """Coarse training pairs (inputs, targets, weights) from iterates of a solve of A x = b."""
+        cnt = int(x_iters.shape[0])
+        Hc, Wc = self.grid_shape[0] // factor, self.grid_shape[1] // factor
+        xo = torch.empty((cnt, self.channels, Hc, Wc), dtype=torch.float32, device=b.device)
+        to = torch.empty_like(xo)
+        wo = torch.empty((cnt,), dtype=torch.float32, device=b.device)
+        n = self.channels * self.cells
+        _check(load().rte_pc_make_pairs(self._h, _ptr(b, torch.float64, n), _ptr(x_star, torch.float64, n),
+                                        _ptr(x_iters, torch.float64, cnt * n), cnt, int(factor),
+                                        C.c_void_p(xo.data_ptr()), C.c_void_p(to.data_ptr()),
+                                        C.c_void_p(wo.data_ptr())))
+        return xo, to, wo
 
     def modes_to_channels(self, x):
         out = torch.empty(self.channel_shape, dtype=torch.float64, device=x.device)
@@ -260,3 +285,55 @@ def solve_batched(ctxs, fs, tols, max_iter=1000, allow_not_converged=False):
     allow = (RTE_OK, RTE_NOT_CONVERGED) if allow_not_converged else (RTE_OK,)
     rc = _check(lib.rte_solve_batched(n, hs, fp, tl, int(max_iter), up, infos), allow)
     return us, [i.as_dict() for i in infos], rc
+
+
+class Net:
+    """The preconditioner network's parameters, forward, gradient and Adam (rte_nn.h)."""
+
+    def __init__(self, channels, hidden=32, layers=5, seed=0):
+        lib = load()
+        h = C.c_void_p()
+        _check(lib.rte_nn_create(C.byref(h), int(channels), int(hidden), int(layers), int(seed),
+                                 C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        self._h = h
+        self.channels, self.hidden, self.layers = int(channels), int(hidden), int(layers)
+        cnt = C.c_longlong()
+        _check(lib.rte_nn_param_count(h, C.byref(cnt)))
+        self.nparam = cnt.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().rte_nn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self):
+        out = torch.empty(self.nparam, dtype=torch.float32, device="cuda")
+        _check(load().rte_nn_get_params(self._h, C.c_void_p(out.data_ptr())))
+        return out
+
+    def set_params(self, p):
+        _check(load().rte_nn_set_params(self._h, _ptr(p, torch.float32, self.nparam)))
+
+    def forward(self, x):
+        B, Cc, H, W = x.shape
+        y = torch.empty((B, self.channels, H, W), dtype=torch.float32, device=x.device)
+        _check(load().rte_nn_forward(self._h, _ptr(x, torch.float32), B, H, W, C.c_void_p(y.data_ptr())))
+        return y
+
+    def loss_grad(self, x, t, w, want_grad=False):
+        B, Cc, H, W = x.shape
+        loss = C.c_double()
+        g = torch.empty(self.nparam, dtype=torch.float32, device=x.device) if want_grad else None
+        _check(load().rte_nn_loss_grad(self._h, _ptr(x, torch.float32), _ptr(t, torch.float32),
+                                       _ptr(w, torch.float32, B), B, H, W, C.byref(loss),
+                                       C.c_void_p(g.data_ptr()) if g is not None else None))
+        return (loss.value, g) if want_grad else loss.value
+
+    def adam_step(self, lr=1e-3):
+        _check(load().rte_nn_adam_step(self._h, float(lr)))

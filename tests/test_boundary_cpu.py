@@ -7,12 +7,12 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "rte.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("rte.h", "rte_nn.h")]
 LIB = os.path.join(ROOT, "paper_1802_03061_amd", "librte.so")
 
 
 def declared_functions():
-    src = open(HEADER).read()
+    src = "".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(rte_[a-z_0-9]+)\s*\(", src)))
 
@@ -28,7 +28,8 @@ def lib():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for must in ("rte_setup", "rte_apply", "rte_solve", "rte_solve_batched", "rte_destroy",
-                 "rte_last_error", "rte_pc_attach"):
+                 "rte_last_error", "rte_pc_attach", "rte_nn_create", "rte_nn_loss_grad", "rte_nn_adam_step",
+                 "rte_pc_make_pairs"):
         assert must in names
 
 
@@ -91,3 +92,13 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.rte_query(None, None, None, None) == rte.RTE_EINVAL
     lib.rte_destroy(None)
     assert b"gfx950" in lib.rte_version()
+
+
+def test_nn_create_rejects_bad_shapes(lib):
+    from paper_1802_03061_amd import rte
+    out = C.c_void_p()
+    for ch, hid, lay in ((2, 32, 5), (19, 32, 5), (9, 24, 5), (9, 32, 1), (9, 32, 9)):
+        assert lib.rte_nn_create(C.byref(out), ch, hid, lay, 0, None) == rte.RTE_EINVAL
+        assert out.value is None
+    assert lib.rte_nn_adam_step(None, C.c_float(1e-3)) == rte.RTE_EINVAL
+    assert lib.rte_pc_attach(None, None, 32, 5, 4) == rte.RTE_EINVAL

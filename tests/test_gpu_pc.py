@@ -1,0 +1,218 @@
+"""GPU tests of the learned preconditioner: the MFMA convolution network against the FP64 oracle
+(forward, parameter gradient, Adam), the training-pair builder against the oracle's definition, the
+gain of the trained network in FGMRES over plain GMRES, and the fallback when the network is broken.
+
+BF16 operands with FP32 accumulation through 5 layers give relative errors of a few 1e-3 per
+layer; the bars below (3e-2 forward, 5e-2 gradients) leave room for that and catch any layout or
+indexing error, which shows up as O(1)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import dev, host, relerr, say
+from oracle import convnet as cn
+from oracle import krylov as kr
+from oracle import operator2d as op2
+from paper_1802_03061_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rte():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1802_03061_amd import rte as r
+    r.load()
+    return r
+
+
+def unpack(p, C, hidden, layers):
+    """Packed parameters -> [(W, b)] in FP64 (layout of rte_nn.h)."""
+    out, off = [], 0
+    for l in range(layers):
+        ci = C if l == 0 else hidden
+        co = C if l == layers - 1 else hidden
+        W = p[off:off + co * ci * 9].reshape(co, ci, 3, 3).astype(np.float64); off += co * ci * 9
+        b = p[off:off + co].astype(np.float64); off += co
+        out.append((W, b))
+    return out
+
+
+def pack(params):
+    return np.concatenate([np.concatenate([W.reshape(-1), b]) for W, b in params]).astype(np.float32)
+
+
+@pytest.mark.parametrize("C,hidden,H,W", [(17, 32, 9, 37), (9, 32, 32, 32), (1, 16, 5, 7), (5, 32, 16, 40)])
+def test_forward_matches_oracle(rte, C, hidden, H, W):
+    say("nn forward", C, hidden, H, W)
+    rng = np.random.default_rng(C + H)
+    net = rte.Net(C, hidden, 5, seed=C)
+    params = unpack(host(net.params()), C, hidden, 5)
+    # non-zero biases to exercise the bias path
+    params = [(Wt, 0.1 * rng.standard_normal(b.shape)) for Wt, b in params]
+    net.set_params(dev(pack(params)))
+    x = rng.standard_normal((3, C, H, W)).astype(np.float32)
+    y = host(net.forward(dev(x)))
+    ref, _ = cn.net_forward(x.astype(np.float64), params)
+    e = relerr(y, ref)
+    say("  relerr", e)
+    assert e <= 3e-2
+    net.close()
+
+
+def bf16(a):
+    """Round to the nearest BF16 (ties to even), returned as float64."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return u.view(np.float32).astype(np.float64)
+
+
+def emulated_grads(x, t, w, params):
+    """The oracle's convolutions applied to the operands the GPU kernels use: BF16-rounded layer
+    inputs and weights in the forward and data-gradient convolutions, FP32-level weight gradients
+    from the unrounded activations."""
+    acts, pre = [x], []
+    a = x
+    for l, (W, b) in enumerate(params):
+        z = cn.conv3x3(bf16(a), bf16(W), b)
+        pre.append(z)
+        a = np.maximum(z, 0.0) if l < len(params) - 1 else z
+        acts.append(a)
+    B = x.shape[0]
+    g = 2.0 * (acts[-1] - t) * (w / B)[:, None, None, None]
+    grads = [None] * len(params)
+    for l in range(len(params) - 1, -1, -1):
+        _, gW, gb = cn.conv3x3_backward(acts[l], params[l][0], g)
+        grads[l] = (gW, gb)
+        if l > 0:
+            gx, _, _ = cn.conv3x3_backward(acts[l], bf16(params[l][0]), bf16(g))
+            g = gx * (pre[l - 1] > 0)
+    return grads
+
+
+def test_gradient_matches_oracle(rte):
+    C, hidden, H, W, B = 9, 32, 12, 20, 4
+    rng = np.random.default_rng(7)
+    net = rte.Net(C, hidden, 5, seed=3)
+    params = unpack(host(net.params()), C, hidden, 5)
+    params = [(Wt, 0.05 * rng.standard_normal(b.shape)) for Wt, b in params]
+    net.set_params(dev(pack(params)))
+    x = rng.standard_normal((B, C, H, W)).astype(np.float32)
+    t = rng.standard_normal((B, C, H, W)).astype(np.float32)
+    w = (rng.random(B) + 0.5).astype(np.float32)
+    loss, g = net.loss_grad(dev(x), dev(t), dev(w), want_grad=True)
+    gg = host(g)
+    x64, t64, w64 = x.astype(np.float64), t.astype(np.float64), w.astype(np.float64)
+    ref_loss, ref_grads = cn.coarse_loss(x64, t64, w64, params)
+    gref = np.concatenate([np.concatenate([gW.reshape(-1), gb]) for gW, gb in ref_grads])
+    say("loss", loss, ref_loss, "grad relerr vs FP64 oracle", relerr(gg, gref))
+    assert abs(loss - ref_loss) <= 2e-2 * abs(ref_loss)
+    assert relerr(gg, gref) <= 5e-2
+    # per layer against the same definition on BF16-rounded operands: tight
+    emu = emulated_grads(x64, t64, w64, params)
+    off = 0
+    for l, ((gW, gb), (rW, rb)) in enumerate(zip(emu, ref_grads)):
+        k = gW.size
+        e1 = relerr(gg[off:off + k], gW.reshape(-1))
+        e2 = relerr(gg[off + k:off + k + gb.size], gb)
+        say("  layer", l, "W relerr (bf16-emulated)", e1, "b", e2, "W vs FP64", relerr(gg[off:off + k], rW.reshape(-1)))
+        assert e1 <= 2e-3 and e2 <= 2e-3
+        assert relerr(gg[off:off + k], rW.reshape(-1)) <= 0.2
+        off += k + gb.size
+    # one Adam step from zero moments: p - lr * g / (|g| + eps)
+    p0 = pack(params)
+    net.adam_step(1e-3)
+    p1 = host(net.params())
+    want, _, _ = cn.adam_step(p0.astype(np.float64), gg.astype(np.float64), 0.0, 0.0, 1, lr=1e-3)
+    assert np.abs(p1 - want).max() <= 1e-6
+    net.close()
+
+
+def _to_ch(u, L):
+    out = [u[L].real]
+    for k in range(1, L + 1):
+        out += [np.sqrt(2) * u[L + k].real, np.sqrt(2) * u[L + k].imag]
+    return np.stack(out)
+
+
+def _to_modes(c, L):
+    n = c.shape[-1]
+    u = np.zeros((2 * L + 1,) + c.shape[1:], complex)
+    u[L] = c[0]
+    for k in range(1, L + 1):
+        z = (c[2 * k - 1] + 1j * c[2 * k]) / np.sqrt(2)
+        u[L + k] = z
+        u[L - k] = np.conj(z)
+    return u
+
+
+def test_make_pairs_matches_definition(rte):
+    n, L, F = 16, 2, 4
+    mu_a, mu_s = 0.05, 8.0
+    sh = inputs.hg_sigma_hat(0.4, L)
+    rng = np.random.default_rng(9)
+    ctx = rte.Context(n, mu_a=mu_a, mu_s=mu_s, sigma_hat=sh, L=L, prec=rte.PREC_FP64)
+    f = rng.random((n, n))
+    h, mu_t = 1.0 / n, mu_a + mu_s
+    b = op2.rhs(f, L, h, mu_t, method="direct")
+    xstar = kr.solve_dense(op2.dense_A(n, n, L, h, mu_t, mu_s, sh), b.reshape(-1)).reshape(b.shape)
+    xs = [inputs.random_conj_symmetric_modes(rng, L, n) * 0.01 for _ in range(3)]
+    bc, xsc = _to_ch(b, L), _to_ch(xstar, L)
+    it = np.stack([_to_ch(x, L) for x in xs])
+    xo, to, wo = ctx.make_pairs(dev(bc), dev(xsc), dev(it), F)
+    for j, x in enumerate(xs):
+        r = _to_ch(b - op2.apply_direct(x, L, h, mu_t, mu_s, sh), L)
+        e = xsc - it[j]
+        Rr = cn.restrict(r, F)
+        s = np.sqrt(np.mean(Rr ** 2))
+        assert relerr(host(xo)[j], Rr / s) <= 1e-5
+        assert relerr(host(to)[j], cn.restrict(e - r, F) / s) <= 1e-5
+        assert abs(host(wo)[j] - F * F * s * s / np.sum(e ** 2)) <= 1e-5 * abs(host(wo)[j])
+    ctx.close()
+
+
+def test_learned_pc_reduces_iterations(rte):
+    """Diffusion regime, 64^2, L = 2 (HG g = 0.3), mu_s = 50, mu_a = 0.01: a network trained on
+    pairs from 12 training sources (seeds 10000+) cuts FGMRES iterations on held-out sources
+    (seeds 0-2) against plain GMRES, with the same true-residual tolerance met."""
+    from paper_1802_03061_amd import pc_train
+    n, L, F = 64, 2, 4
+    ctx = rte.Context(n, mu_a=0.01, mu_s=50.0, sigma_hat=inputs.hg_sigma_hat(0.3, L), L=L, prec=rte.PREC_FP32)
+    srcs = [inputs.workload("diff256", seed=10000 + s, n=n)["f"] for s in range(12)]
+    x, t, w = pc_train.generate_pairs(ctx, srcs, F)
+    say("pairs", x.shape)
+    net, hist = pc_train.train(x, t, w, ctx.channels, steps=1500, batch=32, lr=1e-3, log_every=500)
+    say("loss history", hist)
+    plain, pcd = [], []
+    for s in range(3):
+        f = dev(inputs.workload("diff256", seed=s, n=n)["f"])
+        ctx.attach_pc(None)
+        _, i0 = ctx.solve(f, tol=1e-8)
+        ctx.attach_pc(net.params(), factor=F)
+        _, i1 = ctx.solve(f, tol=1e-8)
+        say("seed", s, "plain", i0["iterations"], "pc", i1["iterations"], "fallback", i1["pc_fallback"],
+            "relres", i1["relres_true"])
+        assert i1["relres_true"] <= 1e-8 and i1["pc_fallback"] == 0
+        plain.append(i0["iterations"]); pcd.append(i1["iterations"])
+    assert np.mean(pcd) <= 0.8 * np.mean(plain)
+    ctx.close()
+    net.close()
+
+
+def test_broken_network_falls_back_to_plain_gmres(rte):
+    n, L = 32, 1
+    ctx = rte.Context(n, mu_a=0.1, mu_s=5.0, sigma_hat=inputs.hg_sigma_hat(0.5, L), L=L, prec=rte.PREC_FP32)
+    net = rte.Net(ctx.channels, 32, 5, seed=1)
+    bad = torch.full((net.nparam,), float("nan"), dtype=torch.float32, device="cuda")
+    ctx.attach_pc(bad, factor=4)
+    f = dev(inputs.centred_gaussian_source(n))
+    u, info = ctx.solve(f, tol=1e-8)
+    say("nan net:", info)
+    assert info["pc_fallback"] == 1 and info["relres_true"] <= 1e-8
+    huge = torch.full((net.nparam,), 50.0, dtype=torch.float32, device="cuda")
+    ctx.attach_pc(huge, factor=4)
+    u, info = ctx.solve(f, tol=1e-8)
+    say("huge net:", info)
+    assert info["relres_true"] <= 1e-8
+    ctx.close()
+    net.close()
