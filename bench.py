@@ -2,10 +2,13 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--mu-s 10] [--no-cpu-baseline]
 
-One step = one full solve (right-hand side b = K~ g by an FP64 apply, then GMRES with FP32 FFT
-applies, FP64 Krylov and FP64 true-residual refinement) of a seeded Gaussian-mixture source
-(2D, 512^2 cells, HG g = 0.5 truncated to |k| <= 8: 17 coupled modes, mu_a = 0.1).  Inputs are
-resident in HBM before the timed region; the timed region is K solves bracketed by device
+One step = one full solve (right-hand side b = K~ g by an FP64 apply, then flexible GMRES with the
+learned coarse-grid preconditioner, FP32 FFT applies, FP64 Krylov and FP64 true-residual
+refinement) of a seeded Gaussian-mixture source (2D, 512^2 cells, HG g = 0.5 truncated to
+|k| <= 8: 17 coupled modes, mu_a = 0.1).  The same solves without the preconditioner (plain GMRES)
+are timed beside it.  The network is trained before timing by the library's own kernels on pairs
+from training sources (seeds 10000+), disjoint from the timed sources (seeds 0..K-1).  Inputs are
+resident in HBM before the timed region; each timed region is K solves bracketed by device
 synchronisation.  Prints one JSON line.
 
 Also reported: operator applies/s, per-pass apply times from HIP events on the context stream
@@ -79,6 +82,8 @@ def main():
     ap.add_argument("--mu-s", type=float, default=10.0)
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pc", action="store_true", help="time plain GMRES only")
+    ap.add_argument("--train-steps", type=int, default=1500)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU "
@@ -96,28 +101,50 @@ def main():
     n, L = base["n"], base["L"]
     ctx = rte.Context(n, mu_a=base["mu_a"], mu_s=base["mu_s"], sigma_hat=base["sigma_hat"], L=L,
                       prec=rte.PREC_FP32)
-    t_setup_ms = None
     # seeded sources, resident on the device before timing
     nsrc = max(args.steps, 1)
     fs = [torch.from_numpy(inputs.workload("hg512", seed=s, mu_s=args.mu_s)["f"]).cuda()
           for s in range(nsrc)]
     torch.cuda.synchronize()
 
-    for i in range(args.warmup):
-        ctx.solve(fs[i % nsrc], tol=1e-8)
-    torch.cuda.synchronize()
-    infos = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        _, info = ctx.solve(fs[i % nsrc], tol=1e-8)
-        infos.append(info)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = 1000.0 * elapsed / args.steps
-    t_setup_ms = infos[0]["t_setup_ms"]
-    iters = float(np.mean([i["iterations"] for i in infos]))
-    applies = float(np.mean([i["applies"] for i in infos]))
-    relres = float(max(i["relres_true"] for i in infos))
+    def timed(label):
+        for i in range(args.warmup):
+            ctx.solve(fs[i % nsrc], tol=1e-8)
+        torch.cuda.synchronize()
+        infos = []
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            _, info = ctx.solve(fs[i % nsrc], tol=1e-8)
+            infos.append(info)
+        torch.cuda.synchronize()
+        ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+        return ms, {"label": label, "ms_per_solve": ms, "solves_per_s": 1000.0 / ms,
+                    "iterations": float(np.mean([i["iterations"] for i in infos])),
+                    "applies": float(np.mean([i["applies"] for i in infos])),
+                    "cycles": float(np.mean([i["cycles"] for i in infos])),
+                    "pc_fallback": int(max(i["pc_fallback"] for i in infos)),
+                    "max_relres_true": float(max(i["relres_true"] for i in infos))}
+
+    ms_plain, plain = timed("plain GMRES")
+    t_setup_ms = ctx.solve(fs[0], tol=1e-8)[1]["t_setup_ms"]
+    pc = None
+    if not args.no_pc:
+        from paper_1802_03061_amd import pc_train
+        F = pc_train.coarse_factor(n)
+        net, meta = pc_train.train_for(ctx, range(10000, 10012), "hg512", F, steps=args.train_steps,
+                                       mu_s=args.mu_s)
+        ctx.attach_pc(net.params(), hidden=meta["hidden"], layers=meta["layers"], factor=F)
+        ms_pc, pc = timed("learned-PC FGMRES")
+        pc["training"] = {k: meta[k] for k in ("pairs", "factor", "hidden", "layers", "steps", "t_data_s",
+                                                "t_train_s", "noise_ratio", "multiscale_ratio", "use_bias")}
+        pc["training"]["final_loss"] = meta["loss_history"][-1][1] if meta["loss_history"] else None
+        ctx.attach_pc(None)
+        net.close()
+    head = pc if pc is not None else plain
+    ms_per_step = head["ms_per_solve"]
+    iters = head["iterations"]
+    applies = plain["applies"]
+    relres = head["max_relres_true"]
 
     # apply throughput and per-pass times (HIP events on the context stream)
     ms_apply, ms_pass = ctx.time_apply(rte.OP_A, rte.PREC_FP32, reps=args.apply_reps)
@@ -144,9 +171,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"2D HG g=0.5, L=8 (17 modes), 512^2 cells, mu_a=0.1, mu_s={args.mu_s:g}, "
                                f"seeded Gaussian-mixture sources, tol 1e-8 (true FP64 residual)",
-                   "n": n, "L": L, "mu_s": args.mu_s, "tol": 1e-8, "preconditioner": "none"},
-        "solve": {"iterations": iters, "applies": applies, "max_relres_true": relres,
-                  "t_setup_ms": t_setup_ms},
+                   "n": n, "L": L, "mu_s": args.mu_s, "tol": 1e-8,
+                   "preconditioner": "learned coarse-grid CNN (FGMRES)" if pc else "none"},
+        "solve": {"iterations": iters, "max_relres_true": relres, "t_setup_ms": t_setup_ms},
+        "plain": plain,
+        "learned_pc": pc,
+        "pc_speedup_vs_plain": (plain["ms_per_solve"] / pc["ms_per_solve"]) if pc else None,
         "applies_per_s": 1000.0 / ms_apply,
         "apply_ms": {"fp32_total": ms_apply, "fp32_passes": dict(zip(names, ms_pass[:3])),
                      "fp64_total": ms_apply64, "fp64_passes": dict(zip(names, ms_pass64[:3]))},

@@ -142,8 +142,8 @@ int rte_solve_batched(int count, rte_ctx* const* ctxs, const double* const* f_de
                       const double* tol, int max_iter, void* const* u_dev, rte_solve_info* infos);
 
 /* Attach a learned right preconditioner for flexible GMRES: the coarse-grid correction
- * z = v + s P N(R v / s) of rte_nn.h (R: factor x factor block average, P: piecewise-constant
- * prolongation, s: RMS of R v, N: `layers` 3x3 convolutions C -> hidden -> ... -> C with ReLU
+ * z = v + s P N(R v / s) of rte_nn.h (R: factor x factor block average, P: bilinear interpolation from
+ * the coarse cell centres, s: RMS of v, N: `layers` 3x3 convolutions C -> hidden -> ... -> C with ReLU
  * between, C = 2L+1).  weights_dev: packed float32 parameters (layout in rte_nn.h); the context
  * keeps a BF16 copy.  factor must divide n_x and n_y.  NULL detaches.  2D contexts only.
  * A preconditioned cycle that fails to cut the true residual 10x, or produces a non-finite value,

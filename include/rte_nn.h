@@ -4,13 +4,14 @@
  * last) maps C = 2L+1 channels through `hidden` channels back to C channels.  As a
  * preconditioner it acts on a coarse grid:
  *
- *     z = v + s P N(R v / s),   R: F x F block average, P: piecewise-constant prolongation,
- *                               s: root-mean-square of R v,
+ *     z = v + s P N(R v / s),   R: F x F block average, P: bilinear interpolation from the coarse cell centres,
+ *                               s: root-mean-square of v over all cells and channels,
  *
  * and flexible GMRES uses z_j for the Arnoldi vector v_j.  It is trained on pairs (residual r,
- * error e = x* - x) of plain GMRES iterates: with x = R r / s and t = R(e - r) / s the objective
- * ||r + s P N(x) - e||^2 / ||e||^2 equals w ||N(x) - t||^2 + const with w = F^2 s^2 / ||e||^2
- * (P R is the orthogonal projector onto block-constant fields), so training runs on coarse data.
+ * error e = x* - x) of plain GMRES iterates and pairs (A u, u) of noise u: with x = R r / s and
+ * t = R(e - r) / s the network minimises w ||N(x) - t||^2, w = F^2 s^2 / ||e||^2, the coarse part
+ * of ||r + s P N(x) - e||^2 / ||e||^2 (exactly so for a block-constant P, for which P R is the
+ * orthogonal projector onto block-constant fields; a surrogate for the bilinear P used).
  *
  * Packed parameters (float32): for each layer l = 0..layers-1 the weights W_l[Cout][Cin][3][3]
  * followed by the bias b_l[Cout]; layer 0 is C -> hidden, the last hidden -> C.  Activations are
@@ -31,9 +32,12 @@ extern "C" {
 typedef struct rte_nn rte_nn;
 
 /* channels in 1..17 (odd: 2L+1), hidden 16 or 32, layers in 2..8.  Weights are drawn with a
- * seeded He-normal initialiser on the host, biases are zero; Adam moments start at zero. */
+ * seeded He-normal initialiser on the host, biases start at zero; Adam moments start at zero.
+ * use_bias = 0 keeps every bias at zero (their gradients are zeroed before each Adam step): the
+ * network is then positively homogeneous, N(c x) = c N(x) for c > 0, and so is the
+ * preconditioner, M(c v) = c M(v). */
 int rte_nn_create(rte_nn** out, int channels, int hidden, int layers, unsigned long long seed,
-                  void* hip_stream);
+                  int use_bias, void* hip_stream);
 void rte_nn_destroy(rte_nn* nn);
 int rte_nn_param_count(const rte_nn* nn, long long* count);
 int rte_nn_get_params(rte_nn* nn, float* dst_dev);
@@ -54,12 +58,15 @@ int rte_nn_adam_step(rte_nn* nn, float lr);
 /* Training pairs from `count` iterates x_j of a solve of A x = b with solution x_star (all FP64
  * channel vectors of the context): r_j = b - A x_j (FP64 apply), e_j = x_star - x_j, written as
  * coarse inputs x_out[j] = R r_j / s_j, targets t_out[j] = R (e_j - r_j) / s_j ([count][C][Hc][Wc],
- * Hc = ny / factor, Wc = nx / factor; factor must divide both) and weights
- * w_out[j] = factor^2 s_j^2 / ||e_j||^2. */
+ * Hc = ny / factor, Wc = nx / factor; factor must divide both), s_j = ||r_j|| / sqrt(C ny nx), and
+ * weights w_out[j] = factor^2 s_j^2 / ||e_j||^2.  With b = 0 and x_star = 0 an "iterate" -u gives
+ * the pair (r, e) = (A u, u) without a solve. */
 int rte_pc_make_pairs(rte_ctx* ctx, const double* b_dev, const double* x_star_dev, const double* x_iters_dev,
                       int count, int factor, float* x_out, float* t_out, float* w_out);
 
-/* The network is attached to a solver context with rte_pc_attach (rte.h). */
+/* The network is attached to a solver context with rte_pc_attach (rte.h).  z = M v with the
+ * attached preconditioner on one FP64 channel vector of the context (z may not alias v). */
+int rte_pc_apply(rte_ctx* ctx, const double* v_dev, double* z_dev);
 
 #ifdef __cplusplus
 }

@@ -114,6 +114,38 @@ def prolong(vc: np.ndarray, F: int) -> np.ndarray:
     return np.repeat(np.repeat(vc, F, axis=-2), F, axis=-1)
 
 
+def prolong_bilinear(vc: np.ndarray, F: int) -> np.ndarray:
+    """Bilinear interpolation from coarse cell centres to fine cell centres (cell-centred grids,
+    coarse cell I covers fine cells I*F .. I*F+F-1).  A fine centre at coarse coordinate
+    xi = (i + 1/2)/F - 1/2 takes (1 - a) v[I0] + a v[I0+1], I0 = floor(xi), a = xi - I0, with the
+    indices clamped to the coarse grid (constant extension beyond the outer coarse centres)."""
+    *lead, Hc, Wc = vc.shape
+    def weights(nc):
+        n = nc * F
+        xi = (np.arange(n) + 0.5) / F - 0.5
+        i0 = np.floor(xi).astype(int)
+        a = xi - i0
+        lo = np.clip(i0, 0, nc - 1)
+        hi = np.clip(i0 + 1, 0, nc - 1)
+        W = np.zeros((n, nc))
+        W[np.arange(n), lo] += 1 - a
+        W[np.arange(n), hi] += a
+        return W
+    Wy, Wx = weights(Hc), weights(Wc)
+    return np.einsum("yI,...IJ,xJ->...yx", Wy, vc, Wx)
+
+
+def precondition(v: np.ndarray, params, F: int) -> np.ndarray:
+    """The learned right preconditioner on one channel vector v [C, ny, nx]:
+    z = v + s P N(R v / s), R = F x F block average, P = bilinear prolongation,
+    s = root-mean-square of v."""
+    s = np.sqrt(np.mean(v ** 2))
+    if s == 0.0:
+        return v.copy()
+    y, _ = net_forward(restrict(v, F)[None] / s, params)
+    return v + s * prolong_bilinear(y[0], F)
+
+
 def adam_step(param, grad, m, v, t: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     """One Adam update (Kingma and Ba), bias-corrected; returns new (param, m, v)."""
     m = beta1 * m + (1 - beta1) * grad

@@ -57,6 +57,9 @@ struct rte_ctx {
     float* pc_act1 = nullptr;
     float* pc_coarse = nullptr; // restricted input
     float* pc_st = nullptr;     // [s, 1/s]
+    double* pc_nrm = nullptr;   // |v|^2
+    double* pc_part = nullptr;  // per-block partial sums of v^2
+    int* pc_meta = nullptr;     // per layer: cin, cout, weight pack offset, bias offset
 };
 
 namespace rte {

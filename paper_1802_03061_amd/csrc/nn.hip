@@ -1,4 +1,8 @@
 // Learned right preconditioner: a coarse-grid 3x3 convolution network (see include/rte_nn.h).
+// The correction is computed on an F x F block-averaged grid and interpolated back bilinearly:
+// the predicted error is tens of times larger than the residual, so it must come back smooth --
+// jumps at block edges would reappear almost unchanged in A z (A is close to the identity on
+// rough fields) and swamp the residual.
 //
 // Convolution as an implicit GEMM on MFMA: out[o][p] = sum_k W[o][k] X[k][p] with k = c*9 + tap
 // (tap = 3*(dy+1) + (dx+1)) and X[k][p] the input at p + (dy, dx).  Each 64-lane wave computes a
@@ -220,13 +224,44 @@ __global__ void k_pool(const double* __restrict__ a, const double* __restrict__ 
     out[idx] = (float)(s / ((double)F * F));
 }
 
-// Single block: s = sqrt(mean(x^2)) over n values; st[0] = s, st[1] = 1/s (0 if s == 0).
-__global__ __launch_bounds__(256) void k_rms(const float* __restrict__ x, int n, float* __restrict__ st) {
+// One block per (channel, coarse row): column sums over the F fine rows, then F-wide groups into
+// coarse cells; also the block's sum of v^2 for the RMS (partial[blockIdx], fixed order later).
+__global__ __launch_bounds__(256) void k_pool_norm(const double* __restrict__ v, float* __restrict__ out,
+                                                   double* __restrict__ partial, int ny, int nx, int F) {
+    __shared__ double colsum[512];
     __shared__ double sh[4];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) s += (double)x[i] * x[i];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    const int Hc = ny / F, Wc = nx / F;
+    const int c = blockIdx.x / Hc, I = blockIdx.x % Hc;
+    double sq = 0.0;
+    for (int x = threadIdx.x; x < nx; x += 256) {
+        double cs = 0.0;
+        for (int u = 0; u < F; ++u) {
+            const double val = v[((size_t)c * ny + I * F + u) * nx + x];
+            cs += val;
+            sq += val * val;
+        }
+        colsum[x] = cs;
+    }
+    __syncthreads();
+    for (int J = threadIdx.x; J < Wc; J += 256) {
+        double t = 0.0;
+        for (int q = 0; q < F; ++q) t += colsum[J * F + q];
+        out[((size_t)c * Hc + I) * Wc + J] = (float)(t / ((double)F * F));
+    }
+    for (int off = 32; off > 0; off >>= 1) sq += __shfl_down(sq, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// Single block: n2 = sum of the np partials in a fixed order; st = [s, 1/s], s = sqrt(n2 / n).
+__global__ __launch_bounds__(256) void k_scale_from_partials(const double* __restrict__ partial, int np, double n,
+                                                             float* __restrict__ st) {
+    __shared__ double sh[4];
+    double t = 0.0;
+    for (int i = threadIdx.x; i < np; i += 256) t += partial[i];
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
     __syncthreads();
     if (threadIdx.x == 0) {
         const double r = sqrt((sh[0] + sh[1] + sh[2] + sh[3]) / n);
@@ -235,7 +270,93 @@ __global__ __launch_bounds__(256) void k_rms(const float* __restrict__ x, int n,
     }
 }
 
-// z = v + s * y[c][i/F][j/F]
+// The whole network in one workgroup for a small coarse grid (Hc <= 32 rows, Wc <= 32): activations
+// stay in LDS as BF16 with a zero halo; each wave takes rows of the grid and runs the same MFMA
+// tile as k_conv3x3 on them; the last layer writes FP32 to global memory.
+template <int HID>
+__global__ __launch_bounds__(256) void k_net_fused(const float* __restrict__ in, const float* __restrict__ in_scale,
+                                                   const unsigned short* __restrict__ wf, const float* __restrict__ params,
+                                                   const int* __restrict__ meta, int layers, int C, int Hc, int Wc,
+                                                   float* __restrict__ out) {
+    // meta: per layer [cin, cout, wpack offset, bias offset]
+    constexpr int MAXC = HID > 17 ? HID : 17;
+    extern __shared__ unsigned short lds[];
+    const int P = (Hc + 2) * (Wc + 2);
+    unsigned short* buf[2] = {lds, lds + MAXC * P};
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const float sc = *in_scale;
+    for (int idx = threadIdx.x; idx < 2 * MAXC * P; idx += 256) lds[idx] = 0;
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < C * Hc * Wc; idx += 256) {
+        const int c = idx / (Hc * Wc), r = idx % (Hc * Wc);
+        const int y = r / Wc, x = r % Wc;
+        buf[0][c * P + (y + 1) * (Wc + 2) + x + 1] = f2bf(in[idx] * sc);
+    }
+    __syncthreads();
+    for (int l = 0; l < layers; ++l) {
+        const int cin = meta[4 * l], cout = meta[4 * l + 1];
+        const unsigned short* Wp = wf + meta[4 * l + 2];
+        const float* bias = params + meta[4 * l + 3];
+        const bool last = l == layers - 1;
+        const int KP = (cin * 9 + 7) / 8 * 8, K = cin * 9;
+        const unsigned short* src = buf[l & 1];
+        unsigned short* dst = buf[(l + 1) & 1];
+        const int ai = lane & 31, kq = (lane >> 5) * 4, j = lane & 31;
+        for (int y = wave; y < Hc; y += 4) {
+            f32x16 acc;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+            for (int kb = 0; kb < KP / 8; ++kb) {
+                const bf16x4 a = *reinterpret_cast<const bf16x4*>(Wp + (size_t)ai * KP + kb * 8 + kq);
+                bf16x4 bv;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int k = kb * 8 + kq + r;
+                    unsigned short val = 0;
+                    if (k < K && j < Wc) {
+                        const int c = k / 9, t = k % 9;
+                        val = src[c * P + (y + t / 3) * (Wc + 2) + j + t % 3];
+                    }
+                    bv[r] = (short)val;
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bv, acc, 0, 0, 0);
+            }
+            if (j < Wc) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    if (i < cout) {
+                        const float v = acc[r] + bias[i];
+                        if (last) out[((size_t)i * Hc + y) * Wc + j] = v;
+                        else dst[i * P + (y + 1) * (Wc + 2) + j + 1] = f2bf(fmaxf(v, 0.f));
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// st[0] = s = sqrt(norm2 / n), st[1] = 1/s (0 if s == 0).
+__global__ void k_scale_from_norm2(const double* __restrict__ norm2, double n, float* __restrict__ st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double r = sqrt(norm2[0] / n);
+        st[0] = (float)r;
+        st[1] = r > 0.0 ? (float)(1.0 / r) : 0.f;
+    }
+}
+
+// z = v + s * (P y): P is bilinear interpolation from the coarse cell centres (coarse cell I
+// spans fine cells I*F .. I*F+F-1), clamped to the outer coarse centres.
+__device__ __forceinline__ void lerp_index(int i, int F, int nc, int& lo, int& hi, float& a) {
+    const float xi = ((float)i + 0.5f) / (float)F - 0.5f;
+    const float f0 = floorf(xi);
+    a = xi - f0;
+    const int i0 = (int)f0;
+    lo = min(max(i0, 0), nc - 1);
+    hi = min(max(i0 + 1, 0), nc - 1);
+}
+
 __global__ void k_prolong_add(const double* __restrict__ v, const float* __restrict__ y, const float* __restrict__ st,
                               double* __restrict__ z, int C, int ny, int nx, int F) {
     const size_t n = (size_t)C * ny * nx;
@@ -245,28 +366,26 @@ __global__ void k_prolong_add(const double* __restrict__ v, const float* __restr
         const int xx = (int)(i % nx);
         const int yy = (int)((i / nx) % ny);
         const int c = (int)(i / ((size_t)nx * ny));
-        z[i] = v[i] + s * (double)y[((size_t)c * Hc + yy / F) * Wc + xx / F];
+        int y0, y1, x0, x1;
+        float ay, ax;
+        lerp_index(yy, F, Hc, y0, y1, ay);
+        lerp_index(xx, F, Wc, x0, x1, ax);
+        const float* yc = y + (size_t)c * Hc * Wc;
+        const float top = (1.f - ax) * yc[y0 * Wc + x0] + ax * yc[y0 * Wc + x1];
+        const float bot = (1.f - ax) * yc[y1 * Wc + x0] + ax * yc[y1 * Wc + x1];
+        z[i] = v[i] + s * (double)((1.f - ay) * top + ay * bot);
     }
 }
 
-// Training pair normalisation (single block): s^2 = mean(xr^2); x = xr/s, t = xt/s,
-// w = F^2 s^2 / |e|^2 (e2 on the device).
-__global__ __launch_bounds__(256) void k_pair_finish(float* __restrict__ xr, float* __restrict__ xt, int n,
+// Training pair normalisation (single block): s^2 = |r|^2 / n (fine grid); x = xr/s, t = xt/s,
+// w = F^2 s^2 / |e|^2 (|r|^2 in r2, |e|^2 in e2, both on the device).
+__global__ __launch_bounds__(256) void k_pair_finish(float* __restrict__ xr, float* __restrict__ xt, int nco,
+                                                     const double* __restrict__ r2, double nfine,
                                                      const double* __restrict__ e2, float* __restrict__ w, int F) {
-    __shared__ double sh[4];
-    __shared__ double sc;
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) s += (double)xr[i] * xr[i];
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const double ms = (sh[0] + sh[1] + sh[2] + sh[3]) / n;
-        sc = ms > 0.0 ? 1.0 / sqrt(ms) : 0.0;
-        w[0] = (e2[0] > 0.0) ? (float)((double)F * F * ms / e2[0]) : 0.f;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += 256) {
+    const double ms = r2[0] / nfine;
+    const double sc = ms > 0.0 ? 1.0 / sqrt(ms) : 0.0;
+    if (threadIdx.x == 0) w[0] = (e2[0] > 0.0) ? (float)((double)F * F * ms / e2[0]) : 0.f;
+    for (int i = threadIdx.x; i < nco; i += 256) {
         xr[i] = (float)(xr[i] * sc);
         xt[i] = (float)(xt[i] * sc);
     }
@@ -321,6 +440,12 @@ struct NetShape {
     }
 };
 
+// The fused network kernel holds two BF16 activation grids with halo in LDS (at most 64 KiB).
+static bool fused_net_fits(int hidden, int Hc, int Wc) {
+    const int MAXC = hidden > 17 ? hidden : 17;
+    return Hc <= 32 && Wc <= 32 && (size_t)2 * MAXC * (Hc + 2) * (Wc + 2) * 2 <= 65536;
+}
+
 static bool valid_net(int C, int hidden, int layers) {
     return C >= 1 && C <= 17 && (C & 1) && (hidden == 16 || hidden == 32) && layers >= 2 && layers <= 8;
 }
@@ -333,6 +458,7 @@ struct rte_nn {
     float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
     unsigned short *wf = nullptr, *wb = nullptr;
     int step = 0;
+    bool use_bias = true;
     size_t cap = 0;                    // activation capacity in floats per tensor
     std::vector<float*> act, pre;      // act[l]: input of layer l (act[0] unused), pre[l]: pre-activation
     float *gA = nullptr, *gB = nullptr;
@@ -400,6 +526,9 @@ void pc_free(rte_ctx* c) {
     nfree(c->pc_act1);
     nfree(c->pc_coarse);
     nfree(c->pc_st);
+    nfree(c->pc_nrm);
+    nfree(c->pc_part);
+    nfree(c->pc_meta);
     c->pc_attached = false;
 }
 
@@ -408,22 +537,34 @@ int pc_apply(rte_ctx* c, const double* v, double* z) {
     sh.init(c->C, c->pc_hidden, c->pc_layers);
     const int F = c->pc_factor;
     const int Hc = c->ny / F, Wc = c->nx / F;
-    const int nco = c->C * Hc * Wc;
     hipStream_t st = c->stream;
-    hipLaunchKernelGGL(k_pool, dim3((nco + 255) / 256), dim3(256), 0, st, v, (const double*)nullptr,
-                       (const double*)nullptr, c->pc_coarse, c->C, c->ny, c->nx, F);
-    hipLaunchKernelGGL(k_rms, dim3(1), dim3(256), 0, st, c->pc_coarse, nco, c->pc_st);
-    // ping-pong activations: layer l writes act[(l % 2)]
-    float* bufs[2] = {c->pc_act0, c->pc_act1};
+    // restriction and the RMS of v in one pass
+    hipLaunchKernelGGL(k_pool_norm, dim3(c->C * Hc), dim3(256), 0, st, v, c->pc_coarse, c->pc_part, c->ny, c->nx, F);
+    hipLaunchKernelGGL(k_scale_from_partials, dim3(1), dim3(256), 0, st, c->pc_part, c->C * Hc, (double)c->nvec,
+                       c->pc_st);
     const float* a = c->pc_coarse;
     const unsigned short* wf = (const unsigned short*)c->pc_w;
-    for (int l = 0; l < sh.layers; ++l) {
-        const bool last = l == sh.layers - 1;
-        float* o = bufs[l & 1];
-        if (conv_launch(sh.cin[l], a, wf + sh.pf_off[l], c->pc_b + sh.boff[l], sh.cout[l], o, nullptr, nullptr, !last,
-                        l == 0 ? c->pc_st + 1 : nullptr, 1, Hc, Wc, st))
-            return set_error(RTE_EUNSUPPORTED, "unsupported convolution width");
-        a = o;
+    if (fused_net_fits(c->pc_hidden, Hc, Wc)) {
+        const int MAXC = std::max(c->pc_hidden, 17);
+        const size_t lds = (size_t)2 * MAXC * (Hc + 2) * (Wc + 2) * sizeof(unsigned short);
+        if (c->pc_hidden == 32)
+            hipLaunchKernelGGL((k_net_fused<32>), dim3(1), dim3(256), lds, st, c->pc_coarse, c->pc_st + 1, wf, c->pc_b,
+                               c->pc_meta, sh.layers, c->C, Hc, Wc, c->pc_act0);
+        else
+            hipLaunchKernelGGL((k_net_fused<16>), dim3(1), dim3(256), lds, st, c->pc_coarse, c->pc_st + 1, wf, c->pc_b,
+                               c->pc_meta, sh.layers, c->C, Hc, Wc, c->pc_act0);
+        a = c->pc_act0;
+    } else {
+        // ping-pong activations: layer l writes act[(l % 2)]
+        float* bufs[2] = {c->pc_act0, c->pc_act1};
+        for (int l = 0; l < sh.layers; ++l) {
+            const bool last = l == sh.layers - 1;
+            float* o = bufs[l & 1];
+            if (conv_launch(sh.cin[l], a, wf + sh.pf_off[l], c->pc_b + sh.boff[l], sh.cout[l], o, nullptr, nullptr, !last,
+                            l == 0 ? c->pc_st + 1 : nullptr, 1, Hc, Wc, st))
+                return set_error(RTE_EUNSUPPORTED, "unsupported convolution width");
+            a = o;
+        }
     }
     const size_t n = c->nvec;
     hipLaunchKernelGGL(k_prolong_add, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, st, v, a,
@@ -454,7 +595,9 @@ int rte_pc_attach(rte_ctx* c, const float* weights, int hidden, int layers, int 
     if ((rc = nalloc(&wf, sh.pf_off_total))) return rc;
     c->pc_w = wf;
     if ((rc = nalloc(&c->pc_b, sh.nparam)) || (rc = nalloc(&c->pc_act0, per)) || (rc = nalloc(&c->pc_act1, per)) ||
-        (rc = nalloc(&c->pc_coarse, (size_t)c->C * Hc * Wc)) || (rc = nalloc(&c->pc_st, 4))) {
+        (rc = nalloc(&c->pc_coarse, (size_t)c->C * Hc * Wc)) || (rc = nalloc(&c->pc_st, 4)) ||
+        (rc = nalloc(&c->pc_nrm, 2)) || (rc = nalloc(&c->pc_part, (size_t)c->C * Hc)) ||
+        (rc = nalloc(&c->pc_meta, (size_t)4 * layers))) {
         pc_free(c);
         return rc;
     }
@@ -462,6 +605,17 @@ int rte_pc_attach(rte_ctx* c, const float* weights, int hidden, int layers, int 
     hipError_t e = hipMemcpyAsync(c->pc_b, weights, sh.nparam * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) { pc_free(c); return set_hip_error(e, "pc weights", __FILE__, __LINE__); }
     pack_all(sh, weights, wf, nullptr, c->stream);
+    std::vector<int> meta(4 * layers);
+    for (int l = 0; l < layers; ++l) {
+        meta[4 * l] = sh.cin[l];
+        meta[4 * l + 1] = sh.cout[l];
+        meta[4 * l + 2] = (int)sh.pf_off[l];
+        meta[4 * l + 3] = (int)sh.boff[l];
+    }
+    e = hipMemcpyAsync(c->pc_meta, meta.data(), meta.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) { pc_free(c); return set_hip_error(e, "pc meta", __FILE__, __LINE__); }
+    if (c->nx > 512) { pc_free(c); return set_error(RTE_EUNSUPPORTED, "grid too wide for the restriction kernel"); }
     c->pc_hidden = hidden;
     c->pc_layers = layers;
     c->pc_factor = factor;
@@ -470,13 +624,20 @@ int rte_pc_attach(rte_ctx* c, const float* weights, int hidden, int layers, int 
     return e == hipSuccess ? RTE_OK : set_hip_error(e, "rte_pc_attach", __FILE__, __LINE__);
 }
 
-int rte_nn_create(rte_nn** out, int C, int hidden, int layers, unsigned long long seed, void* stream) {
+int rte_pc_apply(rte_ctx* c, const double* v, double* z) {
+    if (!c || !v || !z || v == z) return set_error(RTE_EINVAL, "bad argument");
+    if (!c->pc_attached) return set_error(RTE_EINVAL, "no preconditioner attached");
+    return pc_apply(c, v, z);
+}
+
+int rte_nn_create(rte_nn** out, int C, int hidden, int layers, unsigned long long seed, int use_bias, void* stream) {
     if (!out) return set_error(RTE_EINVAL, "out is NULL");
     *out = nullptr;
     if (!valid_net(C, hidden, layers)) return set_error(RTE_EINVAL, "bad network shape");
     rte_nn* nn = new rte_nn();
     nn->sh.init(C, hidden, layers);
     nn->stream = (hipStream_t)stream;
+    nn->use_bias = use_bias != 0;
     const size_t np = nn->sh.nparam;
     int rc;
     if ((rc = nalloc(&nn->p, np)) || (rc = nalloc(&nn->g, np)) || (rc = nalloc(&nn->m, np)) || (rc = nalloc(&nn->v, np)) ||
@@ -566,6 +727,9 @@ int rte_nn_loss_grad(rte_nn* nn, const float* x, const float* t, const float* w,
             std::swap(gcur, gnext);
         }
     }
+    if (!nn->use_bias)
+        for (int l = 0; l < sh.layers; ++l)
+            RTE_HIP_TRY(hipMemsetAsync(nn->g + sh.boff[l], 0, sh.cout[l] * sizeof(float), st));
     std::vector<double> lb(B);
     RTE_HIP_TRY(hipMemcpyAsync(lb.data(), nn->lossb, B * sizeof(double), hipMemcpyDeviceToHost, st));
     if (grad) RTE_HIP_TRY(hipMemcpyAsync(grad, nn->g, sh.nparam * sizeof(float), hipMemcpyDeviceToDevice, st));
@@ -603,13 +767,15 @@ int rte_pc_make_pairs(rte_ctx* c, const double* b, const double* xs, const doubl
         if (rc) return rc;
         hipLaunchKernelGGL(k_sub, dim3(2048), dim3(256), 0, st, xs, xj, c->t1, n);
         krylov_dots(c->t1, n, 1, c->t1, n, c->partial, c->dsmall, false, st);
+        krylov_dots(c->rv, n, 1, c->rv, n, c->partial, c->dsmall + 1, false, st);
         float* xr = xo + (size_t)j * nco;
         float* xt = to + (size_t)j * nco;
         hipLaunchKernelGGL(k_pool, dim3((nco + 255) / 256), dim3(256), 0, st, c->rv, (const double*)nullptr,
                            (const double*)nullptr, xr, c->C, c->ny, c->nx, F);
         hipLaunchKernelGGL(k_pool, dim3((nco + 255) / 256), dim3(256), 0, st, c->t1, c->rv, (const double*)nullptr, xt,
                            c->C, c->ny, c->nx, F);
-        hipLaunchKernelGGL(k_pair_finish, dim3(1), dim3(256), 0, st, xr, xt, nco, c->dsmall, wo + j, F);
+        hipLaunchKernelGGL(k_pair_finish, dim3(1), dim3(256), 0, st, xr, xt, nco, c->dsmall + 1, (double)n, c->dsmall,
+                           wo + j, F);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? RTE_OK : set_hip_error(e, "rte_pc_make_pairs", __FILE__, __LINE__);

@@ -69,7 +69,7 @@ def load():
         "rte_solve_batched": (I, [I, C.POINTER(P), C.POINTER(P), C.POINTER(D), I, C.POINTER(P),
                                   C.POINTER(SolveInfo)]),
         "rte_pc_attach": (I, [P, P, I, I, I]),
-        "rte_nn_create": (I, [C.POINTER(P), I, I, I, C.c_ulonglong, P]),
+        "rte_nn_create": (I, [C.POINTER(P), I, I, I, C.c_ulonglong, I, P]),
         "rte_nn_destroy": (None, [P]),
         "rte_nn_param_count": (I, [P, C.POINTER(C.c_longlong)]),
         "rte_nn_get_params": (I, [P, P]),
@@ -78,6 +78,7 @@ def load():
         "rte_nn_loss_grad": (I, [P, P, P, P, I, I, I, C.POINTER(D), P]),
         "rte_nn_adam_step": (I, [P, C.c_float]),
         "rte_pc_make_pairs": (I, [P, P, P, P, I, I, P, P, P]),
+        "rte_pc_apply": (I, [P, P, P]),
         "rte_time_apply": (I, [P, I, I, I, C.POINTER(D), C.POINTER(D)]),
         "rte_query": (I, [P, C.POINTER(I), C.POINTER(I), C.POINTER(C.c_longlong)]),
         "rte_modes_to_channels": (I, [P, P, P]),
@@ -245,6 +246,13 @@ class Context:
         wp = _ptr(weights, torch.float32)
         _check(load().rte_pc_attach(self._h, wp, int(hidden), int(layers), int(factor)))
 
+    def pc_apply(self, v):
+        """z = M v with the attached preconditioner (channel layout, FP64)."""
+        z = torch.empty_like(v)
+        _check(load().rte_pc_apply(self._h, _ptr(v, torch.float64, self.channels * self.cells),
+                                   C.c_void_p(z.data_ptr())))
+        return z
+
     def make_pairs(self, b, x_star, x_iters, factor):
         """Coarse training pairs (inputs, targets, weights) from iterates of a solve of A x = b."""
         cnt = int(x_iters.shape[0])
@@ -290,11 +298,11 @@ def solve_batched(ctxs, fs, tols, max_iter=1000, allow_not_converged=False):
 class Net:
     """The preconditioner network's parameters, forward, gradient and Adam (rte_nn.h)."""
 
-    def __init__(self, channels, hidden=32, layers=5, seed=0):
+    def __init__(self, channels, hidden=32, layers=5, seed=0, use_bias=True):
         lib = load()
         h = C.c_void_p()
         _check(lib.rte_nn_create(C.byref(h), int(channels), int(hidden), int(layers), int(seed),
-                                 C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+                                 1 if use_bias else 0, C.c_void_p(torch.cuda.current_stream().cuda_stream)))
         self._h = h
         self.channels, self.hidden, self.layers = int(channels), int(hidden), int(layers)
         cnt = C.c_longlong()

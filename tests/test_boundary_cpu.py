@@ -98,7 +98,7 @@ def test_nn_create_rejects_bad_shapes(lib):
     from paper_1802_03061_amd import rte
     out = C.c_void_p()
     for ch, hid, lay in ((2, 32, 5), (19, 32, 5), (9, 24, 5), (9, 32, 1), (9, 32, 9)):
-        assert lib.rte_nn_create(C.byref(out), ch, hid, lay, 0, None) == rte.RTE_EINVAL
+        assert lib.rte_nn_create(C.byref(out), ch, hid, lay, 0, 1, None) == rte.RTE_EINVAL
         assert out.value is None
     assert lib.rte_nn_adam_step(None, C.c_float(1e-3)) == rte.RTE_EINVAL
     assert lib.rte_pc_attach(None, None, 32, 5, 4) == rte.RTE_EINVAL

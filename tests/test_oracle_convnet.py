@@ -95,3 +95,32 @@ def test_coarse_loss_gradient_and_decomposition():
     rhs = np.sum(((r - e) - cn.prolong(cn.restrict(r - e, F), F)) ** 2) + \
         F * F * s * s * np.sum((y - cn.restrict(e - r, F) / s) ** 2)
     assert abs(lhs - rhs) <= 1e-12 * lhs
+
+
+def test_bilinear_prolongation_reproduces_linear_fields():
+    """Bilinear interpolation is exact for fields linear in the coordinates (away from the outer
+    half coarse cell, where the clamp extends the outer values), and keeps constants everywhere."""
+    F, Hc, Wc = 4, 5, 6
+    yc = (np.arange(Hc) + 0.5) * F
+    xc = (np.arange(Wc) + 0.5) * F
+    vc = 2.0 + 0.3 * yc[:, None] - 0.7 * xc[None, :]
+    v = cn.prolong_bilinear(vc, F)
+    yf = np.arange(Hc * F) + 0.5
+    xf = np.arange(Wc * F) + 0.5
+    exact = 2.0 + 0.3 * yf[:, None] - 0.7 * xf[None, :]
+    inner = slice(F // 2, -(F // 2))
+    assert np.abs(v[inner, inner] - exact[inner, inner]).max() < 1e-12
+    c = cn.prolong_bilinear(np.full((2, Hc, Wc), 3.25), F)
+    assert np.abs(c - 3.25).max() < 1e-15
+    # block average of the prolongation of a linear field returns it (interior blocks)
+    assert np.abs(cn.restrict(v, F)[1:-1, 1:-1] - vc[1:-1, 1:-1]).max() < 1e-12
+
+
+def test_precondition_is_homogeneous_without_biases():
+    rng = np.random.default_rng(4)
+    C, Hd, F = 3, 8, 4
+    params = [(0.3 * rng.standard_normal((Hd, C, 3, 3)), np.zeros(Hd)),
+              (0.3 * rng.standard_normal((C, Hd, 3, 3)), np.zeros(C))]
+    v = rng.standard_normal((C, 16, 12))
+    z = cn.precondition(v, params, F)
+    assert np.abs(cn.precondition(3.7 * v, params, F) - 3.7 * z).max() < 1e-12 * np.abs(z).max()
