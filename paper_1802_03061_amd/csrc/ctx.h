@@ -59,7 +59,9 @@ struct rte_ctx {
     float* pc_st = nullptr;     // [s, 1/s]
     double* pc_nrm = nullptr;   // |v|^2
     double* pc_part = nullptr;  // per-block partial sums of v^2
-    int* pc_meta = nullptr;     // per layer: cin, cout, weight pack offset, bias offset
+    int* pc_meta = nullptr;     // per layer: cin, cout, tap-major pack offset, bias offset
+    unsigned short* pc_wn = nullptr;   // tap-major BF16 weights of the single-workgroup network kernel
+    size_t pc_wn_len = 0;              // its length in shorts
 };
 
 namespace rte {

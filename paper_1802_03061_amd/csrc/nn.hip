@@ -235,6 +235,7 @@ __global__ __launch_bounds__(256) void k_pool_norm(const double* __restrict__ v,
     double sq = 0.0;
     for (int x = threadIdx.x; x < nx; x += 256) {
         double cs = 0.0;
+#pragma unroll 8
         for (int u = 0; u < F; ++u) {
             const double val = v[((size_t)c * ny + I * F + u) * nx + x];
             cs += val;
@@ -270,65 +271,99 @@ __global__ __launch_bounds__(256) void k_scale_from_partials(const double* __res
     }
 }
 
-// The whole network in one workgroup for a small coarse grid (Hc <= 32 rows, Wc <= 32): activations
-// stay in LDS as BF16 with a zero halo; each wave takes rows of the grid and runs the same MFMA
-// tile as k_conv3x3 on them; the last layer writes FP32 to global memory.
+// The whole network in one workgroup for a small coarse grid (Hc <= 32 rows, Wc <= 32).
+// Activations stay in LDS as BF16, channel-innermost ([pixel][channel], pixel stride NET_PS shorts,
+// zero halo and zero padded channels), so that for one 3x3 tap the four consecutive K values a
+// lane feeds to the MFMA are one 8-byte LDS read.  The reduction index is tap-major,
+// k = t * CP + c (CP: input channels rounded up to 8, so an 8-wide K step never straddles taps).
+// Every layer's weights are loaded into LDS up front (tap-major rows of stride KS, prepacked by
+// k_pack_tapmajor), so the only global reads are that copy, the input and the biases.  One wave per
+// coarse row; the last layer writes FP32 [c][y][x] to global memory.
+constexpr int NET_THREADS = 1024;
+constexpr int NET_PS = 36;                  // pixel stride in shorts: 32 channels + 4 (bank spread)
+__host__ __device__ constexpr int net_cp(int c) { return (c + 7) / 8 * 8; }
+__host__ __device__ constexpr int net_ks(int cin) { return 9 * net_cp(cin) + 4; }   // weight row stride
+
+// dst[i][k] (row stride KS) = weight of output i, tap t = k / CP, input channel c = k % CP, taken
+// from the forward pack (k' = c*9 + t, stride KG); zero for padded channels and the row tail.
+__global__ void k_pack_tapmajor(const unsigned short* __restrict__ wf, int cin, unsigned short* __restrict__ dst) {
+    const int CP = net_cp(cin), KS = net_ks(cin), KG = kpad(cin);
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < 32 * KS; idx += gridDim.x * blockDim.x) {
+        const int i = idx / KS, k = idx % KS;
+        unsigned short v = 0;
+        if (k < 9 * CP) {
+            const int t = k / CP, c = k % CP;
+            if (c < cin) v = wf[(size_t)i * KG + c * 9 + t];
+        }
+        dst[idx] = v;
+    }
+}
+
 template <int HID>
-__global__ __launch_bounds__(256) void k_net_fused(const float* __restrict__ in, const float* __restrict__ in_scale,
-                                                   const unsigned short* __restrict__ wf, const float* __restrict__ params,
-                                                   const int* __restrict__ meta, int layers, int C, int Hc, int Wc,
-                                                   float* __restrict__ out) {
-    // meta: per layer [cin, cout, wpack offset, bias offset]
-    constexpr int MAXC = HID > 17 ? HID : 17;
-    extern __shared__ unsigned short lds[];
+__global__ __launch_bounds__(NET_THREADS) void k_net_fused(const float* __restrict__ in, const float* __restrict__ in_scale,
+                                                           const unsigned short* __restrict__ wn, int nwn,
+                                                           const float* __restrict__ params, const int* __restrict__ meta,
+                                                           int layers, int C, int Hc, int Wc, float* __restrict__ out) {
+    // meta: per layer [cin, cout, tap-major pack offset, bias offset]; nwn: pack length (multiple of 8)
+    static_assert(HID <= 32 && NET_PS >= 32 + 4, "pixel stride");
+    extern __shared__ __attribute__((aligned(16))) unsigned short lds[];
     const int P = (Hc + 2) * (Wc + 2);
-    unsigned short* buf[2] = {lds, lds + MAXC * P};
+    unsigned short* act[2] = {lds, lds + (size_t)P * NET_PS};
+    unsigned short* Wall = lds + (size_t)2 * P * NET_PS;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const float sc = *in_scale;
-    for (int idx = threadIdx.x; idx < 2 * MAXC * P; idx += 256) lds[idx] = 0;
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < C * Hc * Wc; idx += 256) {
-        const int c = idx / (Hc * Wc), r = idx % (Hc * Wc);
-        const int y = r / Wc, x = r % Wc;
-        buf[0][c * P + (y + 1) * (Wc + 2) + x + 1] = f2bf(in[idx] * sc);
+    {
+        const uint4* ws = reinterpret_cast<const uint4*>(wn);
+        uint4* wd = reinterpret_cast<uint4*>(Wall);
+        for (int idx = threadIdx.x; idx < nwn / 8; idx += NET_THREADS) wd[idx] = ws[idx];
+        uint4* az = reinterpret_cast<uint4*>(lds);
+        const uint4 zero = {0u, 0u, 0u, 0u};
+        for (int idx = threadIdx.x; idx < 2 * P * NET_PS / 8; idx += NET_THREADS) az[idx] = zero;
     }
     __syncthreads();
+    for (int idx = threadIdx.x; idx < C * Hc * Wc; idx += NET_THREADS) {
+        const int c = idx / (Hc * Wc), r = idx % (Hc * Wc);
+        const int y = r / Wc, x = r % Wc;
+        act[0][((y + 1) * (Wc + 2) + x + 1) * NET_PS + c] = f2bf(in[idx] * sc);
+    }
+    __syncthreads();
+    const int j = lane & 31, hi = lane >> 5;
     for (int l = 0; l < layers; ++l) {
         const int cin = meta[4 * l], cout = meta[4 * l + 1];
-        const unsigned short* Wp = wf + meta[4 * l + 2];
+        const unsigned short* Wl = Wall + meta[4 * l + 2];
         const float* bias = params + meta[4 * l + 3];
         const bool last = l == layers - 1;
-        const int KP = (cin * 9 + 7) / 8 * 8, K = cin * 9;
-        const unsigned short* src = buf[l & 1];
-        unsigned short* dst = buf[(l + 1) & 1];
-        const int ai = lane & 31, kq = (lane >> 5) * 4, j = lane & 31;
-        for (int y = wave; y < Hc; y += 4) {
+        const int CP = net_cp(cin), K = 9 * CP, KS = net_ks(cin);
+        const unsigned short* src = act[l & 1];
+        unsigned short* dst = act[(l + 1) & 1];
+        for (int y = wave; y < Hc; y += NET_THREADS / 64) {
             f32x16 acc;
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-            for (int kb = 0; kb < KP / 8; ++kb) {
-                const bf16x4 a = *reinterpret_cast<const bf16x4*>(Wp + (size_t)ai * KP + kb * 8 + kq);
-                bf16x4 bv;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int k = kb * 8 + kq + r;
-                    unsigned short val = 0;
-                    if (k < K && j < Wc) {
-                        const int c = k / 9, t = k % 9;
-                        val = src[c * P + (y + t / 3) * (Wc + 2) + j + t % 3];
-                    }
-                    bv[r] = (short)val;
-                }
+            const int jj = j < Wc ? j : Wc - 1;      // lanes past the row edge read a valid pixel, masked below
+            for (int kb = 0; kb < K / 8; ++kb) {
+                const int k0 = kb * 8 + 4 * hi;
+                const int t = k0 / CP, c0 = k0 % CP;
+                const bf16x4 a = *reinterpret_cast<const bf16x4*>(Wl + j * KS + k0);
+                const int pix = (y + t / 3) * (Wc + 2) + jj + t % 3;
+                const bf16x4 bv = *reinterpret_cast<const bf16x4*>(src + pix * NET_PS + c0);
                 acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bv, acc, 0, 0, 0);
             }
             if (j < Wc) {
+                const int pix = (y + 1) * (Wc + 2) + j + 1;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                    if (i < cout) {
-                        const float v = acc[r] + bias[i];
-                        if (last) out[((size_t)i * Hc + y) * Wc + j] = v;
-                        else dst[i * P + (y + 1) * (Wc + 2) + j + 1] = f2bf(fmaxf(v, 0.f));
+                for (int g = 0; g < 4; ++g) {
+                    const int i0 = 8 * g + 4 * hi;
+                    if (last) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (i0 + r < cout) out[((size_t)(i0 + r) * Hc + y) * Wc + j] = acc[4 * g + r] + bias[i0 + r];
+                    } else if (i0 < cout) {
+                        bf16x4 o;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            o[r] = (short)(i0 + r < cout ? f2bf(fmaxf(acc[4 * g + r] + bias[i0 + r], 0.f)) : 0);
+                        *reinterpret_cast<bf16x4*>(dst + pix * NET_PS + i0) = o;
                     }
                 }
             }
@@ -357,24 +392,24 @@ __device__ __forceinline__ void lerp_index(int i, int F, int nc, int& lo, int& h
     hi = min(max(i0 + 1, 0), nc - 1);
 }
 
-__global__ void k_prolong_add(const double* __restrict__ v, const float* __restrict__ y, const float* __restrict__ st,
-                              double* __restrict__ z, int C, int ny, int nx, int F) {
-    const size_t n = (size_t)C * ny * nx;
-    const double s = st[0];
+// One block row per fine row (blockIdx.y = c * ny + y), threads along x.
+__global__ __launch_bounds__(256) void k_prolong_add(const double* __restrict__ v, const float* __restrict__ y,
+                                                     const float* __restrict__ st, double* __restrict__ z, int C, int ny,
+                                                     int nx, int F) {
+    const int xx = blockIdx.x * 256 + threadIdx.x;
+    if (xx >= nx) return;
+    const int c = blockIdx.y / ny, yy = blockIdx.y % ny;
     const int Hc = ny / F, Wc = nx / F;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const int xx = (int)(i % nx);
-        const int yy = (int)((i / nx) % ny);
-        const int c = (int)(i / ((size_t)nx * ny));
-        int y0, y1, x0, x1;
-        float ay, ax;
-        lerp_index(yy, F, Hc, y0, y1, ay);
-        lerp_index(xx, F, Wc, x0, x1, ax);
-        const float* yc = y + (size_t)c * Hc * Wc;
-        const float top = (1.f - ax) * yc[y0 * Wc + x0] + ax * yc[y0 * Wc + x1];
-        const float bot = (1.f - ax) * yc[y1 * Wc + x0] + ax * yc[y1 * Wc + x1];
-        z[i] = v[i] + s * (double)((1.f - ay) * top + ay * bot);
-    }
+    const double s = st[0];
+    int y0, y1, x0, x1;
+    float ay, ax;
+    lerp_index(yy, F, Hc, y0, y1, ay);
+    lerp_index(xx, F, Wc, x0, x1, ax);
+    const float* yc = y + (size_t)c * Hc * Wc;
+    const float top = (1.f - ax) * yc[y0 * Wc + x0] + ax * yc[y0 * Wc + x1];
+    const float bot = (1.f - ax) * yc[y1 * Wc + x0] + ax * yc[y1 * Wc + x1];
+    const size_t i = (size_t)blockIdx.y * nx + xx;
+    z[i] = v[i] + s * (double)((1.f - ay) * top + ay * bot);
 }
 
 // Training pair normalisation (single block): s^2 = |r|^2 / n (fine grid); x = xr/s, t = xt/s,
@@ -440,10 +475,21 @@ struct NetShape {
     }
 };
 
-// The fused network kernel holds two BF16 activation grids with halo in LDS (at most 64 KiB).
-static bool fused_net_fits(int hidden, int Hc, int Wc) {
-    const int MAXC = hidden > 17 ? hidden : 17;
-    return Hc <= 32 && Wc <= 32 && (size_t)2 * MAXC * (Hc + 2) * (Wc + 2) * 2 <= 65536;
+// Length in shorts of the tap-major weight pack of every layer (each layer's block 16-byte aligned).
+static size_t tapmajor_len(const NetShape& sh, std::vector<int>* off = nullptr) {
+    size_t t = 0;
+    for (int l = 0; l < sh.layers; ++l) {
+        if (off) off->push_back((int)t);
+        t += (size_t)32 * net_ks(sh.cin[l]);
+    }
+    return t;
+}
+// LDS of the fused network kernel: two BF16 activation grids with halo plus every layer's weights.
+static size_t fused_net_lds(const NetShape& sh, int Hc, int Wc) {
+    return ((size_t)2 * (Hc + 2) * (Wc + 2) * NET_PS + tapmajor_len(sh)) * 2;
+}
+static bool fused_net_fits(const NetShape& sh, int Hc, int Wc) {
+    return Hc <= 32 && Wc <= 32 && fused_net_lds(sh, Hc, Wc) <= 160 * 1024;
 }
 
 static bool valid_net(int C, int hidden, int layers) {
@@ -529,6 +575,8 @@ void pc_free(rte_ctx* c) {
     nfree(c->pc_nrm);
     nfree(c->pc_part);
     nfree(c->pc_meta);
+    nfree(c->pc_wn);
+    c->pc_wn_len = 0;
     c->pc_attached = false;
 }
 
@@ -544,15 +592,15 @@ int pc_apply(rte_ctx* c, const double* v, double* z) {
                        c->pc_st);
     const float* a = c->pc_coarse;
     const unsigned short* wf = (const unsigned short*)c->pc_w;
-    if (fused_net_fits(c->pc_hidden, Hc, Wc)) {
-        const int MAXC = std::max(c->pc_hidden, 17);
-        const size_t lds = (size_t)2 * MAXC * (Hc + 2) * (Wc + 2) * sizeof(unsigned short);
+    if (c->pc_wn) {
+        const size_t lds = fused_net_lds(sh, Hc, Wc);
+        const int nwn = (int)c->pc_wn_len;
         if (c->pc_hidden == 32)
-            hipLaunchKernelGGL((k_net_fused<32>), dim3(1), dim3(256), lds, st, c->pc_coarse, c->pc_st + 1, wf, c->pc_b,
-                               c->pc_meta, sh.layers, c->C, Hc, Wc, c->pc_act0);
+            hipLaunchKernelGGL((k_net_fused<32>), dim3(1), dim3(NET_THREADS), lds, st, c->pc_coarse, c->pc_st + 1,
+                               c->pc_wn, nwn, c->pc_b, c->pc_meta, sh.layers, c->C, Hc, Wc, c->pc_act0);
         else
-            hipLaunchKernelGGL((k_net_fused<16>), dim3(1), dim3(256), lds, st, c->pc_coarse, c->pc_st + 1, wf, c->pc_b,
-                               c->pc_meta, sh.layers, c->C, Hc, Wc, c->pc_act0);
+            hipLaunchKernelGGL((k_net_fused<16>), dim3(1), dim3(NET_THREADS), lds, st, c->pc_coarse, c->pc_st + 1,
+                               c->pc_wn, nwn, c->pc_b, c->pc_meta, sh.layers, c->C, Hc, Wc, c->pc_act0);
         a = c->pc_act0;
     } else {
         // ping-pong activations: layer l writes act[(l % 2)]
@@ -566,9 +614,8 @@ int pc_apply(rte_ctx* c, const double* v, double* z) {
             a = o;
         }
     }
-    const size_t n = c->nvec;
-    hipLaunchKernelGGL(k_prolong_add, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, st, v, a,
-                       c->pc_st, z, c->C, c->ny, c->nx, F);
+    hipLaunchKernelGGL(k_prolong_add, dim3((c->nx + 255) / 256, c->C * c->ny), dim3(256), 0, st, v, a, c->pc_st, z,
+                       c->C, c->ny, c->nx, F);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? RTE_OK : set_hip_error(e, "pc_apply", __FILE__, __LINE__);
 }
@@ -586,6 +633,7 @@ int rte_pc_attach(rte_ctx* c, const float* weights, int hidden, int layers, int 
     if (c->dim != 2) return set_error(RTE_EUNSUPPORTED, "the learned preconditioner is 2D only");
     if (!valid_net(c->C, hidden, layers)) return set_error(RTE_EINVAL, "bad network shape");
     if (factor < 1 || c->nx % factor || c->ny % factor) return set_error(RTE_EINVAL, "factor must divide n_x and n_y");
+    if (c->nx > 512) return set_error(RTE_EUNSUPPORTED, "grid too wide for the restriction kernel");
     NetShape sh;
     sh.init(c->C, hidden, layers);
     const int Hc = c->ny / factor, Wc = c->nx / factor;
@@ -605,17 +653,25 @@ int rte_pc_attach(rte_ctx* c, const float* weights, int hidden, int layers, int 
     hipError_t e = hipMemcpyAsync(c->pc_b, weights, sh.nparam * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) { pc_free(c); return set_hip_error(e, "pc weights", __FILE__, __LINE__); }
     pack_all(sh, weights, wf, nullptr, c->stream);
+    std::vector<int> toff;
+    const size_t tlen = tapmajor_len(sh, &toff);
+    if (fused_net_fits(sh, Hc, Wc)) {
+        if ((rc = nalloc(&c->pc_wn, tlen))) { pc_free(c); return rc; }
+        c->pc_wn_len = tlen;
+        for (int l = 0; l < layers; ++l)
+            hipLaunchKernelGGL(k_pack_tapmajor, dim3(64), dim3(256), 0, c->stream, wf + sh.pf_off[l], sh.cin[l],
+                               c->pc_wn + toff[l]);
+    }
     std::vector<int> meta(4 * layers);
     for (int l = 0; l < layers; ++l) {
         meta[4 * l] = sh.cin[l];
         meta[4 * l + 1] = sh.cout[l];
-        meta[4 * l + 2] = (int)sh.pf_off[l];
+        meta[4 * l + 2] = toff[l];
         meta[4 * l + 3] = (int)sh.boff[l];
     }
     e = hipMemcpyAsync(c->pc_meta, meta.data(), meta.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) { pc_free(c); return set_hip_error(e, "pc meta", __FILE__, __LINE__); }
-    if (c->nx > 512) { pc_free(c); return set_error(RTE_EUNSUPPORTED, "grid too wide for the restriction kernel"); }
     c->pc_hidden = hidden;
     c->pc_layers = layers;
     c->pc_factor = factor;
