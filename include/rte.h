@@ -71,7 +71,8 @@ typedef struct {
     double relres_est;   /* last Arnoldi estimate of the relative residual */
     double relres_true;  /* ||b - A x|| / ||b|| with the FP64 apply, at exit */
     double t_setup_ms;   /* time of rte_setup for this context */
-    double t_solve_ms;   /* wall time of this solve */
+    double t_solve_ms;   /* wall time of this solve (batched: of the whole batch) */
+    int status;          /* this problem's outcome: RTE_OK, RTE_NOT_CONVERGED or RTE_ENUMERIC */
 } rte_solve_info;
 
 typedef struct {

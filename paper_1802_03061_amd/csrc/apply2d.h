@@ -22,6 +22,43 @@ struct Apply2DArgs {
     int pack;                  // 1: x-frequencies 0 and PX/2 share column 0 of the work buffer
 };
 
+// One isotropic problem (C = 1) of a batched apply.  Pass A reads in (+ j * stride when jin is
+// set, j read from the device), pass C writes out (+ (j + 1) * stride when jout is set) and reads
+// in again (operator A, residual) and bvec (residual).  The x-frequencies 0 and PX/2 are always
+// packed into column 0 of the work buffer.
+template <typename T>
+struct BatchProb {
+    int nx, ny, PX, PY;
+    double s;                  // pass-A factor: mu_s sigma_0 for A and the residual, 1 for K~
+    cx<T>* work;               // [PX/2][ny]
+    const cx<T>* Q;            // quarter spectrum [PX/2+1][PY/2+1], scaled by 1/(PX PY)
+    const cx<T>* twx;
+    const cx<T>* twy;
+    const double* in;
+    double* out;
+    const double* bvec;
+    size_t stride;
+    int jin, jout;
+};
+
+// Batched passes over a list of (problem index, tile) items whose problems all have this PX
+// (passes A, C: tiles of apply2d_batch_rows() rows) or this PY (pass B: groups of
+// apply2d_batch_cols() columns).  act[p] == 0 skips problem p (act may be NULL); dj (may be NULL)
+// points to the Krylov column index j.
+template <typename T>
+int apply2d_batch_rows();
+template <typename T>
+int apply2d_batch_cols(int PY);
+template <typename T>
+int apply2d_batch_pass_a(int PX, const BatchProb<T>* probs, const int2* items, int nitems, const int* act,
+                         const int* dj, hipStream_t st);
+template <typename T>
+int apply2d_batch_pass_b(int PY, const BatchProb<T>* probs, const int2* items, int nitems, const int* act,
+                         hipStream_t st);
+template <typename T>
+int apply2d_batch_pass_c(int PX, const BatchProb<T>* probs, const int2* items, int nitems, const int* act,
+                         const int* dj, int mode, hipStream_t st);
+
 // y = x - K~ D x (APPLY_A), K~ x (APPLY_KT) or b - (x - K~ D x) (APPLY_RESID) on nbatch channel
 // vectors [nbatch][C][ny][nx] of float64, computed with FFTs in precision T.
 template <typename T>

@@ -34,22 +34,14 @@ namespace rte {
 // ---------------------------------------------------------------------------- pass A --------
 // With pack != 0 the x-frequencies 0 and PX/2, whose values are real for real rows, share
 // column 0 of T as (X[0], X[PX/2]); T then has PX/2 columns.
+// One tile of TR rows of one channel: xin is the channel's [ny][nx] input, out its [NKS][ny]
+// transposed x-spectrum; tws holds the staged twiddles.
 template <typename T, int PX, int TR, int NTHR>
-__global__ __launch_bounds__(NTHR) void k_pass_a(const double* __restrict__ x, cx<T>* __restrict__ Tb,
-                                                 const cx<T>* __restrict__ tw, int nx, int ny, int C,
-                                                 ChanScale sc, int pack) {
+__device__ __forceinline__ void pass_a_tile(const double* __restrict__ xin, cx<T>* __restrict__ out, int nx, int ny,
+                                            double s, int pack, int y0, cx<T>* buf, const cx<T>* tws, int tid) {
     constexpr int NP = TR / 2;        // complex FFTs per block (two real rows each)
     constexpr int LD = padded(PX) + 1;   // odd row pitch: the NP transforms start on different banks
     constexpr int H = PX / 2;
-    __shared__ cx<T> buf[NP * LD];
-    __shared__ cx<T> tws[PX];
-    const int tid = threadIdx.x;
-    const int bc = blockIdx.y;
-    const int c = bc % C;
-    const int y0 = blockIdx.x * TR;
-    const double s = sc.s[c];
-    const double* xin = x + (size_t)bc * ny * nx;
-    stage_twiddles<T, PX, NTHR>(tws, tw, tid);
     // rows y0+2p (real part) and y0+2p+1 (imaginary part); only m < nx <= PX/2 is non-zero
     constexpr int NL = NP * H;
     constexpr int IT = (NL + NTHR - 1) / NTHR;
@@ -75,7 +67,6 @@ __global__ __launch_bounds__(NTHR) void k_pass_a(const double* __restrict__ x, c
     __syncthreads();
     block_fft<T, PX, NP, LD, NTHR, false>(buf, tws, tid);
     const int NKS = pack ? H : H + 1;
-    cx<T>* out = Tb + (size_t)bc * NKS * ny;
     for (int idx = tid; idx < NKS * TR; idx += NTHR) {
         const int yl = idx % TR, k = idx / TR;
         const int y = y0 + yl;
@@ -96,22 +87,50 @@ __global__ __launch_bounds__(NTHR) void k_pass_a(const double* __restrict__ x, c
     }
 }
 
-// ---------------------------------------------------------------------------- pass C --------
 template <typename T, int PX, int TR, int NTHR>
-__global__ __launch_bounds__(NTHR) void k_pass_c(const cx<T>* __restrict__ Tb, const double* __restrict__ xin,
-                                                 const double* __restrict__ bin, double* __restrict__ yout,
-                                                 const cx<T>* __restrict__ tw, int nx, int ny, int mode, int pack) {
-    constexpr int NP = TR / 2;
-    constexpr int LD = padded(PX) + 1;   // odd row pitch: the NP transforms start on different banks
-    constexpr int H = PX / 2;
-    __shared__ cx<T> buf[NP * LD];
+__global__ __launch_bounds__(NTHR) void k_pass_a(const double* __restrict__ x, cx<T>* __restrict__ Tb,
+                                                 const cx<T>* __restrict__ tw, int nx, int ny, int C,
+                                                 ChanScale sc, int pack) {
+    constexpr int LD = padded(PX) + 1;
+    __shared__ cx<T> buf[TR / 2 * LD];
     __shared__ cx<T> tws[PX];
     const int tid = threadIdx.x;
     const int bc = blockIdx.y;
-    const int y0 = blockIdx.x * TR;
-    const int NKS = pack ? H : H + 1;
-    const cx<T>* src = Tb + (size_t)bc * NKS * ny;
     stage_twiddles<T, PX, NTHR>(tws, tw, tid);
+    const int NKS = pack ? PX / 2 : PX / 2 + 1;
+    pass_a_tile<T, PX, TR, NTHR>(x + (size_t)bc * ny * nx, Tb + (size_t)bc * NKS * ny, nx, ny, sc.s[bc % C], pack,
+                                 blockIdx.x * TR, buf, tws, tid);
+}
+
+// Batched form (isotropic problems of one padded size): one block per (problem, row tile).
+template <typename T, int PX, int TR, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_pass_a_batch(const BatchProb<T>* __restrict__ probs,
+                                                       const int2* __restrict__ items, const int* __restrict__ act,
+                                                       const int* __restrict__ dj) {
+    constexpr int LD = padded(PX) + 1;
+    __shared__ cx<T> buf[TR / 2 * LD];
+    __shared__ cx<T> tws[PX];
+    const int2 item = items[blockIdx.x];
+    const BatchProb<T>& d = probs[item.x];
+    if (act && !act[item.x]) return;
+    const int tid = threadIdx.x;
+    const size_t j = dj ? (size_t)*dj : 0;
+    stage_twiddles<T, PX, NTHR>(tws, d.twx, tid);
+    pass_a_tile<T, PX, TR, NTHR>(d.in + (d.jin ? j * d.stride : 0), d.work, d.nx, d.ny, d.s, 1, item.y * TR, buf, tws,
+                                 tid);
+}
+
+// ---------------------------------------------------------------------------- pass C --------
+// One tile of TR rows of one channel: src is the channel's [NKS][ny] spectrum; xin, bin, yout its
+// [ny][nx] input, right-hand side and output.
+template <typename T, int PX, int TR, int NTHR>
+__device__ __forceinline__ void pass_c_tile(const cx<T>* __restrict__ src, const double* __restrict__ xin,
+                                            const double* __restrict__ bin, double* __restrict__ yout, int nx, int ny,
+                                            int mode, int pack, int y0, cx<T>* buf, const cx<T>* tws, int tid) {
+    constexpr int NP = TR / 2;
+    constexpr int LD = padded(PX) + 1;   // odd row pitch: the NP transforms start on different banks
+    constexpr int H = PX / 2;
+    const int NKS = pack ? H : H + 1;
     constexpr int NL = (H + 1) * NP;
     constexpr int IT = (NL + NTHR - 1) / NTHR;
     cx<T> xa[IT], xb[IT];
@@ -142,7 +161,6 @@ __global__ __launch_bounds__(NTHR) void k_pass_c(const cx<T>* __restrict__ Tb, c
     }
     __syncthreads();
     block_fft<T, PX, NP, LD, NTHR, true>(buf, tws, tid);
-    const size_t base = (size_t)bc * ny * nx;
     // finalise in chunks of CH iterations so the batched loads stay in a modest register budget
     constexpr int NO = TR * H;
     constexpr int IO = (NO + NTHR - 1) / NTHR;
@@ -155,7 +173,7 @@ __global__ __launch_bounds__(NTHR) void k_pass_c(const cx<T>* __restrict__ Tb, c
             const int yl = idx / H, m = idx % H;
             const int y = y0 + yl;
             const bool ok = idx < NO && m < nx && y < ny;
-            const size_t o = base + (size_t)y * nx + m;
+            const size_t o = (size_t)y * nx + m;
             xv[u] = (ok && mode != APPLY_KT) ? xin[o] : 0.0;
             bv[u] = (ok && mode == APPLY_RESID) ? bin[o] : 0.0;
         }
@@ -171,10 +189,46 @@ __global__ __launch_bounds__(NTHR) void k_pass_c(const cx<T>* __restrict__ Tb, c
                 if (mode == APPLY_A) r = xv[u] - v;
                 else if (mode == APPLY_KT) r = v;
                 else r = bv[u] - xv[u] + v;       // APPLY_RESID: b - A x
-                yout[base + (size_t)y * nx + m] = r;
+                yout[(size_t)y * nx + m] = r;
             }
         }
     }
+}
+
+template <typename T, int PX, int TR, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_pass_c(const cx<T>* __restrict__ Tb, const double* __restrict__ xin,
+                                                 const double* __restrict__ bin, double* __restrict__ yout,
+                                                 const cx<T>* __restrict__ tw, int nx, int ny, int mode, int pack) {
+    constexpr int LD = padded(PX) + 1;
+    __shared__ cx<T> buf[TR / 2 * LD];
+    __shared__ cx<T> tws[PX];
+    const int tid = threadIdx.x;
+    const int bc = blockIdx.y;
+    const int NKS = pack ? PX / 2 : PX / 2 + 1;
+    stage_twiddles<T, PX, NTHR>(tws, tw, tid);
+    const size_t base = (size_t)bc * ny * nx;
+    pass_c_tile<T, PX, TR, NTHR>(Tb + (size_t)bc * NKS * ny, xin ? xin + base : nullptr, bin ? bin + base : nullptr,
+                                 yout + base, nx, ny, mode, pack, blockIdx.x * TR, buf, tws, tid);
+}
+
+// Batched form: one block per (problem, row tile); the output is written to out + (j + 1) stride
+// when jout is set (the next Krylov vector).
+template <typename T, int PX, int TR, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_pass_c_batch(const BatchProb<T>* __restrict__ probs,
+                                                       const int2* __restrict__ items, const int* __restrict__ act,
+                                                       const int* __restrict__ dj, int mode) {
+    constexpr int LD = padded(PX) + 1;
+    __shared__ cx<T> buf[TR / 2 * LD];
+    __shared__ cx<T> tws[PX];
+    const int2 item = items[blockIdx.x];
+    const BatchProb<T>& d = probs[item.x];
+    if (act && !act[item.x]) return;
+    const int tid = threadIdx.x;
+    const size_t j = dj ? (size_t)*dj : 0;
+    stage_twiddles<T, PX, NTHR>(tws, d.twx, tid);
+    pass_c_tile<T, PX, TR, NTHR>(d.work, d.in + (d.jin ? j * d.stride : 0), d.bvec,
+                                 d.out + (d.jout ? (j + 1) * d.stride : 0), d.nx, d.ny, mode, 1, item.y * TR, buf, tws,
+                                 tid);
 }
 
 // ---------------------------------------------------------------------------- dispatch -------
@@ -251,6 +305,45 @@ int apply2d_pass_c(const Apply2DArgs<T>& a, const double* x, const double* b, do
     RTE_P_SWITCH(a.PX, launch_c, a, x, b, y, mode, nbatch * a.C);
     return 0;
 }
+
+template <typename T, int PX>
+static void launch_a_batch(const BatchProb<T>* probs, const int2* items, int nitems, const int* act, const int* dj,
+                           hipStream_t st) {
+    constexpr int TR = tile_rows<T>();
+    hipLaunchKernelGGL((k_pass_a_batch<T, PX, TR, 256>), dim3(nitems), dim3(256), 0, st, probs, items, act, dj);
+}
+template <typename T, int PX>
+static void launch_c_batch(const BatchProb<T>* probs, const int2* items, int nitems, const int* act, const int* dj,
+                           int mode, hipStream_t st) {
+    constexpr int TR = tile_rows<T>();
+    hipLaunchKernelGGL((k_pass_c_batch<T, PX, TR, 256>), dim3(nitems), dim3(256), 0, st, probs, items, act, dj, mode);
+}
+template <typename T>
+int apply2d_batch_rows() { return tile_rows<T>(); }
+template <typename T>
+int apply2d_batch_pass_a(int PX, const BatchProb<T>* probs, const int2* items, int nitems, const int* act,
+                         const int* dj, hipStream_t st) {
+    if (nitems <= 0) return 0;
+    RTE_P_SWITCH(PX, launch_a_batch, probs, items, nitems, act, dj, st);
+    return 0;
+}
+template <typename T>
+int apply2d_batch_pass_c(int PX, const BatchProb<T>* probs, const int2* items, int nitems, const int* act,
+                         const int* dj, int mode, hipStream_t st) {
+    if (nitems <= 0) return 0;
+    RTE_P_SWITCH(PX, launch_c_batch, probs, items, nitems, act, dj, mode, st);
+    return 0;
+}
+template int apply2d_batch_rows<float>();
+template int apply2d_batch_rows<double>();
+template int apply2d_batch_pass_a<float>(int, const BatchProb<float>*, const int2*, int, const int*, const int*,
+                                         hipStream_t);
+template int apply2d_batch_pass_a<double>(int, const BatchProb<double>*, const int2*, int, const int*, const int*,
+                                          hipStream_t);
+template int apply2d_batch_pass_c<float>(int, const BatchProb<float>*, const int2*, int, const int*, const int*, int,
+                                         hipStream_t);
+template int apply2d_batch_pass_c<double>(int, const BatchProb<double>*, const int2*, int, const int*, const int*, int,
+                                          hipStream_t);
 
 template <typename T>
 int apply2d(const Apply2DArgs<T>& a, const double* x, const double* b, double* y, int mode,

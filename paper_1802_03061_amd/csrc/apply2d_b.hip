@@ -143,25 +143,18 @@ __device__ __forceinline__ void couple_packed_pair(PF p, PM pm, const cx<T>* __r
 }
 
 // Fused pass B: NCOL columns x C channels per block, spectra resident in LDS.
-// nkx = columns of the work buffer, nkq = columns of the kernel table (PX/2 + 1).
+// base: the batch entry's [C][nkx][ny] work buffer; nkx = its columns, nkq = columns of the kernel
+// table (PX/2 + 1); kx0 = the block's first column.
 template <typename T, int PY, int L, int NCOL, int NTHR>
-__global__ __launch_bounds__(NTHR) void k_pass_b_lds(cx<T>* __restrict__ Tb, const cx<T>* __restrict__ Q,
-                                                     const cx<T>* __restrict__ tw, int ny, int nkx, int nkq,
-                                                     int pack) {
+__device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T>* __restrict__ Q, int ny, int nkx,
+                                            int nkq, int pack, int kx0, cx<T>* spec, const cx<T>* tws,
+                                            cx<T>* pairtmp, int tid) {
     constexpr int C = 2 * L + 1;
     constexpr int NF = NCOL * C;
     constexpr int LD = padded(PY);
     constexpr int KH = PY / 2 + 1;
     constexpr int HY = PY / 2;
-    __shared__ cx<T> spec[NF * LD];
-    __shared__ cx<T> tws[PY];
-    __shared__ cx<T> pairtmp[2 * C];   // Q of the two self-mirrored frequencies of a packed column
-    const int tid = threadIdx.x;
-    const int kx0 = blockIdx.x * NCOL;
-    const int b = blockIdx.y;
     const size_t cstride = (size_t)nkx * ny;
-    cx<T>* base = Tb + (size_t)b * C * cstride;
-    stage_twiddles<T, PY, NTHR>(tws, tw, tid);
     // spec[(col * C + c) * LD + sw(y)]; rows y < ny <= PY/2 come from memory, the rest is zero
     constexpr int NL = NF * HY;
     constexpr int IT = (NL + NTHR - 1) / NTHR;
@@ -231,6 +224,38 @@ __global__ __launch_bounds__(NTHR) void k_pass_b_lds(cx<T>* __restrict__ Tb, con
         if (y < ny && kx < nkx) base[c * cstride + (size_t)kx * ny + y] = spec[fc * LD + sw(y)];
     }
 }
+
+template <typename T, int PY, int L, int NCOL, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_pass_b_lds(cx<T>* __restrict__ Tb, const cx<T>* __restrict__ Q,
+                                                     const cx<T>* __restrict__ tw, int ny, int nkx, int nkq,
+                                                     int pack) {
+    constexpr int C = 2 * L + 1;
+    __shared__ cx<T> spec[NCOL * C * padded(PY)];
+    __shared__ cx<T> tws[PY];
+    __shared__ cx<T> pairtmp[2 * C];   // Q of the two self-mirrored frequencies of a packed column
+    const int tid = threadIdx.x;
+    stage_twiddles<T, PY, NTHR>(tws, tw, tid);
+    pass_b_cols<T, PY, L, NCOL, NTHR>(Tb + (size_t)blockIdx.y * C * nkx * ny, Q, ny, nkx, nkq, pack,
+                                      blockIdx.x * NCOL, spec, tws, pairtmp, tid);
+}
+
+#if RTE_PASSB_L == 0
+// Batched isotropic form: one block per (problem, group of NCOL columns).
+template <typename T, int PY, int NCOL, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_pass_b_batch(const BatchProb<T>* __restrict__ probs,
+                                                       const int2* __restrict__ items, const int* __restrict__ act) {
+    __shared__ cx<T> spec[NCOL * padded(PY)];
+    __shared__ cx<T> tws[PY];
+    __shared__ cx<T> pairtmp[2];
+    const int2 item = items[blockIdx.x];
+    const BatchProb<T>& d = probs[item.x];
+    if (act && !act[item.x]) return;
+    const int tid = threadIdx.x;
+    stage_twiddles<T, PY, NTHR>(tws, d.twy, tid);
+    pass_b_cols<T, PY, 0, NCOL, NTHR>(d.work, d.Q, d.ny, d.PX / 2, d.PX / 2 + 1, 1, item.y * NCOL, spec, tws, pairtmp,
+                                      tid);
+}
+#endif
 
 // Split form, step 1/3: forward y-FFT of one (channel, column) into a full-length buffer.
 template <typename T, int PY, int NTHR>
@@ -363,6 +388,41 @@ static int launch_pass_b_impl(const Apply2DArgs<T>& a, int nbatch) {
 
 #define RTE_CAT2(a, b) a##b
 #define RTE_CAT(a, b) RTE_CAT2(a, b)
+#if RTE_PASSB_L == 0
+template <typename T, int PY>
+static void launch_b_batch(const BatchProb<T>* probs, const int2* items, int nitems, const int* act, hipStream_t st) {
+    static_assert(fused_fits<T, PY, 0>(), "isotropic pass B is always fused");
+    constexpr int NCOL = ncol_for<T, PY, 0>();
+    constexpr int NT = nthr_for<T, NCOL * PY>();
+    hipLaunchKernelGGL((k_pass_b_batch<T, PY, NCOL, NT>), dim3(nitems), dim3(NT), 0, st, probs, items, act);
+}
+template <typename T>
+int apply2d_batch_cols(int PY) {
+    (void)PY;
+    return ncol_for<T, 1024, 0>();
+}
+template <typename T>
+int apply2d_batch_pass_b(int PY, const BatchProb<T>* probs, const int2* items, int nitems, const int* act,
+                         hipStream_t st) {
+    if (nitems <= 0) return 0;
+    switch (PY) {
+        case 16: launch_b_batch<T, 16>(probs, items, nitems, act, st); break;
+        case 32: launch_b_batch<T, 32>(probs, items, nitems, act, st); break;
+        case 64: launch_b_batch<T, 64>(probs, items, nitems, act, st); break;
+        case 128: launch_b_batch<T, 128>(probs, items, nitems, act, st); break;
+        case 256: launch_b_batch<T, 256>(probs, items, nitems, act, st); break;
+        case 512: launch_b_batch<T, 512>(probs, items, nitems, act, st); break;
+        case 1024: launch_b_batch<T, 1024>(probs, items, nitems, act, st); break;
+        default: return -1;
+    }
+    return 0;
+}
+template int apply2d_batch_cols<float>(int);
+template int apply2d_batch_cols<double>(int);
+template int apply2d_batch_pass_b<float>(int, const BatchProb<float>*, const int2*, int, const int*, hipStream_t);
+template int apply2d_batch_pass_b<double>(int, const BatchProb<double>*, const int2*, int, const int*, hipStream_t);
+#endif
+
 #define RTE_PASSB_FN RTE_CAT(pass_b_L, RTE_PASSB_L)
 
 template <>

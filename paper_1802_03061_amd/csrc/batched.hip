@@ -1,23 +1,669 @@
-// Batched solve of many independent isotropic 2D problems.
-// First version: problems are solved one after another on their own contexts.
+// Batched solve of many independent isotropic 2D problems (rte_solve_batched).
+//
+// Every problem is its own discrete system (I - mu_s K~) u = K~ f (Sec. 2.3, isotropic case of the
+// angularly reduced equation) on its own grid, solved by restarted GMRES with FP64 iterative
+// refinement exactly as the single-problem solver does, but all problems advance together:
+//
+//   * one inner iteration of every unconverged problem is a fixed sequence of launches -- pass A,
+//     pass B and pass C of the FFT apply (one launch per padded grid size, over the row tiles or
+//     column groups of all its problems), then the Krylov kernels over a global list of 4096-element
+//     chunks of all problems' vectors, Givens rotations with one thread per problem, and a tick that
+//     advances the column index j kept in device memory;
+//   * that sequence is captured once into a HIP graph and replayed; a problem whose estimate meets
+//     its target (or that reaches the restart length) clears its active flag on the device and its
+//     blocks exit at once in later replays;
+//   * between cycles the solution update x += V y, the FP64 true residual b - A x (batched FP64
+//     apply) and its norms run for the problems still open, and the host decides which continue.
+//
+// Orthogonalisation is one classical Gram-Schmidt pass (the FP64 refinement bounds the effect of
+// any loss of orthogonality).  Sums over chunks are taken in a fixed order, so results do not
+// depend on scheduling.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "apply2d.h"
 #include "ctx.h"
 
 namespace rte {
+namespace {
+
+constexpr int BT = 256;                  // threads of the chunk kernels
+constexpr int CHUNK = 4096;              // vector elements per chunk
+constexpr int CPT = CHUNK / BT;          // elements per thread
+
+struct Chunk {
+    int p, off, len;
+};
+
+struct KryProb {
+    double* V;          // (m + 1) x nvec Krylov basis
+    double* x;          // solution
+    double* r;          // residual
+    const double* b;    // right-hand side
+    double* H;          // (m + 1) x m Hessenberg (column-major, ld m + 1), R after the rotations
+    double* cs;
+    double* sn;
+    double* g;          // m + 1
+    double* y;          // m
+    cx<double>* u;      // output modes (complex, L = 0)
+    int nvec;
+    int c0, nc;         // chunks of this problem
+};
+
+struct BState {
+    double target;      // absolute inner target of the current cycle
+    double est;         // residual estimate after the last iteration
+    double inv;         // 1 / H[j+1][j], 0 at breakdown
+    double rn;          // residual norm at the cycle start
+    int jd;             // valid columns of the current cycle
+    int iters;          // inner iterations so far
+    int flags;          // bit 1: non-finite value
+    int pad;
+};
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+__device__ __forceinline__ double wave_sum(double s) {
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    return s;
+}
+
+// ---------------------------------------------------------------- inner iteration ------------
+
+// partial[chunk][i] = <V_i, w> over the chunk for i <= j, w = V_{j+1} (the new apply output).
+__global__ __launch_bounds__(BT) void kb_dots(const Chunk* __restrict__ ch, const KryProb* __restrict__ kp,
+                                              const int* __restrict__ act, const int* __restrict__ dj,
+                                              double* __restrict__ partial, int m) {
+    __shared__ double red[(RTE_MAX_RESTART + 1) * 4];
+    const Chunk c = ch[blockIdx.x];
+    if (!act[c.p]) return;
+    const KryProb& k = kp[c.p];
+    const int j = *dj;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double* w = k.V + (size_t)(j + 1) * k.nvec + c.off;
+    double wv[CPT];
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int e = tid + u * BT;
+        wv[u] = e < c.len ? w[e] : 0.0;
+    }
+    for (int i = 0; i <= j; ++i) {
+        const double* v = k.V + (size_t)i * k.nvec + c.off;
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int e = tid + u * BT;
+            if (e < c.len) s += v[e] * wv[u];
+        }
+        s = wave_sum(s);
+        if (lane == 0) red[i * 4 + wave] = s;
+    }
+    __syncthreads();
+    for (int i = tid; i <= j; i += BT)
+        partial[(size_t)blockIdx.x * (m + 1) + i] = (red[i * 4] + red[i * 4 + 1]) + (red[i * 4 + 2] + red[i * 4 + 3]);
+}
+
+// H[0..j][j] = sum over the problem's chunks (in chunk order); one block per problem.
+__global__ __launch_bounds__(64) void kb_hcol(const KryProb* __restrict__ kp, const int* __restrict__ act,
+                                              const int* __restrict__ dj, const double* __restrict__ partial, int m) {
+    const int p = blockIdx.x;
+    if (!act[p]) return;
+    const KryProb& k = kp[p];
+    const int j = *dj;
+    for (int i = threadIdx.x; i <= j; i += 64) {
+        double s = 0.0;
+        for (int c = 0; c < k.nc; ++c) s += partial[(size_t)(k.c0 + c) * (m + 1) + i];
+        k.H[(size_t)j * (m + 1) + i] = s;
+    }
+}
+
+// w -= sum_i H[i][j] V_i over the chunk; part2[chunk] = |w|^2 over the chunk afterwards.
+__global__ __launch_bounds__(BT) void kb_update(const Chunk* __restrict__ ch, const KryProb* __restrict__ kp,
+                                                const int* __restrict__ act, const int* __restrict__ dj,
+                                                double* __restrict__ part2, int m) {
+    __shared__ double h[RTE_MAX_RESTART + 1];
+    __shared__ double red[4];
+    const Chunk c = ch[blockIdx.x];
+    if (!act[c.p]) return;
+    const KryProb& k = kp[c.p];
+    const int j = *dj;
+    const int tid = threadIdx.x;
+    for (int i = tid; i <= j; i += BT) h[i] = k.H[(size_t)j * (m + 1) + i];
+    __syncthreads();
+    double* w = k.V + (size_t)(j + 1) * k.nvec + c.off;
+    double wv[CPT];
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int e = tid + u * BT;
+        wv[u] = e < c.len ? w[e] : 0.0;
+    }
+    for (int i = 0; i <= j; ++i) {
+        const double hi = h[i];
+        const double* v = k.V + (size_t)i * k.nvec + c.off;
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int e = tid + u * BT;
+            if (e < c.len) wv[u] -= hi * v[e];
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+        const int e = tid + u * BT;
+        if (e < c.len) {
+            w[e] = wv[u];
+            s += wv[u] * wv[u];
+        }
+    }
+    s = wave_sum(s);
+    if ((tid & 63) == 0) red[tid >> 6] = s;
+    __syncthreads();
+    if (tid == 0) part2[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// H[j+1][j] = |w|, the previous Givens rotations and a new one on column j, the residual vector
+// g and the estimate |g[j+1]|; decides whether the problem keeps iterating.  One thread per problem.
+__global__ void kb_givens(const KryProb* __restrict__ kp, int* __restrict__ act, const int* __restrict__ dj,
+                          const double* __restrict__ part2, BState* __restrict__ bs, int m, int P, int max_iter) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P || !act[p]) return;
+    const KryProb& k = kp[p];
+    BState& s = bs[p];
+    const int j = *dj;
+    double* Hj = k.H + (size_t)j * (m + 1);
+    double w2 = 0.0;
+    for (int c = 0; c < k.nc; ++c) w2 += part2[k.c0 + c];
+    w2 = w2 > 0.0 ? w2 : 0.0;
+    double h2 = 0.0;
+    for (int i = 0; i <= j; ++i) h2 += Hj[i] * Hj[i];
+    const double hn = sqrt(w2);
+    Hj[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double t = k.cs[i] * Hj[i] + k.sn[i] * Hj[i + 1];
+        Hj[i + 1] = -k.sn[i] * Hj[i] + k.cs[i] * Hj[i + 1];
+        Hj[i] = t;
+    }
+    const double den = hypot(Hj[j], Hj[j + 1]);
+    if (den == 0.0) { k.cs[j] = 1.0; k.sn[j] = 0.0; }
+    else { k.cs[j] = Hj[j] / den; k.sn[j] = Hj[j + 1] / den; }
+    Hj[j] = den;
+    Hj[j + 1] = 0.0;
+    k.g[j + 1] = -k.sn[j] * k.g[j];
+    k.g[j] = k.cs[j] * k.g[j];
+    const double est = fabs(k.g[j + 1]);
+    s.iters += 1;
+    if (!isfinite(den) || !isfinite(est)) {   // drop column j and stop
+        s.flags |= 2;
+        s.jd = j;
+        act[p] = 0;
+        return;
+    }
+    // |w| before orthogonalisation is sqrt(|h|^2 + |w'|^2) in exact arithmetic
+    const bool breakdown = !(hn > 1e-14 * sqrt(h2 + w2));
+    s.jd = j + 1;
+    s.est = est;
+    s.inv = breakdown ? 0.0 : 1.0 / hn;
+    if (breakdown || est <= s.target || j + 1 >= m || s.iters >= max_iter) act[p] = 0;
+}
+
+// V_{j+1} = w / H[j+1][j] for the problems still iterating.
+__global__ __launch_bounds__(BT) void kb_scale_next(const Chunk* __restrict__ ch, const KryProb* __restrict__ kp,
+                                                    const int* __restrict__ act, const int* __restrict__ dj,
+                                                    const BState* __restrict__ bs) {
+    const Chunk c = ch[blockIdx.x];
+    if (!act[c.p]) return;
+    const KryProb& k = kp[c.p];
+    const double a = bs[c.p].inv;
+    double* w = k.V + (size_t)(*dj + 1) * k.nvec + c.off;
+    for (int e = threadIdx.x; e < c.len; e += BT) w[e] *= a;
+}
+
+// j += 1 and the number of problems still iterating.  Single block.
+__global__ __launch_bounds__(BT) void kb_tick(int* __restrict__ dj, const int* __restrict__ act, int P,
+                                              int* __restrict__ count) {
+    __shared__ int red[4];
+    int s = 0;
+    for (int p = threadIdx.x; p < P; p += BT) s += act[p] != 0;
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *count = red[0] + red[1] + red[2] + red[3];
+        *dj += 1;
+    }
+}
+
+// ---------------------------------------------------------------- cycle boundaries -----------
+
+// what: 0 -> x = 0 and r = b; 1 -> V_0 = r / rn (active problems); 2 -> u = (x, 0)
+__global__ __launch_bounds__(BT) void kb_vec(const Chunk* __restrict__ ch, const KryProb* __restrict__ kp,
+                                             const int* __restrict__ mask, const BState* __restrict__ bs, int what) {
+    const Chunk c = ch[blockIdx.x];
+    if (mask && !mask[c.p]) return;
+    const KryProb& k = kp[c.p];
+    for (int e = threadIdx.x; e < c.len; e += BT) {
+        const size_t o = (size_t)c.off + e;
+        if (what == 0) {
+            k.x[o] = 0.0;
+            k.r[o] = k.b[o];
+        } else if (what == 1) {
+            k.V[o] = k.r[o] / bs[c.p].rn;
+        } else {
+            k.u[o] = mk(k.x[o], 0.0);
+        }
+    }
+}
+
+// part2[chunk] = |r|^2 over the chunk (problems in mask).
+__global__ __launch_bounds__(BT) void kb_norm2(const Chunk* __restrict__ ch, const KryProb* __restrict__ kp,
+                                               const int* __restrict__ mask, double* __restrict__ part2) {
+    __shared__ double red[4];
+    const Chunk c = ch[blockIdx.x];
+    if (!mask[c.p]) return;
+    const double* r = kp[c.p].r + c.off;
+    double s = 0.0;
+    for (int e = threadIdx.x; e < c.len; e += BT) s += r[e] * r[e];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part2[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// out[p] = sum of the problem's chunk partials (problems in mask), one thread per problem.
+__global__ void kb_sum_parts(const KryProb* __restrict__ kp, const int* __restrict__ mask,
+                             const double* __restrict__ part2, double* __restrict__ out, int P) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P || !mask[p]) return;
+    double s = 0.0;
+    for (int c = 0; c < kp[p].nc; ++c) s += part2[kp[p].c0 + c];
+    out[p] = s;
+}
+
+// Cycle start for the problems in act: g = (rn, 0, ...), j = 0.
+__global__ void kb_cycle_start(const KryProb* __restrict__ kp, const int* __restrict__ act,
+                               const BState* __restrict__ bs, int* __restrict__ dj, int m, int P) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) *dj = 0;
+    if (p >= P || !act[p]) return;
+    kp[p].g[0] = bs[p].rn;
+    for (int i = 1; i <= m; ++i) kp[p].g[i] = 0.0;
+}
+
+// y = R^{-1} g over the cycle's jd columns (problems in mask without a non-finite value).
+__global__ void kb_backsolve(const KryProb* __restrict__ kp, const int* __restrict__ mask,
+                             const BState* __restrict__ bs, int m, int P) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P || !mask[p] || (bs[p].flags & 2)) return;
+    const KryProb& k = kp[p];
+    const int jd = bs[p].jd;
+    for (int i = jd - 1; i >= 0; --i) {
+        double s = k.g[i];
+        for (int q = i + 1; q < jd; ++q) s -= k.H[(size_t)q * (m + 1) + i] * k.y[q];
+        k.y[i] = s / k.H[(size_t)i * (m + 1) + i];
+    }
+}
+
+// x += sum_{i < jd} y_i V_i over the chunk.
+__global__ __launch_bounds__(BT) void kb_combine(const Chunk* __restrict__ ch, const KryProb* __restrict__ kp,
+                                                 const int* __restrict__ mask, const BState* __restrict__ bs) {
+    __shared__ double y[RTE_MAX_RESTART];
+    const Chunk c = ch[blockIdx.x];
+    if (!mask[c.p] || (bs[c.p].flags & 2)) return;
+    const KryProb& k = kp[c.p];
+    const int jd = bs[c.p].jd;
+    if (jd <= 0) return;
+    for (int i = threadIdx.x; i < jd; i += BT) y[i] = k.y[i];
+    __syncthreads();
+    for (int e = threadIdx.x; e < c.len; e += BT) {
+        const size_t o = (size_t)c.off + e;
+        double s = k.x[o];
+        for (int i = 0; i < jd; ++i) s += y[i] * k.V[(size_t)i * k.nvec + o];
+        k.x[o] = s;
+    }
+}
+
+// ---------------------------------------------------------------- host side -----------------
+
+struct SizeClass {
+    int PX, PY;
+    std::vector<int2> ac, b;   // (problem, row tile) and (problem, column group)
+    int2* dac = nullptr;
+    int2* db = nullptr;
+};
+
+// Device memory carved out of one allocation; freed on scope exit.
+struct Arena {
+    char* base = nullptr;
+    size_t used = 0, cap = 0;
+    ~Arena() { if (base) (void)hipFree(base); }
+    template <typename X>
+    X* take(size_t n) {
+        const size_t off = (used + 255) / 256 * 256;
+        used = off + n * sizeof(X);
+        return reinterpret_cast<X*>(base + off);
+    }
+};
+
+struct Resources {
+    hipStream_t st = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipEvent_t> ev;
+    void* pinned = nullptr;
+    ~Resources() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto e : ev) if (e) (void)hipEventDestroy(e);
+        if (pinned) (void)hipHostFree(pinned);
+        if (st) (void)hipStreamDestroy(st);
+    }
+};
+
+template <typename T>
+BatchProb<T> batch_prob(const rte_ctx* c, const cx<T>* Q, const cx<T>* twx, const cx<T>* twy, cx<T>* work,
+                        double s, const double* in, double* out, const double* bvec, int jin, int jout) {
+    BatchProb<T> d;
+    d.nx = c->nx; d.ny = c->ny; d.PX = c->PX; d.PY = c->PY;
+    d.s = s;
+    d.work = work; d.Q = Q; d.twx = twx; d.twy = twy;
+    d.in = in; d.out = out; d.bvec = bvec;
+    d.stride = c->nvec;
+    d.jin = jin; d.jout = jout;
+    return d;
+}
+
+template <typename T>
+int apply_batch(const std::vector<SizeClass>& cls, const BatchProb<T>* probs, const int* mask, const int* dj, int mode,
+                hipStream_t st) {
+    for (const auto& k : cls)
+        if (apply2d_batch_pass_a<T>(k.PX, probs, k.dac, (int)k.ac.size(), mask, dj, st)) return -1;
+    for (const auto& k : cls)
+        if (apply2d_batch_pass_b<T>(k.PY, probs, k.db, (int)k.b.size(), mask, st)) return -1;
+    for (const auto& k : cls)
+        if (apply2d_batch_pass_c<T>(k.PX, probs, k.dac, (int)k.ac.size(), mask, dj, mode, st)) return -1;
+    return 0;
+}
+
+#define BK_TRY(expr)                                                          \
+    do {                                                                      \
+        hipError_t e_ = (expr);                                               \
+        if (e_ != hipSuccess) return set_hip_error(e_, #expr, __FILE__, __LINE__); \
+    } while (0)
+
+template <typename T>
+int solve_batched_t(int P, rte_ctx* const* ctxs, const double* const* f, const double* tol, int max_iter, void* const* u,
+                    rte_solve_info* infos) {
+    const double t0 = now_ms();
+    const rte_ctx* c0 = ctxs[0];
+    const int m = c0->opts.restart;
+    const int max_cycles = c0->opts.max_cycles;
+    const bool mixed = c0->prec == RTE_PREC_FP32;
+    const double inner_tol = c0->opts.inner_tol;
+    for (int p = 0; p < P; ++p) {
+        int rc = ensure_krylov(ctxs[p], m, false);
+        if (rc) return rc;
+        BK_TRY(hipStreamSynchronize(ctxs[p]->stream));
+    }
+    // ---- chunk list and size classes
+    std::vector<Chunk> chunks;
+    std::vector<KryProb> kp(P);
+    std::map<std::pair<int, int>, int> cls_index;
+    std::vector<SizeClass> cls;
+    const int TRf = apply2d_batch_rows<T>(), TRd = apply2d_batch_rows<double>();
+    const int NCf = apply2d_batch_cols<T>(0), NCd = apply2d_batch_cols<double>(0);
+    for (int p = 0; p < P; ++p) {
+        const rte_ctx* c = ctxs[p];
+        KryProb& k = kp[p];
+        k.nvec = (int)c->nvec;
+        k.c0 = (int)chunks.size();
+        for (int off = 0; off < k.nvec; off += CHUNK) chunks.push_back({p, off, std::min(CHUNK, k.nvec - off)});
+        k.nc = (int)chunks.size() - k.c0;
+        auto key = std::make_pair(c->PX, c->PY);
+        if (!cls_index.count(key)) {
+            cls_index[key] = (int)cls.size();
+            SizeClass s;
+            s.PX = c->PX;
+            s.PY = c->PY;
+            cls.push_back(s);
+        }
+    }
+    // the iteration uses precision T, the right-hand side and residual FP64: separate item lists
+    std::vector<SizeClass> cls_d = cls;
+    for (int p = 0; p < P; ++p) {
+        const rte_ctx* c = ctxs[p];
+        const int ci = cls_index[std::make_pair(c->PX, c->PY)];
+        for (int t = 0; t < (c->ny + TRf - 1) / TRf; ++t) cls[ci].ac.push_back(make_int2(p, t));
+        for (int t = 0; t < (c->PX / 2 + NCf - 1) / NCf; ++t) cls[ci].b.push_back(make_int2(p, t));
+        for (int t = 0; t < (c->ny + TRd - 1) / TRd; ++t) cls_d[ci].ac.push_back(make_int2(p, t));
+        for (int t = 0; t < (c->PX / 2 + NCd - 1) / NCd; ++t) cls_d[ci].b.push_back(make_int2(p, t));
+    }
+    const int NCH = (int)chunks.size();
+    const size_t S = (size_t)(m + 1) * m + 4 * (size_t)m + 2;   // Arnoldi slab per problem
+    // ---- device arena
+    Arena ar;
+    size_t items = 0;
+    for (auto& k : cls) items += k.ac.size() + k.b.size();
+    for (auto& k : cls_d) items += k.ac.size() + k.b.size();
+    ar.cap = 256 * 64 + sizeof(Chunk) * NCH + sizeof(KryProb) * P + sizeof(BState) * P + sizeof(int) * (2 * P + 4) +
+             sizeof(double) * ((size_t)NCH * (m + 2) + P + S * P) + sizeof(int2) * items +
+             sizeof(BatchProb<T>) * P + 2 * sizeof(BatchProb<double>) * P;
+    BK_TRY(hipMalloc((void**)&ar.base, ar.cap));
+    Chunk* d_ch = ar.take<Chunk>(NCH);
+    KryProb* d_kp = ar.take<KryProb>(P);
+    BState* d_bs = ar.take<BState>(P);
+    int* d_act = ar.take<int>(P);
+    int* d_todo = ar.take<int>(P);
+    int* d_j = ar.take<int>(2);
+    int* d_cnt = d_j + 1;
+    double* d_part = ar.take<double>((size_t)NCH * (m + 1));
+    double* d_part2 = ar.take<double>(NCH);
+    double* d_rn2 = ar.take<double>(P);
+    double* d_slab = ar.take<double>(S * P);
+    for (auto& k : cls) {
+        k.dac = ar.take<int2>(k.ac.size());
+        k.db = ar.take<int2>(k.b.size());
+    }
+    for (auto& k : cls_d) {
+        k.dac = ar.take<int2>(k.ac.size());
+        k.db = ar.take<int2>(k.b.size());
+    }
+    BatchProb<T>* d_it = ar.take<BatchProb<T>>(P);
+    BatchProb<double>* d_res = ar.take<BatchProb<double>>(P);
+    BatchProb<double>* d_rhs = ar.take<BatchProb<double>>(P);
+    if (ar.used > ar.cap) return set_error(RTE_EDEVICE, "batched arena overflow");
+    // ---- descriptors
+    std::vector<BatchProb<T>> it(P);
+    std::vector<BatchProb<double>> res(P), rhs(P);
+    for (int p = 0; p < P; ++p) {
+        rte_ctx* c = ctxs[p];
+        KryProb& k = kp[p];
+        double* sl = d_slab + S * p;
+        k.V = c->V; k.x = c->xv; k.r = c->rv; k.b = c->bv;
+        k.H = sl;
+        k.cs = sl + (size_t)(m + 1) * m;
+        k.sn = k.cs + m;
+        k.g = k.sn + m;
+        k.y = k.g + m + 1;
+        k.u = (cx<double>*)u[p];
+        const double s = c->mu_s * c->sigma[0];
+        if constexpr (sizeof(T) == 4)
+            it[p] = batch_prob<float>(c, c->Qf, c->twf[0], c->twf[1], c->wf, s, c->V, c->V, nullptr, 1, 1);
+        else
+            it[p] = batch_prob<double>(c, c->Qd, c->twd[0], c->twd[1], c->wd, s, c->V, c->V, nullptr, 1, 1);
+        res[p] = batch_prob<double>(c, c->Qd, c->twd[0], c->twd[1], c->wd, s, c->xv, c->rv, c->bv, 0, 0);
+        rhs[p] = batch_prob<double>(c, c->Qd, c->twd[0], c->twd[1], c->wd, 1.0, f[p], c->bv, nullptr, 0, 0);
+    }
+    Resources rs;
+    BK_TRY(hipStreamCreateWithFlags(&rs.st, hipStreamNonBlocking));
+    hipStream_t st = rs.st;
+    BK_TRY(hipMemcpyAsync(d_ch, chunks.data(), sizeof(Chunk) * NCH, hipMemcpyHostToDevice, st));
+    BK_TRY(hipMemcpyAsync(d_kp, kp.data(), sizeof(KryProb) * P, hipMemcpyHostToDevice, st));
+    BK_TRY(hipMemcpyAsync(d_it, it.data(), sizeof(BatchProb<T>) * P, hipMemcpyHostToDevice, st));
+    BK_TRY(hipMemcpyAsync(d_res, res.data(), sizeof(BatchProb<double>) * P, hipMemcpyHostToDevice, st));
+    BK_TRY(hipMemcpyAsync(d_rhs, rhs.data(), sizeof(BatchProb<double>) * P, hipMemcpyHostToDevice, st));
+    for (size_t i = 0; i < cls.size(); ++i) {
+        BK_TRY(hipMemcpyAsync(cls[i].dac, cls[i].ac.data(), sizeof(int2) * cls[i].ac.size(), hipMemcpyHostToDevice, st));
+        BK_TRY(hipMemcpyAsync(cls[i].db, cls[i].b.data(), sizeof(int2) * cls[i].b.size(), hipMemcpyHostToDevice, st));
+        BK_TRY(hipMemcpyAsync(cls_d[i].dac, cls_d[i].ac.data(), sizeof(int2) * cls_d[i].ac.size(), hipMemcpyHostToDevice, st));
+        BK_TRY(hipMemcpyAsync(cls_d[i].db, cls_d[i].b.data(), sizeof(int2) * cls_d[i].b.size(), hipMemcpyHostToDevice, st));
+    }
+    // pinned host staging: states, masks, norms, per-iteration active counts
+    const size_t pin_bytes = sizeof(BState) * P + sizeof(int) * 2 * P + sizeof(double) * P + sizeof(int) * m + 64;
+    BK_TRY(hipHostMalloc(&rs.pinned, pin_bytes, hipHostMallocDefault));
+    BState* h_bs = (BState*)rs.pinned;
+    int* h_act = (int*)(h_bs + P);
+    int* h_todo = h_act + P;
+    double* h_rn2 = (double*)(((uintptr_t)(h_todo + P) + 7) / 8 * 8);
+    int* h_cnt = (int*)(h_rn2 + P);
+    rs.ev.assign(m, nullptr);
+    for (auto& e : rs.ev) BK_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    const unsigned gP = (unsigned)((P + 63) / 64);
+
+    // ---- right-hand sides b = K~ f (FP64), x = 0, r = b, |b|
+    if (apply_batch<double>(cls_d, d_rhs, nullptr, nullptr, APPLY_KT, st)) return set_error(RTE_EUNSUPPORTED, "batched apply: unsupported size");
+    hipLaunchKernelGGL(kb_vec, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, nullptr, d_bs, 0);
+    for (int p = 0; p < P; ++p) h_todo[p] = 1;
+    BK_TRY(hipMemcpyAsync(d_todo, h_todo, sizeof(int) * P, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(kb_norm2, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, d_todo, d_part2);
+    hipLaunchKernelGGL(kb_sum_parts, dim3(gP), dim3(64), 0, st, d_kp, d_todo, d_part2, d_rn2, P);
+    BK_TRY(hipMemcpyAsync(h_rn2, d_rn2, sizeof(double) * P, hipMemcpyDeviceToHost, st));
+    BK_TRY(hipStreamSynchronize(st));
+    std::vector<double> bn(P), rn(P), est(P);
+    std::vector<int> status(P, RTE_NOT_CONVERGED), cycles(P, 0);
+    memset(h_bs, 0, sizeof(BState) * P);
+    for (int p = 0; p < P; ++p) {
+        bn[p] = std::sqrt(h_rn2[p]);
+        rn[p] = est[p] = bn[p];
+        if (!std::isfinite(h_rn2[p])) { status[p] = RTE_ENUMERIC; h_todo[p] = 0; }
+        else if (h_rn2[p] == 0.0) { status[p] = RTE_OK; h_todo[p] = 0; }
+    }
+
+    // ---- capture one inner iteration
+    BK_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+    int crc = apply_batch<T>(cls, d_it, d_act, d_j, APPLY_A, st);
+    hipLaunchKernelGGL(kb_dots, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, d_act, d_j, d_part, m);
+    hipLaunchKernelGGL(kb_hcol, dim3(P), dim3(64), 0, st, d_kp, d_act, d_j, d_part, m);
+    hipLaunchKernelGGL(kb_update, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, d_act, d_j, d_part2, m);
+    hipLaunchKernelGGL(kb_givens, dim3(gP), dim3(64), 0, st, d_kp, d_act, d_j, d_part2, d_bs, m, P, max_iter);
+    hipLaunchKernelGGL(kb_scale_next, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, d_act, d_j, d_bs);
+    hipLaunchKernelGGL(kb_tick, dim3(1), dim3(BT), 0, st, d_j, d_act, P, d_cnt);
+    hipError_t ce = hipStreamEndCapture(st, &rs.graph);
+    if (crc) return set_error(RTE_EUNSUPPORTED, "batched apply: unsupported size");
+    BK_TRY(ce);
+    BK_TRY(hipGraphInstantiate(&rs.exec, rs.graph, nullptr, nullptr, 0));
+
+    // ---- cycles
+    int ncyc = 0;
+    while (true) {
+        bool any = false;
+        for (int p = 0; p < P; ++p) any = any || h_todo[p];
+        if (!any || ncyc >= max_cycles) break;
+        ++ncyc;
+        for (int p = 0; p < P; ++p) {
+            h_act[p] = h_todo[p];
+            if (!h_todo[p]) continue;
+            ++cycles[p];
+            double target = 0.5 * tol[p] * bn[p];
+            if (mixed) target = std::max(target, inner_tol * rn[p]);
+            h_bs[p].target = target;
+            h_bs[p].rn = rn[p];
+            h_bs[p].jd = 0;
+            h_bs[p].inv = 0.0;
+            h_bs[p].flags = 0;
+        }
+        BK_TRY(hipMemcpyAsync(d_bs, h_bs, sizeof(BState) * P, hipMemcpyHostToDevice, st));
+        BK_TRY(hipMemcpyAsync(d_act, h_act, sizeof(int) * P, hipMemcpyHostToDevice, st));
+        BK_TRY(hipMemcpyAsync(d_todo, h_todo, sizeof(int) * P, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(kb_cycle_start, dim3(gP), dim3(64), 0, st, d_kp, d_act, d_bs, d_j, m, P);
+        hipLaunchKernelGGL(kb_vec, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, d_act, d_bs, 1);
+        // inner iterations: replay the graph; the active count of replay i-1 is read while i runs
+        for (int i = 0; i < m; ++i) {
+            BK_TRY(hipGraphLaunch(rs.exec, st));
+            BK_TRY(hipMemcpyAsync(h_cnt + i, d_cnt, sizeof(int), hipMemcpyDeviceToHost, st));
+            BK_TRY(hipEventRecord(rs.ev[i], st));
+            if (i >= 1) {
+                BK_TRY(hipEventSynchronize(rs.ev[i - 1]));
+                if (h_cnt[i - 1] == 0) break;
+            }
+        }
+        // x += V y, r = b - A x (FP64), |r|
+        hipLaunchKernelGGL(kb_backsolve, dim3(gP), dim3(64), 0, st, d_kp, d_todo, d_bs, m, P);
+        hipLaunchKernelGGL(kb_combine, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, d_todo, d_bs);
+        if (apply_batch<double>(cls_d, d_res, d_todo, nullptr, APPLY_RESID, st))
+            return set_error(RTE_EUNSUPPORTED, "batched apply: unsupported size");
+        hipLaunchKernelGGL(kb_norm2, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, d_todo, d_part2);
+        hipLaunchKernelGGL(kb_sum_parts, dim3(gP), dim3(64), 0, st, d_kp, d_todo, d_part2, d_rn2, P);
+        BK_TRY(hipMemcpyAsync(h_rn2, d_rn2, sizeof(double) * P, hipMemcpyDeviceToHost, st));
+        BK_TRY(hipMemcpyAsync(h_bs, d_bs, sizeof(BState) * P, hipMemcpyDeviceToHost, st));
+        BK_TRY(hipStreamSynchronize(st));
+        for (int p = 0; p < P; ++p) {
+            if (!h_todo[p]) continue;
+            if (h_bs[p].flags & 2 || !std::isfinite(h_rn2[p])) {
+                status[p] = RTE_ENUMERIC;
+                h_todo[p] = 0;
+                continue;
+            }
+            est[p] = h_bs[p].est;
+            rn[p] = std::sqrt(h_rn2[p]);
+            if (rn[p] <= tol[p] * bn[p]) { status[p] = RTE_OK; h_todo[p] = 0; }
+            else if (h_bs[p].iters >= max_iter) h_todo[p] = 0;
+        }
+    }
+    // ---- outputs
+    for (int p = 0; p < P; ++p) h_act[p] = 1;
+    BK_TRY(hipMemcpyAsync(d_act, h_act, sizeof(int) * P, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(kb_vec, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, d_act, d_bs, 2);
+    BK_TRY(hipGetLastError());
+    BK_TRY(hipStreamSynchronize(st));
+    const double t_solve = now_ms() - t0;
+    int worst = RTE_OK;
+    for (int p = 0; p < P; ++p) {
+        if (status[p] == RTE_ENUMERIC) worst = RTE_ENUMERIC;
+        else if (status[p] == RTE_NOT_CONVERGED && worst == RTE_OK) worst = RTE_NOT_CONVERGED;
+        if (!infos) continue;
+        rte_solve_info& in = infos[p];
+        memset(&in, 0, sizeof(in));
+        in.iterations = h_bs[p].iters;
+        in.cycles = cycles[p];
+        in.applies = h_bs[p].iters + cycles[p];
+        in.relres_est = bn[p] > 0 ? est[p] / bn[p] : 0.0;
+        in.relres_true = bn[p] > 0 ? rn[p] / bn[p] : 0.0;
+        in.t_setup_ms = ctxs[p]->t_setup_ms;
+        in.t_solve_ms = t_solve;
+        in.status = status[p];
+    }
+    if (worst == RTE_ENUMERIC) return set_error(RTE_ENUMERIC, "non-finite value in a batched problem");
+    if (worst == RTE_NOT_CONVERGED) set_error(RTE_NOT_CONVERGED, "some batched problems did not converge");
+    return worst;
+}
+
+}  // namespace
 
 int solve_batched_impl(int count, rte_ctx* const* ctxs, const double* const* f, const double* tol, int max_iter,
                        void* const* u, rte_solve_info* infos) {
     if (count < 0 || (count > 0 && (!ctxs || !f || !tol || !u))) return set_error(RTE_EINVAL, "bad batched arguments");
-    int worst = RTE_OK;
+    if (max_iter < 1) return set_error(RTE_EINVAL, "max_iter must be >= 1");
+    if (count == 0) return RTE_OK;
     for (int i = 0; i < count; ++i) {
         if (!ctxs[i] || ctxs[i]->dim != 2 || ctxs[i]->L != 0)
             return set_error(RTE_EINVAL, "problem %d: batched solves take 2D isotropic contexts", i);
+        if (!f[i] || !u[i]) return set_error(RTE_EINVAL, "problem %d: NULL source or output", i);
+        if (!(tol[i] > 0.0) || !(tol[i] < 1.0)) return set_error(RTE_EINVAL, "problem %d: tol must be in (0, 1)", i);
+        if (ctxs[i]->prec != ctxs[0]->prec || ctxs[i]->device != ctxs[0]->device)
+            return set_error(RTE_EINVAL, "problem %d: batched contexts must share precision and device", i);
+        for (int q = 0; q < i; ++q)
+            if (ctxs[q] == ctxs[i]) return set_error(RTE_EINVAL, "problem %d: a context appears twice", i);
     }
-    for (int i = 0; i < count; ++i) {
-        int rc = rte_solve(ctxs[i], f[i], tol[i], max_iter, u[i], infos ? &infos[i] : nullptr);
-        if (rc < 0) return rc;
-        if (rc > worst) worst = rc;
-    }
-    return worst;
+    if (ctxs[0]->opts.restart > RTE_MAX_RESTART) return set_error(RTE_EINVAL, "restart too long");
+    if (ctxs[0]->prec == RTE_PREC_FP32) return solve_batched_t<float>(count, ctxs, f, tol, max_iter, u, infos);
+    return solve_batched_t<double>(count, ctxs, f, tol, max_iter, u, infos);
 }
 
 }  // namespace rte

@@ -265,6 +265,7 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
     if ((rc = dot_host(c, b, b, &bn2))) return rc;
     vec_fill(x, 0.0, n, st);
     if (!std::isfinite(bn2)) {
+        inf.status = RTE_ENUMERIC;
         if (info) *info = inf;
         return set_error(RTE_ENUMERIC, "non-finite right-hand side");
     }
@@ -368,6 +369,7 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
             }
             inf.iterations = it;
             inf.cycles = cycles;
+            inf.status = RTE_ENUMERIC;
             if (info) *info = inf;
             return set_error(RTE_ENUMERIC, "non-finite value in the Arnoldi process");
         }
@@ -398,6 +400,7 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
         if (!std::isfinite(rn2)) {
             inf.iterations = it;
             inf.cycles = cycles;
+            inf.status = RTE_ENUMERIC;
             if (info) *info = inf;
             return set_error(RTE_ENUMERIC, "non-finite true residual");
         }
@@ -414,6 +417,7 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
     inf.relres_est = est / bn;
     inf.relres_true = rn / bn;
     inf.t_solve_ms = now_ms() - t_start;
+    inf.status = status;
     if (info) *info = inf;
     if (status == RTE_NOT_CONVERGED)
         set_error(RTE_NOT_CONVERGED, "not converged: relative residual %.3e after %d iterations", rn / bn, it);

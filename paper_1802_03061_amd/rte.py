@@ -36,7 +36,7 @@ class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int), ("applies", C.c_int), ("cycles", C.c_int),
                 ("pc_used", C.c_int), ("pc_fallback", C.c_int),
                 ("relres_est", C.c_double), ("relres_true", C.c_double),
-                ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double)]
+                ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double), ("status", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -281,8 +281,10 @@ class Context:
 
 
 def solve_batched(ctxs, fs, tols, max_iter=1000, allow_not_converged=False):
-    """Solve several isotropic 2D problems together (rte_solve_batched)."""
+    """Solve several isotropic 2D problems together (rte_solve_batched).  The library runs the batch
+    on a stream of its own, so pending work on torch's stream is completed first."""
     lib = load()
+    torch.cuda.synchronize()
     n = len(ctxs)
     hs = (C.c_void_p * n)(*[c._h for c in ctxs])
     fp = (C.c_void_p * n)(*[_ptr(f, torch.float64, c.cells) for f, c in zip(fs, ctxs)])
