@@ -1,18 +1,28 @@
-"""Benchmark: solve time to relative residual 1e-8 on the 512^2, L = 8 Henyey-Greenstein problem.
+"""Benchmark of the RTE solver on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mu-s 10] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload hg512|batched|iso3d|diff256]
 
-One step = one full solve (right-hand side b = K~ g by an FP64 apply, then flexible GMRES with the
-learned coarse-grid preconditioner, FP32 FFT applies, FP64 Krylov and FP64 true-residual
-refinement) of a seeded Gaussian-mixture source (2D, 512^2 cells, HG g = 0.5 truncated to
-|k| <= 8: 17 coupled modes, mu_a = 0.1).  The same solves without the preconditioner (plain GMRES)
-are timed beside it.  The network is trained before timing by the library's own kernels on pairs
-from training sources (seeds 10000+), disjoint from the timed sources (seeds 0..K-1).  Inputs are
-resident in HBM before the timed region; each timed region is K solves bracketed by device
-synchronisation.  Prints one JSON line.
+Default workload (hg512): solve time to relative residual 1e-8 on the 512^2, L = 8
+Henyey-Greenstein problem.  One step = one full solve (right-hand side b = K~ g by an FP64 apply,
+then flexible GMRES with the learned coarse-grid preconditioner, FP32 FFT applies, FP64 Krylov and
+FP64 true-residual refinement) of a seeded Gaussian-mixture source (2D, 512^2 cells, HG g = 0.5
+truncated to |k| <= 8: 17 coupled modes, mu_a = 0.1, mu_s = 10).  The same solves without the
+preconditioner (plain GMRES) are timed beside it.  The network is trained before timing by the
+library's own kernels on pairs from training sources (seeds 10000+), disjoint from the timed
+sources (seeds 0..K-1).  Inputs are resident in HBM before the timed region; each timed region is
+K solves bracketed by device synchronisation.  Prints one JSON line.
 
-Also reported: operator applies/s, per-pass apply times from HIP events on the context stream
-with the HBM roofline of the dominant kernel, and the CPU oracle timed on a bounded sample.
+Other workloads (same JSON shape):
+  batched  one step = one rte_solve_batched call over 128 isotropic problems (n drawn from
+           {64, 128, 256, 512}, mu_s ~ U[0.5, 20], mu_a ~ U[0.01, 0.5]), FP32 apply, tol 1e-8
+  iso3d    one step = one solve of the 128^3 isotropic problem (mu_a = 0.05, mu_s = 10), FP32
+           FFT on the 256^3 padded grid, FP64 GMRES, tol 1e-8
+  diff256  like hg512 on the diffusion-regime problem (256^2, HG g = 0.3, L = 4, mu_s = 50,
+           mu_a = 0.01)
+
+Also reported: operator applies/s, per-pass apply times from HIP events on the context stream with
+the HBM roofline of the dominant kernel, the measured copy bandwidth, and the CPU oracle timed on
+a bounded sample.
 """
 from __future__ import annotations
 
@@ -31,31 +41,82 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "solve time to rel-res 1e-8 (512^2, L=8 HG), learned-PC vs plain; applies/s"
 
 
+def padded(n: int) -> int:
+    P = 16
+    while P < 2 * n - 1:
+        P *= 2
+    return P
+
+
 def apply_pass_bytes(n: int, L: int) -> dict:
-    """Algorithmic HBM bytes of one FP32 apply on FP64 channel vectors (C = 2L+1 channels, n^2
-    cells, x-spectrum of n+1 columns): pass A reads x (8 B/value) and writes the complex64
-    x-spectrum; pass B reads and writes that spectrum and reads the quarter kernel spectra;
-    pass C reads the spectrum and x and writes y."""
+    """Algorithmic HBM bytes of one FP32 2D apply on FP64 channel vectors (C = 2L+1 channels, n^2
+    cells, padded size P, x-spectrum of P/2 packed columns): pass A reads x (8 B/value) and writes
+    the complex64 x-spectrum; pass B reads and writes that spectrum and reads the quarter kernel
+    spectra [2L+1][P/2+1][P/2+1]; pass C reads the spectrum and x and writes y."""
     C = 2 * L + 1
     N = n * n
-    spec = C * (n + 1) * n * 8
-    kern = (2 * L + 1) * (n + 1) * (n + 1) * 8
+    H = padded(n) // 2
+    spec = 8 * C * H * n
+    kern = 8 * (2 * L + 1) * (H + 1) * (H + 1)
     return {"A": 8 * C * N + spec, "B": 2 * spec + kern, "C": spec + 16 * C * N}
 
 
-def cpu_baseline(w, gpu_applies_per_solve: float) -> dict:
+def apply3d_pass_bytes(n: int) -> dict:
+    """Algorithmic HBM bytes of one FP32 3D isotropic apply (n^3 cells, padded P): x-FFT pass
+    (read x, write T1 [n][P/2+1][n] complex64), y-FFT pass (T1 -> T2 [P/2+1][P][n]), z pass (read
+    and write T2, read the real octant spectrum), inverse y pass (T2 -> T1), inverse x pass (read
+    T1 and x, write y)."""
+    N = n ** 3
+    P = padded(n)
+    H = P // 2 + 1
+    t1 = 8 * n * H * n
+    t2 = 8 * H * P * n
+    q = 4 * H * (P // 2 + 1) * (P // 2 + 1)
+    return {"A": 8 * N + t1, "B": t1 + t2, "C": 2 * t2 + q, "D": t2 + t1, "E": t1 + 16 * N}
+
+
+def copy_peak_gbs(torch, mib: int = 1024, reps: int = 10) -> float:
+    """Measured device-to-device copy bandwidth (read + write bytes / time) of a plain copy of
+    `mib` MiB, timed with events on torch's stream."""
+    a = torch.empty(mib * 2 ** 20 // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    e.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del a, b
+    return 2 * mib * 2 ** 20 / (ms * 1e-3) / 1e9
+
+
+def roofline(ctx, rte, pb: dict, reps: int, names) -> dict:
+    """Per-pass FP32 apply times (HIP events on the context stream) and the dominant pass against
+    8 TB/s."""
+    ms_apply, ms_pass = ctx.time_apply(rte.OP_A, rte.PREC_FP32, reps=reps)
+    ms_pass = ms_pass[:len(names)]
+    dom = int(np.argmax(ms_pass))
+    achieved = pb[names[dom]] / (ms_pass[dom] * 1e-3) / 1e9
+    return {"ms_apply": ms_apply, "passes": dict(zip(names, ms_pass)),
+            "roofline": {"bound": "hbm", "kernel": f"apply pass {names[dom]}", "achieved": achieved,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+            "apply_hbm_fraction": sum(pb.values()) / (ms_apply * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def cpu_baseline_2d(w, gpu_applies_per_solve: float) -> dict:
     """The oracle's FP64 FFT apply (scipy.fft, as written) timed on the host on a bounded sample:
-    two applies of the same 512^2, L = 8 operator after its spectra are built; solves/s is scaled
-    by the applies one GPU solve used."""
+    two applies of the workload's operator after its spectra are built; solves/s is scaled by the
+    applies one GPU solve used."""
     from oracle import operator2d as op2
+    from paper_1802_03061_amd import inputs
     n, L = w["n"], w["L"]
     h, mu_t = 1.0 / n, w["mu_a"] + w["mu_s"]
     t0 = time.perf_counter()
     spectra = op2.kernel_spectra(n, n, L, h, mu_t)
     t_pre = time.perf_counter() - t0
-    rng = np.random.default_rng(0)
-    from paper_1802_03061_amd import inputs
-    u = inputs.random_conj_symmetric_modes(rng, L, n)
+    u = inputs.random_conj_symmetric_modes(np.random.default_rng(0), L, n)
     reps = 2
     t0 = time.perf_counter()
     for _ in range(reps):
@@ -66,12 +127,138 @@ def cpu_baseline(w, gpu_applies_per_solve: float) -> dict:
         "unit": "solves/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"{reps} FP64 FFT applies of the 512^2 L=8 operator (oracle.operator2d.apply_fft, "
-                   f"numpy/scipy single thread) at {t_apply:.2f} s each, scaled by the "
+        "sample": (f"{reps} FP64 FFT applies of the {n}^2 L={L} operator (oracle.operator2d.apply_fft, "
+                   f"numpy/scipy single thread) at {t_apply:.3f} s each, scaled by the "
                    f"{gpu_applies_per_solve:.1f} applies per GPU solve; spectra precompute "
                    f"{t_pre:.1f} s excluded"),
         "applies_per_s": 1.0 / t_apply,
     }
+
+
+def timed_solves(ctx, fs, steps, warmup, torch):
+    nsrc = len(fs)
+    for i in range(warmup):
+        ctx.solve(fs[i % nsrc], tol=1e-8)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        _, info = ctx.solve(fs[i % nsrc], tol=1e-8)
+        infos.append(info)
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / steps
+    return {"ms_per_solve": ms, "solves_per_s": 1000.0 / ms,
+            "iterations": float(np.mean([i["iterations"] for i in infos])),
+            "applies": float(np.mean([i["applies"] for i in infos])),
+            "cycles": float(np.mean([i["cycles"] for i in infos])),
+            "pc_fallback": int(max(i["pc_fallback"] for i in infos)),
+            "max_relres_true": float(max(i["relres_true"] for i in infos))}
+
+
+def bench_pc_workload(args, torch, rte, name, mu_s):
+    """hg512 / diff256: plain GMRES, then FGMRES with a freshly trained learned preconditioner."""
+    from paper_1802_03061_amd import inputs, pc_train
+    base = inputs.workload(name, seed=0, mu_s=mu_s)
+    n, L = base["n"], base["L"]
+    ctx = rte.Context(n, mu_a=base["mu_a"], mu_s=base["mu_s"], sigma_hat=base["sigma_hat"], L=L,
+                      prec=rte.PREC_FP32)
+    fs = [torch.from_numpy(inputs.workload(name, seed=s, mu_s=mu_s)["f"]).cuda() for s in range(max(args.steps, 1))]
+    torch.cuda.synchronize()
+    plain = timed_solves(ctx, fs, args.steps, args.warmup, torch)
+    plain["label"] = "plain GMRES"
+    t_setup_ms = ctx.solve(fs[0], tol=1e-8)[1]["t_setup_ms"]
+    pc = None
+    if not args.no_pc:
+        F = pc_train.coarse_factor(n)
+        net, meta = pc_train.train_for(ctx, range(10000, 10012), name, F, steps=args.train_steps, mu_s=mu_s)
+        ctx.attach_pc(net.params(), hidden=meta["hidden"], layers=meta["layers"], factor=F)
+        pc = timed_solves(ctx, fs, args.steps, args.warmup, torch)
+        pc["label"] = "learned-PC FGMRES"
+        pc["training"] = {k: meta[k] for k in ("pairs", "factor", "hidden", "layers", "steps", "t_data_s",
+                                                "t_train_s", "noise_ratio", "multiscale_ratio", "use_bias")}
+        pc["training"]["final_loss"] = meta["loss_history"][-1][1] if meta["loss_history"] else None
+        ctx.attach_pc(None)
+        net.close()
+    head = pc if pc is not None else plain
+    rf = roofline(ctx, rte, apply_pass_bytes(n, L), args.apply_reps, ["A", "B", "C"])
+    ms64, pass64 = ctx.time_apply(rte.OP_A, rte.PREC_FP64, reps=max(5, args.apply_reps // 5))
+    out = {
+        "value": head["solves_per_s"], "unit": "solves/s", "ms_per_step": head["ms_per_solve"],
+        "dtype": "f32 apply + f64 krylov",
+        "config": {"workload": (f"2D HG g={'0.5' if name == 'hg512' else '0.3'}, L={L} ({2 * L + 1} modes), "
+                                f"{n}^2 cells, mu_a={base['mu_a']:g}, mu_s={mu_s:g}, seeded Gaussian-mixture "
+                                f"sources, tol 1e-8 (true FP64 residual)"),
+                   "n": n, "L": L, "mu_s": mu_s, "tol": 1e-8,
+                   "preconditioner": "learned coarse-grid CNN (FGMRES)" if pc else "none"},
+        "solve": {"iterations": head["iterations"], "max_relres_true": head["max_relres_true"],
+                  "t_setup_ms": t_setup_ms},
+        "plain": plain, "learned_pc": pc,
+        "pc_speedup_vs_plain": (plain["ms_per_solve"] / pc["ms_per_solve"]) if pc else None,
+        "applies_per_s": 1000.0 / rf["ms_apply"],
+        "apply_ms": {"fp32_total": rf["ms_apply"], "fp32_passes": rf["passes"], "fp64_total": ms64,
+                     "fp64_passes": dict(zip("ABC", pass64[:3]))},
+        "apply_hbm_fraction": rf["apply_hbm_fraction"], "apply_bytes": apply_pass_bytes(n, L),
+        "roofline": rf["roofline"],
+    }
+    return out, ctx, base, plain["applies"]
+
+
+def bench_batched(args, torch, rte):
+    from paper_1802_03061_amd import inputs
+    probs = inputs.batched_problems(count=128, seed=3)
+    ctxs = [rte.Context(p["n"], mu_a=p["mu_a"], mu_s=p["mu_s"], L=0, prec=rte.PREC_FP32) for p in probs]
+    fs = [torch.from_numpy(inputs.gaussian_mixture_source(p["n"], p["params"])).cuda() for p in probs]
+    torch.cuda.synchronize()
+    tols = [1e-8] * len(ctxs)
+    for _ in range(args.warmup):
+        rte.solve_batched(ctxs, fs, tols)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, infos, _ = rte.solve_batched(ctxs, fs, tols)
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+    its = [i["iterations"] for i in infos]
+    cells = sum(p["n"] ** 2 for p in probs)
+    big = next(i for i, p in enumerate(probs) if p["n"] == 512)
+    rf = roofline(ctxs[big], rte, apply_pass_bytes(512, 0), args.apply_reps, ["A", "B", "C"])
+    out = {
+        "value": len(ctxs) * 1000.0 / ms, "unit": "solves/s", "ms_per_step": ms, "dtype": "f32 apply + f64 krylov",
+        "config": {"workload": ("128 batched 2D isotropic solves, n from {64,128,256,512}, mu_s~U[0.5,20], "
+                                "mu_a~U[0.01,0.5], Gaussian-mixture sources, tol 1e-8"),
+                   "problems": len(ctxs), "cells": cells, "tol": 1e-8},
+        "solve": {"iterations_min": min(its), "iterations_max": max(its), "iterations_mean": float(np.mean(its)),
+                  "max_relres_true": max(i["relres_true"] for i in infos),
+                  "max_cycles": max(i["cycles"] for i in infos)},
+        "applies_per_s": None,
+        "apply_ms": {"iso512_fp32_total": rf["ms_apply"], "iso512_fp32_passes": rf["passes"]},
+        "roofline": rf["roofline"],
+    }
+    for c in ctxs:
+        c.close()
+    return out
+
+
+def bench_iso3d(args, torch, rte, mu_s):
+    from paper_1802_03061_amd import inputs
+    w = inputs.workload("iso3d", seed=0, mu_s=mu_s)
+    n = w["n"]
+    ctx = rte.Context(n, dim=3, mu_a=w["mu_a"], mu_s=w["mu_s"], L=0, prec=rte.PREC_FP32)
+    fs = [torch.from_numpy(inputs.workload("iso3d", seed=s, mu_s=mu_s)["f"]).cuda() for s in range(max(args.steps, 1))]
+    torch.cuda.synchronize()
+    r = timed_solves(ctx, fs, args.steps, args.warmup, torch)
+    pb = apply3d_pass_bytes(n)
+    rf = roofline(ctx, rte, pb, args.apply_reps, ["A", "B", "C", "D", "E"])
+    out = {
+        "value": r["solves_per_s"], "unit": "solves/s", "ms_per_step": r["ms_per_solve"],
+        "dtype": "f32 apply + f64 krylov",
+        "config": {"workload": f"3D isotropic {n}^3, mu_a={w['mu_a']:g}, mu_s={mu_s:g}, Gaussian-mixture sources, "
+                               f"FP32 FFT on the {padded(n)}^3 padded grid, tol 1e-8", "n": n, "mu_s": mu_s},
+        "solve": r, "applies_per_s": 1000.0 / rf["ms_apply"],
+        "apply_ms": {"fp32_total": rf["ms_apply"], "fp32_passes": rf["passes"]},
+        "apply_hbm_fraction": rf["apply_hbm_fraction"], "apply_bytes": pb, "roofline": rf["roofline"],
+    }
+    return out, ctx
 
 
 def main():
@@ -79,7 +266,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mu-s", type=float, default=10.0)
+    ap.add_argument("--workload", default="hg512", choices=["hg512", "batched", "iso3d", "diff256"])
+    ap.add_argument("--mu-s", type=float, default=None)
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pc", action="store_true", help="time plain GMRES only")
@@ -91,104 +279,32 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1802_03061_amd import inputs, rte
+    from paper_1802_03061_amd import rte
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     rank = int(os.environ.get("RANK", "0"))
-
-    base = inputs.workload("hg512", seed=0, mu_s=args.mu_s)
-    n, L = base["n"], base["L"]
-    ctx = rte.Context(n, mu_a=base["mu_a"], mu_s=base["mu_s"], sigma_hat=base["sigma_hat"], L=L,
-                      prec=rte.PREC_FP32)
-    # seeded sources, resident on the device before timing
-    nsrc = max(args.steps, 1)
-    fs = [torch.from_numpy(inputs.workload("hg512", seed=s, mu_s=args.mu_s)["f"]).cuda()
-          for s in range(nsrc)]
-    torch.cuda.synchronize()
-
-    def timed(label):
-        for i in range(args.warmup):
-            ctx.solve(fs[i % nsrc], tol=1e-8)
-        torch.cuda.synchronize()
-        infos = []
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            _, info = ctx.solve(fs[i % nsrc], tol=1e-8)
-            infos.append(info)
-        torch.cuda.synchronize()
-        ms = 1000.0 * (time.perf_counter() - t0) / args.steps
-        return ms, {"label": label, "ms_per_solve": ms, "solves_per_s": 1000.0 / ms,
-                    "iterations": float(np.mean([i["iterations"] for i in infos])),
-                    "applies": float(np.mean([i["applies"] for i in infos])),
-                    "cycles": float(np.mean([i["cycles"] for i in infos])),
-                    "pc_fallback": int(max(i["pc_fallback"] for i in infos)),
-                    "max_relres_true": float(max(i["relres_true"] for i in infos))}
-
-    ms_plain, plain = timed("plain GMRES")
-    t_setup_ms = ctx.solve(fs[0], tol=1e-8)[1]["t_setup_ms"]
-    pc = None
-    if not args.no_pc:
-        from paper_1802_03061_amd import pc_train
-        F = pc_train.coarse_factor(n)
-        net, meta = pc_train.train_for(ctx, range(10000, 10012), "hg512", F, steps=args.train_steps,
-                                       mu_s=args.mu_s)
-        ctx.attach_pc(net.params(), hidden=meta["hidden"], layers=meta["layers"], factor=F)
-        ms_pc, pc = timed("learned-PC FGMRES")
-        pc["training"] = {k: meta[k] for k in ("pairs", "factor", "hidden", "layers", "steps", "t_data_s",
-                                                "t_train_s", "noise_ratio", "multiscale_ratio", "use_bias")}
-        pc["training"]["final_loss"] = meta["loss_history"][-1][1] if meta["loss_history"] else None
-        ctx.attach_pc(None)
-        net.close()
-    head = pc if pc is not None else plain
-    ms_per_step = head["ms_per_solve"]
-    iters = head["iterations"]
-    applies = plain["applies"]
-    relres = head["max_relres_true"]
-
-    # apply throughput and per-pass times (HIP events on the context stream)
-    ms_apply, ms_pass = ctx.time_apply(rte.OP_A, rte.PREC_FP32, reps=args.apply_reps)
-    ms_apply64, ms_pass64 = ctx.time_apply(rte.OP_A, rte.PREC_FP64, reps=max(5, args.apply_reps // 5))
-    pb = apply_pass_bytes(n, L)
-    names = ["A", "B", "C"]
-    dom = int(np.argmax(ms_pass[:3]))
-    dom_name = names[dom]
-    achieved = pb[dom_name] / (ms_pass[dom] * 1e-3) / 1e9
-    tot_bytes = sum(pb.values())
-
-    out = {
-        "metric": METRIC,
-        "value": 1000.0 / ms_per_step,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32 apply + f64 krylov",
-        "data": "synthetic",
-        "config": {"workload": f"2D HG g=0.5, L=8 (17 modes), 512^2 cells, mu_a=0.1, mu_s={args.mu_s:g}, "
-                               f"seeded Gaussian-mixture sources, tol 1e-8 (true FP64 residual)",
-                   "n": n, "L": L, "mu_s": args.mu_s, "tol": 1e-8,
-                   "preconditioner": "learned coarse-grid CNN (FGMRES)" if pc else "none"},
-        "solve": {"iterations": iters, "max_relres_true": relres, "t_setup_ms": t_setup_ms},
-        "plain": plain,
-        "learned_pc": pc,
-        "pc_speedup_vs_plain": (plain["ms_per_solve"] / pc["ms_per_solve"]) if pc else None,
-        "applies_per_s": 1000.0 / ms_apply,
-        "apply_ms": {"fp32_total": ms_apply, "fp32_passes": dict(zip(names, ms_pass[:3])),
-                     "fp64_total": ms_apply64, "fp64_passes": dict(zip(names, ms_pass64[:3]))},
-        "apply_hbm_fraction": tot_bytes / (ms_apply * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "roofline": {"bound": "hbm", "kernel": f"apply pass {dom_name}", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None},
-    }
-    if rank == 0 and not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(base, applies)
-    ctx.close()
-    print(json.dumps(out), flush=True)
+    cpu = None
+    if args.workload in ("hg512", "diff256"):
+        mu_s = args.mu_s if args.mu_s is not None else (10.0 if args.workload == "hg512" else 50.0)
+        out, ctx, base, applies = bench_pc_workload(args, torch, rte, args.workload, mu_s)
+        if rank == 0 and not args.no_cpu_baseline:
+            cpu = cpu_baseline_2d(base, applies)
+        ctx.close()
+    elif args.workload == "batched":
+        out = bench_batched(args, torch, rte)
+    else:
+        out, ctx = bench_iso3d(args, torch, rte, args.mu_s if args.mu_s is not None else 10.0)
+        ctx.close()
+    line = {"metric": METRIC if args.workload == "hg512" else f"solves/s ({args.workload})"}
+    line.update({"value": out.pop("value"), "unit": out.pop("unit"), "n_gpus": 1, "steps": args.steps,
+                 "warmup": args.warmup, "ms_per_step": out.pop("ms_per_step"), "higher_is_better": True,
+                 "scaling": "weak", "vs_baseline": None, "dtype": out.pop("dtype"), "data": "synthetic"})
+    line.update(out)
+    line["copy_peak_gbs"] = copy_peak_gbs(torch)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":
