@@ -34,8 +34,11 @@ __host__ __device__ inline cx<T> mul_mi(cx<T> a) { return mk(a.im, -a.re); }
 // a += b * c
 template <typename T>
 __host__ __device__ inline void cmac(cx<T>& a, cx<T> b, cx<T> c) {
-    a.re += b.re * c.re - b.im * c.im;
-    a.im += b.re * c.im + b.im * c.re;
+    // a += b c as four fused multiply-adds into the accumulator (no separately rounded product)
+    a.re = fma(b.re, c.re, a.re);
+    a.re = fma(-b.im, c.im, a.re);
+    a.im = fma(b.re, c.im, a.im);
+    a.im = fma(b.im, c.re, a.im);
 }
 
 template <typename To, typename Ti>
