@@ -182,6 +182,8 @@ def bench_pc_workload(args, torch, rte, name, mu_s):
     head = pc if pc is not None else plain
     rf = roofline(ctx, rte, apply_pass_bytes(n, L), args.apply_reps, ["A", "B", "C"])
     ms64, pass64 = ctx.time_apply(rte.OP_A, rte.PREC_FP64, reps=max(5, args.apply_reps // 5))
+    variants = {name: [list(ctx.get_variant(p, q)) for q in range(3)]
+                for name, p in (("fp32", rte.PREC_FP32), ("fp64", rte.PREC_FP64))}
     out = {
         "value": head["solves_per_s"], "unit": "solves/s", "ms_per_step": head["ms_per_solve"],
         "dtype": "f32 apply + f64 krylov",
@@ -198,6 +200,7 @@ def bench_pc_workload(args, torch, rte, name, mu_s):
         "apply_ms": {"fp32_total": rf["ms_apply"], "fp32_passes": rf["passes"], "fp64_total": ms64,
                      "fp64_passes": dict(zip("ABC", pass64[:3]))},
         "apply_hbm_fraction": rf["apply_hbm_fraction"], "apply_bytes": apply_pass_bytes(n, L),
+        "kernel_variants": variants,
         "roofline": rf["roofline"],
     }
     return out, ctx, base, plain["applies"]

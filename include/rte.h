@@ -156,6 +156,18 @@ int rte_pc_attach(rte_ctx* ctx, const float* weights_dev, int hidden, int layers
  * 3D: five passes; unused entries 0).  Input/output are internal buffers. */
 int rte_time_apply(rte_ctx* ctx, int op, int prec, int reps, double* ms_total, double* ms_pass);
 
+/* Kernel variants of the 2D apply (pass 0 = A, 1 = B, 2 = C; prec = RTE_PREC_FP32 or
+ * RTE_PREC_FP64 apply).  Variants differ only in tiling (row tiles, thread counts, FFT grouping):
+ * the same arithmetic, equal results up to rounding.  rte_setup of a 2D context with n_x or n_y >= 128 picks the
+ * fastest variant of every pass by timing them on the context's buffers, once per (precision,
+ * L, n_x, n_y) per process (environment RTE_AUTOTUNE=0: keep variant 0).  rte_autotune re-times
+ * them (`reps` launches each; synchronises the stream); rte_set_variant forces one
+ * (RTE_EINVAL if out of range); rte_get_variant reports the current one and how many exist.
+ * 3D contexts: RTE_EUNSUPPORTED (get_variant reports variant 0 of 1). */
+int rte_autotune(rte_ctx* ctx, int reps);
+int rte_set_variant(rte_ctx* ctx, int prec, int pass, int variant);
+int rte_get_variant(const rte_ctx* ctx, int prec, int pass, int* variant, int* count);
+
 /* Sizes: *channels = 2L+1 (3D: 1), *modes = 2L+1, *cells = n_x n_y (n_z). */
 int rte_query(const rte_ctx* ctx, int* channels, int* modes, long long* cells);
 

@@ -19,8 +19,17 @@ struct Apply2DArgs {
     const cx<T>* twx;          // exp(-2 pi i q/PX), q < PX
     const cx<T>* twy;          // exp(-2 pi i q/PY), q < PY
     hipStream_t stream;
-    int pack;                  // 1: x-frequencies 0 and PX/2 share column 0 of the work buffer
+    int pack = 0;              // 1: x-frequencies 0 and PX/2 share column 0 of the work buffer
+    int var[3] = {0, 0, 0};    // kernel variant of passes A, B, C (see apply2d_variant_count)
 };
+
+// Kernel variants (same arithmetic, different tiling; results agree up to rounding):
+//   passes A and C: row tiles of 16, 8 or 32 rows (FP32) / 8, 4 or 16 rows (FP64)
+//   pass B (fused form, PY >= 128): default threads and FFT grouping, 1024 threads with groups of
+//   4 transforms (FP32 only), or 256 threads
+// Number of variants of `pass` (0 = A, 1 = B, 2 = C) for this shape and precision.
+template <typename T>
+int apply2d_variant_count(int pass, int L, int PX, int PY);
 
 // One isotropic problem (C = 1) of a batched apply.  Pass A reads in (+ j * stride when jin is
 // set, j read from the device), pass C writes out (+ (j + 1) * stride when jout is set) and reads

@@ -233,21 +233,38 @@ __global__ __launch_bounds__(NTHR) void k_pass_c_batch(const BatchProb<T>* __res
 
 // ---------------------------------------------------------------------------- dispatch -------
 template <typename T> constexpr int tile_rows() { return sizeof(T) == 4 ? 16 : 8; }
-template <typename T, int PX>
-static void launch_a(const Apply2DArgs<T>& a, const double* x, const ChanScale& sc, int nchan_total) {
-    constexpr int TR = tile_rows<T>();
+template <typename T, int PX, int TR>
+static void launch_a_tr(const Apply2DArgs<T>& a, const double* x, const ChanScale& sc, int nchan_total) {
     dim3 grid((a.ny + TR - 1) / TR, nchan_total);
     hipLaunchKernelGGL((k_pass_a<T, PX, TR, 256>), grid, dim3(256), 0, a.stream, x, a.work, a.twx, a.nx,
                        a.ny, a.C, sc, a.pack);
 }
+template <typename T, int PX>
+static void launch_a(const Apply2DArgs<T>& a, const double* x, const ChanScale& sc, int nchan_total) {
+    constexpr int TR = tile_rows<T>();
+    if constexpr (PX >= 128) {
+        if (a.var[0] == 1) return launch_a_tr<T, PX, TR / 2>(a, x, sc, nchan_total);
+        if (a.var[0] == 2) return launch_a_tr<T, PX, TR * 2>(a, x, sc, nchan_total);
+    }
+    launch_a_tr<T, PX, TR>(a, x, sc, nchan_total);
+}
 
+template <typename T, int PX, int TR>
+static void launch_c_tr(const Apply2DArgs<T>& a, const double* x, const double* b, double* y, int mode,
+                        int nchan_total) {
+    dim3 grid((a.ny + TR - 1) / TR, nchan_total);
+    hipLaunchKernelGGL((k_pass_c<T, PX, TR, 256>), grid, dim3(256), 0, a.stream, a.work, x, b, y, a.twx,
+                       a.nx, a.ny, mode, a.pack);
+}
 template <typename T, int PX>
 static void launch_c(const Apply2DArgs<T>& a, const double* x, const double* b, double* y, int mode,
                      int nchan_total) {
     constexpr int TR = tile_rows<T>();
-    dim3 grid((a.ny + TR - 1) / TR, nchan_total);
-    hipLaunchKernelGGL((k_pass_c<T, PX, TR, 256>), grid, dim3(256), 0, a.stream, a.work, x, b, y, a.twx,
-                       a.nx, a.ny, mode, a.pack);
+    if constexpr (PX >= 128) {
+        if (a.var[2] == 1) return launch_c_tr<T, PX, TR / 2>(a, x, b, y, mode, nchan_total);
+        if (a.var[2] == 2) return launch_c_tr<T, PX, TR * 2>(a, x, b, y, mode, nchan_total);
+    }
+    launch_c_tr<T, PX, TR>(a, x, b, y, mode, nchan_total);
 }
 
 #define RTE_P_SWITCH(P, FN, ...)                  \
@@ -261,6 +278,26 @@ static void launch_c(const Apply2DArgs<T>& a, const double* x, const double* b, 
         case 1024: FN<T, 1024>(__VA_ARGS__); break; \
         default: return -1;                       \
     }
+
+template <typename T>
+int apply2d_variant_count(int pass, int L, int PX, int PY) {
+    if (pass == 0 || pass == 2) return PX >= 128 ? 3 : 1;
+    if (pass != 1) return 0;
+    switch (L) {
+        case 0: return pass_b_variants_L0<T>(PY);
+        case 1: return pass_b_variants_L1<T>(PY);
+        case 2: return pass_b_variants_L2<T>(PY);
+        case 3: return pass_b_variants_L3<T>(PY);
+        case 4: return pass_b_variants_L4<T>(PY);
+        case 5: return pass_b_variants_L5<T>(PY);
+        case 6: return pass_b_variants_L6<T>(PY);
+        case 7: return pass_b_variants_L7<T>(PY);
+        case 8: return pass_b_variants_L8<T>(PY);
+    }
+    return 0;
+}
+template int apply2d_variant_count<float>(int, int, int, int);
+template int apply2d_variant_count<double>(int, int, int, int);
 
 template <typename T>
 int apply2d_pass_a(const Apply2DArgs<T>& a, const double* x, const ChanScale& sc, int nbatch) {

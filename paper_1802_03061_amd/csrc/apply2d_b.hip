@@ -145,7 +145,7 @@ __device__ __forceinline__ void couple_packed_pair(PF p, PM pm, const cx<T>* __r
 // Fused pass B: NCOL columns x C channels per block, spectra resident in LDS.
 // base: the batch entry's [C][nkx][ny] work buffer; nkx = its columns, nkq = columns of the kernel
 // table (PX/2 + 1); kx0 = the block's first column.
-template <typename T, int PY, int L, int NCOL, int NTHR>
+template <typename T, int PY, int L, int NCOL, int NTHR, int GV = 0>
 __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T>* __restrict__ Q, int ny, int nkx,
                                             int nkq, int pack, int kx0, cx<T>* spec, const cx<T>* tws,
                                             cx<T>* pairtmp, int tid) {
@@ -178,8 +178,9 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
         }
     }
     __syncthreads();
-    // at most ~3 radix-8 butterflies per thread and stage
-    constexpr int G = (3 * NTHR * 8) / PY >= NF ? NF : ((3 * NTHR * 8) / PY < 1 ? 1 : (3 * NTHR * 8) / PY);
+    // at most ~3 radix-8 butterflies per thread and stage, or groups of GV transforms if given
+    constexpr int G0 = (3 * NTHR * 8) / PY >= NF ? NF : ((3 * NTHR * 8) / PY < 1 ? 1 : (3 * NTHR * 8) / PY);
+    constexpr int G = GV > 0 ? (GV < NF ? GV : NF) : G0;
     block_fft_grouped<T, PY, NF, G, LD, NTHR, false>(spec, tws, tid);
     const size_t qs = (size_t)nkq * KH;
 #pragma unroll 1
@@ -225,7 +226,7 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
     }
 }
 
-template <typename T, int PY, int L, int NCOL, int NTHR>
+template <typename T, int PY, int L, int NCOL, int NTHR, int GV>
 __global__ __launch_bounds__(NTHR) void k_pass_b_lds(cx<T>* __restrict__ Tb, const cx<T>* __restrict__ Q,
                                                      const cx<T>* __restrict__ tw, int ny, int nkx, int nkq,
                                                      int pack) {
@@ -235,8 +236,8 @@ __global__ __launch_bounds__(NTHR) void k_pass_b_lds(cx<T>* __restrict__ Tb, con
     __shared__ cx<T> pairtmp[2 * C];   // Q of the two self-mirrored frequencies of a packed column
     const int tid = threadIdx.x;
     stage_twiddles<T, PY, NTHR>(tws, tw, tid);
-    pass_b_cols<T, PY, L, NCOL, NTHR>(Tb + (size_t)blockIdx.y * C * nkx * ny, Q, ny, nkx, nkq, pack,
-                                      blockIdx.x * NCOL, spec, tws, pairtmp, tid);
+    pass_b_cols<T, PY, L, NCOL, NTHR, GV>(Tb + (size_t)blockIdx.y * C * nkx * ny, Q, ny, nkx, nkq, pack,
+                                          blockIdx.x * NCOL, spec, tws, pairtmp, tid);
 }
 
 #if RTE_PASSB_L == 0
@@ -344,6 +345,23 @@ constexpr int nthr_for() {
     return NFPY / 8 >= 512 ? 512 : (NFPY / 8 >= 256 ? 256 : (NFPY / 8 >= 128 ? 128 : 64));
 }
 
+// Fused-form variants: 0 = default threads and grouping; 1 = 1024 threads, groups of 4 transforms
+// (FP32 only); 2 = 256 threads.  Variants 1 and 2 exist for PY >= 128 when they have enough work.
+template <typename T, int PY, int L>
+constexpr int fused_variants() {
+    constexpr int C = 2 * L + 1;
+    constexpr int NF = ncol_for<T, PY, L>() * C * PY;
+    if (PY < 128) return 1;
+    return (sizeof(T) == 4 && NF / 8 >= 1024) ? 3 : 2;
+}
+
+template <typename T, int PY, int L, int NCOL, int NT, int GV>
+static void launch_fused(const Apply2DArgs<T>& a, int nbatch, int nkx, int nkq) {
+    dim3 grid((nkx + NCOL - 1) / NCOL, nbatch);
+    hipLaunchKernelGGL((k_pass_b_lds<T, PY, L, NCOL, NT, GV>), grid, dim3(NT), 0, a.stream, a.work, a.Q, a.twy, a.ny,
+                       nkx, nkq, a.pack);
+}
+
 template <typename T, int PY>
 static int launch_py(const Apply2DArgs<T>& a, int nbatch) {
     constexpr int L = RTE_PASSB_L;
@@ -353,9 +371,14 @@ static int launch_py(const Apply2DArgs<T>& a, int nbatch) {
     if constexpr (fused_fits<T, PY, L>()) {
         constexpr int NCOL = ncol_for<T, PY, L>();
         constexpr int NT = nthr_for<T, NCOL * C * PY>();
-        dim3 grid((nkx + NCOL - 1) / NCOL, nbatch);
-        hipLaunchKernelGGL((k_pass_b_lds<T, PY, L, NCOL, NT>), grid, dim3(NT), 0, a.stream, a.work, a.Q,
-                           a.twy, a.ny, nkx, nkq, a.pack);
+        constexpr int NV = fused_variants<T, PY, L>();
+        if constexpr (NV >= 3) {
+            if (a.var[1] == 1) { launch_fused<T, PY, L, NCOL, 1024, 4>(a, nbatch, nkx, nkq); return 0; }
+        }
+        if constexpr (NV >= 2) {
+            if (a.var[1] == 2) { launch_fused<T, PY, L, NCOL, 256, 0>(a, nbatch, nkx, nkq); return 0; }
+        }
+        launch_fused<T, PY, L, NCOL, NT, 0>(a, nbatch, nkx, nkq);
         return 0;
     } else {
         if (!a.work2) return -2;
@@ -370,6 +393,12 @@ static int launch_py(const Apply2DArgs<T>& a, int nbatch) {
                            nkx);
         return 0;
     }
+}
+
+template <typename T, int PY>
+static int variants_py() {
+    if constexpr (fused_fits<T, PY, RTE_PASSB_L>()) return fused_variants<T, PY, RTE_PASSB_L>();
+    return 1;
 }
 
 template <typename T>
@@ -424,6 +453,22 @@ template int apply2d_batch_pass_b<double>(int, const BatchProb<double>*, const i
 #endif
 
 #define RTE_PASSB_FN RTE_CAT(pass_b_L, RTE_PASSB_L)
+#define RTE_PASSB_VARIANTS RTE_CAT(pass_b_variants_L, RTE_PASSB_L)
+template <typename T>
+int RTE_PASSB_VARIANTS(int PY) {
+    switch (PY) {
+        case 16: return variants_py<T, 16>();
+        case 32: return variants_py<T, 32>();
+        case 64: return variants_py<T, 64>();
+        case 128: return variants_py<T, 128>();
+        case 256: return variants_py<T, 256>();
+        case 512: return variants_py<T, 512>();
+        case 1024: return variants_py<T, 1024>();
+    }
+    return 0;
+}
+template int RTE_PASSB_VARIANTS<float>(int);
+template int RTE_PASSB_VARIANTS<double>(int);
 
 template <>
 int RTE_PASSB_FN<float>(const Apply2DArgs<float>& a, int nbatch) { return launch_pass_b_impl<float>(a, nbatch); }

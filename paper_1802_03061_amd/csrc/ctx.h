@@ -48,6 +48,9 @@ struct rte_ctx {
     int* hpipe_flags = nullptr; // pinned per-iteration (breakdown, non-finite)
     std::vector<hipEvent_t> ev_iter;
     rte_solve_opts opts{};
+    // kernel variants of the 2D apply passes A, B, C (FP32 and FP64 applies), set by the autotuner
+    int varf[3] = {0, 0, 0};
+    int vard[3] = {0, 0, 0};
     // learned preconditioner (see nn.hip)
     bool pc_attached = false;
     int pc_hidden = 0, pc_layers = 0, pc_factor = 1;
@@ -69,6 +72,7 @@ int ensure_krylov(rte_ctx* c, int m, bool need_z);
 int apply_channels(rte_ctx* c, int mode, int prec, const double* x, const double* b, double* y, int nbatch);
 int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
                double* rec, int max_rec, int* nrec);
+int autotune_2d(rte_ctx* c, int reps, bool use_cache);
 }  // namespace rte
 
 namespace rte {

@@ -14,7 +14,10 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -161,11 +164,13 @@ static Apply2DArgs<T> args2d(const rte_ctx* c);
 template <>
 Apply2DArgs<float> args2d<float>(const rte_ctx* c) {
     Apply2DArgs<float> a{c->nx, c->ny, c->PX, c->PY, c->L, c->C, c->wf, c->wf2, c->Qf, c->twf[0], c->twf[1], c->stream};
+    for (int p = 0; p < 3; ++p) a.var[p] = c->varf[p];
     return a;
 }
 template <>
 Apply2DArgs<double> args2d<double>(const rte_ctx* c) {
     Apply2DArgs<double> a{c->nx, c->ny, c->PX, c->PY, c->L, c->C, c->wd, c->wd2, c->Qd, c->twd[0], c->twd[1], c->stream};
+    for (int p = 0; p < 3; ++p) a.var[p] = c->vard[p];
     return a;
 }
 
@@ -221,6 +226,73 @@ static int apply_t(rte_ctx* c, int mode, const double* x, const double* b, doubl
 int apply_channels(rte_ctx* c, int mode, int prec, const double* x, const double* b, double* y, int nbatch) {
     if (prec == RTE_PREC_FP32) return apply_t<float>(c, mode, x, b, y, nbatch, nullptr);
     return apply_t<double>(c, mode, x, b, y, nbatch, nullptr);
+}
+
+// ------------------------------------------------------------------ autotuning -----------------
+// Every pass of the 2D apply has a few kernel variants with the same arithmetic (different row
+// tiles, thread counts, FFT grouping).  The tuner times each variant of each pass on the
+// context's own buffers (`reps` launches between events, the other passes at their current
+// choice) and keeps the fastest.  Choices are cached per (precision, L, nx, ny) for the process.
+
+static std::mutex g_tune_mu;
+static std::map<std::vector<int>, std::vector<int>> g_tune_cache;
+
+template <typename T>
+static int tune_t(rte_ctx* c, int* var, int reps, bool use_cache) {
+    const std::vector<int> key = {(int)sizeof(T), c->L, c->nx, c->ny};
+    if (use_cache) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            for (int p = 0; p < 3; ++p) var[p] = it->second[p];
+            return RTE_OK;
+        }
+    }
+    const ChanScale sc = channel_scale(c, APPLY_A);
+    vec_fill(c->t0, 1.0, c->nvec, c->stream);
+    hipEvent_t e0, e1;
+    RTE_HIP_TRY(hipEventCreate(&e0));
+    RTE_HIP_TRY(hipEventCreate(&e1));
+    int rc = RTE_OK;
+    for (int pass = 0; pass < 3 && !rc; ++pass) {
+        const int nv = apply2d_variant_count<T>(pass, c->L, c->PX, c->PY);
+        int best = 0;
+        float best_ms = 1e30f;
+        for (int v = 0; v < nv && !rc; ++v) {
+            Apply2DArgs<T> a = args2d<T>(c);
+            a.pack = 1;
+            for (int p = 0; p < 3; ++p) a.var[p] = var[p];
+            a.var[pass] = v;
+            // one full apply first: the work buffer then holds a valid spectrum for passes B and C
+            if (apply2d<T>(a, c->t0, nullptr, c->t1, APPLY_A, sc, 1)) { rc = set_error(RTE_EUNSUPPORTED, "tune"); break; }
+            (void)hipEventRecord(e0, c->stream);
+            for (int r = 0; r < reps; ++r) {
+                int lr = pass == 0 ? apply2d_pass_a<T>(a, c->t0, sc, 1)
+                                   : pass == 1 ? apply2d_pass_b<T>(a, 1) : apply2d_pass_c<T>(a, c->t0, nullptr, c->t1, APPLY_A, 1);
+                if (lr) { rc = set_error(RTE_EUNSUPPORTED, "tune"); break; }
+            }
+            (void)hipEventRecord(e1, c->stream);
+            hipError_t e = hipEventSynchronize(e1);
+            if (e != hipSuccess) { rc = set_hip_error(e, "tune", __FILE__, __LINE__); break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) { best_ms = ms; best = v; }
+        }
+        var[pass] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = std::vector<int>(var, var + 3);
+    return RTE_OK;
+}
+
+int autotune_2d(rte_ctx* c, int reps, bool use_cache) {
+    if (c->dim != 2) return RTE_OK;
+    int rc = tune_t<double>(c, c->vard, reps, use_cache);
+    if (!rc && c->prec == RTE_PREC_FP32) rc = tune_t<float>(c, c->varf, reps, use_cache);
+    return rc;
 }
 
 // ------------------------------------------------------------------ small host helpers ---------
@@ -561,8 +633,39 @@ int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const 
         return rc;
     }
     if ((rc = ensure_krylov(c, c->opts.restart, false))) { free_ctx(c); return rc; }
+    // kernel variants: tuned once per shape and process (RTE_AUTOTUNE=0 keeps the defaults)
+    const char* at = std::getenv("RTE_AUTOTUNE");
+    if (c->dim == 2 && std::max(c->nx, c->ny) >= 128 && !(at && at[0] == '0')) {
+        if ((rc = autotune_2d(c, 5, true))) { free_ctx(c); return rc; }
+    }
     c->t_setup_ms = now_ms() - t0;
     *out = c;
+    return RTE_OK;
+}
+
+int rte_autotune(rte_ctx* c, int reps) {
+    if (!c || reps < 1) return set_error(RTE_EINVAL, "bad argument");
+    if (c->dim != 2) return set_error(RTE_EUNSUPPORTED, "variants exist for 2D contexts only");
+    return autotune_2d(c, reps, false);
+}
+
+int rte_set_variant(rte_ctx* c, int prec, int pass, int variant) {
+    if (!c || pass < 0 || pass > 2 || (prec != RTE_PREC_FP32 && prec != RTE_PREC_FP64)) return set_error(RTE_EINVAL, "bad argument");
+    if (c->dim != 2) return set_error(RTE_EUNSUPPORTED, "variants exist for 2D contexts only");
+    const int nv = prec == RTE_PREC_FP32 ? apply2d_variant_count<float>(pass, c->L, c->PX, c->PY)
+                                         : apply2d_variant_count<double>(pass, c->L, c->PX, c->PY);
+    if (variant < 0 || variant >= nv) return set_error(RTE_EINVAL, "variant %d out of range (%d variants)", variant, nv);
+    (prec == RTE_PREC_FP32 ? c->varf : c->vard)[pass] = variant;
+    return RTE_OK;
+}
+
+int rte_get_variant(const rte_ctx* c, int prec, int pass, int* variant, int* count) {
+    if (!c || pass < 0 || pass > 2 || (prec != RTE_PREC_FP32 && prec != RTE_PREC_FP64)) return set_error(RTE_EINVAL, "bad argument");
+    if (variant) *variant = c->dim == 2 ? (prec == RTE_PREC_FP32 ? c->varf : c->vard)[pass] : 0;
+    if (count)
+        *count = c->dim != 2 ? 1
+                 : prec == RTE_PREC_FP32 ? apply2d_variant_count<float>(pass, c->L, c->PX, c->PY)
+                                         : apply2d_variant_count<double>(pass, c->L, c->PX, c->PY);
     return RTE_OK;
 }
 

@@ -81,6 +81,9 @@ def load():
         "rte_pc_apply": (I, [P, P, P]),
         "rte_time_apply": (I, [P, I, I, I, C.POINTER(D), C.POINTER(D)]),
         "rte_query": (I, [P, C.POINTER(I), C.POINTER(I), C.POINTER(C.c_longlong)]),
+        "rte_autotune": (I, [P, I]),
+        "rte_set_variant": (I, [P, I, I, I]),
+        "rte_get_variant": (I, [P, I, I, C.POINTER(I), C.POINTER(I)]),
         "rte_modes_to_channels": (I, [P, P, P]),
         "rte_channels_to_modes": (I, [P, P, P]),
         "rte_destroy": (None, [P]),
@@ -236,6 +239,17 @@ class Context:
         passes = (C.c_double * 5)()
         _check(load().rte_time_apply(self._h, op, prec, reps, C.byref(tot), passes))
         return tot.value, list(passes)
+
+    def autotune(self, reps=5):
+        _check(load().rte_autotune(self._h, int(reps)))
+
+    def set_variant(self, prec, pass_, variant):
+        _check(load().rte_set_variant(self._h, int(prec), int(pass_), int(variant)))
+
+    def get_variant(self, prec, pass_):
+        v, n = C.c_int(), C.c_int()
+        _check(load().rte_get_variant(self._h, int(prec), int(pass_), C.byref(v), C.byref(n)))
+        return v.value, n.value
 
     def attach_pc(self, weights, hidden=32, layers=5, factor=8):
         """Attach the coarse-grid network (packed float32 parameters) as the FGMRES right
