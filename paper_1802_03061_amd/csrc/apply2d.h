@@ -21,10 +21,16 @@ struct Apply2DArgs {
     hipStream_t stream;
     int pack = 0;              // 1: x-frequencies 0 and PX/2 share column 0 of the work buffer
     int var[3] = {0, 0, 0};    // kernel variant of passes A, B, C (see apply2d_variant_count)
+    // Optional coarse correction (operator A, one batch entry): the input of the apply is taken as
+    // x + cs P y, y = corr[C][ny/cF][nx/cF] (FP32), P = bilinear interpolation from the coarse
+    // cell centres, clamped -- the flexible-GMRES vector z = v + s P N(R v / s) formed on the fly.
+    const float* corr = nullptr;
+    int cF = 1;
+    double cs = 0.0;
 };
 
 // Kernel variants (same arithmetic, different tiling; results agree up to rounding):
-//   passes A and C: row tiles of 16, 8 or 32 rows (FP32) / 8, 4 or 16 rows (FP64)
+//   passes A and C (PX >= 128): row tiles of 16, 8, 32 or 4 rows (FP32) / 8, 4, 16 or 2 rows (FP64)
 //   pass B (fused form, PY >= 128): default threads and FFT grouping, 1024 threads with groups of
 //   4 transforms (FP32 only), or 256 threads
 // Number of variants of `pass` (0 = A, 1 = B, 2 = C) for this shape and precision.

@@ -31,6 +31,26 @@
 
 namespace rte {
 
+// Bilinear interpolation of a coarse field yc[Hc][Wc] (cell-centred, coarse cell I covering fine
+// cells I*F .. I*F+F-1, clamped to the outer coarse centres) at fine cell (y, x).
+__device__ __forceinline__ void lerp_at(int i, int F, int nc, int& lo, int& hi, float& a) {
+    const float xi = ((float)i + 0.5f) / (float)F - 0.5f;
+    const float f0 = floorf(xi);
+    a = xi - f0;
+    const int i0 = (int)f0;
+    lo = min(max(i0, 0), nc - 1);
+    hi = min(max(i0 + 1, 0), nc - 1);
+}
+__device__ __forceinline__ float coarse_bilerp(const float* __restrict__ yc, int Hc, int Wc, int F, int y, int x) {
+    int y0, y1, x0, x1;
+    float ay, ax;
+    lerp_at(y, F, Hc, y0, y1, ay);
+    lerp_at(x, F, Wc, x0, x1, ax);
+    const float top = (1.f - ax) * yc[y0 * Wc + x0] + ax * yc[y0 * Wc + x1];
+    const float bot = (1.f - ax) * yc[y1 * Wc + x0] + ax * yc[y1 * Wc + x1];
+    return (1.f - ay) * top + ay * bot;
+}
+
 // ---------------------------------------------------------------------------- pass A --------
 // With pack != 0 the x-frequencies 0 and PX/2, whose values are real for real rows, share
 // column 0 of T as (X[0], X[PX/2]); T then has PX/2 columns.
@@ -38,7 +58,8 @@ namespace rte {
 // transposed x-spectrum; tws holds the staged twiddles.
 template <typename T, int PX, int TR, int NTHR>
 __device__ __forceinline__ void pass_a_tile(const double* __restrict__ xin, cx<T>* __restrict__ out, int nx, int ny,
-                                            double s, int pack, int y0, cx<T>* buf, const cx<T>* tws, int tid) {
+                                            double s, int pack, int y0, cx<T>* buf, const cx<T>* tws, int tid,
+                                            const float* __restrict__ corr_c = nullptr, int cF = 1, double cs = 0.0) {
     constexpr int NP = TR / 2;        // complex FFTs per block (two real rows each)
     constexpr int LD = padded(PX) + 1;   // odd row pitch: the NP transforms start on different banks
     constexpr int H = PX / 2;
@@ -54,6 +75,18 @@ __device__ __forceinline__ void pass_a_tile(const double* __restrict__ xin, cx<T
         const bool ok = (NL % NTHR == 0 || idx < NL) && m < nx;
         ra[it] = (ok && ya < ny) ? xin[(size_t)ya * nx + m] : 0.0;
         rb[it] = (ok && yb < ny) ? xin[(size_t)yb * nx + m] : 0.0;
+    }
+    if (corr_c) {
+        const int Hc = ny / cF, Wc = nx / cF;
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int idx = tid + it * NTHR;
+            const int p = idx / H, m = idx % H;
+            const int ya = y0 + 2 * p, yb = ya + 1;
+            const bool ok = (NL % NTHR == 0 || idx < NL) && m < nx;
+            if (ok && ya < ny) ra[it] += cs * (double)coarse_bilerp(corr_c, Hc, Wc, cF, ya, m);
+            if (ok && yb < ny) rb[it] += cs * (double)coarse_bilerp(corr_c, Hc, Wc, cF, yb, m);
+        }
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -90,7 +123,8 @@ __device__ __forceinline__ void pass_a_tile(const double* __restrict__ xin, cx<T
 template <typename T, int PX, int TR, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_pass_a(const double* __restrict__ x, cx<T>* __restrict__ Tb,
                                                  const cx<T>* __restrict__ tw, int nx, int ny, int C,
-                                                 ChanScale sc, int pack) {
+                                                 ChanScale sc, int pack, const float* __restrict__ corr, int cF,
+                                                 double cs) {
     constexpr int LD = padded(PX) + 1;
     __shared__ cx<T> buf[TR / 2 * LD];
     __shared__ cx<T> tws[PX];
@@ -98,8 +132,9 @@ __global__ __launch_bounds__(NTHR) void k_pass_a(const double* __restrict__ x, c
     const int bc = blockIdx.y;
     stage_twiddles<T, PX, NTHR>(tws, tw, tid);
     const int NKS = pack ? PX / 2 : PX / 2 + 1;
+    const float* cc = corr ? corr + (size_t)(bc % C) * (ny / cF) * (nx / cF) : nullptr;
     pass_a_tile<T, PX, TR, NTHR>(x + (size_t)bc * ny * nx, Tb + (size_t)bc * NKS * ny, nx, ny, sc.s[bc % C], pack,
-                                 blockIdx.x * TR, buf, tws, tid);
+                                 blockIdx.x * TR, buf, tws, tid, cc, cF, cs);
 }
 
 // Batched form (isotropic problems of one padded size): one block per (problem, row tile).
@@ -126,7 +161,8 @@ __global__ __launch_bounds__(NTHR) void k_pass_a_batch(const BatchProb<T>* __res
 template <typename T, int PX, int TR, int NTHR>
 __device__ __forceinline__ void pass_c_tile(const cx<T>* __restrict__ src, const double* __restrict__ xin,
                                             const double* __restrict__ bin, double* __restrict__ yout, int nx, int ny,
-                                            int mode, int pack, int y0, cx<T>* buf, const cx<T>* tws, int tid) {
+                                            int mode, int pack, int y0, cx<T>* buf, const cx<T>* tws, int tid,
+                                            const float* __restrict__ corr_c = nullptr, int cF = 1, double cs = 0.0) {
     constexpr int NP = TR / 2;
     constexpr int LD = padded(PX) + 1;   // odd row pitch: the NP transforms start on different banks
     constexpr int H = PX / 2;
@@ -176,6 +212,7 @@ __device__ __forceinline__ void pass_c_tile(const cx<T>* __restrict__ src, const
             const size_t o = (size_t)y * nx + m;
             xv[u] = (ok && mode != APPLY_KT) ? xin[o] : 0.0;
             bv[u] = (ok && mode == APPLY_RESID) ? bin[o] : 0.0;
+            if (corr_c && ok) xv[u] += cs * (double)coarse_bilerp(corr_c, ny / cF, nx / cF, cF, y, m);
         }
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
@@ -198,7 +235,8 @@ __device__ __forceinline__ void pass_c_tile(const cx<T>* __restrict__ src, const
 template <typename T, int PX, int TR, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_pass_c(const cx<T>* __restrict__ Tb, const double* __restrict__ xin,
                                                  const double* __restrict__ bin, double* __restrict__ yout,
-                                                 const cx<T>* __restrict__ tw, int nx, int ny, int mode, int pack) {
+                                                 const cx<T>* __restrict__ tw, int nx, int ny, int mode, int pack,
+                                                 int C, const float* __restrict__ corr, int cF, double cs) {
     constexpr int LD = padded(PX) + 1;
     __shared__ cx<T> buf[TR / 2 * LD];
     __shared__ cx<T> tws[PX];
@@ -207,8 +245,9 @@ __global__ __launch_bounds__(NTHR) void k_pass_c(const cx<T>* __restrict__ Tb, c
     const int NKS = pack ? PX / 2 : PX / 2 + 1;
     stage_twiddles<T, PX, NTHR>(tws, tw, tid);
     const size_t base = (size_t)bc * ny * nx;
+    const float* cc = corr ? corr + (size_t)(bc % C) * (ny / cF) * (nx / cF) : nullptr;
     pass_c_tile<T, PX, TR, NTHR>(Tb + (size_t)bc * NKS * ny, xin ? xin + base : nullptr, bin ? bin + base : nullptr,
-                                 yout + base, nx, ny, mode, pack, blockIdx.x * TR, buf, tws, tid);
+                                 yout + base, nx, ny, mode, pack, blockIdx.x * TR, buf, tws, tid, cc, cF, cs);
 }
 
 // Batched form: one block per (problem, row tile); the output is written to out + (j + 1) stride
@@ -237,7 +276,7 @@ template <typename T, int PX, int TR>
 static void launch_a_tr(const Apply2DArgs<T>& a, const double* x, const ChanScale& sc, int nchan_total) {
     dim3 grid((a.ny + TR - 1) / TR, nchan_total);
     hipLaunchKernelGGL((k_pass_a<T, PX, TR, 256>), grid, dim3(256), 0, a.stream, x, a.work, a.twx, a.nx,
-                       a.ny, a.C, sc, a.pack);
+                       a.ny, a.C, sc, a.pack, a.corr, a.cF, a.cs);
 }
 template <typename T, int PX>
 static void launch_a(const Apply2DArgs<T>& a, const double* x, const ChanScale& sc, int nchan_total) {
@@ -245,6 +284,7 @@ static void launch_a(const Apply2DArgs<T>& a, const double* x, const ChanScale& 
     if constexpr (PX >= 128) {
         if (a.var[0] == 1) return launch_a_tr<T, PX, TR / 2>(a, x, sc, nchan_total);
         if (a.var[0] == 2) return launch_a_tr<T, PX, TR * 2>(a, x, sc, nchan_total);
+        if (a.var[0] == 3) return launch_a_tr<T, PX, TR / 4>(a, x, sc, nchan_total);
     }
     launch_a_tr<T, PX, TR>(a, x, sc, nchan_total);
 }
@@ -254,7 +294,7 @@ static void launch_c_tr(const Apply2DArgs<T>& a, const double* x, const double* 
                         int nchan_total) {
     dim3 grid((a.ny + TR - 1) / TR, nchan_total);
     hipLaunchKernelGGL((k_pass_c<T, PX, TR, 256>), grid, dim3(256), 0, a.stream, a.work, x, b, y, a.twx,
-                       a.nx, a.ny, mode, a.pack);
+                       a.nx, a.ny, mode, a.pack, a.C, mode == APPLY_A ? a.corr : nullptr, a.cF, a.cs);
 }
 template <typename T, int PX>
 static void launch_c(const Apply2DArgs<T>& a, const double* x, const double* b, double* y, int mode,
@@ -263,6 +303,7 @@ static void launch_c(const Apply2DArgs<T>& a, const double* x, const double* b, 
     if constexpr (PX >= 128) {
         if (a.var[2] == 1) return launch_c_tr<T, PX, TR / 2>(a, x, b, y, mode, nchan_total);
         if (a.var[2] == 2) return launch_c_tr<T, PX, TR * 2>(a, x, b, y, mode, nchan_total);
+        if (a.var[2] == 3) return launch_c_tr<T, PX, TR / 4>(a, x, b, y, mode, nchan_total);
     }
     launch_c_tr<T, PX, TR>(a, x, b, y, mode, nchan_total);
 }
@@ -281,7 +322,7 @@ static void launch_c(const Apply2DArgs<T>& a, const double* x, const double* b, 
 
 template <typename T>
 int apply2d_variant_count(int pass, int L, int PX, int PY) {
-    if (pass == 0 || pass == 2) return PX >= 128 ? 3 : 1;
+    if (pass == 0 || pass == 2) return PX >= 128 ? 4 : 1;
     if (pass != 1) return 0;
     switch (L) {
         case 0: return pass_b_variants_L0<T>(PY);

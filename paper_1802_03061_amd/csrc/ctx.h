@@ -65,11 +65,14 @@ struct rte_ctx {
     int* pc_meta = nullptr;     // per layer: cin, cout, tap-major pack offset, bias offset
     unsigned short* pc_wn = nullptr;   // tap-major BF16 weights of the single-workgroup network kernel
     size_t pc_wn_len = 0;              // its length in shorts
+    float* pc_Y = nullptr;             // coarse network outputs of the current cycle (+ a combine slot)
+    int pc_slots = 0;
 };
 
 namespace rte {
 int ensure_krylov(rte_ctx* c, int m, bool need_z);
 int apply_channels(rte_ctx* c, int mode, int prec, const double* x, const double* b, double* y, int nbatch);
+int apply_channels_pc(rte_ctx* c, const double* v, double* y, const float* Y);
 int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
                double* rec, int max_rec, int* nrec);
 int autotune_2d(rte_ctx* c, int reps, bool use_cache);

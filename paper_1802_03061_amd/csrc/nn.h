@@ -6,4 +6,13 @@ namespace rte {
 // z = v + ||v|| N(v / ||v||) on one channel vector (FP64 in/out, BF16 x BF16 -> FP32 inside).
 int pc_apply(rte_ctx* c, const double* v, double* z);
 void pc_free(rte_ctx* c);
+
+// Flexible GMRES without a stored Z basis: z_j = v_j + s P y_j is formed inside the apply from the
+// coarse network output y_j (slot j), with s = 1 / sqrt(nvec) for the unit-norm v_j.
+size_t pc_coarse_len(const rte_ctx* c);
+int pc_begin_solve(rte_ctx* c, int m);                 // slots for m columns, s in c->pc_st
+void pc_scale_pool(rte_ctx* c, const double* w, double* v, const double* a_dev, double a_host);  // v = a w + pool
+int pc_net_slot(rte_ctx* c, int j);                    // Y_j = N(pooled v_j / s)
+const float* pc_slot(const rte_ctx* c, int j);
+void pc_add_correction(rte_ctx* c, double* x, const double* y_dev, int k);  // x += s P sum y_j Y_j
 }  // namespace rte

@@ -412,6 +412,61 @@ __global__ __launch_bounds__(256) void k_prolong_add(const double* __restrict__ 
     z[i] = v[i] + s * (double)((1.f - ay) * top + ay * bot);
 }
 
+// v = a w (a = *a_dev, or a_host when a_dev is NULL; in place allowed) and the F x F block means of
+// v into coarse[c][I][J] (FP32).  One block per (channel, coarse row I, chunk of CW = max(F, 64)
+// columns); 256 threads = CW columns x (256 / CW) row groups, so a block owns its coarse cells.
+__global__ __launch_bounds__(256) void k_scale_pool(const double* __restrict__ w, double* __restrict__ v,
+                                                    const double* __restrict__ a_dev, double a_host,
+                                                    float* __restrict__ coarse, int ny, int nx, int F) {
+    __shared__ double part[256];
+    const int CW = F > 64 ? F : 64;
+    const int RG = 256 / CW;                       // row groups
+    const int nchunk = (nx + CW - 1) / CW;
+    const int Hc = ny / F, Wc = nx / F;
+    const int chunk = blockIdx.x % nchunk;
+    const int I = (blockIdx.x / nchunk) % Hc;
+    const int c = blockIdx.x / (nchunk * Hc);
+    const double a = a_dev ? *a_dev : a_host;
+    const int col = threadIdx.x % CW, rg = threadIdx.x / CW;
+    const int x = chunk * CW + col;
+    const int rows = (F + RG - 1) / RG;
+    double s = 0.0;
+    if (x < nx) {
+#pragma unroll 8
+        for (int u = 0; u < rows; ++u) {
+            const int r = rg * rows + u;
+            if (r < F) {
+                const size_t o = ((size_t)c * ny + I * F + r) * nx + x;
+                const double val = a * w[o];
+                v[o] = val;
+                s += val;
+            }
+        }
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    // coarse cells of this chunk: J = chunk * CW / F + q, q < CW / F
+    const int ncell = CW / F;
+    for (int q = threadIdx.x; q < ncell; q += 256) {
+        const int J = chunk * ncell + q;
+        if (J >= Wc) continue;
+        double t = 0.0;
+        for (int g = 0; g < RG; ++g)
+            for (int cc = 0; cc < F; ++cc) t += part[g * CW + q * F + cc];
+        coarse[((size_t)c * Hc + I) * Wc + J] = (float)(t / ((double)F * F));
+    }
+}
+
+// out[i] = sum_{j < k} y_j Y[j][i] over one coarse vector of n entries (y FP64 on the device).
+__global__ void k_coarse_combine(const float* __restrict__ Y, const double* __restrict__ y, int k, int n,
+                                 float* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double t = 0.0;
+    for (int j = 0; j < k; ++j) t += y[j] * (double)Y[(size_t)j * n + i];
+    out[i] = (float)t;
+}
+
 // Training pair normalisation (single block): s^2 = |r|^2 / n (fine grid); x = xr/s, t = xt/s,
 // w = F^2 s^2 / |e|^2 (|r|^2 in r2, |e|^2 in e2, both on the device).
 __global__ __launch_bounds__(256) void k_pair_finish(float* __restrict__ xr, float* __restrict__ xt, int nco,
@@ -577,7 +632,85 @@ void pc_free(rte_ctx* c) {
     nfree(c->pc_meta);
     nfree(c->pc_wn);
     c->pc_wn_len = 0;
+    nfree(c->pc_Y);
+    c->pc_slots = 0;
     c->pc_attached = false;
+}
+
+// The network on the coarse input c->pc_coarse (already the F x F block means of a unit-norm v,
+// so s = 1 / sqrt(nvec) is in c->pc_st) into out [C][Hc][Wc].
+static int pc_net(rte_ctx* c, float* out) {
+    NetShape sh;
+    sh.init(c->C, c->pc_hidden, c->pc_layers);
+    const int F = c->pc_factor;
+    const int Hc = c->ny / F, Wc = c->nx / F;
+    hipStream_t st = c->stream;
+    const unsigned short* wf = (const unsigned short*)c->pc_w;
+    if (c->pc_wn) {
+        const size_t lds = fused_net_lds(sh, Hc, Wc);
+        const int nwn = (int)c->pc_wn_len;
+        if (c->pc_hidden == 32)
+            hipLaunchKernelGGL((k_net_fused<32>), dim3(1), dim3(NET_THREADS), lds, st, c->pc_coarse, c->pc_st + 1,
+                               c->pc_wn, nwn, c->pc_b, c->pc_meta, sh.layers, c->C, Hc, Wc, out);
+        else
+            hipLaunchKernelGGL((k_net_fused<16>), dim3(1), dim3(NET_THREADS), lds, st, c->pc_coarse, c->pc_st + 1,
+                               c->pc_wn, nwn, c->pc_b, c->pc_meta, sh.layers, c->C, Hc, Wc, out);
+    } else {
+        const float* a = c->pc_coarse;
+        float* bufs[2] = {c->pc_act0, c->pc_act1};
+        for (int l = 0; l < sh.layers; ++l) {
+            const bool last = l == sh.layers - 1;
+            float* o = last ? out : bufs[l & 1];
+            if (conv_launch(sh.cin[l], a, wf + sh.pf_off[l], c->pc_b + sh.boff[l], sh.cout[l], o, nullptr, nullptr, !last,
+                            l == 0 ? c->pc_st + 1 : nullptr, 1, Hc, Wc, st))
+                return set_error(RTE_EUNSUPPORTED, "unsupported convolution width");
+            a = o;
+        }
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RTE_OK : set_hip_error(e, "pc_net", __FILE__, __LINE__);
+}
+
+size_t pc_coarse_len(const rte_ctx* c) {
+    return (size_t)c->C * (c->ny / c->pc_factor) * (c->nx / c->pc_factor);
+}
+
+int pc_begin_solve(rte_ctx* c, int m) {
+    const size_t nco = pc_coarse_len(c);
+    if (c->pc_slots < m + 1) {
+        nfree(c->pc_Y);
+        c->pc_slots = 0;
+        int rc = nalloc(&c->pc_Y, (size_t)(m + 2) * nco);
+        if (rc) return rc;
+        c->pc_slots = m + 1;
+    }
+    // s = RMS of a unit-norm vector = 1 / sqrt(nvec); the combine slot is pc_Y[m + 1]
+    const float st[4] = {(float)(1.0 / std::sqrt((double)c->nvec)), (float)std::sqrt((double)c->nvec), 0.f, 0.f};
+    hipError_t e = hipMemcpyAsync(c->pc_st, st, sizeof(st), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);   // st lives on the host stack
+    return e == hipSuccess ? RTE_OK : set_hip_error(e, "pc_begin_solve", __FILE__, __LINE__);
+}
+
+void pc_scale_pool(rte_ctx* c, const double* w, double* v, const double* a_dev, double a_host) {
+    const int F = c->pc_factor;
+    const int CW = F > 64 ? F : 64;
+    const int nchunk = (c->nx + CW - 1) / CW;
+    hipLaunchKernelGGL(k_scale_pool, dim3(c->C * (c->ny / F) * nchunk), dim3(256), 0, c->stream, w, v, a_dev, a_host,
+                       c->pc_coarse, c->ny, c->nx, F);
+}
+
+int pc_net_slot(rte_ctx* c, int j) { return pc_net(c, c->pc_Y + (size_t)j * pc_coarse_len(c)); }
+
+const float* pc_slot(const rte_ctx* c, int j) { return c->pc_Y + (size_t)j * pc_coarse_len(c); }
+
+// x += s P (sum_{j < k} y_j Y_j) with y on the device.
+void pc_add_correction(rte_ctx* c, double* x, const double* y_dev, int k) {
+    const size_t nco = pc_coarse_len(c);
+    float* comb = c->pc_Y + (size_t)(c->pc_slots) * nco;
+    hipLaunchKernelGGL(k_coarse_combine, dim3((unsigned)((nco + 255) / 256)), dim3(256), 0, c->stream, c->pc_Y, y_dev, k,
+                       (int)nco, comb);
+    hipLaunchKernelGGL(k_prolong_add, dim3((c->nx + 255) / 256, c->C * c->ny), dim3(256), 0, c->stream, x, comb,
+                       c->pc_st, x, c->C, c->ny, c->nx, c->pc_factor);
 }
 
 int pc_apply(rte_ctx* c, const double* v, double* z) {
@@ -634,6 +767,7 @@ int rte_pc_attach(rte_ctx* c, const float* weights, int hidden, int layers, int 
     if (!valid_net(c->C, hidden, layers)) return set_error(RTE_EINVAL, "bad network shape");
     if (factor < 1 || c->nx % factor || c->ny % factor) return set_error(RTE_EINVAL, "factor must divide n_x and n_y");
     if (c->nx > 512) return set_error(RTE_EUNSUPPORTED, "grid too wide for the restriction kernel");
+    if (factor > 256) return set_error(RTE_EUNSUPPORTED, "coarsening factor above 256");
     NetShape sh;
     sh.init(c->C, hidden, layers);
     const int Hc = c->ny / factor, Wc = c->nx / factor;

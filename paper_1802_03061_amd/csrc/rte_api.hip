@@ -228,6 +228,23 @@ int apply_channels(rte_ctx* c, int mode, int prec, const double* x, const double
     return apply_t<double>(c, mode, x, b, y, nbatch, nullptr);
 }
 
+// y = A (v + s P Y) in the context precision, the coarse correction added inside passes A and C.
+template <typename T>
+static int apply_pc_t(rte_ctx* c, const double* v, double* y, const float* Y) {
+    const ChanScale sc = channel_scale(c, APPLY_A);
+    Apply2DArgs<T> a = args2d<T>(c);
+    a.pack = 1;
+    a.corr = Y;
+    a.cF = c->pc_factor;
+    a.cs = 1.0 / std::sqrt((double)c->nvec);
+    if (apply2d<T>(a, v, nullptr, y, APPLY_A, sc, 1)) return set_error(RTE_EUNSUPPORTED, "apply: unsupported size");
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RTE_OK : set_hip_error(e, "apply launch", __FILE__, __LINE__);
+}
+int apply_channels_pc(rte_ctx* c, const double* v, double* y, const float* Y) {
+    return c->prec == RTE_PREC_FP32 ? apply_pc_t<float>(c, v, y, Y) : apply_pc_t<double>(c, v, y, Y);
+}
+
 // ------------------------------------------------------------------ autotuning -----------------
 // Every pass of the 2D apply has a few kernel variants with the same arithmetic (different row
 // tiles, thread counts, FFT grouping).  The tuner times each variant of each pass on the
@@ -325,8 +342,9 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
     const int m = c->opts.restart;
     const bool use_pc = c->pc_attached && c->opts.use_pc;
     const bool mixed = c->prec == RTE_PREC_FP32;
-    int rc = ensure_krylov(c, m, use_pc);
+    int rc = ensure_krylov(c, m, false);
     if (rc) return rc;
+    if (use_pc && (rc = pc_begin_solve(c, m))) return rc;
     if (nrec) *nrec = 0;
     rte_solve_info inf;
     memset(&inf, 0, sizeof(inf));
@@ -370,7 +388,9 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
         ++cycles;
         double target = 0.5 * tol * bn;
         if (mixed) target = std::max(target, c->opts.inner_tol * rn);
-        vec_scale(c->V, c->rv, 1.0 / rn, n, st);
+        // v_0 = r / rn (with the pooled coarse input of the network when preconditioning)
+        if (pc_live) pc_scale_pool(c, c->rv, c->V, nullptr, 1.0 / rn);
+        else vec_scale(c->V, c->rv, 1.0 / rn, n, st);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = rn;
         RTE_HIP_TRY(hipMemcpyAsync(dg, g.data(), (m + 1) * sizeof(double), hipMemcpyHostToDevice, st));
@@ -385,17 +405,13 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
         for (int j = 0; j < m && it + launched < max_iter && !stop; ++j) {
             double* vj = c->V + (size_t)j * n;
             double* w = c->V + (size_t)(j + 1) * n;
-            const double* zj = vj;
-            if (use_pc) {
-                double* z = c->Z + (size_t)j * n;
-                if (pc_live) {
-                    if ((rc = pc_apply(c, vj, z))) return rc;
-                } else {
-                    RTE_HIP_TRY(hipMemcpyAsync(z, vj, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-                }
-                zj = z;
+            // flexible GMRES: w = A z_j with z_j = v_j + s P Y_j formed inside the apply
+            if (pc_live) {
+                if ((rc = pc_net_slot(c, j))) return rc;
+                if ((rc = apply_channels_pc(c, vj, w, pc_slot(c, j)))) return rc;
+            } else if ((rc = apply_channels(c, APPLY_A, c->prec, vj, nullptr, w, 1))) {
+                return rc;
             }
-            if ((rc = apply_channels(c, APPLY_A, c->prec, zj, nullptr, w, 1))) return rc;
             ++inf.applies;
             double* sd = c->dsmall;
             krylov_dots(c->V, n, j + 1, w, n, c->partial, sd, true, st);
@@ -406,7 +422,8 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
                 krylov_update(w, c->V, n, j + 1, sd + m + 4, n, c->partial, sd + j + 2, st, dfl);
             }
             arnoldi_step(1, j, m, sd, dH, dcs, dsn, dg, dest, dinv, dfl, c->opts.reorth, st);
-            vec_scale_dev(w, w, dinv + j + 1, n, st);
+            if (pc_live) pc_scale_pool(c, w, w, dinv + j + 1, 0.0);
+            else vec_scale_dev(w, w, dinv + j + 1, n, st);
             RTE_HIP_TRY(hipMemcpyAsync(hp + j, dest + j, sizeof(double), hipMemcpyDeviceToHost, st));
             RTE_HIP_TRY(hipMemcpyAsync(hfl + 2 * j, dfl + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
             RTE_HIP_TRY(hipEventRecord(c->ev_iter[j], st));
@@ -455,14 +472,16 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
                     RTE_HIP_TRY(hipMemcpyAsync(c->dsmall, yv.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
                     double* xr = rec + (size_t)(k - 1) * n;
                     vec_fill(xr, 0.0, n, st);
-                    krylov_combine(xr, use_pc ? c->Z : c->V, n, k, c->dsmall, n, st);
+                    krylov_combine(xr, c->V, n, k, c->dsmall, n, st);
+                    if (pc_live) pc_add_correction(c, xr, c->dsmall, k);
                     RTE_HIP_TRY(hipStreamSynchronize(st));
                 }
                 if (nrec) *nrec = nr;
             }
             back_solve(H, m + 1, g, jd, yv);
             RTE_HIP_TRY(hipMemcpyAsync(c->dsmall, yv.data(), jd * sizeof(double), hipMemcpyHostToDevice, st));
-            krylov_combine(x, use_pc ? c->Z : c->V, n, jd, c->dsmall, n, st);
+            krylov_combine(x, c->V, n, jd, c->dsmall, n, st);
+            if (pc_live) pc_add_correction(c, x, c->dsmall, jd);
         }
         // true residual with the FP64 apply
         if ((rc = apply_channels(c, APPLY_RESID, RTE_PREC_FP64, x, b, c->rv, 1))) return rc;

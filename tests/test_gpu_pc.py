@@ -239,3 +239,34 @@ def test_pc_apply_matches_oracle(rte, L, n, F):
     assert e <= 3e-2
     ctx.close()
     net.close()
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_fgmres_with_network_matches_lu(rte, prec):
+    """Flexible GMRES with an attached (untrained, bias-free) network forms z_j = v_j + s P N(R v_j/s)
+    inside the apply and updates x with V y plus one prolongation of the combined coarse outputs;
+    whatever the network, the solution is the discrete system's: it matches the oracle's dense LU
+    solution (32^2, L = 2, F = 4)."""
+    say("fgmres vs LU prec", prec)
+    from oracle import krylov as kr
+    from oracle import operator2d as op2
+    n, L, F = 32, 2, 4
+    mu_a, mu_s = 0.1, 4.0
+    sh = inputs.hg_sigma_hat(0.5, L)
+    f = inputs.gaussian_mixture_source(n, inputs.gaussian_mixture_params(np.random.default_rng(7), 2))
+    ctx = rte.Context(n, mu_a=mu_a, mu_s=mu_s, sigma_hat=sh, L=L, prec=prec)
+    net = rte.Net(ctx.channels, 32, 5, seed=3, use_bias=False)
+    scaled = net.params() * 0.05
+    ctx.attach_pc(scaled, factor=F)
+    u, info = ctx.solve(dev(f), tol=1e-11)
+    say("  info", info)
+    h, mu_t = 1.0 / n, mu_a + mu_s
+    A = op2.dense_A(n, n, L, h, mu_t, mu_s, sh)
+    b = op2.rhs(f, L, h, mu_t, method="direct")
+    x = kr.solve_dense(A, b.reshape(-1)).reshape(b.shape)
+    e = relerr(host(u), x)
+    say("  vs LU", e)
+    assert info["pc_used"] == 1 and info["pc_fallback"] == 0
+    assert e <= 1e-9
+    ctx.close()
+    net.close()
