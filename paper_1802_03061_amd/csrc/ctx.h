@@ -65,6 +65,8 @@ struct rte_ctx {
     int* pc_meta = nullptr;     // per layer: cin, cout, tap-major pack offset, bias offset
     unsigned short* pc_wn = nullptr;   // tap-major BF16 weights of the single-workgroup network kernel
     size_t pc_wn_len = 0;              // its length in shorts
+    float* pc_bn = nullptr;            // biases of every layer, contiguous (fused kernel)
+    int pc_nbias = 0;
     float* pc_Y = nullptr;             // coarse network outputs of the current cycle (+ a combine slot)
     int pc_slots = 0;
 };

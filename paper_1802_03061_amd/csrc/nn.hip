@@ -299,56 +299,117 @@ __global__ void k_pack_tapmajor(const unsigned short* __restrict__ wf, int cin, 
     }
 }
 
+// One output row y of a layer: D[32 out][32 columns] = W[32][9 CP] x B[9 CP][32] on MFMA, the
+// reduction walked tap by tap (t = 3 dy + dx) and, within a tap, 8 channels per MFMA, so every
+// LDS address is a base plus an immediate offset.  Lanes past the row edge read a valid pixel
+// (their outputs are discarded).
+template <int CP>
+__device__ __forceinline__ f32x16 net_row(const unsigned short* __restrict__ Wl, const unsigned short* __restrict__ src,
+                                          int y, int j, int hi, int Wc) {
+    constexpr int KS = net_ks(CP);
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    const int jj = j < Wc ? j : Wc - 1;
+    const unsigned short* arow = Wl + j * KS + 4 * hi;
+    const unsigned short* brow = src + ((size_t)y * (Wc + 2) + jj) * NET_PS + 4 * hi;
+#pragma unroll 1
+    for (int dy = 0; dy < 3; ++dy) {
+        const unsigned short* bd = brow + dy * (Wc + 2) * NET_PS;
+        const unsigned short* ad = arow + 3 * dy * CP;
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+#pragma unroll
+            for (int cb = 0; cb < CP / 8; ++cb) {
+                const bf16x4 a = *reinterpret_cast<const bf16x4*>(ad + dx * CP + cb * 8);
+                const bf16x4 bv = *reinterpret_cast<const bf16x4*>(bd + dx * NET_PS + cb * 8);
+                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bv, acc, 0, 0, 0);
+            }
+        }
+    }
+    return acc;
+}
+
 template <int HID>
 __global__ __launch_bounds__(NET_THREADS) void k_net_fused(const float* __restrict__ in, const float* __restrict__ in_scale,
                                                            const unsigned short* __restrict__ wn, int nwn,
-                                                           const float* __restrict__ params, const int* __restrict__ meta,
-                                                           int layers, int C, int Hc, int Wc, float* __restrict__ out) {
-    // meta: per layer [cin, cout, tap-major pack offset, bias offset]; nwn: pack length (multiple of 8)
+                                                           const float* __restrict__ bias_all, int nbias,
+                                                           const int* __restrict__ meta, int layers, int C, int Hc,
+                                                           int Wc, float* __restrict__ out) {
+    // meta: per layer [cin, cout, tap-major pack offset, bias offset into bias_all]; nwn: pack length
+    // (multiple of 8 shorts); all of it is staged in LDS first, with every global load of the
+    // prologue in flight together (the kernel is latency-bound: one workgroup).
     static_assert(HID <= 32 && NET_PS >= 32 + 4, "pixel stride");
     extern __shared__ __attribute__((aligned(16))) unsigned short lds[];
+    __shared__ int smeta[4 * 8];
+    __shared__ float sbias[8 * 32];
     const int P = (Hc + 2) * (Wc + 2);
-    unsigned short* act[2] = {lds, lds + (size_t)P * NET_PS};
+    unsigned short* const act0 = lds;
+    unsigned short* const act1 = lds + (size_t)P * NET_PS;
     unsigned short* Wall = lds + (size_t)2 * P * NET_PS;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const float sc = *in_scale;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
     {
         const uint4* ws = reinterpret_cast<const uint4*>(wn);
         uint4* wd = reinterpret_cast<uint4*>(Wall);
-        for (int idx = threadIdx.x; idx < nwn / 8; idx += NET_THREADS) wd[idx] = ws[idx];
+        const int nw4 = nwn / 8;
+        const int nin = C * Hc * Wc;
+        constexpr int U = 8;
+        const uint4 zero4 = {0u, 0u, 0u, 0u};
+        for (int base = 0; base < nw4; base += U * NET_THREADS) {
+            uint4 r[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = base + tid + u * NET_THREADS;
+                r[u] = idx < nw4 ? ws[idx] : zero4;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = base + tid + u * NET_THREADS;
+                if (idx < nw4) wd[idx] = r[u];
+            }
+        }
+        if (tid < 4 * layers) smeta[tid] = meta[tid];
+        if (tid < nbias) sbias[tid] = bias_all[tid];
         uint4* az = reinterpret_cast<uint4*>(lds);
         const uint4 zero = {0u, 0u, 0u, 0u};
-        for (int idx = threadIdx.x; idx < 2 * P * NET_PS / 8; idx += NET_THREADS) az[idx] = zero;
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < C * Hc * Wc; idx += NET_THREADS) {
-        const int c = idx / (Hc * Wc), r = idx % (Hc * Wc);
-        const int y = r / Wc, x = r % Wc;
-        act[0][((y + 1) * (Wc + 2) + x + 1) * NET_PS + c] = f2bf(in[idx] * sc);
+        for (int idx = tid; idx < 2 * P * NET_PS / 8; idx += NET_THREADS) az[idx] = zero;
+        const float sc = *in_scale;
+        __syncthreads();   // the zero fill of the activations is complete
+        for (int base = 0; base < nin; base += U * NET_THREADS) {
+            float xin[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = base + tid + u * NET_THREADS;
+                xin[u] = idx < nin ? in[idx] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = base + tid + u * NET_THREADS;
+                if (idx < nin) {
+                    const int c = idx / (Hc * Wc), r = idx % (Hc * Wc);
+                    const int y = r / Wc, x = r % Wc;
+                    act0[((y + 1) * (Wc + 2) + x + 1) * NET_PS + c] = f2bf(xin[u] * sc);
+                }
+            }
+        }
     }
     __syncthreads();
     const int j = lane & 31, hi = lane >> 5;
     for (int l = 0; l < layers; ++l) {
-        const int cin = meta[4 * l], cout = meta[4 * l + 1];
-        const unsigned short* Wl = Wall + meta[4 * l + 2];
-        const float* bias = params + meta[4 * l + 3];
+        const int cin = smeta[4 * l], cout = smeta[4 * l + 1];
+        const unsigned short* Wl = Wall + smeta[4 * l + 2];
+        const float* bias = sbias + smeta[4 * l + 3];
         const bool last = l == layers - 1;
-        const int CP = net_cp(cin), K = 9 * CP, KS = net_ks(cin);
-        const unsigned short* src = act[l & 1];
-        unsigned short* dst = act[(l + 1) & 1];
+        const int CP = net_cp(cin);
+        const unsigned short* src = (l & 1) ? act1 : act0;
+        unsigned short* dst = (l & 1) ? act0 : act1;
         for (int y = wave; y < Hc; y += NET_THREADS / 64) {
             f32x16 acc;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-            const int jj = j < Wc ? j : Wc - 1;      // lanes past the row edge read a valid pixel, masked below
-            for (int kb = 0; kb < K / 8; ++kb) {
-                const int k0 = kb * 8 + 4 * hi;
-                const int t = k0 / CP, c0 = k0 % CP;
-                const bf16x4 a = *reinterpret_cast<const bf16x4*>(Wl + j * KS + k0);
-                const int pix = (y + t / 3) * (Wc + 2) + jj + t % 3;
-                const bf16x4 bv = *reinterpret_cast<const bf16x4*>(src + pix * NET_PS + c0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bv, acc, 0, 0, 0);
-            }
+            if (CP == 32) acc = net_row<32>(Wl, src, y, j, hi, Wc);
+            else if (CP == 24) acc = net_row<24>(Wl, src, y, j, hi, Wc);
+            else if (CP == 16) acc = net_row<16>(Wl, src, y, j, hi, Wc);
+            else acc = net_row<8>(Wl, src, y, j, hi, Wc);
             if (j < Wc) {
                 const int pix = (y + 1) * (Wc + 2) + j + 1;
 #pragma unroll
@@ -544,7 +605,8 @@ static size_t fused_net_lds(const NetShape& sh, int Hc, int Wc) {
     return ((size_t)2 * (Hc + 2) * (Wc + 2) * NET_PS + tapmajor_len(sh)) * 2;
 }
 static bool fused_net_fits(const NetShape& sh, int Hc, int Wc) {
-    return Hc <= 32 && Wc <= 32 && fused_net_lds(sh, Hc, Wc) <= 160 * 1024;
+    // dynamic LDS plus the kernel's static meta and bias arrays within the 160 KiB of a workgroup
+    return Hc <= 32 && Wc <= 32 && fused_net_lds(sh, Hc, Wc) <= 156 * 1024;
 }
 
 static bool valid_net(int C, int hidden, int layers) {
@@ -631,7 +693,9 @@ void pc_free(rte_ctx* c) {
     nfree(c->pc_part);
     nfree(c->pc_meta);
     nfree(c->pc_wn);
+    nfree(c->pc_bn);
     c->pc_wn_len = 0;
+    c->pc_nbias = 0;
     nfree(c->pc_Y);
     c->pc_slots = 0;
     c->pc_attached = false;
@@ -651,10 +715,10 @@ static int pc_net(rte_ctx* c, float* out) {
         const int nwn = (int)c->pc_wn_len;
         if (c->pc_hidden == 32)
             hipLaunchKernelGGL((k_net_fused<32>), dim3(1), dim3(NET_THREADS), lds, st, c->pc_coarse, c->pc_st + 1,
-                               c->pc_wn, nwn, c->pc_b, c->pc_meta, sh.layers, c->C, Hc, Wc, out);
+                               c->pc_wn, nwn, c->pc_bn, c->pc_nbias, c->pc_meta, sh.layers, c->C, Hc, Wc, out);
         else
             hipLaunchKernelGGL((k_net_fused<16>), dim3(1), dim3(NET_THREADS), lds, st, c->pc_coarse, c->pc_st + 1,
-                               c->pc_wn, nwn, c->pc_b, c->pc_meta, sh.layers, c->C, Hc, Wc, out);
+                               c->pc_wn, nwn, c->pc_bn, c->pc_nbias, c->pc_meta, sh.layers, c->C, Hc, Wc, out);
     } else {
         const float* a = c->pc_coarse;
         float* bufs[2] = {c->pc_act0, c->pc_act1};
@@ -730,10 +794,10 @@ int pc_apply(rte_ctx* c, const double* v, double* z) {
         const int nwn = (int)c->pc_wn_len;
         if (c->pc_hidden == 32)
             hipLaunchKernelGGL((k_net_fused<32>), dim3(1), dim3(NET_THREADS), lds, st, c->pc_coarse, c->pc_st + 1,
-                               c->pc_wn, nwn, c->pc_b, c->pc_meta, sh.layers, c->C, Hc, Wc, c->pc_act0);
+                               c->pc_wn, nwn, c->pc_bn, c->pc_nbias, c->pc_meta, sh.layers, c->C, Hc, Wc, c->pc_act0);
         else
             hipLaunchKernelGGL((k_net_fused<16>), dim3(1), dim3(NET_THREADS), lds, st, c->pc_coarse, c->pc_st + 1,
-                               c->pc_wn, nwn, c->pc_b, c->pc_meta, sh.layers, c->C, Hc, Wc, c->pc_act0);
+                               c->pc_wn, nwn, c->pc_bn, c->pc_nbias, c->pc_meta, sh.layers, c->C, Hc, Wc, c->pc_act0);
         a = c->pc_act0;
     } else {
         // ping-pong activations: layer l writes act[(l % 2)]
@@ -789,19 +853,29 @@ int rte_pc_attach(rte_ctx* c, const float* weights, int hidden, int layers, int 
     pack_all(sh, weights, wf, nullptr, c->stream);
     std::vector<int> toff;
     const size_t tlen = tapmajor_len(sh, &toff);
+    std::vector<int> boff_packed(layers);
+    int nbias = 0;
+    for (int l = 0; l < layers; ++l) { boff_packed[l] = nbias; nbias += sh.cout[l]; }
     if (fused_net_fits(sh, Hc, Wc)) {
-        if ((rc = nalloc(&c->pc_wn, tlen))) { pc_free(c); return rc; }
+        if ((rc = nalloc(&c->pc_wn, tlen)) || (rc = nalloc(&c->pc_bn, (size_t)nbias))) { pc_free(c); return rc; }
         c->pc_wn_len = tlen;
-        for (int l = 0; l < layers; ++l)
+        c->pc_nbias = nbias;
+        for (int l = 0; l < layers; ++l) {
             hipLaunchKernelGGL(k_pack_tapmajor, dim3(64), dim3(256), 0, c->stream, wf + sh.pf_off[l], sh.cin[l],
                                c->pc_wn + toff[l]);
+            e = hipMemcpyAsync(c->pc_bn + boff_packed[l], weights + sh.boff[l], sh.cout[l] * sizeof(float),
+                               hipMemcpyDeviceToDevice, c->stream);
+            if (e != hipSuccess) { pc_free(c); return set_hip_error(e, "pc biases", __FILE__, __LINE__); }
+        }
     }
+    // meta: cin, cout, tap-major pack offset, bias offset (into the packed biases of the fused
+    // kernel when it is used, else into the full parameter copy)
     std::vector<int> meta(4 * layers);
     for (int l = 0; l < layers; ++l) {
         meta[4 * l] = sh.cin[l];
         meta[4 * l + 1] = sh.cout[l];
         meta[4 * l + 2] = toff[l];
-        meta[4 * l + 3] = (int)sh.boff[l];
+        meta[4 * l + 3] = c->pc_wn ? boff_packed[l] : (int)sh.boff[l];
     }
     e = hipMemcpyAsync(c->pc_meta, meta.data(), meta.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
