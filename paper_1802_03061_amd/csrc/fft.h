@@ -6,8 +6,10 @@
 // registers, and writing the R results spaced Ns apart.  The result comes out in natural order.
 // Stages run in place in LDS: every thread first reads and transforms all its butterflies into
 // registers, a barrier, then writes.  Radices are 8 (with one leading 2 or 4 stage when
-// log2 P is not a multiple of 3).  Twiddles come from a table tw[q] = exp(-2 pi i q / P)
-// computed in FP64 on the host, rounded to the working precision and staged into LDS.
+// log2 P is not a multiple of 3).  Twiddles come from a table computed in FP64 on the host,
+// rounded to the working precision and staged into LDS, laid out per stage: the R-1 factors of
+// butterfly k of the stage with sub-length Ns are contiguous at stage_tw_offset(P, Ns) +
+// k (R-1), so the lanes of a wave read consecutive 56-byte runs (no bank conflicts).
 //
 // LDS layout: element i of a transform lives at sw(i) = i + i/16, i.e. one pad slot per 16
 // elements.  The strided writes of the early stages (stride R or Ns elements) then fall on
@@ -23,6 +25,18 @@ constexpr int padded(int P) { return P + P / 16; }
 constexpr int fft_radix(int P, int Ns) {
     // log2 of what remains to be combined
     return (ilog2(P) - ilog2(Ns)) % 3 == 1 ? 2 : ((ilog2(P) - ilog2(Ns)) % 3 == 2 ? 4 : 8);
+}
+
+// Offset of the twiddles of the stage with sub-transform length NS (> 1) in the per-stage table;
+// the table holds sum over those stages of NS (R - 1) = P - (first radix) entries.
+constexpr int stage_tw_offset(int P, int NS) {
+    int off = 0, ns = 1;
+    while (ns < NS) {
+        const int R = fft_radix(P, ns);
+        if (ns > 1) off += ns * (R - 1);
+        ns *= R;
+    }
+    return off;
 }
 
 template <typename T, bool INV>
@@ -73,7 +87,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* tw, int tid) 
     constexpr int TOTAL = NB * NFFT;
     constexpr int ITEMS = (TOTAL + NTHR - 1) / NTHR;
     constexpr int S = NS * R;
-    constexpr int TWSTEP = P / S;
+    constexpr int TWOFF = stage_tw_offset(P, NS);
     cx<T> v[ITEMS][R];
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
@@ -87,7 +101,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* tw, int tid) 
                 const int k = j % NS;
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    cx<T> w = tw[k * r * TWSTEP];
+                    cx<T> w = tw[TWOFF + k * (R - 1) + (r - 1)];
                     if (INV) w.im = -w.im;
                     v[it][r] = v[it][r] * w;
                 }

@@ -95,22 +95,39 @@ double self_cell_3d(double h, double mu_t) {
     return 6.0 / (4.0 * pi) * 4.0 * s;
 }
 
-// exp(-2 pi i q / P), q = 0..P-1: long-double angle, rounded to FP64; exact at the quarter points.
+// The twiddle table of the length-P LDS FFT (fft.h), in its per-stage layout: for every Stockham
+// stage after the first (sub-transform length NS, radix R), the factors exp(-2 pi i k r / (NS R))
+// for k < NS, r = 1..R-1 at stage_tw_offset(P, NS) + k (R - 1) + (r - 1).  The angle is computed
+// in long double from the exact integer fraction (k r mod NS R) / (NS R), rounded to FP64, with
+// the quarter points exact.
 void twiddles(int P, std::vector<double>& re, std::vector<double>& im) {
-    re.resize(P);
-    im.resize(P);
+    re.assign(P, 0.0);
+    im.assign(P, 0.0);
     const long double pi = 3.141592653589793238462643383279502884L;
-    for (int q = 0; q < P; ++q) {
-        long double ang = -2.0L * pi * (long double)q / (long double)P;
-        re[q] = (double)std::cos(ang);
-        im[q] = (double)std::sin(ang);
-    }
-    // exact values at the quarter points
-    for (int q = 0; q < P; q += (P >= 4 ? P / 4 : P)) {
-        int quarter = P >= 4 ? q / (P / 4) : 0;
-        const double rv[4] = {1, 0, -1, 0}, iv[4] = {0, -1, 0, 1};
-        re[q] = rv[quarter];
-        im[q] = iv[quarter];
+    int ns = 1, off = 0;
+    while (ns < P) {
+        const int R = fft_radix(P, ns);
+        if (ns > 1) {
+            const int S = ns * R;
+            for (int k = 0; k < ns; ++k)
+                for (int r = 1; r < R; ++r) {
+                    const int q = (k * r) % S;
+                    double cr, ci;
+                    if (4 * q == 0) { cr = 1; ci = 0; }
+                    else if (4 * q == S) { cr = 0; ci = -1; }
+                    else if (4 * q == 2 * S) { cr = -1; ci = 0; }
+                    else if (4 * q == 3 * S) { cr = 0; ci = 1; }
+                    else {
+                        const long double ang = -2.0L * pi * (long double)q / (long double)S;
+                        cr = (double)std::cos(ang);
+                        ci = (double)std::sin(ang);
+                    }
+                    re[off + k * (R - 1) + (r - 1)] = cr;
+                    im[off + k * (R - 1) + (r - 1)] = ci;
+                }
+            off += ns * (R - 1);
+        }
+        ns *= R;
     }
 }
 
