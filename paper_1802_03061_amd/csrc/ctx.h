@@ -46,6 +46,8 @@ struct rte_ctx {
     int* arn_flags = nullptr;   // [second pass, breakdown, non-finite, spare]
     double* hpipe = nullptr;    // pinned per-iteration residual estimates
     int* hpipe_flags = nullptr; // pinned per-iteration (breakdown, non-finite)
+    double* hpipe_dev = nullptr;     // device addresses of the two (mapped) host arrays above
+    int* hpipe_flags_dev = nullptr;
     std::vector<hipEvent_t> ev_iter;
     rte_solve_opts opts{};
     // kernel variants of the 2D apply passes A, B, C (FP32 and FP64 applies), set by the autotuner

@@ -17,8 +17,11 @@ void krylov_update(double* w, const double* V, size_t ld, int nvec, const double
                    double* norm_out, hipStream_t st, const int* active = nullptr);
 void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hipStream_t st);
 // Device-side Arnoldi bookkeeping for column j (see k_arnoldi in krylov.hip).
+// stage 1 also writes the iteration's estimate and (breakdown, non-finite) flags to est_out and
+// flags_out (device-visible host memory, may be NULL) for the host's convergence check.
 void arnoldi_step(int stage, int j, int m, double* st, double* H, double* cs, double* sn, double* g, double* est,
-                  double* inv, int* flags, int reorth, hipStream_t s);
+                  double* inv, int* flags, int reorth, hipStream_t s, double* est_out = nullptr,
+                  int* flags_out = nullptr);
 // x += sum_v y[v] Z_v (y on the device)
 void krylov_combine(double* x, const double* Z, size_t ld, int nvec, const double* y, size_t n, hipStream_t st);
 void vec_scale(double* dst, const double* src, double a, size_t n, hipStream_t st);

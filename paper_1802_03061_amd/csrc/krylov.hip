@@ -128,7 +128,8 @@ __global__ __launch_bounds__(KT) void k_scale_dev(double* __restrict__ dst, cons
 // st layout: [0..m] h pass 1 | [m+1] |w|^2 | [m+2] |w1|^2 | [m+4..2m+4] h pass 2
 __global__ void k_arnoldi(int stage, int j, int m, double* __restrict__ st, double* __restrict__ H,
                           double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
-                          double* __restrict__ est, double* __restrict__ inv, int* __restrict__ flags, int reorth) {
+                          double* __restrict__ est, double* __restrict__ inv, int* __restrict__ flags, int reorth,
+                          double* __restrict__ est_out, int* __restrict__ flags_out) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double* Hj = H + (size_t)j * (m + 1);
     const double* h1 = st;
@@ -162,6 +163,11 @@ __global__ void k_arnoldi(int stage, int j, int m, double* __restrict__ st, doub
     inv[j + 1] = breakdown ? 0.0 : 1.0 / hn;
     flags[1] = breakdown ? 1 : 0;
     if (!isfinite(den) || !isfinite(est[j])) flags[2] = 1;
+    if (est_out) *est_out = est[j];
+    if (flags_out) {
+        flags_out[0] = flags[1];
+        flags_out[1] = flags[2];
+    }
 }
 
 // dst[i] = a * src[i]
@@ -258,8 +264,9 @@ void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hi
 }
 
 void arnoldi_step(int stage, int j, int m, double* st, double* H, double* cs, double* sn, double* g, double* est,
-                  double* inv, int* flags, int reorth, hipStream_t s) {
-    hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), 0, s, stage, j, m, st, H, cs, sn, g, est, inv, flags, reorth);
+                  double* inv, int* flags, int reorth, hipStream_t s, double* est_out, int* flags_out) {
+    hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), 0, s, stage, j, m, st, H, cs, sn, g, est, inv, flags, reorth,
+                       est_out, flags_out);
 }
 
 void krylov_combine(double* x, const double* Z, size_t ld, int nvec, const double* y, size_t n, hipStream_t st) {

@@ -133,9 +133,13 @@ int ensure_krylov(rte_ctx* c, int m, bool need_z) {
     hipError_t e = hipHostMalloc((void**)&c->hsmall, (size_t)(2 * m + 16) * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) return set_hip_error(e, "hipHostMalloc", __FILE__, __LINE__);
     // per-iteration pinned slots: estimate; (breakdown, non-finite) flags
-    e = hipHostMalloc((void**)&c->hpipe, (size_t)m * sizeof(double), hipHostMallocDefault);
+    // per-iteration slots written by the Arnoldi kernel itself (mapped, coherent host memory)
+    e = hipHostMalloc((void**)&c->hpipe, (size_t)m * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent);
     if (e != hipSuccess) return set_hip_error(e, "hipHostMalloc", __FILE__, __LINE__);
-    e = hipHostMalloc((void**)&c->hpipe_flags, (size_t)2 * m * sizeof(int), hipHostMallocDefault);
+    e = hipHostMalloc((void**)&c->hpipe_flags, (size_t)2 * m * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent);
+    if (e != hipSuccess) return set_hip_error(e, "hipHostMalloc", __FILE__, __LINE__);
+    e = hipHostGetDevicePointer((void**)&c->hpipe_dev, c->hpipe, 0);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->hpipe_flags_dev, c->hpipe_flags, 0);
     if (e != hipSuccess) return set_hip_error(e, "hipHostMalloc", __FILE__, __LINE__);
     c->ev_iter.assign(m, nullptr);
     for (int i = 0; i < m; ++i) {
@@ -421,11 +425,10 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
                 krylov_dots(c->V, n, j + 1, w, n, c->partial, sd + m + 4, false, st, dfl);
                 krylov_update(w, c->V, n, j + 1, sd + m + 4, n, c->partial, sd + j + 2, st, dfl);
             }
-            arnoldi_step(1, j, m, sd, dH, dcs, dsn, dg, dest, dinv, dfl, c->opts.reorth, st);
+            arnoldi_step(1, j, m, sd, dH, dcs, dsn, dg, dest, dinv, dfl, c->opts.reorth, st, c->hpipe_dev + j,
+                         c->hpipe_flags_dev + 2 * j);
             if (pc_live) pc_scale_pool(c, w, w, dinv + j + 1, 0.0);
             else vec_scale_dev(w, w, dinv + j + 1, n, st);
-            RTE_HIP_TRY(hipMemcpyAsync(hp + j, dest + j, sizeof(double), hipMemcpyDeviceToHost, st));
-            RTE_HIP_TRY(hipMemcpyAsync(hfl + 2 * j, dfl + 1, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
             RTE_HIP_TRY(hipEventRecord(c->ev_iter[j], st));
             ++launched;
             // check the previous iteration

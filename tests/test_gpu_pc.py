@@ -270,3 +270,40 @@ def test_fgmres_with_network_matches_lu(rte, prec):
     assert e <= 1e-9
     ctx.close()
     net.close()
+
+
+def test_learned_pc_diffusion_full_size(rte):
+    """The diffusion-regime workload at full size (256^2, HG g = 0.3, L = 4, mu_s = 50,
+    mu_a = 0.01): a network trained by the library (16^2 coarse grid, 12 training sources, noise and
+    multiscale pairs) at least halves the iterations on held-out sources; the oracle's FP64 FFT
+    apply confirms the true residual of a preconditioned solution."""
+    from paper_1802_03061_amd import pc_train
+    say("learned pc diff256")
+    w = inputs.workload("diff256", seed=0)
+    n, L = w["n"], w["L"]
+    ctx = rte.Context(n, mu_a=w["mu_a"], mu_s=w["mu_s"], sigma_hat=w["sigma_hat"], L=L, prec=rte.PREC_FP32)
+    F = pc_train.coarse_factor(n)
+    net, meta = pc_train.train_for(ctx, range(10000, 10012), "diff256", F, steps=1500)
+    say("  training", {k: meta[k] for k in ("pairs", "factor", "t_data_s", "t_train_s")}, meta["loss_history"])
+    plain, pcd = [], []
+    for s_ in range(3):
+        f = dev(inputs.workload("diff256", seed=s_)["f"])
+        ctx.attach_pc(None)
+        _, i0 = ctx.solve(f, tol=1e-8)
+        ctx.attach_pc(net.params(), factor=F)
+        u, i1 = ctx.solve(f, tol=1e-8)
+        say(f"  seed {s_}: plain {i0['iterations']} it {i0['t_solve_ms']:.2f} ms, pc {i1['iterations']} it "
+            f"{i1['t_solve_ms']:.2f} ms, fallback {i1['pc_fallback']}")
+        assert i1["pc_fallback"] == 0 and i1["relres_true"] <= 1e-8
+        plain.append(i0["iterations"]); pcd.append(i1["iterations"])
+    assert np.mean(pcd) <= 0.5 * np.mean(plain)
+    h, mu_t = 1.0 / n, w["mu_a"] + w["mu_s"]
+    spectra = op2.kernel_spectra(n, n, L, h, mu_t)
+    b = op2.rhs(w["f"], L, h, mu_t, spectra=spectra)
+    u, _ = ctx.solve(dev(w["f"]), tol=1e-8)
+    r = b - op2.apply_fft(host(u), L, h, mu_t, w["mu_s"], w["sigma_hat"], "A", spectra=spectra)
+    rr = np.linalg.norm(r) / np.linalg.norm(b)
+    say("  oracle true residual (preconditioned solve)", rr)
+    assert rr <= 1.5e-8
+    ctx.close()
+    net.close()
