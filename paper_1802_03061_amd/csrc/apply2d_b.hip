@@ -62,20 +62,14 @@ __device__ __forceinline__ void couple_modes(cx<T>* v /* C values, in/out */, co
     }
 }
 
-// The same coupling reading the C channel values at base[c * stride] and writing the result back
-// in place, one output pair (V_k, V_{-k}) at a time; only W and the 2L+1 kernel values stay live.
+// The same coupling reading the C channel values at base[c * stride] and writing the result back in
+// place, accumulated diagonal by diagonal (one kernel spectrum K_m at a time, all 2L+1 outputs
+// accumulating in parallel: 2L+1 independent FMA chains per thread).
 template <typename T, int L>
 __device__ __forceinline__ void couple_inplace(cx<T>* base, int stride, const cx<T>* __restrict__ Q,
-                                               size_t qstride_m, size_t qoff, bool flip) {
+                                                    size_t qstride_m, size_t qoff, bool flip) {
     constexpr int C = 2 * L + 1;
     const T r2 = (T)0.70710678118654752440084436210485;
-    cx<T> Kp[2 * L + 1];
-#pragma unroll
-    for (int m = 0; m <= 2 * L; ++m) {
-        cx<T> K = Q[m * qstride_m + qoff];
-        if (flip) { K.im = -K.im; if (m & 1) { K.re = -K.re; K.im = -K.im; } }
-        Kp[m] = K;
-    }
     cx<T> W[C];
     W[L] = base[0];
 #pragma unroll
@@ -84,28 +78,28 @@ __device__ __forceinline__ void couple_inplace(cx<T>* base, int stride, const cx
         W[L + k] = scale(a + mul_i(bb), r2);
         W[L - k] = scale(a - mul_i(bb), r2);
     }
+    cx<T> V[C];
 #pragma unroll
-    for (int k = 0; k <= L; ++k) {
-        cx<T> Vp = mk((T)0, (T)0), Vm = mk((T)0, (T)0);
+    for (int k = 0; k < C; ++k) V[k] = mk((T)0, (T)0);
 #pragma unroll
-        for (int kp = -L; kp <= L; ++kp) {
-            const int mp = kp - k;           // Khat_{kp-k} multiplies W_kp in V_k
-            cx<T> Ka = mp >= 0 ? Kp[mp] : conj(Kp[-mp]);
-            if (mp < 0 && ((-mp) & 1)) { Ka.re = -Ka.re; Ka.im = -Ka.im; }
-            cmac(Vp, Ka, W[kp + L]);
-            if (k > 0) {
-                const int mm = kp + k;       // Khat_{kp+k} multiplies W_kp in V_{-k}
-                cx<T> Kb = mm >= 0 ? Kp[mm] : conj(Kp[-mm]);
-                if (mm < 0 && ((-mm) & 1)) { Kb.re = -Kb.re; Kb.im = -Kb.im; }
-                cmac(Vm, Kb, W[kp + L]);
-            }
+    for (int m = 0; m <= 2 * L; ++m) {
+        cx<T> K = Q[m * qstride_m + qoff];
+        if (flip) { K.im = -K.im; if (m & 1) { K.re = -K.re; K.im = -K.im; } }
+        // V_k += Khat_m W_{k+m}; for m > 0 also V_k += Khat_{-m} W_{k-m}, Khat_{-m} = (-1)^m conj Khat_m
+#pragma unroll
+        for (int k = -L; k + m <= L; ++k) cmac(V[k + L], K, W[k + m + L]);
+        if (m > 0) {
+            cx<T> Kn = conj(K);
+            if (m & 1) { Kn.re = -Kn.re; Kn.im = -Kn.im; }
+#pragma unroll
+            for (int k = -L + m; k <= L; ++k) cmac(V[k + L], Kn, W[k - m + L]);
         }
-        if (k == 0) {
-            base[0] = Vp;
-        } else {
-            base[(2 * k - 1) * stride] = scale(Vp + Vm, r2);
-            base[2 * k * stride] = scale(mul_mi(Vp - Vm), r2);
-        }
+    }
+    base[0] = V[L];
+#pragma unroll
+    for (int k = 1; k <= L; ++k) {
+        base[(2 * k - 1) * stride] = scale(V[L + k] + V[L - k], r2);
+        base[2 * k * stride] = scale(mul_mi(V[L + k] - V[L - k]), r2);
     }
 }
 

@@ -23,6 +23,9 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
+#include <mutex>
+#include <new>
 #include <vector>
 
 #include "apply2d.h"
@@ -171,9 +174,11 @@ __global__ __launch_bounds__(BT) void kb_update(const Chunk* __restrict__ ch, co
 // H[j+1][j] = |w|, the previous Givens rotations and a new one on column j, the residual vector
 // g and the estimate |g[j+1]|; decides whether the problem keeps iterating.  One thread per problem.
 __global__ void kb_givens(const KryProb* __restrict__ kp, int* __restrict__ act, const int* __restrict__ dj,
-                          const double* __restrict__ part2, BState* __restrict__ bs, int m, int P, int max_iter) {
+                          const double* __restrict__ part2, BState* __restrict__ bs, int m, int P,
+                          const int* __restrict__ dmax_iter) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P || !act[p]) return;
+    const int max_iter = *dmax_iter;
     const KryProb& k = kp[p];
     BState& s = bs[p];
     const int j = *dj;
@@ -338,34 +343,6 @@ struct SizeClass {
     int2* db = nullptr;
 };
 
-// Device memory carved out of one allocation; freed on scope exit.
-struct Arena {
-    char* base = nullptr;
-    size_t used = 0, cap = 0;
-    ~Arena() { if (base) (void)hipFree(base); }
-    template <typename X>
-    X* take(size_t n) {
-        const size_t off = (used + 255) / 256 * 256;
-        used = off + n * sizeof(X);
-        return reinterpret_cast<X*>(base + off);
-    }
-};
-
-struct Resources {
-    hipStream_t st = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    std::vector<hipEvent_t> ev;
-    void* pinned = nullptr;
-    ~Resources() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        for (auto e : ev) if (e) (void)hipEventDestroy(e);
-        if (pinned) (void)hipHostFree(pinned);
-        if (st) (void)hipStreamDestroy(st);
-    }
-};
-
 template <typename T>
 BatchProb<T> batch_prob(const rte_ctx* c, const cx<T>* Q, const cx<T>* twx, const cx<T>* twy, cx<T>* work,
                         double s, const double* in, double* out, const double* bvec, int jin, int jout) {
@@ -397,143 +374,229 @@ int apply_batch(const std::vector<SizeClass>& cls, const BatchProb<T>* probs, co
         if (e_ != hipSuccess) return set_hip_error(e_, #expr, __FILE__, __LINE__); \
     } while (0)
 
-template <typename T>
-int solve_batched_t(int P, rte_ctx* const* ctxs, const double* const* f, const double* tol, int max_iter, void* const* u,
-                    rte_solve_info* infos) {
-    const double t0 = now_ms();
-    const rte_ctx* c0 = ctxs[0];
-    const int m = c0->opts.restart;
-    const int max_cycles = c0->opts.max_cycles;
-    const bool mixed = c0->prec == RTE_PREC_FP32;
-    const double inner_tol = c0->opts.inner_tol;
-    for (int p = 0; p < P; ++p) {
-        int rc = ensure_krylov(ctxs[p], m, false);
-        if (rc) return rc;
-        BK_TRY(hipStreamSynchronize(ctxs[p]->stream));
-    }
-    // ---- chunk list and size classes
+// Everything a batch needs that does not change between calls on the same contexts: the device
+// arena (descriptors, item lists, chunk list, partial sums, Arnoldi slabs, state), the stream,
+// pinned staging, events and the instantiated graph of one inner iteration.  Cached per process
+// for a few context lists; dropped when any of its contexts is destroyed.
+// The device buffers of a context a plan's descriptors point at (checked on every lookup).
+std::vector<const void*> ctx_buffers(const rte_ctx* c) {
+    return {c->V, c->xv, c->rv, c->bv, c->wd, c->Qd, c->twd[0], c->twd[1], c->wf, c->Qf, c->twf[0], c->twf[1]};
+}
+
+struct Plan {
+    std::vector<unsigned long long> ids;   // context ids, in order
+    std::vector<const void*> bufs;         // ctx_buffers of every context, in order
+    int m = 0, prec = 0, P = 0, NCH = 0;
+    size_t S = 0;
+    std::vector<SizeClass> cls, cls_d;
+    std::vector<KryProb> kp;
     std::vector<Chunk> chunks;
-    std::vector<KryProb> kp(P);
-    std::map<std::pair<int, int>, int> cls_index;
-    std::vector<SizeClass> cls;
+    char* arena = nullptr;
+    Chunk* d_ch = nullptr;
+    KryProb* d_kp = nullptr;
+    BState* d_bs = nullptr;
+    int *d_act = nullptr, *d_todo = nullptr, *d_j = nullptr, *d_maxit = nullptr;
+    double *d_part = nullptr, *d_part2 = nullptr, *d_rn2 = nullptr, *d_slab = nullptr;
+    void* d_it = nullptr;                  // BatchProb<T>[P] of the iteration
+    BatchProb<double>* d_res = nullptr;
+    BatchProb<double>* d_rhs = nullptr;
+    hipStream_t st = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipEvent_t> ev;
+    void* pinned = nullptr;                // BState[P] | act[P] | todo[P] | rn2[P] | count (mapped)
+    BState* h_bs = nullptr;
+    int *h_act = nullptr, *h_todo = nullptr, *h_cnt = nullptr, *h_cnt_dev = nullptr;
+    double* h_rn2 = nullptr;
+    ~Plan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto e : ev) if (e) (void)hipEventDestroy(e);
+        if (pinned) (void)hipHostFree(pinned);
+        if (st) (void)hipStreamDestroy(st);
+        if (arena) (void)hipFree(arena);
+    }
+};
+
+// Most recently used last.  Never destroyed: its plans hold HIP resources, which must not be
+// released from static destructors after the runtime may have shut down (the process exit
+// reclaims them).
+std::mutex g_plan_mu;
+std::vector<std::unique_ptr<Plan>>& plans() {
+    static auto* v = new std::vector<std::unique_ptr<Plan>>();
+    return *v;
+}
+constexpr size_t MAX_PLANS = 4;
+
+template <typename X>
+X* carve(char* base, size_t& used, size_t n) {
+    const size_t off = (used + 255) / 256 * 256;
+    used = off + n * sizeof(X);
+    return reinterpret_cast<X*>(base + off);
+}
+
+template <typename T>
+int build_plan(Plan& pl, int P, rte_ctx* const* ctxs) {
+    const int m = pl.m;
     const int TRf = apply2d_batch_rows<T>(), TRd = apply2d_batch_rows<double>();
     const int NCf = apply2d_batch_cols<T>(0), NCd = apply2d_batch_cols<double>(0);
+    std::map<std::pair<int, int>, int> cls_index;
+    pl.kp.assign(P, KryProb{});
     for (int p = 0; p < P; ++p) {
         const rte_ctx* c = ctxs[p];
-        KryProb& k = kp[p];
+        KryProb& k = pl.kp[p];
         k.nvec = (int)c->nvec;
-        k.c0 = (int)chunks.size();
-        for (int off = 0; off < k.nvec; off += CHUNK) chunks.push_back({p, off, std::min(CHUNK, k.nvec - off)});
-        k.nc = (int)chunks.size() - k.c0;
+        k.c0 = (int)pl.chunks.size();
+        for (int off = 0; off < k.nvec; off += CHUNK) pl.chunks.push_back({p, off, std::min(CHUNK, k.nvec - off)});
+        k.nc = (int)pl.chunks.size() - k.c0;
         auto key = std::make_pair(c->PX, c->PY);
         if (!cls_index.count(key)) {
-            cls_index[key] = (int)cls.size();
-            SizeClass s;
-            s.PX = c->PX;
-            s.PY = c->PY;
-            cls.push_back(s);
+            cls_index[key] = (int)pl.cls.size();
+            SizeClass sc;
+            sc.PX = c->PX;
+            sc.PY = c->PY;
+            pl.cls.push_back(sc);
         }
     }
     // the iteration uses precision T, the right-hand side and residual FP64: separate item lists
-    std::vector<SizeClass> cls_d = cls;
+    pl.cls_d = pl.cls;
     for (int p = 0; p < P; ++p) {
         const rte_ctx* c = ctxs[p];
         const int ci = cls_index[std::make_pair(c->PX, c->PY)];
-        for (int t = 0; t < (c->ny + TRf - 1) / TRf; ++t) cls[ci].ac.push_back(make_int2(p, t));
-        for (int t = 0; t < (c->PX / 2 + NCf - 1) / NCf; ++t) cls[ci].b.push_back(make_int2(p, t));
-        for (int t = 0; t < (c->ny + TRd - 1) / TRd; ++t) cls_d[ci].ac.push_back(make_int2(p, t));
-        for (int t = 0; t < (c->PX / 2 + NCd - 1) / NCd; ++t) cls_d[ci].b.push_back(make_int2(p, t));
+        for (int t = 0; t < (c->ny + TRf - 1) / TRf; ++t) pl.cls[ci].ac.push_back(make_int2(p, t));
+        for (int t = 0; t < (c->PX / 2 + NCf - 1) / NCf; ++t) pl.cls[ci].b.push_back(make_int2(p, t));
+        for (int t = 0; t < (c->ny + TRd - 1) / TRd; ++t) pl.cls_d[ci].ac.push_back(make_int2(p, t));
+        for (int t = 0; t < (c->PX / 2 + NCd - 1) / NCd; ++t) pl.cls_d[ci].b.push_back(make_int2(p, t));
     }
-    const int NCH = (int)chunks.size();
-    const size_t S = (size_t)(m + 1) * m + 4 * (size_t)m + 2;   // Arnoldi slab per problem
-    // ---- device arena
-    Arena ar;
+    const int NCH = pl.NCH = (int)pl.chunks.size();
+    const size_t S = pl.S = (size_t)(m + 1) * m + 4 * (size_t)m + 2;   // Arnoldi slab per problem
     size_t items = 0;
-    for (auto& k : cls) items += k.ac.size() + k.b.size();
-    for (auto& k : cls_d) items += k.ac.size() + k.b.size();
-    ar.cap = 256 * 64 + sizeof(Chunk) * NCH + sizeof(KryProb) * P + sizeof(BState) * P + sizeof(int) * (2 * P + 4) +
-             sizeof(double) * ((size_t)NCH * (m + 2) + P + S * P) + sizeof(int2) * items +
-             sizeof(BatchProb<T>) * P + 2 * sizeof(BatchProb<double>) * P;
-    BK_TRY(hipMalloc((void**)&ar.base, ar.cap));
-    Chunk* d_ch = ar.take<Chunk>(NCH);
-    KryProb* d_kp = ar.take<KryProb>(P);
-    BState* d_bs = ar.take<BState>(P);
-    int* d_act = ar.take<int>(P);
-    int* d_todo = ar.take<int>(P);
-    int* d_j = ar.take<int>(2);
-    int* d_cnt = d_j + 1;
-    double* d_part = ar.take<double>((size_t)NCH * (m + 1));
-    double* d_part2 = ar.take<double>(NCH);
-    double* d_rn2 = ar.take<double>(P);
-    double* d_slab = ar.take<double>(S * P);
-    for (auto& k : cls) {
-        k.dac = ar.take<int2>(k.ac.size());
-        k.db = ar.take<int2>(k.b.size());
-    }
-    for (auto& k : cls_d) {
-        k.dac = ar.take<int2>(k.ac.size());
-        k.db = ar.take<int2>(k.b.size());
-    }
-    BatchProb<T>* d_it = ar.take<BatchProb<T>>(P);
-    BatchProb<double>* d_res = ar.take<BatchProb<double>>(P);
-    BatchProb<double>* d_rhs = ar.take<BatchProb<double>>(P);
-    if (ar.used > ar.cap) return set_error(RTE_EDEVICE, "batched arena overflow");
-    // ---- descriptors
+    for (auto& k : pl.cls) items += k.ac.size() + k.b.size();
+    for (auto& k : pl.cls_d) items += k.ac.size() + k.b.size();
+    const size_t ntake = 16 + 4 * pl.cls.size();
+    const size_t cap = 256 * ntake + sizeof(Chunk) * NCH + sizeof(KryProb) * P + sizeof(BState) * P +
+                       sizeof(int) * (2 * P + 4) + sizeof(double) * ((size_t)NCH * (m + 2) + P + S * P) +
+                       sizeof(int2) * items + sizeof(BatchProb<T>) * P + 2 * sizeof(BatchProb<double>) * P;
+    BK_TRY(hipMalloc((void**)&pl.arena, cap));
+    size_t used = 0;
+    char* a = pl.arena;
+    pl.d_ch = carve<Chunk>(a, used, NCH);
+    pl.d_kp = carve<KryProb>(a, used, P);
+    pl.d_bs = carve<BState>(a, used, P);
+    pl.d_act = carve<int>(a, used, P);
+    pl.d_todo = carve<int>(a, used, P);
+    pl.d_j = carve<int>(a, used, 4);
+    pl.d_maxit = pl.d_j + 2;
+    pl.d_part = carve<double>(a, used, (size_t)NCH * (m + 1));
+    pl.d_part2 = carve<double>(a, used, NCH);
+    pl.d_rn2 = carve<double>(a, used, P);
+    pl.d_slab = carve<double>(a, used, S * P);
+    for (auto& k : pl.cls) { k.dac = carve<int2>(a, used, k.ac.size()); k.db = carve<int2>(a, used, k.b.size()); }
+    for (auto& k : pl.cls_d) { k.dac = carve<int2>(a, used, k.ac.size()); k.db = carve<int2>(a, used, k.b.size()); }
+    pl.d_it = carve<BatchProb<T>>(a, used, P);
+    pl.d_res = carve<BatchProb<double>>(a, used, P);
+    pl.d_rhs = carve<BatchProb<double>>(a, used, P);
+    if (used > cap) return set_error(RTE_EDEVICE, "batched arena overflow");
+    BK_TRY(hipStreamCreateWithFlags(&pl.st, hipStreamNonBlocking));
+    hipStream_t st = pl.st;
+    // descriptors that do not depend on the call's sources and outputs
     std::vector<BatchProb<T>> it(P);
-    std::vector<BatchProb<double>> res(P), rhs(P);
+    std::vector<BatchProb<double>> res(P);
     for (int p = 0; p < P; ++p) {
         rte_ctx* c = ctxs[p];
-        KryProb& k = kp[p];
-        double* sl = d_slab + S * p;
+        KryProb& k = pl.kp[p];
+        double* sl = pl.d_slab + S * p;
         k.V = c->V; k.x = c->xv; k.r = c->rv; k.b = c->bv;
         k.H = sl;
         k.cs = sl + (size_t)(m + 1) * m;
         k.sn = k.cs + m;
         k.g = k.sn + m;
         k.y = k.g + m + 1;
-        k.u = (cx<double>*)u[p];
+        k.u = nullptr;
         const double s = c->mu_s * c->sigma[0];
         if constexpr (sizeof(T) == 4)
             it[p] = batch_prob<float>(c, c->Qf, c->twf[0], c->twf[1], c->wf, s, c->V, c->V, nullptr, 1, 1);
         else
             it[p] = batch_prob<double>(c, c->Qd, c->twd[0], c->twd[1], c->wd, s, c->V, c->V, nullptr, 1, 1);
         res[p] = batch_prob<double>(c, c->Qd, c->twd[0], c->twd[1], c->wd, s, c->xv, c->rv, c->bv, 0, 0);
-        rhs[p] = batch_prob<double>(c, c->Qd, c->twd[0], c->twd[1], c->wd, 1.0, f[p], c->bv, nullptr, 0, 0);
     }
-    Resources rs;
-    BK_TRY(hipStreamCreateWithFlags(&rs.st, hipStreamNonBlocking));
-    hipStream_t st = rs.st;
-    BK_TRY(hipMemcpyAsync(d_ch, chunks.data(), sizeof(Chunk) * NCH, hipMemcpyHostToDevice, st));
-    BK_TRY(hipMemcpyAsync(d_kp, kp.data(), sizeof(KryProb) * P, hipMemcpyHostToDevice, st));
-    BK_TRY(hipMemcpyAsync(d_it, it.data(), sizeof(BatchProb<T>) * P, hipMemcpyHostToDevice, st));
-    BK_TRY(hipMemcpyAsync(d_res, res.data(), sizeof(BatchProb<double>) * P, hipMemcpyHostToDevice, st));
-    BK_TRY(hipMemcpyAsync(d_rhs, rhs.data(), sizeof(BatchProb<double>) * P, hipMemcpyHostToDevice, st));
-    for (size_t i = 0; i < cls.size(); ++i) {
-        BK_TRY(hipMemcpyAsync(cls[i].dac, cls[i].ac.data(), sizeof(int2) * cls[i].ac.size(), hipMemcpyHostToDevice, st));
-        BK_TRY(hipMemcpyAsync(cls[i].db, cls[i].b.data(), sizeof(int2) * cls[i].b.size(), hipMemcpyHostToDevice, st));
-        BK_TRY(hipMemcpyAsync(cls_d[i].dac, cls_d[i].ac.data(), sizeof(int2) * cls_d[i].ac.size(), hipMemcpyHostToDevice, st));
-        BK_TRY(hipMemcpyAsync(cls_d[i].db, cls_d[i].b.data(), sizeof(int2) * cls_d[i].b.size(), hipMemcpyHostToDevice, st));
+    BK_TRY(hipMemcpyAsync(pl.d_ch, pl.chunks.data(), sizeof(Chunk) * NCH, hipMemcpyHostToDevice, st));
+    BK_TRY(hipMemcpyAsync(pl.d_it, it.data(), sizeof(BatchProb<T>) * P, hipMemcpyHostToDevice, st));
+    BK_TRY(hipMemcpyAsync(pl.d_res, res.data(), sizeof(BatchProb<double>) * P, hipMemcpyHostToDevice, st));
+    for (size_t i = 0; i < pl.cls.size(); ++i) {
+        auto up = [&](int2* d, const std::vector<int2>& h) {
+            return hipMemcpyAsync(d, h.data(), sizeof(int2) * h.size(), hipMemcpyHostToDevice, st);
+        };
+        BK_TRY(up(pl.cls[i].dac, pl.cls[i].ac));
+        BK_TRY(up(pl.cls[i].db, pl.cls[i].b));
+        BK_TRY(up(pl.cls_d[i].dac, pl.cls_d[i].ac));
+        BK_TRY(up(pl.cls_d[i].db, pl.cls_d[i].b));
     }
-    // pinned host staging: states, masks, norms, per-iteration active counts
-    const size_t pin_bytes = sizeof(BState) * P + sizeof(int) * 2 * P + sizeof(double) * P + sizeof(int) * m + 64;
-    BK_TRY(hipHostMalloc(&rs.pinned, pin_bytes, hipHostMallocDefault));
-    BState* h_bs = (BState*)rs.pinned;
-    int* h_act = (int*)(h_bs + P);
-    int* h_todo = h_act + P;
-    double* h_rn2 = (double*)(((uintptr_t)(h_todo + P) + 7) / 8 * 8);
-    int* h_cnt = (int*)(h_rn2 + P);
-    rs.ev.assign(m, nullptr);
-    for (auto& e : rs.ev) BK_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    BK_TRY(hipStreamSynchronize(st));   // host staging vectors go out of scope
+    // pinned host staging; the active count is written by the tick kernel straight into it
+    const size_t pin_bytes = sizeof(BState) * P + sizeof(int) * 2 * P + 8 + sizeof(double) * P + sizeof(int) * (m + 1) + 64;
+    BK_TRY(hipHostMalloc(&pl.pinned, pin_bytes, hipHostMallocMapped | hipHostMallocCoherent));
+    pl.h_bs = (BState*)pl.pinned;
+    pl.h_act = (int*)(pl.h_bs + P);
+    pl.h_todo = pl.h_act + P;
+    pl.h_rn2 = (double*)(((uintptr_t)(pl.h_todo + P) + 7) / 8 * 8);
+    pl.h_cnt = (int*)(pl.h_rn2 + P);
+    BK_TRY(hipHostGetDevicePointer((void**)&pl.h_cnt_dev, pl.h_cnt, 0));
+    pl.ev.assign(m, nullptr);
+    for (auto& e : pl.ev) BK_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    // capture one inner iteration; replay i writes its active count to h_cnt[i % (m + 1)]... the
+    // count slot is a single int: replays are checked one behind through events (see run_plan)
     const unsigned gP = (unsigned)((P + 63) / 64);
+    BK_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+    int crc = apply_batch<T>(pl.cls, (const BatchProb<T>*)pl.d_it, pl.d_act, pl.d_j, APPLY_A, st);
+    hipLaunchKernelGGL(kb_dots, dim3(NCH), dim3(BT), 0, st, pl.d_ch, pl.d_kp, pl.d_act, pl.d_j, pl.d_part, m);
+    hipLaunchKernelGGL(kb_hcol, dim3(P), dim3(64), 0, st, pl.d_kp, pl.d_act, pl.d_j, pl.d_part, m);
+    hipLaunchKernelGGL(kb_update, dim3(NCH), dim3(BT), 0, st, pl.d_ch, pl.d_kp, pl.d_act, pl.d_j, pl.d_part2, m);
+    hipLaunchKernelGGL(kb_givens, dim3(gP), dim3(64), 0, st, pl.d_kp, pl.d_act, pl.d_j, pl.d_part2, pl.d_bs, m, P,
+                       pl.d_maxit);
+    hipLaunchKernelGGL(kb_scale_next, dim3(NCH), dim3(BT), 0, st, pl.d_ch, pl.d_kp, pl.d_act, pl.d_j, pl.d_bs);
+    hipLaunchKernelGGL(kb_tick, dim3(1), dim3(BT), 0, st, pl.d_j, pl.d_act, P, pl.h_cnt_dev);
+    hipError_t ce = hipStreamEndCapture(st, &pl.graph);
+    if (crc) return set_error(RTE_EUNSUPPORTED, "batched apply: unsupported size");
+    BK_TRY(ce);
+    BK_TRY(hipGraphInstantiate(&pl.exec, pl.graph, nullptr, nullptr, 0));
+    return RTE_OK;
+}
 
+template <typename T>
+int run_plan(Plan& pl, rte_ctx* const* ctxs, const double* const* f, const double* tol, int max_iter, void* const* u,
+             rte_solve_info* infos, double t0) {
+    const int P = pl.P, m = pl.m, NCH = pl.NCH;
+    const rte_ctx* c0 = ctxs[0];
+    const int max_cycles = c0->opts.max_cycles;
+    const bool mixed = c0->prec == RTE_PREC_FP32;
+    const double inner_tol = c0->opts.inner_tol;
+    hipStream_t st = pl.st;
+    // per-call descriptors: sources (right-hand side apply) and outputs
+    std::vector<BatchProb<double>> rhs(P);
+    for (int p = 0; p < P; ++p) {
+        rte_ctx* c = ctxs[p];
+        rhs[p] = batch_prob<double>(c, c->Qd, c->twd[0], c->twd[1], c->wd, 1.0, f[p], c->bv, nullptr, 0, 0);
+        pl.kp[p].u = (cx<double>*)u[p];
+    }
+    BK_TRY(hipMemcpyAsync(pl.d_rhs, rhs.data(), sizeof(BatchProb<double>) * P, hipMemcpyHostToDevice, st));
+    BK_TRY(hipMemcpyAsync(pl.d_kp, pl.kp.data(), sizeof(KryProb) * P, hipMemcpyHostToDevice, st));
+    const int mi[2] = {max_iter, 0};
+    BK_TRY(hipMemcpyAsync(pl.d_maxit, mi, sizeof(int), hipMemcpyHostToDevice, st));
+    const unsigned gP = (unsigned)((P + 63) / 64);
+    BState* h_bs = pl.h_bs;
+    int* h_act = pl.h_act;
+    int* h_todo = pl.h_todo;
+    double* h_rn2 = pl.h_rn2;
     // ---- right-hand sides b = K~ f (FP64), x = 0, r = b, |b|
-    if (apply_batch<double>(cls_d, d_rhs, nullptr, nullptr, APPLY_KT, st)) return set_error(RTE_EUNSUPPORTED, "batched apply: unsupported size");
-    hipLaunchKernelGGL(kb_vec, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, nullptr, d_bs, 0);
+    if (apply_batch<double>(pl.cls_d, pl.d_rhs, nullptr, nullptr, APPLY_KT, st))
+        return set_error(RTE_EUNSUPPORTED, "batched apply: unsupported size");
+    hipLaunchKernelGGL(kb_vec, dim3(NCH), dim3(BT), 0, st, pl.d_ch, pl.d_kp, nullptr, pl.d_bs, 0);
     for (int p = 0; p < P; ++p) h_todo[p] = 1;
-    BK_TRY(hipMemcpyAsync(d_todo, h_todo, sizeof(int) * P, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(kb_norm2, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, d_todo, d_part2);
-    hipLaunchKernelGGL(kb_sum_parts, dim3(gP), dim3(64), 0, st, d_kp, d_todo, d_part2, d_rn2, P);
-    BK_TRY(hipMemcpyAsync(h_rn2, d_rn2, sizeof(double) * P, hipMemcpyDeviceToHost, st));
+    BK_TRY(hipMemcpyAsync(pl.d_todo, h_todo, sizeof(int) * P, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(kb_norm2, dim3(NCH), dim3(BT), 0, st, pl.d_ch, pl.d_kp, pl.d_todo, pl.d_part2);
+    hipLaunchKernelGGL(kb_sum_parts, dim3(gP), dim3(64), 0, st, pl.d_kp, pl.d_todo, pl.d_part2, pl.d_rn2, P);
+    BK_TRY(hipMemcpyAsync(h_rn2, pl.d_rn2, sizeof(double) * P, hipMemcpyDeviceToHost, st));
     BK_TRY(hipStreamSynchronize(st));
     std::vector<double> bn(P), rn(P), est(P);
     std::vector<int> status(P, RTE_NOT_CONVERGED), cycles(P, 0);
@@ -544,21 +607,6 @@ int solve_batched_t(int P, rte_ctx* const* ctxs, const double* const* f, const d
         if (!std::isfinite(h_rn2[p])) { status[p] = RTE_ENUMERIC; h_todo[p] = 0; }
         else if (h_rn2[p] == 0.0) { status[p] = RTE_OK; h_todo[p] = 0; }
     }
-
-    // ---- capture one inner iteration
-    BK_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
-    int crc = apply_batch<T>(cls, d_it, d_act, d_j, APPLY_A, st);
-    hipLaunchKernelGGL(kb_dots, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, d_act, d_j, d_part, m);
-    hipLaunchKernelGGL(kb_hcol, dim3(P), dim3(64), 0, st, d_kp, d_act, d_j, d_part, m);
-    hipLaunchKernelGGL(kb_update, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, d_act, d_j, d_part2, m);
-    hipLaunchKernelGGL(kb_givens, dim3(gP), dim3(64), 0, st, d_kp, d_act, d_j, d_part2, d_bs, m, P, max_iter);
-    hipLaunchKernelGGL(kb_scale_next, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, d_act, d_j, d_bs);
-    hipLaunchKernelGGL(kb_tick, dim3(1), dim3(BT), 0, st, d_j, d_act, P, d_cnt);
-    hipError_t ce = hipStreamEndCapture(st, &rs.graph);
-    if (crc) return set_error(RTE_EUNSUPPORTED, "batched apply: unsupported size");
-    BK_TRY(ce);
-    BK_TRY(hipGraphInstantiate(&rs.exec, rs.graph, nullptr, nullptr, 0));
-
     // ---- cycles
     int ncyc = 0;
     while (true) {
@@ -578,30 +626,31 @@ int solve_batched_t(int P, rte_ctx* const* ctxs, const double* const* f, const d
             h_bs[p].inv = 0.0;
             h_bs[p].flags = 0;
         }
-        BK_TRY(hipMemcpyAsync(d_bs, h_bs, sizeof(BState) * P, hipMemcpyHostToDevice, st));
-        BK_TRY(hipMemcpyAsync(d_act, h_act, sizeof(int) * P, hipMemcpyHostToDevice, st));
-        BK_TRY(hipMemcpyAsync(d_todo, h_todo, sizeof(int) * P, hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(kb_cycle_start, dim3(gP), dim3(64), 0, st, d_kp, d_act, d_bs, d_j, m, P);
-        hipLaunchKernelGGL(kb_vec, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, d_act, d_bs, 1);
-        // inner iterations: replay the graph; the active count of replay i-1 is read while i runs
+        BK_TRY(hipMemcpyAsync(pl.d_bs, h_bs, sizeof(BState) * P, hipMemcpyHostToDevice, st));
+        BK_TRY(hipMemcpyAsync(pl.d_act, h_act, sizeof(int) * P, hipMemcpyHostToDevice, st));
+        BK_TRY(hipMemcpyAsync(pl.d_todo, h_todo, sizeof(int) * P, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(kb_cycle_start, dim3(gP), dim3(64), 0, st, pl.d_kp, pl.d_act, pl.d_bs, pl.d_j, m, P);
+        hipLaunchKernelGGL(kb_vec, dim3(NCH), dim3(BT), 0, st, pl.d_ch, pl.d_kp, pl.d_act, pl.d_bs, 1);
+        // inner iterations: replay the graph; replay i's tick writes the active count to mapped
+        // host memory, read after replay i's event while replay i + 1 runs
         for (int i = 0; i < m; ++i) {
-            BK_TRY(hipGraphLaunch(rs.exec, st));
-            BK_TRY(hipMemcpyAsync(h_cnt + i, d_cnt, sizeof(int), hipMemcpyDeviceToHost, st));
-            BK_TRY(hipEventRecord(rs.ev[i], st));
+            BK_TRY(hipGraphLaunch(pl.exec, st));
+            BK_TRY(hipEventRecord(pl.ev[i], st));
             if (i >= 1) {
-                BK_TRY(hipEventSynchronize(rs.ev[i - 1]));
-                if (h_cnt[i - 1] == 0) break;
+                BK_TRY(hipEventSynchronize(pl.ev[i - 1]));
+                // the count may already be replay i's (it only decreases): 0 means all have stopped
+                if (*(volatile int*)pl.h_cnt == 0) break;
             }
         }
         // x += V y, r = b - A x (FP64), |r|
-        hipLaunchKernelGGL(kb_backsolve, dim3(gP), dim3(64), 0, st, d_kp, d_todo, d_bs, m, P);
-        hipLaunchKernelGGL(kb_combine, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, d_todo, d_bs);
-        if (apply_batch<double>(cls_d, d_res, d_todo, nullptr, APPLY_RESID, st))
+        hipLaunchKernelGGL(kb_backsolve, dim3(gP), dim3(64), 0, st, pl.d_kp, pl.d_todo, pl.d_bs, m, P);
+        hipLaunchKernelGGL(kb_combine, dim3(NCH), dim3(BT), 0, st, pl.d_ch, pl.d_kp, pl.d_todo, pl.d_bs);
+        if (apply_batch<double>(pl.cls_d, pl.d_res, pl.d_todo, nullptr, APPLY_RESID, st))
             return set_error(RTE_EUNSUPPORTED, "batched apply: unsupported size");
-        hipLaunchKernelGGL(kb_norm2, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, d_todo, d_part2);
-        hipLaunchKernelGGL(kb_sum_parts, dim3(gP), dim3(64), 0, st, d_kp, d_todo, d_part2, d_rn2, P);
-        BK_TRY(hipMemcpyAsync(h_rn2, d_rn2, sizeof(double) * P, hipMemcpyDeviceToHost, st));
-        BK_TRY(hipMemcpyAsync(h_bs, d_bs, sizeof(BState) * P, hipMemcpyDeviceToHost, st));
+        hipLaunchKernelGGL(kb_norm2, dim3(NCH), dim3(BT), 0, st, pl.d_ch, pl.d_kp, pl.d_todo, pl.d_part2);
+        hipLaunchKernelGGL(kb_sum_parts, dim3(gP), dim3(64), 0, st, pl.d_kp, pl.d_todo, pl.d_part2, pl.d_rn2, P);
+        BK_TRY(hipMemcpyAsync(h_rn2, pl.d_rn2, sizeof(double) * P, hipMemcpyDeviceToHost, st));
+        BK_TRY(hipMemcpyAsync(h_bs, pl.d_bs, sizeof(BState) * P, hipMemcpyDeviceToHost, st));
         BK_TRY(hipStreamSynchronize(st));
         for (int p = 0; p < P; ++p) {
             if (!h_todo[p]) continue;
@@ -618,8 +667,8 @@ int solve_batched_t(int P, rte_ctx* const* ctxs, const double* const* f, const d
     }
     // ---- outputs
     for (int p = 0; p < P; ++p) h_act[p] = 1;
-    BK_TRY(hipMemcpyAsync(d_act, h_act, sizeof(int) * P, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(kb_vec, dim3(NCH), dim3(BT), 0, st, d_ch, d_kp, d_act, d_bs, 2);
+    BK_TRY(hipMemcpyAsync(pl.d_act, h_act, sizeof(int) * P, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(kb_vec, dim3(NCH), dim3(BT), 0, st, pl.d_ch, pl.d_kp, pl.d_act, pl.d_bs, 2);
     BK_TRY(hipGetLastError());
     BK_TRY(hipStreamSynchronize(st));
     const double t_solve = now_ms() - t0;
@@ -644,7 +693,66 @@ int solve_batched_t(int P, rte_ctx* const* ctxs, const double* const* f, const d
     return worst;
 }
 
+template <typename T>
+int solve_batched_t(int P, rte_ctx* const* ctxs, const double* const* f, const double* tol, int max_iter, void* const* u,
+                    rte_solve_info* infos) {
+    const double t0 = now_ms();
+    const int m = ctxs[0]->opts.restart;
+    for (int p = 0; p < P; ++p) {
+        int rc = ensure_krylov(ctxs[p], m, false);
+        if (rc) return rc;
+        BK_TRY(hipStreamSynchronize(ctxs[p]->stream));
+    }
+    std::vector<unsigned long long> ids(P);
+    std::vector<const void*> bufs;
+    for (int p = 0; p < P; ++p) {
+        ids[p] = ctxs[p]->id;
+        const auto b = ctx_buffers(ctxs[p]);
+        bufs.insert(bufs.end(), b.begin(), b.end());
+    }
+    std::lock_guard<std::mutex> lk(g_plan_mu);   // one batched solve at a time per process
+    auto& g_plans = plans();
+    Plan* pl = nullptr;
+    for (size_t i = 0; i < g_plans.size(); ++i) {
+        Plan& q = *g_plans[i];
+        // the Krylov buffers a plan points at are reallocated when the restart length changes
+        if (q.ids == ids && q.m == m && q.prec == ctxs[0]->prec && q.bufs == bufs) {
+            std::unique_ptr<Plan> keep = std::move(g_plans[i]);
+            g_plans.erase(g_plans.begin() + i);
+            g_plans.push_back(std::move(keep));
+            pl = g_plans.back().get();
+            break;
+        }
+    }
+    if (!pl) {
+        std::unique_ptr<Plan> np(new (std::nothrow) Plan);
+        if (!np) return set_error(RTE_ENOMEM, "host allocation failed");
+        np->ids = ids;
+        np->bufs = bufs;
+        np->m = m;
+        np->prec = ctxs[0]->prec;
+        np->P = P;
+        int rc = build_plan<T>(*np, P, ctxs);
+        if (rc) return rc;
+        if (g_plans.size() >= MAX_PLANS) g_plans.erase(g_plans.begin());
+        g_plans.push_back(std::move(np));
+        pl = g_plans.back().get();
+    }
+    return run_plan<T>(*pl, ctxs, f, tol, max_iter, u, infos, t0);
+}
+
 }  // namespace
+
+// A context is going away: drop every cached batch plan that refers to it.
+void batched_forget(unsigned long long id) {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto& g_plans = plans();
+    for (size_t i = 0; i < g_plans.size();) {
+        const auto& ids = g_plans[i]->ids;
+        if (std::find(ids.begin(), ids.end(), id) != ids.end()) g_plans.erase(g_plans.begin() + i);
+        else ++i;
+    }
+}
 
 int solve_batched_impl(int count, rte_ctx* const* ctxs, const double* const* f, const double* tol, int max_iter,
                        void* const* u, rte_solve_info* infos) {

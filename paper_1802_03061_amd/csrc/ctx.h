@@ -7,6 +7,7 @@
 #include "common.h"
 
 struct rte_ctx {
+    unsigned long long id = 0;   // unique per context in the process (cached batch plans key on it)
     int dim = 2, nx = 0, ny = 0, nz = 1, L = 0, C = 1, M = 1, prec = RTE_PREC_FP64;
     double h = 0, mu_a = 0, mu_s = 0, mu_t = 0;
     std::vector<double> sigma;
@@ -85,4 +86,5 @@ int autotune_2d(rte_ctx* c, int reps, bool use_cache);
 namespace rte {
 int solve_batched_impl(int count, rte_ctx* const* ctxs, const double* const* f, const double* tol, int max_iter,
                        void* const* u, rte_solve_info* infos);
+void batched_forget(unsigned long long id);
 }  // namespace rte

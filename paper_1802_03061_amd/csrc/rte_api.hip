@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -95,6 +96,7 @@ static void free_krylov(rte_ctx* c) {
 static void free_ctx(rte_ctx* c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    batched_forget(c->id);
     free_krylov(c);
     dfree(c->Qf);
     dfree(c->Qd);
@@ -561,6 +563,8 @@ int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const 
     if (rc) return rc;
     const double t0 = now_ms();
     rte_ctx* c = new (std::nothrow) rte_ctx();
+    static std::atomic<unsigned long long> next_id{1};
+    if (c) c->id = next_id.fetch_add(1);
     if (!c) return set_error(RTE_ENOMEM, "host allocation failed");
     c->dim = g->dim;
     c->nx = g->n[0];
