@@ -38,7 +38,67 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 METRIC = "solve time to rel-res 1e-8 (512^2, L=8 HG), learned-PC vs plain; applies/s"
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "hbm_traffic_hg512_L8.json")
+# sources of the 2D apply kernels: counter readings are only reported while these are unchanged
+APPLY_SOURCES = ["paper_1802_03061_amd/csrc/" + f for f in
+                 ("apply2d.hip", "apply2d_b.hip", "apply2d.h", "fft.h", "common.h")]
+
+
+def sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in APPLY_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pmc_summary(fetch_csv: str, write_csv: str, variants) -> dict:
+    """Per-launch HBM traffic of the FP32 apply passes from two rocprofv3 --pmc runs (FETCH_SIZE and
+    WRITE_SIZE, KiB per dispatch), each scaled by what the same counter reads for the 1 GiB device
+    copy that copy_peak_gbs() performs (1 GiB read and 1 GiB written)."""
+    import csv
+    import collections
+
+    def load(path):
+        agg = collections.defaultdict(list)
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return agg
+    fe, wr = load(fetch_csv), load(write_csv)
+    copy = "__amd_rocclr_copyBuffer"
+    true_kib = float(2 ** 20)
+    ff, fw = true_kib / max(fe[copy]), true_kib / max(wr[copy])
+    out = {"fetch_factor": ff, "write_factor": fw, "passes": {}}
+    for label, key in (("A", "k_pass_a<float, 1024,"), ("B", "k_pass_b_lds<float, 1024, 8,"), ("C", "k_pass_c<float, 1024,")):
+        names = [k for k in fe if key in k]
+        if not names:
+            continue
+        name = max(names, key=lambda k: len(fe[k]))       # the variant the applies used most
+        f_kib = sum(fe[name]) / len(fe[name])
+        w_kib = sum(wr[name]) / len(wr[name])
+        out["passes"][label] = {"kernel": name.split("(")[0], "dispatches": len(fe[name]), "fetch_kib": f_kib,
+                                "write_kib": w_kib, "traffic_bytes": (f_kib * ff + w_kib * fw) * 1024}
+    out["sources_sha256"] = sources_digest()
+    out["kernel_variants_fp32"] = variants
+    return out
+
+
+def traffic_for(dom: str, variants):
+    """Counter-measured bytes per launch of pass `dom`, or None when no summary exists for the
+    current kernel sources and variant choice."""
+    try:
+        with open(TRAFFIC_JSON) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("sources_sha256") != sources_digest() or t.get("kernel_variants_fp32") != variants:
+        return None
+    p = t.get("passes", {}).get(dom)
+    return p["traffic_bytes"] if p else None
 
 
 def padded(n: int) -> int:
@@ -162,6 +222,9 @@ def bench_pc_workload(args, torch, rte, name, mu_s):
     n, L = base["n"], base["L"]
     ctx = rte.Context(n, mu_a=base["mu_a"], mu_s=base["mu_s"], sigma_hat=base["sigma_hat"], L=L,
                       prec=rte.PREC_FP32)
+    if args.force_variants:
+        for q, v in enumerate(json.loads(args.force_variants)):
+            ctx.set_variant(rte.PREC_FP32, q, int(v))
     fs = [torch.from_numpy(inputs.workload(name, seed=s, mu_s=mu_s)["f"]).cuda() for s in range(max(args.steps, 1))]
     torch.cuda.synchronize()
     plain = timed_solves(ctx, fs, args.steps, args.warmup, torch)
@@ -184,6 +247,16 @@ def bench_pc_workload(args, torch, rte, name, mu_s):
     ms64, pass64 = ctx.time_apply(rte.OP_A, rte.PREC_FP64, reps=max(5, args.apply_reps // 5))
     variants = {name: [list(ctx.get_variant(p, q)) for q in range(3)]
                 for name, p in (("fp32", rte.PREC_FP32), ("fp64", rte.PREC_FP64))}
+    dom = rf["roofline"]["kernel"].split()[-1]
+    if name == "hg512":
+        rf["roofline"]["traffic"] = traffic_for(dom, variants["fp32"])
+    # pass B is also arithmetic-heavy: FLOPs of its FFTs (5 N log2 N per complex transform, forward
+    # and inverse, C channels per column) and of the mode coupling ((2L+1)^2 complex MACs per
+    # frequency) against the FP32 vector peak
+    P = padded(n)
+    C = 2 * L + 1
+    flops_b = 2 * C * (P // 2) * 5 * P * int(np.log2(P)) + (P // 2) * P * C * C * 8
+    ach = flops_b / (rf["passes"]["B"] * 1e-3) / 1e12
     out = {
         "value": head["solves_per_s"], "unit": "solves/s", "ms_per_step": head["ms_per_solve"],
         "dtype": "f32 apply + f64 krylov",
@@ -202,6 +275,8 @@ def bench_pc_workload(args, torch, rte, name, mu_s):
         "apply_hbm_fraction": rf["apply_hbm_fraction"], "apply_bytes": apply_pass_bytes(n, L),
         "kernel_variants": variants,
         "roofline": rf["roofline"],
+        "roofline_alu_pass_B": {"bound": "alu", "achieved": ach, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                "frac": ach / FP32_VECTOR_PEAK_TFLOPS, "flops": flops_b},
     }
     return out, ctx, base, plain["applies"]
 
@@ -275,7 +350,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pc", action="store_true", help="time plain GMRES only")
     ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the per-launch HBM traffic summary of the hg512 apply passes from two "
+                         "rocprofv3 --pmc counter_collection.csv files (FETCH_SIZE, WRITE_SIZE) and exit; "
+                         "--variants gives the FP32 kernel variants of those runs")
+    ap.add_argument("--variants", default=None, help="JSON list of [variant, count] for passes A, B, C")
+    ap.add_argument("--force-variants", default=None,
+                    help="JSON list of the FP32 kernel variants of passes A, B, C to use instead of the tuned ones")
     args = ap.parse_args()
+    if args.pmc_summary:
+        t = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], json.loads(args.variants) if args.variants else None)
+        with open(TRAFFIC_JSON, "w") as fh:
+            json.dump(t, fh, indent=1)
+        print(json.dumps(t))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU "
               f"path", file=sys.stderr)
