@@ -149,33 +149,46 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
     constexpr int KH = PY / 2 + 1;
     constexpr int HY = PY / 2;
     const size_t cstride = (size_t)nkx * ny;
-    // spec[(col * C + c) * LD + sw(y)]; rows y < ny <= PY/2 come from memory, the rest is zero
-    constexpr int NL = NF * HY;
-    constexpr int IT = (NL + NTHR - 1) / NTHR;
-    cx<T> r[IT];
+    // Forward y-FFT of the NF = NCOL * C column sequences into spec[(col * C + c) * LD + sw(.)].
+    // Rows y >= ny (<= PY/2) are zero padding, so the first Stockham stage (radix R0, no twiddles)
+    // is done in registers straight from the loads: butterfly j takes inputs y = j + r PY/R0, of
+    // which only r < R0/2 can be non-zero, and writes its R0 outputs at j R0 + r.
+    constexpr int R0 = fft_radix(PY, 1);
+    constexpr int NB0 = PY / R0;
+    constexpr int NBT = NF * NB0;
+    constexpr int IT = (NBT + NTHR - 1) / NTHR;
+    cx<T> ld[IT][R0 / 2];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int idx = tid + it * NTHR;
-        const int y = idx % HY, fc = idx / HY;
+        const int j = idx % NB0, fc = idx / NB0;
         const int col = fc / C, c = fc % C;
         const int kx = kx0 + col;
-        const bool ok = (NL % NTHR == 0 || idx < NL) && y < ny && kx < nkx;
-        r[it] = ok ? base[c * cstride + (size_t)kx * ny + y] : mk((T)0, (T)0);
+        const bool ok = (NBT % NTHR == 0 || idx < NBT) && kx < nkx;
+#pragma unroll
+        for (int r = 0; r < R0 / 2; ++r) {
+            const int y = j + r * NB0;
+            ld[it][r] = (ok && y < ny) ? base[c * cstride + (size_t)kx * ny + y] : mk((T)0, (T)0);
+        }
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int idx = tid + it * NTHR;
-        if (NL % NTHR == 0 || idx < NL) {
-            const int y = idx % HY, fc = idx / HY;
-            spec[fc * LD + sw(y)] = r[it];
-            spec[fc * LD + sw(y + HY)] = mk((T)0, (T)0);
+        if (NBT % NTHR == 0 || idx < NBT) {
+            const int j = idx % NB0, fc = idx / NB0;
+            cx<T> v[R0];
+#pragma unroll
+            for (int r = 0; r < R0; ++r) v[r] = r < R0 / 2 ? ld[it][r] : mk((T)0, (T)0);
+            dft_small<T, R0, false>(v);
+#pragma unroll
+            for (int r = 0; r < R0; ++r) spec[fc * LD + sw(j * R0 + r)] = v[r];
         }
     }
     __syncthreads();
     // at most ~3 radix-8 butterflies per thread and stage, or groups of GV transforms if given
     constexpr int G0 = (3 * NTHR * 8) / PY >= NF ? NF : ((3 * NTHR * 8) / PY < 1 ? 1 : (3 * NTHR * 8) / PY);
     constexpr int G = GV > 0 ? (GV < NF ? GV : NF) : G0;
-    block_fft_grouped<T, PY, NF, G, LD, NTHR, false>(spec, tws, tid);
+    block_fft_grouped_range<T, PY, NF, G, LD, NTHR, false, R0, PY>(spec, tws, tid);
     const size_t qs = (size_t)nkq * KH;
 #pragma unroll 1
     for (int idx = tid; idx < NCOL * PY; idx += NTHR) {
@@ -211,12 +224,33 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
         }
     }
     __syncthreads();
-    block_fft_grouped<T, PY, NF, G, LD, NTHR, true>(spec, tws, tid);
-    for (int idx = tid; idx < NL; idx += NTHR) {
-        const int y = idx % HY, fc = idx / HY;
+    // Inverse y-FFT: every stage but the last in LDS; the last stage (sub-length NSL, radix RL) goes
+    // straight to memory, where only its outputs y = j + r NSL < ny are kept.
+    constexpr int NSL = fft_last_ns(PY);
+    constexpr int RL = PY / NSL;
+    block_fft_grouped_range<T, PY, NF, G, LD, NTHR, true, 1, NSL>(spec, tws, tid);
+    constexpr int TWL = stage_tw_offset(PY, NSL);
+    for (int idx = tid; idx < NF * NSL; idx += NTHR) {
+        const int j = idx % NSL, fc = idx / NSL;
         const int col = fc / C, c = fc % C;
         const int kx = kx0 + col;
-        if (y < ny && kx < nkx) base[c * cstride + (size_t)kx * ny + y] = spec[fc * LD + sw(y)];
+        cx<T> v[RL];
+#pragma unroll
+        for (int r = 0; r < RL; ++r) v[r] = spec[fc * LD + sw(j + r * NSL)];
+#pragma unroll
+        for (int r = 1; r < RL; ++r) {
+            cx<T> w = tws[TWL + j * (RL - 1) + (r - 1)];
+            w.im = -w.im;
+            v[r] = v[r] * w;
+        }
+        dft_small<T, RL, true>(v);
+        if (kx < nkx) {
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int y = j + r * NSL;
+                if (y < ny) base[c * cstride + (size_t)kx * ny + y] = v[r];
+            }
+        }
     }
 }
 

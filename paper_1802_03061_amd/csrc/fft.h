@@ -156,6 +156,32 @@ __device__ __forceinline__ void block_fft_grouped(cx<T>* buf, const cx<T>* tw, i
     }
 }
 
+// The stages with sub-transform length in [NS, NSEND) only (for transforms whose first stage is
+// fused into the load or whose last stage is fused into the store by the caller).
+template <typename T, int P, int NFFT, int LD, int NTHR, bool INV, int NS, int NSEND>
+__device__ __forceinline__ void fft_stages_range(cx<T>* buf, const cx<T>* tw, int tid) {
+    if constexpr (NS < NSEND) {
+        constexpr int R = fft_radix(P, NS);
+        fft_stage<T, P, NFFT, LD, NTHR, R, NS, INV>(buf, tw, tid);
+        fft_stages_range<T, P, NFFT, LD, NTHR, INV, NS * R, NSEND>(buf, tw, tid);
+    }
+}
+template <typename T, int P, int NFFT, int G, int LD, int NTHR, bool INV, int NS, int NSEND>
+__device__ __forceinline__ void block_fft_grouped_range(cx<T>* buf, const cx<T>* tw, int tid) {
+    if constexpr (NFFT <= G) {
+        fft_stages_range<T, P, NFFT, LD, NTHR, INV, NS, NSEND>(buf, tw, tid);
+    } else {
+        fft_stages_range<T, P, G, LD, NTHR, INV, NS, NSEND>(buf, tw, tid);
+        block_fft_grouped_range<T, P, NFFT - G, G, LD, NTHR, INV, NS, NSEND>(buf + G * LD, tw, tid);
+    }
+}
+// Sub-transform length of the last stage of a length-P transform.
+constexpr int fft_last_ns(int P) {
+    int ns = 1;
+    while (ns * fft_radix(P, ns) < P) ns *= fft_radix(P, ns);
+    return ns;
+}
+
 // Copy the P-entry twiddle table into LDS (all threads; followed by the caller's barrier).
 template <typename T, int P, int NTHR>
 __device__ __forceinline__ void stage_twiddles(cx<T>* tws, const cx<T>* __restrict__ tw, int tid) {
