@@ -63,42 +63,59 @@ __device__ __forceinline__ void pass_a_tile(const double* __restrict__ xin, cx<T
     constexpr int NP = TR / 2;        // complex FFTs per block (two real rows each)
     constexpr int LD = padded(PX) + 1;   // odd row pitch: the NP transforms start on different banks
     constexpr int H = PX / 2;
-    // rows y0+2p (real part) and y0+2p+1 (imaginary part); only m < nx <= PX/2 is non-zero
-    constexpr int NL = NP * H;
-    constexpr int IT = (NL + NTHR - 1) / NTHR;
-    double ra[IT], rb[IT];
+    // Rows y0+2p (real part) and y0+2p+1 (imaginary part); only m < nx <= PX/2 is non-zero, so the
+    // first Stockham stage (radix R0, no twiddles) runs in registers on the loads: butterfly j takes
+    // m = j + r PX/R0 (non-zero only for r < R0/2) and writes its R0 outputs at j R0 + r.
+    constexpr int R0 = fft_radix(PX, 1);
+    constexpr int NB0 = PX / R0;
+    constexpr int NBT = NP * NB0;
+    constexpr int IT = (NBT + NTHR - 1) / NTHR;
+    double ra[IT][R0 / 2], rb[IT][R0 / 2];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int idx = tid + it * NTHR;
-        const int p = idx / H, m = idx % H;
+        const int p = idx / NB0, j = idx % NB0;
         const int ya = y0 + 2 * p, yb = ya + 1;
-        const bool ok = (NL % NTHR == 0 || idx < NL) && m < nx;
-        ra[it] = (ok && ya < ny) ? xin[(size_t)ya * nx + m] : 0.0;
-        rb[it] = (ok && yb < ny) ? xin[(size_t)yb * nx + m] : 0.0;
+#pragma unroll
+        for (int r = 0; r < R0 / 2; ++r) {
+            const int m = j + r * NB0;
+            const bool ok = (NBT % NTHR == 0 || idx < NBT) && m < nx;
+            ra[it][r] = (ok && ya < ny) ? xin[(size_t)ya * nx + m] : 0.0;
+            rb[it][r] = (ok && yb < ny) ? xin[(size_t)yb * nx + m] : 0.0;
+        }
     }
     if (corr_c) {
         const int Hc = ny / cF, Wc = nx / cF;
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             const int idx = tid + it * NTHR;
-            const int p = idx / H, m = idx % H;
+            const int p = idx / NB0, j = idx % NB0;
             const int ya = y0 + 2 * p, yb = ya + 1;
-            const bool ok = (NL % NTHR == 0 || idx < NL) && m < nx;
-            if (ok && ya < ny) ra[it] += cs * (double)coarse_bilerp(corr_c, Hc, Wc, cF, ya, m);
-            if (ok && yb < ny) rb[it] += cs * (double)coarse_bilerp(corr_c, Hc, Wc, cF, yb, m);
+#pragma unroll
+            for (int r = 0; r < R0 / 2; ++r) {
+                const int m = j + r * NB0;
+                const bool ok = (NBT % NTHR == 0 || idx < NBT) && m < nx;
+                if (ok && ya < ny) ra[it][r] += cs * (double)coarse_bilerp(corr_c, Hc, Wc, cF, ya, m);
+                if (ok && yb < ny) rb[it][r] += cs * (double)coarse_bilerp(corr_c, Hc, Wc, cF, yb, m);
+            }
         }
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         const int idx = tid + it * NTHR;
-        if (NL % NTHR == 0 || idx < NL) {
-            const int p = idx / H, m = idx % H;
-            buf[p * LD + sw(m)] = mk((T)(s * ra[it]), (T)(s * rb[it]));
-            buf[p * LD + sw(m + H)] = mk((T)0, (T)0);
+        if (NBT % NTHR == 0 || idx < NBT) {
+            const int p = idx / NB0, j = idx % NB0;
+            cx<T> v[R0];
+#pragma unroll
+            for (int r = 0; r < R0; ++r)
+                v[r] = r < R0 / 2 ? mk((T)(s * ra[it][r]), (T)(s * rb[it][r])) : mk((T)0, (T)0);
+            dft_small<T, R0, false>(v);
+#pragma unroll
+            for (int r = 0; r < R0; ++r) buf[p * LD + sw(j * R0 + r)] = v[r];
         }
     }
     __syncthreads();
-    block_fft<T, PX, NP, LD, NTHR, false>(buf, tws, tid);
+    fft_stages_range<T, PX, NP, LD, NTHR, false, R0, PX>(buf, tws, tid);
     const int NKS = pack ? H : H + 1;
     for (int idx = tid; idx < NKS * TR; idx += NTHR) {
         const int yl = idx % TR, k = idx / TR;
@@ -196,38 +213,50 @@ __device__ __forceinline__ void pass_c_tile(const cx<T>* __restrict__ src, const
         }
     }
     __syncthreads();
-    block_fft<T, PX, NP, LD, NTHR, true>(buf, tws, tid);
-    // finalise in chunks of CH iterations so the batched loads stay in a modest register budget
-    constexpr int NO = TR * H;
-    constexpr int IO = (NO + NTHR - 1) / NTHR;
-    constexpr int CH = IO < 8 ? IO : 8;
-    for (int i0 = 0; i0 < IO; i0 += CH) {
-        double xv[CH], bv[CH];
+    // Inverse x-FFT: every stage but the last in LDS; the last stage (sub-length NSL, radix RL) is
+    // done per butterfly in registers and finalised at once.  Its outputs m = j + r NSL with
+    // r < RL/2 are the columns m < PX/2 (only m < nx are kept); the real part is row y0 + 2p, the
+    // imaginary part row y0 + 2p + 1.
+    constexpr int NSL = fft_last_ns(PX);
+    constexpr int RL = PX / NSL;
+    fft_stages_range<T, PX, NP, LD, NTHR, true, 1, NSL>(buf, tws, tid);
+    constexpr int TWL = stage_tw_offset(PX, NSL);
+    constexpr int NBT = NP * NSL;
+    const int Hc = corr_c ? ny / cF : 1, Wc = corr_c ? nx / cF : 1;
+    for (int idx = tid; idx < NBT; idx += NTHR) {
+        const int p = idx / NSL, j = idx % NSL;
+        const int ya = y0 + 2 * p, yb = ya + 1;
+        double xa_[RL / 2], xb_[RL / 2], ba_[RL / 2], bb_[RL / 2];
 #pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            const int idx = tid + (i0 + u) * NTHR;
-            const int yl = idx / H, m = idx % H;
-            const int y = y0 + yl;
-            const bool ok = idx < NO && m < nx && y < ny;
-            const size_t o = (size_t)y * nx + m;
-            xv[u] = (ok && mode != APPLY_KT) ? xin[o] : 0.0;
-            bv[u] = (ok && mode == APPLY_RESID) ? bin[o] : 0.0;
-            if (corr_c && ok) xv[u] += cs * (double)coarse_bilerp(corr_c, ny / cF, nx / cF, cF, y, m);
+        for (int r = 0; r < RL / 2; ++r) {
+            const int m = j + r * NSL;
+            const bool oka = m < nx && ya < ny, okb = m < nx && yb < ny;
+            xa_[r] = (oka && mode != APPLY_KT) ? xin[(size_t)ya * nx + m] : 0.0;
+            xb_[r] = (okb && mode != APPLY_KT) ? xin[(size_t)yb * nx + m] : 0.0;
+            ba_[r] = (oka && mode == APPLY_RESID) ? bin[(size_t)ya * nx + m] : 0.0;
+            bb_[r] = (okb && mode == APPLY_RESID) ? bin[(size_t)yb * nx + m] : 0.0;
+            if (corr_c && oka) xa_[r] += cs * (double)coarse_bilerp(corr_c, Hc, Wc, cF, ya, m);
+            if (corr_c && okb) xb_[r] += cs * (double)coarse_bilerp(corr_c, Hc, Wc, cF, yb, m);
         }
+        cx<T> v[RL];
 #pragma unroll
-        for (int u = 0; u < CH; ++u) {
-            const int idx = tid + (i0 + u) * NTHR;
-            const int yl = idx / H, m = idx % H;
-            const int y = y0 + yl;
-            if (idx < NO && m < nx && y < ny) {
-                const cx<T> z = buf[(yl >> 1) * LD + sw(m)];
-                const double v = (double)((yl & 1) ? z.im : z.re);
-                double r;
-                if (mode == APPLY_A) r = xv[u] - v;
-                else if (mode == APPLY_KT) r = v;
-                else r = bv[u] - xv[u] + v;       // APPLY_RESID: b - A x
-                yout[(size_t)y * nx + m] = r;
-            }
+        for (int r = 0; r < RL; ++r) v[r] = buf[p * LD + sw(j + r * NSL)];
+#pragma unroll
+        for (int r = 1; r < RL; ++r) {
+            cx<T> w = tws[TWL + j * (RL - 1) + (r - 1)];
+            w.im = -w.im;
+            v[r] = v[r] * w;
+        }
+        dft_small<T, RL, true>(v);
+#pragma unroll
+        for (int r = 0; r < RL / 2; ++r) {
+            const int m = j + r * NSL;
+            if (m >= nx) continue;
+            const double va = (double)v[r].re, vb = (double)v[r].im;
+            if (ya < ny)
+                yout[(size_t)ya * nx + m] = mode == APPLY_A ? xa_[r] - va : mode == APPLY_KT ? va : ba_[r] - xa_[r] + va;
+            if (yb < ny)
+                yout[(size_t)yb * nx + m] = mode == APPLY_A ? xb_[r] - vb : mode == APPLY_KT ? vb : bb_[r] - xb_[r] + vb;
         }
     }
 }
