@@ -51,6 +51,12 @@ __device__ __forceinline__ float coarse_bilerp(const float* __restrict__ yc, int
     return (1.f - ay) * top + ay * bot;
 }
 
+// Row tile of a block: workgroups are dispatched round-robin over the 8 XCDs (linear id mod 8), and
+// neighbouring tiles share 128-byte lines of the transposed spectrum (a tile reads or writes TR
+// consecutive rows of every column).  When the x-grid is a multiple of 8, XCD k is given the
+// contiguous tiles k G/8 .. (k+1) G/8 - 1 so that those lines meet in one L2.
+__device__ __forceinline__ int xcd_tile(int b, int G) { return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3); }
+
 // ---------------------------------------------------------------------------- pass A --------
 // With pack != 0 the x-frequencies 0 and PX/2, whose values are real for real rows, share
 // column 0 of T as (X[0], X[PX/2]); T then has PX/2 columns.
@@ -151,7 +157,7 @@ __global__ __launch_bounds__(NTHR) void k_pass_a(const double* __restrict__ x, c
     const int NKS = pack ? PX / 2 : PX / 2 + 1;
     const float* cc = corr ? corr + (size_t)(bc % C) * (ny / cF) * (nx / cF) : nullptr;
     pass_a_tile<T, PX, TR, NTHR>(x + (size_t)bc * ny * nx, Tb + (size_t)bc * NKS * ny, nx, ny, sc.s[bc % C], pack,
-                                 blockIdx.x * TR, buf, tws, tid, cc, cF, cs);
+                                 xcd_tile(blockIdx.x, gridDim.x) * TR, buf, tws, tid, cc, cF, cs);
 }
 
 // Batched form (isotropic problems of one padded size): one block per (problem, row tile).
@@ -276,7 +282,8 @@ __global__ __launch_bounds__(NTHR) void k_pass_c(const cx<T>* __restrict__ Tb, c
     const size_t base = (size_t)bc * ny * nx;
     const float* cc = corr ? corr + (size_t)(bc % C) * (ny / cF) * (nx / cF) : nullptr;
     pass_c_tile<T, PX, TR, NTHR>(Tb + (size_t)bc * NKS * ny, xin ? xin + base : nullptr, bin ? bin + base : nullptr,
-                                 yout + base, nx, ny, mode, pack, blockIdx.x * TR, buf, tws, tid, cc, cF, cs);
+                                 yout + base, nx, ny, mode, pack, xcd_tile(blockIdx.x, gridDim.x) * TR, buf, tws, tid,
+                                 cc, cF, cs);
 }
 
 // Batched form: one block per (problem, row tile); the output is written to out + (j + 1) stride

@@ -428,6 +428,19 @@ std::vector<std::unique_ptr<Plan>>& plans() {
 }
 constexpr size_t MAX_PLANS = 4;
 
+// Workgroups are dispatched round-robin over the 8 XCDs: block b runs on XCD b % 8.  Reorder an
+// item list so that XCD k executes a contiguous run of the original list (neighbouring row tiles
+// of a problem share 128-byte lines of its spectrum, which then meet in one L2).
+std::vector<int2> xcd_order(const std::vector<int2>& in) {
+    const size_t N = in.size(), q = N / 8, rem = N % 8;
+    std::vector<int2> out(N);
+    for (size_t b = 0; b < N; ++b) {
+        const size_t k = b % 8, l = b / 8;
+        out[b] = in[k * q + std::min(k, rem) + l];
+    }
+    return out;
+}
+
 template <typename X>
 X* carve(char* base, size_t& used, size_t n) {
     const size_t off = (used + 255) / 256 * 256;
@@ -468,6 +481,11 @@ int build_plan(Plan& pl, int P, rte_ctx* const* ctxs) {
         for (int t = 0; t < (c->ny + TRd - 1) / TRd; ++t) pl.cls_d[ci].ac.push_back(make_int2(p, t));
         for (int t = 0; t < (c->PX / 2 + NCd - 1) / NCd; ++t) pl.cls_d[ci].b.push_back(make_int2(p, t));
     }
+    for (auto* list : {&pl.cls, &pl.cls_d})
+        for (auto& k : *list) {
+            k.ac = xcd_order(k.ac);
+            k.b = xcd_order(k.b);
+        }
     const int NCH = pl.NCH = (int)pl.chunks.size();
     const size_t S = pl.S = (size_t)(m + 1) * m + 4 * (size_t)m + 2;   // Arnoldi slab per problem
     size_t items = 0;
