@@ -122,6 +122,7 @@ __global__ __launch_bounds__(64) void kb_hcol(const KryProb* __restrict__ kp, co
     const int j = *dj;
     for (int i = threadIdx.x; i <= j; i += 64) {
         double s = 0.0;
+#pragma unroll 8
         for (int c = 0; c < k.nc; ++c) s += partial[(size_t)(k.c0 + c) * (m + 1) + i];
         k.H[(size_t)j * (m + 1) + i] = s;
     }
@@ -172,22 +173,28 @@ __global__ __launch_bounds__(BT) void kb_update(const Chunk* __restrict__ ch, co
 }
 
 // H[j+1][j] = |w|, the previous Givens rotations and a new one on column j, the residual vector
-// g and the estimate |g[j+1]|; decides whether the problem keeps iterating.  One thread per problem.
-__global__ void kb_givens(const KryProb* __restrict__ kp, int* __restrict__ act, const int* __restrict__ dj,
-                          const double* __restrict__ part2, BState* __restrict__ bs, int m, int P,
-                          const int* __restrict__ dmax_iter) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+// g and the estimate |g[j+1]|; decides whether the problem keeps iterating.  One 64-lane block per
+// problem: the lanes sum the chunk partials of |w|^2 and the squares of H[.][j] (fixed-order
+// shuffle reduction), lane 0 applies the rotations.
+__global__ __launch_bounds__(64) void kb_givens(const KryProb* __restrict__ kp, int* __restrict__ act,
+                                                const int* __restrict__ dj, const double* __restrict__ part2,
+                                                BState* __restrict__ bs, int m, int P,
+                                                const int* __restrict__ dmax_iter) {
+    const int p = blockIdx.x;
     if (p >= P || !act[p]) return;
-    const int max_iter = *dmax_iter;
     const KryProb& k = kp[p];
-    BState& s = bs[p];
     const int j = *dj;
+    const int lane = threadIdx.x;
     double* Hj = k.H + (size_t)j * (m + 1);
-    double w2 = 0.0;
-    for (int c = 0; c < k.nc; ++c) w2 += part2[k.c0 + c];
+    double w2 = 0.0, h2 = 0.0;
+    for (int c = lane; c < k.nc; c += 64) w2 += part2[k.c0 + c];
+    for (int i = lane; i <= j; i += 64) h2 += Hj[i] * Hj[i];
+    w2 = wave_sum(w2);
+    h2 = wave_sum(h2);
+    if (lane != 0) return;
+    const int max_iter = *dmax_iter;
+    BState& s = bs[p];
     w2 = w2 > 0.0 ? w2 : 0.0;
-    double h2 = 0.0;
-    for (int i = 0; i <= j; ++i) h2 += Hj[i] * Hj[i];
     const double hn = sqrt(w2);
     Hj[j + 1] = hn;
     for (int i = 0; i < j; ++i) {
@@ -570,7 +577,7 @@ int build_plan(Plan& pl, int P, rte_ctx* const* ctxs) {
     hipLaunchKernelGGL(kb_dots, dim3(NCH), dim3(BT), 0, st, pl.d_ch, pl.d_kp, pl.d_act, pl.d_j, pl.d_part, m);
     hipLaunchKernelGGL(kb_hcol, dim3(P), dim3(64), 0, st, pl.d_kp, pl.d_act, pl.d_j, pl.d_part, m);
     hipLaunchKernelGGL(kb_update, dim3(NCH), dim3(BT), 0, st, pl.d_ch, pl.d_kp, pl.d_act, pl.d_j, pl.d_part2, m);
-    hipLaunchKernelGGL(kb_givens, dim3(gP), dim3(64), 0, st, pl.d_kp, pl.d_act, pl.d_j, pl.d_part2, pl.d_bs, m, P,
+    hipLaunchKernelGGL(kb_givens, dim3(P), dim3(64), 0, st, pl.d_kp, pl.d_act, pl.d_j, pl.d_part2, pl.d_bs, m, P,
                        pl.d_maxit);
     hipLaunchKernelGGL(kb_scale_next, dim3(NCH), dim3(BT), 0, st, pl.d_ch, pl.d_kp, pl.d_act, pl.d_j, pl.d_bs);
     hipLaunchKernelGGL(kb_tick, dim3(1), dim3(BT), 0, st, pl.d_j, pl.d_act, P, pl.h_cnt_dev);
