@@ -247,11 +247,13 @@ __device__ __forceinline__ void pass_c_tile(const cx<T>* __restrict__ src, const
         cx<T> v[RL];
 #pragma unroll
         for (int r = 0; r < RL; ++r) v[r] = buf[p * LD + sw(j + r * NSL)];
+        if constexpr (NSL > 1) {   // a single-stage transform has no twiddles
 #pragma unroll
-        for (int r = 1; r < RL; ++r) {
-            cx<T> w = tws[TWL + j * (RL - 1) + (r - 1)];
-            w.im = -w.im;
-            v[r] = v[r] * w;
+            for (int r = 1; r < RL; ++r) {
+                cx<T> w = tws[TWL + j * (RL - 1) + (r - 1)];
+                w.im = -w.im;
+                v[r] = v[r] * w;
+            }
         }
         dft_small<T, RL, true>(v);
 #pragma unroll

@@ -23,8 +23,10 @@ __device__ __forceinline__ int sw(int i) { return i + (i >> 4); }
 constexpr int padded(int P) { return P + P / 16; }
 
 constexpr int fft_radix(int P, int Ns) {
-    // log2 of what remains to be combined
-    return (ilog2(P) - ilog2(Ns)) % 3 == 1 ? 2 : ((ilog2(P) - ilog2(Ns)) % 3 == 2 ? 4 : 8);
+    // r = log2 of what remains to be combined: radix 8 stages, led by one radix-16 stage when
+    // r = 1 (mod 3) and r >= 4 (2 when r = 1), or one radix-4 stage when r = 2 (mod 3)
+    return (ilog2(P) - ilog2(Ns)) % 3 == 1 ? ((ilog2(P) - ilog2(Ns)) >= 4 ? 16 : 2)
+                                           : ((ilog2(P) - ilog2(Ns)) % 3 == 2 ? 4 : 8);
 }
 
 // Offset of the twiddles of the stage with sub-transform length NS (> 1) in the per-stage table;
@@ -57,6 +59,34 @@ __device__ __forceinline__ void dft_small(cx<T>* v) {
         v[2] = t0 - t2;
         v[1] = t1 + t3;
         v[3] = t1 - t3;
+    } else if constexpr (R == 16) {
+        // 16 = 4 x 4: v[4 n1 + n2] -> A[n2][k1] = DFT4 over n1, times W16^(n2 k1), then
+        // X[k1 + 4 k2] = DFT4 over n2.  W16^q = exp(-+2 pi i q / 16) for q = n2 k1 <= 9.
+        const T c1 = (T)0.92387953251128675612818318939679, s1 = (T)0.38268343236508977172845998403040;
+        const T c2 = (T)0.70710678118654752440084436210485;
+        const T wr[10] = {(T)1, c1, c2, s1, (T)0, -s1, -c2, -c1, (T)-1, -c1};
+        const T wi[10] = {(T)0, s1, c2, c1, (T)1, c1, c2, s1, (T)0, -s1};   // sin(2 pi q / 16)
+        cx<T> a[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < 4; ++n1) a[n2][n1] = v[4 * n1 + n2];
+            dft_small<T, 4, INV>(a[n2]);
+#pragma unroll
+            for (int k1 = 1; k1 < 4; ++k1) {
+                if (n2 == 0) continue;
+                const int q = n2 * k1;
+                const cx<T> w = mk(wr[q], INV ? wi[q] : -wi[q]);
+                a[n2][k1] = a[n2][k1] * w;
+            }
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            cx<T> b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+            dft_small<T, 4, INV>(b);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
+        }
     } else {  // R == 8: two 4-point DFTs on the even and odd samples, then W8^q
         cx<T> e[4] = {v[0], v[2], v[4], v[6]};
         cx<T> o[4] = {v[1], v[3], v[5], v[7]};
