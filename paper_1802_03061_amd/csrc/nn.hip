@@ -506,15 +506,16 @@ __global__ __launch_bounds__(256) void k_scale_pool(const double* __restrict__ w
     }
     part[threadIdx.x] = s;
     __syncthreads();
-    // coarse cells of this chunk: J = chunk * CW / F + q, q < CW / F
+    // coarse cells of this chunk: J = chunk * CW / F + q, q < CW / F; one wave per cell sums its
+    // RG x F column partials (fixed order: strided lanes, then a shuffle reduction)
     const int ncell = CW / F;
-    for (int q = threadIdx.x; q < ncell; q += 256) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int q = wave; q < ncell; q += 4) {
         const int J = chunk * ncell + q;
-        if (J >= Wc) continue;
         double t = 0.0;
-        for (int g = 0; g < RG; ++g)
-            for (int cc = 0; cc < F; ++cc) t += part[g * CW + q * F + cc];
-        coarse[((size_t)c * Hc + I) * Wc + J] = (float)(t / ((double)F * F));
+        for (int e = lane; e < RG * F; e += 64) t += part[(e / F) * CW + q * F + (e % F)];
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if (lane == 0 && J < Wc) coarse[((size_t)c * Hc + I) * Wc + J] = (float)(t / ((double)F * F));
     }
 }
 
