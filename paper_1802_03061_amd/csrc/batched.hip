@@ -336,6 +336,7 @@ __global__ __launch_bounds__(BT) void kb_combine(const Chunk* __restrict__ ch, c
     for (int e = threadIdx.x; e < c.len; e += BT) {
         const size_t o = (size_t)c.off + e;
         double s = k.x[o];
+#pragma unroll 8
         for (int i = 0; i < jd; ++i) s += y[i] * k.V[(size_t)i * k.nvec + o];
         k.x[o] = s;
     }

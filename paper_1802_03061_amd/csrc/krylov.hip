@@ -90,6 +90,8 @@ __global__ __launch_bounds__(KT) void k_cgs_update(double* __restrict__ w, const
     const size_t stride = (size_t)gridDim.x * KT;
     for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) {
         double s = w[i];
+        // unrolled so that eight basis loads are in flight; subtraction order unchanged
+#pragma unroll 8
         for (int v = 0; v < nvec; ++v) s -= V[(size_t)v * ld + i] * hs[v];
         w[i] = s;
         nrm += s * s;
@@ -107,6 +109,7 @@ __global__ __launch_bounds__(KT) void k_combine(double* __restrict__ x, const do
     const size_t stride = (size_t)gridDim.x * KT;
     for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) {
         double s = x[i];
+#pragma unroll 8
         for (int v = 0; v < nvec; ++v) s += Z[(size_t)v * ld + i] * ys[v];
         x[i] = s;
     }
