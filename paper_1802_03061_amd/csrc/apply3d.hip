@@ -22,13 +22,12 @@ __global__ __launch_bounds__(NTHR) void k_pass3_b(const cx<T>* __restrict__ T1, 
     const int tid = threadIdx.x;
     const int kx = blockIdx.x, z0 = blockIdx.y * TZ;
     stage_twiddles<T, PY, NTHR>(tws, tw, tid);
-    for (int idx = tid; idx < TZ * PY; idx += NTHR) {
-        const int zl = idx / PY, y = idx % PY;
-        const int z = z0 + zl;
-        buf[zl * LD + sw(y)] = (z < nz && y < ny) ? T1[((size_t)z * nkx + kx) * ny + y] : mk((T)0, (T)0);
-    }
     __syncthreads();
-    block_fft<T, PY, TZ, LD, NTHR, false>(buf, tws, tid);
+    // rows y >= ny are zero padding: the first stage is computed from the loads
+    fft_forward_padded<T, PY, TZ, LD, NTHR>(buf, tws, tid, [&](int zl, int y) {
+        const int z = z0 + zl;
+        return (z < nz && y < ny) ? T1[((size_t)z * nkx + kx) * ny + y] : mk((T)0, (T)0);
+    });
     for (int idx = tid; idx < TZ * PY; idx += NTHR) {
         const int zl = idx % TZ, ky = idx / TZ;
         const int z = z0 + zl;
@@ -46,30 +45,34 @@ __global__ __launch_bounds__(NTHR) void k_pass3_c(cx<T>* __restrict__ T2, const 
     const size_t c0 = (size_t)blockIdx.x * NC;
     const int HY = PY / 2 + 1, HZ = PZ / 2 + 1;
     stage_twiddles<T, PZ, NTHR>(tws, tw, tid);
-    for (int idx = tid; idx < NC * PZ; idx += NTHR) {
-        const int c = idx / PZ, z = idx % PZ;
+    __syncthreads();
+    // entries z >= nz are zero padding; only z < nz are kept after the inverse transform
+    fft_forward_padded<T, PZ, NC, LD, NTHR>(buf, tws, tid, [&](int c, int z) {
         const size_t col = c0 + c;
-        buf[c * LD + sw(z)] = (col < ncol && z < nz) ? T2[col * nz + z] : mk((T)0, (T)0);
+        return (col < ncol && z < nz) ? T2[col * nz + z] : mk((T)0, (T)0);
+    });
+    // spectrum row of each of the block's columns, decoded once (col = kx PY + ky)
+    __shared__ int qrow[NC];
+    if (tid < NC) {
+        const int col = (int)(c0 + tid);
+        const int kx = col / PY, ky = col % PY;
+        const int fy = ky <= PY / 2 ? ky : PY - ky;
+        qrow[tid] = (col < (int)ncol) ? (kx * HY + fy) * HZ : -1;
     }
     __syncthreads();
-    block_fft<T, PZ, NC, LD, NTHR, false>(buf, tws, tid);
     for (int idx = tid; idx < NC * PZ; idx += NTHR) {
         const int c = idx / PZ, kz = idx % PZ;
-        const size_t col = c0 + c;
-        if (col < ncol) {
-            const int kx = (int)(col / PY), ky = (int)(col % PY);
-            const int fy = ky <= PY / 2 ? ky : PY - ky;
+        const int q = qrow[c];
+        if (q >= 0) {
             const int fz = kz <= PZ / 2 ? kz : PZ - kz;
-            buf[c * LD + sw(kz)] = scale(buf[c * LD + sw(kz)], Q3[((size_t)kx * HY + fy) * HZ + fz]);
+            buf[c * LD + sw(kz)] = scale(buf[c * LD + sw(kz)], Q3[(size_t)q + fz]);
         }
     }
     __syncthreads();
-    block_fft<T, PZ, NC, LD, NTHR, true>(buf, tws, tid);
-    for (int idx = tid; idx < NC * PZ; idx += NTHR) {
-        const int c = idx / PZ, z = idx % PZ;
+    fft_inverse_cropped<T, PZ, NC, LD, NTHR>(buf, tws, tid, [&](int c, int z, cx<T> v) {
         const size_t col = c0 + c;
-        if (col < ncol && z < nz) T2[col * nz + z] = buf[c * LD + sw(z)];
-    }
+        if (col < ncol && z < nz) T2[col * nz + z] = v;
+    });
 }
 
 template <typename T, int PY, int TZ, int NTHR>
@@ -87,12 +90,11 @@ __global__ __launch_bounds__(NTHR) void k_pass3_d(cx<T>* __restrict__ T1, const 
         buf[zl * LD + sw(ky)] = z < nz ? T2[((size_t)kx * PY + ky) * nz + z] : mk((T)0, (T)0);
     }
     __syncthreads();
-    block_fft<T, PY, TZ, LD, NTHR, true>(buf, tws, tid);
-    for (int idx = tid; idx < TZ * ny; idx += NTHR) {
-        const int zl = idx / ny, y = idx % ny;
+    // only rows y < ny are kept: the last inverse stage writes them directly
+    fft_inverse_cropped<T, PY, TZ, LD, NTHR>(buf, tws, tid, [&](int zl, int y, cx<T> v) {
         const int z = z0 + zl;
-        if (z < nz) T1[((size_t)z * nkx + kx) * ny + y] = buf[zl * LD + sw(y)];
-    }
+        if (z < nz && y < ny) T1[((size_t)z * nkx + kx) * ny + y] = v;
+    });
 }
 
 template <typename T> constexpr int tz_rows() { return sizeof(T) == 4 ? 16 : 8; }

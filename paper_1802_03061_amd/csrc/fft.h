@@ -212,6 +212,69 @@ constexpr int fft_last_ns(int P) {
     return ns;
 }
 
+// Forward transforms of NFFT sequences whose entries y >= P/2 are zero (zero padding): the first
+// stage (radix R0, no twiddles) is computed in registers from ld(f, y), y < P/2 (the functor returns
+// zero past the data), and written to buf; the remaining stages run in LDS.  Ends with a barrier.
+template <typename T, int P, int NFFT, int LD, int NTHR, typename Ld>
+__device__ __forceinline__ void fft_forward_padded(cx<T>* buf, const cx<T>* tws, int tid, Ld ld) {
+    constexpr int R0 = fft_radix(P, 1);
+    constexpr int NB0 = P / R0;
+    constexpr int NBT = NFFT * NB0;
+    constexpr int IT = (NBT + NTHR - 1) / NTHR;
+    cx<T> in[IT][R0 / 2];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int idx = tid + it * NTHR;
+        const int f = idx / NB0, j = idx % NB0;
+#pragma unroll
+        for (int r = 0; r < R0 / 2; ++r)
+            in[it][r] = (NBT % NTHR == 0 || idx < NBT) ? ld(f, j + r * NB0) : mk((T)0, (T)0);
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int idx = tid + it * NTHR;
+        if (NBT % NTHR == 0 || idx < NBT) {
+            const int f = idx / NB0, j = idx % NB0;
+            cx<T> v[R0];
+#pragma unroll
+            for (int r = 0; r < R0; ++r) v[r] = r < R0 / 2 ? in[it][r] : mk((T)0, (T)0);
+            dft_small<T, R0, false>(v);
+#pragma unroll
+            for (int r = 0; r < R0; ++r) buf[f * LD + sw(j * R0 + r)] = v[r];
+        }
+    }
+    __syncthreads();
+    fft_stages_range<T, P, NFFT, LD, NTHR, false, R0, P>(buf, tws, tid);
+}
+
+// Inverse transforms of the NFFT sequences in buf of which only outputs y < P/2 are wanted: every
+// stage but the last in LDS, the last in registers, handing y = j + r NSL (r < RL/2) to
+// st(f, y, value) (the functor skips y past the data).  No barrier at the end.
+template <typename T, int P, int NFFT, int LD, int NTHR, typename St>
+__device__ __forceinline__ void fft_inverse_cropped(cx<T>* buf, const cx<T>* tws, int tid, St st) {
+    constexpr int NSL = fft_last_ns(P);
+    constexpr int RL = P / NSL;
+    fft_stages_range<T, P, NFFT, LD, NTHR, true, 1, NSL>(buf, tws, tid);
+    constexpr int TWL = stage_tw_offset(P, NSL);
+    for (int idx = tid; idx < NFFT * NSL; idx += NTHR) {
+        const int j = idx % NSL, f = idx / NSL;
+        cx<T> v[RL];
+#pragma unroll
+        for (int r = 0; r < RL; ++r) v[r] = buf[f * LD + sw(j + r * NSL)];
+        if constexpr (NSL > 1) {
+#pragma unroll
+            for (int r = 1; r < RL; ++r) {
+                cx<T> w = tws[TWL + j * (RL - 1) + (r - 1)];
+                w.im = -w.im;
+                v[r] = v[r] * w;
+            }
+        }
+        dft_small<T, RL, true>(v);
+#pragma unroll
+        for (int r = 0; r < RL / 2; ++r) st(f, j + r * NSL, v[r]);
+    }
+}
+
 // Copy the P-entry twiddle table into LDS (all threads; followed by the caller's barrier).
 template <typename T, int P, int NTHR>
 __device__ __forceinline__ void stage_twiddles(cx<T>* tws, const cx<T>* __restrict__ tw, int tid) {
