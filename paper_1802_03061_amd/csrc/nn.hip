@@ -26,6 +26,7 @@
 namespace rte {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ unsigned short f2bf(float f) {   // round to nearest even
@@ -273,16 +274,16 @@ __global__ __launch_bounds__(256) void k_scale_from_partials(const double* __res
 
 // The whole network in one workgroup for a small coarse grid (Hc <= 32 rows, Wc <= 32).
 // Activations stay in LDS as BF16, channel-innermost ([pixel][channel], pixel stride NET_PS shorts,
-// zero halo and zero padded channels), so that for one 3x3 tap the four consecutive K values a
-// lane feeds to the MFMA are one 8-byte LDS read.  The reduction index is tap-major,
-// k = t * CP + c (CP: input channels rounded up to 8, so an 8-wide K step never straddles taps).
+// zero halo and zero padded channels), so that for one 3x3 tap the eight consecutive K values a
+// lane feeds to the MFMA are one 16-byte LDS read.  The reduction index is tap-major,
+// k = t * CP + c (CP: input channels rounded up to 8, so a K step never straddles taps).
 // Every layer's weights are loaded into LDS up front (tap-major rows of stride KS, prepacked by
 // k_pack_tapmajor), so the only global reads are that copy, the input and the biases.  One wave per
 // coarse row; the last layer writes FP32 [c][y][x] to global memory.
 constexpr int NET_THREADS = 1024;
-constexpr int NET_PS = 36;                  // pixel stride in shorts: 32 channels + 4 (bank spread)
+constexpr int NET_PS = 40;                  // pixel stride in shorts: 32 channels + 8 (16-byte aligned, bank spread)
 __host__ __device__ constexpr int net_cp(int c) { return (c + 7) / 8 * 8; }
-__host__ __device__ constexpr int net_ks(int cin) { return 9 * net_cp(cin) + 4; }   // weight row stride
+__host__ __device__ constexpr int net_ks(int cin) { return 9 * net_cp(cin) + 8; }   // weight row stride
 
 // dst[i][k] (row stride KS) = weight of output i, tap t = k / CP, input channel c = k % CP, taken
 // from the forward pack (k' = c*9 + t, stride KG); zero for padded channels and the row tail.
@@ -300,29 +301,38 @@ __global__ void k_pack_tapmajor(const unsigned short* __restrict__ wf, int cin, 
 }
 
 // One output row y of a layer: D[32 out][32 columns] = W[32][9 CP] x B[9 CP][32] on MFMA, the
-// reduction walked tap by tap (t = 3 dy + dx) and, within a tap, 8 channels per MFMA, so every
-// LDS address is a base plus an immediate offset.  Lanes past the row edge read a valid pixel
+// reduction walked tap by tap (t = 3 dy + dx) and, within a tap, 16 channels per MFMA (8 for a
+// remainder), so every LDS address is a base plus an immediate offset.  Lanes past the row edge read a valid pixel
 // (their outputs are discarded).
 template <int CP>
 __device__ __forceinline__ f32x16 net_row(const unsigned short* __restrict__ Wl, const unsigned short* __restrict__ src,
                                           int y, int j, int hi, int Wc) {
+    // K steps of 16 on v_mfma_f32_32x32x16_bf16 (lane l holds k = 8 (l / 32) .. +7 of row / column
+    // l % 32), and for CP = 8 (mod 16) one last step of 8 on the 32x32x8 form (k = 4 (l / 32) .. +3)
     constexpr int KS = net_ks(CP);
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
     const int jj = j < Wc ? j : Wc - 1;
-    const unsigned short* arow = Wl + j * KS + 4 * hi;
-    const unsigned short* brow = src + ((size_t)y * (Wc + 2) + jj) * NET_PS + 4 * hi;
+    const unsigned short* arow = Wl + j * KS;
+    const unsigned short* brow = src + ((size_t)y * (Wc + 2) + jj) * NET_PS;
 #pragma unroll 1
     for (int dy = 0; dy < 3; ++dy) {
         const unsigned short* bd = brow + dy * (Wc + 2) * NET_PS;
         const unsigned short* ad = arow + 3 * dy * CP;
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
+            const unsigned short* at = ad + dx * CP;
+            const unsigned short* bt = bd + dx * NET_PS;
 #pragma unroll
-            for (int cb = 0; cb < CP / 8; ++cb) {
-                const bf16x4 a = *reinterpret_cast<const bf16x4*>(ad + dx * CP + cb * 8);
-                const bf16x4 bv = *reinterpret_cast<const bf16x4*>(bd + dx * NET_PS + cb * 8);
+            for (int cb = 0; cb < CP / 16; ++cb) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(at + cb * 16 + 8 * hi);
+                const bf16x8 bv = *reinterpret_cast<const bf16x8*>(bt + cb * 16 + 8 * hi);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc, 0, 0, 0);
+            }
+            if constexpr (CP % 16 != 0) {
+                const bf16x4 a = *reinterpret_cast<const bf16x4*>(at + (CP / 16) * 16 + 4 * hi);
+                const bf16x4 bv = *reinterpret_cast<const bf16x4*>(bt + (CP / 16) * 16 + 4 * hi);
                 acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bv, acc, 0, 0, 0);
             }
         }
@@ -339,7 +349,7 @@ __global__ __launch_bounds__(NET_THREADS) void k_net_fused(const float* __restri
     // meta: per layer [cin, cout, tap-major pack offset, bias offset into bias_all]; nwn: pack length
     // (multiple of 8 shorts); all of it is staged in LDS first, with every global load of the
     // prologue in flight together (the kernel is latency-bound: one workgroup).
-    static_assert(HID <= 32 && NET_PS >= 32 + 4, "pixel stride");
+    static_assert(HID <= 32 && NET_PS >= 32 + 8 && NET_PS % 8 == 0, "pixel stride");
     extern __shared__ __attribute__((aligned(16))) unsigned short lds[];
     __shared__ int smeta[4 * 8];
     __shared__ float sbias[8 * 32];

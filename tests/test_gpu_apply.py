@@ -52,6 +52,25 @@ def test_apply_modes_small_vs_direct_sum(rte, L, ny, nx, prec):
     ctx.close()
 
 
+@pytest.mark.parametrize("L,ny,nx", [(3, 96, 200), (1, 150, 40)])
+@pytest.mark.parametrize("prec", [1, 0])
+def test_apply_nonsquare_vs_oracle_fft(rte, L, ny, nx, prec):
+    """Non-square grids (different padded sizes in x and y, ragged row tiles and column groups)
+    against the oracle's FP64 FFT apply."""
+    say("apply nonsquare", L, ny, nx, "prec", prec)
+    rng = np.random.default_rng(ny + nx + L)
+    h = 1.0 / max(nx, ny)
+    mu_a, mu_s = 0.1, 3.0
+    ctx, sh = _ctx(rte, (nx, ny), L, mu_a=mu_a, mu_s=mu_s, prec=prec, h=h)
+    u = inputs.random_conj_symmetric_modes(rng, L, max(nx, ny))[:, :ny, :nx].copy()
+    y = host(ctx.apply(dev(u), op=rte.OP_A))
+    ref = op2.apply_fft(u, L, h, mu_a + mu_s, mu_s, sh, "A")
+    e = relerr(y, ref)
+    say("  relerr", e)
+    assert e <= (TOL64 if prec == 1 else TOL32)
+    ctx.close()
+
+
 @pytest.mark.parametrize("L,n", [(8, 64), (4, 100), (0, 128), (2, 33)])
 @pytest.mark.parametrize("prec", [1, 0])
 def test_apply_mid_vs_oracle_fft(rte, L, n, prec):
