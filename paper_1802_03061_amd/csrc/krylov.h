@@ -7,21 +7,42 @@
 
 namespace rte {
 
-// out[v] = <V_v, w> for v < nvec (V_v = V + v*ld); out[nvec] = <w, w> if with_norm.
+// Arguments of one Arnoldi column on the device (k_arnoldi in krylov.hip): the Hessenberg column
+// j of a restart length m, the Givens rotations, the residual vector g and the flags.
+struct ArnoldiArgs {
+    int stage = 0, j = 0, m = 0, reorth = 0, fused = 0;
+    double renorm_tol = 1e-10;
+    double* st = nullptr;
+    double* H = nullptr;
+    double* cs = nullptr;
+    double* sn = nullptr;
+    double* g = nullptr;
+    double* est = nullptr;
+    double* inv = nullptr;
+    int* flags = nullptr;
+    double* est_out = nullptr;
+    int* flags_out = nullptr;
+};
+
+// Blocks of the dot and update kernels for vectors of n entries (rows of their partial sums).
+unsigned krylov_nblk(size_t n);
+// out[v] = <V_v, w> for v < nvec (V_v = V + v*ld); out[nvec] = <w, w> if with_norm.  With out NULL
+// only the per-block partial sums are written (row v of krylov_nblk(n) entries).
 // partial needs (nvec + 1) * RTE_KRYLOV_NBLK doubles.
 // active (device int, may be null): the kernels do nothing when *active == 0.
 void krylov_dots(const double* V, size_t ld, int nvec, const double* w, size_t n, double* partial,
                  double* out, bool with_norm, hipStream_t st, const int* active = nullptr);
-// w -= sum_v h[v] V_v (h on the device); *norm_out = <w, w> after the update.
+// w = a (w - sum_v h[v] V_v) (h on the device; a = *scale, 1 when scale is NULL);
+// *norm_out = <w, w> after the update (with norm_out NULL only partial row 0 is written).
 void krylov_update(double* w, const double* V, size_t ld, int nvec, const double* h, size_t n, double* partial,
-                   double* norm_out, hipStream_t st, const int* active = nullptr);
-void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hipStream_t st);
-// Device-side Arnoldi bookkeeping for column j (see k_arnoldi in krylov.hip).
-// stage 1 also writes the iteration's estimate and (breakdown, non-finite) flags to est_out and
-// flags_out (device-visible host memory, may be NULL) for the host's convergence check.
-void arnoldi_step(int stage, int j, int m, double* st, double* H, double* cs, double* sn, double* g, double* est,
-                  double* inv, int* flags, int reorth, hipStream_t s, double* est_out = nullptr,
-                  int* flags_out = nullptr);
+                   double* norm_out, hipStream_t st, const int* active = nullptr, const double* scale = nullptr);
+// dst = (*a) src; nothing when active is given and *active == 0
+void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hipStream_t st,
+                   const int* active = nullptr);
+// out[v] = sum_b partial[v * nblk + b] for v < nout, in a fixed order
+void reduce_partials(const double* partial, int nblk, double* out, int nout, hipStream_t st);
+// One Arnoldi column on the device (see k_arnoldi in krylov.hip).
+void arnoldi_run(const ArnoldiArgs& t, hipStream_t s);
 // x += sum_v y[v] Z_v (y on the device)
 void krylov_combine(double* x, const double* Z, size_t ld, int nvec, const double* y, size_t n, hipStream_t st);
 void vec_scale(double* dst, const double* src, double a, size_t n, hipStream_t st);

@@ -4,12 +4,14 @@
 //
 // Reductions are deterministic: a fixed grid of blocks writes one partial per (vector, block) and
 // a second kernel adds the partials in a fixed order, so repeated runs give bitwise equal sums.
+#include <algorithm>
+
 #include "krylov.h"
 
 namespace rte {
 
 constexpr int KT = 256;           // threads per block
-constexpr int VB = 8;             // basis vectors per dot block
+constexpr int VB = 16;            // basis vectors per dot block
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -31,37 +33,75 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return r;
 }
 
-// partial[v * nblk + blk] = sum over the block's slice of V[v][i] * w[i], v < nvec; an extra row
-// v = nvec holds sum w[i]^2 when with_norm.
-__global__ __launch_bounds__(KT) void k_dot_partial(const double* __restrict__ V, size_t ld, int nvec,
+// partial[v * nblk + blk] = sum over the block's slice of V[v][i] * w[i] for the NV vectors V[v]
+// (v < NV, row stride ld), and norm_partial[blk] = sum of w[i]^2 over the slice when norm_partial
+// is given.  The vector count is a template parameter so that every load of a step is issued before
+// the first multiply.  With even n and ld (and 16-byte aligned V and w) each thread reads element
+// pairs as 16-byte loads.  The slice a block covers and the order of its sums do not depend on the data.
+template <int NV, bool PAIRS>
+__global__ __launch_bounds__(KT) void k_dot_partial(const double* __restrict__ V, size_t ld,
                                                     const double* __restrict__ w, size_t n,
-                                                    double* __restrict__ partial, int with_norm,
+                                                    double* __restrict__ partial,
+                                                    double* __restrict__ norm_partial,
                                                     const int* __restrict__ active) {
     __shared__ double sh[KT / 64];
     if (active && *active == 0) return;
     const int nblk = gridDim.x;
-    const int v0 = blockIdx.y * VB;
-    const int nv = min(VB, nvec - v0);
-    const bool do_norm = with_norm && blockIdx.y == 0;
-    double acc[VB];
+    const bool do_norm = norm_partial != nullptr;
+    double acc[NV > 0 ? NV : 1];
 #pragma unroll
-    for (int v = 0; v < VB; ++v) acc[v] = 0.0;
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
     double nrm = 0.0;
     const size_t stride = (size_t)nblk * KT;
-    for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) {
-        const double wi = w[i];
-        if (do_norm) nrm += wi * wi;
+    if constexpr (PAIRS) {
+        const size_t np = n / 2, ldp = ld / 2;
+        const double2* w2 = reinterpret_cast<const double2*>(w);
+        const double2* V2 = reinterpret_cast<const double2*>(V);
+        for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < np; i += stride) {
+            const double2 wa = w2[i];
+            double2 a[NV > 0 ? NV : 1];
 #pragma unroll
-        for (int v = 0; v < VB; ++v)
-            if (v < nv) acc[v] += V[(size_t)(v0 + v) * ld + i] * wi;
+            for (int v = 0; v < NV; ++v) a[v] = V2[(size_t)v * ldp + i];
+            if (do_norm) nrm += wa.x * wa.x + wa.y * wa.y;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] += a[v].x * wa.x + a[v].y * wa.y;
+        }
+    } else {
+        for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) {
+            const double wi = w[i];
+            double a[NV > 0 ? NV : 1];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) a[v] = V[(size_t)v * ld + i];
+            if (do_norm) nrm += wi * wi;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] += a[v] * wi;
+        }
     }
-    for (int v = 0; v < nv; ++v) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
         const double s = block_sum(acc[v], sh);
-        if (threadIdx.x == 0) partial[(size_t)(v0 + v) * nblk + blockIdx.x] = s;
+        if (threadIdx.x == 0) partial[(size_t)v * nblk + blockIdx.x] = s;
     }
     if (do_norm) {
         const double s = block_sum(nrm, sh);
-        if (threadIdx.x == 0) partial[(size_t)nvec * nblk + blockIdx.x] = s;
+        if (threadIdx.x == 0) norm_partial[blockIdx.x] = s;
+    }
+}
+
+template <bool PAIRS>
+static void launch_dots(int nv, unsigned nblk, hipStream_t st, const double* V, size_t ld, const double* w, size_t n,
+                        double* partial, double* norm_partial, const int* active) {
+    switch (nv) {
+#define RTE_DOTS_CASE(K)                                                                                     \
+    case K:                                                                                                  \
+        hipLaunchKernelGGL((k_dot_partial<K, PAIRS>), dim3(nblk), dim3(KT), 0, st, V, ld, w, n, partial,     \
+                           norm_partial, active);                                                            \
+        break;
+        RTE_DOTS_CASE(0) RTE_DOTS_CASE(1) RTE_DOTS_CASE(2) RTE_DOTS_CASE(3) RTE_DOTS_CASE(4) RTE_DOTS_CASE(5)
+        RTE_DOTS_CASE(6) RTE_DOTS_CASE(7) RTE_DOTS_CASE(8) RTE_DOTS_CASE(9) RTE_DOTS_CASE(10) RTE_DOTS_CASE(11)
+        RTE_DOTS_CASE(12) RTE_DOTS_CASE(13) RTE_DOTS_CASE(14) RTE_DOTS_CASE(15) RTE_DOTS_CASE(16)
+#undef RTE_DOTS_CASE
+        default: break;
     }
 }
 
@@ -71,30 +111,60 @@ __global__ __launch_bounds__(KT) void k_reduce_partials(const double* __restrict
     __shared__ double sh[KT / 64];
     if (active && *active == 0) return;
     const int v = blockIdx.x;
+    const double* __restrict__ p = partial + (size_t)v * nblk;
     double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += KT) s += partial[(size_t)v * nblk + b];
+    int b = threadIdx.x;
+    for (; b + 3 * KT < nblk; b += 4 * KT) {   // four loads in flight per step
+        const double a0 = p[b], a1 = p[b + KT], a2 = p[b + 2 * KT], a3 = p[b + 3 * KT];
+        s += (a0 + a1) + (a2 + a3);
+    }
+    for (; b < nblk; b += KT) s += p[b];
     s = block_sum(s, sh);
     if (threadIdx.x == 0) out[v] = s;
 }
 
-// w[i] -= sum_v V[v][i] h[v]; partial_norm[blk] = sum over the slice of w_new[i]^2.
+// w[i] = a (w[i] - sum_v V[v][i] h[v]) with a = *scale (1 when scale is NULL); partial_norm[blk] =
+// sum over the slice of the new w[i]^2.  PAIRS: as in k_dot_partial, element pairs as 16-byte loads.
+template <bool PAIRS>
 __global__ __launch_bounds__(KT) void k_cgs_update(double* __restrict__ w, const double* __restrict__ V, size_t ld,
                                                    int nvec, const double* __restrict__ h, size_t n,
-                                                   double* __restrict__ partial_norm, const int* __restrict__ active) {
+                                                   double* __restrict__ partial_norm, const int* __restrict__ active,
+                                                   const double* __restrict__ scale) {
     __shared__ double sh[KT / 64];
     __shared__ double hs[RTE_KRYLOV_MAXVEC];
     if (active && *active == 0) return;
     for (int v = threadIdx.x; v < nvec; v += KT) hs[v] = h[v];
+    const double a = scale ? *scale : 1.0;
     __syncthreads();
     double nrm = 0.0;
     const size_t stride = (size_t)gridDim.x * KT;
-    for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) {
-        double s = w[i];
-        // unrolled so that eight basis loads are in flight; subtraction order unchanged
+    if constexpr (PAIRS) {
+        const size_t np = n / 2, ldp = ld / 2;
+        double2* w2 = reinterpret_cast<double2*>(w);
+        const double2* V2 = reinterpret_cast<const double2*>(V);
+        for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < np; i += stride) {
+            double2 s = w2[i];
 #pragma unroll 8
-        for (int v = 0; v < nvec; ++v) s -= V[(size_t)v * ld + i] * hs[v];
-        w[i] = s;
-        nrm += s * s;
+            for (int v = 0; v < nvec; ++v) {
+                const double2 b = V2[(size_t)v * ldp + i];
+                s.x -= b.x * hs[v];
+                s.y -= b.y * hs[v];
+            }
+            s.x *= a;
+            s.y *= a;
+            w2[i] = s;
+            nrm += s.x * s.x + s.y * s.y;
+        }
+    } else {
+        for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) {
+            double s = w[i];
+            // unrolled so that eight basis loads are in flight; subtraction order unchanged
+#pragma unroll 8
+            for (int v = 0; v < nvec; ++v) s -= V[(size_t)v * ld + i] * hs[v];
+            s *= a;
+            w[i] = s;
+            nrm += s * s;
+        }
     }
     const double t = block_sum(nrm, sh);
     if (threadIdx.x == 0) partial_norm[blockIdx.x] = t;
@@ -115,63 +185,126 @@ __global__ __launch_bounds__(KT) void k_combine(double* __restrict__ x, const do
     }
 }
 
-// dst[i] = (*a) * src[i] with the factor read from device memory
+// dst[i] = (*a) * src[i] with the factor read from device memory; nothing when *active == 0
 __global__ __launch_bounds__(KT) void k_scale_dev(double* __restrict__ dst, const double* __restrict__ src,
-                                                  const double* __restrict__ a, size_t n) {
+                                                  const double* __restrict__ a, size_t n, const int* __restrict__ active) {
+    if (active && *active == 0) return;
     const double s = *a;
     const size_t stride = (size_t)gridDim.x * KT;
     for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) dst[i] = s * src[i];
 }
 
-// One Arnoldi column on the device.  stage 0: after the first Gram-Schmidt pass, decide whether
-// a second pass runs (reorth 2: always; 1: when the norm fell below 1/sqrt2 of its value; 0: never)
-// and store h into H[:, j].
+constexpr int ARN_MAXROW = RTE_KRYLOV_MAXVEC + 2;   // column entries
+constexpr int ARN_THREADS = 256;
+
+// One Arnoldi column, run by one block (the reductions it needs are done by k_reduce_partials).
+//
+// stage 0: after the first Gram-Schmidt pass, decide whether a second pass runs (reorth 2:
+// always; 1: when the norm fell below 1/sqrt2 of its value; 0: never) and store h into H[:, j].
 // stage 1: add the second pass, form H[j+1, j], apply the previous Givens rotations and a new
 // one, update the residual vector g, and write the estimate |g[j+1]| and 1/H[j+1, j].
-// st layout: [0..m] h pass 1 | [m+1] |w|^2 | [m+2] |w1|^2 | [m+4..2m+4] h pass 2
-__global__ void k_arnoldi(int stage, int j, int m, double* __restrict__ st, double* __restrict__ H,
-                          double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
-                          double* __restrict__ est, double* __restrict__ inv, int* __restrict__ flags, int reorth,
-                          double* __restrict__ est_out, int* __restrict__ flags_out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double* Hj = H + (size_t)j * (m + 1);
-    const double* h1 = st;
-    const double* h2 = st + m + 4;
-    if (stage == 0) {
-        for (int i = 0; i <= j; ++i) Hj[i] = h1[i];
-        flags[0] = (reorth == 2 || (reorth == 1 && st[j + 2] < 0.5 * st[j + 1])) ? 1 : 0;
-        st[m + 3] = st[j + 1];   // |w|^2 before orthogonalisation
+//
+// fused (one pass only): the update also normalises.  Stage 0 then estimates the norm of
+// w - V h as sqrt(|w|^2 - |h|^2) (orthonormal V) and stores the factor a = 1/estimate in
+// st[2m+5] (a = 1 when the difference has lost more than five digits to cancellation).  The
+// update writes a (w - V h) and its squared norm nu2 into st[j+2].  Stage 1 takes
+// H[j+1, j] = 1/a, the exact factor of the stored vector; when nu2 is not 1 within renorm_tol (or
+// on breakdown) it sets flags[3] and inv[j+1] = 1/sqrt(nu2), and the caller's rescale pass, which
+// runs only under that flag, makes the stored vector unit-norm with H[j+1, j] = sqrt(nu2)/a.
+// st layout: [0..m] h pass 1 | [m+1] |w|^2 | [m+2] |w1|^2 | [m+4..2m+4] h pass 2 | [2m+5] a
+__device__ __forceinline__ void arnoldi_block(const ArnoldiArgs t) {
+    __shared__ double red[ARN_MAXROW];
+    __shared__ double hl[ARN_MAXROW], csl[ARN_MAXROW], snl[ARN_MAXROW];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int j = t.j, m = t.m;
+    double* Hj = t.H + (size_t)j * (m + 1);
+    if (t.stage == 0)   // h, |w|^2 (and |w1|^2 after a separate update) into LDS
+        for (int i = tid; i <= j + 2; i += nt) red[i] = t.st[i];
+    if (t.stage == 1) {   // the column and the rotations, loaded in parallel
+        for (int i = tid; i <= j; i += nt) hl[i] = Hj[i];
+        for (int i = tid; i < j; i += nt) {
+            csl[i] = t.cs[i];
+            snl[i] = t.sn[i];
+        }
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    // thread 0: the scalar bookkeeping, from registers and LDS (no reads of its own global writes)
+    double* st = t.st;
+    int* flags = t.flags;
+    if (t.stage == 0) {
+        // red holds h[0..j] and |w|^2 (and |w1|^2 when the update ran first)
+        const double w0 = red[j + 1];
+        double hh = 0.0;
+        for (int i = 0; i <= j; ++i) {
+            const double hi = red[i];
+            Hj[i] = hi;
+            hh += hi * hi;
+        }
+        flags[0] = (t.reorth == 2 || (t.reorth == 1 && red[j + 2] < 0.5 * w0)) ? 1 : 0;
+        st[m + 3] = w0;   // |w|^2 before orthogonalisation
+        if (t.fused) {
+            const double d = w0 - hh;
+            st[2 * m + 5] = (w0 > 0.0 && d > 1e-5 * w0) ? 1.0 / sqrt(d) : 1.0;
+        }
         return;
     }
-    if (flags[0])
-        for (int i = 0; i <= j; ++i) Hj[i] += h2[i];
+    const int second = flags[0];
+    const int prev_nonfinite = flags[2];
     const double w0 = st[m + 3];
-    const double w1 = st[j + 2] > 0.0 ? st[j + 2] : 0.0;
-    const double hn = sqrt(w1);
-    Hj[j + 1] = hn;
-    for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * Hj[i] + sn[i] * Hj[i + 1];
-        Hj[i + 1] = -sn[i] * Hj[i] + cs[i] * Hj[i + 1];
-        Hj[i] = t;
+    const double w1r = st[j + 2];
+    const double a = t.fused ? st[2 * m + 5] : 1.0;
+    const double gj = t.g[j];
+    if (second) {
+        const double* h2 = st + m + 4;
+        for (int i = 0; i <= j; ++i) hl[i] += h2[i];
     }
-    const double den = hypot(Hj[j], Hj[j + 1]);
-    if (den == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
-    else { cs[j] = Hj[j] / den; sn[j] = Hj[j + 1] / den; }
-    Hj[j] = den;
-    Hj[j + 1] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
-    est[j] = fabs(g[j + 1]);
+    const double w1 = w1r > 0.0 ? w1r : 0.0;
+    double hn, hval;
+    bool renorm = false;
+    if (t.fused) {
+        hn = sqrt(w1) / a;                      // norm of w - V h
+        renorm = !(fabs(w1 - 1.0) <= t.renorm_tol);
+        hval = renorm ? hn : 1.0 / a;
+    } else {
+        hn = sqrt(w1);
+        hval = hn;
+    }
+    hl[j + 1] = hval;
+    for (int i = 0; i < j; ++i) {
+        const double x = csl[i] * hl[i] + snl[i] * hl[i + 1];
+        hl[i + 1] = -snl[i] * hl[i] + csl[i] * hl[i + 1];
+        hl[i] = x;
+    }
+    const double den = hypot(hl[j], hl[j + 1]);
+    double cj, sj;
+    if (den == 0.0) { cj = 1.0; sj = 0.0; }
+    else { cj = hl[j] / den; sj = hl[j + 1] / den; }
+    t.cs[j] = cj;
+    t.sn[j] = sj;
+    hl[j] = den;
+    hl[j + 1] = 0.0;
+    for (int i = 0; i <= j + 1; ++i) Hj[i] = hl[i];
+    const double gn = -sj * gj;
+    t.g[j + 1] = gn;
+    t.g[j] = cj * gj;
+    const double ej = fabs(gn);
+    t.est[j] = ej;
     const bool breakdown = !(hn > 1e-14 * sqrt(w0 > 0.0 ? w0 : 0.0));
-    inv[j + 1] = breakdown ? 0.0 : 1.0 / hn;
+    const bool nonfinite = !isfinite(den) || !isfinite(ej);
+    // factor that makes the stored vector unit-norm (fused: relative to the scaled vector)
+    t.inv[j + 1] = breakdown ? 0.0 : (t.fused ? 1.0 / sqrt(w1) : 1.0 / hn);
     flags[1] = breakdown ? 1 : 0;
-    if (!isfinite(den) || !isfinite(est[j])) flags[2] = 1;
-    if (est_out) *est_out = est[j];
-    if (flags_out) {
-        flags_out[0] = flags[1];
-        flags_out[1] = flags[2];
+    flags[3] = (breakdown || renorm) ? 1 : 0;
+    if (nonfinite) flags[2] = 1;
+    if (t.est_out) *t.est_out = ej;
+    if (t.flags_out) {
+        t.flags_out[0] = breakdown ? 1 : 0;
+        t.flags_out[1] = (nonfinite || prev_nonfinite) ? 1 : 0;
     }
 }
+
+__global__ __launch_bounds__(ARN_THREADS) void k_arnoldi(ArnoldiArgs t) { arnoldi_block(t); }
 
 // dst[i] = a * src[i]
 __global__ __launch_bounds__(KT) void k_scale(double* __restrict__ dst, const double* __restrict__ src, double a,
@@ -245,31 +378,48 @@ static inline unsigned grid_for(size_t n, unsigned cap) {
     return (unsigned)(g < cap ? (g ? g : 1) : cap);
 }
 
+unsigned krylov_nblk(size_t n) { return grid_for(n, RTE_KRYLOV_NBLK); }
+
 void krylov_dots(const double* V, size_t ld, int nvec, const double* w, size_t n, double* partial,
                  double* out, bool with_norm, hipStream_t st, const int* active) {
     const unsigned nblk = grid_for(n, RTE_KRYLOV_NBLK);
-    dim3 grid(nblk, (nvec + VB - 1) / VB);
-    if (nvec == 0) grid.y = 1;
-    hipLaunchKernelGGL(k_dot_partial, grid, dim3(KT), 0, st, V, ld, nvec, w, n, partial, with_norm ? 1 : 0, active);
+    const bool pairs = n % 2 == 0 && ld % 2 == 0 && ((uintptr_t)V % 16) == 0 && ((uintptr_t)w % 16) == 0;
+    // groups of up to VB basis vectors; the first group also sums w^2 (into row nvec of partial)
+    for (int v0 = 0; v0 < nvec || (v0 == 0 && with_norm); v0 += VB) {
+        const int nv = std::min(VB, nvec - v0);
+        double* np = (with_norm && v0 == 0) ? partial + (size_t)nvec * nblk : nullptr;
+        if (pairs) launch_dots<true>(nv, nblk, st, V + (size_t)v0 * ld, ld, w, n, partial + (size_t)v0 * nblk, np, active);
+        else launch_dots<false>(nv, nblk, st, V + (size_t)v0 * ld, ld, w, n, partial + (size_t)v0 * nblk, np, active);
+    }
     const int nout = nvec + (with_norm ? 1 : 0);
-    if (nout > 0) hipLaunchKernelGGL(k_reduce_partials, dim3(nout), dim3(KT), 0, st, partial, (int)nblk, out, active);
+    if (out && nout > 0)
+        hipLaunchKernelGGL(k_reduce_partials, dim3(nout), dim3(KT), 0, st, partial, (int)nblk, out, active);
 }
 
 void krylov_update(double* w, const double* V, size_t ld, int nvec, const double* h, size_t n, double* partial,
-                   double* norm_out, hipStream_t st, const int* active) {
+                   double* norm_out, hipStream_t st, const int* active, const double* scale) {
     const unsigned nblk = grid_for(n, RTE_KRYLOV_NBLK);
-    hipLaunchKernelGGL(k_cgs_update, dim3(nblk), dim3(KT), 0, st, w, V, ld, nvec, h, n, partial, active);
-    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(KT), 0, st, partial, (int)nblk, norm_out, active);
+    const bool pairs = n % 2 == 0 && ld % 2 == 0 && ((uintptr_t)V % 16) == 0 && ((uintptr_t)w % 16) == 0;
+    if (pairs)
+        hipLaunchKernelGGL(k_cgs_update<true>, dim3(nblk), dim3(KT), 0, st, w, V, ld, nvec, h, n, partial, active,
+                           scale);
+    else
+        hipLaunchKernelGGL(k_cgs_update<false>, dim3(nblk), dim3(KT), 0, st, w, V, ld, nvec, h, n, partial, active,
+                           scale);
+    if (norm_out) hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(KT), 0, st, partial, (int)nblk, norm_out, active);
 }
 
-void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_scale_dev, dim3(grid_for(n, 4096)), dim3(KT), 0, st, dst, src, a, n);
+void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hipStream_t st, const int* active) {
+    // a flag-gated launch usually finds nothing to do, so it takes a small grid
+    hipLaunchKernelGGL(k_scale_dev, dim3(grid_for(n, active ? 512 : 4096)), dim3(KT), 0, st, dst, src, a, n, active);
 }
 
-void arnoldi_step(int stage, int j, int m, double* st, double* H, double* cs, double* sn, double* g, double* est,
-                  double* inv, int* flags, int reorth, hipStream_t s, double* est_out, int* flags_out) {
-    hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(64), 0, s, stage, j, m, st, H, cs, sn, g, est, inv, flags, reorth,
-                       est_out, flags_out);
+void reduce_partials(const double* partial, int nblk, double* out, int nout, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nout), dim3(KT), 0, st, partial, nblk, out, nullptr);
+}
+
+void arnoldi_run(const ArnoldiArgs& t, hipStream_t s) {
+    hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(ARN_THREADS), 0, s, t);
 }
 
 void krylov_combine(double* x, const double* Z, size_t ld, int nvec, const double* y, size_t n, hipStream_t st) {

@@ -11,7 +11,14 @@ void pc_free(rte_ctx* c);
 // coarse network output y_j (slot j), with s = 1 / sqrt(nvec) for the unit-norm v_j.
 size_t pc_coarse_len(const rte_ctx* c);
 int pc_begin_solve(rte_ctx* c, int m);                 // slots for m columns, s in c->pc_st
-void pc_scale_pool(rte_ctx* c, const double* w, double* v, const double* a_dev, double a_host);  // v = a w + pool
+// v = a w + pool (nothing when active is given and *active == 0)
+void pc_scale_pool(rte_ctx* c, const double* w, double* v, const double* a_dev, double a_host,
+                   const int* active = nullptr);
+// w = (*scale) (w - sum_{v < nvec} h[v] V_v) + pool; *norm_out = <w, w> (partial: one double per
+// block, pc_update_pool_blocks(c) of them; with norm_out NULL only those are written)
+void pc_update_pool(rte_ctx* c, double* w, const double* V, int nvec, const double* h, const double* scale,
+                    double* partial, double* norm_out);
+int pc_update_pool_blocks(const rte_ctx* c);
 int pc_net_slot(rte_ctx* c, int j);                    // Y_j = N(pooled v_j / s)
 const float* pc_slot(const rte_ctx* c, int j);
 void pc_add_correction(rte_ctx* c, double* x, const double* y_dev, int k);  // x += s P sum y_j Y_j

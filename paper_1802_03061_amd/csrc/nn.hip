@@ -483,41 +483,11 @@ __global__ __launch_bounds__(256) void k_prolong_add(const double* __restrict__ 
     z[i] = v[i] + s * (double)((1.f - ay) * top + ay * bot);
 }
 
-// v = a w (a = *a_dev, or a_host when a_dev is NULL; in place allowed) and the F x F block means of
-// v into coarse[c][I][J] (FP32).  One block per (channel, coarse row I, chunk of CW = max(F, 64)
-// columns); 256 threads = CW columns x (256 / CW) row groups, so a block owns its coarse cells.
-__global__ __launch_bounds__(256) void k_scale_pool(const double* __restrict__ w, double* __restrict__ v,
-                                                    const double* __restrict__ a_dev, double a_host,
-                                                    float* __restrict__ coarse, int ny, int nx, int F) {
-    __shared__ double part[256];
-    const int CW = F > 64 ? F : 64;
-    const int RG = 256 / CW;                       // row groups
-    const int nchunk = (nx + CW - 1) / CW;
-    const int Hc = ny / F, Wc = nx / F;
-    const int chunk = blockIdx.x % nchunk;
-    const int I = (blockIdx.x / nchunk) % Hc;
-    const int c = blockIdx.x / (nchunk * Hc);
-    const double a = a_dev ? *a_dev : a_host;
-    const int col = threadIdx.x % CW, rg = threadIdx.x / CW;
-    const int x = chunk * CW + col;
-    const int rows = (F + RG - 1) / RG;
-    double s = 0.0;
-    if (x < nx) {
-#pragma unroll 8
-        for (int u = 0; u < rows; ++u) {
-            const int r = rg * rows + u;
-            if (r < F) {
-                const size_t o = ((size_t)c * ny + I * F + r) * nx + x;
-                const double val = a * w[o];
-                v[o] = val;
-                s += val;
-            }
-        }
-    }
-    part[threadIdx.x] = s;
-    __syncthreads();
-    // coarse cells of this chunk: J = chunk * CW / F + q, q < CW / F; one wave per cell sums its
-    // RG x F column partials (fixed order: strided lanes, then a shuffle reduction)
+// Block means of one block's columns into coarse[c][I][J]: part[] holds each thread's column sum
+// over its rows (CW columns x RG row groups).  One wave per coarse cell sums its RG x F column
+// partials in a fixed order (strided lanes, then a shuffle reduction).
+__device__ __forceinline__ void pool_block_cells(const double* part, int CW, int RG, int F, int chunk, int c, int I,
+                                                 int Hc, int Wc, float* __restrict__ coarse) {
     const int ncell = CW / F;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int q = wave; q < ncell; q += 4) {
@@ -527,6 +497,129 @@ __global__ __launch_bounds__(256) void k_scale_pool(const double* __restrict__ w
         for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
         if (lane == 0 && J < Wc) coarse[((size_t)c * Hc + I) * Wc + J] = (float)(t / ((double)F * F));
     }
+}
+
+// v = a w (a = *a_dev, or a_host when a_dev is NULL; in place allowed) and the F x F block means of
+// v into coarse[c][I][J] (FP32).  Work unit: (channel, coarse row I, chunk of CW = max(F, 64)
+// columns), so that a unit owns its coarse cells; 256 threads = CW columns x (256 / CW) row groups.
+// The grid strides over the units.  Nothing when active is given and *active == 0.
+__global__ __launch_bounds__(256) void k_scale_pool(const double* __restrict__ w, double* __restrict__ v,
+                                                    const double* __restrict__ a_dev, double a_host,
+                                                    float* __restrict__ coarse, int C, int ny, int nx, int F,
+                                                    const int* __restrict__ active) {
+    __shared__ double part[256];
+    if (active && *active == 0) return;
+    const int CW = F > 64 ? F : 64;
+    const int RG = 256 / CW;                       // row groups
+    const int nchunk = (nx + CW - 1) / CW;
+    const int Hc = ny / F, Wc = nx / F;
+    const int nunit = C * Hc * nchunk;
+    const double a = a_dev ? *a_dev : a_host;
+    const int col = threadIdx.x % CW, rg = threadIdx.x / CW;
+    const int rows = (F + RG - 1) / RG;
+    for (int unit = blockIdx.x; unit < nunit; unit += gridDim.x) {
+        const int chunk = unit % nchunk;
+        const int I = (unit / nchunk) % Hc;
+        const int c = unit / (nchunk * Hc);
+        const int x = chunk * CW + col;
+        double s = 0.0;
+        if (x < nx) {
+#pragma unroll 8
+            for (int u = 0; u < rows; ++u) {
+                const int r = rg * rows + u;
+                if (r < F) {
+                    const size_t o = ((size_t)c * ny + I * F + r) * nx + x;
+                    const double val = a * w[o];
+                    v[o] = val;
+                    s += val;
+                }
+            }
+        }
+        part[threadIdx.x] = s;
+        __syncthreads();
+        pool_block_cells(part, CW, RG, F, chunk, c, I, Hc, Wc, coarse);
+        __syncthreads();   // part is reused by the next unit
+    }
+}
+
+// The single Gram-Schmidt pass of the preconditioned Arnoldi step with its normalisation and the
+// network's restriction fused: w = a (w - sum_v V[v] h[v]) (a = *scale), the F x F block means of
+// the new w into coarse (as k_scale_pool), and partial_norm[blk] = sum of the new w^2 over the
+// block.  Same work units as k_scale_pool, one per block (every fine cell of the grid [C][ny][nx]
+// with ny, nx multiples of F belongs to exactly one block).  PAIRS (even nx and ld, 16-byte
+// aligned w and V): each thread takes two adjacent columns as 16-byte loads, so a row group is
+// CW / 2 threads and the block covers twice the rows per step.
+template <bool PAIRS>
+__global__ __launch_bounds__(256) void k_update_pool(double* __restrict__ w, const double* __restrict__ V, size_t ld,
+                                                     int nvec, const double* __restrict__ h,
+                                                     const double* __restrict__ scale, float* __restrict__ coarse,
+                                                     double* __restrict__ partial_norm, int ny, int nx, int F) {
+    __shared__ double part[512];
+    __shared__ double hs[256];
+    __shared__ double nsh[4];
+    const int CW = F > 64 ? F : 64;
+    constexpr int PW = PAIRS ? 2 : 1;              // columns per thread
+    const int TPR = CW / PW;                       // threads per row group
+    const int RG = 256 / TPR;                      // row groups
+    const int nchunk = (nx + CW - 1) / CW;
+    const int Hc = ny / F, Wc = nx / F;
+    const int chunk = blockIdx.x % nchunk;
+    const int I = (blockIdx.x / nchunk) % Hc;
+    const int c = blockIdx.x / (nchunk * Hc);
+    for (int v = threadIdx.x; v < nvec; v += 256) hs[v] = h[v];
+    const double a = *scale;
+    __syncthreads();
+    const int col = (threadIdx.x % TPR) * PW, rg = threadIdx.x / TPR;
+    const int x = chunk * CW + col;
+    const int rows = (F + RG - 1) / RG;
+    const int nr = rg < RG ? min(rows, F - rg * rows) : 0;   // rows of this thread's group in the cell
+    double s0 = 0.0, s1 = 0.0, q = 0.0;
+    if (x < nx) {
+        const size_t o0 = ((size_t)c * ny + I * F + rg * rows) * nx + x;
+        if constexpr (PAIRS) {
+            double2* w2 = reinterpret_cast<double2*>(w);
+            const double2* V2 = reinterpret_cast<const double2*>(V);
+            const size_t ldp = ld / 2;
+#pragma unroll 2
+            for (int u = 0; u < nr; ++u) {
+                const size_t op = (o0 + (size_t)u * nx) / 2;
+                double2 t = w2[op];
+#pragma unroll 8
+                for (int v = 0; v < nvec; ++v) {
+                    const double2 b = V2[(size_t)v * ldp + op];
+                    t.x -= b.x * hs[v];
+                    t.y -= b.y * hs[v];
+                }
+                t.x *= a;
+                t.y *= a;
+                w2[op] = t;
+                s0 += t.x;
+                s1 += t.y;
+                q += t.x * t.x + t.y * t.y;
+            }
+        } else {
+#pragma unroll 2
+            for (int u = 0; u < nr; ++u) {
+                const size_t o = o0 + (size_t)u * nx;
+                double t = w[o];
+#pragma unroll 8
+                for (int v = 0; v < nvec; ++v) t -= V[(size_t)v * ld + o] * hs[v];
+                t *= a;
+                w[o] = t;
+                s0 += t;
+                q += t * t;
+            }
+        }
+    }
+    // part[rg * CW + column] = this thread's column sums (= part[PW * threadIdx.x + k])
+    part[PW * threadIdx.x] = s0;
+    if (PAIRS) part[PW * threadIdx.x + 1] = s1;
+    // block sum of q: waves, then thread 0 in a fixed order
+    for (int off = 32; off > 0; off >>= 1) q += __shfl_xor(q, off, 64);
+    if ((threadIdx.x & 63) == 0) nsh[threadIdx.x >> 6] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) partial_norm[blockIdx.x] = (nsh[0] + nsh[1]) + (nsh[2] + nsh[3]);
+    pool_block_cells(part, CW, RG, F, chunk, c, I, Hc, Wc, coarse);
 }
 
 // out[i] = sum_{j < k} y_j Y[j][i] over one coarse vector of n entries (y FP64 on the device).
@@ -766,12 +859,34 @@ int pc_begin_solve(rte_ctx* c, int m) {
     return e == hipSuccess ? RTE_OK : set_hip_error(e, "pc_begin_solve", __FILE__, __LINE__);
 }
 
-void pc_scale_pool(rte_ctx* c, const double* w, double* v, const double* a_dev, double a_host) {
+void pc_scale_pool(rte_ctx* c, const double* w, double* v, const double* a_dev, double a_host, const int* active) {
     const int F = c->pc_factor;
     const int CW = F > 64 ? F : 64;
     const int nchunk = (c->nx + CW - 1) / CW;
-    hipLaunchKernelGGL(k_scale_pool, dim3(c->C * (c->ny / F) * nchunk), dim3(256), 0, c->stream, w, v, a_dev, a_host,
-                       c->pc_coarse, c->ny, c->nx, F);
+    // a flag-gated launch usually finds nothing to do, so it takes a small grid
+    const int nunit = c->C * (c->ny / F) * nchunk;
+    const int grid = active ? std::min(nunit, 512) : nunit;
+    hipLaunchKernelGGL(k_scale_pool, dim3(grid), dim3(256), 0, c->stream, w, v, a_dev, a_host, c->pc_coarse, c->C,
+                       c->ny, c->nx, F, active);
+}
+
+int pc_update_pool_blocks(const rte_ctx* c) {
+    const int F = c->pc_factor;
+    const int CW = F > 64 ? F : 64;
+    return c->C * (c->ny / F) * ((c->nx + CW - 1) / CW);
+}
+
+void pc_update_pool(rte_ctx* c, double* w, const double* V, int nvec, const double* h, const double* scale,
+                    double* partial, double* norm_out) {
+    const int nblk = pc_update_pool_blocks(c);
+    const bool pairs = c->nx % 2 == 0 && c->nvec % 2 == 0 && ((uintptr_t)w % 16) == 0 && ((uintptr_t)V % 16) == 0;
+    if (pairs)
+        hipLaunchKernelGGL(k_update_pool<true>, dim3(nblk), dim3(256), 0, c->stream, w, V, c->nvec, nvec, h, scale,
+                           c->pc_coarse, partial, c->ny, c->nx, c->pc_factor);
+    else
+        hipLaunchKernelGGL(k_update_pool<false>, dim3(nblk), dim3(256), 0, c->stream, w, V, c->nvec, nvec, h, scale,
+                           c->pc_coarse, partial, c->ny, c->nx, c->pc_factor);
+    if (norm_out) reduce_partials(partial, nblk, norm_out, 1, c->stream);
 }
 
 int pc_net_slot(rte_ctx* c, int j) { return pc_net(c, c->pc_Y + (size_t)j * pc_coarse_len(c)); }

@@ -378,6 +378,10 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
     double est = bn;
     std::vector<double> H((size_t)(m + 1) * m), g(m + 1), yv;
     bool pc_live = use_pc;
+    // single-pass Gram-Schmidt with the normalisation (and the network's restriction) fused into the
+    // update; the preconditioned form needs one partial sum per pooling block in c->partial
+    const bool fused = c->opts.reorth == 0 &&
+                       (!use_pc || (size_t)pc_update_pool_blocks(c) <= (size_t)(m + 3) * RTE_KRYLOV_NBLK);
 
     double* dH = c->arn;
     double* dcs = dH + (size_t)(m + 1) * m;
@@ -420,17 +424,53 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
             }
             ++inf.applies;
             double* sd = c->dsmall;
-            krylov_dots(c->V, n, j + 1, w, n, c->partial, sd, true, st);
-            krylov_update(w, c->V, n, j + 1, sd, n, c->partial, sd + j + 2, st);
-            arnoldi_step(0, j, m, sd, dH, dcs, dsn, dg, dest, dinv, dfl, c->opts.reorth, st);
-            if (c->opts.reorth > 0) {   // second pass, skipped on the device unless flagged
-                krylov_dots(c->V, n, j + 1, w, n, c->partial, sd + m + 4, false, st, dfl);
-                krylov_update(w, c->V, n, j + 1, sd + m + 4, n, c->partial, sd + j + 2, st, dfl);
+            // Arnoldi column j on the device (stage 0 after the dots, stage 1 after the update)
+            ArnoldiArgs at;
+            at.j = j;
+            at.m = m;
+            at.reorth = c->opts.reorth;
+            at.fused = fused ? 1 : 0;
+            at.renorm_tol = mixed ? 1e-8 : 1e-10;
+            at.st = sd;
+            at.H = dH;
+            at.cs = dcs;
+            at.sn = dsn;
+            at.g = dg;
+            at.est = dest;
+            at.inv = dinv;
+            at.flags = dfl;
+            if (fused) {
+                // one pass: the update writes the normalised vector (factor from |w|^2 - |h|^2, stored
+                // by stage 0) and, when preconditioning, the network's pooled input; the rescale
+                // pass runs only when the device flags the norm as off
+                krylov_dots(c->V, n, j + 1, w, n, c->partial, sd, true, st);
+                at.stage = 0;
+                arnoldi_run(at, st);
+                const double* a = sd + 2 * m + 5;
+                if (pc_live) pc_update_pool(c, w, c->V, j + 1, sd, a, c->partial, sd + j + 2);
+                else krylov_update(w, c->V, n, j + 1, sd, n, c->partial, sd + j + 2, st, nullptr, a);
+                at.stage = 1;
+                at.est_out = c->hpipe_dev + j;
+                at.flags_out = c->hpipe_flags_dev + 2 * j;
+                arnoldi_run(at, st);
+                if (pc_live) pc_scale_pool(c, w, w, dinv + j + 1, 0.0, dfl + 3);
+                else vec_scale_dev(w, w, dinv + j + 1, n, st, dfl + 3);
+            } else {
+                krylov_dots(c->V, n, j + 1, w, n, c->partial, sd, true, st);
+                krylov_update(w, c->V, n, j + 1, sd, n, c->partial, sd + j + 2, st);
+                at.stage = 0;
+                arnoldi_run(at, st);
+                if (c->opts.reorth > 0) {   // second pass, skipped on the device unless flagged
+                    krylov_dots(c->V, n, j + 1, w, n, c->partial, sd + m + 4, false, st, dfl);
+                    krylov_update(w, c->V, n, j + 1, sd + m + 4, n, c->partial, sd + j + 2, st, dfl);
+                }
+                at.stage = 1;
+                at.est_out = c->hpipe_dev + j;
+                at.flags_out = c->hpipe_flags_dev + 2 * j;
+                arnoldi_run(at, st);
+                if (pc_live) pc_scale_pool(c, w, w, dinv + j + 1, 0.0);
+                else vec_scale_dev(w, w, dinv + j + 1, n, st);
             }
-            arnoldi_step(1, j, m, sd, dH, dcs, dsn, dg, dest, dinv, dfl, c->opts.reorth, st, c->hpipe_dev + j,
-                         c->hpipe_flags_dev + 2 * j);
-            if (pc_live) pc_scale_pool(c, w, w, dinv + j + 1, 0.0);
-            else vec_scale_dev(w, w, dinv + j + 1, n, st);
             RTE_HIP_TRY(hipEventRecord(c->ev_iter[j], st));
             ++launched;
             // check the previous iteration

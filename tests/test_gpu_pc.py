@@ -307,3 +307,66 @@ def test_learned_pc_diffusion_full_size(rte):
     assert rr <= 1.5e-8
     ctx.close()
     net.close()
+
+
+def _oracle_fgmres_iterates(matvec, precond, b, k):
+    """The first k iterates of flexible GMRES from x0 = 0 (right preconditioning z_j = precond(v_j),
+    modified Gram-Schmidt, x_i = Z_i y_i with y_i the least-squares solution of the Hessenberg
+    system), written out from the definition."""
+    beta = np.linalg.norm(b)
+    V, Z = [b / beta], []
+    H = np.zeros((k + 1, k))
+    xs = []
+    for j in range(k):
+        z = precond(V[j])
+        Z.append(z)
+        w = matvec(z)
+        for i in range(j + 1):
+            H[i, j] = np.vdot(V[i], w).real
+            w = w - H[i, j] * V[i]
+        H[j + 1, j] = np.linalg.norm(w)
+        V.append(w / H[j + 1, j])
+        e1 = np.zeros(j + 2)
+        e1[0] = beta
+        y = np.linalg.lstsq(H[:j + 2, :j + 1], e1, rcond=None)[0]
+        xs.append(sum(y[i] * Z[i] for i in range(j + 1)))
+    return xs
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_fgmres_iterates_match_oracle(rte, prec):
+    """The first flexible-GMRES iterates with the attached network, from the single Gram-Schmidt
+    pass whose update also normalises and restricts v_{j+1} for the network (reorth 0), and from
+    the separate passes (reorth 2): the two agree closely, and both follow the oracle's flexible
+    GMRES with z_j = v_j + s P N(R v_j / s), within the BF16 network's accuracy
+    (32^2, L = 2, F = 4)."""
+    n, L, F, k = 32, 2, 4, 4
+    mu_a, mu_s = 0.1, 4.0
+    h, mu_t = 1.0 / n, mu_a + mu_s
+    sh = inputs.hg_sigma_hat(0.5, L)
+    f = inputs.gaussian_mixture_source(n, inputs.gaussian_mixture_params(np.random.default_rng(11), 2))
+    ctx = rte.Context(n, mu_a=mu_a, mu_s=mu_s, sigma_hat=sh, L=L, prec=prec)
+    net = rte.Net(ctx.channels, 32, 5, seed=5, use_bias=False)
+    w = net.params() * 0.3
+    params = unpack(host(w), ctx.channels, 32, 5)
+    ctx.attach_pc(w, factor=F)
+    b = op2.rhs(f, L, h, mu_t, method="direct")
+    bc = _to_ch(b, L)
+    recs = {}
+    for reorth in (0, 2):
+        ctx.set_opts(reorth=reorth)
+        _, info, rec = ctx.solve_rhs(dev(bc), tol=1e-11, record=k)
+        say("  reorth", reorth, info)
+        assert info["pc_used"] == 1 and info["pc_fallback"] == 0 and rec.shape[0] == k
+        recs[reorth] = host(rec)
+    spectra = op2.kernel_spectra(n, n, L, h, mu_t)
+    matvec = lambda v: _to_ch(op2.apply_fft(_to_modes(v, L), L, h, mu_t, mu_s, sh, spectra=spectra), L)
+    xs = _oracle_fgmres_iterates(matvec, lambda v: cn.precondition(v, params, F), bc, k)
+    for i in range(k):
+        d_paths = relerr(recs[0][i], recs[2][i])
+        d_oracle = max(relerr(recs[0][i], xs[i]), relerr(recs[2][i], xs[i]))
+        say("  iterate", i + 1, "fused vs separate", d_paths, "vs oracle", d_oracle)
+        assert d_paths <= 1e-4
+        assert d_oracle <= 3e-2
+    ctx.close()
+    net.close()

@@ -167,3 +167,48 @@ def test_solve_bad_tolerance_is_einval(rte):
             ctx.solve(f, tol=tol)
         assert ei.value.code == rte.RTE_EINVAL
     ctx.close()
+
+
+@pytest.mark.parametrize("reorth", [0, 1, 2])
+@pytest.mark.parametrize("prec", [1, 0])
+def test_solve_gram_schmidt_variants_vs_lu(rte, reorth, prec):
+    """One classical Gram-Schmidt pass with the normalisation fused into the update (reorth 0), the
+    adaptive and the forced second pass (1, 2); a short restart length makes every cycle restart
+    several times."""
+    L, ny, nx, mu_s = 3, 14, 11, 8.0
+    say("solve gram-schmidt", reorth, "prec", prec)
+    rng = np.random.default_rng(7)
+    h = 1.0 / max(nx, ny)
+    sh = inputs.hg_sigma_hat(0.7, L)
+    f = rng.random((ny, nx))
+    ctx = rte.Context((nx, ny), h=h, mu_a=0.05, mu_s=mu_s, sigma_hat=sh, L=L, prec=prec)
+    ctx.set_opts(restart=6, max_cycles=60, reorth=reorth)
+    u, info = ctx.solve(dev(f), tol=1e-11)
+    say("  info", info)
+    assert info["cycles"] > 1
+    ref = _lu(f, L, ny, nx, h, 0.05, mu_s, sh)
+    e = relerr(host(u), ref)
+    say("  relerr vs LU", e)
+    assert e <= (1e-10 if prec == 1 else 1e-6)
+    ctx.close()
+
+
+@pytest.mark.parametrize("reorth", [0, 1])
+def test_solve_no_scattering_is_one_step(rte, reorth):
+    """mu_s = 0 makes A the identity: the first Arnoldi column breaks down (w = v_0), and the
+    solution is the right-hand side b = K f, which the KT apply gives directly."""
+    L, n = 2, 16
+    rng = np.random.default_rng(3)
+    f = rng.random((n, n))
+    sh = inputs.hg_sigma_hat(0.5, L)
+    ctx = rte.Context(n, mu_a=1.5, mu_s=0.0, sigma_hat=sh, L=L, prec=rte.PREC_FP64)
+    ctx.set_opts(reorth=reorth)
+    u, info = ctx.solve(dev(f), tol=1e-12)
+    say("  info", info)
+    # one column decides; the host may have queued one more iteration before reading its flags
+    assert info["iterations"] <= 2 and info["cycles"] == 1
+    ref = op2.rhs(f, L, 1.0 / n, 1.5, method="direct")
+    e = relerr(host(u), ref)
+    say("  relerr vs K f", e)
+    assert e <= 1e-12
+    ctx.close()
