@@ -272,14 +272,15 @@ __global__ __launch_bounds__(256) void k_scale_from_partials(const double* __res
     }
 }
 
-// The whole network in one workgroup for a small coarse grid (Hc <= 32 rows, Wc <= 32).
+// The whole network in one workgroup for a small coarse grid (Hc <= 32 rows, Wc <= 32).  The MFMA's 32
+// columns hold whole coarse rows (one row of up to 32 pixels, two of up to 16, ...).
 // Activations stay in LDS as BF16, channel-innermost ([pixel][channel], pixel stride NET_PS shorts,
 // zero halo and zero padded channels), so that for one 3x3 tap the eight consecutive K values a
 // lane feeds to the MFMA are one 16-byte LDS read.  The reduction index is tap-major,
 // k = t * CP + c (CP: input channels rounded up to 8, so a K step never straddles taps).
 // Every layer's weights are loaded into LDS up front (tap-major rows of stride KS, prepacked by
 // k_pack_tapmajor), so the only global reads are that copy, the input and the biases.  One wave per
-// coarse row; the last layer writes FP32 [c][y][x] to global memory.
+// group of coarse rows; the last layer writes FP32 [c][y][x] to global memory.
 constexpr int NET_THREADS = 1024;
 constexpr int NET_PS = 40;                  // pixel stride in shorts: 32 channels + 8 (16-byte aligned, bank spread)
 __host__ __device__ constexpr int net_cp(int c) { return (c + 7) / 8 * 8; }
@@ -306,16 +307,21 @@ __global__ void k_pack_tapmajor(const unsigned short* __restrict__ wf, int cin, 
 // (their outputs are discarded).
 template <int CP>
 __device__ __forceinline__ f32x16 net_row(const unsigned short* __restrict__ Wl, const unsigned short* __restrict__ src,
-                                          int y, int j, int hi, int Wc) {
+                                          int pix, int j, int hi, int Wc) {
     // K steps of 16 on v_mfma_f32_32x32x16_bf16 (lane l holds k = 8 (l / 32) .. +7 of row / column
-    // l % 32), and for CP = 8 (mod 16) one last step of 8 on the 32x32x8 form (k = 4 (l / 32) .. +3)
+    // l % 32), and for CP = 8 (mod 16) one last step of 8 on the 32x32x8 form (k = 4 (l / 32) .. +3).
+    // pix: the halo-grid index of the pixel whose 3x3 neighbourhood starts this lane's column.
+    // Two accumulators take alternate steps, so that two independent MFMA chains are in flight.
     constexpr int KS = net_ks(CP);
-    f32x16 acc;
+    constexpr int NCB = CP / 16 + (CP % 16 != 0 ? 1 : 0);   // MFMA steps per tap
+    f32x16 acc[2];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-    const int jj = j < Wc ? j : Wc - 1;
+    for (int r = 0; r < 16; ++r) {
+        acc[0][r] = 0.f;
+        acc[1][r] = 0.f;
+    }
     const unsigned short* arow = Wl + j * KS;
-    const unsigned short* brow = src + ((size_t)y * (Wc + 2) + jj) * NET_PS;
+    const unsigned short* brow = src + (size_t)pix * NET_PS;
 #pragma unroll 1
     for (int dy = 0; dy < 3; ++dy) {
         const unsigned short* bd = brow + dy * (Wc + 2) * NET_PS;
@@ -328,16 +334,20 @@ __device__ __forceinline__ f32x16 net_row(const unsigned short* __restrict__ Wl,
             for (int cb = 0; cb < CP / 16; ++cb) {
                 const bf16x8 a = *reinterpret_cast<const bf16x8*>(at + cb * 16 + 8 * hi);
                 const bf16x8 bv = *reinterpret_cast<const bf16x8*>(bt + cb * 16 + 8 * hi);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, acc, 0, 0, 0);
+                f32x16& c = acc[(dx * NCB + cb) & 1];
+                c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bv, c, 0, 0, 0);
             }
             if constexpr (CP % 16 != 0) {
                 const bf16x4 a = *reinterpret_cast<const bf16x4*>(at + (CP / 16) * 16 + 4 * hi);
                 const bf16x4 bv = *reinterpret_cast<const bf16x4*>(bt + (CP / 16) * 16 + 4 * hi);
-                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bv, acc, 0, 0, 0);
+                f32x16& c = acc[(dx * NCB + CP / 16) & 1];
+                c = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bv, c, 0, 0, 0);
             }
         }
     }
-    return acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[0][r] += acc[1][r];
+    return acc[0];
 }
 
 template <int HID>
@@ -381,17 +391,25 @@ __global__ __launch_bounds__(NET_THREADS) void k_net_fused(const float* __restri
         }
         if (tid < 4 * layers) smeta[tid] = meta[tid];
         if (tid < nbias) sbias[tid] = bias_all[tid];
+        // the first U * NET_THREADS inputs are loaded now, with the weights still in flight
+        float xin[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = tid + u * NET_THREADS;
+            xin[u] = idx < nin ? in[idx] : 0.f;
+        }
         uint4* az = reinterpret_cast<uint4*>(lds);
         const uint4 zero = {0u, 0u, 0u, 0u};
         for (int idx = tid; idx < 2 * P * NET_PS / 8; idx += NET_THREADS) az[idx] = zero;
         const float sc = *in_scale;
         __syncthreads();   // the zero fill of the activations is complete
         for (int base = 0; base < nin; base += U * NET_THREADS) {
-            float xin[U];
+            if (base > 0) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int idx = base + tid + u * NET_THREADS;
-                xin[u] = idx < nin ? in[idx] : 0.f;
+                for (int u = 0; u < U; ++u) {
+                    const int idx = base + tid + u * NET_THREADS;
+                    xin[u] = idx < nin ? in[idx] : 0.f;
+                }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -405,7 +423,14 @@ __global__ __launch_bounds__(NET_THREADS) void k_net_fused(const float* __restri
         }
     }
     __syncthreads();
+    // The 32 MFMA columns take RPM = 32 / PR coarse rows of PR = (Wc rounded up to a power of two)
+    // pixels each: lane column j is pixel px = j % PR of row y0 + j / PR.  Columns past the grid
+    // read a valid pixel and their outputs are dropped.
     const int j = lane & 31, hi = lane >> 5;
+    int PR = 1;
+    while (PR < Wc) PR <<= 1;
+    const int RPM = 32 / PR;
+    const int px = j % PR, ry = j / PR;
     for (int l = 0; l < layers; ++l) {
         const int cin = smeta[4 * l], cout = smeta[4 * l + 1];
         const unsigned short* Wl = Wall + smeta[4 * l + 2];
@@ -414,21 +439,24 @@ __global__ __launch_bounds__(NET_THREADS) void k_net_fused(const float* __restri
         const int CP = net_cp(cin);
         const unsigned short* src = (l & 1) ? act1 : act0;
         unsigned short* dst = (l & 1) ? act0 : act1;
-        for (int y = wave; y < Hc; y += NET_THREADS / 64) {
+        for (int y0 = wave * RPM; y0 < Hc; y0 += (NET_THREADS / 64) * RPM) {
+            const int y = y0 + ry;
+            const bool valid = px < Wc && y < Hc;
+            const int pin = (y < Hc ? y : Hc - 1) * (Wc + 2) + (px < Wc ? px : Wc - 1);
             f32x16 acc;
-            if (CP == 32) acc = net_row<32>(Wl, src, y, j, hi, Wc);
-            else if (CP == 24) acc = net_row<24>(Wl, src, y, j, hi, Wc);
-            else if (CP == 16) acc = net_row<16>(Wl, src, y, j, hi, Wc);
-            else acc = net_row<8>(Wl, src, y, j, hi, Wc);
-            if (j < Wc) {
-                const int pix = (y + 1) * (Wc + 2) + j + 1;
+            if (CP == 32) acc = net_row<32>(Wl, src, pin, j, hi, Wc);
+            else if (CP == 24) acc = net_row<24>(Wl, src, pin, j, hi, Wc);
+            else if (CP == 16) acc = net_row<16>(Wl, src, pin, j, hi, Wc);
+            else acc = net_row<8>(Wl, src, pin, j, hi, Wc);
+            if (valid) {
+                const int pix = (y + 1) * (Wc + 2) + px + 1;
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
                     const int i0 = 8 * g + 4 * hi;
                     if (last) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r)
-                            if (i0 + r < cout) out[((size_t)(i0 + r) * Hc + y) * Wc + j] = acc[4 * g + r] + bias[i0 + r];
+                            if (i0 + r < cout) out[((size_t)(i0 + r) * Hc + y) * Wc + px] = acc[4 * g + r] + bias[i0 + r];
                     } else if (i0 < cout) {
                         bf16x4 o;
 #pragma unroll
