@@ -121,6 +121,16 @@ def apply_pass_bytes(n: int, L: int) -> dict:
     return {"A": 8 * C * N + spec, "B": 2 * spec + kern, "C": spec + 16 * C * N}
 
 
+def model_3pass_bytes(n: int, L: int) -> int:
+    """Bytes of the 3-pass model of one FP32 2D apply on complex mode vectors, the reference
+    denominator for the apply's HBM fraction: M = 2L+1 modes, N = n^2 cells, P = 4N padded cells;
+    pass A 8MN -> 16MN, pass B 16MN plus the 2L+1 kernel spectra (8P each) -> 16MN, pass C 16MN
+    plus 8MN -> 8MN, i.e. 88MN + 8(2L+1)P.  This design's own algorithmic bytes (apply_pass_bytes)
+    are lower: real-to-complex x transforms and quarter-stored spectra."""
+    M, N = 2 * L + 1, n * n
+    return 88 * M * N + 8 * (2 * L + 1) * 4 * N
+
+
 def apply3d_pass_bytes(n: int) -> dict:
     """Algorithmic HBM bytes of one FP32 3D isotropic apply (n^3 cells, padded P): x-FFT pass
     (read x, write T1 [n][P/2+1][n] complex64), y-FFT pass (T1 -> T2 [P/2+1][P][n]), z pass (read
@@ -273,6 +283,7 @@ def bench_pc_workload(args, torch, rte, name, mu_s):
         "apply_ms": {"fp32_total": rf["ms_apply"], "fp32_passes": rf["passes"], "fp64_total": ms64,
                      "fp64_passes": dict(zip("ABC", pass64[:3]))},
         "apply_hbm_fraction": rf["apply_hbm_fraction"], "apply_bytes": apply_pass_bytes(n, L),
+        "apply_hbm_fraction_3pass_model": model_3pass_bytes(n, L) / (rf["ms_apply"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "kernel_variants": variants,
         "roofline": rf["roofline"],
         "roofline_alu_pass_B": {"bound": "alu", "achieved": ach, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -6,6 +6,7 @@
 // a second kernel adds the partials in a fixed order, so repeated runs give bitwise equal sums.
 #include <algorithm>
 
+#include "arnoldi_dev.h"
 #include "krylov.h"
 
 namespace rte {
@@ -125,17 +126,26 @@ __global__ __launch_bounds__(KT) void k_reduce_partials(const double* __restrict
 
 // w[i] = a (w[i] - sum_v V[v][i] h[v]) with a = *scale (1 when scale is NULL); partial_norm[blk] =
 // sum over the slice of the new w[i]^2.  PAIRS: as in k_dot_partial, element pairs as 16-byte loads.
+// With s0.st set (the fused single pass, h = s0.st) the factor is computed here instead
+// (arnoldi_stage0_in_update), and block 0 also does stage 0 of the Arnoldi column.
 template <bool PAIRS>
 __global__ __launch_bounds__(KT) void k_cgs_update(double* __restrict__ w, const double* __restrict__ V, size_t ld,
                                                    int nvec, const double* __restrict__ h, size_t n,
                                                    double* __restrict__ partial_norm, const int* __restrict__ active,
-                                                   const double* __restrict__ scale) {
+                                                   const double* __restrict__ scale, ArnoldiArgs s0) {
     __shared__ double sh[KT / 64];
     __shared__ double hs[RTE_KRYLOV_MAXVEC];
+    __shared__ double a_sh;
     if (active && *active == 0) return;
     for (int v = threadIdx.x; v < nvec; v += KT) hs[v] = h[v];
-    const double a = scale ? *scale : 1.0;
+    if (s0.st) {
+        __syncthreads();
+        arnoldi_stage0_in_update(s0, hs, &a_sh);
+    } else if (threadIdx.x == 0) {
+        a_sh = scale ? *scale : 1.0;
+    }
     __syncthreads();
+    const double a = a_sh;
     double nrm = 0.0;
     const size_t stride = (size_t)gridDim.x * KT;
     if constexpr (PAIRS) {
@@ -185,6 +195,15 @@ __global__ __launch_bounds__(KT) void k_combine(double* __restrict__ x, const do
     }
 }
 
+// Stage 1 of the fused single pass (block 0: the Arnoldi column's bookkeeping) and, when the
+// stored vector needs it, w *= 1/sqrt(nu2) over the grid.
+__global__ __launch_bounds__(KT) void k_rescale_arn1(ArnoldiArgs t, double* __restrict__ w, size_t n) {
+    const double inv = arnoldi_stage1_in_rescale(t);
+    if (inv < 0.0) return;
+    const size_t stride = (size_t)gridDim.x * KT;
+    for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) w[i] *= inv;
+}
+
 // dst[i] = (*a) * src[i] with the factor read from device memory; nothing when *active == 0
 __global__ __launch_bounds__(KT) void k_scale_dev(double* __restrict__ dst, const double* __restrict__ src,
                                                   const double* __restrict__ a, size_t n, const int* __restrict__ active) {
@@ -194,115 +213,7 @@ __global__ __launch_bounds__(KT) void k_scale_dev(double* __restrict__ dst, cons
     for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) dst[i] = s * src[i];
 }
 
-constexpr int ARN_MAXROW = RTE_KRYLOV_MAXVEC + 2;   // column entries
 constexpr int ARN_THREADS = 256;
-
-// One Arnoldi column, run by one block (the reductions it needs are done by k_reduce_partials).
-//
-// stage 0: after the first Gram-Schmidt pass, decide whether a second pass runs (reorth 2:
-// always; 1: when the norm fell below 1/sqrt2 of its value; 0: never) and store h into H[:, j].
-// stage 1: add the second pass, form H[j+1, j], apply the previous Givens rotations and a new
-// one, update the residual vector g, and write the estimate |g[j+1]| and 1/H[j+1, j].
-//
-// fused (one pass only): the update also normalises.  Stage 0 then estimates the norm of
-// w - V h as sqrt(|w|^2 - |h|^2) (orthonormal V) and stores the factor a = 1/estimate in
-// st[2m+5] (a = 1 when the difference has lost more than five digits to cancellation).  The
-// update writes a (w - V h) and its squared norm nu2 into st[j+2].  Stage 1 takes
-// H[j+1, j] = 1/a, the exact factor of the stored vector; when nu2 is not 1 within renorm_tol (or
-// on breakdown) it sets flags[3] and inv[j+1] = 1/sqrt(nu2), and the caller's rescale pass, which
-// runs only under that flag, makes the stored vector unit-norm with H[j+1, j] = sqrt(nu2)/a.
-// st layout: [0..m] h pass 1 | [m+1] |w|^2 | [m+2] |w1|^2 | [m+4..2m+4] h pass 2 | [2m+5] a
-__device__ __forceinline__ void arnoldi_block(const ArnoldiArgs t) {
-    __shared__ double red[ARN_MAXROW];
-    __shared__ double hl[ARN_MAXROW], csl[ARN_MAXROW], snl[ARN_MAXROW];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int j = t.j, m = t.m;
-    double* Hj = t.H + (size_t)j * (m + 1);
-    if (t.stage == 0)   // h, |w|^2 (and |w1|^2 after a separate update) into LDS
-        for (int i = tid; i <= j + 2; i += nt) red[i] = t.st[i];
-    if (t.stage == 1) {   // the column and the rotations, loaded in parallel
-        for (int i = tid; i <= j; i += nt) hl[i] = Hj[i];
-        for (int i = tid; i < j; i += nt) {
-            csl[i] = t.cs[i];
-            snl[i] = t.sn[i];
-        }
-    }
-    __syncthreads();
-    if (tid != 0) return;
-    // thread 0: the scalar bookkeeping, from registers and LDS (no reads of its own global writes)
-    double* st = t.st;
-    int* flags = t.flags;
-    if (t.stage == 0) {
-        // red holds h[0..j] and |w|^2 (and |w1|^2 when the update ran first)
-        const double w0 = red[j + 1];
-        double hh = 0.0;
-        for (int i = 0; i <= j; ++i) {
-            const double hi = red[i];
-            Hj[i] = hi;
-            hh += hi * hi;
-        }
-        flags[0] = (t.reorth == 2 || (t.reorth == 1 && red[j + 2] < 0.5 * w0)) ? 1 : 0;
-        st[m + 3] = w0;   // |w|^2 before orthogonalisation
-        if (t.fused) {
-            const double d = w0 - hh;
-            st[2 * m + 5] = (w0 > 0.0 && d > 1e-5 * w0) ? 1.0 / sqrt(d) : 1.0;
-        }
-        return;
-    }
-    const int second = flags[0];
-    const int prev_nonfinite = flags[2];
-    const double w0 = st[m + 3];
-    const double w1r = st[j + 2];
-    const double a = t.fused ? st[2 * m + 5] : 1.0;
-    const double gj = t.g[j];
-    if (second) {
-        const double* h2 = st + m + 4;
-        for (int i = 0; i <= j; ++i) hl[i] += h2[i];
-    }
-    const double w1 = w1r > 0.0 ? w1r : 0.0;
-    double hn, hval;
-    bool renorm = false;
-    if (t.fused) {
-        hn = sqrt(w1) / a;                      // norm of w - V h
-        renorm = !(fabs(w1 - 1.0) <= t.renorm_tol);
-        hval = renorm ? hn : 1.0 / a;
-    } else {
-        hn = sqrt(w1);
-        hval = hn;
-    }
-    hl[j + 1] = hval;
-    for (int i = 0; i < j; ++i) {
-        const double x = csl[i] * hl[i] + snl[i] * hl[i + 1];
-        hl[i + 1] = -snl[i] * hl[i] + csl[i] * hl[i + 1];
-        hl[i] = x;
-    }
-    const double den = hypot(hl[j], hl[j + 1]);
-    double cj, sj;
-    if (den == 0.0) { cj = 1.0; sj = 0.0; }
-    else { cj = hl[j] / den; sj = hl[j + 1] / den; }
-    t.cs[j] = cj;
-    t.sn[j] = sj;
-    hl[j] = den;
-    hl[j + 1] = 0.0;
-    for (int i = 0; i <= j + 1; ++i) Hj[i] = hl[i];
-    const double gn = -sj * gj;
-    t.g[j + 1] = gn;
-    t.g[j] = cj * gj;
-    const double ej = fabs(gn);
-    t.est[j] = ej;
-    const bool breakdown = !(hn > 1e-14 * sqrt(w0 > 0.0 ? w0 : 0.0));
-    const bool nonfinite = !isfinite(den) || !isfinite(ej);
-    // factor that makes the stored vector unit-norm (fused: relative to the scaled vector)
-    t.inv[j + 1] = breakdown ? 0.0 : (t.fused ? 1.0 / sqrt(w1) : 1.0 / hn);
-    flags[1] = breakdown ? 1 : 0;
-    flags[3] = (breakdown || renorm) ? 1 : 0;
-    if (nonfinite) flags[2] = 1;
-    if (t.est_out) *t.est_out = ej;
-    if (t.flags_out) {
-        t.flags_out[0] = breakdown ? 1 : 0;
-        t.flags_out[1] = (nonfinite || prev_nonfinite) ? 1 : 0;
-    }
-}
 
 __global__ __launch_bounds__(ARN_THREADS) void k_arnoldi(ArnoldiArgs t) { arnoldi_block(t); }
 
@@ -397,21 +308,29 @@ void krylov_dots(const double* V, size_t ld, int nvec, const double* w, size_t n
 }
 
 void krylov_update(double* w, const double* V, size_t ld, int nvec, const double* h, size_t n, double* partial,
-                   double* norm_out, hipStream_t st, const int* active, const double* scale) {
+                   double* norm_out, hipStream_t st, const int* active, const double* scale,
+                   const ArnoldiArgs* stage0) {
+    const ArnoldiArgs none;
+    const ArnoldiArgs& s0 = stage0 ? *stage0 : none;
     const unsigned nblk = grid_for(n, RTE_KRYLOV_NBLK);
     const bool pairs = n % 2 == 0 && ld % 2 == 0 && ((uintptr_t)V % 16) == 0 && ((uintptr_t)w % 16) == 0;
     if (pairs)
         hipLaunchKernelGGL(k_cgs_update<true>, dim3(nblk), dim3(KT), 0, st, w, V, ld, nvec, h, n, partial, active,
-                           scale);
+                           scale, s0);
     else
         hipLaunchKernelGGL(k_cgs_update<false>, dim3(nblk), dim3(KT), 0, st, w, V, ld, nvec, h, n, partial, active,
-                           scale);
+                           scale, s0);
     if (norm_out) hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(KT), 0, st, partial, (int)nblk, norm_out, active);
 }
 
 void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hipStream_t st, const int* active) {
     // a flag-gated launch usually finds nothing to do, so it takes a small grid
     hipLaunchKernelGGL(k_scale_dev, dim3(grid_for(n, active ? 512 : 4096)), dim3(KT), 0, st, dst, src, a, n, active);
+}
+
+void rescale_arn1(const ArnoldiArgs& t, double* w, size_t n, hipStream_t st) {
+    // usually nothing to rescale, so a small grid
+    hipLaunchKernelGGL(k_rescale_arn1, dim3(grid_for(n, 512)), dim3(KT), 0, st, t, w, n);
 }
 
 void reduce_partials(const double* partial, int nblk, double* out, int nout, hipStream_t st) {

@@ -1,6 +1,7 @@
 // Learned right preconditioner: 3x3 convolution network kernels (see nn.hip).
 #pragma once
 #include "ctx.h"
+#include "krylov.h"
 
 namespace rte {
 // z = v + ||v|| N(v / ||v||) on one channel vector (FP64 in/out, BF16 x BF16 -> FP32 inside).
@@ -17,7 +18,9 @@ void pc_scale_pool(rte_ctx* c, const double* w, double* v, const double* a_dev, 
 // w = (*scale) (w - sum_{v < nvec} h[v] V_v) + pool; *norm_out = <w, w> (partial: one double per
 // block, pc_update_pool_blocks(c) of them; with norm_out NULL only those are written)
 void pc_update_pool(rte_ctx* c, double* w, const double* V, int nvec, const double* h, const double* scale,
-                    double* partial, double* norm_out);
+                    double* partial, double* norm_out, const ArnoldiArgs* stage0 = nullptr);
+// stage 1 of the fused single pass and, when flagged by the device, w's rescale and new block means
+void pc_rescale_pool_arn1(rte_ctx* c, const ArnoldiArgs& t, double* w);
 int pc_update_pool_blocks(const rte_ctx* c);
 int pc_net_slot(rte_ctx* c, int j);                    // Y_j = N(pooled v_j / s)
 const float* pc_slot(const rte_ctx* c, int j);

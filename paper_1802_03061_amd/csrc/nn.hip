@@ -20,6 +20,7 @@
 #include "../../include/rte_nn.h"
 #include "apply2d.h"
 #include "ctx.h"
+#include "arnoldi_dev.h"
 #include "krylov.h"
 #include "nn.h"
 
@@ -527,22 +528,17 @@ __device__ __forceinline__ void pool_block_cells(const double* part, int CW, int
     }
 }
 
-// v = a w (a = *a_dev, or a_host when a_dev is NULL; in place allowed) and the F x F block means of
-// v into coarse[c][I][J] (FP32).  Work unit: (channel, coarse row I, chunk of CW = max(F, 64)
-// columns), so that a unit owns its coarse cells; 256 threads = CW columns x (256 / CW) row groups.
-// The grid strides over the units.  Nothing when active is given and *active == 0.
-__global__ __launch_bounds__(256) void k_scale_pool(const double* __restrict__ w, double* __restrict__ v,
-                                                    const double* __restrict__ a_dev, double a_host,
-                                                    float* __restrict__ coarse, int C, int ny, int nx, int F,
-                                                    const int* __restrict__ active) {
+// v = a w (in place allowed) and the F x F block means of v into coarse[c][I][J] (FP32).  Work
+// unit: (channel, coarse row I, chunk of CW = max(F, 64) columns), so that a unit owns its coarse
+// cells; 256 threads = CW columns x (256 / CW) row groups.  The grid strides over the units.
+__device__ __forceinline__ void scale_pool_units(const double* __restrict__ w, double* __restrict__ v, double a,
+                                                 float* __restrict__ coarse, int C, int ny, int nx, int F) {
     __shared__ double part[256];
-    if (active && *active == 0) return;
     const int CW = F > 64 ? F : 64;
     const int RG = 256 / CW;                       // row groups
     const int nchunk = (nx + CW - 1) / CW;
     const int Hc = ny / F, Wc = nx / F;
     const int nunit = C * Hc * nchunk;
-    const double a = a_dev ? *a_dev : a_host;
     const int col = threadIdx.x % CW, rg = threadIdx.x / CW;
     const int rows = (F + RG - 1) / RG;
     for (int unit = blockIdx.x; unit < nunit; unit += gridDim.x) {
@@ -570,8 +566,28 @@ __global__ __launch_bounds__(256) void k_scale_pool(const double* __restrict__ w
     }
 }
 
+// v = a w and its block means (scale_pool_units), a = *a_dev or a_host when a_dev is NULL; nothing
+// when active is given and *active == 0.
+__global__ __launch_bounds__(256) void k_scale_pool(const double* __restrict__ w, double* __restrict__ v,
+                                                    const double* __restrict__ a_dev, double a_host,
+                                                    float* __restrict__ coarse, int C, int ny, int nx, int F,
+                                                    const int* __restrict__ active) {
+    if (active && *active == 0) return;
+    scale_pool_units(w, v, a_dev ? *a_dev : a_host, coarse, C, ny, nx, F);
+}
+
+// Stage 1 of the fused single pass (block 0: the Arnoldi column's bookkeeping) and, when the
+// stored vector needs it, its rescale with the block means taken again.
+__global__ __launch_bounds__(256) void k_rescale_pool_arn1(ArnoldiArgs t, double* __restrict__ w,
+                                                           float* __restrict__ coarse, int C, int ny, int nx, int F) {
+    const double inv = arnoldi_stage1_in_rescale(t);
+    if (inv < 0.0) return;
+    scale_pool_units(w, w, inv, coarse, C, ny, nx, F);
+}
+
 // The single Gram-Schmidt pass of the preconditioned Arnoldi step with its normalisation and the
-// network's restriction fused: w = a (w - sum_v V[v] h[v]) (a = *scale), the F x F block means of
+// network's restriction fused: w = a (w - sum_v V[v] h[v]) (a = *scale, or with st0.st set computed
+// here by arnoldi_stage0_in_update, h = st0.st, block 0 also running stage 0), the F x F block means of
 // the new w into coarse (as k_scale_pool), and partial_norm[blk] = sum of the new w^2 over the
 // block.  Same work units as k_scale_pool, one per block (every fine cell of the grid [C][ny][nx]
 // with ny, nx multiples of F belongs to exactly one block).  PAIRS (even nx and ld, 16-byte
@@ -581,10 +597,12 @@ template <bool PAIRS>
 __global__ __launch_bounds__(256) void k_update_pool(double* __restrict__ w, const double* __restrict__ V, size_t ld,
                                                      int nvec, const double* __restrict__ h,
                                                      const double* __restrict__ scale, float* __restrict__ coarse,
-                                                     double* __restrict__ partial_norm, int ny, int nx, int F) {
+                                                     double* __restrict__ partial_norm, int ny, int nx, int F,
+                                                     ArnoldiArgs st0) {
     __shared__ double part[512];
     __shared__ double hs[256];
     __shared__ double nsh[4];
+    __shared__ double a_sh;
     const int CW = F > 64 ? F : 64;
     constexpr int PW = PAIRS ? 2 : 1;              // columns per thread
     const int TPR = CW / PW;                       // threads per row group
@@ -595,8 +613,14 @@ __global__ __launch_bounds__(256) void k_update_pool(double* __restrict__ w, con
     const int I = (blockIdx.x / nchunk) % Hc;
     const int c = blockIdx.x / (nchunk * Hc);
     for (int v = threadIdx.x; v < nvec; v += 256) hs[v] = h[v];
-    const double a = *scale;
+    if (st0.st) {   // the fused single pass: the factor and stage 0 of the Arnoldi column here
+        __syncthreads();
+        arnoldi_stage0_in_update(st0, hs, &a_sh);
+    } else if (threadIdx.x == 0) {
+        a_sh = *scale;
+    }
     __syncthreads();
+    const double a = a_sh;
     const int col = (threadIdx.x % TPR) * PW, rg = threadIdx.x / TPR;
     const int x = chunk * CW + col;
     const int rows = (F + RG - 1) / RG;
@@ -898,6 +922,15 @@ void pc_scale_pool(rte_ctx* c, const double* w, double* v, const double* a_dev, 
                        c->ny, c->nx, F, active);
 }
 
+void pc_rescale_pool_arn1(rte_ctx* c, const ArnoldiArgs& t, double* w) {
+    const int F = c->pc_factor;
+    const int CW = F > 64 ? F : 64;
+    const int nunit = c->C * (c->ny / F) * ((c->nx + CW - 1) / CW);
+    // usually nothing to rescale, so a small grid
+    hipLaunchKernelGGL(k_rescale_pool_arn1, dim3(std::min(nunit, 512)), dim3(256), 0, c->stream, t, w, c->pc_coarse,
+                       c->C, c->ny, c->nx, F);
+}
+
 int pc_update_pool_blocks(const rte_ctx* c) {
     const int F = c->pc_factor;
     const int CW = F > 64 ? F : 64;
@@ -905,15 +938,17 @@ int pc_update_pool_blocks(const rte_ctx* c) {
 }
 
 void pc_update_pool(rte_ctx* c, double* w, const double* V, int nvec, const double* h, const double* scale,
-                    double* partial, double* norm_out) {
+                    double* partial, double* norm_out, const ArnoldiArgs* stage0) {
     const int nblk = pc_update_pool_blocks(c);
+    const ArnoldiArgs none;
+    const ArnoldiArgs& s0 = stage0 ? *stage0 : none;
     const bool pairs = c->nx % 2 == 0 && c->nvec % 2 == 0 && ((uintptr_t)w % 16) == 0 && ((uintptr_t)V % 16) == 0;
     if (pairs)
         hipLaunchKernelGGL(k_update_pool<true>, dim3(nblk), dim3(256), 0, c->stream, w, V, c->nvec, nvec, h, scale,
-                           c->pc_coarse, partial, c->ny, c->nx, c->pc_factor);
+                           c->pc_coarse, partial, c->ny, c->nx, c->pc_factor, s0);
     else
         hipLaunchKernelGGL(k_update_pool<false>, dim3(nblk), dim3(256), 0, c->stream, w, V, c->nvec, nvec, h, scale,
-                           c->pc_coarse, partial, c->ny, c->nx, c->pc_factor);
+                           c->pc_coarse, partial, c->ny, c->nx, c->pc_factor, s0);
     if (norm_out) reduce_partials(partial, nblk, norm_out, 1, c->stream);
 }
 

@@ -440,21 +440,19 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
             at.inv = dinv;
             at.flags = dfl;
             if (fused) {
-                // one pass: the update writes the normalised vector (factor from |w|^2 - |h|^2, stored
-                // by stage 0) and, when preconditioning, the network's pooled input; the rescale
-                // pass runs only when the device flags the norm as off
+                // one pass: the update computes the normalising factor from |w|^2 - |h|^2 and writes
+                // the normalised vector (and, when preconditioning, the network's pooled input),
+                // with stage 0 of the column in its block 0; the rescale kernel runs stage 1 in its
+                // block 0 and rescales only when the device finds the norm off
                 krylov_dots(c->V, n, j + 1, w, n, c->partial, sd, true, st);
                 at.stage = 0;
-                arnoldi_run(at, st);
-                const double* a = sd + 2 * m + 5;
-                if (pc_live) pc_update_pool(c, w, c->V, j + 1, sd, a, c->partial, sd + j + 2);
-                else krylov_update(w, c->V, n, j + 1, sd, n, c->partial, sd + j + 2, st, nullptr, a);
+                if (pc_live) pc_update_pool(c, w, c->V, j + 1, sd, nullptr, c->partial, sd + j + 2, &at);
+                else krylov_update(w, c->V, n, j + 1, sd, n, c->partial, sd + j + 2, st, nullptr, nullptr, &at);
                 at.stage = 1;
                 at.est_out = c->hpipe_dev + j;
                 at.flags_out = c->hpipe_flags_dev + 2 * j;
-                arnoldi_run(at, st);
-                if (pc_live) pc_scale_pool(c, w, w, dinv + j + 1, 0.0, dfl + 3);
-                else vec_scale_dev(w, w, dinv + j + 1, n, st, dfl + 3);
+                if (pc_live) pc_rescale_pool_arn1(c, at, w);
+                else rescale_arn1(at, w, n, st);
             } else {
                 krylov_dots(c->V, n, j + 1, w, n, c->partial, sd, true, st);
                 krylov_update(w, c->V, n, j + 1, sd, n, c->partial, sd + j + 2, st);

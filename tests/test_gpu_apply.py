@@ -144,6 +144,26 @@ def test_apply_3d_small_vs_dense(rte, shape, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_apply_3d_max_size_sampled(rte, prec):
+    """The largest 3D grid the library accepts (256^3, a 512^3 padded FFT): sampled outputs,
+    corners included, against the oracle's direct sum."""
+    n = 256
+    say("apply 3d 256 prec", prec)
+    rng = np.random.default_rng(8)
+    h, mu_a, mu_s = 1.0 / n, 0.05, 10.0
+    ctx = rte.Context(n, dim=3, h=h, mu_a=mu_a, mu_s=mu_s, L=0, prec=prec)
+    u = rng.standard_normal((n, n, n))
+    y = host(ctx.apply(dev(u[None]), layout=rte.LAYOUT_CHANNELS))[0]
+    cells = [(0, 0, 0), (255, 255, 255), (0, 255, 128)] + [tuple(rng.integers(0, n, 3)) for _ in range(3)]
+    ref = op3.apply_sampled(u, cells, h, mu_a + mu_s, mu_s)
+    got = np.array([y[c] for c in cells])
+    e = relerr(got, ref)
+    say("  sampled relerr", e)
+    assert e <= (TOL64 if prec == 1 else TOL32)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_apply_3d_full_size_sampled(rte, prec):
     n = 128
     say("apply 3d 128 prec", prec)
