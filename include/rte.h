@@ -82,7 +82,10 @@ typedef struct {
                             ignored for RTE_PREC_FP64, whose cycles run to the requested tol) */
     int reorth;          /* classical Gram-Schmidt passes: 0 = one pass (default; each restart
                             cycle ends with an FP64 true-residual check), 1 = a second pass when
-                            the norm drops below 1/sqrt(2) of its value, 2 = always two passes */
+                            the norm drops below 1/sqrt(2) of its value, 2 = always two passes.
+                            With one pass the update also normalises the new basis vector, by
+                            1/sqrt(|w|^2 - |h|^2), and it is rescaled in a second pass only when its
+                            measured norm is off 1 by more than 1e-8 (FP32 apply) or 1e-10 (FP64) */
     int use_pc;          /* 1: flexible GMRES with the attached preconditioner (default 1 if one
                             is attached) */
 } rte_solve_opts;

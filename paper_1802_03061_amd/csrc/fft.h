@@ -215,29 +215,43 @@ constexpr int fft_last_ns(int P) {
 // Forward transforms of NFFT sequences whose entries y >= P/2 are zero (zero padding): the first
 // stage (radix R0, no twiddles) is computed in registers from ld(f, y), y < P/2 (the functor returns
 // zero past the data), and written to buf; the remaining stages run in LDS.  Ends with a barrier.
-template <typename T, int P, int NFFT, int LD, int NTHR, typename Ld>
-__device__ __forceinline__ void fft_forward_padded(cx<T>* buf, const cx<T>* tws, int tid, Ld ld) {
-    constexpr int R0 = fft_radix(P, 1);
-    constexpr int NB0 = P / R0;
-    constexpr int NBT = NFFT * NB0;
-    constexpr int IT = (NBT + NTHR - 1) / NTHR;
-    cx<T> in[IT][R0 / 2];
+// Split in two so that a caller can issue the loads of its next group early:
+// fft_padded_load fills the registers (PaddedIn), fft_padded_from_regs does the rest.
+template <typename T, int P, int NFFT, int NTHR>
+struct PaddedIn {
+    static constexpr int R0 = fft_radix(P, 1);
+    static constexpr int NB0 = P / R0;
+    static constexpr int NBT = NFFT * NB0;
+    static constexpr int IT = (NBT + NTHR - 1) / NTHR;
+    cx<T> v[IT][R0 / 2];
+};
+
+template <typename T, int P, int NFFT, int NTHR, typename Ld>
+__device__ __forceinline__ void fft_padded_load(PaddedIn<T, P, NFFT, NTHR>& in, int tid, Ld ld) {
+    using PI = PaddedIn<T, P, NFFT, NTHR>;
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
+    for (int it = 0; it < PI::IT; ++it) {
         const int idx = tid + it * NTHR;
-        const int f = idx / NB0, j = idx % NB0;
+        const int f = idx / PI::NB0, j = idx % PI::NB0;
 #pragma unroll
-        for (int r = 0; r < R0 / 2; ++r)
-            in[it][r] = (NBT % NTHR == 0 || idx < NBT) ? ld(f, j + r * NB0) : mk((T)0, (T)0);
+        for (int r = 0; r < PI::R0 / 2; ++r)
+            in.v[it][r] = (PI::NBT % NTHR == 0 || idx < PI::NBT) ? ld(f, j + r * PI::NB0) : mk((T)0, (T)0);
     }
+}
+
+template <typename T, int P, int NFFT, int LD, int NTHR>
+__device__ __forceinline__ void fft_padded_from_regs(cx<T>* buf, const cx<T>* tws, int tid,
+                                                     const PaddedIn<T, P, NFFT, NTHR>& in) {
+    using PI = PaddedIn<T, P, NFFT, NTHR>;
+    constexpr int R0 = PI::R0;
 #pragma unroll
-    for (int it = 0; it < IT; ++it) {
+    for (int it = 0; it < PI::IT; ++it) {
         const int idx = tid + it * NTHR;
-        if (NBT % NTHR == 0 || idx < NBT) {
-            const int f = idx / NB0, j = idx % NB0;
+        if (PI::NBT % NTHR == 0 || idx < PI::NBT) {
+            const int f = idx / PI::NB0, j = idx % PI::NB0;
             cx<T> v[R0];
 #pragma unroll
-            for (int r = 0; r < R0; ++r) v[r] = r < R0 / 2 ? in[it][r] : mk((T)0, (T)0);
+            for (int r = 0; r < R0; ++r) v[r] = r < R0 / 2 ? in.v[it][r] : mk((T)0, (T)0);
             dft_small<T, R0, false>(v);
 #pragma unroll
             for (int r = 0; r < R0; ++r) buf[f * LD + sw(j * R0 + r)] = v[r];
@@ -245,6 +259,13 @@ __device__ __forceinline__ void fft_forward_padded(cx<T>* buf, const cx<T>* tws,
     }
     __syncthreads();
     fft_stages_range<T, P, NFFT, LD, NTHR, false, R0, P>(buf, tws, tid);
+}
+
+template <typename T, int P, int NFFT, int LD, int NTHR, typename Ld>
+__device__ __forceinline__ void fft_forward_padded(cx<T>* buf, const cx<T>* tws, int tid, Ld ld) {
+    PaddedIn<T, P, NFFT, NTHR> in;
+    fft_padded_load<T, P, NFFT, NTHR>(in, tid, ld);
+    fft_padded_from_regs<T, P, NFFT, LD, NTHR>(buf, tws, tid, in);
 }
 
 // Inverse transforms of the NFFT sequences in buf of which only outputs y < P/2 are wanted: every
