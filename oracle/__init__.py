@@ -18,6 +18,7 @@ Modules
   operator2d  dense matrix, direct-sum apply, sampled apply, FFT apply (2D, 2L+1 modes)
   operator3d  the same for the 3D isotropic kernel
   krylov      dense LU, unrestarted GMRES, Neumann series
+  scattering  the scattering term S(x, theta) at discrete angles from the modes (eq. ani_2d_scattering)
   closed_form the mu_s = 0 solution for f = 1 on the unit square/cube (attenuated source)
   convnet     3x3 convolution network forward/backward in FP64 (learned preconditioner)
 
