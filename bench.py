@@ -225,6 +225,22 @@ def timed_solves(ctx, fs, steps, warmup, torch):
             "max_relres_true": float(max(i["relres_true"] for i in infos))}
 
 
+def scattering_timing(ctx, f, torch, ntheta: int = 64, reps: int = 20) -> dict:
+    """The scattering term of a solved flux at ntheta angles (rte_scattering_term): wall time per
+    call over `reps` back-to-back calls, against its algorithmic bytes (read the complex128 modes,
+    write ntheta float64 values per cell)."""
+    u, _ = ctx.solve(f, tol=1e-8)
+    S = ctx.scattering_term(u, ntheta)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.scattering_term(u, ntheta, out=S)
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / reps
+    nbytes = u.numel() * 16 + S.numel() * 8
+    return {"ntheta": ntheta, "ms": ms, "bytes": nbytes, "hbm_fraction": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
 def bench_pc_workload(args, torch, rte, name, mu_s):
     """hg512 / diff256: plain GMRES, then FGMRES with a freshly trained learned preconditioner."""
     from paper_1802_03061_amd import inputs, pc_train
@@ -253,6 +269,7 @@ def bench_pc_workload(args, torch, rte, name, mu_s):
         ctx.attach_pc(None)
         net.close()
     head = pc if pc is not None else plain
+    post = scattering_timing(ctx, fs[0], torch)
     rf = roofline(ctx, rte, apply_pass_bytes(n, L), args.apply_reps, ["A", "B", "C"])
     ms64, pass64 = ctx.time_apply(rte.OP_A, rte.PREC_FP64, reps=max(5, args.apply_reps // 5))
     variants = {name: [list(ctx.get_variant(p, q)) for q in range(3)]
@@ -285,6 +302,7 @@ def bench_pc_workload(args, torch, rte, name, mu_s):
         "apply_hbm_fraction": rf["apply_hbm_fraction"], "apply_bytes": apply_pass_bytes(n, L),
         "apply_hbm_fraction_3pass_model": model_3pass_bytes(n, L) / (rf["ms_apply"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "kernel_variants": variants,
+        "scattering_term": post,
         "roofline": rf["roofline"],
         "roofline_alu_pass_B": {"bound": "alu", "achieved": ach, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                                 "frac": ach / FP32_VECTOR_PEAK_TFLOPS, "flops": flops_b},

@@ -117,6 +117,17 @@ int rte_apply(rte_ctx* ctx, int op, int layout, int prec, const void* x_dev, voi
  * b_dev: FP64 in the given layout.  Uses the FP64 apply.  Asynchronous. */
 int rte_rhs(rte_ctx* ctx, const double* f_dev, int layout, void* b_dev);
 
+/* The scattering term of the solved flux at ntheta equispaced angles theta_q = 2 pi q / ntheta
+ * (Sec. 3.1, eq. ani_2d_scattering, times mu_s):
+ *     S[q][y][x] = Re( mu_s sum_{k=-L..L} sigma_hat_|k| u_k(x) e^{i k theta_q} )
+ * the right-hand side that, with f, gives the angular flux by one transport sweep (Sec. 1).
+ *   layout   RTE_LAYOUT_MODES (u complex128 [M][ny][nx], any complex vector; the real part of
+ *            the sum is written) or RTE_LAYOUT_CHANNELS (u float64 [C][ny][nx])
+ *   ntheta   1 .. 2^24
+ *   S_dev    float64 [ntheta][ny][nx], caller-owned; may not overlap u
+ * 2D contexts only (3D: RTE_EUNSUPPORTED).  Asynchronous on the context stream. */
+int rte_scattering_term(rte_ctx* ctx, int layout, const void* u_dev, int ntheta, double* S_dev);
+
 /* Replace the solver options (NULL restores the defaults). */
 int rte_set_solve_opts(rte_ctx* ctx, const rte_solve_opts* opts);
 

@@ -63,6 +63,7 @@ def load():
         "rte_setup": (I, [C.POINTER(P), C.POINTER(Grid), D, D, C.POINTER(D), I, I, P]),
         "rte_apply": (I, [P, I, I, I, P, P]),
         "rte_rhs": (I, [P, P, I, P]),
+        "rte_scattering_term": (I, [P, I, P, I, P]),
         "rte_set_solve_opts": (I, [P, C.POINTER(SolveOpts)]),
         "rte_solve": (I, [P, P, D, I, P, C.POINTER(SolveInfo)]),
         "rte_solve_rhs": (I, [P, P, D, I, P, C.POINTER(SolveInfo), P, I, C.POINTER(I)]),
@@ -197,6 +198,19 @@ class Context:
         else:
             out = torch.empty(self.channel_shape, dtype=torch.float64, device=f.device)
         _check(load().rte_rhs(self._h, fp, layout, C.c_void_p(out.data_ptr())))
+        return out
+
+    def scattering_term(self, u, ntheta, layout=LAYOUT_MODES, out=None):
+        """S[q] = Re(mu_s sum_k sigma_hat_|k| u_k e^{i k theta_q}), theta_q = 2 pi q / ntheta
+        (rte_scattering_term); float64 [ntheta, ny, nx]."""
+        if layout == LAYOUT_MODES:
+            up = _ptr(u, torch.complex128, self.modes * self.cells)
+        else:
+            up = _ptr(u, torch.float64, self.channels * self.cells)
+        if out is None:
+            out = torch.empty((int(ntheta),) + tuple(self.channel_shape[1:]), dtype=torch.float64, device=u.device)
+        sp = _ptr(out, torch.float64, int(ntheta) * self.cells)
+        _check(load().rte_scattering_term(self._h, layout, up, int(ntheta), sp))
         return out
 
     def set_opts(self, restart=64, max_cycles=8, inner_tol=1e-5, reorth=0, use_pc=1):

@@ -91,6 +91,7 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.rte_set_solve_opts(None, None) == rte.RTE_EINVAL
     assert lib.rte_query(None, None, None, None) == rte.RTE_EINVAL
     assert lib.rte_autotune(None, 5) == rte.RTE_EINVAL
+    assert lib.rte_scattering_term(None, 0, None, 8, None) == rte.RTE_EINVAL
     assert lib.rte_set_variant(None, 0, 0, 0) == rte.RTE_EINVAL
     assert lib.rte_get_variant(None, 0, 0, None, None) == rte.RTE_EINVAL
     lib.rte_destroy(None)
