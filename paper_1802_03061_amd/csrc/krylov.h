@@ -32,15 +32,14 @@ unsigned krylov_nblk(size_t n);
 // active (device int, may be null): the kernels do nothing when *active == 0.
 void krylov_dots(const double* V, size_t ld, int nvec, const double* w, size_t n, double* partial,
                  double* out, bool with_norm, hipStream_t st, const int* active = nullptr);
-// w = a (w - sum_v h[v] V_v) (h on the device; a = *scale, 1 when scale is NULL);
-// *norm_out = <w, w> after the update (with norm_out NULL only partial row 0 is written).
+// w -= sum_v h[v] V_v (h on the device); *norm_out = <w, w> after the update (with norm_out NULL
+// only partial row 0 is written).  With stage0 (the fused single pass, h = stage0->st) w is also
+// multiplied by the normalising factor, see rescale_arn1.
 void krylov_update(double* w, const double* V, size_t ld, int nvec, const double* h, size_t n, double* partial,
-                   double* norm_out, hipStream_t st, const int* active = nullptr, const double* scale = nullptr,
-                   const ArnoldiArgs* stage0 = nullptr);
+                   double* norm_out, hipStream_t st, const int* active = nullptr, const ArnoldiArgs* stage0 = nullptr);
 void rescale_arn1(const ArnoldiArgs& t, double* w, size_t n, hipStream_t st);
-// dst = (*a) src; nothing when active is given and *active == 0
-void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hipStream_t st,
-                   const int* active = nullptr);
+// dst = (*a) src
+void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hipStream_t st);
 // out[v] = sum_b partial[v * nblk + b] for v < nout, in a fixed order
 void reduce_partials(const double* partial, int nblk, double* out, int nout, hipStream_t st);
 // One Arnoldi column on the device (see k_arnoldi in krylov.hip).

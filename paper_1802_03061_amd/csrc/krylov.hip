@@ -124,15 +124,15 @@ __global__ __launch_bounds__(KT) void k_reduce_partials(const double* __restrict
     if (threadIdx.x == 0) out[v] = s;
 }
 
-// w[i] = a (w[i] - sum_v V[v][i] h[v]) with a = *scale (1 when scale is NULL); partial_norm[blk] =
-// sum over the slice of the new w[i]^2.  PAIRS: as in k_dot_partial, element pairs as 16-byte loads.
-// With s0.st set (the fused single pass, h = s0.st) the factor is computed here instead
-// (arnoldi_stage0_in_update), and block 0 also does stage 0 of the Arnoldi column.
+// w[i] = a (w[i] - sum_v V[v][i] h[v]); partial_norm[blk] = sum over the slice of the new w[i]^2.
+// a = 1, or with s0.st set (the fused single pass, h = s0.st) the normalising factor computed here
+// (arnoldi_stage0_in_update), block 0 also doing stage 0 of the Arnoldi column.  PAIRS: as in
+// k_dot_partial, element pairs as 16-byte loads.
 template <bool PAIRS>
 __global__ __launch_bounds__(KT) void k_cgs_update(double* __restrict__ w, const double* __restrict__ V, size_t ld,
                                                    int nvec, const double* __restrict__ h, size_t n,
                                                    double* __restrict__ partial_norm, const int* __restrict__ active,
-                                                   const double* __restrict__ scale, ArnoldiArgs s0) {
+                                                   ArnoldiArgs s0) {
     __shared__ double sh[KT / 64];
     __shared__ double hs[RTE_KRYLOV_MAXVEC];
     __shared__ double a_sh;
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(KT) void k_cgs_update(double* __restrict__ w, const
         __syncthreads();
         arnoldi_stage0_in_update(s0, hs, &a_sh);
     } else if (threadIdx.x == 0) {
-        a_sh = scale ? *scale : 1.0;
+        a_sh = 1.0;
     }
     __syncthreads();
     const double a = a_sh;
@@ -204,10 +204,9 @@ __global__ __launch_bounds__(KT) void k_rescale_arn1(ArnoldiArgs t, double* __re
     for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) w[i] *= inv;
 }
 
-// dst[i] = (*a) * src[i] with the factor read from device memory; nothing when *active == 0
+// dst[i] = (*a) * src[i] with the factor read from device memory
 __global__ __launch_bounds__(KT) void k_scale_dev(double* __restrict__ dst, const double* __restrict__ src,
-                                                  const double* __restrict__ a, size_t n, const int* __restrict__ active) {
-    if (active && *active == 0) return;
+                                                  const double* __restrict__ a, size_t n) {
     const double s = *a;
     const size_t stride = (size_t)gridDim.x * KT;
     for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) dst[i] = s * src[i];
@@ -308,24 +307,22 @@ void krylov_dots(const double* V, size_t ld, int nvec, const double* w, size_t n
 }
 
 void krylov_update(double* w, const double* V, size_t ld, int nvec, const double* h, size_t n, double* partial,
-                   double* norm_out, hipStream_t st, const int* active, const double* scale,
-                   const ArnoldiArgs* stage0) {
+                   double* norm_out, hipStream_t st, const int* active, const ArnoldiArgs* stage0) {
     const ArnoldiArgs none;
     const ArnoldiArgs& s0 = stage0 ? *stage0 : none;
     const unsigned nblk = grid_for(n, RTE_KRYLOV_NBLK);
     const bool pairs = n % 2 == 0 && ld % 2 == 0 && ((uintptr_t)V % 16) == 0 && ((uintptr_t)w % 16) == 0;
     if (pairs)
         hipLaunchKernelGGL(k_cgs_update<true>, dim3(nblk), dim3(KT), 0, st, w, V, ld, nvec, h, n, partial, active,
-                           scale, s0);
+                           s0);
     else
         hipLaunchKernelGGL(k_cgs_update<false>, dim3(nblk), dim3(KT), 0, st, w, V, ld, nvec, h, n, partial, active,
-                           scale, s0);
+                           s0);
     if (norm_out) hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(KT), 0, st, partial, (int)nblk, norm_out, active);
 }
 
-void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hipStream_t st, const int* active) {
-    // a flag-gated launch usually finds nothing to do, so it takes a small grid
-    hipLaunchKernelGGL(k_scale_dev, dim3(grid_for(n, active ? 512 : 4096)), dim3(KT), 0, st, dst, src, a, n, active);
+void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_dev, dim3(grid_for(n, 4096)), dim3(KT), 0, st, dst, src, a, n);
 }
 
 void rescale_arn1(const ArnoldiArgs& t, double* w, size_t n, hipStream_t st) {

@@ -12,13 +12,14 @@ void pc_free(rte_ctx* c);
 // coarse network output y_j (slot j), with s = 1 / sqrt(nvec) for the unit-norm v_j.
 size_t pc_coarse_len(const rte_ctx* c);
 int pc_begin_solve(rte_ctx* c, int m);                 // slots for m columns, s in c->pc_st
-// v = a w + pool (nothing when active is given and *active == 0)
-void pc_scale_pool(rte_ctx* c, const double* w, double* v, const double* a_dev, double a_host,
-                   const int* active = nullptr);
-// w = (*scale) (w - sum_{v < nvec} h[v] V_v) + pool; *norm_out = <w, w> (partial: one double per
-// block, pc_update_pool_blocks(c) of them; with norm_out NULL only those are written)
-void pc_update_pool(rte_ctx* c, double* w, const double* V, int nvec, const double* h, const double* scale,
-                    double* partial, double* norm_out, const ArnoldiArgs* stage0 = nullptr);
+// v = a w + pool (a = *a_dev, or a_host when a_dev is NULL)
+void pc_scale_pool(rte_ctx* c, const double* w, double* v, const double* a_dev, double a_host);
+// The fused single pass of the preconditioned Arnoldi step: w = a (w - sum_{v < nvec} h[v] V_v)
+// with h = s0.st and the normalising factor a computed on the device (stage 0 of the column in
+// block 0), and the block means of the new w; *norm_out = <w, w> (partial: one double per block,
+// pc_update_pool_blocks(c) of them; with norm_out NULL only those are written)
+void pc_update_pool(rte_ctx* c, double* w, const double* V, int nvec, double* partial, double* norm_out,
+                    const ArnoldiArgs& s0);
 // stage 1 of the fused single pass and, when flagged by the device, w's rescale and new block means
 void pc_rescale_pool_arn1(rte_ctx* c, const ArnoldiArgs& t, double* w);
 int pc_update_pool_blocks(const rte_ctx* c);

@@ -566,13 +566,10 @@ __device__ __forceinline__ void scale_pool_units(const double* __restrict__ w, d
     }
 }
 
-// v = a w and its block means (scale_pool_units), a = *a_dev or a_host when a_dev is NULL; nothing
-// when active is given and *active == 0.
+// v = a w and its block means (scale_pool_units), a = *a_dev or a_host when a_dev is NULL.
 __global__ __launch_bounds__(256) void k_scale_pool(const double* __restrict__ w, double* __restrict__ v,
                                                     const double* __restrict__ a_dev, double a_host,
-                                                    float* __restrict__ coarse, int C, int ny, int nx, int F,
-                                                    const int* __restrict__ active) {
-    if (active && *active == 0) return;
+                                                    float* __restrict__ coarse, int C, int ny, int nx, int F) {
     scale_pool_units(w, v, a_dev ? *a_dev : a_host, coarse, C, ny, nx, F);
 }
 
@@ -586,8 +583,8 @@ __global__ __launch_bounds__(256) void k_rescale_pool_arn1(ArnoldiArgs t, double
 }
 
 // The single Gram-Schmidt pass of the preconditioned Arnoldi step with its normalisation and the
-// network's restriction fused: w = a (w - sum_v V[v] h[v]) (a = *scale, or with st0.st set computed
-// here by arnoldi_stage0_in_update, h = st0.st, block 0 also running stage 0), the F x F block means of
+// network's restriction fused: w = a (w - sum_v V[v] h[v]) (h = st0.st, a computed here by
+// arnoldi_stage0_in_update, block 0 also running stage 0 of the column), the F x F block means of
 // the new w into coarse (as k_scale_pool), and partial_norm[blk] = sum of the new w^2 over the
 // block.  Same work units as k_scale_pool, one per block (every fine cell of the grid [C][ny][nx]
 // with ny, nx multiples of F belongs to exactly one block).  PAIRS (even nx and ld, 16-byte
@@ -595,8 +592,7 @@ __global__ __launch_bounds__(256) void k_rescale_pool_arn1(ArnoldiArgs t, double
 // CW / 2 threads and the block covers twice the rows per step.
 template <bool PAIRS>
 __global__ __launch_bounds__(256) void k_update_pool(double* __restrict__ w, const double* __restrict__ V, size_t ld,
-                                                     int nvec, const double* __restrict__ h,
-                                                     const double* __restrict__ scale, float* __restrict__ coarse,
+                                                     int nvec, float* __restrict__ coarse,
                                                      double* __restrict__ partial_norm, int ny, int nx, int F,
                                                      ArnoldiArgs st0) {
     __shared__ double part[512];
@@ -612,13 +608,9 @@ __global__ __launch_bounds__(256) void k_update_pool(double* __restrict__ w, con
     const int chunk = blockIdx.x % nchunk;
     const int I = (blockIdx.x / nchunk) % Hc;
     const int c = blockIdx.x / (nchunk * Hc);
-    for (int v = threadIdx.x; v < nvec; v += 256) hs[v] = h[v];
-    if (st0.st) {   // the fused single pass: the factor and stage 0 of the Arnoldi column here
-        __syncthreads();
-        arnoldi_stage0_in_update(st0, hs, &a_sh);
-    } else if (threadIdx.x == 0) {
-        a_sh = *scale;
-    }
+    for (int v = threadIdx.x; v < nvec; v += 256) hs[v] = st0.st[v];
+    __syncthreads();
+    arnoldi_stage0_in_update(st0, hs, &a_sh);   // the normalising factor; stage 0 in block 0
     __syncthreads();
     const double a = a_sh;
     const int col = (threadIdx.x % TPR) * PW, rg = threadIdx.x / TPR;
@@ -911,15 +903,13 @@ int pc_begin_solve(rte_ctx* c, int m) {
     return e == hipSuccess ? RTE_OK : set_hip_error(e, "pc_begin_solve", __FILE__, __LINE__);
 }
 
-void pc_scale_pool(rte_ctx* c, const double* w, double* v, const double* a_dev, double a_host, const int* active) {
+void pc_scale_pool(rte_ctx* c, const double* w, double* v, const double* a_dev, double a_host) {
     const int F = c->pc_factor;
     const int CW = F > 64 ? F : 64;
     const int nchunk = (c->nx + CW - 1) / CW;
-    // a flag-gated launch usually finds nothing to do, so it takes a small grid
     const int nunit = c->C * (c->ny / F) * nchunk;
-    const int grid = active ? std::min(nunit, 512) : nunit;
-    hipLaunchKernelGGL(k_scale_pool, dim3(grid), dim3(256), 0, c->stream, w, v, a_dev, a_host, c->pc_coarse, c->C,
-                       c->ny, c->nx, F, active);
+    hipLaunchKernelGGL(k_scale_pool, dim3(nunit), dim3(256), 0, c->stream, w, v, a_dev, a_host, c->pc_coarse, c->C,
+                       c->ny, c->nx, F);
 }
 
 void pc_rescale_pool_arn1(rte_ctx* c, const ArnoldiArgs& t, double* w) {
@@ -937,17 +927,15 @@ int pc_update_pool_blocks(const rte_ctx* c) {
     return c->C * (c->ny / F) * ((c->nx + CW - 1) / CW);
 }
 
-void pc_update_pool(rte_ctx* c, double* w, const double* V, int nvec, const double* h, const double* scale,
-                    double* partial, double* norm_out, const ArnoldiArgs* stage0) {
+void pc_update_pool(rte_ctx* c, double* w, const double* V, int nvec, double* partial, double* norm_out,
+                    const ArnoldiArgs& s0) {
     const int nblk = pc_update_pool_blocks(c);
-    const ArnoldiArgs none;
-    const ArnoldiArgs& s0 = stage0 ? *stage0 : none;
     const bool pairs = c->nx % 2 == 0 && c->nvec % 2 == 0 && ((uintptr_t)w % 16) == 0 && ((uintptr_t)V % 16) == 0;
     if (pairs)
-        hipLaunchKernelGGL(k_update_pool<true>, dim3(nblk), dim3(256), 0, c->stream, w, V, c->nvec, nvec, h, scale,
+        hipLaunchKernelGGL(k_update_pool<true>, dim3(nblk), dim3(256), 0, c->stream, w, V, c->nvec, nvec,
                            c->pc_coarse, partial, c->ny, c->nx, c->pc_factor, s0);
     else
-        hipLaunchKernelGGL(k_update_pool<false>, dim3(nblk), dim3(256), 0, c->stream, w, V, c->nvec, nvec, h, scale,
+        hipLaunchKernelGGL(k_update_pool<false>, dim3(nblk), dim3(256), 0, c->stream, w, V, c->nvec, nvec,
                            c->pc_coarse, partial, c->ny, c->nx, c->pc_factor, s0);
     if (norm_out) reduce_partials(partial, nblk, norm_out, 1, c->stream);
 }
