@@ -374,7 +374,6 @@ __global__ __launch_bounds__(NET_THREADS) void k_net_fused(const float* __restri
         const uint4* ws = reinterpret_cast<const uint4*>(wn);
         uint4* wd = reinterpret_cast<uint4*>(Wall);
         const int nw4 = nwn / 8;
-        const int nin = C * Hc * Wc;
         constexpr int U = 8;
         const uint4 zero4 = {0u, 0u, 0u, 0u};
         for (int base = 0; base < nw4; base += U * NET_THREADS) {
@@ -392,34 +391,39 @@ __global__ __launch_bounds__(NET_THREADS) void k_net_fused(const float* __restri
         }
         if (tid < 4 * layers) smeta[tid] = meta[tid];
         if (tid < nbias) sbias[tid] = bias_all[tid];
-        // the first U * NET_THREADS inputs are loaded now, with the weights still in flight
-        float xin[U];
+        // the input: thread t takes pixel t % (Hc Wc) of channels t / (Hc Wc), t / (Hc Wc) + cstep, ...
+        // (Hc Wc <= NET_THREADS), so the index arithmetic is done once; the loads are issued now,
+        // with the weights still in flight
+        const int HW = Hc * Wc;
+        const int cstep = NET_THREADS / HW;
+        const int pin = tid % HW, c0 = tid / HW;
+        const bool lane_in = tid < cstep * HW;
+        const int yin = pin / Wc, xin0 = pin % Wc;
+        constexpr int UI = 8;   // channels per thread per batch (C <= 17; cstep >= 1)
+        float xin[UI];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int idx = tid + u * NET_THREADS;
-            xin[u] = idx < nin ? in[idx] : 0.f;
+        for (int u = 0; u < UI; ++u) {
+            const int c = c0 + u * cstep;
+            xin[u] = (lane_in && c < C) ? in[(size_t)c * HW + pin] : 0.f;
         }
         uint4* az = reinterpret_cast<uint4*>(lds);
         const uint4 zero = {0u, 0u, 0u, 0u};
         for (int idx = tid; idx < 2 * P * NET_PS / 8; idx += NET_THREADS) az[idx] = zero;
         const float sc = *in_scale;
         __syncthreads();   // the zero fill of the activations is complete
-        for (int base = 0; base < nin; base += U * NET_THREADS) {
-            if (base > 0) {
+        unsigned short* const arow = act0 + ((yin + 1) * (Wc + 2) + xin0 + 1) * NET_PS;
+        for (int cb = 0; cb < C; cb += UI * cstep) {
+            if (cb > 0) {
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int idx = base + tid + u * NET_THREADS;
-                    xin[u] = idx < nin ? in[idx] : 0.f;
+                for (int u = 0; u < UI; ++u) {
+                    const int c = c0 + cb + u * cstep;
+                    xin[u] = (lane_in && c < C) ? in[(size_t)c * HW + pin] : 0.f;
                 }
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int idx = base + tid + u * NET_THREADS;
-                if (idx < nin) {
-                    const int c = idx / (Hc * Wc), r = idx % (Hc * Wc);
-                    const int y = r / Wc, x = r % Wc;
-                    act0[((y + 1) * (Wc + 2) + x + 1) * NET_PS + c] = f2bf(xin[u] * sc);
-                }
+            for (int u = 0; u < UI; ++u) {
+                const int c = c0 + cb + u * cstep;
+                if (lane_in && c < C) arow[c] = f2bf(xin[u] * sc);
             }
         }
     }
