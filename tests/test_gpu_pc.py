@@ -174,8 +174,8 @@ def test_make_pairs_matches_definition(rte):
 def test_learned_pc_reduces_iterations(rte):
     """Diffusion regime, 64^2, L = 2 (HG g = 0.3), mu_s = 50, mu_a = 0.01, 16^2 coarse grid: a
     network trained on pairs from 12 training sources (seeds 10000+) plus noise and multiscale
-    pairs cuts FGMRES iterations on held-out sources (seeds 0-2) against plain GMRES, with the
-    same true-residual tolerance met."""
+    pairs cuts FGMRES iterations on held-out sources (seeds 0-2) against plain GMRES and against
+    FGMRES with the same network untrained, with the same true-residual tolerance met."""
     from paper_1802_03061_amd import pc_train
     n, L, F = 64, 2, 4
     ctx = rte.Context(n, mu_a=0.01, mu_s=50.0, sigma_hat=inputs.hg_sigma_hat(0.3, L), L=L, prec=rte.PREC_FP32)
@@ -184,20 +184,26 @@ def test_learned_pc_reduces_iterations(rte):
     say("pairs", x.shape)
     net, hist = pc_train.train(x, t, w, ctx.channels, steps=1500, batch=32, lr=1e-3, log_every=500)
     say("loss history", hist)
-    plain, pcd = [], []
+    untrained = rte.Net(ctx.channels, 32, 5, seed=1, use_bias=False)   # same shape, initial weights
+    plain, pcd, raw = [], [], []
     for s in range(3):
         f = dev(inputs.workload("diff256", seed=s, n=n)["f"])
         ctx.attach_pc(None)
         _, i0 = ctx.solve(f, tol=1e-8)
+        ctx.attach_pc(untrained.params(), factor=F)
+        _, i2 = ctx.solve(f, tol=1e-8)
         ctx.attach_pc(net.params(), factor=F)
         _, i1 = ctx.solve(f, tol=1e-8)
         say("seed", s, "plain", i0["iterations"], "pc", i1["iterations"], "fallback", i1["pc_fallback"],
-            "relres", i1["relres_true"])
+            "relres", i1["relres_true"], "untrained", i2["iterations"], "fallback", i2["pc_fallback"])
         assert i1["relres_true"] <= 1e-8 and i1["pc_fallback"] == 0
-        plain.append(i0["iterations"]); pcd.append(i1["iterations"])
+        assert i2["relres_true"] <= 1e-8
+        plain.append(i0["iterations"]); pcd.append(i1["iterations"]); raw.append(i2["iterations"])
     assert np.mean(pcd) <= 0.8 * np.mean(plain)
+    assert np.mean(pcd) < np.mean(raw)      # the gain is the training's, not the flexible method's
     ctx.close()
     net.close()
+    untrained.close()
 
 
 def test_broken_network_falls_back_to_plain_gmres(rte):
