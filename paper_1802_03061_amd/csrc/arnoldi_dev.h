@@ -159,17 +159,47 @@ __device__ __forceinline__ void arnoldi_block(const ArnoldiArgs t) {
 }
 
 
-// Stage 1 of the fused single pass inside the rescale kernel: block 0 runs the column's
-// bookkeeping (arnoldi_block); every block decides from the reduced nu2 (st[j+2]), a (st[2m+5])
-// and |w|^2 (st[m+3]) whether the stored vector needs the rescale, and by which factor.  Returns
+// Sum of partial[0..nblk) over the whole block in a fixed order (thread-strided sums, four loads
+// in flight per step, then a wave reduction and the wave results in index order); every block
+// that calls it gets the same bits.  Valid in every thread.
+__device__ __forceinline__ double block_sum_fixed(const double* __restrict__ partial, int nblk) {
+    __shared__ double wsum[16];
+    __shared__ double total;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    double s = 0.0;
+    int b = tid;
+    for (; b + 3 * nt < nblk; b += 4 * nt) {
+        const double a0 = partial[b], a1 = partial[b + nt], a2 = partial[b + 2 * nt], a3 = partial[b + 3 * nt];
+        s += (a0 + a1) + (a2 + a3);
+    }
+    for (; b < nblk; b += nt) s += partial[b];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((tid & 63) == 0) wsum[tid >> 6] = s;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (nt + 63) / 64; ++w) t += wsum[w];
+        total = t;
+    }
+    __syncthreads();
+    return total;
+}
+
+// Stage 1 of the fused single pass inside the rescale kernel: every block adds up the update's
+// per-block partial sums of nu2 (partial[0..nblk), fixed order) and decides from nu2, a
+// (st[2m+5]) and |w|^2 (st[m+3]) whether the stored vector needs the rescale, and by which factor;
+// block 0 also stores nu2 in st[j+2] and runs the column's bookkeeping (arnoldi_block).  Returns
 // that factor, or a negative value when nothing is to be done; every thread of the block gets it.
-__device__ __forceinline__ double arnoldi_stage1_in_rescale(const ArnoldiArgs& t) {
+__device__ __forceinline__ double arnoldi_stage1_in_rescale(const ArnoldiArgs& t, const double* partial, int nblk) {
     __shared__ double inv_sh;
+    const double nu2 = block_sum_fixed(partial, nblk);
     if (threadIdx.x == 0) {
         double hn, inv;
         bool renorm, breakdown;
-        fused_decision(t.st[t.j + 2], t.st[2 * t.m + 5], t.st[t.m + 3], t.renorm_tol, hn, renorm, breakdown, inv);
+        fused_decision(nu2, t.st[2 * t.m + 5], t.st[t.m + 3], t.renorm_tol, hn, renorm, breakdown, inv);
         inv_sh = (renorm || breakdown) ? inv : -1.0;
+        if (blockIdx.x == 0) t.st[t.j + 2] = nu2;   // read back by arnoldi_block in this thread
     }
     if (blockIdx.x == 0) arnoldi_block(t);
     __syncthreads();

@@ -37,7 +37,7 @@ void krylov_dots(const double* V, size_t ld, int nvec, const double* w, size_t n
 // multiplied by the normalising factor, see rescale_arn1.
 void krylov_update(double* w, const double* V, size_t ld, int nvec, const double* h, size_t n, double* partial,
                    double* norm_out, hipStream_t st, const int* active = nullptr, const ArnoldiArgs* stage0 = nullptr);
-void rescale_arn1(const ArnoldiArgs& t, double* w, size_t n, hipStream_t st);
+void rescale_arn1(const ArnoldiArgs& t, double* w, size_t n, const double* partial, int nblk, hipStream_t st);
 // dst = (*a) src
 void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hipStream_t st);
 // out[v] = sum_b partial[v * nblk + b] for v < nout, in a fixed order
@@ -45,8 +45,9 @@ void reduce_partials(const double* partial, int nblk, double* out, int nout, hip
 // One Arnoldi column on the device (see k_arnoldi in krylov.hip).
 void arnoldi_run(const ArnoldiArgs& t, hipStream_t s);
 // Fused single pass: krylov_update with stage0 (h = stage0->st) computes the normalising factor
-// itself and runs stage 0 of the column; rescale_arn1 then runs stage 1 and rescales w when the
-// device finds its norm off (see arnoldi_dev.h).
+// itself and runs stage 0 of the column; rescale_arn1, given the update's nblk per-block partial
+// sums of the new norm, then runs stage 1 and rescales w when the device finds its norm off (see
+// arnoldi_dev.h).
 // x += sum_v y[v] Z_v (y on the device)
 void krylov_combine(double* x, const double* Z, size_t ld, int nvec, const double* y, size_t n, hipStream_t st);
 void vec_scale(double* dst, const double* src, double a, size_t n, hipStream_t st);

@@ -195,10 +195,12 @@ __global__ __launch_bounds__(KT) void k_combine(double* __restrict__ x, const do
     }
 }
 
-// Stage 1 of the fused single pass (block 0: the Arnoldi column's bookkeeping) and, when the
-// stored vector needs it, w *= 1/sqrt(nu2) over the grid.
-__global__ __launch_bounds__(KT) void k_rescale_arn1(ArnoldiArgs t, double* __restrict__ w, size_t n) {
-    const double inv = arnoldi_stage1_in_rescale(t);
+// Stage 1 of the fused single pass (block 0: the Arnoldi column's bookkeeping; every block adds
+// up the update's partial sums of nu2 itself) and, when the stored vector needs it,
+// w *= 1/sqrt(nu2) over the grid.
+__global__ __launch_bounds__(KT) void k_rescale_arn1(ArnoldiArgs t, double* __restrict__ w, size_t n,
+                                                    const double* __restrict__ partial, int nblk) {
+    const double inv = arnoldi_stage1_in_rescale(t, partial, nblk);
     if (inv < 0.0) return;
     const size_t stride = (size_t)gridDim.x * KT;
     for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) w[i] *= inv;
@@ -325,9 +327,9 @@ void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hi
     hipLaunchKernelGGL(k_scale_dev, dim3(grid_for(n, 4096)), dim3(KT), 0, st, dst, src, a, n);
 }
 
-void rescale_arn1(const ArnoldiArgs& t, double* w, size_t n, hipStream_t st) {
+void rescale_arn1(const ArnoldiArgs& t, double* w, size_t n, const double* partial, int nblk, hipStream_t st) {
     // usually nothing to rescale, so a small grid
-    hipLaunchKernelGGL(k_rescale_arn1, dim3(grid_for(n, 512)), dim3(KT), 0, st, t, w, n);
+    hipLaunchKernelGGL(k_rescale_arn1, dim3(grid_for(n, 512)), dim3(KT), 0, st, t, w, n, partial, nblk);
 }
 
 void reduce_partials(const double* partial, int nblk, double* out, int nout, hipStream_t st) {

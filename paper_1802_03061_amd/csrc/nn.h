@@ -21,7 +21,7 @@ void pc_scale_pool(rte_ctx* c, const double* w, double* v, const double* a_dev, 
 void pc_update_pool(rte_ctx* c, double* w, const double* V, int nvec, double* partial, double* norm_out,
                     const ArnoldiArgs& s0);
 // stage 1 of the fused single pass and, when flagged by the device, w's rescale and new block means
-void pc_rescale_pool_arn1(rte_ctx* c, const ArnoldiArgs& t, double* w);
+void pc_rescale_pool_arn1(rte_ctx* c, const ArnoldiArgs& t, double* w, const double* partial);
 int pc_update_pool_blocks(const rte_ctx* c);
 int pc_net_slot(rte_ctx* c, int j);                    // Y_j = N(pooled v_j / s)
 const float* pc_slot(const rte_ctx* c, int j);

@@ -580,8 +580,9 @@ __global__ __launch_bounds__(256) void k_scale_pool(const double* __restrict__ w
 // Stage 1 of the fused single pass (block 0: the Arnoldi column's bookkeeping) and, when the
 // stored vector needs it, its rescale with the block means taken again.
 __global__ __launch_bounds__(256) void k_rescale_pool_arn1(ArnoldiArgs t, double* __restrict__ w,
-                                                           float* __restrict__ coarse, int C, int ny, int nx, int F) {
-    const double inv = arnoldi_stage1_in_rescale(t);
+                                                           float* __restrict__ coarse, int C, int ny, int nx, int F,
+                                                           const double* __restrict__ partial, int nblk) {
+    const double inv = arnoldi_stage1_in_rescale(t, partial, nblk);
     if (inv < 0.0) return;
     scale_pool_units(w, w, inv, coarse, C, ny, nx, F);
 }
@@ -916,13 +917,13 @@ void pc_scale_pool(rte_ctx* c, const double* w, double* v, const double* a_dev, 
                        c->ny, c->nx, F);
 }
 
-void pc_rescale_pool_arn1(rte_ctx* c, const ArnoldiArgs& t, double* w) {
+void pc_rescale_pool_arn1(rte_ctx* c, const ArnoldiArgs& t, double* w, const double* partial) {
     const int F = c->pc_factor;
     const int CW = F > 64 ? F : 64;
     const int nunit = c->C * (c->ny / F) * ((c->nx + CW - 1) / CW);
     // usually nothing to rescale, so a small grid
     hipLaunchKernelGGL(k_rescale_pool_arn1, dim3(std::min(nunit, 512)), dim3(256), 0, c->stream, t, w, c->pc_coarse,
-                       c->C, c->ny, c->nx, F);
+                       c->C, c->ny, c->nx, F, partial, pc_update_pool_blocks(c));
 }
 
 int pc_update_pool_blocks(const rte_ctx* c) {

@@ -446,13 +446,15 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
                 // block 0 and rescales only when the device finds the norm off
                 krylov_dots(c->V, n, j + 1, w, n, c->partial, sd, true, st);
                 at.stage = 0;
-                if (pc_live) pc_update_pool(c, w, c->V, j + 1, c->partial, sd + j + 2, at);
-                else krylov_update(w, c->V, n, j + 1, sd, n, c->partial, sd + j + 2, st, nullptr, &at);
+                // the update leaves its per-block partial sums of the new norm in c->partial; the
+                // rescale kernel adds them up itself
+                if (pc_live) pc_update_pool(c, w, c->V, j + 1, c->partial, nullptr, at);
+                else krylov_update(w, c->V, n, j + 1, sd, n, c->partial, nullptr, st, nullptr, &at);
                 at.stage = 1;
                 at.est_out = c->hpipe_dev + j;
                 at.flags_out = c->hpipe_flags_dev + 2 * j;
-                if (pc_live) pc_rescale_pool_arn1(c, at, w);
-                else rescale_arn1(at, w, n, st);
+                if (pc_live) pc_rescale_pool_arn1(c, at, w, c->partial);
+                else rescale_arn1(at, w, n, c->partial, (int)krylov_nblk(n), st);
             } else {
                 krylov_dots(c->V, n, j + 1, w, n, c->partial, sd, true, st);
                 krylov_update(w, c->V, n, j + 1, sd, n, c->partial, sd + j + 2, st);
