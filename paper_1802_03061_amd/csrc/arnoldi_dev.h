@@ -151,10 +151,14 @@ __device__ __forceinline__ void arnoldi_block(const ArnoldiArgs t) {
     flags[1] = breakdown ? 1 : 0;
     flags[3] = (breakdown || renorm) ? 1 : 0;
     if (nonfinite) flags[2] = 1;
-    if (t.est_out) *t.est_out = ej;
+    // the host polls est_out (a write-once slot): the flags go out first, behind a system fence
     if (t.flags_out) {
         t.flags_out[0] = breakdown ? 1 : 0;
         t.flags_out[1] = (nonfinite || prev_nonfinite) ? 1 : 0;
+    }
+    if (t.est_out) {
+        __threadfence_system();
+        *t.est_out = ej;
     }
 }
 

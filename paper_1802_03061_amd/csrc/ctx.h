@@ -42,7 +42,6 @@ struct rte_ctx {
     double* Z = nullptr;
     double* partial = nullptr;
     double* dsmall = nullptr;
-    double* hsmall = nullptr;   // pinned
     double* arn = nullptr;      // device Arnoldi state (H, Givens, g, estimates)
     int* arn_flags = nullptr;   // [second pass, breakdown, non-finite, spare]
     double* hpipe = nullptr;    // pinned per-iteration residual estimates

@@ -38,6 +38,11 @@ void krylov_dots(const double* V, size_t ld, int nvec, const double* w, size_t n
 void krylov_update(double* w, const double* V, size_t ld, int nvec, const double* h, size_t n, double* partial,
                    double* norm_out, hipStream_t st, const int* active = nullptr, const ArnoldiArgs* stage0 = nullptr);
 void rescale_arn1(const ArnoldiArgs& t, double* w, size_t n, const double* partial, int nblk, hipStream_t st);
+// y = R^{-1} g for the leading k x k block (k <= RTE_MAX_RESTART) of the rotated Hessenberg
+// matrix H (column-major, leading dimension ld) and rotated residual vector g, on the device
+void back_solve_dev(const double* H, int ld, const double* g, int k, double* y, hipStream_t st);
+// g = (g0, 0, ..., 0) with n entries and flags[0..nflags) = 0, on the device
+void init_g(double* g, int n, double g0, int* flags, int nflags, hipStream_t st);
 // dst = (*a) src
 void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hipStream_t st);
 // out[v] = sum_b partial[v * nblk + b] for v < nout, in a fixed order

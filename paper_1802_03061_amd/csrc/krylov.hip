@@ -218,6 +218,45 @@ constexpr int ARN_THREADS = 256;
 
 __global__ __launch_bounds__(ARN_THREADS) void k_arnoldi(ArnoldiArgs t) { arnoldi_block(t); }
 
+// y = R^{-1} g for the leading k x k block of the rotated Hessenberg matrix (upper triangular,
+// column-major with leading dimension ld) and the first k entries of the rotated residual vector:
+// the least-squares solution of k Arnoldi columns (later rotations do not touch these entries).
+// The block is staged in LDS; one wave then runs the back substitution, lane l holding y_l and
+// y_{l+64} (k <= 128), each row's sum taken by a butterfly reduction that gives every lane the
+// same bits.
+__global__ __launch_bounds__(256) void k_back_solve(const double* __restrict__ H, int ld, const double* __restrict__ g,
+                                                    int k, double* __restrict__ y) {
+    extern __shared__ double Rs[];   // [k][k] column-major, then g[k]
+    double* gs = Rs + (size_t)k * k;
+    for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
+        const int i = idx % k, j = idx / k;
+        Rs[idx] = i <= j ? H[(size_t)j * ld + i] : 0.0;
+    }
+    for (int i = threadIdx.x; i < k; i += blockDim.x) gs[i] = g[i];
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
+    const int l = threadIdx.x;
+    double y0 = 0.0, y1 = 0.0;   // y[l], y[l + 64]
+    for (int i = k - 1; i >= 0; --i) {
+        double s = 0.0;
+        if (l > i && l < k) s += Rs[(size_t)l * k + i] * y0;
+        if (l + 64 > i && l + 64 < k) s += Rs[(size_t)(l + 64) * k + i] * y1;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        const double yi = (gs[i] - s) / Rs[(size_t)i * k + i];
+        if (l == i) y0 = yi;
+        if (l + 64 == i) y1 = yi;
+    }
+    if (l < k) y[l] = y0;
+    if (l + 64 < k) y[l + 64] = y1;
+}
+
+// g = (g0, 0, ..., 0), n entries, and flags[0..nflags) = 0
+__global__ void k_init_g(double* __restrict__ g, int n, double g0, int* __restrict__ flags, int nflags) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) g[i] = i == 0 ? g0 : 0.0;
+    for (int i = threadIdx.x; i < nflags; i += blockDim.x) flags[i] = 0;
+}
+
 // dst[i] = a * src[i]
 __global__ __launch_bounds__(KT) void k_scale(double* __restrict__ dst, const double* __restrict__ src, double a,
                                               size_t n) {
@@ -325,6 +364,15 @@ void krylov_update(double* w, const double* V, size_t ld, int nvec, const double
 
 void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_scale_dev, dim3(grid_for(n, 4096)), dim3(KT), 0, st, dst, src, a, n);
+}
+
+void back_solve_dev(const double* H, int ld, const double* g, int k, double* y, hipStream_t st) {
+    const size_t lds = ((size_t)k * k + k) * sizeof(double);
+    hipLaunchKernelGGL(k_back_solve, dim3(1), dim3(256), lds, st, H, ld, g, k, y);
+}
+
+void init_g(double* g, int n, double g0, int* flags, int nflags, hipStream_t st) {
+    hipLaunchKernelGGL(k_init_g, dim3(1), dim3(256), 0, st, g, n, g0, flags, nflags);
 }
 
 void rescale_arn1(const ArnoldiArgs& t, double* w, size_t n, const double* partial, int nblk, hipStream_t st) {

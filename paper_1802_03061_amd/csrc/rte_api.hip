@@ -81,8 +81,6 @@ static void free_krylov(rte_ctx* c) {
     dfree(c->dsmall);
     dfree(c->arn);
     dfree(c->arn_flags);
-    if (c->hsmall) (void)hipHostFree(c->hsmall);
-    c->hsmall = nullptr;
     if (c->hpipe) (void)hipHostFree(c->hpipe);
     c->hpipe = nullptr;
     if (c->hpipe_flags) (void)hipHostFree(c->hpipe_flags);
@@ -132,11 +130,11 @@ int ensure_krylov(rte_ctx* c, int m, bool need_z) {
     // device Arnoldi state: H [(m+1) x m] | cs [m] | sn [m] | g [m+1] | est [m] | inv [m+1]
     if ((rc = dalloc(&c->arn, (size_t)(m + 1) * m + 4 * (size_t)m + 2))) return rc;
     if ((rc = dalloc(&c->arn_flags, 4))) return rc;
-    hipError_t e = hipHostMalloc((void**)&c->hsmall, (size_t)(2 * m + 16) * sizeof(double), hipHostMallocDefault);
-    if (e != hipSuccess) return set_hip_error(e, "hipHostMalloc", __FILE__, __LINE__);
+    hipError_t e = hipSuccess;
     // per-iteration pinned slots: estimate; (breakdown, non-finite) flags
     // per-iteration slots written by the Arnoldi kernel itself (mapped, coherent host memory)
-    e = hipHostMalloc((void**)&c->hpipe, (size_t)m * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent);
+    // [0, m): per-iteration estimates; [m]: the result of a host-side dot product
+    e = hipHostMalloc((void**)&c->hpipe, (size_t)(m + 1) * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent);
     if (e != hipSuccess) return set_hip_error(e, "hipHostMalloc", __FILE__, __LINE__);
     e = hipHostMalloc((void**)&c->hpipe_flags, (size_t)2 * m * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent);
     if (e != hipSuccess) return set_hip_error(e, "hipHostMalloc", __FILE__, __LINE__);
@@ -320,22 +318,35 @@ int autotune_2d(rte_ctx* c, int reps, bool use_cache) {
 
 // ------------------------------------------------------------------ small host helpers ---------
 
-static int dot_host(rte_ctx* c, const double* a, const double* b, double* out) {
-    krylov_dots(a, c->nvec, 1, b, c->nvec, c->partial, c->dsmall, false, c->stream);
-    RTE_HIP_TRY(hipMemcpyAsync(c->hsmall, c->dsmall, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    RTE_HIP_TRY(hipStreamSynchronize(c->stream));
-    *out = c->hsmall[0];
+// Slots of device-visible host memory that the device writes once per use: the host sets them to
+// kPending before the work that writes them is enqueued and polls them, which wakes it sooner than
+// a blocking synchronisation.  The device values (an estimate |g|, a sum of squares) are never
+// negative, so the sentinel cannot be confused with one (NaN included).
+constexpr double kPending = -1.0;
+
+static int wait_slot(rte_ctx* c, const double* slot, hipEvent_t ev) {
+    const volatile double* p = slot;
+    const double t0 = now_ms();
+    while (*p == kPending) {
+        if (now_ms() - t0 > 20.0) {   // a long step: block on the event / stream instead
+            if (ev) RTE_HIP_TRY(hipEventSynchronize(ev));
+            else RTE_HIP_TRY(hipStreamSynchronize(c->stream));
+            if (*p == kPending) return set_error(RTE_EDEVICE, "device result missing after synchronisation");
+            break;
+        }
+    }
     return RTE_OK;
 }
 
-// Solve the upper-triangular k x k system R y = g (R column-major with leading dimension ld).
-static void back_solve(const std::vector<double>& R, int ld, const std::vector<double>& g, int k, std::vector<double>& y) {
-    y.assign(k, 0.0);
-    for (int i = k - 1; i >= 0; --i) {
-        double s = g[i];
-        for (int j = i + 1; j < k; ++j) s -= R[(size_t)j * ld + i] * y[j];
-        y[i] = s / R[(size_t)i * ld + i];
-    }
+static int dot_host(rte_ctx* c, const double* a, const double* b, double* out) {
+    // the reduction writes the result straight into device-visible host memory (slot m of hpipe)
+    const int m = c->krylov_m;
+    c->hpipe[m] = kPending;
+    krylov_dots(a, c->nvec, 1, b, c->nvec, c->partial, c->hpipe_dev + m, false, c->stream);
+    int rc = wait_slot(c, c->hpipe + m, nullptr);
+    if (rc) return rc;
+    *out = c->hpipe[m];
+    return RTE_OK;
 }
 
 // ------------------------------------------------------------------ GMRES ---------------------
@@ -376,7 +387,6 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
     double rn = bn;
     int it = 0, cycles = 0, status = RTE_NOT_CONVERGED;
     double est = bn;
-    std::vector<double> H((size_t)(m + 1) * m), g(m + 1), yv;
     bool pc_live = use_pc;
     // single-pass Gram-Schmidt with the normalisation (and the network's restriction) fused into the
     // update; the preconditioned form needs one partial sum per pooling block in c->partial
@@ -401,10 +411,7 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
         // v_0 = r / rn (with the pooled coarse input of the network when preconditioning)
         if (pc_live) pc_scale_pool(c, c->rv, c->V, nullptr, 1.0 / rn);
         else vec_scale(c->V, c->rv, 1.0 / rn, n, st);
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = rn;
-        RTE_HIP_TRY(hipMemcpyAsync(dg, g.data(), (m + 1) * sizeof(double), hipMemcpyHostToDevice, st));
-        RTE_HIP_TRY(hipMemsetAsync(dfl, 0, 4 * sizeof(int), st));
+        init_g(dg, m + 1, rn, dfl, 4, st);
         est = rn;
         const double cycle_start_rn = rn;
         // Iterations are enqueued one ahead of the convergence check: when iteration j is queued the
@@ -423,6 +430,7 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
                 return rc;
             }
             ++inf.applies;
+            hp[j] = kPending;   // written by this step's Arnoldi stage 1
             double* sd = c->dsmall;
             // Arnoldi column j on the device (stage 0 after the dots, stage 1 after the update)
             ArnoldiArgs at;
@@ -475,7 +483,7 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
             ++launched;
             // check the previous iteration
             if (j >= 1) {
-                RTE_HIP_TRY(hipEventSynchronize(c->ev_iter[j - 1]));
+                if ((rc = wait_slot(c, hp + (j - 1), c->ev_iter[j - 1]))) return rc;
                 const double e1 = hp[j - 1];
                 if (hfl[2 * (j - 1) + 1] != 0 || !std::isfinite(e1)) { bad = true; stop = true; break; }
                 if (hfl[2 * (j - 1)] != 0) { est = e1; jd = j; stop = true; break; }   // breakdown: drop column j
@@ -485,7 +493,7 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
             }
         }
         // settle the last enqueued iteration
-        RTE_HIP_TRY(hipStreamSynchronize(st));
+        if (launched > 0 && (rc = wait_slot(c, hp + (launched - 1), c->ev_iter[launched - 1]))) return rc;
         if (!bad && launched > 0) {
             const int jl = launched - 1;
             const bool prev_brk = jl >= 1 && hfl[2 * (jl - 1)] != 0;
@@ -508,23 +516,19 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
             return set_error(RTE_ENUMERIC, "non-finite value in the Arnoldi process");
         }
         if (jd > 0) {
-            RTE_HIP_TRY(hipMemcpy(H.data(), dH, (size_t)(m + 1) * jd * sizeof(double), hipMemcpyDeviceToHost));
-            RTE_HIP_TRY(hipMemcpy(g.data(), dg, (m + 1) * sizeof(double), hipMemcpyDeviceToHost));
+            // least squares on the device: the rotated H and g never leave it
             if (rec && cycles == 1) {
                 const int nr = std::min(jd, max_rec);
                 for (int k = 1; k <= nr; ++k) {
-                    back_solve(H, m + 1, g, k, yv);
-                    RTE_HIP_TRY(hipMemcpyAsync(c->dsmall, yv.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
+                    back_solve_dev(dH, m + 1, dg, k, c->dsmall, st);
                     double* xr = rec + (size_t)(k - 1) * n;
                     vec_fill(xr, 0.0, n, st);
                     krylov_combine(xr, c->V, n, k, c->dsmall, n, st);
                     if (pc_live) pc_add_correction(c, xr, c->dsmall, k);
-                    RTE_HIP_TRY(hipStreamSynchronize(st));
                 }
                 if (nrec) *nrec = nr;
             }
-            back_solve(H, m + 1, g, jd, yv);
-            RTE_HIP_TRY(hipMemcpyAsync(c->dsmall, yv.data(), jd * sizeof(double), hipMemcpyHostToDevice, st));
+            back_solve_dev(dH, m + 1, dg, jd, c->dsmall, st);
             krylov_combine(x, c->V, n, jd, c->dsmall, n, st);
             if (pc_live) pc_add_correction(c, x, c->dsmall, jd);
         }
