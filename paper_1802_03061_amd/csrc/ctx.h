@@ -48,7 +48,6 @@ struct rte_ctx {
     int* hpipe_flags = nullptr; // pinned per-iteration (breakdown, non-finite)
     double* hpipe_dev = nullptr;     // device addresses of the two (mapped) host arrays above
     int* hpipe_flags_dev = nullptr;
-    std::vector<hipEvent_t> ev_iter;
     rte_solve_opts opts{};
     // kernel variants of the 2D apply passes A, B, C (FP32 and FP64 applies), set by the autotuner
     int varf[3] = {0, 0, 0};

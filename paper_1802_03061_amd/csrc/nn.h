@@ -22,6 +22,10 @@ void pc_update_pool(rte_ctx* c, double* w, const double* V, int nvec, double* pa
                     const ArnoldiArgs& s0);
 // stage 1 of the fused single pass and, when flagged by the device, w's rescale and new block means
 void pc_rescale_pool_arn1(rte_ctx* c, const ArnoldiArgs& t, double* w, const double* partial);
+// Stage 1 with the flagged rescale (without new block means) and the network of the block means
+// the update wrote, into output slot `slot`, in one launch; usable when pc_rescale_net_ok(c).
+bool pc_rescale_net_ok(const rte_ctx* c);
+int pc_rescale_net(rte_ctx* c, const ArnoldiArgs& t, double* w, const double* partial, int slot);
 int pc_update_pool_blocks(const rte_ctx* c);
 int pc_net_slot(rte_ctx* c, int j);                    // Y_j = N(pooled v_j / s)
 const float* pc_slot(const rte_ctx* c, int j);

@@ -352,11 +352,12 @@ __device__ __forceinline__ f32x16 net_row(const unsigned short* __restrict__ Wl,
 }
 
 template <int HID>
-__global__ __launch_bounds__(NET_THREADS) void k_net_fused(const float* __restrict__ in, const float* __restrict__ in_scale,
-                                                           const unsigned short* __restrict__ wn, int nwn,
-                                                           const float* __restrict__ bias_all, int nbias,
-                                                           const int* __restrict__ meta, int layers, int C, int Hc,
-                                                           int Wc, float* __restrict__ out) {
+__device__ __forceinline__ void net_fused_block(const float* __restrict__ in, const float* __restrict__ in_scale,
+                                                const unsigned short* __restrict__ wn, int nwn,
+                                                const float* __restrict__ bias_all, int nbias,
+                                                const int* __restrict__ meta, int layers, int C, int Hc, int Wc,
+                                                float* __restrict__ out, float in_mul) {
+    // in_mul: an extra factor on the input (with *in_scale).
     // meta: per layer [cin, cout, tap-major pack offset, bias offset into bias_all]; nwn: pack length
     // (multiple of 8 shorts); all of it is staged in LDS first, with every global load of the
     // prologue in flight together (the kernel is latency-bound: one workgroup).
@@ -409,7 +410,7 @@ __global__ __launch_bounds__(NET_THREADS) void k_net_fused(const float* __restri
         uint4* az = reinterpret_cast<uint4*>(lds);
         const uint4 zero = {0u, 0u, 0u, 0u};
         for (int idx = tid; idx < 2 * P * NET_PS / 8; idx += NET_THREADS) az[idx] = zero;
-        const float sc = *in_scale;
+        const float sc = *in_scale * in_mul;
         __syncthreads();   // the zero fill of the activations is complete
         unsigned short* const arow = act0 + ((yin + 1) * (Wc + 2) + xin0 + 1) * NET_PS;
         for (int cb = 0; cb < C; cb += UI * cstep) {
@@ -474,6 +475,16 @@ __global__ __launch_bounds__(NET_THREADS) void k_net_fused(const float* __restri
         }
         __syncthreads();
     }
+}
+
+// The whole network as a kernel of its own: one workgroup of NET_THREADS threads.
+template <int HID>
+__global__ __launch_bounds__(NET_THREADS) void k_net_fused(const float* __restrict__ in, const float* __restrict__ in_scale,
+                                                           const unsigned short* __restrict__ wn, int nwn,
+                                                           const float* __restrict__ bias_all, int nbias,
+                                                           const int* __restrict__ meta, int layers, int C, int Hc,
+                                                           int Wc, float* __restrict__ out) {
+    net_fused_block<HID>(in, in_scale, wn, nwn, bias_all, nbias, meta, layers, C, Hc, Wc, out, 1.0f);
 }
 
 // st[0] = s = sqrt(norm2 / n), st[1] = 1/s (0 if s == 0).
@@ -585,6 +596,33 @@ __global__ __launch_bounds__(256) void k_rescale_pool_arn1(ArnoldiArgs t, double
     const double inv = arnoldi_stage1_in_rescale(t, partial, nblk);
     if (inv < 0.0) return;
     scale_pool_units(w, w, inv, coarse, C, ny, nx, F);
+}
+
+// Stage 1 of the fused single pass and the next step's network in one launch: block 1 runs the
+// whole network (net_fused_block) on the block means the update just wrote; every other block
+// takes part in stage 1 (block 0: the column's bookkeeping) and, when the device finds the stored
+// vector's norm off, in w's rescale.  The rescale does not pool again: block 1 takes the same
+// decision from the same partial sums and puts the rescale factor on the network's input instead
+// (the block means are linear in w), so the network sees the block means of the final vector.
+template <int HID>
+__global__ __launch_bounds__(NET_THREADS) void k_rescale_net(ArnoldiArgs t, double* __restrict__ w, size_t n,
+                                                             const double* __restrict__ partial, int nblk,
+                                                             const float* __restrict__ in,
+                                                             const float* __restrict__ in_scale,
+                                                             const unsigned short* __restrict__ wn, int nwn,
+                                                             const float* __restrict__ bias_all, int nbias,
+                                                             const int* __restrict__ meta, int layers, int C, int Hc,
+                                                             int Wc, float* __restrict__ out) {
+    const double inv = arnoldi_stage1_in_rescale(t, partial, nblk);   // bookkeeping in block 0 only
+    if (blockIdx.x == 1) {
+        net_fused_block<HID>(in, in_scale, wn, nwn, bias_all, nbias, meta, layers, C, Hc, Wc, out,
+                             inv < 0.0 ? 1.0f : (float)inv);
+        return;
+    }
+    if (inv < 0.0) return;
+    const size_t wb = blockIdx.x == 0 ? 0 : blockIdx.x - 1, nwb = gridDim.x - 1;
+    const size_t stride = nwb * NET_THREADS;
+    for (size_t i = wb * NET_THREADS + threadIdx.x; i < n; i += stride) w[i] *= inv;
 }
 
 // The single Gram-Schmidt pass of the preconditioned Arnoldi step with its normalisation and the
@@ -946,6 +984,42 @@ void pc_update_pool(rte_ctx* c, double* w, const double* V, int nvec, double* pa
 }
 
 int pc_net_slot(rte_ctx* c, int j) { return pc_net(c, c->pc_Y + (size_t)j * pc_coarse_len(c)); }
+
+// Static LDS of k_rescale_net (Arnoldi column staging, reductions, network metadata) on top of the
+// network's dynamic LDS, with some headroom.
+constexpr size_t RESCALE_NET_STATIC_LDS = 12 * 1024;
+
+bool pc_rescale_net_ok(const rte_ctx* c) {
+    if (!c->pc_wn) return false;
+    NetShape sh;
+    sh.init(c->C, c->pc_hidden, c->pc_layers);
+    const int F = c->pc_factor;
+    return fused_net_lds(sh, c->ny / F, c->nx / F) + RESCALE_NET_STATIC_LDS <= 160 * 1024;
+}
+
+int pc_rescale_net(rte_ctx* c, const ArnoldiArgs& t, double* w, const double* partial, int slot) {
+    NetShape sh;
+    sh.init(c->C, c->pc_hidden, c->pc_layers);
+    const int F = c->pc_factor;
+    const int Hc = c->ny / F, Wc = c->nx / F;
+    const size_t lds = fused_net_lds(sh, Hc, Wc);
+    const int nwn = (int)c->pc_wn_len;
+    float* out = c->pc_Y + (size_t)slot * pc_coarse_len(c);
+    // block 1 is the network; the others share stage 1 and the (rare) rescale
+    const size_t want = (c->nvec + NET_THREADS - 1) / NET_THREADS;
+    const unsigned grid = 2 + (unsigned)std::min<size_t>(want, 254);
+    const int nblk = pc_update_pool_blocks(c);
+    if (c->pc_hidden == 32)
+        hipLaunchKernelGGL((k_rescale_net<32>), dim3(grid), dim3(NET_THREADS), lds, c->stream, t, w, c->nvec, partial,
+                           nblk, c->pc_coarse, c->pc_st + 1, c->pc_wn, nwn, c->pc_bn, c->pc_nbias, c->pc_meta,
+                           sh.layers, c->C, Hc, Wc, out);
+    else
+        hipLaunchKernelGGL((k_rescale_net<16>), dim3(grid), dim3(NET_THREADS), lds, c->stream, t, w, c->nvec, partial,
+                           nblk, c->pc_coarse, c->pc_st + 1, c->pc_wn, nwn, c->pc_bn, c->pc_nbias, c->pc_meta,
+                           sh.layers, c->C, Hc, Wc, out);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RTE_OK : set_hip_error(e, "pc_rescale_net", __FILE__, __LINE__);
+}
 
 const float* pc_slot(const rte_ctx* c, int j) { return c->pc_Y + (size_t)j * pc_coarse_len(c); }
 

@@ -85,8 +85,6 @@ static void free_krylov(rte_ctx* c) {
     c->hpipe = nullptr;
     if (c->hpipe_flags) (void)hipHostFree(c->hpipe_flags);
     c->hpipe_flags = nullptr;
-    for (auto& e : c->ev_iter) if (e) (void)hipEventDestroy(e);
-    c->ev_iter.clear();
     c->krylov_m = 0;
     c->krylov_z = false;
 }
@@ -141,11 +139,6 @@ int ensure_krylov(rte_ctx* c, int m, bool need_z) {
     e = hipHostGetDevicePointer((void**)&c->hpipe_dev, c->hpipe, 0);
     if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->hpipe_flags_dev, c->hpipe_flags, 0);
     if (e != hipSuccess) return set_hip_error(e, "hipHostMalloc", __FILE__, __LINE__);
-    c->ev_iter.assign(m, nullptr);
-    for (int i = 0; i < m; ++i) {
-        e = hipEventCreateWithFlags(&c->ev_iter[i], hipEventDisableTiming);
-        if (e != hipSuccess) return set_hip_error(e, "hipEventCreate", __FILE__, __LINE__);
-    }
     c->krylov_m = m;
     c->krylov_z = need_z;
     return RTE_OK;
@@ -324,13 +317,12 @@ int autotune_2d(rte_ctx* c, int reps, bool use_cache) {
 // negative, so the sentinel cannot be confused with one (NaN included).
 constexpr double kPending = -1.0;
 
-static int wait_slot(rte_ctx* c, const double* slot, hipEvent_t ev) {
+static int wait_slot(rte_ctx* c, const double* slot) {
     const volatile double* p = slot;
     const double t0 = now_ms();
     while (*p == kPending) {
-        if (now_ms() - t0 > 20.0) {   // a long step: block on the event / stream instead
-            if (ev) RTE_HIP_TRY(hipEventSynchronize(ev));
-            else RTE_HIP_TRY(hipStreamSynchronize(c->stream));
+        if (now_ms() - t0 > 20.0) {   // a long step: block on the stream instead
+            RTE_HIP_TRY(hipStreamSynchronize(c->stream));
             if (*p == kPending) return set_error(RTE_EDEVICE, "device result missing after synchronisation");
             break;
         }
@@ -343,7 +335,7 @@ static int dot_host(rte_ctx* c, const double* a, const double* b, double* out) {
     const int m = c->krylov_m;
     c->hpipe[m] = kPending;
     krylov_dots(a, c->nvec, 1, b, c->nvec, c->partial, c->hpipe_dev + m, false, c->stream);
-    int rc = wait_slot(c, c->hpipe + m, nullptr);
+    int rc = wait_slot(c, c->hpipe + m);
     if (rc) return rc;
     *out = c->hpipe[m];
     return RTE_OK;
@@ -392,6 +384,7 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
     // update; the preconditioned form needs one partial sum per pooling block in c->partial
     const bool fused = c->opts.reorth == 0 &&
                        (!use_pc || (size_t)pc_update_pool_blocks(c) <= (size_t)(m + 3) * RTE_KRYLOV_NBLK);
+    const bool rescale_net = fused && use_pc && pc_rescale_net_ok(c);
 
     double* dH = c->arn;
     double* dcs = dH + (size_t)(m + 1) * m;
@@ -418,13 +411,15 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
         // host reads the estimate of iteration j-1, so the device never waits for the host.
         int jd = 0;           // columns of this cycle that are valid
         int launched = 0;
+        bool net_ready = false;   // the network output of the next step is already being computed
         bool stop = false, bad = false;
         for (int j = 0; j < m && it + launched < max_iter && !stop; ++j) {
             double* vj = c->V + (size_t)j * n;
             double* w = c->V + (size_t)(j + 1) * n;
             // flexible GMRES: w = A z_j with z_j = v_j + s P Y_j formed inside the apply
             if (pc_live) {
-                if ((rc = pc_net_slot(c, j))) return rc;
+                if (!net_ready && (rc = pc_net_slot(c, j))) return rc;   // else the last launch ran it
+                net_ready = false;
                 if ((rc = apply_channels_pc(c, vj, w, pc_slot(c, j)))) return rc;
             } else if ((rc = apply_channels(c, APPLY_A, c->prec, vj, nullptr, w, 1))) {
                 return rc;
@@ -461,8 +456,15 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
                 at.stage = 1;
                 at.est_out = c->hpipe_dev + j;
                 at.flags_out = c->hpipe_flags_dev + 2 * j;
-                if (pc_live) pc_rescale_pool_arn1(c, at, w, c->partial);
-                else rescale_arn1(at, w, n, c->partial, (int)krylov_nblk(n), st);
+                if (pc_live && j + 1 < m && rescale_net) {
+                    // stage 1 and the next step's network in one launch
+                    if ((rc = pc_rescale_net(c, at, w, c->partial, j + 1))) return rc;
+                    net_ready = true;
+                } else if (pc_live) {
+                    pc_rescale_pool_arn1(c, at, w, c->partial);
+                } else {
+                    rescale_arn1(at, w, n, c->partial, (int)krylov_nblk(n), st);
+                }
             } else {
                 krylov_dots(c->V, n, j + 1, w, n, c->partial, sd, true, st);
                 krylov_update(w, c->V, n, j + 1, sd, n, c->partial, sd + j + 2, st);
@@ -479,11 +481,12 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
                 if (pc_live) pc_scale_pool(c, w, w, dinv + j + 1, 0.0);
                 else vec_scale_dev(w, w, dinv + j + 1, n, st);
             }
-            RTE_HIP_TRY(hipEventRecord(c->ev_iter[j], st));
+            // no event per step: an event record releases the caches at system scope, an idle
+            // gap of about 6 us before the next launch; the host polls the slot instead
             ++launched;
             // check the previous iteration
             if (j >= 1) {
-                if ((rc = wait_slot(c, hp + (j - 1), c->ev_iter[j - 1]))) return rc;
+                if ((rc = wait_slot(c, hp + (j - 1)))) return rc;
                 const double e1 = hp[j - 1];
                 if (hfl[2 * (j - 1) + 1] != 0 || !std::isfinite(e1)) { bad = true; stop = true; break; }
                 if (hfl[2 * (j - 1)] != 0) { est = e1; jd = j; stop = true; break; }   // breakdown: drop column j
@@ -493,7 +496,7 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
             }
         }
         // settle the last enqueued iteration
-        if (launched > 0 && (rc = wait_slot(c, hp + (launched - 1), c->ev_iter[launched - 1]))) return rc;
+        if (launched > 0 && (rc = wait_slot(c, hp + (launched - 1)))) return rc;
         if (!bad && launched > 0) {
             const int jl = launched - 1;
             const bool prev_brk = jl >= 1 && hfl[2 * (jl - 1)] != 0;
