@@ -237,7 +237,8 @@ __global__ __launch_bounds__(BT) void kb_scale_next(const Chunk* __restrict__ ch
     for (int e = threadIdx.x; e < c.len; e += BT) w[e] *= a;
 }
 
-// j += 1 and the number of problems still iterating.  Single block.
+// count[j] = the number of problems still iterating, then j += 1.  Single block.  count is
+// device-visible host memory that the host polls (one write-once slot per step of the cycle).
 __global__ __launch_bounds__(BT) void kb_tick(int* __restrict__ dj, const int* __restrict__ act, int P,
                                               int* __restrict__ count) {
     __shared__ int red[4];
@@ -247,8 +248,9 @@ __global__ __launch_bounds__(BT) void kb_tick(int* __restrict__ dj, const int* _
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) {
-        *count = red[0] + red[1] + red[2] + red[3];
-        *dj += 1;
+        const int j = *dj;
+        count[j] = red[0] + red[1] + red[2] + red[3];
+        *dj = j + 1;
     }
 }
 
@@ -411,15 +413,13 @@ struct Plan {
     hipStream_t st = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::vector<hipEvent_t> ev;
-    void* pinned = nullptr;                // BState[P] | act[P] | todo[P] | rn2[P] | count (mapped)
+    void* pinned = nullptr;                // BState[P] | act[P] | todo[P] | rn2[P] | count[m + 1] (mapped)
     BState* h_bs = nullptr;
     int *h_act = nullptr, *h_todo = nullptr, *h_cnt = nullptr, *h_cnt_dev = nullptr;
     double* h_rn2 = nullptr;
     ~Plan() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
-        for (auto e : ev) if (e) (void)hipEventDestroy(e);
         if (pinned) (void)hipHostFree(pinned);
         if (st) (void)hipStreamDestroy(st);
         if (arena) (void)hipFree(arena);
@@ -568,10 +568,8 @@ int build_plan(Plan& pl, int P, rte_ctx* const* ctxs) {
     pl.h_rn2 = (double*)(((uintptr_t)(pl.h_todo + P) + 7) / 8 * 8);
     pl.h_cnt = (int*)(pl.h_rn2 + P);
     BK_TRY(hipHostGetDevicePointer((void**)&pl.h_cnt_dev, pl.h_cnt, 0));
-    pl.ev.assign(m, nullptr);
-    for (auto& e : pl.ev) BK_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    // capture one inner iteration; replay i writes its active count to h_cnt[i % (m + 1)]... the
-    // count slot is a single int: replays are checked one behind through events (see run_plan)
+    // capture one inner iteration; replay i (i < m, the step index) writes its active count to
+    // h_cnt[i], which the host polls one replay behind
     const unsigned gP = (unsigned)((P + 63) / 64);
     BK_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
     int crc = apply_batch<T>(pl.cls, (const BatchProb<T>*)pl.d_it, pl.d_act, pl.d_j, APPLY_A, st);
@@ -657,15 +655,23 @@ int run_plan(Plan& pl, rte_ctx* const* ctxs, const double* const* f, const doubl
         BK_TRY(hipMemcpyAsync(pl.d_todo, h_todo, sizeof(int) * P, hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(kb_cycle_start, dim3(gP), dim3(64), 0, st, pl.d_kp, pl.d_act, pl.d_bs, pl.d_j, m, P);
         hipLaunchKernelGGL(kb_vec, dim3(NCH), dim3(BT), 0, st, pl.d_ch, pl.d_kp, pl.d_act, pl.d_bs, 1);
-        // inner iterations: replay the graph; replay i's tick writes the active count to mapped
-        // host memory, read after replay i's event while replay i + 1 runs
+        // inner iterations: replay the graph; replay i's tick writes the active count into the
+        // write-once slot h_cnt[i] (mapped host memory, -1 until written), which the host polls
+        // while replay i + 1 runs.  No event per replay: a record costs an idle gap on the GPU.
+        volatile int* cnt = pl.h_cnt;
+        for (int i = 0; i < m; ++i) cnt[i] = -1;
         for (int i = 0; i < m; ++i) {
             BK_TRY(hipGraphLaunch(pl.exec, st));
-            BK_TRY(hipEventRecord(pl.ev[i], st));
             if (i >= 1) {
-                BK_TRY(hipEventSynchronize(pl.ev[i - 1]));
-                // the count may already be replay i's (it only decreases): 0 means all have stopped
-                if (*(volatile int*)pl.h_cnt == 0) break;
+                const double tw = now_ms();
+                while (cnt[i - 1] < 0) {
+                    if (now_ms() - tw > 20.0) {   // a long replay: block on the stream instead
+                        BK_TRY(hipStreamSynchronize(st));
+                        if (cnt[i - 1] < 0) return set_error(RTE_EDEVICE, "batched step count missing");
+                        break;
+                    }
+                }
+                if (cnt[i - 1] == 0) break;   // every problem has stopped
             }
         }
         // x += V y, r = b - A x (FP64), |r|
