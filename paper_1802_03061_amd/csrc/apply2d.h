@@ -75,19 +75,20 @@ int apply2d_batch_pass_c(int PX, const BatchProb<T>* probs, const int2* items, i
                          const int* dj, int mode, hipStream_t st);
 
 // y = x - K~ D x (APPLY_A), K~ x (APPLY_KT) or b - (x - K~ D x) (APPLY_RESID) on nbatch channel
-// vectors [nbatch][C][ny][nx] of float64, computed with FFTs in precision T.
-template <typename T>
-int apply2d(const Apply2DArgs<T>& a, const double* x, const double* b, double* y, int mode,
+// vectors [nbatch][C][ny][nx] stored as TV (float64, or float32 with T = float; b is float64),
+// computed with FFTs in precision T.
+template <typename T, typename TV>
+int apply2d(const Apply2DArgs<T>& a, const TV* x, const double* b, TV* y, int mode,
             const ChanScale& sc, int nbatch);
-template <typename T>
-int apply2d_pass_a(const Apply2DArgs<T>& a, const double* x, const ChanScale& sc, int nbatch);
+template <typename T, typename TV>
+int apply2d_pass_a(const Apply2DArgs<T>& a, const TV* x, const ChanScale& sc, int nbatch);
 template <typename T>
 int apply2d_pass_b(const Apply2DArgs<T>& a, int nbatch);
 // True when pass B for (L, PY) in precision T needs the work2 buffer.
 template <typename T>
 bool apply2d_needs_work2(int L, int PY);
-template <typename T>
-int apply2d_pass_c(const Apply2DArgs<T>& a, const double* x, const double* b, double* y, int mode,
+template <typename T, typename TV>
+int apply2d_pass_c(const Apply2DArgs<T>& a, const TV* x, const double* b, TV* y, int mode,
                    int nbatch);
 
 }  // namespace rte

@@ -62,8 +62,8 @@ __device__ __forceinline__ int xcd_tile(int b, int G) { return (G & 7) ? b : (b 
 // column 0 of T as (X[0], X[PX/2]); T then has PX/2 columns.
 // One tile of TR rows of one channel: xin is the channel's [ny][nx] input, out its [NKS][ny]
 // transposed x-spectrum; tws holds the staged twiddles.
-template <typename T, int PX, int TR, int NTHR>
-__device__ __forceinline__ void pass_a_tile(const double* __restrict__ xin, cx<T>* __restrict__ out, int nx, int ny,
+template <typename T, int PX, int TR, int NTHR, typename TV>
+__device__ __forceinline__ void pass_a_tile(const TV* __restrict__ xin, cx<T>* __restrict__ out, int nx, int ny,
                                             double s, int pack, int y0, cx<T>* buf, const cx<T>* tws, int tid,
                                             const float* __restrict__ corr_c = nullptr, int cF = 1, double cs = 0.0) {
     constexpr int NP = TR / 2;        // complex FFTs per block (two real rows each)
@@ -86,8 +86,8 @@ __device__ __forceinline__ void pass_a_tile(const double* __restrict__ xin, cx<T
         for (int r = 0; r < R0 / 2; ++r) {
             const int m = j + r * NB0;
             const bool ok = (NBT % NTHR == 0 || idx < NBT) && m < nx;
-            ra[it][r] = (ok && ya < ny) ? xin[(size_t)ya * nx + m] : 0.0;
-            rb[it][r] = (ok && yb < ny) ? xin[(size_t)yb * nx + m] : 0.0;
+            ra[it][r] = (ok && ya < ny) ? (double)xin[(size_t)ya * nx + m] : 0.0;
+            rb[it][r] = (ok && yb < ny) ? (double)xin[(size_t)yb * nx + m] : 0.0;
         }
     }
     if (corr_c) {
@@ -143,8 +143,8 @@ __device__ __forceinline__ void pass_a_tile(const double* __restrict__ xin, cx<T
     }
 }
 
-template <typename T, int PX, int TR, int NTHR>
-__global__ __launch_bounds__(NTHR) void k_pass_a(const double* __restrict__ x, cx<T>* __restrict__ Tb,
+template <typename T, int PX, int TR, int NTHR, typename TV>
+__global__ __launch_bounds__(NTHR) void k_pass_a(const TV* __restrict__ x, cx<T>* __restrict__ Tb,
                                                  const cx<T>* __restrict__ tw, int nx, int ny, int C,
                                                  ChanScale sc, int pack, const float* __restrict__ corr, int cF,
                                                  double cs) {
@@ -181,9 +181,9 @@ __global__ __launch_bounds__(NTHR) void k_pass_a_batch(const BatchProb<T>* __res
 // ---------------------------------------------------------------------------- pass C --------
 // One tile of TR rows of one channel: src is the channel's [NKS][ny] spectrum; xin, bin, yout its
 // [ny][nx] input, right-hand side and output.
-template <typename T, int PX, int TR, int NTHR>
-__device__ __forceinline__ void pass_c_tile(const cx<T>* __restrict__ src, const double* __restrict__ xin,
-                                            const double* __restrict__ bin, double* __restrict__ yout, int nx, int ny,
+template <typename T, int PX, int TR, int NTHR, typename TV>
+__device__ __forceinline__ void pass_c_tile(const cx<T>* __restrict__ src, const TV* __restrict__ xin,
+                                            const double* __restrict__ bin, TV* __restrict__ yout, int nx, int ny,
                                             int mode, int pack, int y0, cx<T>* buf, const cx<T>* tws, int tid,
                                             const float* __restrict__ corr_c = nullptr, int cF = 1, double cs = 0.0) {
     constexpr int NP = TR / 2;
@@ -237,8 +237,8 @@ __device__ __forceinline__ void pass_c_tile(const cx<T>* __restrict__ src, const
         for (int r = 0; r < RL / 2; ++r) {
             const int m = j + r * NSL;
             const bool oka = m < nx && ya < ny, okb = m < nx && yb < ny;
-            xa_[r] = (oka && mode != APPLY_KT) ? xin[(size_t)ya * nx + m] : 0.0;
-            xb_[r] = (okb && mode != APPLY_KT) ? xin[(size_t)yb * nx + m] : 0.0;
+            xa_[r] = (oka && mode != APPLY_KT) ? (double)xin[(size_t)ya * nx + m] : 0.0;
+            xb_[r] = (okb && mode != APPLY_KT) ? (double)xin[(size_t)yb * nx + m] : 0.0;
             ba_[r] = (oka && mode == APPLY_RESID) ? bin[(size_t)ya * nx + m] : 0.0;
             bb_[r] = (okb && mode == APPLY_RESID) ? bin[(size_t)yb * nx + m] : 0.0;
             if (corr_c && oka) xa_[r] += cs * (double)coarse_bilerp(corr_c, Hc, Wc, cF, ya, m);
@@ -262,16 +262,18 @@ __device__ __forceinline__ void pass_c_tile(const cx<T>* __restrict__ src, const
             if (m >= nx) continue;
             const double va = (double)v[r].re, vb = (double)v[r].im;
             if (ya < ny)
-                yout[(size_t)ya * nx + m] = mode == APPLY_A ? xa_[r] - va : mode == APPLY_KT ? va : ba_[r] - xa_[r] + va;
+                yout[(size_t)ya * nx + m] =
+                    (TV)(mode == APPLY_A ? xa_[r] - va : mode == APPLY_KT ? va : ba_[r] - xa_[r] + va);
             if (yb < ny)
-                yout[(size_t)yb * nx + m] = mode == APPLY_A ? xb_[r] - vb : mode == APPLY_KT ? vb : bb_[r] - xb_[r] + vb;
+                yout[(size_t)yb * nx + m] =
+                    (TV)(mode == APPLY_A ? xb_[r] - vb : mode == APPLY_KT ? vb : bb_[r] - xb_[r] + vb);
         }
     }
 }
 
-template <typename T, int PX, int TR, int NTHR>
-__global__ __launch_bounds__(NTHR) void k_pass_c(const cx<T>* __restrict__ Tb, const double* __restrict__ xin,
-                                                 const double* __restrict__ bin, double* __restrict__ yout,
+template <typename T, int PX, int TR, int NTHR, typename TV>
+__global__ __launch_bounds__(NTHR) void k_pass_c(const cx<T>* __restrict__ Tb, const TV* __restrict__ xin,
+                                                 const double* __restrict__ bin, TV* __restrict__ yout,
                                                  const cx<T>* __restrict__ tw, int nx, int ny, int mode, int pack,
                                                  int C, const float* __restrict__ corr, int cF, double cs) {
     constexpr int LD = padded(PX) + 1;
@@ -310,14 +312,14 @@ __global__ __launch_bounds__(NTHR) void k_pass_c_batch(const BatchProb<T>* __res
 
 // ---------------------------------------------------------------------------- dispatch -------
 template <typename T> constexpr int tile_rows() { return sizeof(T) == 4 ? 16 : 8; }
-template <typename T, int PX, int TR>
-static void launch_a_tr(const Apply2DArgs<T>& a, const double* x, const ChanScale& sc, int nchan_total) {
+template <typename T, int PX, int TR, typename TV>
+static void launch_a_tr(const Apply2DArgs<T>& a, const TV* x, const ChanScale& sc, int nchan_total) {
     dim3 grid((a.ny + TR - 1) / TR, nchan_total);
-    hipLaunchKernelGGL((k_pass_a<T, PX, TR, 256>), grid, dim3(256), 0, a.stream, x, a.work, a.twx, a.nx,
+    hipLaunchKernelGGL((k_pass_a<T, PX, TR, 256, TV>), grid, dim3(256), 0, a.stream, x, a.work, a.twx, a.nx,
                        a.ny, a.C, sc, a.pack, a.corr, a.cF, a.cs);
 }
-template <typename T, int PX>
-static void launch_a(const Apply2DArgs<T>& a, const double* x, const ChanScale& sc, int nchan_total) {
+template <typename T, int PX, typename TV>
+static void launch_a(const Apply2DArgs<T>& a, const TV* x, const ChanScale& sc, int nchan_total) {
     constexpr int TR = tile_rows<T>();
     if constexpr (PX >= 128) {
         if (a.var[0] == 1) return launch_a_tr<T, PX, TR / 2>(a, x, sc, nchan_total);
@@ -327,15 +329,15 @@ static void launch_a(const Apply2DArgs<T>& a, const double* x, const ChanScale& 
     launch_a_tr<T, PX, TR>(a, x, sc, nchan_total);
 }
 
-template <typename T, int PX, int TR>
-static void launch_c_tr(const Apply2DArgs<T>& a, const double* x, const double* b, double* y, int mode,
+template <typename T, int PX, int TR, typename TV>
+static void launch_c_tr(const Apply2DArgs<T>& a, const TV* x, const double* b, TV* y, int mode,
                         int nchan_total) {
     dim3 grid((a.ny + TR - 1) / TR, nchan_total);
-    hipLaunchKernelGGL((k_pass_c<T, PX, TR, 256>), grid, dim3(256), 0, a.stream, a.work, x, b, y, a.twx,
+    hipLaunchKernelGGL((k_pass_c<T, PX, TR, 256, TV>), grid, dim3(256), 0, a.stream, a.work, x, b, y, a.twx,
                        a.nx, a.ny, mode, a.pack, a.C, mode == APPLY_A ? a.corr : nullptr, a.cF, a.cs);
 }
-template <typename T, int PX>
-static void launch_c(const Apply2DArgs<T>& a, const double* x, const double* b, double* y, int mode,
+template <typename T, int PX, typename TV>
+static void launch_c(const Apply2DArgs<T>& a, const TV* x, const double* b, TV* y, int mode,
                      int nchan_total) {
     constexpr int TR = tile_rows<T>();
     if constexpr (PX >= 128) {
@@ -378,8 +380,8 @@ int apply2d_variant_count(int pass, int L, int PX, int PY) {
 template int apply2d_variant_count<float>(int, int, int, int);
 template int apply2d_variant_count<double>(int, int, int, int);
 
-template <typename T>
-int apply2d_pass_a(const Apply2DArgs<T>& a, const double* x, const ChanScale& sc, int nbatch) {
+template <typename T, typename TV>
+int apply2d_pass_a(const Apply2DArgs<T>& a, const TV* x, const ChanScale& sc, int nbatch) {
     RTE_P_SWITCH(a.PX, launch_a, a, x, sc, nbatch * a.C);
     return 0;
 }
@@ -415,8 +417,8 @@ bool apply2d_needs_work2(int L, int PY) {
 }
 template bool apply2d_needs_work2<float>(int, int);
 template bool apply2d_needs_work2<double>(int, int);
-template <typename T>
-int apply2d_pass_c(const Apply2DArgs<T>& a, const double* x, const double* b, double* y, int mode,
+template <typename T, typename TV>
+int apply2d_pass_c(const Apply2DArgs<T>& a, const TV* x, const double* b, TV* y, int mode,
                    int nbatch) {
     RTE_P_SWITCH(a.PX, launch_c, a, x, b, y, mode, nbatch * a.C);
     return 0;
@@ -461,25 +463,26 @@ template int apply2d_batch_pass_c<float>(int, const BatchProb<float>*, const int
 template int apply2d_batch_pass_c<double>(int, const BatchProb<double>*, const int2*, int, const int*, const int*, int,
                                           hipStream_t);
 
-template <typename T>
-int apply2d(const Apply2DArgs<T>& a, const double* x, const double* b, double* y, int mode,
+template <typename T, typename TV>
+int apply2d(const Apply2DArgs<T>& a, const TV* x, const double* b, TV* y, int mode,
             const ChanScale& sc, int nbatch) {
     if (apply2d_pass_a<T>(a, x, sc, nbatch)) return -1;
     if (apply2d_pass_b<T>(a, nbatch)) return -1;
     return apply2d_pass_c<T>(a, x, b, y, mode, nbatch);
 }
 
-template int apply2d<float>(const Apply2DArgs<float>&, const double*, const double*, double*, int,
-                            const ChanScale&, int);
-template int apply2d<double>(const Apply2DArgs<double>&, const double*, const double*, double*, int,
-                             const ChanScale&, int);
-template int apply2d_pass_a<float>(const Apply2DArgs<float>&, const double*, const ChanScale&, int);
-template int apply2d_pass_a<double>(const Apply2DArgs<double>&, const double*, const ChanScale&, int);
+// (compute precision, vector storage): FP64 vectors for both precisions, FP32 vectors for the
+// FP32 apply (the inner solve's basis)
+#define RTE_APPLY2D_INST(T, TV)                                                                             \
+    template int apply2d<T, TV>(const Apply2DArgs<T>&, const TV*, const double*, TV*, int, const ChanScale&, \
+                                int);                                                                       \
+    template int apply2d_pass_a<T, TV>(const Apply2DArgs<T>&, const TV*, const ChanScale&, int);            \
+    template int apply2d_pass_c<T, TV>(const Apply2DArgs<T>&, const TV*, const double*, TV*, int, int);
+RTE_APPLY2D_INST(float, double)
+RTE_APPLY2D_INST(double, double)
+RTE_APPLY2D_INST(float, float)
+#undef RTE_APPLY2D_INST
 template int apply2d_pass_b<float>(const Apply2DArgs<float>&, int);
 template int apply2d_pass_b<double>(const Apply2DArgs<double>&, int);
-template int apply2d_pass_c<float>(const Apply2DArgs<float>&, const double*, const double*, double*, int,
-                                   int);
-template int apply2d_pass_c<double>(const Apply2DArgs<double>&, const double*, const double*, double*,
-                                    int, int);
 
 }  // namespace rte

@@ -532,7 +532,7 @@ int build_plan(Plan& pl, int P, rte_ctx* const* ctxs) {
         rte_ctx* c = ctxs[p];
         KryProb& k = pl.kp[p];
         double* sl = pl.d_slab + S * p;
-        k.V = c->V; k.x = c->xv; k.r = c->rv; k.b = c->bv;
+        k.V = basis<double>(c); k.x = c->xv; k.r = c->rv; k.b = c->bv;
         k.H = sl;
         k.cs = sl + (size_t)(m + 1) * m;
         k.sn = k.cs + m;
@@ -541,9 +541,9 @@ int build_plan(Plan& pl, int P, rte_ctx* const* ctxs) {
         k.u = nullptr;
         const double s = c->mu_s * c->sigma[0];
         if constexpr (sizeof(T) == 4)
-            it[p] = batch_prob<float>(c, c->Qf, c->twf[0], c->twf[1], c->wf, s, c->V, c->V, nullptr, 1, 1);
+            it[p] = batch_prob<float>(c, c->Qf, c->twf[0], c->twf[1], c->wf, s, k.V, k.V, nullptr, 1, 1);
         else
-            it[p] = batch_prob<double>(c, c->Qd, c->twd[0], c->twd[1], c->wd, s, c->V, c->V, nullptr, 1, 1);
+            it[p] = batch_prob<double>(c, c->Qd, c->twd[0], c->twd[1], c->wd, s, k.V, k.V, nullptr, 1, 1);
         res[p] = batch_prob<double>(c, c->Qd, c->twd[0], c->twd[1], c->wd, s, c->xv, c->rv, c->bv, 0, 0);
     }
     BK_TRY(hipMemcpyAsync(pl.d_ch, pl.chunks.data(), sizeof(Chunk) * NCH, hipMemcpyHostToDevice, st));
@@ -731,7 +731,7 @@ int solve_batched_t(int P, rte_ctx* const* ctxs, const double* const* f, const d
     const double t0 = now_ms();
     const int m = ctxs[0]->opts.restart;
     for (int p = 0; p < P; ++p) {
-        int rc = ensure_krylov(ctxs[p], m, false);
+        int rc = ensure_krylov(ctxs[p], m, false, sizeof(double));   // an FP64 basis in every precision
         if (rc) return rc;
         BK_TRY(hipStreamSynchronize(ctxs[p]->stream));
     }

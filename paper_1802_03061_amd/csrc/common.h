@@ -44,6 +44,14 @@ __host__ __device__ inline void cmac(cx<T>& a, cx<T> b, cx<T> c) {
 template <typename To, typename Ti>
 __host__ __device__ inline cx<To> cvt(cx<Ti> a) { return mk((To)a.re, (To)a.im); }
 
+// Two consecutive elements of a real vector, loaded or stored as one access.
+template <typename T>
+struct pair_of;
+template <>
+struct pair_of<double> { using type = double2; };
+template <>
+struct pair_of<float> { using type = float2; };
+
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v >> 1); }
 constexpr bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 inline int next_pow2(int v) { int p = 1; while (p < v) p <<= 1; return p; }

@@ -38,7 +38,10 @@ struct rte_ctx {
     // Krylov basis
     int krylov_m = 0;
     bool krylov_z = false;
-    double* V = nullptr;
+    size_t krylov_vbytes = 0;   // bytes per basis entry the allocation was sized for
+    // (m + 1) basis vectors of nvec entries: float in FP32 contexts (the inner solve of the
+    // mixed-precision refinement keeps its basis in the apply's precision), double otherwise
+    unsigned char* V = nullptr;
     double* Z = nullptr;
     double* partial = nullptr;
     double* dsmall = nullptr;
@@ -73,9 +76,12 @@ struct rte_ctx {
 };
 
 namespace rte {
-int ensure_krylov(rte_ctx* c, int m, bool need_z);
+// Basis of m + 1 vectors with vbytes per entry (and Z when need_z), kept when large enough.
+int ensure_krylov(rte_ctx* c, int m, bool need_z, size_t vbytes);
 int apply_channels(rte_ctx* c, int mode, int prec, const double* x, const double* b, double* y, int nbatch);
-int apply_channels_pc(rte_ctx* c, const double* v, double* y, const float* Y);
+// Basis vector element type of a context.
+template <typename TV>
+inline TV* basis(rte_ctx* c) { return reinterpret_cast<TV*>(c->V); }
 int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
                double* rec, int max_rec, int* nrec);
 int autotune_2d(rte_ctx* c, int reps, bool use_cache);

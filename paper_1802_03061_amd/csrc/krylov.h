@@ -1,4 +1,5 @@
-// FP64 Krylov vector kernels (host wrappers).
+// Krylov vector kernels (host wrappers).  Sums and products are FP64; basis vectors (TV) are
+// double, or float for the inner solve of the FP32 apply.
 #pragma once
 #include "common.h"
 
@@ -30,21 +31,25 @@ unsigned krylov_nblk(size_t n);
 // only the per-block partial sums are written (row v of krylov_nblk(n) entries).
 // partial needs (nvec + 1) * RTE_KRYLOV_NBLK doubles.
 // active (device int, may be null): the kernels do nothing when *active == 0.
-void krylov_dots(const double* V, size_t ld, int nvec, const double* w, size_t n, double* partial,
+template <typename TV>
+void krylov_dots(const TV* V, size_t ld, int nvec, const TV* w, size_t n, double* partial,
                  double* out, bool with_norm, hipStream_t st, const int* active = nullptr);
 // w -= sum_v h[v] V_v (h on the device); *norm_out = <w, w> after the update (with norm_out NULL
 // only partial row 0 is written).  With stage0 (the fused single pass, h = stage0->st) w is also
 // multiplied by the normalising factor, see rescale_arn1.
-void krylov_update(double* w, const double* V, size_t ld, int nvec, const double* h, size_t n, double* partial,
+template <typename TV>
+void krylov_update(TV* w, const TV* V, size_t ld, int nvec, const double* h, size_t n, double* partial,
                    double* norm_out, hipStream_t st, const int* active = nullptr, const ArnoldiArgs* stage0 = nullptr);
-void rescale_arn1(const ArnoldiArgs& t, double* w, size_t n, const double* partial, int nblk, hipStream_t st);
+template <typename TV>
+void rescale_arn1(const ArnoldiArgs& t, TV* w, size_t n, const double* partial, int nblk, hipStream_t st);
 // y = R^{-1} g for the leading k x k block (k <= RTE_MAX_RESTART) of the rotated Hessenberg
 // matrix H (column-major, leading dimension ld) and rotated residual vector g, on the device
 void back_solve_dev(const double* H, int ld, const double* g, int k, double* y, hipStream_t st);
 // g = (g0, 0, ..., 0) with n entries and flags[0..nflags) = 0, on the device
 void init_g(double* g, int n, double g0, int* flags, int nflags, hipStream_t st);
 // dst = (*a) src
-void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hipStream_t st);
+template <typename TV>
+void vec_scale_dev(TV* dst, const TV* src, const double* a, size_t n, hipStream_t st);
 // out[v] = sum_b partial[v * nblk + b] for v < nout, in a fixed order
 void reduce_partials(const double* partial, int nblk, double* out, int nout, hipStream_t st);
 // One Arnoldi column on the device (see k_arnoldi in krylov.hip).
@@ -54,8 +59,11 @@ void arnoldi_run(const ArnoldiArgs& t, hipStream_t s);
 // sums of the new norm, then runs stage 1 and rescales w when the device finds its norm off (see
 // arnoldi_dev.h).
 // x += sum_v y[v] Z_v (y on the device)
-void krylov_combine(double* x, const double* Z, size_t ld, int nvec, const double* y, size_t n, hipStream_t st);
-void vec_scale(double* dst, const double* src, double a, size_t n, hipStream_t st);
+template <typename TV>
+void krylov_combine(double* x, const TV* Z, size_t ld, int nvec, const double* y, size_t n, hipStream_t st);
+// dst = a src (src FP64, dst rounded to TD)
+template <typename TD>
+void vec_scale(TD* dst, const double* src, double a, size_t n, hipStream_t st);
 void vec_fill(double* dst, double a, size_t n, hipStream_t st);
 void modes_to_channels(const void* x, double* ch, int L, size_t N, bool one_part, hipStream_t st);
 void channels_to_modes(const double* ch, void* y, int L, size_t N, bool one_part, hipStream_t st);

@@ -1,6 +1,7 @@
-// FP64 vector kernels of the (flexible) GMRES iteration: multi-vector dot products against the
-// Krylov basis, the classical Gram-Schmidt update with its norm, linear combinations, and the
-// packing between complex mode vectors and real channel vectors.
+// Vector kernels of the (flexible) GMRES iteration: multi-vector dot products against the Krylov
+// basis, the classical Gram-Schmidt update with its norm, linear combinations, and the packing
+// between complex mode vectors and real channel vectors.  Basis vectors are stored as TV (double,
+// or float for the inner solve of the FP32 apply); every sum and product is taken in FP64.
 //
 // Reductions are deterministic: a fixed grid of blocks writes one partial per (vector, block) and
 // a second kernel adds the partials in a fixed order, so repeated runs give bitwise equal sums.
@@ -39,9 +40,9 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // is given.  The vector count is a template parameter so that every load of a step is issued before
 // the first multiply.  With even n and ld (and 16-byte aligned V and w) each thread reads element
 // pairs as 16-byte loads.  The slice a block covers and the order of its sums do not depend on the data.
-template <int NV, bool PAIRS>
-__global__ __launch_bounds__(KT) void k_dot_partial(const double* __restrict__ V, size_t ld,
-                                                    const double* __restrict__ w, size_t n,
+template <int NV, bool PAIRS, typename TV>
+__global__ __launch_bounds__(KT) void k_dot_partial(const TV* __restrict__ V, size_t ld,
+                                                    const TV* __restrict__ w, size_t n,
                                                     double* __restrict__ partial,
                                                     double* __restrict__ norm_partial,
                                                     const int* __restrict__ active) {
@@ -55,24 +56,26 @@ __global__ __launch_bounds__(KT) void k_dot_partial(const double* __restrict__ V
     double nrm = 0.0;
     const size_t stride = (size_t)nblk * KT;
     if constexpr (PAIRS) {
+        using P2 = typename pair_of<TV>::type;
         const size_t np = n / 2, ldp = ld / 2;
-        const double2* w2 = reinterpret_cast<const double2*>(w);
-        const double2* V2 = reinterpret_cast<const double2*>(V);
+        const P2* w2 = reinterpret_cast<const P2*>(w);
+        const P2* V2 = reinterpret_cast<const P2*>(V);
         for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < np; i += stride) {
-            const double2 wa = w2[i];
-            double2 a[NV > 0 ? NV : 1];
+            const P2 wl = w2[i];
+            P2 al[NV > 0 ? NV : 1];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) a[v] = V2[(size_t)v * ldp + i];
-            if (do_norm) nrm += wa.x * wa.x + wa.y * wa.y;
+            for (int v = 0; v < NV; ++v) al[v] = V2[(size_t)v * ldp + i];
+            const double wx = (double)wl.x, wy = (double)wl.y;
+            if (do_norm) nrm += wx * wx + wy * wy;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) acc[v] += a[v].x * wa.x + a[v].y * wa.y;
+            for (int v = 0; v < NV; ++v) acc[v] += (double)al[v].x * wx + (double)al[v].y * wy;
         }
     } else {
         for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) {
-            const double wi = w[i];
+            const double wi = (double)w[i];
             double a[NV > 0 ? NV : 1];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) a[v] = V[(size_t)v * ld + i];
+            for (int v = 0; v < NV; ++v) a[v] = (double)V[(size_t)v * ld + i];
             if (do_norm) nrm += wi * wi;
 #pragma unroll
             for (int v = 0; v < NV; ++v) acc[v] += a[v] * wi;
@@ -89,13 +92,13 @@ __global__ __launch_bounds__(KT) void k_dot_partial(const double* __restrict__ V
     }
 }
 
-template <bool PAIRS>
-static void launch_dots(int nv, unsigned nblk, hipStream_t st, const double* V, size_t ld, const double* w, size_t n,
+template <bool PAIRS, typename TV>
+static void launch_dots(int nv, unsigned nblk, hipStream_t st, const TV* V, size_t ld, const TV* w, size_t n,
                         double* partial, double* norm_partial, const int* active) {
     switch (nv) {
 #define RTE_DOTS_CASE(K)                                                                                     \
     case K:                                                                                                  \
-        hipLaunchKernelGGL((k_dot_partial<K, PAIRS>), dim3(nblk), dim3(KT), 0, st, V, ld, w, n, partial,     \
+        hipLaunchKernelGGL((k_dot_partial<K, PAIRS, TV>), dim3(nblk), dim3(KT), 0, st, V, ld, w, n, partial,     \
                            norm_partial, active);                                                            \
         break;
         RTE_DOTS_CASE(0) RTE_DOTS_CASE(1) RTE_DOTS_CASE(2) RTE_DOTS_CASE(3) RTE_DOTS_CASE(4) RTE_DOTS_CASE(5)
@@ -124,12 +127,13 @@ __global__ __launch_bounds__(KT) void k_reduce_partials(const double* __restrict
     if (threadIdx.x == 0) out[v] = s;
 }
 
-// w[i] = a (w[i] - sum_v V[v][i] h[v]); partial_norm[blk] = sum over the slice of the new w[i]^2.
+// w[i] = a (w[i] - sum_v V[v][i] h[v]) (FP64 arithmetic, stored as TV); partial_norm[blk] = sum over
+// the slice of the stored new w[i]^2.
 // a = 1, or with s0.st set (the fused single pass, h = s0.st) the normalising factor computed here
 // (arnoldi_stage0_in_update), block 0 also doing stage 0 of the Arnoldi column.  PAIRS: as in
 // k_dot_partial, element pairs as 16-byte loads.
-template <bool PAIRS>
-__global__ __launch_bounds__(KT) void k_cgs_update(double* __restrict__ w, const double* __restrict__ V, size_t ld,
+template <bool PAIRS, typename TV>
+__global__ __launch_bounds__(KT) void k_cgs_update(TV* __restrict__ w, const TV* __restrict__ V, size_t ld,
                                                    int nvec, const double* __restrict__ h, size_t n,
                                                    double* __restrict__ partial_norm, const int* __restrict__ active,
                                                    ArnoldiArgs s0) {
@@ -149,31 +153,34 @@ __global__ __launch_bounds__(KT) void k_cgs_update(double* __restrict__ w, const
     double nrm = 0.0;
     const size_t stride = (size_t)gridDim.x * KT;
     if constexpr (PAIRS) {
+        using P2 = typename pair_of<TV>::type;
         const size_t np = n / 2, ldp = ld / 2;
-        double2* w2 = reinterpret_cast<double2*>(w);
-        const double2* V2 = reinterpret_cast<const double2*>(V);
+        P2* w2 = reinterpret_cast<P2*>(w);
+        const P2* V2 = reinterpret_cast<const P2*>(V);
         for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < np; i += stride) {
-            double2 s = w2[i];
+            const P2 wl = w2[i];
+            double sx = (double)wl.x, sy = (double)wl.y;
 #pragma unroll 8
             for (int v = 0; v < nvec; ++v) {
-                const double2 b = V2[(size_t)v * ldp + i];
-                s.x -= b.x * hs[v];
-                s.y -= b.y * hs[v];
+                const P2 b = V2[(size_t)v * ldp + i];
+                sx -= (double)b.x * hs[v];
+                sy -= (double)b.y * hs[v];
             }
-            s.x *= a;
-            s.y *= a;
-            w2[i] = s;
-            nrm += s.x * s.x + s.y * s.y;
+            P2 q;
+            q.x = (TV)(sx * a);
+            q.y = (TV)(sy * a);
+            w2[i] = q;
+            nrm += (double)q.x * (double)q.x + (double)q.y * (double)q.y;
         }
     } else {
         for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) {
-            double s = w[i];
+            double s = (double)w[i];
             // unrolled so that eight basis loads are in flight; subtraction order unchanged
 #pragma unroll 8
-            for (int v = 0; v < nvec; ++v) s -= V[(size_t)v * ld + i] * hs[v];
-            s *= a;
-            w[i] = s;
-            nrm += s * s;
+            for (int v = 0; v < nvec; ++v) s -= (double)V[(size_t)v * ld + i] * hs[v];
+            const TV q = (TV)(s * a);
+            w[i] = q;
+            nrm += (double)q * (double)q;
         }
     }
     const double t = block_sum(nrm, sh);
@@ -181,7 +188,8 @@ __global__ __launch_bounds__(KT) void k_cgs_update(double* __restrict__ w, const
 }
 
 // x[i] += sum_v Z[v][i] y[v]
-__global__ __launch_bounds__(KT) void k_combine(double* __restrict__ x, const double* __restrict__ Z, size_t ld,
+template <typename TV>
+__global__ __launch_bounds__(KT) void k_combine(double* __restrict__ x, const TV* __restrict__ Z, size_t ld,
                                                 int nvec, const double* __restrict__ y, size_t n) {
     __shared__ double ys[RTE_KRYLOV_MAXVEC];
     for (int v = threadIdx.x; v < nvec; v += KT) ys[v] = y[v];
@@ -190,7 +198,7 @@ __global__ __launch_bounds__(KT) void k_combine(double* __restrict__ x, const do
     for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) {
         double s = x[i];
 #pragma unroll 8
-        for (int v = 0; v < nvec; ++v) s += Z[(size_t)v * ld + i] * ys[v];
+        for (int v = 0; v < nvec; ++v) s += (double)Z[(size_t)v * ld + i] * ys[v];
         x[i] = s;
     }
 }
@@ -198,20 +206,22 @@ __global__ __launch_bounds__(KT) void k_combine(double* __restrict__ x, const do
 // Stage 1 of the fused single pass (block 0: the Arnoldi column's bookkeeping; every block adds
 // up the update's partial sums of nu2 itself) and, when the stored vector needs it,
 // w *= 1/sqrt(nu2) over the grid.
-__global__ __launch_bounds__(KT) void k_rescale_arn1(ArnoldiArgs t, double* __restrict__ w, size_t n,
+template <typename TV>
+__global__ __launch_bounds__(KT) void k_rescale_arn1(ArnoldiArgs t, TV* __restrict__ w, size_t n,
                                                     const double* __restrict__ partial, int nblk) {
     const double inv = arnoldi_stage1_in_rescale(t, partial, nblk);
     if (inv < 0.0) return;
     const size_t stride = (size_t)gridDim.x * KT;
-    for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) w[i] *= inv;
+    for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) w[i] = (TV)((double)w[i] * inv);
 }
 
 // dst[i] = (*a) * src[i] with the factor read from device memory
-__global__ __launch_bounds__(KT) void k_scale_dev(double* __restrict__ dst, const double* __restrict__ src,
+template <typename TV>
+__global__ __launch_bounds__(KT) void k_scale_dev(TV* __restrict__ dst, const TV* __restrict__ src,
                                                   const double* __restrict__ a, size_t n) {
     const double s = *a;
     const size_t stride = (size_t)gridDim.x * KT;
-    for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) dst[i] = s * src[i];
+    for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) dst[i] = (TV)(s * (double)src[i]);
 }
 
 constexpr int ARN_THREADS = 256;
@@ -258,10 +268,11 @@ __global__ void k_init_g(double* __restrict__ g, int n, double g0, int* __restri
 }
 
 // dst[i] = a * src[i]
-__global__ __launch_bounds__(KT) void k_scale(double* __restrict__ dst, const double* __restrict__ src, double a,
+template <typename TD>
+__global__ __launch_bounds__(KT) void k_scale(TD* __restrict__ dst, const double* __restrict__ src, double a,
                                               size_t n) {
     const size_t stride = (size_t)gridDim.x * KT;
-    for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) dst[i] = a * src[i];
+    for (size_t i = (size_t)blockIdx.x * KT + threadIdx.x; i < n; i += stride) dst[i] = (TD)(a * src[i]);
 }
 
 __global__ __launch_bounds__(KT) void k_fill(double* __restrict__ dst, double a, size_t n) {
@@ -331,7 +342,8 @@ static inline unsigned grid_for(size_t n, unsigned cap) {
 
 unsigned krylov_nblk(size_t n) { return grid_for(n, RTE_KRYLOV_NBLK); }
 
-void krylov_dots(const double* V, size_t ld, int nvec, const double* w, size_t n, double* partial,
+template <typename TV>
+void krylov_dots(const TV* V, size_t ld, int nvec, const TV* w, size_t n, double* partial,
                  double* out, bool with_norm, hipStream_t st, const int* active) {
     const unsigned nblk = grid_for(n, RTE_KRYLOV_NBLK);
     const bool pairs = n % 2 == 0 && ld % 2 == 0 && ((uintptr_t)V % 16) == 0 && ((uintptr_t)w % 16) == 0;
@@ -347,23 +359,25 @@ void krylov_dots(const double* V, size_t ld, int nvec, const double* w, size_t n
         hipLaunchKernelGGL(k_reduce_partials, dim3(nout), dim3(KT), 0, st, partial, (int)nblk, out, active);
 }
 
-void krylov_update(double* w, const double* V, size_t ld, int nvec, const double* h, size_t n, double* partial,
+template <typename TV>
+void krylov_update(TV* w, const TV* V, size_t ld, int nvec, const double* h, size_t n, double* partial,
                    double* norm_out, hipStream_t st, const int* active, const ArnoldiArgs* stage0) {
     const ArnoldiArgs none;
     const ArnoldiArgs& s0 = stage0 ? *stage0 : none;
     const unsigned nblk = grid_for(n, RTE_KRYLOV_NBLK);
     const bool pairs = n % 2 == 0 && ld % 2 == 0 && ((uintptr_t)V % 16) == 0 && ((uintptr_t)w % 16) == 0;
     if (pairs)
-        hipLaunchKernelGGL(k_cgs_update<true>, dim3(nblk), dim3(KT), 0, st, w, V, ld, nvec, h, n, partial, active,
+        hipLaunchKernelGGL((k_cgs_update<true, TV>), dim3(nblk), dim3(KT), 0, st, w, V, ld, nvec, h, n, partial, active,
                            s0);
     else
-        hipLaunchKernelGGL(k_cgs_update<false>, dim3(nblk), dim3(KT), 0, st, w, V, ld, nvec, h, n, partial, active,
+        hipLaunchKernelGGL((k_cgs_update<false, TV>), dim3(nblk), dim3(KT), 0, st, w, V, ld, nvec, h, n, partial, active,
                            s0);
     if (norm_out) hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(KT), 0, st, partial, (int)nblk, norm_out, active);
 }
 
-void vec_scale_dev(double* dst, const double* src, const double* a, size_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_scale_dev, dim3(grid_for(n, 4096)), dim3(KT), 0, st, dst, src, a, n);
+template <typename TV>
+void vec_scale_dev(TV* dst, const TV* src, const double* a, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_dev<TV>, dim3(grid_for(n, 4096)), dim3(KT), 0, st, dst, src, a, n);
 }
 
 void back_solve_dev(const double* H, int ld, const double* g, int k, double* y, hipStream_t st) {
@@ -375,9 +389,10 @@ void init_g(double* g, int n, double g0, int* flags, int nflags, hipStream_t st)
     hipLaunchKernelGGL(k_init_g, dim3(1), dim3(256), 0, st, g, n, g0, flags, nflags);
 }
 
-void rescale_arn1(const ArnoldiArgs& t, double* w, size_t n, const double* partial, int nblk, hipStream_t st) {
+template <typename TV>
+void rescale_arn1(const ArnoldiArgs& t, TV* w, size_t n, const double* partial, int nblk, hipStream_t st) {
     // usually nothing to rescale, so a small grid
-    hipLaunchKernelGGL(k_rescale_arn1, dim3(grid_for(n, 512)), dim3(KT), 0, st, t, w, n, partial, nblk);
+    hipLaunchKernelGGL(k_rescale_arn1<TV>, dim3(grid_for(n, 512)), dim3(KT), 0, st, t, w, n, partial, nblk);
 }
 
 void reduce_partials(const double* partial, int nblk, double* out, int nout, hipStream_t st) {
@@ -388,12 +403,14 @@ void arnoldi_run(const ArnoldiArgs& t, hipStream_t s) {
     hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(ARN_THREADS), 0, s, t);
 }
 
-void krylov_combine(double* x, const double* Z, size_t ld, int nvec, const double* y, size_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_combine, dim3(grid_for(n, 4096)), dim3(KT), 0, st, x, Z, ld, nvec, y, n);
+template <typename TV>
+void krylov_combine(double* x, const TV* Z, size_t ld, int nvec, const double* y, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_combine<TV>, dim3(grid_for(n, 4096)), dim3(KT), 0, st, x, Z, ld, nvec, y, n);
 }
 
-void vec_scale(double* dst, const double* src, double a, size_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_scale, dim3(grid_for(n, 4096)), dim3(KT), 0, st, dst, src, a, n);
+template <typename TD>
+void vec_scale(TD* dst, const double* src, double a, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_scale<TD>, dim3(grid_for(n, 4096)), dim3(KT), 0, st, dst, src, a, n);
 }
 
 void vec_fill(double* dst, double a, size_t n, hipStream_t st) {
@@ -413,5 +430,18 @@ void channels_to_modes(const double* ch, void* y, int L, size_t N, bool one_part
 void nonfinite_scan(const double* x, size_t n, int* flag, hipStream_t st) {
     hipLaunchKernelGGL(k_nonfinite, dim3(grid_for(n, 1024)), dim3(KT), 0, st, x, n, flag);
 }
+
+#define RTE_KRYLOV_INST(TV)                                                                                     \
+    template void krylov_dots<TV>(const TV*, size_t, int, const TV*, size_t, double*, double*, bool, hipStream_t, \
+                                  const int*);                                                                  \
+    template void krylov_update<TV>(TV*, const TV*, size_t, int, const double*, size_t, double*, double*,       \
+                                    hipStream_t, const int*, const ArnoldiArgs*);                               \
+    template void vec_scale_dev<TV>(TV*, const TV*, const double*, size_t, hipStream_t);                        \
+    template void rescale_arn1<TV>(const ArnoldiArgs&, TV*, size_t, const double*, int, hipStream_t);          \
+    template void krylov_combine<TV>(double*, const TV*, size_t, int, const double*, size_t, hipStream_t);     \
+    template void vec_scale<TV>(TV*, const double*, double, size_t, hipStream_t);
+RTE_KRYLOV_INST(double)
+RTE_KRYLOV_INST(float)
+#undef RTE_KRYLOV_INST
 
 }  // namespace rte

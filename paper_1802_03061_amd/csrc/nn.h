@@ -12,20 +12,24 @@ void pc_free(rte_ctx* c);
 // coarse network output y_j (slot j), with s = 1 / sqrt(nvec) for the unit-norm v_j.
 size_t pc_coarse_len(const rte_ctx* c);
 int pc_begin_solve(rte_ctx* c, int m);                 // slots for m columns, s in c->pc_st
-// v = a w + pool (a = *a_dev, or a_host when a_dev is NULL)
-void pc_scale_pool(rte_ctx* c, const double* w, double* v, const double* a_dev, double a_host);
+// v = a w + pool (a = *a_dev, or a_host when a_dev is NULL); v (and the basis) stored as TV
+template <typename TW, typename TV>
+void pc_scale_pool(rte_ctx* c, const TW* w, TV* v, const double* a_dev, double a_host);
 // The fused single pass of the preconditioned Arnoldi step: w = a (w - sum_{v < nvec} h[v] V_v)
 // with h = s0.st and the normalising factor a computed on the device (stage 0 of the column in
 // block 0), and the block means of the new w; *norm_out = <w, w> (partial: one double per block,
 // pc_update_pool_blocks(c) of them; with norm_out NULL only those are written)
-void pc_update_pool(rte_ctx* c, double* w, const double* V, int nvec, double* partial, double* norm_out,
+template <typename TV>
+void pc_update_pool(rte_ctx* c, TV* w, const TV* V, int nvec, double* partial, double* norm_out,
                     const ArnoldiArgs& s0);
 // stage 1 of the fused single pass and, when flagged by the device, w's rescale and new block means
-void pc_rescale_pool_arn1(rte_ctx* c, const ArnoldiArgs& t, double* w, const double* partial);
+template <typename TV>
+void pc_rescale_pool_arn1(rte_ctx* c, const ArnoldiArgs& t, TV* w, const double* partial);
 // Stage 1 with the flagged rescale (without new block means) and the network of the block means
 // the update wrote, into output slot `slot`, in one launch; usable when pc_rescale_net_ok(c).
 bool pc_rescale_net_ok(const rte_ctx* c);
-int pc_rescale_net(rte_ctx* c, const ArnoldiArgs& t, double* w, const double* partial, int slot);
+template <typename TV>
+int pc_rescale_net(rte_ctx* c, const ArnoldiArgs& t, TV* w, const double* partial, int slot);
 int pc_update_pool_blocks(const rte_ctx* c);
 int pc_net_slot(rte_ctx* c, int j);                    // Y_j = N(pooled v_j / s)
 const float* pc_slot(const rte_ctx* c, int j);

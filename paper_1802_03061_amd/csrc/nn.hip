@@ -546,7 +546,8 @@ __device__ __forceinline__ void pool_block_cells(const double* part, int CW, int
 // v = a w (in place allowed) and the F x F block means of v into coarse[c][I][J] (FP32).  Work
 // unit: (channel, coarse row I, chunk of CW = max(F, 64) columns), so that a unit owns its coarse
 // cells; 256 threads = CW columns x (256 / CW) row groups.  The grid strides over the units.
-__device__ __forceinline__ void scale_pool_units(const double* __restrict__ w, double* __restrict__ v, double a,
+template <typename TW, typename TV>
+__device__ __forceinline__ void scale_pool_units(const TW* __restrict__ w, TV* __restrict__ v, double a,
                                                  float* __restrict__ coarse, int C, int ny, int nx, int F) {
     __shared__ double part[256];
     const int CW = F > 64 ? F : 64;
@@ -568,9 +569,9 @@ __device__ __forceinline__ void scale_pool_units(const double* __restrict__ w, d
                 const int r = rg * rows + u;
                 if (r < F) {
                     const size_t o = ((size_t)c * ny + I * F + r) * nx + x;
-                    const double val = a * w[o];
+                    const TV val = (TV)(a * (double)w[o]);   // the block means are of the stored values
                     v[o] = val;
-                    s += val;
+                    s += (double)val;
                 }
             }
         }
@@ -582,7 +583,8 @@ __device__ __forceinline__ void scale_pool_units(const double* __restrict__ w, d
 }
 
 // v = a w and its block means (scale_pool_units), a = *a_dev or a_host when a_dev is NULL.
-__global__ __launch_bounds__(256) void k_scale_pool(const double* __restrict__ w, double* __restrict__ v,
+template <typename TW, typename TV>
+__global__ __launch_bounds__(256) void k_scale_pool(const TW* __restrict__ w, TV* __restrict__ v,
                                                     const double* __restrict__ a_dev, double a_host,
                                                     float* __restrict__ coarse, int C, int ny, int nx, int F) {
     scale_pool_units(w, v, a_dev ? *a_dev : a_host, coarse, C, ny, nx, F);
@@ -590,7 +592,8 @@ __global__ __launch_bounds__(256) void k_scale_pool(const double* __restrict__ w
 
 // Stage 1 of the fused single pass (block 0: the Arnoldi column's bookkeeping) and, when the
 // stored vector needs it, its rescale with the block means taken again.
-__global__ __launch_bounds__(256) void k_rescale_pool_arn1(ArnoldiArgs t, double* __restrict__ w,
+template <typename TV>
+__global__ __launch_bounds__(256) void k_rescale_pool_arn1(ArnoldiArgs t, TV* __restrict__ w,
                                                            float* __restrict__ coarse, int C, int ny, int nx, int F,
                                                            const double* __restrict__ partial, int nblk) {
     const double inv = arnoldi_stage1_in_rescale(t, partial, nblk);
@@ -604,8 +607,8 @@ __global__ __launch_bounds__(256) void k_rescale_pool_arn1(ArnoldiArgs t, double
 // vector's norm off, in w's rescale.  The rescale does not pool again: block 1 takes the same
 // decision from the same partial sums and puts the rescale factor on the network's input instead
 // (the block means are linear in w), so the network sees the block means of the final vector.
-template <int HID>
-__global__ __launch_bounds__(NET_THREADS) void k_rescale_net(ArnoldiArgs t, double* __restrict__ w, size_t n,
+template <int HID, typename TV>
+__global__ __launch_bounds__(NET_THREADS) void k_rescale_net(ArnoldiArgs t, TV* __restrict__ w, size_t n,
                                                              const double* __restrict__ partial, int nblk,
                                                              const float* __restrict__ in,
                                                              const float* __restrict__ in_scale,
@@ -622,7 +625,7 @@ __global__ __launch_bounds__(NET_THREADS) void k_rescale_net(ArnoldiArgs t, doub
     if (inv < 0.0) return;
     const size_t wb = blockIdx.x == 0 ? 0 : blockIdx.x - 1, nwb = gridDim.x - 1;
     const size_t stride = nwb * NET_THREADS;
-    for (size_t i = wb * NET_THREADS + threadIdx.x; i < n; i += stride) w[i] *= inv;
+    for (size_t i = wb * NET_THREADS + threadIdx.x; i < n; i += stride) w[i] = (TV)((double)w[i] * inv);
 }
 
 // The single Gram-Schmidt pass of the preconditioned Arnoldi step with its normalisation and the
@@ -633,8 +636,8 @@ __global__ __launch_bounds__(NET_THREADS) void k_rescale_net(ArnoldiArgs t, doub
 // with ny, nx multiples of F belongs to exactly one block).  PAIRS (even nx and ld, 16-byte
 // aligned w and V): each thread takes two adjacent columns as 16-byte loads, so a row group is
 // CW / 2 threads and the block covers twice the rows per step.
-template <bool PAIRS>
-__global__ __launch_bounds__(256) void k_update_pool(double* __restrict__ w, const double* __restrict__ V, size_t ld,
+template <bool PAIRS, typename TV>
+__global__ __launch_bounds__(256) void k_update_pool(TV* __restrict__ w, const TV* __restrict__ V, size_t ld,
                                                      int nvec, float* __restrict__ coarse,
                                                      double* __restrict__ partial_norm, int ny, int nx, int F,
                                                      ArnoldiArgs st0) {
@@ -664,37 +667,42 @@ __global__ __launch_bounds__(256) void k_update_pool(double* __restrict__ w, con
     if (x < nx) {
         const size_t o0 = ((size_t)c * ny + I * F + rg * rows) * nx + x;
         if constexpr (PAIRS) {
-            double2* w2 = reinterpret_cast<double2*>(w);
-            const double2* V2 = reinterpret_cast<const double2*>(V);
+            using P2 = typename pair_of<TV>::type;
+            P2* w2 = reinterpret_cast<P2*>(w);
+            const P2* V2 = reinterpret_cast<const P2*>(V);
             const size_t ldp = ld / 2;
 #pragma unroll 2
             for (int u = 0; u < nr; ++u) {
                 const size_t op = (o0 + (size_t)u * nx) / 2;
-                double2 t = w2[op];
+                const P2 wl = w2[op];
+                double tx = (double)wl.x, ty = (double)wl.y;
 #pragma unroll 8
                 for (int v = 0; v < nvec; ++v) {
-                    const double2 b = V2[(size_t)v * ldp + op];
-                    t.x -= b.x * hs[v];
-                    t.y -= b.y * hs[v];
+                    const P2 b = V2[(size_t)v * ldp + op];
+                    tx -= (double)b.x * hs[v];
+                    ty -= (double)b.y * hs[v];
                 }
-                t.x *= a;
-                t.y *= a;
+                P2 t;
+                t.x = (TV)(tx * a);
+                t.y = (TV)(ty * a);
                 w2[op] = t;
-                s0 += t.x;
-                s1 += t.y;
-                q += t.x * t.x + t.y * t.y;
+                const double ux = (double)t.x, uy = (double)t.y;   // sums of the stored values
+                s0 += ux;
+                s1 += uy;
+                q += ux * ux + uy * uy;
             }
         } else {
 #pragma unroll 2
             for (int u = 0; u < nr; ++u) {
                 const size_t o = o0 + (size_t)u * nx;
-                double t = w[o];
+                double t = (double)w[o];
 #pragma unroll 8
-                for (int v = 0; v < nvec; ++v) t -= V[(size_t)v * ld + o] * hs[v];
-                t *= a;
-                w[o] = t;
-                s0 += t;
-                q += t * t;
+                for (int v = 0; v < nvec; ++v) t -= (double)V[(size_t)v * ld + o] * hs[v];
+                const TV tq = (TV)(t * a);
+                w[o] = tq;
+                const double u2 = (double)tq;
+                s0 += u2;
+                q += u2 * u2;
             }
         }
     }
@@ -946,21 +954,23 @@ int pc_begin_solve(rte_ctx* c, int m) {
     return e == hipSuccess ? RTE_OK : set_hip_error(e, "pc_begin_solve", __FILE__, __LINE__);
 }
 
-void pc_scale_pool(rte_ctx* c, const double* w, double* v, const double* a_dev, double a_host) {
+template <typename TW, typename TV>
+void pc_scale_pool(rte_ctx* c, const TW* w, TV* v, const double* a_dev, double a_host) {
     const int F = c->pc_factor;
     const int CW = F > 64 ? F : 64;
     const int nchunk = (c->nx + CW - 1) / CW;
     const int nunit = c->C * (c->ny / F) * nchunk;
-    hipLaunchKernelGGL(k_scale_pool, dim3(nunit), dim3(256), 0, c->stream, w, v, a_dev, a_host, c->pc_coarse, c->C,
-                       c->ny, c->nx, F);
+    hipLaunchKernelGGL((k_scale_pool<TW, TV>), dim3(nunit), dim3(256), 0, c->stream, w, v, a_dev, a_host,
+                       c->pc_coarse, c->C, c->ny, c->nx, F);
 }
 
-void pc_rescale_pool_arn1(rte_ctx* c, const ArnoldiArgs& t, double* w, const double* partial) {
+template <typename TV>
+void pc_rescale_pool_arn1(rte_ctx* c, const ArnoldiArgs& t, TV* w, const double* partial) {
     const int F = c->pc_factor;
     const int CW = F > 64 ? F : 64;
     const int nunit = c->C * (c->ny / F) * ((c->nx + CW - 1) / CW);
     // usually nothing to rescale, so a small grid
-    hipLaunchKernelGGL(k_rescale_pool_arn1, dim3(std::min(nunit, 512)), dim3(256), 0, c->stream, t, w, c->pc_coarse,
+    hipLaunchKernelGGL(k_rescale_pool_arn1<TV>, dim3(std::min(nunit, 512)), dim3(256), 0, c->stream, t, w, c->pc_coarse,
                        c->C, c->ny, c->nx, F, partial, pc_update_pool_blocks(c));
 }
 
@@ -970,15 +980,16 @@ int pc_update_pool_blocks(const rte_ctx* c) {
     return c->C * (c->ny / F) * ((c->nx + CW - 1) / CW);
 }
 
-void pc_update_pool(rte_ctx* c, double* w, const double* V, int nvec, double* partial, double* norm_out,
+template <typename TV>
+void pc_update_pool(rte_ctx* c, TV* w, const TV* V, int nvec, double* partial, double* norm_out,
                     const ArnoldiArgs& s0) {
     const int nblk = pc_update_pool_blocks(c);
     const bool pairs = c->nx % 2 == 0 && c->nvec % 2 == 0 && ((uintptr_t)w % 16) == 0 && ((uintptr_t)V % 16) == 0;
     if (pairs)
-        hipLaunchKernelGGL(k_update_pool<true>, dim3(nblk), dim3(256), 0, c->stream, w, V, c->nvec, nvec,
+        hipLaunchKernelGGL((k_update_pool<true, TV>), dim3(nblk), dim3(256), 0, c->stream, w, V, c->nvec, nvec,
                            c->pc_coarse, partial, c->ny, c->nx, c->pc_factor, s0);
     else
-        hipLaunchKernelGGL(k_update_pool<false>, dim3(nblk), dim3(256), 0, c->stream, w, V, c->nvec, nvec,
+        hipLaunchKernelGGL((k_update_pool<false, TV>), dim3(nblk), dim3(256), 0, c->stream, w, V, c->nvec, nvec,
                            c->pc_coarse, partial, c->ny, c->nx, c->pc_factor, s0);
     if (norm_out) reduce_partials(partial, nblk, norm_out, 1, c->stream);
 }
@@ -997,7 +1008,8 @@ bool pc_rescale_net_ok(const rte_ctx* c) {
     return fused_net_lds(sh, c->ny / F, c->nx / F) + RESCALE_NET_STATIC_LDS <= 160 * 1024;
 }
 
-int pc_rescale_net(rte_ctx* c, const ArnoldiArgs& t, double* w, const double* partial, int slot) {
+template <typename TV>
+int pc_rescale_net(rte_ctx* c, const ArnoldiArgs& t, TV* w, const double* partial, int slot) {
     NetShape sh;
     sh.init(c->C, c->pc_hidden, c->pc_layers);
     const int F = c->pc_factor;
@@ -1010,16 +1022,26 @@ int pc_rescale_net(rte_ctx* c, const ArnoldiArgs& t, double* w, const double* pa
     const unsigned grid = 2 + (unsigned)std::min<size_t>(want, 254);
     const int nblk = pc_update_pool_blocks(c);
     if (c->pc_hidden == 32)
-        hipLaunchKernelGGL((k_rescale_net<32>), dim3(grid), dim3(NET_THREADS), lds, c->stream, t, w, c->nvec, partial,
+        hipLaunchKernelGGL((k_rescale_net<32, TV>), dim3(grid), dim3(NET_THREADS), lds, c->stream, t, w, c->nvec, partial,
                            nblk, c->pc_coarse, c->pc_st + 1, c->pc_wn, nwn, c->pc_bn, c->pc_nbias, c->pc_meta,
                            sh.layers, c->C, Hc, Wc, out);
     else
-        hipLaunchKernelGGL((k_rescale_net<16>), dim3(grid), dim3(NET_THREADS), lds, c->stream, t, w, c->nvec, partial,
+        hipLaunchKernelGGL((k_rescale_net<16, TV>), dim3(grid), dim3(NET_THREADS), lds, c->stream, t, w, c->nvec, partial,
                            nblk, c->pc_coarse, c->pc_st + 1, c->pc_wn, nwn, c->pc_bn, c->pc_nbias, c->pc_meta,
                            sh.layers, c->C, Hc, Wc, out);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? RTE_OK : set_hip_error(e, "pc_rescale_net", __FILE__, __LINE__);
 }
+
+#define RTE_PC_INST(TV)                                                                                           \
+    template void pc_scale_pool<double, TV>(rte_ctx*, const double*, TV*, const double*, double);                 \
+    template void pc_rescale_pool_arn1<TV>(rte_ctx*, const ArnoldiArgs&, TV*, const double*);                    \
+    template void pc_update_pool<TV>(rte_ctx*, TV*, const TV*, int, double*, double*, const ArnoldiArgs&);       \
+    template int pc_rescale_net<TV>(rte_ctx*, const ArnoldiArgs&, TV*, const double*, int);
+RTE_PC_INST(float)
+RTE_PC_INST(double)
+#undef RTE_PC_INST
+template void pc_scale_pool<float, float>(rte_ctx*, const float*, float*, const double*, double);
 
 const float* pc_slot(const rte_ctx* c, int j) { return c->pc_Y + (size_t)j * pc_coarse_len(c); }
 

@@ -87,6 +87,7 @@ static void free_krylov(rte_ctx* c) {
     c->hpipe_flags = nullptr;
     c->krylov_m = 0;
     c->krylov_z = false;
+    c->krylov_vbytes = 0;
 }
 
 static void free_ctx(rte_ctx* c) {
@@ -116,12 +117,12 @@ static void free_ctx(rte_ctx* c) {
     delete c;
 }
 
-int ensure_krylov(rte_ctx* c, int m, bool need_z) {
-    if (c->krylov_m >= m && (!need_z || c->krylov_z)) return RTE_OK;
+int ensure_krylov(rte_ctx* c, int m, bool need_z, size_t vbytes) {
+    if (c->krylov_m >= m && c->krylov_vbytes >= vbytes && (!need_z || c->krylov_z)) return RTE_OK;
     free_krylov(c);
     const size_t n = c->nvec;
     int rc;
-    if ((rc = dalloc(&c->V, (size_t)(m + 1) * n))) return rc;
+    if ((rc = dalloc(&c->V, (size_t)(m + 1) * n * vbytes))) return rc;
     if (need_z && (rc = dalloc(&c->Z, (size_t)m * n))) return rc;
     if ((rc = dalloc(&c->partial, (size_t)(m + 3) * RTE_KRYLOV_NBLK))) return rc;
     if ((rc = dalloc(&c->dsmall, (size_t)(2 * m + 16)))) return rc;
@@ -141,6 +142,7 @@ int ensure_krylov(rte_ctx* c, int m, bool need_z) {
     if (e != hipSuccess) return set_hip_error(e, "hipHostMalloc", __FILE__, __LINE__);
     c->krylov_m = m;
     c->krylov_z = need_z;
+    c->krylov_vbytes = vbytes;
     return RTE_OK;
 }
 
@@ -171,8 +173,8 @@ Apply2DArgs<double> args2d<double>(const rte_ctx* c) {
     return a;
 }
 
-template <typename T>
-static int apply_t(rte_ctx* c, int mode, const double* x, const double* b, double* y, int nbatch, hipEvent_t* ev) {
+template <typename T, typename TV>
+static int apply_t(rte_ctx* c, int mode, const TV* x, const double* b, TV* y, int nbatch, hipEvent_t* ev) {
     const ChanScale sc = channel_scale(c, mode);
     if (c->dim == 2) {
         Apply2DArgs<T> a = args2d<T>(c);
@@ -225,9 +227,18 @@ int apply_channels(rte_ctx* c, int mode, int prec, const double* x, const double
     return apply_t<double>(c, mode, x, b, y, nbatch, nullptr);
 }
 
+// y = A x on basis vectors (stored as TV) in the context precision: float vectors only with the
+// FP32 apply.
+template <typename TV>
+static int apply_basis(rte_ctx* c, const TV* x, TV* y) {
+    if constexpr (sizeof(TV) == sizeof(float)) return apply_t<float>(c, APPLY_A, x, nullptr, y, 1, nullptr);
+    else return c->prec == RTE_PREC_FP32 ? apply_t<float>(c, APPLY_A, x, nullptr, y, 1, nullptr)
+                                         : apply_t<double>(c, APPLY_A, x, nullptr, y, 1, nullptr);
+}
+
 // y = A (v + s P Y) in the context precision, the coarse correction added inside passes A and C.
-template <typename T>
-static int apply_pc_t(rte_ctx* c, const double* v, double* y, const float* Y) {
+template <typename T, typename TV>
+static int apply_pc_t(rte_ctx* c, const TV* v, TV* y, const float* Y) {
     const ChanScale sc = channel_scale(c, APPLY_A);
     Apply2DArgs<T> a = args2d<T>(c);
     a.pack = 1;
@@ -238,8 +249,10 @@ static int apply_pc_t(rte_ctx* c, const double* v, double* y, const float* Y) {
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? RTE_OK : set_hip_error(e, "apply launch", __FILE__, __LINE__);
 }
-int apply_channels_pc(rte_ctx* c, const double* v, double* y, const float* Y) {
-    return c->prec == RTE_PREC_FP32 ? apply_pc_t<float>(c, v, y, Y) : apply_pc_t<double>(c, v, y, Y);
+template <typename TV>
+static int apply_basis_pc(rte_ctx* c, const TV* v, TV* y, const float* Y) {
+    if constexpr (sizeof(TV) == sizeof(float)) return apply_pc_t<float>(c, v, y, Y);
+    else return c->prec == RTE_PREC_FP32 ? apply_pc_t<float>(c, v, y, Y) : apply_pc_t<double>(c, v, y, Y);
 }
 
 // ------------------------------------------------------------------ autotuning -----------------
@@ -343,16 +356,20 @@ static int dot_host(rte_ctx* c, const double* a, const double* b, double* out) {
 
 // ------------------------------------------------------------------ GMRES ---------------------
 
-int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
-               double* rec, int max_rec, int* nrec) {
+// TV: element type of the basis (float with the FP32 apply, double with the FP64 apply); the
+// Hessenberg matrix, rotations, dot products, x and the true residual are FP64 in both.
+template <typename TV>
+static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
+                        double* rec, int max_rec, int* nrec) {
     const double t_start = now_ms();
     hipStream_t st = c->stream;
     const size_t n = c->nvec;
     const int m = c->opts.restart;
     const bool use_pc = c->pc_attached && c->opts.use_pc;
     const bool mixed = c->prec == RTE_PREC_FP32;
-    int rc = ensure_krylov(c, m, false);
+    int rc = ensure_krylov(c, m, false, sizeof(TV));
     if (rc) return rc;
+    TV* const V = basis<TV>(c);
     if (use_pc && (rc = pc_begin_solve(c, m))) return rc;
     if (nrec) *nrec = 0;
     rte_solve_info inf;
@@ -402,8 +419,8 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
         double target = 0.5 * tol * bn;
         if (mixed) target = std::max(target, c->opts.inner_tol * rn);
         // v_0 = r / rn (with the pooled coarse input of the network when preconditioning)
-        if (pc_live) pc_scale_pool(c, c->rv, c->V, nullptr, 1.0 / rn);
-        else vec_scale(c->V, c->rv, 1.0 / rn, n, st);
+        if (pc_live) pc_scale_pool(c, (const double*)c->rv, V, nullptr, 1.0 / rn);
+        else vec_scale(V, c->rv, 1.0 / rn, n, st);
         init_g(dg, m + 1, rn, dfl, 4, st);
         est = rn;
         const double cycle_start_rn = rn;
@@ -414,14 +431,14 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
         bool net_ready = false;   // the network output of the next step is already being computed
         bool stop = false, bad = false;
         for (int j = 0; j < m && it + launched < max_iter && !stop; ++j) {
-            double* vj = c->V + (size_t)j * n;
-            double* w = c->V + (size_t)(j + 1) * n;
+            TV* vj = V + (size_t)j * n;
+            TV* w = V + (size_t)(j + 1) * n;
             // flexible GMRES: w = A z_j with z_j = v_j + s P Y_j formed inside the apply
             if (pc_live) {
                 if (!net_ready && (rc = pc_net_slot(c, j))) return rc;   // else the last launch ran it
                 net_ready = false;
-                if ((rc = apply_channels_pc(c, vj, w, pc_slot(c, j)))) return rc;
-            } else if ((rc = apply_channels(c, APPLY_A, c->prec, vj, nullptr, w, 1))) {
+                if ((rc = apply_basis_pc(c, vj, w, pc_slot(c, j)))) return rc;
+            } else if ((rc = apply_basis(c, vj, w))) {
                 return rc;
             }
             ++inf.applies;
@@ -447,12 +464,12 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
                 // the normalised vector (and, when preconditioning, the network's pooled input),
                 // with stage 0 of the column in its block 0; the rescale kernel runs stage 1 in its
                 // block 0 and rescales only when the device finds the norm off
-                krylov_dots(c->V, n, j + 1, w, n, c->partial, sd, true, st);
+                krylov_dots(V, n, j + 1, w, n, c->partial, sd, true, st);
                 at.stage = 0;
                 // the update leaves its per-block partial sums of the new norm in c->partial; the
                 // rescale kernel adds them up itself
-                if (pc_live) pc_update_pool(c, w, c->V, j + 1, c->partial, nullptr, at);
-                else krylov_update(w, c->V, n, j + 1, sd, n, c->partial, nullptr, st, nullptr, &at);
+                if (pc_live) pc_update_pool(c, w, V, j + 1, c->partial, nullptr, at);
+                else krylov_update(w, V, n, j + 1, sd, n, c->partial, nullptr, st, nullptr, &at);
                 at.stage = 1;
                 at.est_out = c->hpipe_dev + j;
                 at.flags_out = c->hpipe_flags_dev + 2 * j;
@@ -466,13 +483,13 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
                     rescale_arn1(at, w, n, c->partial, (int)krylov_nblk(n), st);
                 }
             } else {
-                krylov_dots(c->V, n, j + 1, w, n, c->partial, sd, true, st);
-                krylov_update(w, c->V, n, j + 1, sd, n, c->partial, sd + j + 2, st);
+                krylov_dots(V, n, j + 1, w, n, c->partial, sd, true, st);
+                krylov_update(w, V, n, j + 1, sd, n, c->partial, sd + j + 2, st);
                 at.stage = 0;
                 arnoldi_run(at, st);
                 if (c->opts.reorth > 0) {   // second pass, skipped on the device unless flagged
-                    krylov_dots(c->V, n, j + 1, w, n, c->partial, sd + m + 4, false, st, dfl);
-                    krylov_update(w, c->V, n, j + 1, sd + m + 4, n, c->partial, sd + j + 2, st, dfl);
+                    krylov_dots(V, n, j + 1, w, n, c->partial, sd + m + 4, false, st, dfl);
+                    krylov_update(w, V, n, j + 1, sd + m + 4, n, c->partial, sd + j + 2, st, dfl);
                 }
                 at.stage = 1;
                 at.est_out = c->hpipe_dev + j;
@@ -526,13 +543,13 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
                     back_solve_dev(dH, m + 1, dg, k, c->dsmall, st);
                     double* xr = rec + (size_t)(k - 1) * n;
                     vec_fill(xr, 0.0, n, st);
-                    krylov_combine(xr, c->V, n, k, c->dsmall, n, st);
+                    krylov_combine(xr, V, n, k, c->dsmall, n, st);
                     if (pc_live) pc_add_correction(c, xr, c->dsmall, k);
                 }
                 if (nrec) *nrec = nr;
             }
             back_solve_dev(dH, m + 1, dg, jd, c->dsmall, st);
-            krylov_combine(x, c->V, n, jd, c->dsmall, n, st);
+            krylov_combine(x, V, n, jd, c->dsmall, n, st);
             if (pc_live) pc_add_correction(c, x, c->dsmall, jd);
         }
         // true residual with the FP64 apply
@@ -565,6 +582,12 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
     if (status == RTE_NOT_CONVERGED)
         set_error(RTE_NOT_CONVERGED, "not converged: relative residual %.3e after %d iterations", rn / bn, it);
     return status;
+}
+
+int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
+               double* rec, int max_rec, int* nrec) {
+    if (c->prec == RTE_PREC_FP32) return solve_core_t<float>(c, b, tol, max_iter, x, info, rec, max_rec, nrec);
+    return solve_core_t<double>(c, b, tol, max_iter, x, info, rec, max_rec, nrec);
 }
 
 }  // namespace rte
@@ -705,7 +728,10 @@ int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const 
         free_ctx(c);
         return rc;
     }
-    if ((rc = ensure_krylov(c, c->opts.restart, false))) { free_ctx(c); return rc; }
+    if ((rc = ensure_krylov(c, c->opts.restart, false, prec == RTE_PREC_FP32 ? sizeof(float) : sizeof(double)))) {
+        free_ctx(c);
+        return rc;
+    }
     // kernel variants: tuned once per shape and process (RTE_AUTOTUNE=0 keeps the defaults)
     const char* at = std::getenv("RTE_AUTOTUNE");
     if (c->dim == 2 && std::max(c->nx, c->ny) >= 128 && !(at && at[0] == '0')) {
