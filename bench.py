@@ -288,7 +288,7 @@ def bench_pc_workload(args, torch, rte, name, mu_s):
     ach = flops_b / (rf["passes"]["B"] * 1e-3) / 1e12
     out = {
         "value": head["solves_per_s"], "unit": "solves/s", "ms_per_step": head["ms_per_solve"],
-        "dtype": "f32 apply + f64 krylov",
+        "dtype": "f32 apply + f32 basis, f64 krylov sums",
         "config": {"workload": (f"2D HG g={'0.5' if name == 'hg512' else '0.3'}, L={L} ({2 * L + 1} modes), "
                                 f"{n}^2 cells, mu_a={base['mu_a']:g}, mu_s={mu_s:g}, seeded Gaussian-mixture "
                                 f"sources, tol 1e-8 (true FP64 residual)"),
@@ -360,7 +360,7 @@ def bench_iso3d(args, torch, rte, mu_s):
     rf = roofline(ctx, rte, pb, args.apply_reps, ["A", "B", "C", "D", "E"])
     out = {
         "value": r["solves_per_s"], "unit": "solves/s", "ms_per_step": r["ms_per_solve"],
-        "dtype": "f32 apply + f64 krylov",
+        "dtype": "f32 apply + f32 basis, f64 krylov sums",
         "config": {"workload": f"3D isotropic {n}^3, mu_a={w['mu_a']:g}, mu_s={mu_s:g}, Gaussian-mixture sources, "
                                f"FP32 FFT on the {padded(n)}^3 padded grid, tol 1e-8", "n": n, "mu_s": mu_s},
         "solve": r, "applies_per_s": 1000.0 / rf["ms_apply"],
