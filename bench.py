@@ -73,8 +73,16 @@ def pmc_summary(fetch_csv: str, write_csv: str, variants) -> dict:
     true_kib = float(2 ** 20)
     ff, fw = true_kib / max(fe[copy]), true_kib / max(wr[copy])
     out = {"fetch_factor": ff, "write_factor": fw, "passes": {}}
-    for label, key in (("A", "k_pass_a<float, 1024,"), ("B", "k_pass_b_lds<float, 1024, 8,"), ("C", "k_pass_c<float, 1024,")):
-        names = [k for k in fe if key in k]
+    # A, B, C: the apply on FP64 channel vectors that the apply timing runs; A_f32, C_f32: the same
+    # passes on the FP32 basis vectors of the solver's inner iterations
+    for label, key, tail in (("A", "k_pass_a<float, 1024,", ", double>"), ("B", "k_pass_b_lds<float, 1024, 8,", ""),
+                             ("C", "k_pass_c<float, 1024,", ", double>"), ("A_f32", "k_pass_a<float, 1024,", ", float>"),
+                             ("C_f32", "k_pass_c<float, 1024,", ", float>")):
+        names = [k for k in fe if key in k and k.split("(")[0].endswith(tail)]
+        if variants and label[0] in "AC":
+            # row tile of the pinned variant (FP32: 16, 8, 32 or 4 rows for variants 0..3)
+            tr = (16, 8, 32, 4)[variants["ABC".index(label[0])][0]]
+            names = [k for k in names if f"<float, 1024, {tr}, 256," in k] or names
         if not names:
             continue
         name = max(names, key=lambda k: len(fe[k]))       # the variant the applies used most
@@ -110,17 +118,18 @@ def padded(n: int) -> int:
     return P
 
 
-def apply_pass_bytes(n: int, L: int) -> dict:
-    """Algorithmic HBM bytes of one FP32 2D apply on FP64 channel vectors (C = 2L+1 channels, n^2
-    cells, padded size P, x-spectrum of P/2 packed columns): pass A reads x (8 B/value) and writes
-    the complex64 x-spectrum; pass B reads and writes that spectrum and reads the quarter kernel
-    spectra [2L+1][P/2+1][P/2+1]; pass C reads the spectrum and x and writes y."""
+def apply_pass_bytes(n: int, L: int, vbytes: int = 8) -> dict:
+    """Algorithmic HBM bytes of one FP32 2D apply on channel vectors of vbytes per value (8: the
+    FP64 vectors of the API; 4: the solver's FP32 basis) (C = 2L+1 channels, n^2 cells, padded size
+    P, x-spectrum of P/2 packed columns): pass A reads x and writes the complex64 x-spectrum; pass
+    B reads and writes that spectrum and reads the quarter kernel spectra [2L+1][P/2+1][P/2+1];
+    pass C reads the spectrum and x and writes y."""
     C = 2 * L + 1
     N = n * n
     H = padded(n) // 2
     spec = 8 * C * H * n
     kern = 8 * (2 * L + 1) * (H + 1) * (H + 1)
-    return {"A": 8 * C * N + spec, "B": 2 * spec + kern, "C": spec + 16 * C * N}
+    return {"A": vbytes * C * N + spec, "B": 2 * spec + kern, "C": spec + 2 * vbytes * C * N}
 
 
 def model_3pass_bytes(n: int, L: int) -> int:

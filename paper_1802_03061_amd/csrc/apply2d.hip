@@ -76,6 +76,23 @@ __device__ __forceinline__ void pass_a_tile(const TV* __restrict__ xin, cx<T>* _
     constexpr int NB0 = PX / R0;
     constexpr int NBT = NP * NB0;
     constexpr int IT = (NBT + NTHR - 1) / NTHR;
+    // Every load of the tile is issued before the first use: the loads take a clamped index (the
+    // channel's first entry when out of range) instead of a branch, and the widening to FP64
+    // follows all of them (a conversion next to each load made the FP32 loads wait one by one).
+    TV la[IT][R0 / 2], lb[IT][R0 / 2];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int idx = tid + it * NTHR;
+        const int p = idx / NB0, j = idx % NB0;
+        const int ya = y0 + 2 * p, yb = ya + 1;
+#pragma unroll
+        for (int r = 0; r < R0 / 2; ++r) {
+            const int m = j + r * NB0;
+            const bool ok = (NBT % NTHR == 0 || idx < NBT) && m < nx;
+            la[it][r] = xin[(ok && ya < ny) ? (size_t)ya * nx + m : 0];
+            lb[it][r] = xin[(ok && yb < ny) ? (size_t)yb * nx + m : 0];
+        }
+    }
     double ra[IT][R0 / 2], rb[IT][R0 / 2];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -86,8 +103,8 @@ __device__ __forceinline__ void pass_a_tile(const TV* __restrict__ xin, cx<T>* _
         for (int r = 0; r < R0 / 2; ++r) {
             const int m = j + r * NB0;
             const bool ok = (NBT % NTHR == 0 || idx < NBT) && m < nx;
-            ra[it][r] = (ok && ya < ny) ? (double)xin[(size_t)ya * nx + m] : 0.0;
-            rb[it][r] = (ok && yb < ny) ? (double)xin[(size_t)yb * nx + m] : 0.0;
+            ra[it][r] = (ok && ya < ny) ? (double)la[it][r] : 0.0;
+            rb[it][r] = (ok && yb < ny) ? (double)lb[it][r] : 0.0;
         }
     }
     if (corr_c) {
@@ -233,12 +250,22 @@ __device__ __forceinline__ void pass_c_tile(const cx<T>* __restrict__ src, const
         const int p = idx / NSL, j = idx % NSL;
         const int ya = y0 + 2 * p, yb = ya + 1;
         double xa_[RL / 2], xb_[RL / 2], ba_[RL / 2], bb_[RL / 2];
+        // x loads with a clamped index (no branch), all issued before the widening (as in pass A)
+        TV la[RL / 2], lb[RL / 2];
+        if (mode != APPLY_KT) {
+#pragma unroll
+            for (int r = 0; r < RL / 2; ++r) {
+                const int m = j + r * NSL;
+                la[r] = xin[(m < nx && ya < ny) ? (size_t)ya * nx + m : 0];
+                lb[r] = xin[(m < nx && yb < ny) ? (size_t)yb * nx + m : 0];
+            }
+        }
 #pragma unroll
         for (int r = 0; r < RL / 2; ++r) {
             const int m = j + r * NSL;
             const bool oka = m < nx && ya < ny, okb = m < nx && yb < ny;
-            xa_[r] = (oka && mode != APPLY_KT) ? (double)xin[(size_t)ya * nx + m] : 0.0;
-            xb_[r] = (okb && mode != APPLY_KT) ? (double)xin[(size_t)yb * nx + m] : 0.0;
+            xa_[r] = (oka && mode != APPLY_KT) ? (double)la[r] : 0.0;
+            xb_[r] = (okb && mode != APPLY_KT) ? (double)lb[r] : 0.0;
             ba_[r] = (oka && mode == APPLY_RESID) ? bin[(size_t)ya * nx + m] : 0.0;
             bb_[r] = (okb && mode == APPLY_RESID) ? bin[(size_t)yb * nx + m] : 0.0;
             if (corr_c && oka) xa_[r] += cs * (double)coarse_bilerp(corr_c, Hc, Wc, cF, ya, m);
