@@ -274,6 +274,12 @@ def bench_pc_workload(args, torch, rte, name, mu_s):
         ctx.attach_pc(net.params(), hidden=meta["hidden"], layers=meta["layers"], factor=F)
         pc = timed_solves(ctx, fs, args.steps, args.warmup, torch)
         pc["label"] = "learned-PC FGMRES"
+        # the same solves with the inner basis stored in FP32 (FP64 sums; an option, not the default)
+        ctx.set_opts(basis_fp32=1)
+        pc32 = timed_solves(ctx, fs, args.steps, args.warmup, torch)
+        ctx.set_opts()
+        pc["basis_fp32_option"] = {k: pc32[k] for k in ("ms_per_solve", "solves_per_s", "iterations",
+                                                          "max_relres_true")}
         pc["training"] = {k: meta[k] for k in ("pairs", "factor", "hidden", "layers", "steps", "t_data_s",
                                                 "t_train_s", "noise_ratio", "multiscale_ratio", "use_bias")}
         pc["training"]["final_loss"] = meta["loss_history"][-1][1] if meta["loss_history"] else None
@@ -297,7 +303,7 @@ def bench_pc_workload(args, torch, rte, name, mu_s):
     ach = flops_b / (rf["passes"]["B"] * 1e-3) / 1e12
     out = {
         "value": head["solves_per_s"], "unit": "solves/s", "ms_per_step": head["ms_per_solve"],
-        "dtype": "f32 apply + f32 basis, f64 krylov sums",
+        "dtype": "f32 apply + f64 krylov",
         "config": {"workload": (f"2D HG g={'0.5' if name == 'hg512' else '0.3'}, L={L} ({2 * L + 1} modes), "
                                 f"{n}^2 cells, mu_a={base['mu_a']:g}, mu_s={mu_s:g}, seeded Gaussian-mixture "
                                 f"sources, tol 1e-8 (true FP64 residual)"),
@@ -369,7 +375,7 @@ def bench_iso3d(args, torch, rte, mu_s):
     rf = roofline(ctx, rte, pb, args.apply_reps, ["A", "B", "C", "D", "E"])
     out = {
         "value": r["solves_per_s"], "unit": "solves/s", "ms_per_step": r["ms_per_solve"],
-        "dtype": "f32 apply + f32 basis, f64 krylov sums",
+        "dtype": "f32 apply + f64 krylov",
         "config": {"workload": f"3D isotropic {n}^3, mu_a={w['mu_a']:g}, mu_s={mu_s:g}, Gaussian-mixture sources, "
                                f"FP32 FFT on the {padded(n)}^3 padded grid, tol 1e-8", "n": n, "mu_s": mu_s},
         "solve": r, "applies_per_s": 1000.0 / rf["ms_apply"],

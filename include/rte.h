@@ -90,6 +90,13 @@ typedef struct {
                             measured norm is off 1 by more than 1e-8 (FP32 apply) or 1e-10 (FP64) */
     int use_pc;          /* 1: flexible GMRES with the attached preconditioner (default 1 if one
                             is attached) */
+    int basis_fp32;      /* RTE_PREC_FP32 only: 1 stores the inner solve's Krylov basis (and the
+                            apply's output) in FP32, halving the Gram-Schmidt traffic; dot
+                            products, the update arithmetic, the Hessenberg matrix, the rotations,
+                            the solution and the true residual stay FP64.  The basis then stays
+                            orthogonal to FP32 rounding only, below the per-cycle reduction
+                            inner_tol, and the FP64 true residual still decides convergence.
+                            0 (default): FP64 basis.  Ignored for RTE_PREC_FP64. */
 } rte_solve_opts;
 
 #define RTE_MAX_L 8

@@ -39,8 +39,8 @@ struct rte_ctx {
     int krylov_m = 0;
     bool krylov_z = false;
     size_t krylov_vbytes = 0;   // bytes per basis entry the allocation was sized for
-    // (m + 1) basis vectors of nvec entries: float in FP32 contexts (the inner solve of the
-    // mixed-precision refinement keeps its basis in the apply's precision), double otherwise
+    // (m + 1) basis vectors of nvec entries: double, or float when an FP32 context solves with
+    // opts.basis_fp32 (the inner solve then keeps its basis in the apply's precision)
     unsigned char* V = nullptr;
     double* Z = nullptr;
     double* partial = nullptr;

@@ -356,8 +356,8 @@ static int dot_host(rte_ctx* c, const double* a, const double* b, double* out) {
 
 // ------------------------------------------------------------------ GMRES ---------------------
 
-// TV: element type of the basis (float with the FP32 apply, double with the FP64 apply); the
-// Hessenberg matrix, rotations, dot products, x and the true residual are FP64 in both.
+// TV: element type of the basis (double; float with the FP32 apply when opts.basis_fp32 is set);
+// the Hessenberg matrix, rotations, dot products, x and the true residual are FP64 in both.
 template <typename TV>
 static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
                         double* rec, int max_rec, int* nrec) {
@@ -586,7 +586,8 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
 
 int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
                double* rec, int max_rec, int* nrec) {
-    if (c->prec == RTE_PREC_FP32) return solve_core_t<float>(c, b, tol, max_iter, x, info, rec, max_rec, nrec);
+    if (c->prec == RTE_PREC_FP32 && c->opts.basis_fp32)
+        return solve_core_t<float>(c, b, tol, max_iter, x, info, rec, max_rec, nrec);
     return solve_core_t<double>(c, b, tol, max_iter, x, info, rec, max_rec, nrec);
 }
 
@@ -661,6 +662,7 @@ int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const 
     c->opts.inner_tol = 3e-5;
     c->opts.reorth = 0;
     c->opts.use_pc = 1;
+    c->opts.basis_fp32 = 0;
     hipError_t e = hipGetDevice(&c->device);
     if (e != hipSuccess) { free_ctx(c); return set_hip_error(e, "hipGetDevice", __FILE__, __LINE__); }
 
@@ -728,7 +730,7 @@ int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const 
         free_ctx(c);
         return rc;
     }
-    if ((rc = ensure_krylov(c, c->opts.restart, false, prec == RTE_PREC_FP32 ? sizeof(float) : sizeof(double)))) {
+    if ((rc = ensure_krylov(c, c->opts.restart, false, sizeof(double)))) {
         free_ctx(c);
         return rc;
     }
@@ -786,11 +788,13 @@ int rte_set_solve_opts(rte_ctx* c, const rte_solve_opts* o) {
     d.inner_tol = 3e-5;
     d.reorth = 0;
     d.use_pc = 1;
+    d.basis_fp32 = 0;
     if (o) {
         if (o->restart < 1 || o->restart > RTE_MAX_RESTART) return set_error(RTE_EINVAL, "restart must be in 1..%d", RTE_MAX_RESTART);
         if (o->max_cycles < 1) return set_error(RTE_EINVAL, "max_cycles must be >= 1");
         if (!(o->inner_tol > 0.0 && o->inner_tol < 1.0)) return set_error(RTE_EINVAL, "inner_tol must be in (0, 1)");
         if (o->reorth < 0 || o->reorth > 2) return set_error(RTE_EINVAL, "reorth must be 0, 1 or 2");
+        if (o->basis_fp32 != 0 && o->basis_fp32 != 1) return set_error(RTE_EINVAL, "basis_fp32 must be 0 or 1");
         d = *o;
     }
     c->opts = d;

@@ -44,7 +44,7 @@ class SolveInfo(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("restart", C.c_int), ("max_cycles", C.c_int), ("inner_tol", C.c_double),
-                ("reorth", C.c_int), ("use_pc", C.c_int)]
+                ("reorth", C.c_int), ("use_pc", C.c_int), ("basis_fp32", C.c_int)]
 
 
 _lib = None
@@ -213,8 +213,8 @@ class Context:
         _check(load().rte_scattering_term(self._h, layout, up, int(ntheta), sp))
         return out
 
-    def set_opts(self, restart=64, max_cycles=8, inner_tol=3e-5, reorth=0, use_pc=1):
-        o = SolveOpts(restart, max_cycles, inner_tol, reorth, use_pc)
+    def set_opts(self, restart=64, max_cycles=8, inner_tol=3e-5, reorth=0, use_pc=1, basis_fp32=0):
+        o = SolveOpts(restart, max_cycles, inner_tol, reorth, use_pc, basis_fp32)
         _check(load().rte_set_solve_opts(self._h, C.byref(o)))
 
     def solve(self, f, tol=1e-8, max_iter=1000, allow_not_converged=False):

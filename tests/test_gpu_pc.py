@@ -339,13 +339,14 @@ def _oracle_fgmres_iterates(matvec, precond, b, k):
     return xs
 
 
-@pytest.mark.parametrize("prec,n", [(1, 32), (0, 32), (1, 160)])
-def test_fgmres_iterates_match_oracle(rte, prec, n):
+@pytest.mark.parametrize("prec,n,basis32", [(1, 32, 0), (0, 32, 0), (0, 32, 1), (1, 160, 0)])
+def test_fgmres_iterates_match_oracle(rte, prec, n, basis32):
     """The first flexible-GMRES iterates with the attached network, from the single Gram-Schmidt
     pass whose update also normalises and restricts v_{j+1} for the network (reorth 0), and from
     the separate passes (reorth 2): the two agree closely, and both follow the oracle's flexible
     GMRES with z_j = v_j + s P N(R v_j / s), within the BF16 network's accuracy (L = 2, F = 4:
-    an 8^2 coarse grid takes the single-workgroup network kernel, 40^2 the per-layer kernels)."""
+    an 8^2 coarse grid takes the single-workgroup network kernel, 40^2 the per-layer kernels).
+    basis32: the FP32 apply's basis stored in FP32."""
     L, F, k = 2, 4, 4
     mu_a, mu_s = 0.1, 4.0
     h, mu_t = 1.0 / n, mu_a + mu_s
@@ -361,7 +362,7 @@ def test_fgmres_iterates_match_oracle(rte, prec, n):
     bc = _to_ch(b, L)
     recs = {}
     for reorth in (0, 2):
-        ctx.set_opts(reorth=reorth)
+        ctx.set_opts(reorth=reorth, basis_fp32=basis32)
         _, info, rec = ctx.solve_rhs(dev(bc), tol=1e-11, record=k)
         say("  reorth", reorth, info)
         assert info["pc_used"] == 1 and info["pc_fallback"] == 0 and rec.shape[0] == k

@@ -52,16 +52,18 @@ def test_solve_iso32_fp64_vs_lu(rte):
     ctx.close()
 
 
-@pytest.mark.parametrize("prec,tol_err", [(1, 1e-10), (0, 1e-6)])
+@pytest.mark.parametrize("prec,basis32,tol_err", [(1, 0, 1e-10), (0, 0, 1e-6), (0, 1, 1e-6)])
 @pytest.mark.parametrize("L,ny,nx,mu_s", [(3, 12, 12, 2.0), (1, 10, 14, 5.0), (8, 8, 8, 10.0)])
-def test_solve_aniso_small_vs_lu(rte, prec, tol_err, L, ny, nx, mu_s):
-    say("solve small", L, ny, nx, mu_s, "prec", prec)
+def test_solve_aniso_small_vs_lu(rte, prec, basis32, tol_err, L, ny, nx, mu_s):
+    """basis32: the FP32 apply's inner solve with its Krylov basis stored in FP32 (FP64 sums)."""
+    say("solve small", L, ny, nx, mu_s, "prec", prec, "basis32", basis32)
     rng = np.random.default_rng(L + ny)
     h = 1.0 / max(nx, ny)
     mu_a = 0.1
     sh = inputs.hg_sigma_hat(0.5, L)
     f = rng.random((ny, nx))
     ctx = rte.Context((nx, ny), h=h, mu_a=mu_a, mu_s=mu_s, sigma_hat=sh, L=L, prec=prec)
+    ctx.set_opts(basis_fp32=basis32)
     u, info = ctx.solve(dev(f), tol=1e-11)
     say("  info", info)
     ref = _lu(f, L, ny, nx, h, mu_a, mu_s, sh)
@@ -71,13 +73,15 @@ def test_solve_aniso_small_vs_lu(rte, prec, tol_err, L, ny, nx, mu_s):
     ctx.close()
 
 
-def test_solve_hg512_full_size_residual(rte):
-    """512^2, HG g = 0.5, L = 8, mu_s = 10, FP32 apply + FP64 Krylov, tol 1e-8: the oracle's FP64
-    FFT apply confirms the true residual of the GPU solution."""
-    say("solve hg512 L8 mu_s 10")
+@pytest.mark.parametrize("basis32", [0, 1])
+def test_solve_hg512_full_size_residual(rte, basis32):
+    """512^2, HG g = 0.5, L = 8, mu_s = 10, FP32 apply + FP64 Krylov (basis32: FP32 basis storage),
+    tol 1e-8: the oracle's FP64 FFT apply confirms the true residual of the GPU solution."""
+    say("solve hg512 L8 mu_s 10 basis32", basis32)
     w = inputs.workload("hg512", seed=0, mu_s=10.0)
     n, L = w["n"], w["L"]
     ctx = rte.Context(n, mu_a=w["mu_a"], mu_s=w["mu_s"], sigma_hat=w["sigma_hat"], L=L, prec=rte.PREC_FP32)
+    ctx.set_opts(basis_fp32=basis32)
     u, info = ctx.solve(dev(w["f"]), tol=1e-8)
     say("  info", info)
     uu = host(u)
@@ -93,13 +97,16 @@ def test_solve_hg512_full_size_residual(rte):
     ctx.close()
 
 
-def test_solve_iso3d_full_size_residual(rte):
+@pytest.mark.parametrize("basis32", [0, 1])
+def test_solve_iso3d_full_size_residual(rte, basis32):
     """128^3 isotropic, mu_a = 0.05, mu_s = 10, Gaussian-mixture source, FP32 FFT on the 256^3 padded
-    grid with FP64 GMRES, tol 1e-8: the oracle's FP64 FFT apply confirms the true residual."""
-    say("solve iso3d 128 mu_s 10")
+    grid with FP64 GMRES (basis32: FP32 basis storage), tol 1e-8: the oracle's FP64 FFT apply
+    confirms the true residual."""
+    say("solve iso3d 128 mu_s 10 basis32", basis32)
     w = inputs.workload("iso3d", seed=0, mu_s=10.0)
     n = w["n"]
     ctx = rte.Context(n, dim=3, mu_a=w["mu_a"], mu_s=w["mu_s"], L=0, prec=rte.PREC_FP32)
+    ctx.set_opts(basis_fp32=basis32)
     u, info = ctx.solve(dev(w["f"]), tol=1e-8)
     say("  info", info)
     uu = host(u).reshape(n, n, n).real
@@ -159,6 +166,15 @@ def test_solve_iteration_cap_reports_not_converged(rte):
     ctx.close()
 
 
+def test_bad_solve_options_are_einval(rte):
+    ctx = rte.Context(16, mu_a=0.1, mu_s=1.0, L=0, prec=0)
+    for kw in ({"basis_fp32": 2}, {"basis_fp32": -1}, {"reorth": 3}, {"restart": 0}, {"inner_tol": 1.0}):
+        with pytest.raises(rte.RteError) as ei:
+            ctx.set_opts(**kw)
+        assert ei.value.code == rte.RTE_EINVAL
+    ctx.close()
+
+
 def test_solve_bad_tolerance_is_einval(rte):
     ctx = rte.Context(16, mu_a=0.1, mu_s=1.0, L=0, prec=1)
     f = torch.ones((16, 16), dtype=torch.float64, device="cuda")
@@ -170,19 +186,19 @@ def test_solve_bad_tolerance_is_einval(rte):
 
 
 @pytest.mark.parametrize("reorth", [0, 1, 2])
-@pytest.mark.parametrize("prec", [1, 0])
-def test_solve_gram_schmidt_variants_vs_lu(rte, reorth, prec):
+@pytest.mark.parametrize("prec,basis32", [(1, 0), (0, 0), (0, 1)])
+def test_solve_gram_schmidt_variants_vs_lu(rte, reorth, prec, basis32):
     """One classical Gram-Schmidt pass with the normalisation fused into the update (reorth 0), the
     adaptive and the forced second pass (1, 2); a short restart length makes every cycle restart
     several times."""
     L, ny, nx, mu_s = 3, 14, 11, 8.0
-    say("solve gram-schmidt", reorth, "prec", prec)
+    say("solve gram-schmidt", reorth, "prec", prec, "basis32", basis32)
     rng = np.random.default_rng(7)
     h = 1.0 / max(nx, ny)
     sh = inputs.hg_sigma_hat(0.7, L)
     f = rng.random((ny, nx))
     ctx = rte.Context((nx, ny), h=h, mu_a=0.05, mu_s=mu_s, sigma_hat=sh, L=L, prec=prec)
-    ctx.set_opts(restart=6, max_cycles=60, reorth=reorth)
+    ctx.set_opts(restart=6, max_cycles=60, reorth=reorth, basis_fp32=basis32)
     u, info = ctx.solve(dev(f), tol=1e-11)
     say("  info", info)
     assert info["cycles"] > 1
