@@ -51,6 +51,28 @@ __device__ __forceinline__ float coarse_bilerp(const float* __restrict__ yc, int
     return (1.f - ay) * top + ay * bot;
 }
 
+// The coarse correction of a tile of TR fine rows, interpolated in y and staged in LDS:
+// crow[yl * CORR_WMAX + X] for fine row y0 + yl and coarse column X < Wc (Wc <= CORR_WMAX).  Pass C
+// then interpolates in x from two LDS values per cell instead of four loads of the coarse field.
+// It is the same bilinear prolongation as coarse_bilerp (pass A), with the two interpolations in
+// the other order, so the two passes agree to FP32 rounding.
+constexpr int CORR_WMAX = 32;   // keeps two 16-row FP32 tiles per CU (2 x 79.9 KB)
+template <int TR, int NTHR>
+__device__ __forceinline__ void stage_corr_rows(const float* __restrict__ yc, int Hc, int Wc, int F, int y0, int ny,
+                                                float* crow, int tid) {
+    for (int idx = tid; idx < TR * Wc; idx += NTHR) {
+        const int yl = idx / Wc, X = idx % Wc;
+        int r0, r1;
+        float ay;
+        lerp_at(min(y0 + yl, ny - 1), F, Hc, r0, r1, ay);
+        crow[yl * CORR_WMAX + X] = (1.f - ay) * yc[r0 * Wc + X] + ay * yc[r1 * Wc + X];
+    }
+}
+__device__ __forceinline__ float corr_row_at(const float* crow, int yl, int x0, int x1, float ax) {
+    const float* r = crow + yl * CORR_WMAX;
+    return (1.f - ax) * r[x0] + ax * r[x1];
+}
+
 // Row tile of a block: workgroups are dispatched round-robin over the 8 XCDs (linear id mod 8), and
 // neighbouring tiles share 128-byte lines of the transposed spectrum (a tile reads or writes TR
 // consecutive rows of every column).  When the x-grid is a multiple of 8, XCD k is given the
@@ -108,6 +130,8 @@ __device__ __forceinline__ void pass_a_tile(const TV* __restrict__ xin, cx<T>* _
         }
     }
     if (corr_c) {
+        // direct reads of the coarse field: staging it in LDS as pass C does raised this kernel's
+        // registers from 66 to 102 and cost occupancy
         const int Hc = ny / cF, Wc = nx / cF;
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
@@ -202,7 +226,8 @@ template <typename T, int PX, int TR, int NTHR, typename TV>
 __device__ __forceinline__ void pass_c_tile(const cx<T>* __restrict__ src, const TV* __restrict__ xin,
                                             const double* __restrict__ bin, TV* __restrict__ yout, int nx, int ny,
                                             int mode, int pack, int y0, cx<T>* buf, const cx<T>* tws, int tid,
-                                            const float* __restrict__ corr_c = nullptr, int cF = 1, double cs = 0.0) {
+                                            const float* __restrict__ corr_c = nullptr, int cF = 1, double cs = 0.0,
+                                            float* crow = nullptr) {
     constexpr int NP = TR / 2;
     constexpr int LD = padded(PX) + 1;   // odd row pitch: the NP transforms start on different banks
     constexpr int H = PX / 2;
@@ -218,6 +243,15 @@ __device__ __forceinline__ void pass_c_tile(const cx<T>* __restrict__ src, const
         const bool ok = k < NKS;
         xa[it] = (ok && ya < ny) ? src[(size_t)k * ny + ya] : mk((T)0, (T)0);
         xb[it] = (ok && yb < ny) ? src[(size_t)k * ny + yb] : mk((T)0, (T)0);
+    }
+    // the staged correction rows are ordered before their use by the barrier after the buf fill
+    int Hc = 1, Wc = 1;
+    bool staged = false;
+    if (corr_c) {
+        Hc = ny / cF;
+        Wc = nx / cF;
+        staged = crow && Wc <= CORR_WMAX;
+        if (staged) stage_corr_rows<TR, NTHR>(corr_c, Hc, Wc, cF, y0, ny, crow, tid);
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -245,7 +279,6 @@ __device__ __forceinline__ void pass_c_tile(const cx<T>* __restrict__ src, const
     fft_stages_range<T, PX, NP, LD, NTHR, true, 1, NSL>(buf, tws, tid);
     constexpr int TWL = stage_tw_offset(PX, NSL);
     constexpr int NBT = NP * NSL;
-    const int Hc = corr_c ? ny / cF : 1, Wc = corr_c ? nx / cF : 1;
     for (int idx = tid; idx < NBT; idx += NTHR) {
         const int p = idx / NSL, j = idx % NSL;
         const int ya = y0 + 2 * p, yb = ya + 1;
@@ -268,8 +301,16 @@ __device__ __forceinline__ void pass_c_tile(const cx<T>* __restrict__ src, const
             xb_[r] = (okb && mode != APPLY_KT) ? (double)lb[r] : 0.0;
             ba_[r] = (oka && mode == APPLY_RESID) ? bin[(size_t)ya * nx + m] : 0.0;
             bb_[r] = (okb && mode == APPLY_RESID) ? bin[(size_t)yb * nx + m] : 0.0;
-            if (corr_c && oka) xa_[r] += cs * (double)coarse_bilerp(corr_c, Hc, Wc, cF, ya, m);
-            if (corr_c && okb) xb_[r] += cs * (double)coarse_bilerp(corr_c, Hc, Wc, cF, yb, m);
+            if (staged) {
+                int x0, x1;
+                float ax;
+                lerp_at(min(m, nx - 1), cF, Wc, x0, x1, ax);
+                if (oka) xa_[r] += cs * (double)corr_row_at(crow, 2 * p, x0, x1, ax);
+                if (okb) xb_[r] += cs * (double)corr_row_at(crow, 2 * p + 1, x0, x1, ax);
+            } else if (corr_c) {
+                if (oka) xa_[r] += cs * (double)coarse_bilerp(corr_c, Hc, Wc, cF, ya, m);
+                if (okb) xb_[r] += cs * (double)coarse_bilerp(corr_c, Hc, Wc, cF, yb, m);
+            }
         }
         cx<T> v[RL];
 #pragma unroll
@@ -306,6 +347,7 @@ __global__ __launch_bounds__(NTHR) void k_pass_c(const cx<T>* __restrict__ Tb, c
     constexpr int LD = padded(PX) + 1;
     __shared__ cx<T> buf[TR / 2 * LD];
     __shared__ cx<T> tws[PX];
+    __shared__ float crow[TR * CORR_WMAX];
     const int tid = threadIdx.x;
     const int bc = blockIdx.y;
     const int NKS = pack ? PX / 2 : PX / 2 + 1;
@@ -314,7 +356,7 @@ __global__ __launch_bounds__(NTHR) void k_pass_c(const cx<T>* __restrict__ Tb, c
     const float* cc = corr ? corr + (size_t)(bc % C) * (ny / cF) * (nx / cF) : nullptr;
     pass_c_tile<T, PX, TR, NTHR>(Tb + (size_t)bc * NKS * ny, xin ? xin + base : nullptr, bin ? bin + base : nullptr,
                                  yout + base, nx, ny, mode, pack, xcd_tile(blockIdx.x, gridDim.x) * TR, buf, tws, tid,
-                                 cc, cF, cs);
+                                 cc, cF, cs, crow);
 }
 
 // Batched form: one block per (problem, row tile); the output is written to out + (j + 1) stride
