@@ -84,10 +84,11 @@ __device__ __forceinline__ int xcd_tile(int b, int G) { return (G & 7) ? b : (b 
 // column 0 of T as (X[0], X[PX/2]); T then has PX/2 columns.
 // One tile of TR rows of one channel: xin is the channel's [ny][nx] input, out its [NKS][ny]
 // transposed x-spectrum; tws holds the staged twiddles.
-template <typename T, int PX, int TR, int NTHR, typename TV>
+template <typename T, int PX, int TR, int NTHR, typename TV, bool STAGED = false>
 __device__ __forceinline__ void pass_a_tile(const TV* __restrict__ xin, cx<T>* __restrict__ out, int nx, int ny,
                                             double s, int pack, int y0, cx<T>* buf, const cx<T>* tws, int tid,
-                                            const float* __restrict__ corr_c = nullptr, int cF = 1, double cs = 0.0) {
+                                            const float* __restrict__ corr_c = nullptr, int cF = 1, double cs = 0.0,
+                                            float* crow = nullptr) {
     constexpr int NP = TR / 2;        // complex FFTs per block (two real rows each)
     constexpr int LD = padded(PX) + 1;   // odd row pitch: the NP transforms start on different banks
     constexpr int H = PX / 2;
@@ -129,9 +130,29 @@ __device__ __forceinline__ void pass_a_tile(const TV* __restrict__ xin, cx<T>* _
             rb[it][r] = (ok && yb < ny) ? (double)lb[it][r] : 0.0;
         }
     }
-    if (corr_c) {
-        // direct reads of the coarse field: staging it in LDS as pass C does raised this kernel's
-        // registers from 66 to 102 and cost occupancy
+    if (STAGED) {
+        // y-interpolated coarse rows in LDS (nx / cF <= CORR_WMAX), as in pass C; a separate
+        // instantiation, since one kernel holding both forms needed 102 registers instead of 66
+        const int Hc = ny / cF, Wc = nx / cF;
+        stage_corr_rows<TR, NTHR>(corr_c, Hc, Wc, cF, y0, ny, crow, tid);
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int idx = tid + it * NTHR;
+            const int p = idx / NB0, j = idx % NB0;
+#pragma unroll
+            for (int r = 0; r < R0 / 2; ++r) {
+                const int m = j + r * NB0;
+                const bool ok = (NBT % NTHR == 0 || idx < NBT) && m < nx;   // p < NP when ok
+                int x0, x1;
+                float ax;
+                lerp_at(min(m, nx - 1), cF, Wc, x0, x1, ax);
+                if (ok && y0 + 2 * p < ny) ra[it][r] += cs * (double)corr_row_at(crow, 2 * p, x0, x1, ax);
+                if (ok && y0 + 2 * p + 1 < ny) rb[it][r] += cs * (double)corr_row_at(crow, 2 * p + 1, x0, x1, ax);
+            }
+        }
+    } else if (corr_c) {
+        // direct reads of the coarse field
         const int Hc = ny / cF, Wc = nx / cF;
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
@@ -184,7 +205,7 @@ __device__ __forceinline__ void pass_a_tile(const TV* __restrict__ xin, cx<T>* _
     }
 }
 
-template <typename T, int PX, int TR, int NTHR, typename TV>
+template <typename T, int PX, int TR, int NTHR, typename TV, bool STAGED>
 __global__ __launch_bounds__(NTHR) void k_pass_a(const TV* __restrict__ x, cx<T>* __restrict__ Tb,
                                                  const cx<T>* __restrict__ tw, int nx, int ny, int C,
                                                  ChanScale sc, int pack, const float* __restrict__ corr, int cF,
@@ -197,8 +218,10 @@ __global__ __launch_bounds__(NTHR) void k_pass_a(const TV* __restrict__ x, cx<T>
     stage_twiddles<T, PX, NTHR>(tws, tw, tid);
     const int NKS = pack ? PX / 2 : PX / 2 + 1;
     const float* cc = corr ? corr + (size_t)(bc % C) * (ny / cF) * (nx / cF) : nullptr;
-    pass_a_tile<T, PX, TR, NTHR>(x + (size_t)bc * ny * nx, Tb + (size_t)bc * NKS * ny, nx, ny, sc.s[bc % C], pack,
-                                 xcd_tile(blockIdx.x, gridDim.x) * TR, buf, tws, tid, cc, cF, cs);
+    __shared__ float crow[STAGED ? TR * CORR_WMAX : 1];
+    pass_a_tile<T, PX, TR, NTHR, TV, STAGED>(x + (size_t)bc * ny * nx, Tb + (size_t)bc * NKS * ny, nx, ny,
+                                             sc.s[bc % C], pack, xcd_tile(blockIdx.x, gridDim.x) * TR, buf, tws,
+                                             tid, cc, cF, cs, crow);
 }
 
 // Batched form (isotropic problems of one padded size): one block per (problem, row tile).
@@ -384,8 +407,12 @@ template <typename T> constexpr int tile_rows() { return sizeof(T) == 4 ? 16 : 8
 template <typename T, int PX, int TR, typename TV>
 static void launch_a_tr(const Apply2DArgs<T>& a, const TV* x, const ChanScale& sc, int nchan_total) {
     dim3 grid((a.ny + TR - 1) / TR, nchan_total);
-    hipLaunchKernelGGL((k_pass_a<T, PX, TR, 256, TV>), grid, dim3(256), 0, a.stream, x, a.work, a.twx, a.nx,
-                       a.ny, a.C, sc, a.pack, a.corr, a.cF, a.cs);
+    if (a.corr && a.nx / a.cF <= CORR_WMAX)
+        hipLaunchKernelGGL((k_pass_a<T, PX, TR, 256, TV, true>), grid, dim3(256), 0, a.stream, x, a.work, a.twx,
+                           a.nx, a.ny, a.C, sc, a.pack, a.corr, a.cF, a.cs);
+    else
+        hipLaunchKernelGGL((k_pass_a<T, PX, TR, 256, TV, false>), grid, dim3(256), 0, a.stream, x, a.work, a.twx,
+                           a.nx, a.ny, a.C, sc, a.pack, a.corr, a.cF, a.cs);
 }
 template <typename T, int PX, typename TV>
 static void launch_a(const Apply2DArgs<T>& a, const TV* x, const ChanScale& sc, int nchan_total) {
