@@ -75,10 +75,15 @@ def pmc_summary(fetch_csv: str, write_csv: str, variants) -> dict:
     out = {"fetch_factor": ff, "write_factor": fw, "passes": {}}
     # A, B, C: the apply on FP64 channel vectors that the apply timing runs; A_f32, C_f32: the same
     # passes on the FP32 basis vectors of the solver's inner iterations
-    for label, key, tail in (("A", "k_pass_a<float, 1024,", ", double>"), ("B", "k_pass_b_lds<float, 1024, 8,", ""),
-                             ("C", "k_pass_c<float, 1024,", ", double>"), ("A_f32", "k_pass_a<float, 1024,", ", float>"),
-                             ("C_f32", "k_pass_c<float, 1024,", ", float>")):
-        names = [k for k in fe if key in k and k.split("(")[0].endswith(tail)]
+    def targs(name):   # template arguments of a kernel name
+        return name.split("(")[0].split("<", 1)[1].rstrip(">").split(", ")
+
+    # passes A and C: template arguments T, PX, TR, threads, vector type (and, for A, whether the
+    # coarse correction is staged); the apply timing runs the unstaged form
+    for label, key, tv in (("A", "k_pass_a<float, 1024,", "double"), ("B", "k_pass_b_lds<float, 1024, 8,", None),
+                           ("C", "k_pass_c<float, 1024,", "double"), ("A_f32", "k_pass_a<float, 1024,", "float"),
+                           ("C_f32", "k_pass_c<float, 1024,", "float")):
+        names = [k for k in fe if key in k and (tv is None or (targs(k)[4] == tv and targs(k)[5:] in ([], ["false"])))]
         if variants and label[0] in "AC":
             # row tile of the pinned variant (FP32: 16, 8, 32 or 4 rows for variants 0..3)
             tr = (16, 8, 32, 4)[variants["ABC".index(label[0])][0]]
