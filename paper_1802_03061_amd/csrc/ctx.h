@@ -82,8 +82,15 @@ int apply_channels(rte_ctx* c, int mode, int prec, const double* x, const double
 // Basis vector element type of a context.
 template <typename TV>
 inline TV* basis(rte_ctx* c) { return reinterpret_cast<TV*>(c->V); }
+// Output step of a solve (e.g. the conversion of x to the caller's layout), enqueued on the
+// context stream after every true residual, while the host waits for its norm; the last call
+// follows the last change of x.
+struct SolveFinish {
+    void (*fn)(rte_ctx* c, void* arg) = nullptr;
+    void* arg = nullptr;
+};
 int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
-               double* rec, int max_rec, int* nrec);
+               double* rec, int max_rec, int* nrec, const SolveFinish* finish = nullptr);
 int autotune_2d(rte_ctx* c, int reps, bool use_cache);
 }  // namespace rte
 

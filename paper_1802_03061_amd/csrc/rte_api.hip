@@ -343,15 +343,22 @@ static int wait_slot(rte_ctx* c, const double* slot) {
     return RTE_OK;
 }
 
-static int dot_host(rte_ctx* c, const double* a, const double* b, double* out) {
-    // the reduction writes the result straight into device-visible host memory (slot m of hpipe)
+// <a, b> into device-visible host memory (slot m of hpipe): enqueue, then wait for the slot.
+static void dot_enqueue(rte_ctx* c, const double* a, const double* b) {
     const int m = c->krylov_m;
     c->hpipe[m] = kPending;
     krylov_dots(a, c->nvec, 1, b, c->nvec, c->partial, c->hpipe_dev + m, false, c->stream);
+}
+static int dot_wait(rte_ctx* c, double* out) {
+    const int m = c->krylov_m;
     int rc = wait_slot(c, c->hpipe + m);
     if (rc) return rc;
     *out = c->hpipe[m];
     return RTE_OK;
+}
+static int dot_host(rte_ctx* c, const double* a, const double* b, double* out) {
+    dot_enqueue(c, a, b);
+    return dot_wait(c, out);
 }
 
 // ------------------------------------------------------------------ GMRES ---------------------
@@ -360,7 +367,7 @@ static int dot_host(rte_ctx* c, const double* a, const double* b, double* out) {
 // the Hessenberg matrix, rotations, dot products, x and the true residual are FP64 in both.
 template <typename TV>
 static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
-                        double* rec, int max_rec, int* nrec) {
+                        double* rec, int max_rec, int* nrec, const SolveFinish* finish) {
     const double t_start = now_ms();
     hipStream_t st = c->stream;
     const size_t n = c->nvec;
@@ -386,6 +393,7 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
         return set_error(RTE_ENUMERIC, "non-finite right-hand side");
     }
     if (bn2 == 0.0) {
+        if (finish && finish->fn) finish->fn(c, finish->arg);
         RTE_HIP_TRY(hipStreamSynchronize(st));
         inf.t_solve_ms = now_ms() - t_start;
         if (info) *info = inf;
@@ -556,7 +564,9 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
         if ((rc = apply_channels(c, APPLY_RESID, RTE_PREC_FP64, x, b, c->rv, 1))) return rc;
         ++inf.applies;
         double rn2;
-        if ((rc = dot_host(c, c->rv, c->rv, &rn2))) return rc;
+        dot_enqueue(c, c->rv, c->rv);
+        if (finish && finish->fn) finish->fn(c, finish->arg);   // runs while the host waits
+        if ((rc = dot_wait(c, &rn2))) return rc;
         if (!std::isfinite(rn2)) {
             inf.iterations = it;
             inf.cycles = cycles;
@@ -585,10 +595,10 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
 }
 
 int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
-               double* rec, int max_rec, int* nrec) {
+               double* rec, int max_rec, int* nrec, const SolveFinish* finish) {
     if (c->prec == RTE_PREC_FP32 && c->opts.basis_fp32)
-        return solve_core_t<float>(c, b, tol, max_iter, x, info, rec, max_rec, nrec);
-    return solve_core_t<double>(c, b, tol, max_iter, x, info, rec, max_rec, nrec);
+        return solve_core_t<float>(c, b, tol, max_iter, x, info, rec, max_rec, nrec, finish);
+    return solve_core_t<double>(c, b, tol, max_iter, x, info, rec, max_rec, nrec, finish);
 }
 
 }  // namespace rte
@@ -855,9 +865,12 @@ int rte_solve(rte_ctx* c, const double* f, double tol, int max_iter, void* u, rt
     if (max_iter < 1) return set_error(RTE_EINVAL, "max_iter must be >= 1");
     int rc = rhs_channels(c, f, c->bv);
     if (rc) return rc;
-    rc = solve_core(c, c->bv, tol, max_iter, c->xv, info, nullptr, 0, nullptr);
+    // the modes of x are written after every true residual, while the host waits for its norm
+    SolveFinish fin;
+    fin.fn = [](rte_ctx* cc, void* uu) { channels_to_modes(cc->xv, uu, cc->L, cc->ncell, true, cc->stream); };
+    fin.arg = u;
+    rc = solve_core(c, c->bv, tol, max_iter, c->xv, info, nullptr, 0, nullptr, &fin);
     if (rc < 0) return rc;
-    channels_to_modes(c->xv, u, c->L, c->ncell, true, c->stream);
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return set_hip_error(e, "rte_solve", __FILE__, __LINE__);
     if (rc == RTE_NOT_CONVERGED)
