@@ -315,7 +315,12 @@ __global__ __launch_bounds__(256) void k_pass_b_couple(cx<T>* __restrict__ T2, c
     const int b = blockIdx.y;
     const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (idx >= (size_t)nkx * PY) return;
-    const int kx = (int)(idx / PY), f = (int)(idx % PY);
+    // Adjacent threads take the mirrored frequencies f and PY - f, which read the same entries of
+    // the quarter spectra, so a wave fetches each once: q = 2p -> f = p, q = 2p + 1 -> f = PY - p
+    // (p = 0 -> f = PY/2); a bijection of [0, PY).
+    const int kx = (int)(idx / PY), q = (int)(idx % PY);
+    const int fp = q >> 1;
+    const int f = (q & 1) ? (fp == 0 ? PY / 2 : PY - fp) : fp;
     const size_t cstride = (size_t)nkx * PY;
     const size_t qs = (size_t)nkq * KH;
     cx<T>* p = T2 + (size_t)b * C * cstride + (size_t)kx * PY;
