@@ -33,5 +33,7 @@ int pc_rescale_net(rte_ctx* c, const ArnoldiArgs& t, TV* w, const double* partia
 int pc_update_pool_blocks(const rte_ctx* c);
 int pc_net_slot(rte_ctx* c, int j);                    // Y_j = N(pooled v_j / s)
 const float* pc_slot(const rte_ctx* c, int j);
-void pc_add_correction(rte_ctx* c, double* x, const double* y_dev, int k);  // x += s P sum y_j Y_j
+// x += sum_{j < k} y_j V_j + s P sum_j y_j Y_j (basis and coarse network parts in one pass over x)
+template <typename TV>
+void pc_combine(rte_ctx* c, double* x, const TV* V, int k, const double* y_dev);
 }  // namespace rte

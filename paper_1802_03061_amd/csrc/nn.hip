@@ -527,6 +527,37 @@ __global__ __launch_bounds__(256) void k_prolong_add(const double* __restrict__ 
     z[i] = v[i] + s * (double)((1.f - ay) * top + ay * bot);
 }
 
+// The flexible-GMRES solution update in one pass over x: x += sum_{v < nvec} V[v] y[v], then
+// + s P comb (comb: the coarse combination sum_j y_j Y_j; s = st[0]), in the order and with the
+// prolongation of k_combine followed by k_prolong_add.  One block row per fine row (blockIdx.y =
+// c * ny + row), threads along x.
+template <typename TV>
+__global__ __launch_bounds__(256) void k_combine_prolong(double* __restrict__ x, const TV* __restrict__ V, size_t ld,
+                                                        int nvec, const double* __restrict__ y,
+                                                        const float* __restrict__ comb,
+                                                        const float* __restrict__ st, int ny, int nx, int F) {
+    __shared__ double ys[RTE_KRYLOV_MAXVEC];
+    for (int v = threadIdx.x; v < nvec; v += 256) ys[v] = y[v];
+    __syncthreads();
+    const int xx = blockIdx.x * 256 + threadIdx.x;
+    if (xx >= nx) return;
+    const int c = blockIdx.y / ny, yy = blockIdx.y % ny;
+    const int Hc = ny / F, Wc = nx / F;
+    int y0, y1, x0, x1;
+    float ay, ax;
+    lerp_index(yy, F, Hc, y0, y1, ay);
+    lerp_index(xx, F, Wc, x0, x1, ax);
+    const float* yc = comb + (size_t)c * Hc * Wc;
+    const float top = (1.f - ax) * yc[y0 * Wc + x0] + ax * yc[y0 * Wc + x1];
+    const float bot = (1.f - ax) * yc[y1 * Wc + x0] + ax * yc[y1 * Wc + x1];
+    const size_t i = (size_t)blockIdx.y * nx + xx;
+    double t = x[i];
+#pragma unroll 8
+    for (int v = 0; v < nvec; ++v) t += (double)V[(size_t)v * ld + i] * ys[v];
+    const double s = st[0];
+    x[i] = t + s * (double)((1.f - ay) * top + ay * bot);
+}
+
 // Block means of one block's columns into coarse[c][I][J]: part[] holds each thread's column sum
 // over its rows (CW columns x RG row groups).  One wave per coarse cell sums its RG x F column
 // partials in a fixed order (strided lanes, then a shuffle reduction).
@@ -1046,14 +1077,17 @@ template void pc_scale_pool<float, float>(rte_ctx*, const float*, float*, const 
 const float* pc_slot(const rte_ctx* c, int j) { return c->pc_Y + (size_t)j * pc_coarse_len(c); }
 
 // x += s P (sum_{j < k} y_j Y_j) with y on the device.
-void pc_add_correction(rte_ctx* c, double* x, const double* y_dev, int k) {
+template <typename TV>
+void pc_combine(rte_ctx* c, double* x, const TV* V, int k, const double* y_dev) {
     const size_t nco = pc_coarse_len(c);
     float* comb = c->pc_Y + (size_t)(c->pc_slots) * nco;
     hipLaunchKernelGGL(k_coarse_combine, dim3((unsigned)((nco + 255) / 256)), dim3(256), 0, c->stream, c->pc_Y, y_dev, k,
                        (int)nco, comb);
-    hipLaunchKernelGGL(k_prolong_add, dim3((c->nx + 255) / 256, c->C * c->ny), dim3(256), 0, c->stream, x, comb,
-                       c->pc_st, x, c->C, c->ny, c->nx, c->pc_factor);
+    hipLaunchKernelGGL((k_combine_prolong<TV>), dim3((c->nx + 255) / 256, c->C * c->ny), dim3(256), 0, c->stream, x, V,
+                       c->nvec, k, y_dev, comb, c->pc_st, c->ny, c->nx, c->pc_factor);
 }
+template void pc_combine<double>(rte_ctx*, double*, const double*, int, const double*);
+template void pc_combine<float>(rte_ctx*, double*, const float*, int, const double*);
 
 int pc_apply(rte_ctx* c, const double* v, double* z) {
     NetShape sh;

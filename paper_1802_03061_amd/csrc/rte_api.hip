@@ -551,14 +551,14 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
                     back_solve_dev(dH, m + 1, dg, k, c->dsmall, st);
                     double* xr = rec + (size_t)(k - 1) * n;
                     vec_fill(xr, 0.0, n, st);
-                    krylov_combine(xr, V, n, k, c->dsmall, n, st);
-                    if (pc_live) pc_add_correction(c, xr, c->dsmall, k);
+                    if (pc_live) pc_combine(c, xr, (const TV*)V, k, c->dsmall);
+                    else krylov_combine(xr, V, n, k, c->dsmall, n, st);
                 }
                 if (nrec) *nrec = nr;
             }
             back_solve_dev(dH, m + 1, dg, jd, c->dsmall, st);
-            krylov_combine(x, V, n, jd, c->dsmall, n, st);
-            if (pc_live) pc_add_correction(c, x, c->dsmall, jd);
+            if (pc_live) pc_combine(c, x, (const TV*)V, jd, c->dsmall);
+            else krylov_combine(x, V, n, jd, c->dsmall, n, st);
         }
         // true residual with the FP64 apply
         if ((rc = apply_channels(c, APPLY_RESID, RTE_PREC_FP64, x, b, c->rv, 1))) return rc;
