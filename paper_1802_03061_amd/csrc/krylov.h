@@ -44,7 +44,9 @@ template <typename TV>
 void rescale_arn1(const ArnoldiArgs& t, TV* w, size_t n, const double* partial, int nblk, hipStream_t st);
 // y = R^{-1} g for the leading k x k block (k <= RTE_MAX_RESTART) of the rotated Hessenberg
 // matrix H (column-major, leading dimension ld) and rotated residual vector g, on the device
-void back_solve_dev(const double* H, int ld, const double* g, int k, double* y, hipStream_t st);
+// With flags (the device Arnoldi flags), y = 0 instead when flags[2] (non-finite) is set.
+void back_solve_dev(const double* H, int ld, const double* g, int k, double* y, hipStream_t st,
+                    const int* flags = nullptr);
 // g = (g0, 0, ..., 0) with n entries and flags[0..nflags) = 0, on the device
 void init_g(double* g, int n, double g0, int* flags, int nflags, hipStream_t st);
 // dst = (*a) src

@@ -235,8 +235,12 @@ __global__ __launch_bounds__(ARN_THREADS) void k_arnoldi(ArnoldiArgs t) { arnold
 // y_{l+64} (k <= 128), each row's sum taken by a butterfly reduction that gives every lane the
 // same bits.
 __global__ __launch_bounds__(256) void k_back_solve(const double* __restrict__ H, int ld, const double* __restrict__ g,
-                                                    int k, double* __restrict__ y) {
+                                                    int k, double* __restrict__ y, const int* __restrict__ flags) {
     extern __shared__ double Rs[];   // [k][k] column-major, then g[k]
+    if (flags && flags[2] != 0) {   // a non-finite value in the cycle: y = 0 leaves x unchanged
+        for (int i = threadIdx.x; i < k; i += blockDim.x) y[i] = 0.0;
+        return;
+    }
     double* gs = Rs + (size_t)k * k;
     for (int idx = threadIdx.x; idx < k * k; idx += blockDim.x) {
         const int i = idx % k, j = idx / k;
@@ -380,9 +384,9 @@ void vec_scale_dev(TV* dst, const TV* src, const double* a, size_t n, hipStream_
     hipLaunchKernelGGL(k_scale_dev<TV>, dim3(grid_for(n, 4096)), dim3(KT), 0, st, dst, src, a, n);
 }
 
-void back_solve_dev(const double* H, int ld, const double* g, int k, double* y, hipStream_t st) {
+void back_solve_dev(const double* H, int ld, const double* g, int k, double* y, hipStream_t st, const int* flags) {
     const size_t lds = ((size_t)k * k + k) * sizeof(double);
-    hipLaunchKernelGGL(k_back_solve, dim3(1), dim3(256), lds, st, H, ld, g, k, y);
+    hipLaunchKernelGGL(k_back_solve, dim3(1), dim3(256), lds, st, H, ld, g, k, y, flags);
 }
 
 void init_g(double* g, int n, double g0, int* flags, int nflags, hipStream_t st) {

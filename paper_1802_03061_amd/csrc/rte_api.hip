@@ -520,6 +520,27 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
                 if (e1 <= target) stop = true;                                  // column j is kept too
             }
         }
+        // The cycle end (least squares, solution update, true residual and its norm) is enqueued
+        // before the last iteration's flags are read, so the device has it queued when that
+        // iteration ends.  The column count assumes that iteration is sound; if it produced a
+        // non-finite value, k_back_solve returns y = 0 (x unchanged) and the host, reading the
+        // same flags below, handles the cycle as before.  Recording solves keep the ordered path.
+        const bool spec = launched > 0 && !bad && !(rec && cycles == 1);
+        if (spec) {
+            const int jl = launched - 1;
+            const bool prev_brk = jl >= 1 && hfl[2 * (jl - 1)] != 0;
+            const bool last_kept = !prev_brk && jd == jl;   // the host's condition for column jl
+            const int jd_end = last_kept ? jl + 1 : jd;
+            if (jd_end > 0) {
+                back_solve_dev(dH, m + 1, dg, jd_end, c->dsmall, st, last_kept ? dfl : nullptr);
+                if (pc_live) pc_combine(c, x, (const TV*)V, jd_end, c->dsmall);
+                else krylov_combine(x, V, n, jd_end, c->dsmall, n, st);
+            }
+            if ((rc = apply_channels(c, APPLY_RESID, RTE_PREC_FP64, x, b, c->rv, 1))) return rc;
+            ++inf.applies;
+            dot_enqueue(c, c->rv, c->rv);
+            if (finish && finish->fn) finish->fn(c, finish->arg);   // runs while the host waits
+        }
         // settle the last enqueued iteration
         if (launched > 0 && (rc = wait_slot(c, hp + (launched - 1)))) return rc;
         if (!bad && launched > 0) {
@@ -532,6 +553,10 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
         }
         it += launched;
         if (bad) {
+            if (spec) {   // the enqueued cycle end left x unchanged; take its norm out of the slot
+                double unused;
+                if ((rc = dot_wait(c, &unused))) return rc;
+            }
             if (pc_live) {   // a broken preconditioner: restart this cycle without it
                 pc_live = false;
                 inf.pc_fallback = 1;
@@ -543,29 +568,31 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
             if (info) *info = inf;
             return set_error(RTE_ENUMERIC, "non-finite value in the Arnoldi process");
         }
-        if (jd > 0) {
-            // least squares on the device: the rotated H and g never leave it
-            if (rec && cycles == 1) {
-                const int nr = std::min(jd, max_rec);
-                for (int k = 1; k <= nr; ++k) {
-                    back_solve_dev(dH, m + 1, dg, k, c->dsmall, st);
-                    double* xr = rec + (size_t)(k - 1) * n;
-                    vec_fill(xr, 0.0, n, st);
-                    if (pc_live) pc_combine(c, xr, (const TV*)V, k, c->dsmall);
-                    else krylov_combine(xr, V, n, k, c->dsmall, n, st);
+        if (!spec) {
+            if (jd > 0) {
+                // least squares on the device: the rotated H and g never leave it
+                if (rec && cycles == 1) {
+                    const int nr = std::min(jd, max_rec);
+                    for (int k = 1; k <= nr; ++k) {
+                        back_solve_dev(dH, m + 1, dg, k, c->dsmall, st);
+                        double* xr = rec + (size_t)(k - 1) * n;
+                        vec_fill(xr, 0.0, n, st);
+                        if (pc_live) pc_combine(c, xr, (const TV*)V, k, c->dsmall);
+                        else krylov_combine(xr, V, n, k, c->dsmall, n, st);
+                    }
+                    if (nrec) *nrec = nr;
                 }
-                if (nrec) *nrec = nr;
+                back_solve_dev(dH, m + 1, dg, jd, c->dsmall, st);
+                if (pc_live) pc_combine(c, x, (const TV*)V, jd, c->dsmall);
+                else krylov_combine(x, V, n, jd, c->dsmall, n, st);
             }
-            back_solve_dev(dH, m + 1, dg, jd, c->dsmall, st);
-            if (pc_live) pc_combine(c, x, (const TV*)V, jd, c->dsmall);
-            else krylov_combine(x, V, n, jd, c->dsmall, n, st);
+            // true residual with the FP64 apply
+            if ((rc = apply_channels(c, APPLY_RESID, RTE_PREC_FP64, x, b, c->rv, 1))) return rc;
+            ++inf.applies;
+            dot_enqueue(c, c->rv, c->rv);
+            if (finish && finish->fn) finish->fn(c, finish->arg);   // runs while the host waits
         }
-        // true residual with the FP64 apply
-        if ((rc = apply_channels(c, APPLY_RESID, RTE_PREC_FP64, x, b, c->rv, 1))) return rc;
-        ++inf.applies;
         double rn2;
-        dot_enqueue(c, c->rv, c->rv);
-        if (finish && finish->fn) finish->fn(c, finish->arg);   // runs while the host waits
         if ((rc = dot_wait(c, &rn2))) return rc;
         if (!std::isfinite(rn2)) {
             inf.iterations = it;
