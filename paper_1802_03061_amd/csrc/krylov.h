@@ -61,8 +61,10 @@ void arnoldi_run(const ArnoldiArgs& t, hipStream_t s);
 // sums of the new norm, then runs stage 1 and rescales w when the device finds its norm off (see
 // arnoldi_dev.h).
 // x += sum_v y[v] Z_v (y on the device)
+// (nothing when skip is given and skip[2], the device's non-finite flag, is set)
 template <typename TV>
-void krylov_combine(double* x, const TV* Z, size_t ld, int nvec, const double* y, size_t n, hipStream_t st);
+void krylov_combine(double* x, const TV* Z, size_t ld, int nvec, const double* y, size_t n, hipStream_t st,
+                    const int* skip = nullptr);
 // dst = a src (src FP64, dst rounded to TD)
 template <typename TD>
 void vec_scale(TD* dst, const double* src, double a, size_t n, hipStream_t st);

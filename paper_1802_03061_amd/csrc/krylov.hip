@@ -187,11 +187,14 @@ __global__ __launch_bounds__(KT) void k_cgs_update(TV* __restrict__ w, const TV*
     if (threadIdx.x == 0) partial_norm[blockIdx.x] = t;
 }
 
-// x[i] += sum_v Z[v][i] y[v]
+// x[i] += sum_v Z[v][i] y[v]; nothing when skip is given and skip[2] (the device's non-finite
+// flag) is set.
 template <typename TV>
 __global__ __launch_bounds__(KT) void k_combine(double* __restrict__ x, const TV* __restrict__ Z, size_t ld,
-                                                int nvec, const double* __restrict__ y, size_t n) {
+                                                int nvec, const double* __restrict__ y, size_t n,
+                                                const int* __restrict__ skip) {
     __shared__ double ys[RTE_KRYLOV_MAXVEC];
+    if (skip && skip[2] != 0) return;
     for (int v = threadIdx.x; v < nvec; v += KT) ys[v] = y[v];
     __syncthreads();
     const size_t stride = (size_t)gridDim.x * KT;
@@ -408,8 +411,9 @@ void arnoldi_run(const ArnoldiArgs& t, hipStream_t s) {
 }
 
 template <typename TV>
-void krylov_combine(double* x, const TV* Z, size_t ld, int nvec, const double* y, size_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_combine<TV>, dim3(grid_for(n, 4096)), dim3(KT), 0, st, x, Z, ld, nvec, y, n);
+void krylov_combine(double* x, const TV* Z, size_t ld, int nvec, const double* y, size_t n, hipStream_t st,
+                    const int* skip) {
+    hipLaunchKernelGGL(k_combine<TV>, dim3(grid_for(n, 4096)), dim3(KT), 0, st, x, Z, ld, nvec, y, n, skip);
 }
 
 template <typename TD>
@@ -442,7 +446,8 @@ void nonfinite_scan(const double* x, size_t n, int* flag, hipStream_t st) {
                                     hipStream_t, const int*, const ArnoldiArgs*);                               \
     template void vec_scale_dev<TV>(TV*, const TV*, const double*, size_t, hipStream_t);                        \
     template void rescale_arn1<TV>(const ArnoldiArgs&, TV*, size_t, const double*, int, hipStream_t);          \
-    template void krylov_combine<TV>(double*, const TV*, size_t, int, const double*, size_t, hipStream_t);     \
+    template void krylov_combine<TV>(double*, const TV*, size_t, int, const double*, size_t, hipStream_t,      \
+                                     const int*);                                                              \
     template void vec_scale<TV>(TV*, const double*, double, size_t, hipStream_t);
 RTE_KRYLOV_INST(double)
 RTE_KRYLOV_INST(float)

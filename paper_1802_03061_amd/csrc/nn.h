@@ -33,7 +33,8 @@ int pc_rescale_net(rte_ctx* c, const ArnoldiArgs& t, TV* w, const double* partia
 int pc_update_pool_blocks(const rte_ctx* c);
 int pc_net_slot(rte_ctx* c, int j);                    // Y_j = N(pooled v_j / s)
 const float* pc_slot(const rte_ctx* c, int j);
-// x += sum_{j < k} y_j V_j + s P sum_j y_j Y_j (basis and coarse network parts in one pass over x)
+// x += sum_{j < k} y_j V_j + s P sum_j y_j Y_j (basis and coarse network parts in one pass over x);
+// nothing when skip is given and skip[2] (the device's non-finite flag) is set
 template <typename TV>
-void pc_combine(rte_ctx* c, double* x, const TV* V, int k, const double* y_dev);
+void pc_combine(rte_ctx* c, double* x, const TV* V, int k, const double* y_dev, const int* skip = nullptr);
 }  // namespace rte

@@ -530,13 +530,16 @@ __global__ __launch_bounds__(256) void k_prolong_add(const double* __restrict__ 
 // The flexible-GMRES solution update in one pass over x: x += sum_{v < nvec} V[v] y[v], then
 // + s P comb (comb: the coarse combination sum_j y_j Y_j; s = st[0]), in the order and with the
 // prolongation of k_combine followed by k_prolong_add.  One block row per fine row (blockIdx.y =
-// c * ny + row), threads along x.
+// c * ny + row), threads along x.  Nothing when skip is given and skip[2] (the device's
+// non-finite flag) is set.
 template <typename TV>
 __global__ __launch_bounds__(256) void k_combine_prolong(double* __restrict__ x, const TV* __restrict__ V, size_t ld,
                                                         int nvec, const double* __restrict__ y,
                                                         const float* __restrict__ comb,
-                                                        const float* __restrict__ st, int ny, int nx, int F) {
+                                                        const float* __restrict__ st, int ny, int nx, int F,
+                                                        const int* __restrict__ skip) {
     __shared__ double ys[RTE_KRYLOV_MAXVEC];
+    if (skip && skip[2] != 0) return;
     for (int v = threadIdx.x; v < nvec; v += 256) ys[v] = y[v];
     __syncthreads();
     const int xx = blockIdx.x * 256 + threadIdx.x;
@@ -1078,16 +1081,16 @@ const float* pc_slot(const rte_ctx* c, int j) { return c->pc_Y + (size_t)j * pc_
 
 // x += s P (sum_{j < k} y_j Y_j) with y on the device.
 template <typename TV>
-void pc_combine(rte_ctx* c, double* x, const TV* V, int k, const double* y_dev) {
+void pc_combine(rte_ctx* c, double* x, const TV* V, int k, const double* y_dev, const int* skip) {
     const size_t nco = pc_coarse_len(c);
     float* comb = c->pc_Y + (size_t)(c->pc_slots) * nco;
     hipLaunchKernelGGL(k_coarse_combine, dim3((unsigned)((nco + 255) / 256)), dim3(256), 0, c->stream, c->pc_Y, y_dev, k,
                        (int)nco, comb);
     hipLaunchKernelGGL((k_combine_prolong<TV>), dim3((c->nx + 255) / 256, c->C * c->ny), dim3(256), 0, c->stream, x, V,
-                       c->nvec, k, y_dev, comb, c->pc_st, c->ny, c->nx, c->pc_factor);
+                       c->nvec, k, y_dev, comb, c->pc_st, c->ny, c->nx, c->pc_factor, skip);
 }
-template void pc_combine<double>(rte_ctx*, double*, const double*, int, const double*);
-template void pc_combine<float>(rte_ctx*, double*, const float*, int, const double*);
+template void pc_combine<double>(rte_ctx*, double*, const double*, int, const double*, const int*);
+template void pc_combine<float>(rte_ctx*, double*, const float*, int, const double*, const int*);
 
 int pc_apply(rte_ctx* c, const double* v, double* z) {
     NetShape sh;

@@ -523,8 +523,10 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
         // The cycle end (least squares, solution update, true residual and its norm) is enqueued
         // before the last iteration's flags are read, so the device has it queued when that
         // iteration ends.  The column count assumes that iteration is sound; if it produced a
-        // non-finite value, k_back_solve returns y = 0 (x unchanged) and the host, reading the
-        // same flags below, handles the cycle as before.  Recording solves keep the ordered path.
+        // non-finite value, the back-substitution and the update see the device's flag and leave
+        // x unchanged (the network outputs may then be non-finite too, so the update is skipped,
+        // not multiplied by zero), and the host, reading the same flags below, handles the cycle
+        // as before.  Recording solves keep the ordered path.
         const bool spec = launched > 0 && !bad && !(rec && cycles == 1);
         if (spec) {
             const int jl = launched - 1;
@@ -532,9 +534,10 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
             const bool last_kept = !prev_brk && jd == jl;   // the host's condition for column jl
             const int jd_end = last_kept ? jl + 1 : jd;
             if (jd_end > 0) {
-                back_solve_dev(dH, m + 1, dg, jd_end, c->dsmall, st, last_kept ? dfl : nullptr);
-                if (pc_live) pc_combine(c, x, (const TV*)V, jd_end, c->dsmall);
-                else krylov_combine(x, V, n, jd_end, c->dsmall, n, st);
+                const int* guard = last_kept ? dfl : nullptr;
+                back_solve_dev(dH, m + 1, dg, jd_end, c->dsmall, st, guard);
+                if (pc_live) pc_combine(c, x, (const TV*)V, jd_end, c->dsmall, guard);
+                else krylov_combine(x, V, n, jd_end, c->dsmall, n, st, guard);
             }
             if ((rc = apply_channels(c, APPLY_RESID, RTE_PREC_FP64, x, b, c->rv, 1))) return rc;
             ++inf.applies;

@@ -225,6 +225,28 @@ def test_broken_network_falls_back_to_plain_gmres(rte):
     net.close()
 
 
+def test_broken_network_in_the_last_step_of_a_cycle(rte):
+    """Restart length 1: the network's non-finite output shows up in the last (only) step of the
+    cycle, whose flags the host reads after the cycle end is already queued.  The queued update
+    must leave x unchanged, and the solve falls back to plain GMRES and matches it."""
+    n, L = 32, 1
+    ctx = rte.Context(n, mu_a=1.0, mu_s=0.5, sigma_hat=inputs.hg_sigma_hat(0.5, L), L=L, prec=rte.PREC_FP32)
+    ctx.set_opts(restart=1, max_cycles=200)
+    f = dev(inputs.centred_gaussian_source(n))
+    u_ref, info_ref = ctx.solve(f, tol=1e-8)
+    net = rte.Net(ctx.channels, 32, 5, seed=1)
+    bad = torch.full((net.nparam,), float("nan"), dtype=torch.float32, device="cuda")
+    ctx.attach_pc(bad, factor=4)
+    ctx.set_opts(restart=1, max_cycles=200)
+    u, info = ctx.solve(f, tol=1e-8)
+    say("nan net, restart 1:", info, "plain:", info_ref)
+    assert info["pc_fallback"] == 1 and info["relres_true"] <= 1e-8
+    assert np.isfinite(host(u)).all()
+    assert relerr(host(u), host(u_ref)) <= 1e-7
+    ctx.close()
+    net.close()
+
+
 @pytest.mark.parametrize("L,n,F", [(2, 32, 4), (4, 64, 8), (0, 48, 16), (1, 256, 4), (2, 128, 8), (1, 80, 4), (0, 60, 4)])
 def test_pc_apply_matches_oracle(rte, L, n, F):
     """The attached preconditioner z = v + s P N(R v / s) (bilinear P) against the oracle."""
