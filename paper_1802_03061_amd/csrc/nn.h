@@ -12,9 +12,11 @@ void pc_free(rte_ctx* c);
 // coarse network output y_j (slot j), with s = 1 / sqrt(nvec) for the unit-norm v_j.
 size_t pc_coarse_len(const rte_ctx* c);
 int pc_begin_solve(rte_ctx* c, int m);                 // slots for m columns, s in c->pc_st
-// v = a w + pool (a = *a_dev, or a_host when a_dev is NULL); v (and the basis) stored as TV
+// v = a w + pool (a = *a_dev, or a_host when a_dev is NULL); v (and the basis) stored as TV.  With g
+// given, the same launch sets g = (g0, 0, ...) (gn entries) and clears flags[0..nflags).
 template <typename TW, typename TV>
-void pc_scale_pool(rte_ctx* c, const TW* w, TV* v, const double* a_dev, double a_host);
+void pc_scale_pool(rte_ctx* c, const TW* w, TV* v, const double* a_dev, double a_host, double* g = nullptr,
+                   int gn = 0, double g0 = 0.0, int* flags = nullptr, int nflags = 0);
 // The fused single pass of the preconditioned Arnoldi step: w = a (w - sum_{v < nvec} h[v] V_v)
 // with h = s0.st and the normalising factor a computed on the device (stage 0 of the column in
 // block 0), and the block means of the new w; *norm_out = <w, w> (partial: one double per block,

@@ -616,11 +616,19 @@ __device__ __forceinline__ void scale_pool_units(const TW* __restrict__ w, TV* _
     }
 }
 
-// v = a w and its block means (scale_pool_units), a = *a_dev or a_host when a_dev is NULL.
+// v = a w and its block means (scale_pool_units), a = *a_dev or a_host when a_dev is NULL.  With g
+// given, block 0 also sets g = (g0, 0, ..., 0) (gn entries) and flags[0..nflags) = 0, the start
+// of a restart cycle.
 template <typename TW, typename TV>
 __global__ __launch_bounds__(256) void k_scale_pool(const TW* __restrict__ w, TV* __restrict__ v,
                                                     const double* __restrict__ a_dev, double a_host,
-                                                    float* __restrict__ coarse, int C, int ny, int nx, int F) {
+                                                    float* __restrict__ coarse, int C, int ny, int nx, int F,
+                                                    double* __restrict__ g, int gn, double g0,
+                                                    int* __restrict__ flags, int nflags) {
+    if (g && blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < gn; i += blockDim.x) g[i] = i == 0 ? g0 : 0.0;
+        for (int i = threadIdx.x; i < nflags; i += blockDim.x) flags[i] = 0;
+    }
     scale_pool_units(w, v, a_dev ? *a_dev : a_host, coarse, C, ny, nx, F);
 }
 
@@ -989,13 +997,14 @@ int pc_begin_solve(rte_ctx* c, int m) {
 }
 
 template <typename TW, typename TV>
-void pc_scale_pool(rte_ctx* c, const TW* w, TV* v, const double* a_dev, double a_host) {
+void pc_scale_pool(rte_ctx* c, const TW* w, TV* v, const double* a_dev, double a_host, double* g, int gn,
+                   double g0, int* flags, int nflags) {
     const int F = c->pc_factor;
     const int CW = F > 64 ? F : 64;
     const int nchunk = (c->nx + CW - 1) / CW;
     const int nunit = c->C * (c->ny / F) * nchunk;
     hipLaunchKernelGGL((k_scale_pool<TW, TV>), dim3(nunit), dim3(256), 0, c->stream, w, v, a_dev, a_host,
-                       c->pc_coarse, c->C, c->ny, c->nx, F);
+                       c->pc_coarse, c->C, c->ny, c->nx, F, g, gn, g0, flags, nflags);
 }
 
 template <typename TV>
@@ -1068,14 +1077,16 @@ int pc_rescale_net(rte_ctx* c, const ArnoldiArgs& t, TV* w, const double* partia
 }
 
 #define RTE_PC_INST(TV)                                                                                           \
-    template void pc_scale_pool<double, TV>(rte_ctx*, const double*, TV*, const double*, double);                 \
+    template void pc_scale_pool<double, TV>(rte_ctx*, const double*, TV*, const double*, double, double*, int,    \
+                                            double, int*, int);                                                 \
     template void pc_rescale_pool_arn1<TV>(rte_ctx*, const ArnoldiArgs&, TV*, const double*);                    \
     template void pc_update_pool<TV>(rte_ctx*, TV*, const TV*, int, double*, double*, const ArnoldiArgs&);       \
     template int pc_rescale_net<TV>(rte_ctx*, const ArnoldiArgs&, TV*, const double*, int);
 RTE_PC_INST(float)
 RTE_PC_INST(double)
 #undef RTE_PC_INST
-template void pc_scale_pool<float, float>(rte_ctx*, const float*, float*, const double*, double);
+template void pc_scale_pool<float, float>(rte_ctx*, const float*, float*, const double*, double, double*, int,
+                                          double, int*, int);
 
 const float* pc_slot(const rte_ctx* c, int j) { return c->pc_Y + (size_t)j * pc_coarse_len(c); }
 

@@ -356,10 +356,6 @@ static int dot_wait(rte_ctx* c, double* out) {
     *out = c->hpipe[m];
     return RTE_OK;
 }
-static int dot_host(rte_ctx* c, const double* a, const double* b, double* out) {
-    dot_enqueue(c, a, b);
-    return dot_wait(c, out);
-}
 
 // ------------------------------------------------------------------ GMRES ---------------------
 
@@ -385,8 +381,11 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
     inf.pc_used = use_pc ? 1 : 0;
 
     double bn2;
-    if ((rc = dot_host(c, b, b, &bn2))) return rc;
+    // x = 0 and r = b do not depend on |b|: queued while the host waits for it
+    dot_enqueue(c, b, b);
     vec_fill(x, 0.0, n, st);
+    RTE_HIP_TRY(hipMemcpyAsync(c->rv, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if ((rc = dot_wait(c, &bn2))) return rc;
     if (!std::isfinite(bn2)) {
         inf.status = RTE_ENUMERIC;
         if (info) *info = inf;
@@ -400,7 +399,6 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
         return RTE_OK;
     }
     const double bn = std::sqrt(bn2);
-    RTE_HIP_TRY(hipMemcpyAsync(c->rv, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     double rn = bn;
     int it = 0, cycles = 0, status = RTE_NOT_CONVERGED;
     double est = bn;
@@ -427,9 +425,12 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
         double target = 0.5 * tol * bn;
         if (mixed) target = std::max(target, c->opts.inner_tol * rn);
         // v_0 = r / rn (with the pooled coarse input of the network when preconditioning)
-        if (pc_live) pc_scale_pool(c, (const double*)c->rv, V, nullptr, 1.0 / rn);
-        else vec_scale(V, c->rv, 1.0 / rn, n, st);
-        init_g(dg, m + 1, rn, dfl, 4, st);
+        if (pc_live) {   // with g = (rn, 0, ...) and the flags cleared in the same launch
+            pc_scale_pool(c, (const double*)c->rv, V, nullptr, 1.0 / rn, dg, m + 1, rn, dfl, 4);
+        } else {
+            vec_scale(V, c->rv, 1.0 / rn, n, st);
+            init_g(dg, m + 1, rn, dfl, 4, st);
+        }
         est = rn;
         const double cycle_start_rn = rn;
         // Iterations are enqueued one ahead of the convergence check: when iteration j is queued the
