@@ -111,19 +111,23 @@ __device__ __forceinline__ void couple_inplace(cx<T>* base, int stride, const cx
 // coupled D' is parked in the Z(f) slot while Q is coupled, to keep few values live.
 template <typename T, int L, typename PF, typename PM>
 __device__ __forceinline__ void couple_packed_pair(PF p, PM pm, const cx<T>* __restrict__ Q, size_t qstride_m,
-                                                   size_t qoff_dc, size_t qoff_ny, bool self) {
+                                                   size_t qoff_dc, size_t qoff_ny, bool self, bool single = false) {
+    // single: only channel 0 of the input is non-zero (the others are not read)
     constexpr int C = 2 * L + 1;
+    const cx<T> zero = mk((T)0, (T)0);
     cx<T> v[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const cx<T> z = *p(c), w = conj(*pm(c));
+        const bool in = !single || c == 0;
+        const cx<T> z = in ? *p(c) : zero, w = in ? conj(*pm(c)) : zero;
         v[c] = scale(z + w, (T)0.5);
     }
     couple_modes<T, L>(v, Q, qstride_m, qoff_dc, false);
     cx<T> q[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const cx<T> z = *p(c), w = conj(*pm(c));
+        const bool in = !single || c == 0;
+        const cx<T> z = in ? *p(c) : zero, w = in ? conj(*pm(c)) : zero;
         q[c] = scale(mul_mi(z - w), (T)0.5);
         *p(c) = v[c];                       // park D'
     }
@@ -309,7 +313,7 @@ __global__ __launch_bounds__(NTHR) void k_pass_b_fwd(const cx<T>* __restrict__ T
 // Split form, step 2/3: pointwise coupling over all (kx, ky).
 template <typename T, int PY, int L>
 __global__ __launch_bounds__(256) void k_pass_b_couple(cx<T>* __restrict__ T2, const cx<T>* __restrict__ Q,
-                                                       int nkx, int nkq, int pack) {
+                                                       int nkx, int nkq, int pack, int single) {
     constexpr int C = 2 * L + 1;
     constexpr int KH = PY / 2 + 1;
     const int b = blockIdx.y;
@@ -328,14 +332,14 @@ __global__ __launch_bounds__(256) void k_pass_b_couple(cx<T>* __restrict__ T2, c
         if (f > PY / 2) return;
         const int fm = (PY - f) & (PY - 1);
         couple_packed_pair<T, L>([&](int c) { return p + c * cstride + f; }, [&](int c) { return p + c * cstride + fm; },
-                                 Q, qs, (size_t)f, (size_t)(nkq - 1) * KH + f, fm == f);
+                                 Q, qs, (size_t)f, (size_t)(nkq - 1) * KH + f, fm == f, single != 0);
         return;
     }
     const bool flip = f > PY / 2;
     const int fy = flip ? PY - f : f;
     cx<T> v[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) v[c] = p[c * cstride + f];
+    for (int c = 0; c < C; ++c) v[c] = (single && c > 0) ? mk((T)0, (T)0) : p[c * cstride + f];
     couple_modes<T, L>(v, Q, qs, (size_t)kx * KH + fy, flip);
 #pragma unroll
     for (int c = 0; c < C; ++c) p[c * cstride + f] = v[c];
@@ -404,6 +408,7 @@ static int launch_py(const Apply2DArgs<T>& a, int nbatch) {
     const int nkq = a.PX / 2 + 1;
     const int nkx = a.pack ? a.PX / 2 : nkq;
     if constexpr (fused_fits<T, PY, L>()) {
+        if (a.single_in) return -3;   // the fused form reads every channel of the work buffer
         constexpr int NCOL = ncol_for<T, PY, L>();
         constexpr int NT = nthr_for<T, NCOL * C * PY>();
         constexpr int NV = fused_variants<T, PY, L>();
@@ -418,12 +423,14 @@ static int launch_py(const Apply2DArgs<T>& a, int nbatch) {
     } else {
         if (!a.work2) return -2;
         constexpr int NT = PY >= 256 ? 256 : (PY < 64 ? 64 : PY);
+        if (a.single_in && nbatch != 1) return -3;
         dim3 g1(nkx, nbatch * C);
-        hipLaunchKernelGGL((k_pass_b_fwd<T, PY, NT>), g1, dim3(NT), 0, a.stream, a.work, a.work2, a.twy, a.ny,
+        dim3 g1f(nkx, a.single_in ? 1 : nbatch * C);   // single_in: channel 0 only
+        hipLaunchKernelGGL((k_pass_b_fwd<T, PY, NT>), g1f, dim3(NT), 0, a.stream, a.work, a.work2, a.twy, a.ny,
                            nkx);
         dim3 g2((unsigned)(((size_t)nkx * PY + 255) / 256), nbatch);
         hipLaunchKernelGGL((k_pass_b_couple<T, PY, L>), g2, dim3(256), 0, a.stream, a.work2, a.Q, nkx, nkq,
-                           a.pack);
+                           a.pack, a.single_in);
         hipLaunchKernelGGL((k_pass_b_inv<T, PY, NT>), g1, dim3(NT), 0, a.stream, a.work, a.work2, a.twy, a.ny,
                            nkx);
         return 0;

@@ -874,6 +874,23 @@ int rte_channels_to_modes(rte_ctx* c, const double* ch, void* modes) {
 
 // b = K~ g with g = f delta_{k0}: channel 0 carries f, the others are zero.
 static int rhs_channels(rte_ctx* c, const double* f, double* b) {
+    if (c->dim == 2 && c->C > 1 && apply2d_needs_work2<double>(c->L, c->PY)) {
+        // b = K~ (f, 0, ..., 0): pass A and the forward y-FFTs of channel 0 only; the coupling
+        // reads channel 0 and writes every channel; inverse y-FFTs and pass C as usual
+        Apply2DArgs<double> a = args2d<double>(c);
+        a.pack = 1;
+        const ChanScale sc = channel_scale(c, APPLY_KT);
+        Apply2DArgs<double> a1 = a;
+        a1.C = 1;
+        if (apply2d_pass_a<double>(a1, f, sc, 1)) return set_error(RTE_EUNSUPPORTED, "rhs pass A: unsupported size");
+        a.single_in = 1;
+        if (apply2d_pass_b<double>(a, 1)) return set_error(RTE_EUNSUPPORTED, "rhs pass B: unsupported size");
+        a.single_in = 0;
+        if (apply2d_pass_c<double>(a, (const double*)nullptr, nullptr, b, APPLY_KT, 1))
+            return set_error(RTE_EUNSUPPORTED, "rhs pass C: unsupported size");
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? RTE_OK : set_hip_error(e, "rhs launch", __FILE__, __LINE__);
+    }
     vec_fill(c->t0, 0.0, c->nvec, c->stream);
     hipError_t e = hipMemcpyAsync(c->t0, f, c->ncell * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return set_hip_error(e, "rhs copy", __FILE__, __LINE__);
