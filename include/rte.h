@@ -145,7 +145,8 @@ int rte_set_solve_opts(rte_ctx* ctx, const rte_solve_opts* opts);
  * iterative refinement.  f_dev: float64 source at the cell centres; u_dev: complex128 modes
  * (RTE_LAYOUT_MODES).  max_iter bounds the total inner iterations.  Synchronises the stream.
  * Returns RTE_OK, RTE_NOT_CONVERGED (u holds the best iterate), RTE_ENUMERIC or an error.
- * f = 0 gives u = 0 and RTE_OK.  info may be NULL. */
+ * f = 0 gives u = 0 and RTE_OK.  info may be NULL.  u is written during the solve (after each
+ * true residual); after an error its content is unspecified. */
 int rte_solve(rte_ctx* ctx, const double* f_dev, double tol, int max_iter, void* u_dev,
               rte_solve_info* info);
 
