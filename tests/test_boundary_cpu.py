@@ -106,3 +106,35 @@ def test_nn_create_rejects_bad_shapes(lib):
         assert out.value is None
     assert lib.rte_nn_adam_step(None, C.c_float(1e-3)) == rte.RTE_EINVAL
     assert lib.rte_pc_attach(None, None, 32, 5, 4) == rte.RTE_EINVAL
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes structures of the binding have the size and field offsets of the C structs in
+    include/rte.h (compiled with the host C compiler)."""
+    import shutil
+    import subprocess
+    from paper_1802_03061_amd import rte
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"rte_grid": rte.Grid, "rte_solve_info": rte.SolveInfo, "rte_solve_opts": rte.SolveOpts}
+    lines = ['#include "rte.h"', "#include <stdio.h>", "#include <stddef.h>", "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'    printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            parts = line.split()
+            got[(parts[0], parts[1])] = int(parts[2])
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
