@@ -21,9 +21,9 @@ struct Apply2DArgs {
     hipStream_t stream;
     int pack = 0;              // 1: x-frequencies 0 and PX/2 share column 0 of the work buffer
     int var[3] = {0, 0, 0};    // kernel variant of passes A, B, C (see apply2d_variant_count)
-    // Split pass B only (apply2d_needs_work2): the input's channels other than channel 0 are zero
-    // and pass A ran for channel 0 alone, so the forward y-FFTs and the coupling's reads cover
-    // channel 0 only (the right-hand side K~ f).
+    // The input's channels other than channel 0 are zero and pass A ran for channel 0 alone, so
+    // pass B reads channel 0 only (split form: forward y-FFTs of channel 0 only; fused form: the
+    // other channels' spectra start as zeros without loads).  The right-hand side K~ f.
     int single_in = 0;
     // Optional coarse correction (operator A, one batch entry): the input of the apply is taken as
     // x + cs P y, y = corr[C][ny/cF][nx/cF] (FP32), P = bilinear interpolation from the coarse

@@ -146,7 +146,8 @@ __device__ __forceinline__ void couple_packed_pair(PF p, PM pm, const cx<T>* __r
 template <typename T, int PY, int L, int NCOL, int NTHR, int GV = 0>
 __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T>* __restrict__ Q, int ny, int nkx,
                                             int nkq, int pack, int kx0, cx<T>* spec, const cx<T>* tws,
-                                            cx<T>* pairtmp, int tid) {
+                                            cx<T>* pairtmp, int tid, int single = 0) {
+    // single: only channel 0 of the input is non-zero; the other channels are not read
     constexpr int C = 2 * L + 1;
     constexpr int NF = NCOL * C;
     constexpr int LD = padded(PY);
@@ -168,7 +169,7 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
         const int j = idx % NB0, fc = idx / NB0;
         const int col = fc / C, c = fc % C;
         const int kx = kx0 + col;
-        const bool ok = (NBT % NTHR == 0 || idx < NBT) && kx < nkx;
+        const bool ok = (NBT % NTHR == 0 || idx < NBT) && kx < nkx && (!single || c == 0);
 #pragma unroll
         for (int r = 0; r < R0 / 2; ++r) {
             const int y = j + r * NB0;
@@ -263,7 +264,7 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
 template <typename T, int PY, int L, int NCOL, int NTHR, int GV>
 __global__ __launch_bounds__(NTHR) void k_pass_b_lds(cx<T>* __restrict__ Tb, const cx<T>* __restrict__ Q,
                                                      const cx<T>* __restrict__ tw, int ny, int nkx, int nkq,
-                                                     int pack) {
+                                                     int pack, int single) {
     constexpr int C = 2 * L + 1;
     __shared__ cx<T> spec[NCOL * C * padded(PY)];
     __shared__ cx<T> tws[PY];
@@ -271,7 +272,7 @@ __global__ __launch_bounds__(NTHR) void k_pass_b_lds(cx<T>* __restrict__ Tb, con
     const int tid = threadIdx.x;
     stage_twiddles<T, PY, NTHR>(tws, tw, tid);
     pass_b_cols<T, PY, L, NCOL, NTHR, GV>(Tb + (size_t)blockIdx.y * C * nkx * ny, Q, ny, nkx, nkq, pack,
-                                          blockIdx.x * NCOL, spec, tws, pairtmp, tid);
+                                          blockIdx.x * NCOL, spec, tws, pairtmp, tid, single);
 }
 
 #if RTE_PASSB_L == 0
@@ -398,7 +399,7 @@ template <typename T, int PY, int L, int NCOL, int NT, int GV>
 static void launch_fused(const Apply2DArgs<T>& a, int nbatch, int nkx, int nkq) {
     dim3 grid((nkx + NCOL - 1) / NCOL, nbatch);
     hipLaunchKernelGGL((k_pass_b_lds<T, PY, L, NCOL, NT, GV>), grid, dim3(NT), 0, a.stream, a.work, a.Q, a.twy, a.ny,
-                       nkx, nkq, a.pack);
+                       nkx, nkq, a.pack, a.single_in);
 }
 
 template <typename T, int PY>
@@ -408,7 +409,6 @@ static int launch_py(const Apply2DArgs<T>& a, int nbatch) {
     const int nkq = a.PX / 2 + 1;
     const int nkx = a.pack ? a.PX / 2 : nkq;
     if constexpr (fused_fits<T, PY, L>()) {
-        if (a.single_in) return -3;   // the fused form reads every channel of the work buffer
         constexpr int NCOL = ncol_for<T, PY, L>();
         constexpr int NT = nthr_for<T, NCOL * C * PY>();
         constexpr int NV = fused_variants<T, PY, L>();

@@ -874,9 +874,9 @@ int rte_channels_to_modes(rte_ctx* c, const double* ch, void* modes) {
 
 // b = K~ g with g = f delta_{k0}: channel 0 carries f, the others are zero.
 static int rhs_channels(rte_ctx* c, const double* f, double* b) {
-    if (c->dim == 2 && c->C > 1 && apply2d_needs_work2<double>(c->L, c->PY)) {
-        // b = K~ (f, 0, ..., 0): pass A and the forward y-FFTs of channel 0 only; the coupling
-        // reads channel 0 and writes every channel; inverse y-FFTs and pass C as usual
+    if (c->dim == 2 && c->C > 1) {
+        // b = K~ (f, 0, ..., 0): pass A for channel 0 only, pass B reading channel 0 only (its
+        // coupling writes every channel); inverse y-FFTs and pass C as usual
         Apply2DArgs<double> a = args2d<double>(c);
         a.pack = 1;
         const ChanScale sc = channel_scale(c, APPLY_KT);
