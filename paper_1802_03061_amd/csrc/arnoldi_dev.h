@@ -176,7 +176,13 @@ __device__ __forceinline__ double block_sum_fixed(const double* __restrict__ par
         const double a0 = partial[b], a1 = partial[b + nt], a2 = partial[b + 2 * nt], a3 = partial[b + 3 * nt];
         s += (a0 + a1) + (a2 + a3);
     }
-    for (; b < nblk; b += nt) s += partial[b];
+    // at most three values are left per thread: loaded together rather than one after another
+    {
+        const double t0 = b < nblk ? partial[b] : 0.0;
+        const double t1 = b + nt < nblk ? partial[b + nt] : 0.0;
+        const double t2 = b + 2 * nt < nblk ? partial[b + 2 * nt] : 0.0;
+        s += (t0 + t1) + t2;
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if ((tid & 63) == 0) wsum[tid >> 6] = s;
