@@ -718,8 +718,38 @@ __global__ __launch_bounds__(256) void k_update_pool(TV* __restrict__ w, const T
                 const size_t op = (o0 + (size_t)u * nx) / 2;
                 const P2 wl = w2[op];
                 double tx = (double)wl.x, ty = (double)wl.y;
-#pragma unroll 8
-                for (int v = 0; v < nvec; ++v) {
+                // eight basis loads issued before their multiplies (the subtraction order is v)
+                int v = 0;
+                for (; v + 8 <= nvec; v += 8) {
+                    P2 b[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) b[q] = V2[(size_t)(v + q) * ldp + op];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        tx -= (double)b[q].x * hs[v + q];
+                        ty -= (double)b[q].y * hs[v + q];
+                    }
+                }
+                if (v + 4 <= nvec) {
+                    P2 b[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) b[q] = V2[(size_t)(v + q) * ldp + op];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        tx -= (double)b[q].x * hs[v + q];
+                        ty -= (double)b[q].y * hs[v + q];
+                    }
+                    v += 4;
+                }
+                if (v + 2 <= nvec) {
+                    const P2 b0 = V2[(size_t)v * ldp + op], b1 = V2[(size_t)(v + 1) * ldp + op];
+                    tx -= (double)b0.x * hs[v];
+                    ty -= (double)b0.y * hs[v];
+                    tx -= (double)b1.x * hs[v + 1];
+                    ty -= (double)b1.y * hs[v + 1];
+                    v += 2;
+                }
+                if (v < nvec) {
                     const P2 b = V2[(size_t)v * ldp + op];
                     tx -= (double)b.x * hs[v];
                     ty -= (double)b.y * hs[v];
