@@ -31,7 +31,9 @@ def _ctx(rte, n, L, g=0.5, mu_a=0.1, mu_s=2.0, prec=1, h=None):
     return rte.Context(n, h=h, mu_a=mu_a, mu_s=mu_s, sigma_hat=sh, L=L, prec=prec), sh
 
 
-SMALL = [(0, 8, 8), (1, 12, 10), (2, 9, 13), (3, 16, 16), (8, 12, 16), (4, 5, 21)]
+# the last five: every L the library compiles a pass B for is covered, down to the smallest grid
+SMALL = [(0, 8, 8), (1, 12, 10), (2, 9, 13), (3, 16, 16), (8, 12, 16), (4, 5, 21),
+         (0, 2, 2), (5, 3, 2), (6, 7, 9), (7, 2, 2), (7, 11, 6)]
 
 
 @pytest.mark.parametrize("L,ny,nx", SMALL)
@@ -125,7 +127,7 @@ def test_rhs_vs_oracle(rte, L, n):
     ctx.close()
 
 
-@pytest.mark.parametrize("shape", [(8, 8, 8), (9, 10, 7)])
+@pytest.mark.parametrize("shape", [(8, 8, 8), (9, 10, 7), (2, 3, 2)])
 @pytest.mark.parametrize("prec", [1, 0])
 def test_apply_3d_small_vs_dense(rte, shape, prec):
     nx, ny, nz = shape

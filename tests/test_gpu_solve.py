@@ -53,7 +53,8 @@ def test_solve_iso32_fp64_vs_lu(rte):
 
 
 @pytest.mark.parametrize("prec,basis32,tol_err", [(1, 0, 1e-10), (0, 0, 1e-6), (0, 1, 1e-6)])
-@pytest.mark.parametrize("L,ny,nx,mu_s", [(3, 12, 12, 2.0), (1, 10, 14, 5.0), (8, 8, 8, 10.0)])
+@pytest.mark.parametrize("L,ny,nx,mu_s", [(3, 12, 12, 2.0), (1, 10, 14, 5.0), (8, 8, 8, 10.0), (5, 2, 2, 3.0),
+                                          (7, 3, 5, 1.0)])
 def test_solve_aniso_small_vs_lu(rte, prec, basis32, tol_err, L, ny, nx, mu_s):
     """basis32: the FP32 apply's inner solve with its Krylov basis stored in FP32 (FP64 sums)."""
     say("solve small", L, ny, nx, mu_s, "prec", prec, "basis32", basis32)
