@@ -74,14 +74,15 @@ def test_solve_aniso_small_vs_lu(rte, prec, basis32, tol_err, L, ny, nx, mu_s):
     ctx.close()
 
 
-@pytest.mark.parametrize("basis32", [0, 1])
-def test_solve_hg512_full_size_residual(rte, basis32):
-    """512^2, HG g = 0.5, L = 8, mu_s = 10, FP32 apply + FP64 Krylov (basis32: FP32 basis storage),
-    tol 1e-8: the oracle's FP64 FFT apply confirms the true residual of the GPU solution."""
-    say("solve hg512 L8 mu_s 10 basis32", basis32)
+@pytest.mark.parametrize("prec,basis32", [(0, 0), (0, 1), (1, 0)])
+def test_solve_hg512_full_size_residual(rte, prec, basis32):
+    """512^2, HG g = 0.5, L = 8, mu_s = 10, FP32 apply + FP64 Krylov (basis32: FP32 basis storage)
+    or FP64 throughout (prec 1, the split pass B), tol 1e-8: the oracle's FP64 FFT apply confirms
+    the true residual of the GPU solution."""
+    say("solve hg512 L8 mu_s 10 prec", prec, "basis32", basis32)
     w = inputs.workload("hg512", seed=0, mu_s=10.0)
     n, L = w["n"], w["L"]
-    ctx = rte.Context(n, mu_a=w["mu_a"], mu_s=w["mu_s"], sigma_hat=w["sigma_hat"], L=L, prec=rte.PREC_FP32)
+    ctx = rte.Context(n, mu_a=w["mu_a"], mu_s=w["mu_s"], sigma_hat=w["sigma_hat"], L=L, prec=prec)
     ctx.set_opts(basis_fp32=basis32)
     u, info = ctx.solve(dev(w["f"]), tol=1e-8)
     say("  info", info)
