@@ -12,7 +12,7 @@
  * mode k at x_i to input mode k' at x_j by h^d kappa(|x_i-x_j|) exp(i (k'-k) theta_ij), with
  * kappa(r) = exp(-mu_t r)/(2 pi r) in 2D and exp(-mu_t r)/(4 pi r^2) in 3D and theta_ij the polar
  * angle of x_i - x_j (eq. ani_2d_operator); the diagonal entry is the exact cell integral of the
- * singular kernel (Sec. 2.3, "the integral of K~ at the i-th cell").  The operator is applied by
+ * singular kernel over the cell (Sec. 2.3, eq. iso_discretization).  The operator is applied by
  * zero-padded FFT convolution (Sec. 2.3.1 and 3.3.1) and the system is solved by GMRES.
  *
  * Conventions shared by every entry point
@@ -153,7 +153,9 @@ int rte_solve(rte_ctx* ctx, const double* f_dev, double tol, int max_iter, void*
 /* Solve A x = b for a right-hand side b given in RTE_LAYOUT_CHANNELS (float64), x in the same
  * layout.  If x_iterates is not NULL, the first inner cycle's iterates are recorded there
  * (x_iterates[j] = the iterate after j+1 inner iterations, up to max_record vectors of the
- * channel size) for generating preconditioner training pairs; *n_recorded gets their count. */
+ * channel size) for generating preconditioner training pairs; *n_recorded gets their count.
+ * x, b and the max_record vectors at x_iterates must not overlap (x is cleared before b is
+ * read): overlapping storage is RTE_EINVAL. */
 int rte_solve_rhs(rte_ctx* ctx, const double* b_dev, double tol, int max_iter, double* x_dev,
                   rte_solve_info* info, double* x_iterates, int max_record, int* n_recorded);
 

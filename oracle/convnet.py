@@ -88,7 +88,7 @@ def coarse_loss(x: np.ndarray, t: np.ndarray, w: np.ndarray, params):
     """Mean over the batch of w_b ||N(x_b) - t_b||^2 and its parameter gradients.
 
     This is the training objective of the coarse-grid correction z = v + s P N(R v / s) (R: F x F
-    block average, P: piecewise-constant prolongation, s: RMS of R v): with x = R r / s and
+    block average, P: piecewise-constant prolongation, s: RMS of v): with x = R r / s and
     t = R(e - r) / s, ||r + s P N(x) - e||^2 = ||(I - P R)(r - e)||^2 + F^2 s^2 ||N(x) - t||^2
     because P R is the orthogonal projector onto block-constant fields, so the fine-grid relative
     loss ||r + s P N(x) - e||^2 / ||e||^2 differs from w ||N(x) - t||^2 (w = F^2 s^2 / ||e||^2)

@@ -9,7 +9,7 @@ Reading of the angle: the paper writes theta as an arccos of the vector (x - y)/
 characteristics of T^{-1} run from y = x - s v to x, so theta is the direction angle of x - y,
 i.e. atan2(y_i - y_j, x_i - x_j).  The exponent is (k' - k), acting on input mode k'.
 
-Self cell (Sec. 2.3, "the integral of K~ at the i-th cell"): the diagonal entry is the exact
+Self cell (Sec. 2.3, the diagonal entry of the Nystrom matrix): the diagonal entry is the exact
 integral of the kernel over the square (cube) cell centred at the node.  The paper evaluates it
 as an analytic mean plus Gauss-Legendre on the smooth remainder; here it is the exact integral
 reduced to one (2D) or two (3D) smooth dimensions and integrated by Gauss-Legendre.

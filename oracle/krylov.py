@@ -3,8 +3,10 @@
 The paper solves step T.2 / S.2 with GMRES (and MINRES for the symmetric isotropic form) to a
 relative-residual tolerance eps (Sec. 2.4, 3.4).  Reading of the unstated details: start from
 x0 = 0, no restart, residual measured as ||b - A x||_2 / ||b||_2 over all entries.  The oracle's
-GMRES orthogonalises by modified Gram-Schmidt repeated twice and solves the small least-squares
-problem by Givens rotations.  Dense LU and the Neumann series are independent cross-checks.
+GMRES orthogonalises by classical Gram-Schmidt repeated twice and solves the small least-squares
+problem by Givens rotations.  For grids beyond a dense matrix it is the full-size reference, as
+the paper's own references for large n are FFT-method solves at a very small tolerance
+(Sec. 2.4.1, Sec. 3.4.1).  Dense LU and the Neumann series are independent cross-checks.
 """
 from __future__ import annotations
 
@@ -19,27 +21,35 @@ def solve_dense(A: np.ndarray, b: np.ndarray) -> np.ndarray:
 def gmres(matvec, b: np.ndarray, tol: float = 1e-13, maxiter: int = 200):
     """Unrestarted GMRES from x0 = 0.  Returns (x, history of estimated relative residuals).
 
-    b may have any shape; matvec maps arrays of that shape to that shape."""
+    b may have any shape; matvec maps arrays of that shape to that shape.  Real b gives real
+    arithmetic throughout, complex b complex arithmetic.  Each new Arnoldi vector is
+    orthogonalised against the basis by classical Gram-Schmidt applied twice (the projection
+    coefficients h = V^H w are formed as one matrix-vector product with the stored basis, then
+    w <- w - V h; the two passes' coefficients add up to the Hessenberg column), which is as
+    orthogonal as modified Gram-Schmidt twice and lets the basis products run as library
+    matrix-vector products on large vectors."""
     shape = b.shape
-    bf = b.reshape(-1).astype(np.complex128)
+    dtype = np.complex128 if np.iscomplexobj(b) else np.float64
+    bf = np.ascontiguousarray(b.reshape(-1), dtype=dtype)
     beta = np.linalg.norm(bf)
     if beta == 0.0:
-        return np.zeros_like(b, dtype=np.complex128), [0.0]
-    V = [bf / beta]
-    H = np.zeros((maxiter + 1, maxiter), dtype=np.complex128)
-    cs = np.zeros(maxiter, dtype=np.complex128)
-    sn = np.zeros(maxiter, dtype=np.complex128)
-    g = np.zeros(maxiter + 1, dtype=np.complex128)
+        return np.zeros(shape, dtype=dtype), [0.0]
+    V = np.empty((maxiter + 1, bf.size), dtype=dtype)     # rows are the basis vectors
+    V[0] = bf / beta
+    H = np.zeros((maxiter + 1, maxiter), dtype=dtype)
+    cs = np.zeros(maxiter, dtype=dtype)
+    sn = np.zeros(maxiter, dtype=dtype)
+    g = np.zeros(maxiter + 1, dtype=dtype)
     g[0] = beta
     hist = [1.0]
     j_end = 0
     for j in range(maxiter):
-        w = matvec(V[j].reshape(shape)).reshape(-1).astype(np.complex128)
-        for _ in range(2):                      # MGS, twice
-            for i in range(j + 1):
-                hij = np.vdot(V[i], w)
-                H[i, j] += hij
-                w = w - hij * V[i]
+        w = np.array(matvec(V[j].reshape(shape)), dtype=dtype).reshape(-1)
+        Vj = V[:j + 1]
+        for _ in range(2):                      # classical Gram-Schmidt, twice
+            hc = np.conj(Vj @ np.conj(w))        # h_i = <V_i, w> = sum conj(V_i) w
+            H[:j + 1, j] += hc
+            w -= hc @ Vj
         H[j + 1, j] = np.linalg.norm(w)
         # previous rotations
         for i in range(j):
@@ -64,11 +74,11 @@ def gmres(matvec, b: np.ndarray, tol: float = 1e-13, maxiter: int = 200):
         hist.append(float(rel))
         j_end = j + 1
         hnext = np.linalg.norm(w)
-        if rel <= tol or hnext == 0.0:
+        if rel <= tol or hnext == 0.0 or j + 1 == maxiter:
             break
-        V.append(w / hnext)
+        V[j + 1] = w / hnext
     y = np.linalg.solve(np.triu(H[:j_end, :j_end]), g[:j_end])
-    x = sum(y[i] * V[i] for i in range(j_end))
+    x = y @ V[:j_end]
     return x.reshape(shape), hist
 
 

@@ -13,6 +13,8 @@ L = 0 is the isotropic u-form u = K u + K~ f (eq. iso_Fredholm, discretised per 
 """
 from __future__ import annotations
 
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import scipy.fft as sfft
 
@@ -96,7 +98,7 @@ def apply_sampled(u: np.ndarray, cells, L: int, h: float, mu_t: float, mu_s: flo
     return out
 
 
-def kernel_spectra(ny: int, nx: int, L: int, h: float, mu_t: float):
+def kernel_spectra(ny: int, nx: int, L: int, h: float, mu_t: float, workers: int | None = None):
     """FFTs of the zero-padded, periodically wrapped kernel tables on a (2ny, 2nx) grid, for
     every mode difference m = -2L..2L (circulant embedding, Sec. 2.3.1 and 3.3.1).  Offset o is
     stored at index o mod P; the offsets +-n are never used and stay zero."""
@@ -108,7 +110,7 @@ def kernel_spectra(ny: int, nx: int, L: int, h: float, mu_t: float):
     for m in range(-2 * L, 2 * L + 1):
         tab = np.zeros((Py, Px), dtype=np.complex128)
         tab[OY % Py, OX % Px] = kernel_entry_2d(OX, OY, m, h, mu_t)
-        spectra[m] = sfft.fft2(tab)
+        spectra[m] = sfft.fft2(tab, workers=workers)
     return spectra
 
 
@@ -126,17 +128,33 @@ def apply_fft(u: np.ndarray, L: int, h: float, mu_t: float, mu_s: float, sigma_h
         pad[:ny, :nx] = d[b] * u[b]
         W.append(sfft.fft2(pad, workers=workers))
     v = np.zeros_like(u, dtype=np.complex128)
-    for a, k in enumerate(range(-L, L + 1)):
+
+    def output_mode(a):
+        # sum over input modes k' in increasing order, as written above
+        k = a - L
         acc = np.zeros((2 * ny, 2 * nx), dtype=np.complex128)
+        tmp = np.empty_like(acc)
         for b, kp in enumerate(range(-L, L + 1)):
-            acc += spectra[kp - k] * W[b]
-        v[a] = sfft.ifft2(acc, workers=workers)[:ny, :nx]
+            np.multiply(spectra[kp - k], W[b], out=tmp)
+            acc += tmp
+        v[a] = sfft.ifft2(acc, workers=inner)[:ny, :nx]
+
+    nthreads = min(M, workers or 1)
+    inner = 1 if nthreads > 1 else workers
+    if nthreads > 1:
+        # the output modes are independent sums: evaluate them on a thread pool
+        with ThreadPoolExecutor(nthreads) as ex:
+            list(ex.map(output_mode, range(M)))
+    else:
+        for a in range(M):
+            output_mode(a)
     return u - v if op == "A" else v
 
 
-def rhs(f: np.ndarray, L: int, h: float, mu_t: float, method: str = "fft", spectra=None):
+def rhs(f: np.ndarray, L: int, h: float, mu_t: float, method: str = "fft", spectra=None,
+        workers: int | None = None):
     """b = K~ g with g = f delta_{k0} (step T.1)."""
     g = source_vector(f, L)
     if method == "direct":
         return apply_direct(g, L, h, mu_t, 0.0, np.ones(L + 1), op="KT")
-    return apply_fft(g, L, h, mu_t, 0.0, np.ones(L + 1), op="KT", spectra=spectra)
+    return apply_fft(g, L, h, mu_t, 0.0, np.ones(L + 1), op="KT", spectra=spectra, workers=workers)

@@ -38,8 +38,10 @@ def apply_sampled(u: np.ndarray, cells, h: float, mu_t: float, mu_s: float, op: 
     return out
 
 
-def kernel_spectrum(nz: int, ny: int, nx: int, h: float, mu_t: float) -> np.ndarray:
-    """FFT of the wrapped kernel table on the (2nz, 2ny, 2nx) padded grid (circulant embedding)."""
+def kernel_spectrum(nz: int, ny: int, nx: int, h: float, mu_t: float,
+                    workers: int | None = None) -> np.ndarray:
+    """FFT of the wrapped kernel table on the (2nz, 2ny, 2nx) padded grid (circulant embedding).
+    The table is real, so its real-input transform (last axis halved) is kept."""
     P = (2 * nz, 2 * ny, 2 * nx)
     oz = np.arange(-(nz - 1), nz)
     oy = np.arange(-(ny - 1), ny)
@@ -47,16 +49,20 @@ def kernel_spectrum(nz: int, ny: int, nx: int, h: float, mu_t: float) -> np.ndar
     OZ, OY, OX = np.meshgrid(oz, oy, ox, indexing="ij")
     tab = np.zeros(P)
     tab[OZ % P[0], OY % P[1], OX % P[2]] = kernel_entry_3d(OX, OY, OZ, h, mu_t)
-    return sfft.fftn(tab)
+    return sfft.rfftn(tab, workers=workers)
 
 
 def apply_fft(u: np.ndarray, h: float, mu_t: float, mu_s: float, op: str = "A",
               spectrum=None, workers: int | None = None) -> np.ndarray:
+    """y = u - mu_s K~ u (op "A") or y = K~ u (op "KT") for a real density u by circulant
+    embedding: zero-pad to (2nz, 2ny, 2nx), transform, multiply by the kernel spectrum, inverse
+    transform, keep the first nz x ny x nx."""
     nz, ny, nx = u.shape
+    P = (2 * nz, 2 * ny, 2 * nx)
     if spectrum is None:
-        spectrum = kernel_spectrum(nz, ny, nx, h, mu_t)
+        spectrum = kernel_spectrum(nz, ny, nx, h, mu_t, workers)
     scale = mu_s if op == "A" else 1.0
-    pad = np.zeros((2 * nz, 2 * ny, 2 * nx))
-    pad[:nz, :ny, :nx] = scale * u
-    v = sfft.ifftn(spectrum * sfft.fftn(pad, workers=workers), workers=workers)[:nz, :ny, :nx].real
+    pad = np.zeros(P)
+    pad[:nz, :ny, :nx] = scale * np.asarray(u).real
+    v = sfft.irfftn(spectrum * sfft.rfftn(pad, workers=workers), s=P, workers=workers)[:nz, :ny, :nx]
     return u - v if op == "A" else v

@@ -932,6 +932,19 @@ int rte_solve_rhs(rte_ctx* c, const double* b, double tol, int max_iter, double*
     if (!(tol > 0.0) || !(tol < 1.0)) return set_error(RTE_EINVAL, "tol must be in (0, 1)");
     if (max_iter < 1) return set_error(RTE_EINVAL, "max_iter must be >= 1");
     if (x_iterates && max_record < 0) return set_error(RTE_EINVAL, "max_record must be >= 0");
+    // x is cleared before b is read, so the two must be distinct storage; so must the iterates
+    auto overlap = [](const void* p, size_t np, const void* q, size_t nq) {
+        const char* a = (const char*)p;
+        const char* b2 = (const char*)q;
+        return a < b2 + nq && b2 < a + np;
+    };
+    const size_t vb = c->nvec * sizeof(double);
+    if (overlap(x, vb, b, vb)) return set_error(RTE_EINVAL, "x and b overlap");
+    if (x_iterates && max_record > 0) {
+        const size_t ib = (size_t)max_record * vb;
+        if (overlap(x_iterates, ib, x, vb) || overlap(x_iterates, ib, b, vb))
+            return set_error(RTE_EINVAL, "x_iterates overlaps x or b");
+    }
     return solve_core(c, b, tol, max_iter, x, info, x_iterates, max_record, n_recorded);
 }
 

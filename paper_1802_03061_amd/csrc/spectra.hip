@@ -1,5 +1,5 @@
-// Precompute of the kernel spectra (the T_pre step of Sec. 2.4; Sec. 2.3.1 and 3.3.1: "one needs
-// to calculate the Fourier modes of kappa").  Everything here runs in FP64.
+// Precompute of the kernel spectra (the T_pre step of Sec. 2.4; the FFT of the kernel table that
+// the convolution applies of Sec. 2.3.1 and 3.3.1 multiply by).  Everything here runs in FP64.
 //
 // 2D: for m = 0..2L the table K_m[oy][ox] on the PY x PX periodic grid holds
 //       h^2 exp(-mu_t r)/(2 pi r) exp(i m theta),  r = h|o|, theta = polar angle of o,

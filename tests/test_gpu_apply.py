@@ -1,8 +1,8 @@
 """GPU parity of the FFT apply and the right-hand side against the CPU oracle (through the C ABI).
 
-Bars: FP64 path relative L2 error <= 1e-12 against the oracle; FP32 path <= 2e-6 (an FP32 FFT of
-length P carries a relative error of order eps32 * log2(P) ~ 6e-8 * 20 per 2D transform pair, with
-headroom for the mode coupling sums)."""
+Bars: FP64 path relative L2 error <= 1e-12 against the oracle; FP32 path <= 1e-6, the FP32 path's
+parity target (an FP32 FFT of length P carries a relative error of order eps32 * log2(P); the
+measured worst case over these cases is about 1.5e-7)."""
 import numpy as np
 import pytest
 import torch
@@ -15,7 +15,7 @@ from paper_1802_03061_amd import inputs
 pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-12
-TOL32 = 2e-6
+TOL32 = 1e-6
 
 
 @pytest.fixture(scope="module")

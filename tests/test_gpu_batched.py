@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle_ref
 from gpu_util import dev, host, relerr, say
 from oracle import krylov as kr
 from oracle import operator2d as op2
@@ -90,11 +91,14 @@ def test_batched_iteration_cap(rte):
     ctx.close()
 
 
+@pytest.mark.timeout(900)
 def test_batched_128_heterogeneous(rte):
     """128 isotropic problems, n drawn from {64, 128, 256, 512}, mu_s ~ U[0.5, 20],
     mu_a ~ U[0.01, 0.5], Gaussian-mixture sources, FP32 apply and FP64 refinement, tol 1e-8: all
-    converge; the oracle's FP64 FFT apply confirms the true residual of a sample (the largest
-    problem of every size and a few more), and a sample matches the single-problem solver."""
+    converge; the oracle's FP64 FFT apply confirms the true residual of every problem; for the
+    first and the hardest problem (largest mu_s / mu_t) of every size the solution matches the
+    oracle's FP64 reference solve element by element (relative L2 error <= 1e-6) and the
+    single-problem solver."""
     say("batched 128 heterogeneous")
     probs = inputs.batched_problems(count=128, seed=3)
     ctxs = [rte.Context(p["n"], mu_a=p["mu_a"], mu_s=p["mu_s"], L=0, prec=rte.PREC_FP32) for p in probs]
@@ -111,21 +115,32 @@ def test_batched_128_heterogeneous(rte):
         if idx:
             sample.add(max(idx, key=lambda i: probs[i]["mu_s"] / (probs[i]["mu_s"] + probs[i]["mu_a"])))
             sample.add(idx[0])
-    for i in sorted(sample):
-        p = probs[i]
+    worst = 0.0
+    for i, p in enumerate(probs):
         n = p["n"]
         h, mu_t = 1.0 / n, p["mu_a"] + p["mu_s"]
         f = host(fs[i])
-        spectra = op2.kernel_spectra(n, n, 0, h, mu_t)
-        b = op2.rhs(f, 0, h, mu_t, spectra=spectra)
-        r = b - op2.apply_fft(host(us[i]), 0, h, mu_t, p["mu_s"], np.ones(1), "A", spectra=spectra)
-        rr = np.linalg.norm(r) / np.linalg.norm(b)
-        u1, _ = ctxs[i].solve(fs[i], tol=1e-8)
-        e1 = relerr(host(us[i]), host(u1))
-        say(f"  problem {i}: n={n} mu_s={p['mu_s']:.2f} mu_a={p['mu_a']:.3f} iters={infos[i]['iterations']} "
-            f"oracle residual {rr:.2e}, vs single {e1:.2e}")
+        uu = host(us[i])
+        if i in sample:
+            ref = oracle_ref.Ref2D(f, n, 0, p["mu_a"], p["mu_s"], np.ones(1))
+            rr = ref.residual(uu)
+            e = relerr(uu, ref.u)
+            u1, _ = ctxs[i].solve(fs[i], tol=1e-8)
+            e1 = relerr(uu, host(u1))
+            say(f"  problem {i}: n={n} mu_s={p['mu_s']:.2f} mu_a={p['mu_a']:.3f} iters={infos[i]['iterations']} "
+                f"vs oracle {e:.2e} (reference {ref.iterations} it, {ref.seconds:.1f} s), oracle residual "
+                f"{rr:.2e}, vs single {e1:.2e}")
+            assert e <= 1e-6
+            assert e1 <= 1e-6
+        else:
+            spectra = op2.kernel_spectra(n, n, 0, h, mu_t, workers=oracle_ref.WORKERS)
+            b = op2.rhs(f, 0, h, mu_t, spectra=spectra, workers=oracle_ref.WORKERS)
+            r = b - op2.apply_fft(uu, 0, h, mu_t, p["mu_s"], np.ones(1), "A", spectra=spectra,
+                                  workers=oracle_ref.WORKERS)
+            rr = float(np.linalg.norm(r) / np.linalg.norm(b))
+        worst = max(worst, rr)
         assert rr <= 1.5e-8
-        assert e1 <= 1e-6
+    say(f"  largest oracle true residual over the 128 problems {worst:.2e}")
     for c in ctxs:
         c.close()
 

@@ -81,8 +81,8 @@ def test_self_cell_3d_vs_spherical_brute_force(mu_t):
 
 
 def test_self_cell_limits_printed_constants():
-    """mu_t -> 0: the mean of 1/(|S| r^{d-1}) over the cell ('evaluate the mean of the first part
-    by analysis', Sec. 2.3): 2D (2/pi) ln(1+sqrt 2) h; 3D (3 I/pi) h with
+    """mu_t -> 0: the mean of 1/(|S| r^{d-1}) over the cell, the part of the self-cell weight the
+    paper evaluates in closed form (Sec. 2.3): 2D (2/pi) ln(1+sqrt 2) h; 3D (3 I/pi) h with
     I = int_0^1 int_0^1 ds dt/(1+s^2+t^2).  Constants in tests/golden/self_cell_limits.json."""
     with open(os.path.join(GOLDEN, "self_cell_limits.json")) as fh:
         gold = json.load(fh)
@@ -311,6 +311,51 @@ def test_mus0_closed_form_first_order_3d():
     assert errs[-1] < 2e-2
     for a, b_ in zip(errs[:-1], errs[1:]):
         assert 1.5 < a / b_ < 2.8
+
+
+# ---------------------------------------------------------------- side of the scattering diagonal
+
+def test_scattering_diagonal_acts_on_the_input_modes():
+    """D multiplies the modes of the flux at the source point, before the transport kernel: the
+    scattering source at y has modes mu_s sigma_hat_k' u_k'(y) + f_k'(y), and K~ carries them to x
+    (eq. ani_2d_Fredholm, Sec. 3.1.1).  With sigma_hat = (1, 0, ..., 0) only mode 0 scatters, so
+    (i) mode 0 obeys the isotropic equation by itself and equals the stored 32^2 isotropic
+    solution, and (ii) every mode k is the transported isotropic source,
+    u_k = (K~ (mu_s u_0 + f) e_0)_k.  With D on the output side (A = I - D K~) both fail, which the
+    last part shows on a small grid."""
+    with open(os.path.join(GOLDEN, "iso32_summary.json")) as fh:
+        gold = json.load(fh)
+    w = inputs.workload("iso32")
+    n, L = 32, 2
+    h, mu_a, mu_s = 1.0 / n, w["mu_a"], w["mu_s"]
+    mu_t = mu_a + mu_s
+    sh = np.zeros(L + 1)
+    sh[0] = 1.0
+    b = op2.rhs(w["f"], L, h, mu_t)
+    u, _ = kr.gmres(lambda x: op2.apply_fft(x, L, h, mu_t, mu_s, sh), b, 1e-14)
+    u0 = u[L]
+    assert np.abs(u0.imag).max() <= 1e-14 * np.abs(u0).max()
+    assert abs(np.linalg.norm(u0.real) - gold["norm2"]) <= 1e-11 * gold["norm2"]
+    for (iy, ix), val in zip(gold["cells"], gold["values"]):
+        assert abs(u0[iy, ix].real - val) <= 1e-11 * abs(val)
+    src = op2.source_vector(mu_s * u0.real + w["f"], L)
+    want = op2.apply_fft(src, L, h, mu_t, 0.0, sh, op="KT")
+    assert np.linalg.norm(u - want) <= 1e-12 * np.linalg.norm(want)
+    assert np.linalg.norm(u[L + 1]) > 1e-2 * np.linalg.norm(u0)      # the check of k != 0 has teeth
+    # the output-side reading gives another solution on a small grid
+    m, Lm = 8, 1
+    hm = 1.0 / m
+    f = inputs.centred_gaussian_source(m)
+    shm = np.array([1.0, 0.0])
+    Kd = op2.dense_Ktilde(m, m, Lm, hm, mu_t)
+    d = np.repeat(op2.mode_scaling(Lm, mu_s, shm), m * m)
+    bm = op2.rhs(f, Lm, hm, mu_t, method="direct").reshape(-1)
+    u_in = np.linalg.solve(np.eye(Kd.shape[0]) - Kd * d[None, :], bm).reshape(2 * Lm + 1, m, m)
+    u_out = np.linalg.solve(np.eye(Kd.shape[0]) - d[:, None] * Kd, bm).reshape(2 * Lm + 1, m, m)
+    A_iso = op2.dense_A(m, m, 0, hm, mu_t, mu_s, np.array([1.0]))
+    u_iso = np.linalg.solve(A_iso, op2.rhs(f, 0, hm, mu_t, method="direct").reshape(-1)).reshape(m, m)
+    assert np.abs(u_in[Lm] - u_iso).max() <= 1e-13 * np.abs(u_iso).max()
+    assert np.abs(u_out[Lm] - u_iso).max() > 1e-4 * np.abs(u_iso).max()
 
 
 # ---------------------------------------------------------------- golden fixture --------------
