@@ -46,6 +46,20 @@ int rte_nn_set_params(rte_nn* nn, const float* src_dev);
 /* y = N(x) with the BF16 MFMA kernels; x, y: [batch][channels][H][W]. */
 int rte_nn_forward(rte_nn* nn, const float* x_dev, int batch, int H, int W, float* y_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops
+ * that forbid hipMalloc): y = N(x) exactly as rte_nn_forward computes it, with the intermediate
+ * activations in a fixed device array of RTE_NN_SCRATCH_BYTES that the library holds on each GPU
+ * (resolved when an rte_nn is created on that GPU) instead of buffers allocated on first use.
+ * It calls no hipMalloc, hipFree or other allocating routine.
+ *   Limit: batch * max(hidden, channels) * H * W <= RTE_NN_SCRATCH_BYTES / 4 floats for a
+ *   2-layer network, half that for deeper ones; larger inputs return RTE_EINVAL before any work.
+ *   Every call on one GPU (any rte_nn object) shares that GPU's array: calls that overlap in time
+ *   on one GPU, e.g. on two streams, race and give undefined results; calls ordered on one stream
+ *   are safe.  Nothing in the array needs to start at zero: every activation is written before it
+ *   is read.  Asynchronous on the object's stream. */
+#define RTE_NN_SCRATCH_BYTES (32UL << 20)
+int rte_nn_forward_noalloc(rte_nn* nn, const float* x_dev, int batch, int H, int W, float* y_dev);
+
 /* loss = mean_b w_b ||N(x_b) - t_b||^2 and its parameter gradient (kept inside the object for
  * rte_nn_adam_step, and copied to grad_dev in the packed layout if not NULL).  Synchronises the
  * stream to return the loss. */

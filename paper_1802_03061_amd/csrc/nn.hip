@@ -14,6 +14,7 @@
 // fixed order.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <random>
 #include <vector>
 
@@ -884,11 +885,44 @@ static bool valid_net(int C, int hidden, int layers) {
     return C >= 1 && C <= 17 && (C & 1) && (hidden == 16 || hidden == 32) && layers >= 2 && layers <= 8;
 }
 
+// ------------------------------------------------------------------ allocation-free forward ---
+// rte_nn_forward_noalloc keeps its intermediate activations in this device array instead of the
+// object's lazily allocated buffers.  Each GPU holds its own copy until the process ends.  Host
+// code never passes the array's name to a kernel: it uses the device address resolved per device
+// by scratch_resolve(), which rte_nn_create calls with the new object's device current.
+static __device__ __align__(256) float scratch[RTE_NN_SCRATCH_BYTES / sizeof(float)];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch_dev[kMaxScratchDevices] = {};
+
+static int scratch_resolve(int dev) {
+    if (dev < 0 || dev >= kMaxScratchDevices) return set_error(RTE_EUNSUPPORTED, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[dev]) return RTE_OK;
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return set_hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)", __FILE__,
+                             __LINE__);
+    }
+    g_scratch_dev[dev] = (float*)p;
+    return RTE_OK;
+}
+
+static float* scratch_ptr(int dev) {
+    if (dev < 0 || dev >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_dev[dev];
+}
+
 }  // namespace rte
 
 struct rte_nn {
     rte::NetShape sh;
     hipStream_t stream = nullptr;
+    int device = 0;                    // device current at creation (where the parameters live)
     float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
     unsigned short *wf = nullptr, *wb = nullptr;
     int step = 0;
@@ -1254,8 +1288,15 @@ int rte_nn_create(rte_nn** out, int C, int hidden, int layers, unsigned long lon
     if (!out) return set_error(RTE_EINVAL, "out is NULL");
     *out = nullptr;
     if (!valid_net(C, hidden, layers)) return set_error(RTE_EINVAL, "bad network shape");
+    int dev = 0;
+    RTE_HIP_TRY(hipGetDevice(&dev));
+    {
+        const int rs = scratch_resolve(dev);
+        if (rs) return rs;
+    }
     rte_nn* nn = new rte_nn();
     nn->sh.init(C, hidden, layers);
+    nn->device = dev;
     nn->stream = (hipStream_t)stream;
     nn->use_bias = use_bias != 0;
     const size_t np = nn->sh.nparam;
@@ -1319,6 +1360,29 @@ int rte_nn_forward(rte_nn* nn, const float* x, int B, int H, int W, float* y) {
     if (rc) return rc;
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? RTE_OK : set_hip_error(e, "rte_nn_forward", __FILE__, __LINE__);
+}
+
+int rte_nn_forward_noalloc(rte_nn* nn, const float* x, int B, int H, int W, float* y) {
+    if (!nn || !x || !y || B < 1 || H < 1 || W < 1) return set_error(RTE_EINVAL, "bad argument");
+    const NetShape& sh = nn->sh;
+    // layers 0..L-2 write intermediate activations, alternating between two halves of the array
+    const size_t per = (size_t)B * std::max(sh.hidden, sh.C) * H * W;
+    const size_t halves = sh.layers > 2 ? 2 : 1;
+    if (per > RTE_NN_SCRATCH_BYTES / sizeof(float) / halves)
+        return set_error(RTE_EINVAL, "batch*channels*H*W = %zu exceeds the allocation-free forward's limit of %zu "
+                         "floats per activation", per, (size_t)RTE_NN_SCRATCH_BYTES / sizeof(float) / halves);
+    float* base = scratch_ptr(nn->device);
+    if (!base) return set_error(RTE_EDEVICE, "scratch not resolved for device %d", nn->device);
+    const size_t half = RTE_NN_SCRATCH_BYTES / sizeof(float) / 2;
+    float* act[9];
+    for (int l = 1; l < sh.layers; ++l) act[l] = base + (size_t)((l - 1) & 1) * half;
+    act[sh.layers] = y;
+    act[0] = nullptr;
+    pack_all(sh, nn->p, nn->wf, nullptr, nn->stream);
+    int rc = net_forward(sh, nn->wf, nn->p, sh.boff, x, nullptr, act, nullptr, B, H, W, nn->stream);
+    if (rc) return rc;
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RTE_OK : set_hip_error(e, "rte_nn_forward_noalloc", __FILE__, __LINE__);
 }
 
 int rte_nn_loss_grad(rte_nn* nn, const float* x, const float* t, const float* w, int B, int H, int W, double* loss,

@@ -20,6 +20,7 @@ PREC_FP32, PREC_FP64 = 0, 1
 OP_A, OP_KT = 0, 1
 LAYOUT_MODES, LAYOUT_CHANNELS = 0, 1
 MAX_L = 8
+NN_SCRATCH_BYTES = 32 << 20      # RTE_NN_SCRATCH_BYTES of rte_nn.h
 
 
 class RteError(RuntimeError):
@@ -76,6 +77,7 @@ def load():
         "rte_nn_get_params": (I, [P, P]),
         "rte_nn_set_params": (I, [P, P]),
         "rte_nn_forward": (I, [P, P, I, I, I, P]),
+        "rte_nn_forward_noalloc": (I, [P, P, I, I, I, P]),
         "rte_nn_loss_grad": (I, [P, P, P, P, I, I, I, C.POINTER(D), P]),
         "rte_nn_adam_step": (I, [P, C.c_float]),
         "rte_pc_make_pairs": (I, [P, P, P, P, I, I, P, P, P]),
@@ -363,6 +365,13 @@ class Net:
         y = torch.empty((B, self.channels, H, W), dtype=torch.float32, device=x.device)
         _check(load().rte_nn_forward(self._h, _ptr(x, torch.float32), B, H, W, C.c_void_p(y.data_ptr())))
         return y
+
+    def forward_noalloc(self, x, out):
+        """y = N(x) into the caller's `out`, with the library's fixed per-GPU activation array."""
+        B, Cc, H, W = x.shape
+        _check(load().rte_nn_forward_noalloc(self._h, _ptr(x, torch.float32), B, H, W,
+                                             _ptr(out, torch.float32, B * self.channels * H * W)))
+        return out
 
     def loss_grad(self, x, t, w, want_grad=False):
         B, Cc, H, W = x.shape
