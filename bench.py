@@ -1,6 +1,6 @@
 """Benchmark of the RTE solver on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload hg512|batched|iso3d|diff256]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload hg512|batched|iso3d|diff256|iso32]
 
 Default workload (hg512): solve time to relative residual 1e-8 on the 512^2, L = 8
 Henyey-Greenstein problem.  One step = one full solve (right-hand side b = K~ g by an FP64 apply,
@@ -19,10 +19,13 @@ Other workloads (same JSON shape):
            FFT on the 256^3 padded grid, FP64 GMRES, tol 1e-8
   diff256  like hg512 on the diffusion-regime problem (256^2, HG g = 0.3, L = 4, mu_s = 50,
            mu_a = 0.01)
+  iso32    the small isotropic problem (32^2, mu_a = 0.1, mu_s = 1, centred Gaussian), FP64
+           throughout, tol 1e-10 (latency-bound)
 
 Also reported: operator applies/s, per-pass apply times from HIP events on the context stream with
-the HBM roofline of the dominant kernel, the measured copy bandwidth, and the CPU oracle timed on
-a bounded sample.
+the HBM roofline of the dominant kernel, the measured copy bandwidth, the error of the GPU solution
+against an FP64 reference solve of the CPU oracle, and the oracle itself timed on the host as the
+CPU baseline (a solve of the same problem to the same tolerance, on a bounded sample for the batch).
 """
 from __future__ import annotations
 
@@ -123,28 +126,19 @@ def padded(n: int) -> int:
     return P
 
 
-def apply_pass_bytes(n: int, L: int, vbytes: int = 8) -> dict:
-    """Algorithmic HBM bytes of one FP32 2D apply on channel vectors of vbytes per value (8: the
-    FP64 vectors of the API; 4: the solver's FP32 basis) (C = 2L+1 channels, n^2 cells, padded size
-    P, x-spectrum of P/2 packed columns): pass A reads x and writes the complex64 x-spectrum; pass
-    B reads and writes that spectrum and reads the quarter kernel spectra [2L+1][P/2+1][P/2+1];
-    pass C reads the spectrum and x and writes y."""
+def apply_pass_bytes(n: int, L: int, vbytes: int = 8, cbytes: int = 8) -> dict:
+    """Algorithmic HBM bytes of one 2D apply on channel vectors of vbytes per value (8: the FP64
+    vectors of the API; 4: the solver's FP32 basis) with spectra of cbytes per complex value (8 for
+    the FP32 apply, 16 for the FP64 apply) (C = 2L+1 channels, n^2 cells, padded size P, x-spectrum
+    of P/2 packed columns): pass A reads x and writes the x-spectrum; pass B reads and writes that
+    spectrum and reads the quarter kernel spectra [2L+1][P/2+1][P/2+1]; pass C reads the spectrum
+    and x and writes y."""
     C = 2 * L + 1
     N = n * n
     H = padded(n) // 2
-    spec = 8 * C * H * n
-    kern = 8 * (2 * L + 1) * (H + 1) * (H + 1)
+    spec = cbytes * C * H * n
+    kern = cbytes * (2 * L + 1) * (H + 1) * (H + 1)
     return {"A": vbytes * C * N + spec, "B": 2 * spec + kern, "C": spec + 2 * vbytes * C * N}
-
-
-def model_3pass_bytes(n: int, L: int) -> int:
-    """Bytes of the 3-pass model of one FP32 2D apply on complex mode vectors, the reference
-    denominator for the apply's HBM fraction: M = 2L+1 modes, N = n^2 cells, P = 4N padded cells;
-    pass A 8MN -> 16MN, pass B 16MN plus the 2L+1 kernel spectra (8P each) -> 16MN, pass C 16MN
-    plus 8MN -> 8MN, i.e. 88MN + 8(2L+1)P.  This design's own algorithmic bytes (apply_pass_bytes)
-    are lower: real-to-complex x transforms and quarter-stored spectra."""
-    M, N = 2 * L + 1, n * n
-    return 88 * M * N + 8 * (2 * L + 1) * 4 * N
 
 
 def apply3d_pass_bytes(n: int) -> dict:
@@ -178,58 +172,136 @@ def copy_peak_gbs(torch, mib: int = 1024, reps: int = 10) -> float:
     return 2 * mib * 2 ** 20 / (ms * 1e-3) / 1e9
 
 
-def roofline(ctx, rte, pb: dict, reps: int, names) -> dict:
-    """Per-pass FP32 apply times (HIP events on the context stream) and the dominant pass against
-    8 TB/s."""
-    ms_apply, ms_pass = ctx.time_apply(rte.OP_A, rte.PREC_FP32, reps=reps)
+def roofline(ctx, rte, pb: dict, reps: int, names, prec=None) -> dict:
+    """Per-pass apply times (HIP events on the context stream) and the dominant pass against
+    8 TB/s; apply_hbm_fraction is the whole apply's algorithmic bytes over its time."""
+    prec = rte.PREC_FP32 if prec is None else prec
+    ms_apply, ms_pass = ctx.time_apply(rte.OP_A, prec, reps=reps)
     ms_pass = ms_pass[:len(names)]
     dom = int(np.argmax(ms_pass))
     achieved = pb[names[dom]] / (ms_pass[dom] * 1e-3) / 1e9
     return {"ms_apply": ms_apply, "passes": dict(zip(names, ms_pass)),
             "roofline": {"bound": "hbm", "kernel": f"apply pass {names[dom]}", "achieved": achieved,
-                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "bytes_per_launch": pb[names[dom]], "ms_per_launch": ms_pass[dom]},
             "apply_hbm_fraction": sum(pb.values()) / (ms_apply * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
-def cpu_baseline_2d(w, gpu_applies_per_solve: float) -> dict:
-    """The oracle's FP64 FFT apply (scipy.fft, as written) timed on the host on a bounded sample:
-    two applies of the workload's operator after its spectra are built; solves/s is scaled by the
-    applies one GPU solve used."""
+# ------------------------------------------------------------------ the CPU oracle beside it ---
+
+def oracle_threads() -> int:
+    """Host threads given to the oracle's FFTs and mode sums: the host's cores, at most 16 (one
+    GPU's share of the box)."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def host_cpu() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
+
+
+def relerr(a, b) -> float:
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def oracle_2d(w, tol: float, gpu_u: dict) -> tuple:
+    """The oracle's FP64 solve of the workload's seed-0 problem (oracle.operator2d FFT apply by
+    circulant embedding inside oracle.krylov.gmres, on the host's threads): timed to the GPU
+    solve's tolerance as the CPU baseline, then continued from scratch to 1e-13 as the reference
+    that every GPU solution in gpu_u is compared with (relative L2 error over all modes).  Also
+    one apply on a single thread."""
+    from oracle import krylov as kr
     from oracle import operator2d as op2
-    from paper_1802_03061_amd import inputs
     n, L = w["n"], w["L"]
     h, mu_t = 1.0 / n, w["mu_a"] + w["mu_s"]
+    nt = oracle_threads()
     t0 = time.perf_counter()
-    spectra = op2.kernel_spectra(n, n, L, h, mu_t)
+    spectra = op2.kernel_spectra(n, n, L, h, mu_t, workers=nt)
     t_pre = time.perf_counter() - t0
-    u = inputs.random_conj_symmetric_modes(np.random.default_rng(0), L, n)
-    reps = 2
+    apply = lambda u, k=nt: op2.apply_fft(u, L, h, mu_t, w["mu_s"], w["sigma_hat"], "A", spectra=spectra, workers=k)
     t0 = time.perf_counter()
-    for _ in range(reps):
-        op2.apply_fft(u, L, h, mu_t, w["mu_s"], w["sigma_hat"], "A", spectra=spectra)
-    t_apply = (time.perf_counter() - t0) / reps
-    return {
-        "value": 1.0 / (t_apply * gpu_applies_per_solve),
-        "unit": "solves/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"{reps} FP64 FFT applies of the {n}^2 L={L} operator (oracle.operator2d.apply_fft, "
-                   f"numpy/scipy single thread) at {t_apply:.3f} s each, scaled by the "
-                   f"{gpu_applies_per_solve:.1f} applies per GPU solve; spectra precompute "
-                   f"{t_pre:.1f} s excluded"),
-        "applies_per_s": 1.0 / t_apply,
-    }
+    b = op2.rhs(w["f"], L, h, mu_t, spectra=spectra, workers=nt)
+    x, hist = kr.gmres(apply, b, tol, 1000)
+    t_sol = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    apply(x, 1)
+    t_apply1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ref, rhist = kr.gmres(apply, b, 1e-13, 1000)
+    t_ref = time.perf_counter() - t0
+    nb = np.linalg.norm(b)
+    cpu = {"value": 1.0 / t_sol, "unit": "solves/s", "cores": nt, "kind": "oracle",
+           "sample": (f"one FP64 solve of the seed-0 source to relative residual {tol:g} "
+                      f"(oracle.krylov.gmres over oracle.operator2d.apply_fft, {nt} threads): "
+                      f"{len(hist) - 1} iterations, {t_sol:.2f} s; kernel spectra {t_pre:.2f} s excluded"),
+           "t_pre_s": t_pre, "t_sol_s": t_sol, "iterations": len(hist) - 1,
+           "relres_true": float(np.linalg.norm(b - apply(x)) / nb),
+           "single_thread_apply_s": t_apply1, "host": host_cpu()}
+    err = {"reference": {"what": "oracle FP64 GMRES over the FFT apply to 1e-13", "iterations": len(rhist) - 1,
+                         "relres_true": float(np.linalg.norm(b - apply(ref)) / nb), "seconds": t_ref},
+           "seed0_cpu_solve": relerr(x, ref)}
+    for k, u in gpu_u.items():
+        err[k] = relerr(u, ref)
+        err[k + "_mode0"] = relerr(u[L], ref[L])
+    return cpu, err
 
 
-def timed_solves(ctx, fs, steps, warmup, torch):
+def oracle_3d(w, tol: float, gpu_u: dict) -> tuple:
+    """As oracle_2d for the 3D isotropic problem (oracle.operator3d)."""
+    from oracle import krylov as kr
+    from oracle import operator3d as op3
+    n = w["n"]
+    h, mu_t = 1.0 / n, w["mu_a"] + w["mu_s"]
+    nt = oracle_threads()
+    t0 = time.perf_counter()
+    spec = op3.kernel_spectrum(n, n, n, h, mu_t, workers=nt)
+    t_pre = time.perf_counter() - t0
+    apply = lambda u, k=nt: op3.apply_fft(u, h, mu_t, w["mu_s"], "A", spectrum=spec, workers=k)
+    t0 = time.perf_counter()
+    b = op3.apply_fft(w["f"], h, mu_t, 0.0, "KT", spectrum=spec, workers=nt)
+    x, hist = kr.gmres(apply, b, tol, 1000)
+    t_sol = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    apply(x, 1)
+    t_apply1 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ref, rhist = kr.gmres(apply, b, 1e-13, 1000)
+    t_ref = time.perf_counter() - t0
+    nb = np.linalg.norm(b)
+    cpu = {"value": 1.0 / t_sol, "unit": "solves/s", "cores": nt, "kind": "oracle",
+           "sample": (f"one FP64 solve of the seed-0 source to relative residual {tol:g} "
+                      f"(oracle.krylov.gmres over oracle.operator3d.apply_fft, {nt} threads): "
+                      f"{len(hist) - 1} iterations, {t_sol:.2f} s; kernel spectrum {t_pre:.2f} s excluded"),
+           "t_pre_s": t_pre, "t_sol_s": t_sol, "iterations": len(hist) - 1,
+           "relres_true": float(np.linalg.norm(b - apply(x)) / nb),
+           "single_thread_apply_s": t_apply1, "host": host_cpu()}
+    err = {"reference": {"what": "oracle FP64 GMRES over the FFT apply to 1e-13", "iterations": len(rhist) - 1,
+                         "relres_true": float(np.linalg.norm(b - apply(ref)) / nb), "seconds": t_ref},
+           "seed0_cpu_solve": relerr(x, ref)}
+    for k, u in gpu_u.items():
+        err[k] = relerr(u, ref)
+    return cpu, err
+
+
+def timed_solves(ctx, fs, steps, warmup, torch, tol=1e-8):
     nsrc = len(fs)
     for i in range(warmup):
-        ctx.solve(fs[i % nsrc], tol=1e-8)
+        ctx.solve(fs[i % nsrc], tol=tol)
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
     for i in range(steps):
-        _, info = ctx.solve(fs[i % nsrc], tol=1e-8)
+        _, info = ctx.solve(fs[i % nsrc], tol=tol)
         infos.append(info)
     torch.cuda.synchronize()
     ms = 1000.0 * (time.perf_counter() - t0) / steps
@@ -239,6 +311,12 @@ def timed_solves(ctx, fs, steps, warmup, torch):
             "cycles": float(np.mean([i["cycles"] for i in infos])),
             "pc_fallback": int(max(i["pc_fallback"] for i in infos)),
             "max_relres_true": float(max(i["relres_true"] for i in infos))}
+
+
+def seed0_solution(ctx, f, tol=1e-8):
+    """The GPU solution of the seed-0 source, as complex modes on the host (untimed)."""
+    u, _ = ctx.solve(f, tol=tol)
+    return u.cpu().numpy()
 
 
 def scattering_timing(ctx, f, torch, ntheta: int = 64, reps: int = 20) -> dict:
@@ -271,6 +349,7 @@ def bench_pc_workload(args, torch, rte, name, mu_s):
     torch.cuda.synchronize()
     plain = timed_solves(ctx, fs, args.steps, args.warmup, torch)
     plain["label"] = "plain GMRES"
+    sols = {"plain": seed0_solution(ctx, fs[0])}
     t_setup_ms = ctx.solve(fs[0], tol=1e-8)[1]["t_setup_ms"]
     pc = None
     if not args.no_pc:
@@ -279,9 +358,11 @@ def bench_pc_workload(args, torch, rte, name, mu_s):
         ctx.attach_pc(net.params(), hidden=meta["hidden"], layers=meta["layers"], factor=F)
         pc = timed_solves(ctx, fs, args.steps, args.warmup, torch)
         pc["label"] = "learned-PC FGMRES"
+        sols["learned_pc"] = seed0_solution(ctx, fs[0])
         # the same solves with the inner basis stored in FP32 (FP64 sums; an option, not the default)
         ctx.set_opts(basis_fp32=1)
         pc32 = timed_solves(ctx, fs, args.steps, args.warmup, torch)
+        sols["learned_pc_basis_fp32"] = seed0_solution(ctx, fs[0])
         ctx.set_opts()
         pc["basis_fp32_option"] = {k: pc32[k] for k in ("ms_per_solve", "solves_per_s", "iterations",
                                                           "max_relres_true")}
@@ -294,8 +375,8 @@ def bench_pc_workload(args, torch, rte, name, mu_s):
     post = scattering_timing(ctx, fs[0], torch)
     rf = roofline(ctx, rte, apply_pass_bytes(n, L), args.apply_reps, ["A", "B", "C"])
     ms64, pass64 = ctx.time_apply(rte.OP_A, rte.PREC_FP64, reps=max(5, args.apply_reps // 5))
-    variants = {name: [list(ctx.get_variant(p, q)) for q in range(3)]
-                for name, p in (("fp32", rte.PREC_FP32), ("fp64", rte.PREC_FP64))}
+    variants = {name_: [list(ctx.get_variant(p, q)) for q in range(3)]
+                for name_, p in (("fp32", rte.PREC_FP32), ("fp64", rte.PREC_FP64))}
     dom = rf["roofline"]["kernel"].split()[-1]
     if name == "hg512":
         rf["roofline"]["traffic"] = traffic_for(dom, variants["fp32"])
@@ -322,21 +403,21 @@ def bench_pc_workload(args, torch, rte, name, mu_s):
         "apply_ms": {"fp32_total": rf["ms_apply"], "fp32_passes": rf["passes"], "fp64_total": ms64,
                      "fp64_passes": dict(zip("ABC", pass64[:3]))},
         "apply_hbm_fraction": rf["apply_hbm_fraction"], "apply_bytes": apply_pass_bytes(n, L),
-        "apply_hbm_fraction_3pass_model": model_3pass_bytes(n, L) / (rf["ms_apply"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "kernel_variants": variants,
         "scattering_term": post,
         "roofline": rf["roofline"],
         "roofline_alu_pass_B": {"bound": "alu", "achieved": ach, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                                 "frac": ach / FP32_VECTOR_PEAK_TFLOPS, "flops": flops_b},
     }
-    return out, ctx, base, plain["applies"]
+    return out, ctx, base, sols
 
 
-def bench_batched(args, torch, rte):
+def bench_batched(args, torch, rte, with_oracle: bool):
     from paper_1802_03061_amd import inputs
     probs = inputs.batched_problems(count=128, seed=3)
     ctxs = [rte.Context(p["n"], mu_a=p["mu_a"], mu_s=p["mu_s"], L=0, prec=rte.PREC_FP32) for p in probs]
-    fs = [torch.from_numpy(inputs.gaussian_mixture_source(p["n"], p["params"])).cuda() for p in probs]
+    srcs = [inputs.gaussian_mixture_source(p["n"], p["params"]) for p in probs]
+    fs = [torch.from_numpy(f).cuda() for f in srcs]
     torch.cuda.synchronize()
     tols = [1e-8] * len(ctxs)
     for _ in range(args.warmup):
@@ -344,13 +425,22 @@ def bench_batched(args, torch, rte):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, infos, _ = rte.solve_batched(ctxs, fs, tols)
+        us, infos, _ = rte.solve_batched(ctxs, fs, tols)
     torch.cuda.synchronize()
     ms = 1000.0 * (time.perf_counter() - t0) / args.steps
     its = [i["iterations"] for i in infos]
     cells = sum(p["n"] ** 2 for p in probs)
-    big = next(i for i, p in enumerate(probs) if p["n"] == 512)
-    rf = roofline(ctxs[big], rte, apply_pass_bytes(512, 0), args.apply_reps, ["A", "B", "C"])
+    # the batched apply of one inner iteration, launch by launch, against the aggregate algorithmic
+    # bytes of the problems each launch covers (FP32 apply, FP64 basis vectors)
+    ms_tot, launches = rte.time_batched_apply(ctxs, reps=args.apply_reps)
+    lrows = []
+    for ps, px, py, lms in launches:
+        members = [p for p in probs if padded(p["n"]) == px]
+        nbytes = sum(apply_pass_bytes(p["n"], 0)["ABC"[ps]] for p in members)
+        lrows.append({"pass": "ABC"[ps], "padded": px, "problems": len(members), "ms": lms, "bytes": nbytes,
+                      "GBs": nbytes / (lms * 1e-3) / 1e9})
+    dom = max(lrows, key=lambda r: r["ms"])
+    total_bytes = sum(r["bytes"] for r in lrows)
     out = {
         "value": len(ctxs) * 1000.0 / ms, "unit": "solves/s", "ms_per_step": ms, "dtype": "f32 apply + f64 krylov",
         "config": {"workload": ("128 batched 2D isotropic solves, n from {64,128,256,512}, mu_s~U[0.5,20], "
@@ -359,13 +449,69 @@ def bench_batched(args, torch, rte):
         "solve": {"iterations_min": min(its), "iterations_max": max(its), "iterations_mean": float(np.mean(its)),
                   "max_relres_true": max(i["relres_true"] for i in infos),
                   "max_cycles": max(i["cycles"] for i in infos)},
-        "applies_per_s": None,
-        "apply_ms": {"iso512_fp32_total": rf["ms_apply"], "iso512_fp32_passes": rf["passes"]},
-        "roofline": rf["roofline"],
+        "applies_per_s": 1000.0 / ms_tot,
+        "batched_apply": {"ms_total": ms_tot, "launches": lrows, "bytes": total_bytes,
+                          "hbm_fraction": total_bytes / (ms_tot * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "roofline": {"bound": "hbm", "kernel": f"batched apply pass {dom['pass']} (padded {dom['padded']}, "
+                                               f"{dom['problems']} problems)",
+                     "achieved": dom["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["GBs"] / HBM_PEAK_GBS,
+                     "traffic": None, "bytes_per_launch": dom["bytes"], "ms_per_launch": dom["ms"]},
     }
+    cpu = None
+    if with_oracle:
+        cpu, err = oracle_batched(probs, srcs, [u.cpu().numpy() for u in us])
+        out["error_vs_oracle"] = err
     for c in ctxs:
         c.close()
-    return out
+    return out, cpu
+
+
+def oracle_batched(probs, srcs, gpu_u) -> tuple:
+    """CPU baseline on a bounded sample (the first 8 problems of the batch, each solved by the
+    oracle to 1e-8 on the host's threads, scaled to solves/s), and the errors against FP64
+    reference solves (1e-13) of the first and the hardest (largest mu_s / mu_t) problem of every
+    grid size."""
+    from oracle import krylov as kr
+    from oracle import operator2d as op2
+    nt = oracle_threads()
+    one = np.ones(1)
+
+    def setup(i):
+        p = probs[i]
+        n = p["n"]
+        h, mu_t = 1.0 / n, p["mu_a"] + p["mu_s"]
+        sp = op2.kernel_spectra(n, n, 0, h, mu_t, workers=nt)
+        apply = lambda u: op2.apply_fft(u, 0, h, mu_t, p["mu_s"], one, "A", spectra=sp, workers=nt)
+        return apply, lambda: op2.rhs(srcs[i], 0, h, mu_t, spectra=sp, workers=nt)
+    sample = list(range(8))
+    t_sol = 0.0
+    its = []
+    for i in sample:
+        apply, rhs = setup(i)
+        t0 = time.perf_counter()
+        x, hist = kr.gmres(apply, rhs(), 1e-8, 1000)
+        t_sol += time.perf_counter() - t0
+        its.append(len(hist) - 1)
+    cpu = {"value": len(sample) / t_sol, "unit": "solves/s", "cores": nt, "kind": "oracle",
+           "sample": (f"the first {len(sample)} problems of the batch (n = "
+                      f"{','.join(str(probs[i]['n']) for i in sample)}), each an FP64 oracle solve to 1e-8 "
+                      f"(oracle.krylov.gmres over oracle.operator2d.apply_fft, {nt} threads): {t_sol:.2f} s in all, "
+                      f"{sum(its)} iterations; kernel spectra excluded"),
+           "t_sol_s": t_sol, "host": host_cpu()}
+    check = set()
+    for n in sorted({p["n"] for p in probs}):
+        idx = [i for i, p in enumerate(probs) if p["n"] == n]
+        if idx:
+            check.add(idx[0])
+            check.add(max(idx, key=lambda i: probs[i]["mu_s"] / (probs[i]["mu_s"] + probs[i]["mu_a"])))
+    errs = {}
+    for i in sorted(check):
+        apply, rhs = setup(i)
+        ref, _ = kr.gmres(apply, rhs(), 1e-13, 1000)
+        errs[str(i)] = relerr(gpu_u[i], ref)
+    err = {"reference": "oracle FP64 GMRES over the FFT apply to 1e-13, per problem",
+           "problems": errs, "max": max(errs.values())}
+    return cpu, err
 
 
 def bench_iso3d(args, torch, rte, mu_s):
@@ -376,6 +522,7 @@ def bench_iso3d(args, torch, rte, mu_s):
     fs = [torch.from_numpy(inputs.workload("iso3d", seed=s, mu_s=mu_s)["f"]).cuda() for s in range(max(args.steps, 1))]
     torch.cuda.synchronize()
     r = timed_solves(ctx, fs, args.steps, args.warmup, torch)
+    sols = {"gpu": seed0_solution(ctx, fs[0]).reshape(n, n, n).real}
     pb = apply3d_pass_bytes(n)
     rf = roofline(ctx, rte, pb, args.apply_reps, ["A", "B", "C", "D", "E"])
     out = {
@@ -387,7 +534,52 @@ def bench_iso3d(args, torch, rte, mu_s):
         "apply_ms": {"fp32_total": rf["ms_apply"], "fp32_passes": rf["passes"]},
         "apply_hbm_fraction": rf["apply_hbm_fraction"], "apply_bytes": pb, "roofline": rf["roofline"],
     }
-    return out, ctx
+    return out, ctx, w, sols
+
+
+def bench_iso32(args, torch, rte, with_oracle: bool):
+    """The small isotropic problem in FP64 to 1e-10: every step solves the same deterministic
+    source; the reference is the oracle's dense LU solution."""
+    from paper_1802_03061_amd import inputs
+    w = inputs.workload("iso32")
+    n = w["n"]
+    ctx = rte.Context(n, mu_a=w["mu_a"], mu_s=w["mu_s"], L=0, prec=rte.PREC_FP64)
+    fs = [torch.from_numpy(w["f"]).cuda()]
+    torch.cuda.synchronize()
+    r = timed_solves(ctx, fs, args.steps, args.warmup, torch, tol=1e-10)
+    u = seed0_solution(ctx, fs[0], tol=1e-10)
+    rf = roofline(ctx, rte, apply_pass_bytes(n, 0, 8, 16), args.apply_reps, ["A", "B", "C"], prec=rte.PREC_FP64)
+    out = {
+        "value": r["solves_per_s"], "unit": "solves/s", "ms_per_step": r["ms_per_solve"], "dtype": "f64",
+        "config": {"workload": "2D isotropic 32^2, mu_a=0.1, mu_s=1, centred Gaussian source (width 0.1), FP64, "
+                               "tol 1e-10 (latency-bound)", "n": n, "tol": 1e-10},
+        "solve": r, "applies_per_s": 1000.0 / rf["ms_apply"],
+        "apply_ms": {"fp64_total": rf["ms_apply"], "fp64_passes": rf["passes"]},
+        "apply_hbm_fraction": rf["apply_hbm_fraction"], "roofline": rf["roofline"],
+    }
+    ctx.close()
+    cpu = None
+    if with_oracle:
+        from oracle import krylov as kr
+        from oracle import operator2d as op2
+        h, mu_t = 1.0 / n, w["mu_a"] + w["mu_s"]
+        A = op2.dense_A(n, n, 0, h, mu_t, w["mu_s"], w["sigma_hat"])
+        b = op2.rhs(w["f"], 0, h, mu_t, method="direct")
+        ref = kr.solve_dense(A, b.reshape(-1)).reshape(b.shape)
+        out["error_vs_oracle"] = {"reference": "oracle dense LU", "gpu": relerr(u, ref)}
+        sp = op2.kernel_spectra(n, n, 0, h, mu_t)
+        apply = lambda x: op2.apply_fft(x, 0, h, mu_t, w["mu_s"], w["sigma_hat"], "A", spectra=sp, workers=1)
+        reps = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 5.0:
+            x, hist = kr.gmres(apply, op2.rhs(w["f"], 0, h, mu_t, spectra=sp), 1e-10, 1000)
+            reps += 1
+        t = (time.perf_counter() - t0) / reps
+        cpu = {"value": 1.0 / t, "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": (f"{reps} FP64 oracle solves to 1e-10 (oracle.krylov.gmres over oracle.operator2d.apply_fft, "
+                          f"one thread), {len(hist) - 1} iterations each; kernel spectra excluded"),
+               "t_sol_s": t, "host": host_cpu()}
+    return out, cpu
 
 
 def main():
@@ -395,10 +587,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="hg512", choices=["hg512", "batched", "iso3d", "diff256"])
+    ap.add_argument("--workload", default="hg512", choices=["hg512", "batched", "iso3d", "diff256", "iso32"])
     ap.add_argument("--mu-s", type=float, default=None)
     ap.add_argument("--apply-reps", type=int, default=50)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the CPU oracle (its timed solve and the reference solve for the error)")
     ap.add_argument("--no-pc", action="store_true", help="time plain GMRES only")
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -426,18 +619,23 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     rank = int(os.environ.get("RANK", "0"))
+    oracle_on = rank == 0 and not args.no_cpu_baseline
     cpu = None
     if args.workload in ("hg512", "diff256"):
         mu_s = args.mu_s if args.mu_s is not None else (10.0 if args.workload == "hg512" else 50.0)
-        out, ctx, base, applies = bench_pc_workload(args, torch, rte, args.workload, mu_s)
-        if rank == 0 and not args.no_cpu_baseline:
-            cpu = cpu_baseline_2d(base, applies)
+        out, ctx, base, sols = bench_pc_workload(args, torch, rte, args.workload, mu_s)
         ctx.close()
+        if oracle_on:
+            cpu, out["error_vs_oracle"] = oracle_2d(base, 1e-8, sols)
     elif args.workload == "batched":
-        out = bench_batched(args, torch, rte)
+        out, cpu = bench_batched(args, torch, rte, oracle_on)
+    elif args.workload == "iso32":
+        out, cpu = bench_iso32(args, torch, rte, oracle_on)
     else:
-        out, ctx = bench_iso3d(args, torch, rte, args.mu_s if args.mu_s is not None else 10.0)
+        out, ctx, w, sols = bench_iso3d(args, torch, rte, args.mu_s if args.mu_s is not None else 10.0)
         ctx.close()
+        if oracle_on:
+            cpu, out["error_vs_oracle"] = oracle_3d(w, 1e-8, sols)
     line = {"metric": METRIC if args.workload == "hg512" else f"solves/s ({args.workload})"}
     line.update({"value": out.pop("value"), "unit": out.pop("unit"), "n_gpus": 1, "steps": args.steps,
                  "warmup": args.warmup, "ms_per_step": out.pop("ms_per_step"), "higher_is_better": True,

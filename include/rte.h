@@ -182,6 +182,18 @@ int rte_pc_attach(rte_ctx* ctx, const float* weights_dev, int hidden, int layers
  * 3D: five passes; unused entries 0).  Input/output are internal buffers. */
 int rte_time_apply(rte_ctx* ctx, int op, int prec, int reps, double* ms_total, double* ms_pass);
 
+/* Time the batched apply of one inner iteration of rte_solve_batched over the same contexts (in
+ * the same order; a batch plan must exist, i.e. rte_solve_batched ran on them): every problem
+ * active, one launch per pass (A, B, C) and padded grid size, `reps` times, each launch bracketed
+ * by HIP events on the batch stream.  Outputs: *ms_total the average time of the whole batched
+ * apply; for launch i < min(*n_launch, max_launch): ms_launch[i] its average time, launch_pass[i]
+ * (0 = A, 1 = B, 2 = C) and launch_px[i], launch_py[i] the padded grid of the problems it covers.
+ * Launches are ordered pass A over the size classes, then B, then C; size classes in the order
+ * their first problem appears.  Overwrites the first two basis columns of each problem.
+ * RTE_EINVAL without a plan for these contexts.  Synchronises the batch stream. */
+int rte_time_batched_apply(int count, rte_ctx* const* ctxs, int reps, double* ms_total, int max_launch,
+                           int* n_launch, double* ms_launch, int* launch_pass, int* launch_px, int* launch_py);
+
 /* Kernel variants of the 2D apply (pass 0 = A, 1 = B, 2 = C; prec = RTE_PREC_FP32 or
  * RTE_PREC_FP64 apply).  Variants differ only in tiling (row tiles, thread counts, FFT grouping):
  * the same arithmetic, equal results up to rounding.  rte_setup of a 2D context with n_x or n_y >= 128 picks the

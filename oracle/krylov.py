@@ -24,7 +24,7 @@ def gmres(matvec, b: np.ndarray, tol: float = 1e-13, maxiter: int = 200):
     b may have any shape; matvec maps arrays of that shape to that shape.  Real b gives real
     arithmetic throughout, complex b complex arithmetic.  Each new Arnoldi vector is
     orthogonalised against the basis by classical Gram-Schmidt applied twice (the projection
-    coefficients h = V^H w are formed as one matrix-vector product with the stored basis, then
+    coefficients h = V^H w are formed as matrix-vector products with the stored basis, then
     w <- w - V h; the two passes' coefficients add up to the Hessenberg column), which is as
     orthogonal as modified Gram-Schmidt twice and lets the basis products run as library
     matrix-vector products on large vectors."""
@@ -34,8 +34,20 @@ def gmres(matvec, b: np.ndarray, tol: float = 1e-13, maxiter: int = 200):
     beta = np.linalg.norm(bf)
     if beta == 0.0:
         return np.zeros(shape, dtype=dtype), [0.0]
-    V = np.empty((maxiter + 1, bf.size), dtype=dtype)     # rows are the basis vectors
-    V[0] = bf / beta
+    # the basis is stored in blocks of rows, allocated as the iteration reaches them
+    BLK = 16
+    blocks = []
+
+    def row(i):
+        if i // BLK == len(blocks):
+            blocks.append(np.empty((BLK, bf.size), dtype=dtype))
+        return blocks[i // BLK][i % BLK]
+
+    def rows(n):     # the first n basis vectors, block by block
+        for q in range((n + BLK - 1) // BLK):
+            yield blocks[q][:min(BLK, n - q * BLK)]
+
+    row(0)[:] = bf / beta
     H = np.zeros((maxiter + 1, maxiter), dtype=dtype)
     cs = np.zeros(maxiter, dtype=dtype)
     sn = np.zeros(maxiter, dtype=dtype)
@@ -44,12 +56,13 @@ def gmres(matvec, b: np.ndarray, tol: float = 1e-13, maxiter: int = 200):
     hist = [1.0]
     j_end = 0
     for j in range(maxiter):
-        w = np.array(matvec(V[j].reshape(shape)), dtype=dtype).reshape(-1)
-        Vj = V[:j + 1]
+        w = np.array(matvec(row(j).reshape(shape)), dtype=dtype).reshape(-1)
         for _ in range(2):                      # classical Gram-Schmidt, twice
-            hc = np.conj(Vj @ np.conj(w))        # h_i = <V_i, w> = sum conj(V_i) w
+            wc = np.conj(w)
+            hc = np.concatenate([np.conj(Vb @ wc) for Vb in rows(j + 1)])   # h_i = <V_i, w>
             H[:j + 1, j] += hc
-            w -= hc @ Vj
+            for q, Vb in enumerate(rows(j + 1)):
+                w -= hc[q * BLK:q * BLK + Vb.shape[0]] @ Vb
         H[j + 1, j] = np.linalg.norm(w)
         # previous rotations
         for i in range(j):
@@ -76,9 +89,11 @@ def gmres(matvec, b: np.ndarray, tol: float = 1e-13, maxiter: int = 200):
         hnext = np.linalg.norm(w)
         if rel <= tol or hnext == 0.0 or j + 1 == maxiter:
             break
-        V[j + 1] = w / hnext
+        row(j + 1)[:] = w / hnext
     y = np.linalg.solve(np.triu(H[:j_end, :j_end]), g[:j_end])
-    x = y @ V[:j_end]
+    x = np.zeros(bf.size, dtype=dtype)
+    for q, Vb in enumerate(rows(j_end)):
+        x += y[q * BLK:q * BLK + Vb.shape[0]] @ Vb
     return x.reshape(shape), hist
 
 

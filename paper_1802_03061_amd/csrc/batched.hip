@@ -773,7 +773,85 @@ int solve_batched_t(int P, rte_ctx* const* ctxs, const double* const* f, const d
     return run_plan<T>(*pl, ctxs, f, tol, max_iter, u, infos, t0);
 }
 
+// Time the batched FP-T apply of one inner iteration (every problem active, input basis column 0):
+// one launch per pass and padded size, each bracketed by events on the plan's stream.
+template <typename T>
+int time_plan(Plan& pl, int reps, double* ms_total, int max_launch, int* n_launch, double* ms_launch, int* launch_pass,
+              int* launch_px, int* launch_py) {
+    hipStream_t st = pl.st;
+    const int P = pl.P, ncls = (int)pl.cls.size(), nl = 3 * ncls;
+    std::vector<int> ones(P, 1);
+    const int j0[2] = {0, 0};
+    BK_TRY(hipMemcpyAsync(pl.d_act, ones.data(), sizeof(int) * P, hipMemcpyHostToDevice, st));
+    BK_TRY(hipMemcpyAsync(pl.d_j, j0, sizeof(int), hipMemcpyHostToDevice, st));
+    std::vector<hipEvent_t> ev(nl + 1, nullptr);
+    int rc = RTE_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) { rc = set_error(RTE_EDEVICE, "hipEventCreate failed"); break; }
+    std::vector<double> acc(nl, 0.0);
+    const BatchProb<T>* probs = (const BatchProb<T>*)pl.d_it;
+    for (int r = 0; r < reps && !rc; ++r) {
+        int q = 0;
+        if (hipEventRecord(ev[0], st) != hipSuccess) { rc = set_error(RTE_EDEVICE, "hipEventRecord failed"); break; }
+        for (int pass = 0; pass < 3 && !rc; ++pass)
+            for (const auto& k : pl.cls) {
+                int bad = pass == 0 ? apply2d_batch_pass_a<T>(k.PX, probs, k.dac, (int)k.ac.size(), pl.d_act, pl.d_j, st)
+                        : pass == 1 ? apply2d_batch_pass_b<T>(k.PY, probs, k.db, (int)k.b.size(), pl.d_act, st)
+                                    : apply2d_batch_pass_c<T>(k.PX, probs, k.dac, (int)k.ac.size(), pl.d_act, pl.d_j,
+                                                              APPLY_A, st);
+                if (bad) { rc = set_error(RTE_EUNSUPPORTED, "batched apply: unsupported size"); break; }
+                if (hipEventRecord(ev[++q], st) != hipSuccess) { rc = set_error(RTE_EDEVICE, "hipEventRecord failed"); break; }
+            }
+        if (rc) break;
+        if (hipEventSynchronize(ev[nl]) != hipSuccess) { rc = set_error(RTE_EDEVICE, "hipEventSynchronize failed"); break; }
+        for (int i = 0; i < nl; ++i) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+            acc[i] += ms;
+        }
+    }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc) return rc;
+    double tot = 0.0;
+    for (int i = 0; i < nl; ++i) tot += acc[i] / reps;
+    if (ms_total) *ms_total = tot;
+    if (n_launch) *n_launch = nl;
+    for (int i = 0; i < nl && i < max_launch; ++i) {
+        if (ms_launch) ms_launch[i] = acc[i] / reps;
+        if (launch_pass) launch_pass[i] = i / ncls;
+        if (launch_px) launch_px[i] = pl.cls[i % ncls].PX;
+        if (launch_py) launch_py[i] = pl.cls[i % ncls].PY;
+    }
+    return RTE_OK;
+}
+
 }  // namespace
+
+int time_batched_impl(int count, rte_ctx* const* ctxs, int reps, double* ms_total, int max_launch, int* n_launch,
+                      double* ms_launch, int* launch_pass, int* launch_px, int* launch_py) {
+    if (count < 1 || !ctxs || reps < 1 || max_launch < 0) return set_error(RTE_EINVAL, "bad argument");
+    for (int i = 0; i < count; ++i)
+        if (!ctxs[i]) return set_error(RTE_EINVAL, "problem %d: NULL context", i);
+    std::vector<unsigned long long> ids(count);
+    std::vector<const void*> bufs;
+    for (int p = 0; p < count; ++p) {
+        ids[p] = ctxs[p]->id;
+        const auto b = ctx_buffers(ctxs[p]);
+        bufs.insert(bufs.end(), b.begin(), b.end());
+    }
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (auto& q : plans()) {
+        if (q->ids == ids && q->m == ctxs[0]->opts.restart && q->prec == ctxs[0]->prec && q->bufs == bufs) {
+            return q->prec == RTE_PREC_FP32
+                       ? time_plan<float>(*q, reps, ms_total, max_launch, n_launch, ms_launch, launch_pass, launch_px,
+                                          launch_py)
+                       : time_plan<double>(*q, reps, ms_total, max_launch, n_launch, ms_launch, launch_pass, launch_px,
+                                           launch_py);
+        }
+    }
+    return set_error(RTE_EINVAL, "no batch plan for these contexts: call rte_solve_batched on them first");
+}
 
 // A context is going away: drop every cached batch plan that refers to it.
 void batched_forget(unsigned long long id) {

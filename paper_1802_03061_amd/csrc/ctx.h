@@ -97,5 +97,7 @@ int autotune_2d(rte_ctx* c, int reps, bool use_cache);
 namespace rte {
 int solve_batched_impl(int count, rte_ctx* const* ctxs, const double* const* f, const double* tol, int max_iter,
                        void* const* u, rte_solve_info* infos);
+int time_batched_impl(int count, rte_ctx* const* ctxs, int reps, double* ms_total, int max_launch, int* n_launch,
+                      double* ms_launch, int* launch_pass, int* launch_px, int* launch_py);
 void batched_forget(unsigned long long id);
 }  // namespace rte

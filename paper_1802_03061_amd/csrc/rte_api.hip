@@ -987,3 +987,10 @@ extern "C" int rte_solve_batched(int count, rte_ctx* const* ctxs, const double* 
                                  int max_iter, void* const* u, rte_solve_info* infos) {
     return rte::solve_batched_impl(count, ctxs, f, tol, max_iter, u, infos);
 }
+
+extern "C" int rte_time_batched_apply(int count, rte_ctx* const* ctxs, int reps, double* ms_total, int max_launch,
+                                      int* n_launch, double* ms_launch, int* launch_pass, int* launch_px,
+                                      int* launch_py) {
+    return rte::time_batched_impl(count, ctxs, reps, ms_total, max_launch, n_launch, ms_launch, launch_pass,
+                                  launch_px, launch_py);
+}

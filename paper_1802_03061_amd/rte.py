@@ -83,6 +83,8 @@ def load():
         "rte_pc_make_pairs": (I, [P, P, P, P, I, I, P, P, P]),
         "rte_pc_apply": (I, [P, P, P]),
         "rte_time_apply": (I, [P, I, I, I, C.POINTER(D), C.POINTER(D)]),
+        "rte_time_batched_apply": (I, [I, C.POINTER(P), I, C.POINTER(D), I, C.POINTER(I), C.POINTER(D),
+                                       C.POINTER(I), C.POINTER(I), C.POINTER(I)]),
         "rte_query": (I, [P, C.POINTER(I), C.POINTER(I), C.POINTER(C.c_longlong)]),
         "rte_autotune": (I, [P, I]),
         "rte_set_variant": (I, [P, I, I, I]),
@@ -325,6 +327,20 @@ def solve_batched(ctxs, fs, tols, max_iter=1000, allow_not_converged=False):
     allow = (RTE_OK, RTE_NOT_CONVERGED) if allow_not_converged else (RTE_OK,)
     rc = _check(lib.rte_solve_batched(n, hs, fp, tl, int(max_iter), up, infos), allow)
     return us, [i.as_dict() for i in infos], rc
+
+
+def time_batched_apply(ctxs, reps=20):
+    """Per-launch times of the batched apply (rte_time_batched_apply); needs a prior solve_batched
+    on the same contexts.  Returns (ms_total, [(pass, PX, PY, ms), ...])."""
+    n = len(ctxs)
+    hs = (C.c_void_p * n)(*[c._h for c in ctxs])
+    cap = 64
+    tot = C.c_double()
+    nl = C.c_int()
+    ms = (C.c_double * cap)()
+    ps, px, py = (C.c_int * cap)(), (C.c_int * cap)(), (C.c_int * cap)()
+    _check(load().rte_time_batched_apply(n, hs, int(reps), C.byref(tot), cap, C.byref(nl), ms, ps, px, py))
+    return tot.value, [(ps[i], px[i], py[i], ms[i]) for i in range(min(nl.value, cap))]
 
 
 class Net:
