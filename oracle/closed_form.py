@@ -72,3 +72,33 @@ def mus0_density_3d(p, mu_t: float) -> float:
                         total += integrate.dblquad(f, ua, ub, va, vb,
                                                    epsabs=1e-12, epsrel=1e-11)[0]
     return total / (4 * np.pi)
+
+
+def mus0_moment_3d(p, a: int, L: int, mu_t: float) -> float:
+    """Mode a of the real spherical-harmonic expansion (oracle.sh3d) of the mu_s = 0, f = 1 flux on
+    [0,1]^3: u_a(x) = (1/4pi) int_{S^2} Y~_a(w) (1 - exp(-mu_t tau(x,w)))/mu_t dw.  The flux at x
+    travelling along w comes from the boundary point y = x - tau w, so w = (x - y)/|x - y|; the same
+    face decomposition as mus0_density_3d, with Y~_a(w) in the integrand."""
+    from .sh3d import real_sh
+    p = np.asarray(p, dtype=np.float64)
+    total = 0.0
+    for axis in range(3):
+        others = [q for q in range(3) if q != axis]
+        for wall in (0.0, 1.0):
+            d = abs(p[axis] - wall)
+            u0, v0 = p[others[0]], p[others[1]]
+
+            def f(v, u, d=d, u0=u0, v0=v0, axis=axis, wall=wall, others=others):
+                y = np.empty(3)
+                y[axis] = wall
+                y[others[0]] = u
+                y[others[1]] = v
+                dv = p - y
+                rho = np.sqrt(dv @ dv)
+                return real_sh(L, dv / rho)[a] * _phi(mu_t, rho) * d / rho ** 3
+
+            for (ua, ub) in ((0.0, u0), (u0, 1.0)):
+                for (va, vb) in ((0.0, v0), (v0, 1.0)):
+                    if ub > ua and vb > va:
+                        total += integrate.dblquad(f, ua, ub, va, vb, epsabs=1e-12, epsrel=1e-10)[0]
+    return total / (4 * np.pi)
