@@ -15,16 +15,30 @@
  * singular kernel over the cell (Sec. 2.3, eq. iso_discretization).  The operator is applied by
  * zero-padded FFT convolution (Sec. 2.3.1 and 3.3.1) and the system is solved by GMRES.
  *
+ * 3D anisotropic scattering (Sec. 3.1.2, eq. ani_3d_Fredholm, re-derived in real spherical
+ * harmonics): mode a = l^2 + l + m (l = 0..L, m = -l..l, M = (L+1)^2) is the coefficient of the
+ * real harmonic Y_a normalised to unit mean square over the sphere (Y_00 = 1,
+ * (Y_{1,-1}, Y_{1,0}, Y_{1,1}) = sqrt(3) (y, z, x); for m > 0, Y_{l,+-m} is
+ * sqrt(2 (2l+1) (l-m)!/(l+m)!) times the associated Legendre function without the Condon-Shortley
+ * phase times cos(m phi) / sin(m phi); Y_{l,0} = sqrt(2l+1) P_l(cos theta)), u_a = mean over
+ * directions of Phi Y_a.  K~ couples output mode a at x_i to input mode b at x_j by
+ * h^3 kappa(|x_i - x_j|) Y_a(w) Y_b(w), w = (x_i - x_j)/|x_i - x_j|, and
+ * D = diag_a(mu_s sigma_hat_l(a)) with sigma_hat_l = (1/2) int_{-1}^{1} sigma(t) P_l(t) dt the
+ * Legendre coefficients of the phase function normalised to unit mean (Henyey-Greenstein: g^l).
+ *
  * Conventions shared by every entry point
  *   - All arrays are device pointers (hipMalloc'd or torch CUDA tensors) owned by the caller and
  *     borrowed for the duration of the call; all work is enqueued on the context's stream.
  *   - Grids: 2D arrays are [ny][nx] (x fastest), 3D arrays [nz][ny][nx].
  *   - RTE_LAYOUT_MODES: complex128 (interleaved re,im doubles) [M][ny][nx], mode k = -L..L at
- *     index k+L (M = 2L+1).  Any complex vector is accepted.  3D: M = 1, [1][nz][ny][nx].
+ *     index k+L (M = 2L+1).  Any complex vector is accepted.  3D: M = (L+1)^2,
+ *     [M][nz][ny][nx], mode a = l^2 + l + m (the solution's modes are real; imaginary parts are
+ *     carried through the real operator).
  *   - RTE_LAYOUT_CHANNELS: real float64 [C][ny][nx], C = 2L+1, the image of a real angular flux
  *     (u_{-k} = conj u_k): channel 0 = Re u_0, channel 2k-1 = sqrt(2) Re u_k,
  *     channel 2k = sqrt(2) Im u_k (k = 1..L).  With the sqrt(2) the Euclidean norm of the channel
- *     vector equals the norm of the full mode vector.  3D: C = 1, [nz][ny][nx].
+ *     vector equals the norm of the full mode vector.  3D: C = (L+1)^2, [C][nz][ny][nx], channel
+ *     a = Re u_a.
  *   - Status: every int-returning function returns RTE_OK (0) on success, a positive value for a
  *     completed call with a caveat, a negative value on error; it never throws or aborts.
  *     rte_last_error() gives a thread-local message for the last non-OK status.
@@ -100,19 +114,23 @@ typedef struct {
 } rte_solve_opts;
 
 #define RTE_MAX_L 8
+#define RTE_MAX_L3 3      /* largest spherical-harmonic degree of a 3D context (M = 16 modes) */
 #define RTE_MAX_RESTART 128
 
 /* Create a context: validates the problem, allocates the device state and precomputes the
  * kernel spectra in FP64 on the device (the T_pre step of Sec. 2.4).
- *   g          grid (2D: any n_x, n_y in [2, 512]; 3D: n in [2, 256], L must be 0)
+ *   g          grid (2D: any n_x, n_y in [2, 512]; 3D: n in [2, 256] for L = 0, [2, 128] for
+ *              L = 1..RTE_MAX_L3)
  *   mu_a, mu_s absorption and scattering coefficients, >= 0, mu_a + mu_s > 0 (assumption C2)
  *   sigma_hat  host array of L+1 real Fourier coefficients of the phase function (Sec. 3.1.1,
  *              eq. ani_Fouriermode; sigma_hat_{-k} = sigma_hat_k), sigma_hat[0] == 1 (C3) and
- *              |sigma_hat[k]| <= 1; may be NULL when L == 0
- *   L          number of retained modes on each side, 0..RTE_MAX_L (M = 2L+1)
+ *              |sigma_hat[k]| <= 1; may be NULL when L == 0.  3D: its Legendre coefficients
+ *              sigma_hat_l, l = 0..L, with the same conditions
+ *   L          2D: number of retained modes on each side, 0..RTE_MAX_L (M = 2L+1); 3D: largest
+ *              spherical-harmonic degree, 0..RTE_MAX_L3 (M = (L+1)^2)
  *   prec       RTE_PREC_FP32 or RTE_PREC_FP64
  *   hip_stream hipStream_t to enqueue on (NULL = default stream)
- * Errors: RTE_EINVAL (before any device work), RTE_EUNSUPPORTED (3D with L > 0, oversize grid),
+ * Errors: RTE_EINVAL (before any device work), RTE_EUNSUPPORTED (3D with L > RTE_MAX_L3, oversize grid),
  * RTE_ENOMEM, RTE_EDEVICE.  On error *out is NULL. */
 int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s,
               const double* sigma_hat, int L, int prec, void* hip_stream);

@@ -157,17 +157,22 @@ def apply_direct(u: np.ndarray, L: int, h: float, mu_t: float, mu_s: float, sigm
 
 def kernel_spectra(nz, ny, nx, L, h, mu_t, workers: int | None = None) -> dict:
     """Real-input FFTs of the wrapped tables K_ab on the (2nz, 2ny, 2nx) grid (circulant embedding;
-    offsets +-n stay zero), for a <= b; K_ba = K_ab."""
+    offsets +-n stay zero), for a <= b; K_ba = K_ab.  The tables are kernel_table_pair's entries,
+    with kappa and the harmonics of every offset evaluated once for all pairs."""
     P = (2 * nz, 2 * ny, 2 * nx)
     OZ, OY, OX = np.meshgrid(np.arange(-(nz - 1), nz), np.arange(-(ny - 1), ny), np.arange(-(nx - 1), nx),
                              indexing="ij")
+    r, Y = _offsets_sh(OX, OY, OZ, L)
+    rr = h * np.where(r == 0.0, 1.0, r)
+    kap = h ** 3 * np.exp(-mu_t * rr) / (4.0 * np.pi * rr * rr)
+    zero = r == 0.0
     c = self_cell_pairs(L, h, mu_t)
     M = nmodes(L)
     spectra = {}
     for a in range(M):
         for b in range(a, M):
             tab = np.zeros(P)
-            tab[OZ % P[0], OY % P[1], OX % P[2]] = kernel_table_pair(nz, ny, nx, a, b, L, h, mu_t, c)
+            tab[OZ % P[0], OY % P[1], OX % P[2]] = np.where(zero, c[a, b], kap * Y[..., a] * Y[..., b])
             spectra[(a, b)] = sfft.rfftn(tab, workers=workers)
     return spectra
 

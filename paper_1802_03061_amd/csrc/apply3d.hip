@@ -1,32 +1,42 @@
-// 3D isotropic FFT apply (Sec. 2.3.1 with d = 3; the M = {0} case of Sec. 3.1.2).
+// 3D FFT apply (Sec. 2.3.1 with d = 3; Sec. 3.1.2 for the spherical-harmonic modes).
 //
-// u is one real field [nz][ny][nx]; the kernel h^3 exp(-mu_t r)/(4 pi r^2) has a real, even
-// spectrum, stored as the octant Q3[kx][ky][kz] (scaled by 1/(PX PY PZ)).  Five passes:
-//   A  x-FFT (real-to-complex) of every row, per z-slab, stored T1[z][kx][y]   (2D pass A)
-//   B  y-FFT of every (z, kx) column, stored transposed T2[kx][ky][z]
-//   C  z-FFT of every (kx, ky) column, multiply by the spectrum, inverse z-FFT, in place
-//   D  inverse y-FFT, stored back to T1[z][kx][y]
-//   E  inverse x-FFT (complex-to-real), crop, y = u - mu_s v / v / residual   (2D pass C)
+// u is C real fields [C][nz][ny][nx] (C = 1: isotropic; C = (L+1)^2: the real spherical-harmonic
+// modes of sh3d.h).  Isotropic: the kernel h^3 exp(-mu_t r)/(4 pi r^2) has a real, even spectrum,
+// stored as the octant Q3[kx][ky][kz] (scaled by 1/(PX PY PZ)).  Modes: the (a, b) block of the
+// kernel, kappa(r) Y_a(w) Y_b(w), has a spectrum F_ab = i^(l_b - l_a) R_ab with R_ab real, stored as
+// one octant per pair a <= b, and reflecting ky or kz multiplies it by the parities of Y_a and Y_b.
+// Five passes per channel:
+//   A  x-FFT (real-to-complex) of every row, per z-slab, stored T1[c][z][kx][y]   (2D pass A)
+//   B  y-FFT of every (c, z, kx) column times the channel's factor of D, stored T2[c][kx][ky][z]
+//   C  z-FFT of every (kx, ky) column of every channel, multiply by the spectrum (C > 1: the
+//      mode coupling y_a = sum_b F_ab w_b per frequency), inverse z-FFT, in place
+//   D  inverse y-FFT, stored back to T1[c][z][kx][y]
+//   E  inverse x-FFT (complex-to-real), crop, y = u - v / v / residual           (2D pass C)
 // Each pass reads and writes HBM in 128-byte runs: B and D move tiles of TZ consecutive z.
 #include "apply3d.h"
 #include "fft.h"
+#include "sh3d.h"
 
 namespace rte {
 
 template <typename T, int PY, int TZ, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_pass3_b(const cx<T>* __restrict__ T1, cx<T>* __restrict__ T2,
-                                                  const cx<T>* __restrict__ tw, int ny, int nz, int nkx) {
+                                                  const cx<T>* __restrict__ tw, int ny, int nz, int nkx, size_t t1sz,
+                                                  size_t t2sz, ChanScale3 sc) {
     constexpr int LD = padded(PY) + 1;   // odd row pitch: the TZ transforms start on different banks
     __shared__ cx<T> buf[TZ * LD];
     __shared__ cx<T> tws[PY];
     const int tid = threadIdx.x;
-    const int kx = blockIdx.x, z0 = blockIdx.y * TZ;
+    const int kx = blockIdx.x, z0 = blockIdx.y * TZ, ch = blockIdx.z;
+    const T s = (T)sc.s[ch];
+    T1 += ch * t1sz;
+    T2 += ch * t2sz;
     stage_twiddles<T, PY, NTHR>(tws, tw, tid);
     __syncthreads();
     // rows y >= ny are zero padding: the first stage is computed from the loads
     fft_forward_padded<T, PY, TZ, LD, NTHR>(buf, tws, tid, [&](int zl, int y) {
         const int z = z0 + zl;
-        return (z < nz && y < ny) ? T1[((size_t)z * nkx + kx) * ny + y] : mk((T)0, (T)0);
+        return (z < nz && y < ny) ? scale(T1[((size_t)z * nkx + kx) * ny + y], s) : mk((T)0, (T)0);
     });
     for (int idx = tid; idx < TZ * PY; idx += NTHR) {
         const int zl = idx % TZ, ky = idx / TZ;
@@ -75,14 +85,92 @@ __global__ __launch_bounds__(NTHR) void k_pass3_c(cx<T>* __restrict__ T2, const 
     });
 }
 
+// Degree and reflection parities of the first 16 modes, as compile-time tables (sh3d.h).
+constexpr int kShDeg[16] = {0, 1, 1, 1, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 3};
+constexpr int kShNegY[16] = {0, 1, 0, 0, 1, 1, 0, 0, 0, 1, 1, 1, 0, 0, 0, 0};   // m < 0
+constexpr int kShNegZ[16] = {0, 0, 1, 0, 0, 1, 0, 1, 0, 0, 1, 0, 1, 0, 1, 0};   // l - |m| odd
+
+template <typename T>
+__device__ __forceinline__ cx<T> times_i_pow(cx<T> v, int q) {   // v i^q, q in 0..3
+    return q == 0 ? v : q == 1 ? mul_i(v) : q == 2 ? mk(-v.re, -v.im) : mul_mi(v);
+}
+
+// Pass C with the mode coupling: per (kx, ky) column, the z-FFT of all CH channels in LDS, then per
+// frequency kz (one thread each)
+//     w'_b = i^(l_b) s_b w_b,   y'_a = sum_b R_ab w'_b,   y_a = i^(-l_a) s_a y'_a,
+// s_a = the parities of Y_a for the reflections that map (ky, kz) into the stored octant, which
+// equals y_a = sum_b F_ab w_b; R_ba = (-1)^(l_a + l_b) R_ab supplies the lower triangle.  Then the
+// inverse z-FFT of every channel.
+template <typename T, int PZ, int CH, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_pass3_c_sh(cx<T>* __restrict__ T2, const T* __restrict__ Q,
+                                                     const cx<T>* __restrict__ tw, int nz, int PY, size_t t2sz,
+                                                     size_t noct) {
+    constexpr int LD = padded(PZ) + 1;
+    __shared__ cx<T> buf[CH * LD];
+    __shared__ cx<T> tws[PZ];
+    const int tid = threadIdx.x;
+    const int col = blockIdx.x;                        // kx * PY + ky
+    const int kx = col / PY, ky = col % PY;
+    const int HY = PY / 2 + 1, HZ = PZ / 2 + 1;
+    stage_twiddles<T, PZ, NTHR>(tws, tw, tid);
+    __syncthreads();
+    fft_forward_padded<T, PZ, CH, LD, NTHR>(buf, tws, tid, [&](int c, int z) {
+        return z < nz ? T2[c * t2sz + (size_t)col * nz + z] : mk((T)0, (T)0);
+    });
+    const bool negy = ky > PY / 2;
+    const int fy = negy ? PY - ky : ky;
+    const T* Qc = Q + ((size_t)kx * HY + fy) * HZ;
+    for (int kz = tid; kz < PZ; kz += NTHR) {
+        const bool negz = kz > PZ / 2;
+        const int fz = negz ? PZ - kz : kz;
+        cx<T> w[CH], y[CH];
+#pragma unroll
+        for (int b = 0; b < CH; ++b) {
+            cx<T> v = buf[b * LD + sw(kz)];
+            const bool flip = (kShNegY[b] && negy) != (kShNegZ[b] && negz);
+            if (flip) v = mk(-v.re, -v.im);
+            w[b] = times_i_pow(v, kShDeg[b] & 3);
+            y[b] = mk((T)0, (T)0);
+        }
+#pragma unroll
+        for (int a = 0; a < CH; ++a) {
+#pragma unroll
+            for (int b = a; b < CH; ++b) {
+                const T r = Qc[(size_t)(a * CH - a * (a - 1) / 2 + (b - a)) * noct + fz];
+                y[a].re = fma(r, w[b].re, y[a].re);
+                y[a].im = fma(r, w[b].im, y[a].im);
+                if (b != a) {
+                    const T rb = ((kShDeg[a] + kShDeg[b]) & 1) ? -r : r;
+                    y[b].re = fma(rb, w[a].re, y[b].re);
+                    y[b].im = fma(rb, w[a].im, y[b].im);
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < CH; ++a) {
+            cx<T> v = times_i_pow(y[a], (4 - (kShDeg[a] & 3)) & 3);
+            const bool flip = (kShNegY[a] && negy) != (kShNegZ[a] && negz);
+            if (flip) v = mk(-v.re, -v.im);
+            buf[a * LD + sw(kz)] = v;
+        }
+    }
+    __syncthreads();
+    fft_inverse_cropped<T, PZ, CH, LD, NTHR>(buf, tws, tid, [&](int c, int z, cx<T> v) {
+        if (z < nz) T2[c * t2sz + (size_t)col * nz + z] = v;
+    });
+}
+
 template <typename T, int PY, int TZ, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_pass3_d(cx<T>* __restrict__ T1, const cx<T>* __restrict__ T2,
-                                                  const cx<T>* __restrict__ tw, int ny, int nz, int nkx) {
+                                                  const cx<T>* __restrict__ tw, int ny, int nz, int nkx, size_t t1sz,
+                                                  size_t t2sz) {
     constexpr int LD = padded(PY) + 1;   // odd row pitch: the TZ transforms start on different banks
     __shared__ cx<T> buf[TZ * LD];
     __shared__ cx<T> tws[PY];
     const int tid = threadIdx.x;
-    const int kx = blockIdx.x, z0 = blockIdx.y * TZ;
+    const int kx = blockIdx.x, z0 = blockIdx.y * TZ, ch = blockIdx.z;
+    T1 += ch * t1sz;
+    T2 += ch * t2sz;
     stage_twiddles<T, PY, NTHR>(tws, tw, tid);
     for (int idx = tid; idx < TZ * PY; idx += NTHR) {
         const int zl = idx % TZ, ky = idx / TZ;
@@ -105,22 +193,42 @@ template <typename T, int PY>
 static void launch3_bd(const Apply3DArgs<T>& a, bool inverse) {
     constexpr int TZ = tz_rows<T>();
     const int nkx = a.PX / 2 + 1;
-    dim3 grid(nkx, (a.nz + TZ - 1) / TZ);
+    const size_t t1sz = (size_t)a.nz * nkx * a.ny, t2sz = (size_t)nkx * a.PY * a.nz;
+    dim3 grid(nkx, (a.nz + TZ - 1) / TZ, a.C);
     if (!inverse)
         hipLaunchKernelGGL((k_pass3_b<T, PY, TZ, 256>), grid, dim3(256), 0, a.stream, a.T1, a.T2, a.twy, a.ny, a.nz,
-                           nkx);
+                           nkx, t1sz, t2sz, a.sc);
     else
         hipLaunchKernelGGL((k_pass3_d<T, PY, TZ, 256>), grid, dim3(256), 0, a.stream, a.T1, a.T2, a.twy, a.ny, a.nz,
-                           nkx);
+                           nkx, t1sz, t2sz);
 }
 
 template <typename T, int PZ>
-static void launch3_c(const Apply3DArgs<T>& a) {
-    constexpr int NC = PZ >= 2048 ? 1 : 2048 / PZ;
+static int launch3_c(const Apply3DArgs<T>& a) {
     const size_t ncol = (size_t)(a.PX / 2 + 1) * a.PY;
-    dim3 grid((unsigned)((ncol + NC - 1) / NC));
-    hipLaunchKernelGGL((k_pass3_c<T, PZ, NC, 256>), grid, dim3(256), 0, a.stream, a.T2, a.Q3, a.twz, a.nz, a.PY,
-                       ncol);
+    if (a.C == 1) {
+        constexpr int NC = PZ >= 2048 ? 1 : 2048 / PZ;
+        dim3 grid((unsigned)((ncol + NC - 1) / NC));
+        hipLaunchKernelGGL((k_pass3_c<T, PZ, NC, 256>), grid, dim3(256), 0, a.stream, a.T2, a.Q3, a.twz, a.nz, a.PY,
+                           ncol);
+        return 0;
+    }
+    if constexpr (PZ > 256) {
+        return -1;                                       // the mode coupling is built for padded z <= 256
+    } else {
+    const size_t t2sz = ncol * a.nz;
+    const size_t noct = (size_t)(a.PX / 2 + 1) * (a.PY / 2 + 1) * (PZ / 2 + 1);
+    switch (a.C) {
+#define RTE_CSH(CHN)                                                                                              \
+    case CHN:                                                                                                     \
+        hipLaunchKernelGGL((k_pass3_c_sh<T, PZ, CHN, 256>), dim3((unsigned)ncol), dim3(256), 0, a.stream, a.T2, a.Q3, \
+                           a.twz, a.nz, a.PY, t2sz, noct);                                                        \
+        return 0;
+        RTE_CSH(4) RTE_CSH(9) RTE_CSH(16)
+#undef RTE_CSH
+    }
+    return -1;
+    }
 }
 
 template <typename T>
@@ -131,7 +239,7 @@ int apply3d_pass(const Apply3DArgs<T>& a, int which) {
     case PP:                                                    \
         if (which == 1) launch3_bd<T, PP>(a, false);            \
         else if (which == 3) launch3_bd<T, PP>(a, true);        \
-        else launch3_c<T, PP>(a);                               \
+        else return launch3_c<T, PP>(a);                        \
         return 0;
         RTE_C3(16) RTE_C3(32) RTE_C3(64) RTE_C3(128) RTE_C3(256) RTE_C3(512)
 #undef RTE_C3

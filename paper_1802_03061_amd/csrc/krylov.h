@@ -71,6 +71,9 @@ void vec_scale(TD* dst, const double* src, double a, size_t n, hipStream_t st);
 void vec_fill(double* dst, double a, size_t n, hipStream_t st);
 void modes_to_channels(const void* x, double* ch, int L, size_t N, bool one_part, hipStream_t st);
 void channels_to_modes(const double* ch, void* y, int L, size_t N, bool one_part, hipStream_t st);
+// The same for modes in a real basis (3D spherical harmonics): n = channels x cells entries.
+void modes_to_channels_real(const void* x, double* ch, size_t n, bool one_part, hipStream_t st);
+void channels_to_modes_real(const double* ch, void* y, size_t n, bool one_part, hipStream_t st);
 void nonfinite_scan(const double* x, size_t n, int* flag, hipStream_t st);
 
 }  // namespace rte

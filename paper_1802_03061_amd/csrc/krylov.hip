@@ -334,6 +334,23 @@ __global__ __launch_bounds__(KT) void k_channels_to_modes(const double* __restri
     }
 }
 
+// Real-basis modes (3D spherical harmonics): channel a is Re u_a (and, for a general complex
+// vector, channel C + a is Im u_a); no mixing between modes.
+__global__ __launch_bounds__(KT) void k_modes_to_channels_real(const cx<double>* __restrict__ x,
+                                                               double* __restrict__ ch, size_t n, int one_part) {
+    const size_t i = (size_t)blockIdx.x * KT + threadIdx.x;
+    if (i >= n) return;
+    const cx<double> v = x[i];
+    ch[i] = v.re;
+    if (!one_part) ch[n + i] = v.im;
+}
+__global__ __launch_bounds__(KT) void k_channels_to_modes_real(const double* __restrict__ ch,
+                                                               cx<double>* __restrict__ y, size_t n, int one_part) {
+    const size_t i = (size_t)blockIdx.x * KT + threadIdx.x;
+    if (i >= n) return;
+    y[i] = mk(ch[i], one_part ? 0.0 : ch[n + i]);
+}
+
 // NaN/Inf scan helper: flag[0] = 1 if any entry is not finite.
 __global__ __launch_bounds__(KT) void k_nonfinite(const double* __restrict__ x, size_t n, int* __restrict__ flag) {
     const size_t stride = (size_t)gridDim.x * KT;
@@ -433,6 +450,16 @@ void modes_to_channels(const void* x, double* ch, int L, size_t N, bool one_part
 void channels_to_modes(const double* ch, void* y, int L, size_t N, bool one_part, hipStream_t st) {
     hipLaunchKernelGGL(k_channels_to_modes, dim3((unsigned)((N + KT - 1) / KT)), dim3(KT), 0, st, ch,
                        (cx<double>*)y, L, N, one_part ? 1 : 0);
+}
+
+void modes_to_channels_real(const void* x, double* ch, size_t n, bool one_part, hipStream_t st) {
+    hipLaunchKernelGGL(k_modes_to_channels_real, dim3((unsigned)((n + KT - 1) / KT)), dim3(KT), 0, st,
+                       (const cx<double>*)x, ch, n, one_part ? 1 : 0);
+}
+
+void channels_to_modes_real(const double* ch, void* y, size_t n, bool one_part, hipStream_t st) {
+    hipLaunchKernelGGL(k_channels_to_modes_real, dim3((unsigned)((n + KT - 1) / KT)), dim3(KT), 0, st, ch,
+                       (cx<double>*)y, n, one_part ? 1 : 0);
 }
 
 void nonfinite_scan(const double* x, size_t n, int* flag, hipStream_t st) {

@@ -25,6 +25,7 @@
 #include "../../include/rte.h"
 #include "apply2d.h"
 #include "apply3d.h"
+#include "sh3d.h"
 #include "ctx.h"
 #include "krylov.h"
 #include "nn.h"
@@ -158,6 +159,15 @@ static ChanScale channel_scale(const rte_ctx* c, int mode) {
     return s;
 }
 
+// 3D: channel a (the real harmonic of degree l(a)) is scaled by mu_s sigma_hat_l(a) (Funk-Hecke).
+static ChanScale3 channel_scale3(const rte_ctx* c, int mode) {
+    ChanScale3 s;
+    for (int i = 0; i < 16; ++i) s.s[i] = 1.0;
+    if (mode != APPLY_KT)
+        for (int a = 0; a < c->C; ++a) s.s[a] = c->mu_s * c->sigma[sh_degree(a)];
+    return s;
+}
+
 template <typename T>
 static Apply2DArgs<T> args2d(const rte_ctx* c);
 template <>
@@ -187,22 +197,29 @@ static int apply_t(rte_ctx* c, int mode, const TV* x, const double* b, TV* y, in
         if (apply2d_pass_c<T>(a, x, b, y, mode, nbatch)) return set_error(RTE_EUNSUPPORTED, "pass C: unsupported size");
         if (ev) (void)hipEventRecord(ev[3], c->stream);
     } else {
-        // x-passes treat every z-slab of every batch entry as one channel of a 2D apply
+        // x-passes treat every z-slab of every channel of every batch entry as one channel of a 2D
+        // apply; the factor of D is applied per channel when pass B loads it
         Apply2DArgs<T> a = args2d<T>(c);
         a.C = 1;
         a.L = 0;
         a.pack = 0;
+        ChanScale ones;
+        for (int i = 0; i < 2 * RTE_MAX_L + 1; ++i) ones.s[i] = 1.0;
         Apply3DArgs<T> a3;
         a3.nx = c->nx; a3.ny = c->ny; a3.nz = c->nz; a3.PX = c->PX; a3.PY = c->PY; a3.PZ = c->PZ;
+        a3.C = c->C;
+        a3.L = c->L;
+        a3.sc = channel_scale3(c, mode);
         a3.stream = c->stream;
-        const size_t t1sz = (size_t)c->nz * (c->PX / 2 + 1) * c->ny;
+        const size_t t1sz = (size_t)c->C * c->nz * (c->PX / 2 + 1) * c->ny;   // one batch entry
         if constexpr (sizeof(T) == 4) {
             a3.T1 = c->wf; a3.T2 = c->wf2; a3.Q3 = c->Q3f; a3.twy = c->twf[1]; a3.twz = c->twf[2];
         } else {
             a3.T1 = c->wd; a3.T2 = c->wd2; a3.Q3 = c->Q3d; a3.twy = c->twd[1]; a3.twz = c->twd[2];
         }
+        const int slabs = nbatch * c->C * c->nz;
         if (ev) (void)hipEventRecord(ev[0], c->stream);
-        if (apply2d_pass_a<T>(a, x, sc, nbatch * c->nz)) return set_error(RTE_EUNSUPPORTED, "3D pass A: unsupported size");
+        if (apply2d_pass_a<T>(a, x, ones, slabs)) return set_error(RTE_EUNSUPPORTED, "3D pass A: unsupported size");
         if (ev) (void)hipEventRecord(ev[1], c->stream);
         cx<T>* T1base = a3.T1;
         for (int bi = 0; bi < nbatch; ++bi) {
@@ -214,7 +231,7 @@ static int apply_t(rte_ctx* c, int mode, const TV* x, const double* b, TV* y, in
             if (apply3d_pass<T>(a3, 3)) return set_error(RTE_EUNSUPPORTED, "3D pass D: unsupported size");
         }
         if (ev) (void)hipEventRecord(ev[4], c->stream);
-        if (apply2d_pass_c<T>(a, x, b, y, mode, nbatch * c->nz)) return set_error(RTE_EUNSUPPORTED, "3D pass E: unsupported size");
+        if (apply2d_pass_c<T>(a, x, b, y, mode, slabs)) return set_error(RTE_EUNSUPPORTED, "3D pass E: unsupported size");
         if (ev) (void)hipEventRecord(ev[5], c->stream);
     }
     hipError_t e = hipGetLastError();
@@ -660,8 +677,9 @@ static int validate_setup(const rte_grid* g, double mu_a, double mu_s, const dou
         for (int k = 1; k <= L; ++k)
             if (!(std::fabs(sigma_hat[k]) <= 1.0)) return set_error(RTE_EINVAL, "|sigma_hat[%d]| must be <= 1", k);
     }
-    if (g->dim == 3 && L > 0) return set_error(RTE_EUNSUPPORTED, "3D is isotropic only (L must be 0)");
-    const int nmax = g->dim == 2 ? 512 : 256;
+    if (g->dim == 3 && L > RTE_MAX_L3)
+        return set_error(RTE_EUNSUPPORTED, "3D keeps spherical harmonics up to degree %d (L = %d)", RTE_MAX_L3, L);
+    const int nmax = g->dim == 2 ? 512 : (L > 0 ? 128 : 256);
     for (int a = 0; a < g->dim; ++a)
         if (g->n[a] > nmax) return set_error(RTE_EUNSUPPORTED, "n[%d] = %d exceeds %d", a, g->n[a], nmax);
     return RTE_OK;
@@ -684,8 +702,8 @@ int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const 
     c->nz = g->dim == 3 ? g->n[2] : 1;
     c->h = g->h;
     c->L = L;
-    c->C = 2 * L + 1;
-    c->M = 2 * L + 1;
+    c->C = g->dim == 3 ? sh_modes(L) : 2 * L + 1;   // 3D: real spherical harmonics to degree L
+    c->M = c->C;
     c->prec = prec;
     c->mu_a = mu_a;
     c->mu_s = mu_s;
@@ -738,10 +756,11 @@ int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const 
             rc = build_spectra_2d(a);
         } else {
             const size_t no = (size_t)NK * (c->PY / 2 + 1) * (c->PZ / 2 + 1);
-            if ((rc = dalloc(&c->Q3d, no)) || (f32 && (rc = dalloc(&c->Q3f, no)))) { dfree(b0); dfree(b1); free_ctx(c); return rc; }
+            const size_t npair = (size_t)c->C * (c->C + 1) / 2;   // one octant per mode pair a <= b
+            if ((rc = dalloc(&c->Q3d, no * npair)) || (f32 && (rc = dalloc(&c->Q3f, no * npair)))) { dfree(b0); dfree(b1); free_ctx(c); return rc; }
             SpectraArgs3D a{c->nx, c->ny, c->nz, c->PX, c->PY, c->PZ, c->h, c->mu_t, b0, b1,
                             c->twd[0], c->twd[1], c->twd[2], c->Q3f, c->Q3d, c->stream};
-            rc = build_spectrum_3d(a);
+            rc = c->L == 0 ? build_spectrum_3d(a) : build_spectra_3d_sh(a, c->L);
         }
         e = hipStreamSynchronize(c->stream);
         dfree(b0);
@@ -760,8 +779,8 @@ int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const 
             if (apply2d_needs_work2<float>(c->L, c->PY) && (rc = dalloc(&c->wf2, nt2))) { free_ctx(c); return rc; }
         }
     } else {
-        const size_t n1 = (size_t)nb * c->nz * NK * c->ny;
-        const size_t n2 = (size_t)NK * c->PY * c->nz;
+        const size_t n1 = (size_t)nb * c->C * c->nz * NK * c->ny;
+        const size_t n2 = (size_t)c->C * NK * c->PY * c->nz;
         if ((rc = dalloc(&c->wd, n1)) || (rc = dalloc(&c->wd2, n2))) { free_ctx(c); return rc; }
         if (f32 && ((rc = dalloc(&c->wf, n1)) || (rc = dalloc(&c->wf2, n2)))) { free_ctx(c); return rc; }
     }
@@ -842,6 +861,20 @@ int rte_set_solve_opts(rte_ctx* c, const rte_solve_opts* o) {
     return RTE_OK;
 }
 
+}  // extern "C"
+
+// Complex modes <-> real channels: 2D pairs modes k and -k (rte.h), 3D modes are real already.
+static void to_channels(const rte_ctx* c, const void* x, double* ch, bool one_part) {
+    if (c->dim == 3) modes_to_channels_real(x, ch, c->nvec, one_part, c->stream);
+    else modes_to_channels(x, ch, c->L, c->ncell, one_part, c->stream);
+}
+static void to_modes(const rte_ctx* c, const double* ch, void* y, bool one_part) {
+    if (c->dim == 3) channels_to_modes_real(ch, y, c->nvec, one_part, c->stream);
+    else channels_to_modes(ch, y, c->L, c->ncell, one_part, c->stream);
+}
+
+extern "C" {
+
 int rte_apply(rte_ctx* c, int op, int layout, int prec, const void* x, void* y) {
     if (!c) return set_error(RTE_EINVAL, "ctx is NULL");
     if (op != RTE_OP_A && op != RTE_OP_KT) return set_error(RTE_EINVAL, "op must be RTE_OP_A or RTE_OP_KT");
@@ -852,23 +885,23 @@ int rte_apply(rte_ctx* c, int op, int layout, int prec, const void* x, void* y) 
     if (x == y) return set_error(RTE_EINVAL, "x and y may not alias");
     const int mode = op == RTE_OP_A ? APPLY_A : APPLY_KT;
     if (layout == RTE_LAYOUT_CHANNELS) return apply_channels(c, mode, prec, (const double*)x, nullptr, (double*)y, 1);
-    modes_to_channels(x, c->t0, c->L, c->ncell, false, c->stream);
+    to_channels(c, x, c->t0, false);
     int rc = apply_channels(c, mode, prec, c->t0, nullptr, c->t1, 2);
     if (rc) return rc;
-    channels_to_modes(c->t1, y, c->L, c->ncell, false, c->stream);
+    to_modes(c, c->t1, y, false);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? RTE_OK : set_hip_error(e, "rte_apply", __FILE__, __LINE__);
 }
 
 int rte_modes_to_channels(rte_ctx* c, const void* modes, double* ch) {
     if (!c || !modes || !ch) return set_error(RTE_EINVAL, "NULL argument");
-    modes_to_channels(modes, ch, c->L, c->ncell, true, c->stream);
+    to_channels(c, modes, ch, true);
     return RTE_OK;
 }
 
 int rte_channels_to_modes(rte_ctx* c, const double* ch, void* modes) {
     if (!c || !modes || !ch) return set_error(RTE_EINVAL, "NULL argument");
-    channels_to_modes(ch, modes, c->L, c->ncell, true, c->stream);
+    to_modes(c, ch, modes, true);
     return RTE_OK;
 }
 
@@ -903,7 +936,7 @@ int rte_rhs(rte_ctx* c, const double* f, int layout, void* b) {
     if (layout == RTE_LAYOUT_CHANNELS) return rhs_channels(c, f, (double*)b);
     int rc = rhs_channels(c, f, c->bv);
     if (rc) return rc;
-    channels_to_modes(c->bv, b, c->L, c->ncell, true, c->stream);
+    to_modes(c, c->bv, b, true);
     return RTE_OK;
 }
 
@@ -915,7 +948,7 @@ int rte_solve(rte_ctx* c, const double* f, double tol, int max_iter, void* u, rt
     if (rc) return rc;
     // the modes of x are written after every true residual, while the host waits for its norm
     SolveFinish fin;
-    fin.fn = [](rte_ctx* cc, void* uu) { channels_to_modes(cc->xv, uu, cc->L, cc->ncell, true, cc->stream); };
+    fin.fn = [](rte_ctx* cc, void* uu) { to_modes(cc, cc->xv, uu, true); };
     fin.arg = u;
     rc = solve_core(c, c->bv, tol, max_iter, c->xv, info, nullptr, 0, nullptr, &fin);
     if (rc < 0) return rc;

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "fft.h"
+#include "sh3d.h"
 #include "spectra.h"
 
 namespace rte {
@@ -93,6 +94,37 @@ double self_cell_3d(double h, double mu_t) {
         }
     }
     return 6.0 / (4.0 * pi) * 4.0 * s;
+}
+
+// c[a M + b] = integral over the cube [-h/2, h/2]^3 of exp(-mu_t r)/(4 pi r^2) Y_a(w) Y_b(w), w the
+// direction of the point from the centre: the radial part exactly, the sphere split by the six
+// faces (face point p with |p_axis| = a: R = |p|, solid angle a/|p|^3 dA), each face integrated by
+// Gauss-Legendre on its four quarters.
+void self_cell_3d_pairs(int L, double h, double mu_t, std::vector<double>& c) {
+    const int M = sh_modes(L);
+    const double pi = 3.14159265358979323846;
+    const double a = 0.5 * h;
+    std::vector<double> x, w;
+    gauss_legendre(48, x, w);
+    std::vector<double> s, ws;          // nodes and weights on [-a, a], four quarters in two halves
+    for (size_t i = 0; i < x.size(); ++i) { s.push_back(-0.5 * a * (x[i] + 1.0)); ws.push_back(0.5 * a * w[i]); }
+    for (size_t i = 0; i < x.size(); ++i) { s.push_back(0.5 * a * (x[i] + 1.0)); ws.push_back(0.5 * a * w[i]); }
+    c.assign((size_t)M * M, 0.0);
+    std::vector<double> Y(M);
+    for (int axis = 0; axis < 3; ++axis)
+        for (int sg = -1; sg <= 1; sg += 2)
+            for (size_t i = 0; i < s.size(); ++i)
+                for (size_t j = 0; j < s.size(); ++j) {
+                    double p[3];
+                    p[axis] = sg * a;
+                    p[(axis + 1) % 3] = s[i];
+                    p[(axis + 2) % 3] = s[j];
+                    const double rho = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+                    const double wgt = ws[i] * ws[j] * one_minus_exp_over(mu_t, rho) * a / (rho * rho * rho) / (4.0 * pi);
+                    for (int q = 0; q < M; ++q) Y[q] = real_sh(q, p[0] / rho, p[1] / rho, p[2] / rho);
+                    for (int q = 0; q < M; ++q)
+                        for (int r = 0; r < M; ++r) c[(size_t)q * M + r] += wgt * Y[q] * Y[r];
+                }
 }
 
 // The twiddle table of the length-P LDS FFT (fft.h), in its per-stage layout: for every Stockham
@@ -178,6 +210,32 @@ __global__ void k_table_3d(cx<double>* __restrict__ out, int PX, int PY, int PZ,
     out[idx] = mk(v, 0.0);
 }
 
+// Table of the mode pair (a, b): h^3 exp(-mu_t r)/(4 pi r^2) Y_a(o/|o|) Y_b(o/|o|), c_self at o = 0.
+__global__ void k_table_3d_pair(cx<double>* __restrict__ out, int PX, int PY, int PZ, int nx, int ny, int nz,
+                                double h, double mu_t, double c_self, int a, int b) {
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)PX * PY * PZ) return;
+    const int ix = (int)(idx % PX);
+    const int iy = (int)((idx / PX) % PY);
+    const int iz = (int)(idx / ((size_t)PX * PY));
+    const int ox = ix < PX / 2 ? ix : ix - PX;
+    const int oy = iy < PY / 2 ? iy : iy - PY;
+    const int oz = iz < PZ / 2 ? iz : iz - PZ;
+    double v = 0.0;
+    if (ox > -nx && ox < nx && oy > -ny && oy < ny && oz > -nz && oz < nz) {
+        if (ox == 0 && oy == 0 && oz == 0) {
+            v = c_self;
+        } else {
+            const double rr = sqrt((double)ox * ox + (double)oy * oy + (double)oz * oz);
+            const double r = h * rr;
+            const double ux = ox / rr, uy = oy / rr, uz = oz / rr;
+            v = h * h * h * exp(-mu_t * r) / (4.0 * 3.14159265358979323846 * r * r) * real_sh(a, ux, uy, uz) *
+                real_sh(b, ux, uy, uz);
+        }
+    }
+    out[idx] = mk(v, 0.0);
+}
+
 // In-place FFT of `rows` contiguous rows of length P.
 template <typename T, int P, bool INV>
 __global__ __launch_bounds__(256) void k_fft_rows(cx<T>* __restrict__ data, const cx<T>* __restrict__ tw,
@@ -246,6 +304,22 @@ __global__ void k_extract_octant(const cx<double>* __restrict__ F, float* __rest
     if (Qf) Qf[idx] = (float)v;
 }
 
+// Octant of a mode pair's spectrum: data is [PY][PX][PZ] after three transforms;
+// Q[kx][ky][kz] = s * Re(F / i^q), i.e. s times Re F, Im F, -Re F, -Im F for q = 0, 1, 2, 3.
+__global__ void k_extract_octant_pair(const cx<double>* __restrict__ F, float* __restrict__ Qf,
+                                      double* __restrict__ Qd, int PX, int PY, int PZ, double s, int q) {
+    const int HX = PX / 2 + 1, HY = PY / 2 + 1, HZ = PZ / 2 + 1;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)HX * HY * HZ) return;
+    const int kz = (int)(idx % HZ);
+    const int ky = (int)((idx / HZ) % HY);
+    const int kx = (int)(idx / ((size_t)HZ * HY));
+    const cx<double> f = F[((size_t)ky * PX + kx) * PZ + kz];
+    const double v = s * (q == 0 ? f.re : q == 1 ? f.im : q == 2 ? -f.re : -f.im);
+    if (Qd) Qd[idx] = v;
+    if (Qf) Qf[idx] = (float)v;
+}
+
 // ------------------------------------------------------------------ host drivers ---------------
 template <typename T, bool INV>
 static int fft_rows_dispatch(cx<T>* data, const cx<T>* tw, int P, size_t rows, hipStream_t st) {
@@ -304,6 +378,32 @@ int build_spectrum_3d(const SpectraArgs3D& a) {
     const double s = 1.0 / ((double)a.PX * a.PY * a.PZ);
     hipLaunchKernelGGL(k_extract_octant, dim3((unsigned)((no + 255) / 256)), dim3(256), 0, a.stream, a.buf0, a.Qf,
                        a.Qd, a.PX, a.PY, a.PZ, s);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+int build_spectra_3d_sh(const SpectraArgs3D& a, int L) {
+    const int M = sh_modes(L);
+    std::vector<double> cself;
+    self_cell_3d_pairs(L, a.h, a.mu_t, cself);
+    const size_t NP = (size_t)a.PX * a.PY * a.PZ;
+    const unsigned nb = (unsigned)((NP + 255) / 256);
+    const size_t no = (size_t)(a.PX / 2 + 1) * (a.PY / 2 + 1) * (a.PZ / 2 + 1);
+    const double s = 1.0 / ((double)a.PX * a.PY * a.PZ);
+    for (int p = 0; p < M; ++p)
+        for (int q = p; q < M; ++q) {
+            hipLaunchKernelGGL(k_table_3d_pair, dim3(nb), dim3(256), 0, a.stream, a.buf0, a.PX, a.PY, a.PZ, a.nx,
+                               a.ny, a.nz, a.h, a.mu_t, cself[(size_t)p * M + q], p, q);
+            if (fft_rows_f64(a.buf0, a.twx, a.PX, (size_t)a.PZ * a.PY, false, a.stream)) return -1;
+            transpose_c128(a.buf0, a.buf1, (size_t)a.PZ * a.PY, a.PX, a.stream);
+            if (fft_rows_f64(a.buf1, a.twy, a.PY, (size_t)a.PX * a.PZ, false, a.stream)) return -1;
+            transpose_c128(a.buf1, a.buf0, (size_t)a.PX * a.PZ, a.PY, a.stream);
+            if (fft_rows_f64(a.buf0, a.twz, a.PZ, (size_t)a.PY * a.PX, false, a.stream)) return -1;
+            const size_t off = sh_pair_index(p, q, M) * no;
+            const int ph = (((sh_degree(q) - sh_degree(p)) % 4) + 4) % 4;
+            hipLaunchKernelGGL(k_extract_octant_pair, dim3((unsigned)((no + 255) / 256)), dim3(256), 0, a.stream,
+                               a.buf0, a.Qf ? a.Qf + off : nullptr, a.Qd ? a.Qd + off : nullptr, a.PX, a.PY, a.PZ, s,
+                               ph);
+        }
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

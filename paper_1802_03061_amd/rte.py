@@ -20,6 +20,7 @@ PREC_FP32, PREC_FP64 = 0, 1
 OP_A, OP_KT = 0, 1
 LAYOUT_MODES, LAYOUT_CHANNELS = 0, 1
 MAX_L = 8
+MAX_L3 = 3          # RTE_MAX_L3: largest spherical-harmonic degree of a 3D context
 NN_SCRATCH_BYTES = 32 << 20      # RTE_NN_SCRATCH_BYTES of rte_nn.h
 
 
