@@ -168,6 +168,19 @@ int rte_set_solve_opts(rte_ctx* ctx, const rte_solve_opts* opts);
 int rte_solve(rte_ctx* ctx, const double* f_dev, double tol, int max_iter, void* u_dev,
               rte_solve_info* info);
 
+/* An anisotropic source f(x, v) given by its angular modes g (Sec. 4: the right-hand side becomes
+ * F T^{-1} f, which for a source with the retained modes only is K~ g with g in every mode, the
+ * same K~ as the solve's): b = K~ g with the FP64 apply.  layout RTE_LAYOUT_MODES: g and b complex128
+ * [M][..] (2D: the modes of a real source, g_{-k} = conj g_k; only k >= 0 are read);
+ * RTE_LAYOUT_CHANNELS: float64 [C][..].  g and b may not alias.  Asynchronous. */
+int rte_rhs_source(rte_ctx* ctx, const void* g_dev, int layout, void* b_dev);
+
+/* Solve A u = K~ g for the anisotropic source g of rte_rhs_source, as rte_solve does for an
+ * isotropic one: u in the same layout as g (modes: complex128 [M][..]; channels: float64 [C][..]),
+ * written after every true residual.  Synchronises the stream; returns as rte_solve. */
+int rte_solve_source(rte_ctx* ctx, const void* g_dev, int layout, double tol, int max_iter, void* u_dev,
+                     rte_solve_info* info);
+
 /* Solve A x = b for a right-hand side b given in RTE_LAYOUT_CHANNELS (float64), x in the same
  * layout.  If x_iterates is not NULL, the first inner cycle's iterates are recorded there
  * (x_iterates[j] = the iterate after j+1 inner iterations, up to max_record vectors of the

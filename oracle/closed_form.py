@@ -102,3 +102,21 @@ def mus0_moment_3d(p, a: int, L: int, mu_t: float) -> float:
                     if ub > ua and vb > va:
                         total += integrate.dblquad(f, ua, ub, va, vb, epsabs=1e-12, epsrel=1e-10)[0]
     return total / (4 * np.pi)
+
+
+def mus0_mode_2d_source(x: float, y: float, k: int, mu_t: float, g: dict) -> complex:
+    """u_k(x, y) for mu_s = 0 and the spatially uniform anisotropic source
+    f(theta) = sum_{k'} g[k'] exp(i k' theta) on [0,1]^2: the characteristic solution is
+    f(theta) (1 - exp(-mu_t tau))/mu_t, so u_k = (1/2pi) int exp(-i k theta) f(theta) (...) dtheta."""
+    corners = [(0.0, 0.0), (1.0, 0.0), (1.0, 1.0), (0.0, 1.0)]
+    pts = sorted(np.mod(np.arctan2(y - cy, x - cx), 2 * np.pi) for cx, cy in corners)
+
+    def integrand(t):
+        ft = sum(gk * np.exp(1j * kp * t) for kp, gk in g.items())
+        return np.exp(-1j * k * t) * ft * _phi(mu_t, tau_2d(x, y, t))
+
+    re = integrate.quad(lambda t: integrand(t).real, 0.0, 2 * np.pi, points=pts, limit=400,
+                        epsabs=1e-13, epsrel=1e-12)[0]
+    im = integrate.quad(lambda t: integrand(t).imag, 0.0, 2 * np.pi, points=pts, limit=400,
+                        epsabs=1e-13, epsrel=1e-12)[0]
+    return (re + 1j * im) / (2 * np.pi)

@@ -959,6 +959,52 @@ int rte_solve(rte_ctx* c, const double* f, double tol, int max_iter, void* u, rt
     return rc;
 }
 
+// b = K~ g for a source given by its angular modes g (all modes, not only mode 0): the FP64 apply
+// of K~ to g in channel form.
+static int rhs_source_channels(rte_ctx* c, const void* g, int layout, double* b) {
+    const double* gc = (const double*)g;
+    if (layout == RTE_LAYOUT_MODES) {
+        to_channels(c, g, c->t0, true);
+        gc = c->t0;
+    }
+    return apply_channels(c, APPLY_KT, RTE_PREC_FP64, gc, nullptr, b, 1);
+}
+
+int rte_rhs_source(rte_ctx* c, const void* g, int layout, void* b) {
+    if (!c || !g || !b) return set_error(RTE_EINVAL, "NULL argument");
+    if (layout != RTE_LAYOUT_MODES && layout != RTE_LAYOUT_CHANNELS) return set_error(RTE_EINVAL, "bad layout");
+    if (g == b) return set_error(RTE_EINVAL, "g and b may not alias");
+    if (layout == RTE_LAYOUT_CHANNELS) return rhs_source_channels(c, g, layout, (double*)b);
+    int rc = rhs_source_channels(c, g, layout, c->bv);
+    if (rc) return rc;
+    to_modes(c, c->bv, b, true);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RTE_OK : set_hip_error(e, "rte_rhs_source", __FILE__, __LINE__);
+}
+
+int rte_solve_source(rte_ctx* c, const void* g, int layout, double tol, int max_iter, void* u, rte_solve_info* info) {
+    if (!c || !g || !u) return set_error(RTE_EINVAL, "NULL argument");
+    if (layout != RTE_LAYOUT_MODES && layout != RTE_LAYOUT_CHANNELS) return set_error(RTE_EINVAL, "bad layout");
+    if (!(tol > 0.0) || !(tol < 1.0)) return set_error(RTE_EINVAL, "tol must be in (0, 1)");
+    if (max_iter < 1) return set_error(RTE_EINVAL, "max_iter must be >= 1");
+    int rc = rhs_source_channels(c, g, layout, c->bv);
+    if (rc) return rc;
+    SolveFinish fin;
+    fin.arg = u;
+    fin.fn = layout == RTE_LAYOUT_MODES
+                 ? (void (*)(rte_ctx*, void*))[](rte_ctx* cc, void* uu) { to_modes(cc, cc->xv, uu, true); }
+                 : (void (*)(rte_ctx*, void*))[](rte_ctx* cc, void* uu) {
+                       (void)hipMemcpyAsync(uu, cc->xv, cc->nvec * sizeof(double), hipMemcpyDeviceToDevice, cc->stream);
+                   };
+    rc = solve_core(c, c->bv, tol, max_iter, c->xv, info, nullptr, 0, nullptr, &fin);
+    if (rc < 0) return rc;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return set_hip_error(e, "rte_solve_source", __FILE__, __LINE__);
+    if (rc == RTE_NOT_CONVERGED)
+        set_error(RTE_NOT_CONVERGED, "not converged: relative residual %.3e", info ? info->relres_true : -1.0);
+    return rc;
+}
+
 int rte_solve_rhs(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
                   double* x_iterates, int max_record, int* n_recorded) {
     if (!c || !b || !x) return set_error(RTE_EINVAL, "NULL argument");

@@ -69,6 +69,8 @@ def load():
         "rte_set_solve_opts": (I, [P, C.POINTER(SolveOpts)]),
         "rte_solve": (I, [P, P, D, I, P, C.POINTER(SolveInfo)]),
         "rte_solve_rhs": (I, [P, P, D, I, P, C.POINTER(SolveInfo), P, I, C.POINTER(I)]),
+        "rte_rhs_source": (I, [P, P, I, P]),
+        "rte_solve_source": (I, [P, P, I, D, I, P, C.POINTER(SolveInfo)]),
         "rte_solve_batched": (I, [I, C.POINTER(P), C.POINTER(P), C.POINTER(D), I, C.POINTER(P),
                                   C.POINTER(SolveInfo)]),
         "rte_pc_attach": (I, [P, P, I, I, I]),
@@ -229,6 +231,29 @@ class Context:
         allow = (RTE_OK, RTE_NOT_CONVERGED) if allow_not_converged else (RTE_OK,)
         rc = _check(load().rte_solve(self._h, fp, float(tol), int(max_iter), C.c_void_p(u.data_ptr()),
                                      C.byref(info)), allow)
+        d = info.as_dict()
+        d["status"] = rc
+        return u, d
+
+    def _src_ptr(self, g, layout):
+        if layout == LAYOUT_MODES:
+            return _ptr(g, torch.complex128, self.modes * self.cells)
+        return _ptr(g, torch.float64, self.channels * self.cells)
+
+    def rhs_source(self, g, layout=LAYOUT_MODES):
+        """b = K~ g for an anisotropic source given by its angular modes (rte_rhs_source)."""
+        out = torch.empty_like(g)
+        _check(load().rte_rhs_source(self._h, self._src_ptr(g, layout), layout, C.c_void_p(out.data_ptr())))
+        return out
+
+    def solve_source(self, g, tol=1e-8, max_iter=1000, layout=LAYOUT_MODES, allow_not_converged=False):
+        """Solve A u = K~ g for an anisotropic source (rte_solve_source); u in g's layout."""
+        gp = self._src_ptr(g, layout)
+        u = torch.empty_like(g)
+        info = SolveInfo()
+        allow = (RTE_OK, RTE_NOT_CONVERGED) if allow_not_converged else (RTE_OK,)
+        rc = _check(load().rte_solve_source(self._h, gp, layout, float(tol), int(max_iter),
+                                            C.c_void_p(u.data_ptr()), C.byref(info)), allow)
         d = info.as_dict()
         d["status"] = rc
         return u, d

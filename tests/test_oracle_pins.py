@@ -295,6 +295,33 @@ def test_mus0_closed_form_first_order_2d():
         assert 1.6 < a / b_ < 2.5
 
 
+def test_mus0_anisotropic_source_first_order_2d():
+    """An anisotropic source enters as g in every mode (b = K~ g, Sec. 4): with mu_s = 0 and the
+    uniform source f(theta) = sum g_k' exp(i k' theta), u = K~ g converges at first order to the
+    attenuated-source integral of f(theta) (1 - exp(-mu_t tau))/mu_t, mode by mode."""
+    mu_t, L = 1.3, 2
+    g = {0: 1.0, 1: 0.3 + 0.1j, -1: 0.3 - 0.1j, 2: -0.2, -2: -0.2}
+    errs = []
+    for n in (16, 32, 64):
+        h = 1.0 / n
+        src = np.zeros((2 * L + 1, n, n), dtype=complex)
+        for k, gk in g.items():
+            src[L + k] = gk
+        b = op2.apply_fft(src, L, h, mu_t, 0.0, np.ones(L + 1), op="KT")
+        e = 0.0
+        for fy, fx in ((0.25, 0.25), (0.5, 0.125), (0.9, 0.6)):
+            iy, ix = int(fy * n), int(fx * n)
+            x, y = (ix + 0.5) * h, (iy + 0.5) * h
+            scale = abs(cf.mus0_mode_2d_source(x, y, 0, mu_t, g))
+            for k in (-2, -1, 0, 1, 2):
+                ex = cf.mus0_mode_2d_source(x, y, k, mu_t, g)
+                e = max(e, abs(b[L + k, iy, ix] - ex) / scale)
+        errs.append(e)
+    assert errs[-1] < 5e-3
+    for a, b_ in zip(errs[:-1], errs[1:]):
+        assert 1.6 < a / b_ < 2.5
+
+
 @pytest.mark.slow
 def test_mus0_closed_form_first_order_3d():
     mu_t = 1.0
