@@ -91,6 +91,10 @@ int apply2d_pass_b(const Apply2DArgs<T>& a, int nbatch);
 // True when pass B for (L, PY) in precision T needs the work2 buffer.
 template <typename T>
 bool apply2d_needs_work2(int L, int PY);
+// Whether the 2D work buffer must be unpacked (x-frequencies 0 and PX/2 in columns of their own
+// instead of sharing column 0) for pass B of this (precision, L, PY) and pass-B variant.
+template <typename T>
+bool apply2d_unpacked(int L, int PY, int var_b);
 template <typename T, typename TV>
 int apply2d_pass_c(const Apply2DArgs<T>& a, const TV* x, const double* b, TV* y, int mode,
                    int nbatch);

@@ -513,6 +513,23 @@ bool apply2d_needs_work2(int L, int PY) {
 }
 template bool apply2d_needs_work2<float>(int, int);
 template bool apply2d_needs_work2<double>(int, int);
+template <typename T>
+bool apply2d_unpacked(int L, int PY, int var_b) {
+    switch (L) {
+        case 0: return pass_b_unpacked_L0<T>(PY, var_b);
+        case 1: return pass_b_unpacked_L1<T>(PY, var_b);
+        case 2: return pass_b_unpacked_L2<T>(PY, var_b);
+        case 3: return pass_b_unpacked_L3<T>(PY, var_b);
+        case 4: return pass_b_unpacked_L4<T>(PY, var_b);
+        case 5: return pass_b_unpacked_L5<T>(PY, var_b);
+        case 6: return pass_b_unpacked_L6<T>(PY, var_b);
+        case 7: return pass_b_unpacked_L7<T>(PY, var_b);
+        case 8: return pass_b_unpacked_L8<T>(PY, var_b);
+    }
+    return false;
+}
+template bool apply2d_unpacked<float>(int, int, int);
+template bool apply2d_unpacked<double>(int, int, int);
 template <typename T, typename TV>
 int apply2d_pass_c(const Apply2DArgs<T>& a, const TV* x, const double* b, TV* y, int mode,
                    int nbatch) {

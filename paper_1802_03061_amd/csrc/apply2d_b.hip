@@ -275,6 +275,129 @@ __global__ __launch_bounds__(NTHR) void k_pass_b_lds(cx<T>* __restrict__ Tb, con
                                           blockIdx.x * NCOL, spec, tws, pairtmp, tid, single);
 }
 
+// Register-resident form (unpacked work buffer: x-frequencies 0 and PX/2 in columns of their
+// own).  One column per block; each thread owns FPT y-frequencies: FPT = 1, PY threads, thread t
+// owns t; FPT = 2, PY/2 threads, thread t owns the mirror pair (t, PY - t) (thread 0: 0 and PY/2),
+// which read the same entries of the quarter kernel table.  The forward y-FFTs run G channels at a
+// time through LDS and every thread keeps its frequencies of those channels in registers; the mode
+// coupling then runs from registers; the inverse y-FFTs run G channels at a time again, each thread
+// writing its coupled values back into LDS first.  LDS holds G transforms instead of all 2L+1.
+// The mode coupling of couple_modes done in place on v: the channel pairs become the complex
+// modes in their own slots (slot 0: W_0, slot 2k-1: W_k, slot 2k: W_-k), only the 2L+1
+// accumulators are extra (fewer live registers when other columns' values are held too).
+template <typename T, int L>
+__device__ __forceinline__ constexpr int mode_slot(int k) { return k == 0 ? 0 : (k > 0 ? 2 * k - 1 : -2 * k); }
+
+template <typename T, int L>
+__device__ __forceinline__ void couple_regs(cx<T>* v, const cx<T>* __restrict__ Q, size_t qstride_m, size_t qoff,
+                                            bool flip) {
+    constexpr int C = 2 * L + 1;
+    const T r2 = (T)0.70710678118654752440084436210485;
+#pragma unroll
+    for (int k = 1; k <= L; ++k) {
+        const cx<T> a = v[2 * k - 1], bb = v[2 * k];
+        v[2 * k - 1] = scale(a + mul_i(bb), r2);
+        v[2 * k] = scale(a - mul_i(bb), r2);
+    }
+    cx<T> V[C];   // V_k at index k + L
+#pragma unroll
+    for (int k = 0; k < C; ++k) V[k] = mk((T)0, (T)0);
+#pragma unroll
+    for (int m = 0; m <= 2 * L; ++m) {
+        cx<T> K = Q[m * qstride_m + qoff];
+        if (flip) { K.im = -K.im; if (m & 1) { K.re = -K.re; K.im = -K.im; } }
+#pragma unroll
+        for (int k = -L; k + m <= L; ++k) cmac(V[k + L], K, v[mode_slot<T, L>(k + m)]);
+        if (m > 0) {
+            cx<T> Kn = conj(K);                     // Khat_{-m} = (-1)^m conj Khat_m
+            if (m & 1) { Kn.re = -Kn.re; Kn.im = -Kn.im; }
+#pragma unroll
+            for (int k = -L + m; k <= L; ++k) cmac(V[k + L], Kn, v[mode_slot<T, L>(k - m)]);
+        }
+    }
+    v[0] = V[L];
+#pragma unroll
+    for (int k = 1; k <= L; ++k) {
+        v[2 * k - 1] = scale(V[L + k] + V[L - k], r2);
+        v[2 * k] = scale(mul_mi(V[L + k] - V[L - k]), r2);
+    }
+}
+
+template <typename T, int L, int FPT>
+struct RegCol {
+    cx<T> d[FPT][2 * L + 1];
+};
+
+template <typename T, int PY, int L, int G, int FPT, int C0>
+__device__ __forceinline__ void reg_forward(RegCol<T, L, FPT>& r, const cx<T>* __restrict__ base, size_t cstride,
+                                            int kx, int ny, int single, cx<T>* spec, const cx<T>* tws, int tid,
+                                            const int* f) {
+    constexpr int C = 2 * L + 1;
+    constexpr int NG = (C - C0) < G ? (C - C0) : G;
+    constexpr int LD = padded(PY);
+    constexpr int NT = PY / FPT;
+    __syncthreads();   // the previous group's reads of spec are done
+    fft_forward_padded<T, PY, NG, LD, NT>(spec, tws, tid, [&](int g, int y) {
+        const int c = C0 + g;
+        return (y < ny && (!single || c == 0)) ? base[c * cstride + (size_t)kx * ny + y] : mk((T)0, (T)0);
+    });
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int q = 0; q < FPT; ++q) r.d[q][C0 + g] = spec[g * LD + sw(f[q])];
+    if constexpr (C0 + NG < C)
+        reg_forward<T, PY, L, G, FPT, C0 + NG>(r, base, cstride, kx, ny, single, spec, tws, tid, f);
+}
+
+template <typename T, int PY, int L, int G, int FPT, int C0>
+__device__ __forceinline__ void reg_inverse(const RegCol<T, L, FPT>& r, cx<T>* __restrict__ base, size_t cstride,
+                                            int kx, int ny, cx<T>* spec, const cx<T>* tws, int tid, const int* f) {
+    constexpr int C = 2 * L + 1;
+    constexpr int NG = (C - C0) < G ? (C - C0) : G;
+    constexpr int LD = padded(PY);
+    constexpr int NT = PY / FPT;
+    __syncthreads();   // the previous group's last-stage reads of spec are done
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int q = 0; q < FPT; ++q) spec[g * LD + sw(f[q])] = r.d[q][C0 + g];
+    __syncthreads();
+    fft_inverse_cropped<T, PY, NG, LD, NT>(spec, tws, tid, [&](int g, int y, cx<T> v) {
+        if (y < ny) base[(C0 + g) * cstride + (size_t)kx * ny + y] = v;
+    });
+    if constexpr (C0 + NG < C) reg_inverse<T, PY, L, G, FPT, C0 + NG>(r, base, cstride, kx, ny, spec, tws, tid, f);
+}
+
+template <typename T, int PY, int L, int G, int FPT, int MINW>
+__global__ __launch_bounds__(PY / FPT, MINW) void k_pass_b_reg(cx<T>* __restrict__ Tb, const cx<T>* __restrict__ Q,
+                                                            const cx<T>* __restrict__ tw, int ny, int nkx, int nkq,
+                                                            int single) {
+    constexpr int C = 2 * L + 1;
+    constexpr int NT = PY / FPT;
+    constexpr int KH = PY / 2 + 1;
+    constexpr int HY = PY / 2;
+    __shared__ cx<T> spec[G * padded(PY)];
+    __shared__ cx<T> tws[PY];
+    const int tid = threadIdx.x;
+    const int kx = blockIdx.x;
+    cx<T>* base = Tb + (size_t)blockIdx.y * C * nkx * ny;
+    const size_t cstride = (size_t)nkx * ny;
+    const size_t qs = (size_t)nkq * KH;
+    stage_twiddles<T, PY, NT>(tws, tw, tid);
+    int f[FPT];
+    if constexpr (FPT == 1) f[0] = tid;
+    else { f[0] = tid; f[1] = tid == 0 ? HY : PY - tid; }
+    RegCol<T, L, FPT> r;
+    reg_forward<T, PY, L, G, FPT, 0>(r, base, cstride, kx, ny, single, spec, tws, tid, f);
+    const size_t qk = (size_t)kx * KH;
+#pragma unroll
+    for (int q = 0; q < FPT; ++q) {
+        const bool flip = f[q] > HY;
+        couple_regs<T, L>(r.d[q], Q, qs, qk + (flip ? PY - f[q] : f[q]), flip);
+    }
+    reg_inverse<T, PY, L, G, FPT, 0>(r, base, cstride, kx, ny, spec, tws, tid, f);
+}
+
 #if RTE_PASSB_L == 0
 // Batched isotropic form: one block per (problem, group of NCOL columns).
 template <typename T, int PY, int NCOL, int NTHR>
@@ -388,11 +511,16 @@ constexpr int nthr_for() {
 // Fused-form variants: 0 = default threads and grouping; 1 = 1024 threads, groups of 4 transforms
 // (FP32 only); 2 = 256 threads.  Variants 1 and 2 exist for PY >= 128 when they have enough work.
 template <typename T, int PY, int L>
+constexpr bool reg_variant() {   // the register-resident form as an FP32 variant: padded y >= 128, 5+ channels
+    return sizeof(T) == 4 && PY >= 128 && L >= 2;
+}
+
+template <typename T, int PY, int L>
 constexpr int fused_variants() {
     constexpr int C = 2 * L + 1;
     constexpr int NF = ncol_for<T, PY, L>() * C * PY;
     if (PY < 128) return 1;
-    return (sizeof(T) == 4 && NF / 8 >= 1024) ? 3 : 2;
+    return reg_variant<T, PY, L>() ? 4 : ((sizeof(T) == 4 && NF / 8 >= 1024) ? 3 : 2);
 }
 
 template <typename T, int PY, int L, int NCOL, int NT, int GV>
@@ -412,6 +540,15 @@ static int launch_py(const Apply2DArgs<T>& a, int nbatch) {
         constexpr int NCOL = ncol_for<T, PY, L>();
         constexpr int NT = nthr_for<T, NCOL * C * PY>();
         constexpr int NV = fused_variants<T, PY, L>();
+        if constexpr (reg_variant<T, PY, L>()) {
+            if (a.var[1] == 3) {   // the work buffer is unpacked for this variant (apply2d_pack)
+                if (a.pack) return -4;
+                dim3 grid(nkx, nbatch);
+                hipLaunchKernelGGL((k_pass_b_reg<T, PY, L, 4, 1, 4>), grid, dim3(PY), 0, a.stream, a.work, a.Q, a.twy,
+                                   a.ny, nkx, nkq, a.single_in);
+                return 0;
+            }
+        }
         if constexpr (NV >= 3) {
             if (a.var[1] == 1) { launch_fused<T, PY, L, NCOL, 1024, 4>(a, nbatch, nkx, nkq); return 0; }
         }
@@ -493,6 +630,30 @@ template int apply2d_batch_cols<double>(int);
 template int apply2d_batch_pass_b<float>(int, const BatchProb<float>*, const int2*, int, const int*, hipStream_t);
 template int apply2d_batch_pass_b<double>(int, const BatchProb<double>*, const int2*, int, const int*, hipStream_t);
 #endif
+
+// Whether pass B takes the work buffer unpacked (x-frequencies 0 and PX/2 in columns of their own)
+// for this (precision, PY, pass-B variant): the register-resident forms.
+template <typename T, int PY>
+static bool unpacked_py(int var) {
+    constexpr int L = RTE_PASSB_L;
+    if constexpr (fused_fits<T, PY, L>()) return reg_variant<T, PY, L>() && var == 3;
+    else return false;
+}
+template <typename T>
+bool RTE_CAT(pass_b_unpacked_L, RTE_PASSB_L)(int PY, int var) {
+    switch (PY) {
+        case 16: return unpacked_py<T, 16>(var);
+        case 32: return unpacked_py<T, 32>(var);
+        case 64: return unpacked_py<T, 64>(var);
+        case 128: return unpacked_py<T, 128>(var);
+        case 256: return unpacked_py<T, 256>(var);
+        case 512: return unpacked_py<T, 512>(var);
+        case 1024: return unpacked_py<T, 1024>(var);
+    }
+    return false;
+}
+template bool RTE_CAT(pass_b_unpacked_L, RTE_PASSB_L)<float>(int, int);
+template bool RTE_CAT(pass_b_unpacked_L, RTE_PASSB_L)<double>(int, int);
 
 #define RTE_PASSB_FN RTE_CAT(pass_b_L, RTE_PASSB_L)
 #define RTE_PASSB_VARIANTS RTE_CAT(pass_b_variants_L, RTE_PASSB_L)

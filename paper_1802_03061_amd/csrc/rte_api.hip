@@ -168,6 +168,11 @@ static ChanScale3 channel_scale3(const rte_ctx* c, int mode) {
     return s;
 }
 
+// Column 0 of the 2D work buffer packs the x-frequencies 0 and PX/2 (two real sequences) except
+// with the register-resident pass B, which takes them as columns of their own.
+template <typename T>
+static int pack_for(const Apply2DArgs<T>& a) { return apply2d_unpacked<T>(a.L, a.PY, a.var[1]) ? 0 : 1; }
+
 template <typename T>
 static Apply2DArgs<T> args2d(const rte_ctx* c);
 template <>
@@ -188,7 +193,7 @@ static int apply_t(rte_ctx* c, int mode, const TV* x, const double* b, TV* y, in
     const ChanScale sc = channel_scale(c, mode);
     if (c->dim == 2) {
         Apply2DArgs<T> a = args2d<T>(c);
-        a.pack = 1;
+        a.pack = pack_for(a);
         if (ev) (void)hipEventRecord(ev[0], c->stream);
         if (apply2d_pass_a<T>(a, x, sc, nbatch)) return set_error(RTE_EUNSUPPORTED, "pass A: unsupported size");
         if (ev) (void)hipEventRecord(ev[1], c->stream);
@@ -258,7 +263,7 @@ template <typename T, typename TV>
 static int apply_pc_t(rte_ctx* c, const TV* v, TV* y, const float* Y) {
     const ChanScale sc = channel_scale(c, APPLY_A);
     Apply2DArgs<T> a = args2d<T>(c);
-    a.pack = 1;
+    a.pack = pack_for(a);
     a.corr = Y;
     a.cF = c->pc_factor;
     a.cs = 1.0 / std::sqrt((double)c->nvec);
@@ -304,9 +309,9 @@ static int tune_t(rte_ctx* c, int* var, int reps, bool use_cache) {
         float best_ms = 1e30f;
         for (int v = 0; v < nv && !rc; ++v) {
             Apply2DArgs<T> a = args2d<T>(c);
-            a.pack = 1;
             for (int p = 0; p < 3; ++p) a.var[p] = var[p];
             a.var[pass] = v;
+            a.pack = pack_for(a);
             // one full apply first: the work buffer then holds a valid spectrum for passes B and C
             if (apply2d<T>(a, c->t0, nullptr, c->t1, APPLY_A, sc, 1)) { rc = set_error(RTE_EUNSUPPORTED, "tune"); break; }
             (void)hipEventRecord(e0, c->stream);
@@ -911,7 +916,7 @@ static int rhs_channels(rte_ctx* c, const double* f, double* b) {
         // b = K~ (f, 0, ..., 0): pass A for channel 0 only, pass B reading channel 0 only (its
         // coupling writes every channel); inverse y-FFTs and pass C as usual
         Apply2DArgs<double> a = args2d<double>(c);
-        a.pack = 1;
+        a.pack = pack_for(a);
         const ChanScale sc = channel_scale(c, APPLY_KT);
         Apply2DArgs<double> a1 = a;
         a1.C = 1;
