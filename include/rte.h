@@ -181,6 +181,22 @@ int rte_rhs_source(rte_ctx* ctx, const void* g_dev, int layout, void* b_dev);
 int rte_solve_source(rte_ctx* ctx, const void* g_dev, int layout, double tol, int max_iter, void* u_dev,
                      rte_solve_info* info);
 
+/* Several sources sharing one medium (the case the paper names for reusing one operator,
+ * Sec. 2.3.2): solve A u_s = K~ g(f_s) for s < nrhs with this context's operator, as one GMRES on
+ * the stacked block-diagonal system with every right-hand side scaled to unit norm (global GMRES):
+ * each iteration applies A to all nrhs vectors in one batched launch per pass and runs one
+ * Gram-Schmidt step on the stacked vector.  Stopping at a stacked relative residual of
+ * tol / sqrt(number of non-zero sources) bounds every source's relative residual by tol; each
+ * source's FP64 true residual is computed at the end and reported in infos[s].relres_true (its
+ * status is RTE_NOT_CONVERGED if it exceeds tol).  f[s]: float64 sources at the cell centres;
+ * u[s]: complex128 modes (RTE_LAYOUT_MODES); nrhs in 1..RTE_MAX_RHS.  Work buffers grow to nrhs
+ * right-hand sides on first use.  The learned preconditioner is not used.  infos may be NULL.
+ * Synchronises the stream.  Returns RTE_OK if every source converged, RTE_NOT_CONVERGED,
+ * RTE_ENUMERIC or an error. */
+#define RTE_MAX_RHS 64
+int rte_solve_multi(rte_ctx* ctx, int nrhs, const double* const* f_dev, double tol, int max_iter,
+                    void* const* u_dev, rte_solve_info* infos);
+
 /* Solve A x = b for a right-hand side b given in RTE_LAYOUT_CHANNELS (float64), x in the same
  * layout.  If x_iterates is not NULL, the first inner cycle's iterates are recorded there
  * (x_iterates[j] = the iterate after j+1 inner iterations, up to max_record vectors of the

@@ -34,9 +34,16 @@ struct rte_ctx {
     double* bv = nullptr;
     double* t0 = nullptr;   // 2 vectors
     double* t1 = nullptr;   // 2 vectors
+    int work_nb = 2;        // batch entries (right-hand sides) the FFT work buffers hold
+    // several right-hand sides sharing the operator (rte_solve_multi): stacked x, r, b
+    int multi_nb = 0;
+    double* xm = nullptr;
+    double* rm = nullptr;
+    double* bm = nullptr;
     int* dflag = nullptr;
     // Krylov basis
     int krylov_m = 0;
+    size_t krylov_n = 0;        // vector length the basis is sized for (a multiple of nvec)
     bool krylov_z = false;
     size_t krylov_vbytes = 0;   // bytes per basis entry the allocation was sized for
     // (m + 1) basis vectors of nvec entries: double, or float when an FP32 context solves with
@@ -77,7 +84,7 @@ struct rte_ctx {
 
 namespace rte {
 // Basis of m + 1 vectors with vbytes per entry (and Z when need_z), kept when large enough.
-int ensure_krylov(rte_ctx* c, int m, bool need_z, size_t vbytes);
+int ensure_krylov(rte_ctx* c, int m, bool need_z, size_t vbytes, size_t n = 0);
 int apply_channels(rte_ctx* c, int mode, int prec, const double* x, const double* b, double* y, int nbatch);
 // Basis vector element type of a context.
 template <typename TV>
@@ -89,8 +96,10 @@ struct SolveFinish {
     void (*fn)(rte_ctx* c, void* arg) = nullptr;
     void* arg = nullptr;
 };
+// nb > 1: b and x are nb stacked channel vectors and the Krylov process runs on the stacked
+// (block-diagonal) system, one batched apply per iteration.
 int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
-               double* rec, int max_rec, int* nrec, const SolveFinish* finish = nullptr);
+               double* rec, int max_rec, int* nrec, const SolveFinish* finish = nullptr, int nb = 1);
 int autotune_2d(rte_ctx* c, int reps, bool use_cache);
 }  // namespace rte
 

@@ -87,6 +87,7 @@ static void free_krylov(rte_ctx* c) {
     if (c->hpipe_flags) (void)hipHostFree(c->hpipe_flags);
     c->hpipe_flags = nullptr;
     c->krylov_m = 0;
+    c->krylov_n = 0;
     c->krylov_z = false;
     c->krylov_vbytes = 0;
 }
@@ -111,6 +112,9 @@ static void free_ctx(rte_ctx* c) {
     dfree(c->xv);
     dfree(c->rv);
     dfree(c->bv);
+    dfree(c->xm);
+    dfree(c->rm);
+    dfree(c->bm);
     dfree(c->t0);
     dfree(c->t1);
     dfree(c->dflag);
@@ -118,10 +122,10 @@ static void free_ctx(rte_ctx* c) {
     delete c;
 }
 
-int ensure_krylov(rte_ctx* c, int m, bool need_z, size_t vbytes) {
-    if (c->krylov_m >= m && c->krylov_vbytes >= vbytes && (!need_z || c->krylov_z)) return RTE_OK;
+int ensure_krylov(rte_ctx* c, int m, bool need_z, size_t vbytes, size_t nlen) {
+    const size_t n = std::max(nlen ? nlen : c->nvec, c->krylov_n);
+    if (c->krylov_m >= m && c->krylov_vbytes >= vbytes && (!need_z || c->krylov_z) && c->krylov_n >= n) return RTE_OK;
     free_krylov(c);
-    const size_t n = c->nvec;
     int rc;
     if ((rc = dalloc(&c->V, (size_t)(m + 1) * n * vbytes))) return rc;
     if (need_z && (rc = dalloc(&c->Z, (size_t)m * n))) return rc;
@@ -142,8 +146,39 @@ int ensure_krylov(rte_ctx* c, int m, bool need_z, size_t vbytes) {
     if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->hpipe_flags_dev, c->hpipe_flags, 0);
     if (e != hipSuccess) return set_hip_error(e, "hipHostMalloc", __FILE__, __LINE__);
     c->krylov_m = m;
+    c->krylov_n = n;
     c->krylov_z = need_z;
     c->krylov_vbytes = vbytes;
+    return RTE_OK;
+}
+
+// FFT work buffers for nb batch entries (right-hand sides); grown on demand, never shrunk.
+static int ensure_work(rte_ctx* c, int nb) {
+    if (nb <= c->work_nb) return RTE_OK;
+    const bool f32 = c->prec == RTE_PREC_FP32;
+    const int NK = c->PX / 2 + 1;
+    dfree(c->wf);
+    dfree(c->wf2);
+    dfree(c->wd);
+    dfree(c->wd2);
+    c->work_nb = 0;
+    int rc;
+    if (c->dim == 2) {
+        const size_t nt = (size_t)nb * c->C * NK * c->ny;
+        const size_t nt2 = (size_t)nb * c->C * NK * c->PY;
+        if ((rc = dalloc(&c->wd, nt))) return rc;
+        if (apply2d_needs_work2<double>(c->L, c->PY) && (rc = dalloc(&c->wd2, nt2))) return rc;
+        if (f32) {
+            if ((rc = dalloc(&c->wf, nt))) return rc;
+            if (apply2d_needs_work2<float>(c->L, c->PY) && (rc = dalloc(&c->wf2, nt2))) return rc;
+        }
+    } else {
+        const size_t n1 = (size_t)nb * c->C * c->nz * NK * c->ny;
+        const size_t n2 = (size_t)c->C * NK * c->PY * c->nz;   // shared by the batch entries
+        if ((rc = dalloc(&c->wd, n1)) || (rc = dalloc(&c->wd2, n2))) return rc;
+        if (f32 && ((rc = dalloc(&c->wf, n1)) || (rc = dalloc(&c->wf2, n2)))) return rc;
+    }
+    c->work_nb = nb;
     return RTE_OK;
 }
 
@@ -252,10 +287,10 @@ int apply_channels(rte_ctx* c, int mode, int prec, const double* x, const double
 // y = A x on basis vectors (stored as TV) in the context precision: float vectors only with the
 // FP32 apply.
 template <typename TV>
-static int apply_basis(rte_ctx* c, const TV* x, TV* y) {
-    if constexpr (sizeof(TV) == sizeof(float)) return apply_t<float>(c, APPLY_A, x, nullptr, y, 1, nullptr);
-    else return c->prec == RTE_PREC_FP32 ? apply_t<float>(c, APPLY_A, x, nullptr, y, 1, nullptr)
-                                         : apply_t<double>(c, APPLY_A, x, nullptr, y, 1, nullptr);
+static int apply_basis(rte_ctx* c, const TV* x, TV* y, int nb = 1) {
+    if constexpr (sizeof(TV) == sizeof(float)) return apply_t<float>(c, APPLY_A, x, nullptr, y, nb, nullptr);
+    else return c->prec == RTE_PREC_FP32 ? apply_t<float>(c, APPLY_A, x, nullptr, y, nb, nullptr)
+                                         : apply_t<double>(c, APPLY_A, x, nullptr, y, nb, nullptr);
 }
 
 // y = A (v + s P Y) in the context precision, the coarse correction added inside passes A and C.
@@ -366,10 +401,11 @@ static int wait_slot(rte_ctx* c, const double* slot) {
 }
 
 // <a, b> into device-visible host memory (slot m of hpipe): enqueue, then wait for the slot.
-static void dot_enqueue(rte_ctx* c, const double* a, const double* b) {
+static void dot_enqueue(rte_ctx* c, const double* a, const double* b, size_t n = 0) {
     const int m = c->krylov_m;
+    if (!n) n = c->nvec;
     c->hpipe[m] = kPending;
-    krylov_dots(a, c->nvec, 1, b, c->nvec, c->partial, c->hpipe_dev + m, false, c->stream);
+    krylov_dots(a, n, 1, b, n, c->partial, c->hpipe_dev + m, false, c->stream);
 }
 static int dot_wait(rte_ctx* c, double* out) {
     const int m = c->krylov_m;
@@ -385,14 +421,17 @@ static int dot_wait(rte_ctx* c, double* out) {
 // the Hessenberg matrix, rotations, dot products, x and the true residual are FP64 in both.
 template <typename TV>
 static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
-                        double* rec, int max_rec, int* nrec, const SolveFinish* finish) {
+                        double* rec, int max_rec, int* nrec, const SolveFinish* finish, int nb) {
     const double t_start = now_ms();
     hipStream_t st = c->stream;
-    const size_t n = c->nvec;
+    const size_t n = (size_t)nb * c->nvec;
     const int m = c->opts.restart;
-    const bool use_pc = c->pc_attached && c->opts.use_pc;
+    // several stacked right-hand sides: no preconditioner, no recorded iterates
+    const bool use_pc = c->pc_attached && c->opts.use_pc && nb == 1;
+    if (nb > 1) rec = nullptr;
+    double* const rv = nb > 1 ? c->rm : c->rv;
     const bool mixed = c->prec == RTE_PREC_FP32;
-    int rc = ensure_krylov(c, m, false, sizeof(TV));
+    int rc = ensure_krylov(c, m, false, sizeof(TV), n);
     if (rc) return rc;
     TV* const V = basis<TV>(c);
     if (use_pc && (rc = pc_begin_solve(c, m))) return rc;
@@ -404,9 +443,9 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
 
     double bn2;
     // x = 0 and r = b do not depend on |b|: queued while the host waits for it
-    dot_enqueue(c, b, b);
+    dot_enqueue(c, b, b, n);
     vec_fill(x, 0.0, n, st);
-    RTE_HIP_TRY(hipMemcpyAsync(c->rv, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    RTE_HIP_TRY(hipMemcpyAsync(rv, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     if ((rc = dot_wait(c, &bn2))) return rc;
     if (!std::isfinite(bn2)) {
         inf.status = RTE_ENUMERIC;
@@ -448,9 +487,9 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
         if (mixed) target = std::max(target, c->opts.inner_tol * rn);
         // v_0 = r / rn (with the pooled coarse input of the network when preconditioning)
         if (pc_live) {   // with g = (rn, 0, ...) and the flags cleared in the same launch
-            pc_scale_pool(c, (const double*)c->rv, V, nullptr, 1.0 / rn, dg, m + 1, rn, dfl, 4);
+            pc_scale_pool(c, (const double*)rv, V, nullptr, 1.0 / rn, dg, m + 1, rn, dfl, 4);
         } else {
-            vec_scale(V, c->rv, 1.0 / rn, n, st);
+            vec_scale(V, rv, 1.0 / rn, n, st);
             init_g(dg, m + 1, rn, dfl, 4, st);
         }
         est = rn;
@@ -469,7 +508,7 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
                 if (!net_ready && (rc = pc_net_slot(c, j))) return rc;   // else the last launch ran it
                 net_ready = false;
                 if ((rc = apply_basis_pc(c, vj, w, pc_slot(c, j)))) return rc;
-            } else if ((rc = apply_basis(c, vj, w))) {
+            } else if ((rc = apply_basis(c, vj, w, nb))) {
                 return rc;
             }
             ++inf.applies;
@@ -562,9 +601,9 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
                 if (pc_live) pc_combine(c, x, (const TV*)V, jd_end, c->dsmall, guard);
                 else krylov_combine(x, V, n, jd_end, c->dsmall, n, st, guard);
             }
-            if ((rc = apply_channels(c, APPLY_RESID, RTE_PREC_FP64, x, b, c->rv, 1))) return rc;
+            if ((rc = apply_channels(c, APPLY_RESID, RTE_PREC_FP64, x, b, rv, nb))) return rc;
             ++inf.applies;
-            dot_enqueue(c, c->rv, c->rv);
+            dot_enqueue(c, rv, rv, n);
             if (finish && finish->fn) finish->fn(c, finish->arg);   // runs while the host waits
         }
         // settle the last enqueued iteration
@@ -613,9 +652,9 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
                 else krylov_combine(x, V, n, jd, c->dsmall, n, st);
             }
             // true residual with the FP64 apply
-            if ((rc = apply_channels(c, APPLY_RESID, RTE_PREC_FP64, x, b, c->rv, 1))) return rc;
+            if ((rc = apply_channels(c, APPLY_RESID, RTE_PREC_FP64, x, b, rv, nb))) return rc;
             ++inf.applies;
-            dot_enqueue(c, c->rv, c->rv);
+            dot_enqueue(c, rv, rv, n);
             if (finish && finish->fn) finish->fn(c, finish->arg);   // runs while the host waits
         }
         double rn2;
@@ -648,10 +687,10 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
 }
 
 int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,
-               double* rec, int max_rec, int* nrec, const SolveFinish* finish) {
+               double* rec, int max_rec, int* nrec, const SolveFinish* finish, int nb) {
     if (c->prec == RTE_PREC_FP32 && c->opts.basis_fp32)
-        return solve_core_t<float>(c, b, tol, max_iter, x, info, rec, max_rec, nrec, finish);
-    return solve_core_t<double>(c, b, tol, max_iter, x, info, rec, max_rec, nrec, finish);
+        return solve_core_t<float>(c, b, tol, max_iter, x, info, rec, max_rec, nrec, finish, nb);
+    return solve_core_t<double>(c, b, tol, max_iter, x, info, rec, max_rec, nrec, finish, nb);
 }
 
 }  // namespace rte
@@ -1008,6 +1047,94 @@ int rte_solve_source(rte_ctx* c, const void* g, int layout, double tol, int max_
     if (rc == RTE_NOT_CONVERGED)
         set_error(RTE_NOT_CONVERGED, "not converged: relative residual %.3e", info ? info->relres_true : -1.0);
     return rc;
+}
+
+// Several right-hand sides sharing the context's operator, solved as one GMRES on the stacked
+// block-diagonal system diag(A, ..., A) [x_1; ...; x_B] = [b_1; ...; b_B] with each b_s scaled to
+// unit norm (global GMRES): every iteration is one batched apply over all B vectors and one
+// Gram-Schmidt step over the stacked vector.  With unit-norm blocks, a stacked relative residual
+// of tol / sqrt(B') (B' the non-zero sources) bounds every block's relative residual by tol.
+int rte_solve_multi(rte_ctx* c, int nrhs, const double* const* f, double tol, int max_iter, void* const* u,
+                    rte_solve_info* infos) {
+    if (!c || nrhs < 1 || !f || !u) return set_error(RTE_EINVAL, "bad argument");
+    if (nrhs > RTE_MAX_RHS) return set_error(RTE_EINVAL, "nrhs = %d exceeds %d", nrhs, RTE_MAX_RHS);
+    if (!(tol > 0.0) || !(tol < 1.0)) return set_error(RTE_EINVAL, "tol must be in (0, 1)");
+    if (max_iter < 1) return set_error(RTE_EINVAL, "max_iter must be >= 1");
+    for (int s = 0; s < nrhs; ++s)
+        if (!f[s] || !u[s]) return set_error(RTE_EINVAL, "source or output %d is NULL", s);
+    const double t0 = now_ms();
+    const size_t nv = c->nvec;
+    int rc = ensure_work(c, nrhs);
+    if (rc) return rc;
+    if (c->multi_nb < nrhs) {
+        dfree(c->xm);
+        dfree(c->rm);
+        dfree(c->bm);
+        c->multi_nb = 0;
+        const size_t n = (size_t)nrhs * nv;
+        if ((rc = dalloc(&c->xm, n)) || (rc = dalloc(&c->rm, n)) || (rc = dalloc(&c->bm, n))) return rc;
+        c->multi_nb = nrhs;
+    }
+    hipStream_t st = c->stream;
+    // right-hand sides and their norms
+    std::vector<double> bn(nrhs);
+    for (int s = 0; s < nrhs; ++s) {
+        if ((rc = rhs_channels(c, f[s], c->bm + s * nv))) return rc;
+        dot_enqueue(c, c->bm + s * nv, c->bm + s * nv);
+        double b2;
+        if ((rc = dot_wait(c, &b2))) return rc;
+        if (!std::isfinite(b2)) return set_error(RTE_ENUMERIC, "non-finite right-hand side %d", s);
+        bn[s] = std::sqrt(b2);
+    }
+    int nz = 0;
+    for (int s = 0; s < nrhs; ++s) {
+        vec_scale(c->bm + s * nv, c->bm + s * nv, bn[s] > 0.0 ? 1.0 / bn[s] : 0.0, nv, st);
+        nz += bn[s] > 0.0;
+    }
+    rte_solve_info inf;
+    memset(&inf, 0, sizeof(inf));
+    int status = RTE_OK;
+    if (nz > 0) {
+        rc = solve_core(c, c->bm, tol / std::sqrt((double)nz), max_iter, c->xm, &inf, nullptr, 0, nullptr, nullptr,
+                        nrhs);
+        if (rc < 0) return rc;
+        status = rc;
+    } else {
+        vec_fill(c->xm, 0.0, (size_t)nrhs * nv, st);
+    }
+    // undo the scaling, then every block's own true residual (FP64, one batched apply)
+    for (int s = 0; s < nrhs; ++s) {
+        vec_scale(c->xm + s * nv, c->xm + s * nv, bn[s], nv, st);
+        vec_scale(c->bm + s * nv, c->bm + s * nv, bn[s], nv, st);
+    }
+    if ((rc = apply_channels(c, APPLY_RESID, RTE_PREC_FP64, c->xm, c->bm, c->rm, nrhs))) return rc;
+    for (int s = 0; s < nrhs; ++s) to_modes(c, c->xm + s * nv, u[s], true);
+    int worst = RTE_OK;
+    for (int s = 0; s < nrhs; ++s) {
+        double r2 = 0.0;
+        dot_enqueue(c, c->rm + s * nv, c->rm + s * nv);
+        if ((rc = dot_wait(c, &r2))) return rc;
+        const double rel = bn[s] > 0.0 ? std::sqrt(r2) / bn[s] : 0.0;
+        const int ss = !std::isfinite(rel) ? RTE_ENUMERIC : (rel <= tol ? RTE_OK : RTE_NOT_CONVERGED);
+        if (ss == RTE_ENUMERIC) worst = RTE_ENUMERIC;
+        else if (ss == RTE_NOT_CONVERGED && worst == RTE_OK) worst = RTE_NOT_CONVERGED;
+        if (infos) {
+            infos[s] = inf;
+            infos[s].relres_true = rel;
+            infos[s].status = bn[s] > 0.0 ? ss : RTE_OK;
+        }
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return set_hip_error(e, "rte_solve_multi", __FILE__, __LINE__);
+    const double t = now_ms() - t0;
+    if (infos)
+        for (int s = 0; s < nrhs; ++s) infos[s].t_solve_ms = t;
+    if (worst == RTE_ENUMERIC) return set_error(RTE_ENUMERIC, "non-finite value in the stacked solve");
+    if (worst == RTE_NOT_CONVERGED || status == RTE_NOT_CONVERGED) {
+        set_error(RTE_NOT_CONVERGED, "some right-hand sides did not converge");
+        return RTE_NOT_CONVERGED;
+    }
+    return RTE_OK;
 }
 
 int rte_solve_rhs(rte_ctx* c, const double* b, double tol, int max_iter, double* x, rte_solve_info* info,

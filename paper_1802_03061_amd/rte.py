@@ -21,6 +21,7 @@ OP_A, OP_KT = 0, 1
 LAYOUT_MODES, LAYOUT_CHANNELS = 0, 1
 MAX_L = 8
 MAX_L3 = 3          # RTE_MAX_L3: largest spherical-harmonic degree of a 3D context
+MAX_RHS = 64        # RTE_MAX_RHS: right-hand sides of one rte_solve_multi call
 NN_SCRATCH_BYTES = 32 << 20      # RTE_NN_SCRATCH_BYTES of rte_nn.h
 
 
@@ -71,6 +72,7 @@ def load():
         "rte_solve_rhs": (I, [P, P, D, I, P, C.POINTER(SolveInfo), P, I, C.POINTER(I)]),
         "rte_rhs_source": (I, [P, P, I, P]),
         "rte_solve_source": (I, [P, P, I, D, I, P, C.POINTER(SolveInfo)]),
+        "rte_solve_multi": (I, [P, I, C.POINTER(P), D, I, C.POINTER(P), C.POINTER(SolveInfo)]),
         "rte_solve_batched": (I, [I, C.POINTER(P), C.POINTER(P), C.POINTER(D), I, C.POINTER(P),
                                   C.POINTER(SolveInfo)]),
         "rte_pc_attach": (I, [P, P, I, I, I]),
@@ -257,6 +259,18 @@ class Context:
         d = info.as_dict()
         d["status"] = rc
         return u, d
+
+    def solve_multi(self, fs, tol=1e-8, max_iter=1000, allow_not_converged=False):
+        """Several sources sharing this context's operator (rte_solve_multi): returns the list of
+        complex mode tensors, the per-source infos and the status."""
+        n = len(fs)
+        fp = (C.c_void_p * n)(*[_ptr(f, torch.float64, self.cells) for f in fs])
+        us = [torch.empty(self.mode_shape, dtype=torch.complex128, device=f.device) for f in fs]
+        up = (C.c_void_p * n)(*[C.c_void_p(u.data_ptr()) for u in us])
+        infos = (SolveInfo * n)()
+        allow = (RTE_OK, RTE_NOT_CONVERGED) if allow_not_converged else (RTE_OK,)
+        rc = _check(load().rte_solve_multi(self._h, n, fp, float(tol), int(max_iter), up, infos), allow)
+        return us, [i.as_dict() for i in infos], rc
 
     def solve_rhs(self, b, tol=1e-8, max_iter=1000, record=0, allow_not_converged=False):
         bp = _ptr(b, torch.float64, self.channels * self.cells)
