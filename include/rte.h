@@ -113,7 +113,11 @@ typedef struct {
                             0 (default): FP64 basis.  Ignored for RTE_PREC_FP64. */
 } rte_solve_opts;
 
-#define RTE_MAX_L 8
+/* Largest 2D mode count L (M = 2L+1 = 65 modes).  Up to L = 8 pass B couples the modes in
+ * registers per y-frequency; above, the coupling runs as a convolution along the mode axis by
+ * FFTs of length 64, 128 or 256 (the kernel depends on k' - k only, Sec. 3.3.1), or as the direct
+ * Toeplitz sum, whichever the autotuner times faster.  The learned preconditioner takes L <= 8. */
+#define RTE_MAX_L 32
 #define RTE_MAX_L3 3      /* largest spherical-harmonic degree of a 3D context (M = 16 modes) */
 #define RTE_MAX_RESTART 128
 
@@ -126,7 +130,7 @@ typedef struct {
  *              eq. ani_Fouriermode; sigma_hat_{-k} = sigma_hat_k), sigma_hat[0] == 1 (C3) and
  *              |sigma_hat[k]| <= 1; may be NULL when L == 0.  3D: its Legendre coefficients
  *              sigma_hat_l, l = 0..L, with the same conditions
- *   L          2D: number of retained modes on each side, 0..RTE_MAX_L (M = 2L+1); 3D: largest
+ *   L          2D: number of retained modes on each side, 0..RTE_MAX_L (M = 2L+1, up to 65); 3D: largest
  *              spherical-harmonic degree, 0..RTE_MAX_L3 (M = (L+1)^2)
  *   prec       RTE_PREC_FP32 or RTE_PREC_FP64
  *   hip_stream hipStream_t to enqueue on (NULL = default stream)
@@ -219,8 +223,8 @@ int rte_solve_batched(int count, rte_ctx* const* ctxs, const double* const* f_de
  * z = v + s P N(R v / s) of rte_nn.h (R: factor x factor block average, P: bilinear interpolation from
  * the coarse cell centres, s: RMS of v, N: `layers` 3x3 convolutions C -> hidden -> ... -> C with ReLU
  * between, C = 2L+1).  weights_dev: packed float32 parameters (layout in rte_nn.h); the context
- * keeps a BF16 copy.  factor must divide n_x and n_y.  NULL detaches.  2D contexts only.
- * A preconditioned cycle that fails to cut the true residual 10x, or produces a non-finite value,
+ * keeps a BF16 copy.  factor must divide n_x and n_y.  NULL detaches.  2D contexts with L <= 8
+ * only (3D, or L > 8: RTE_EUNSUPPORTED).  A preconditioned cycle that fails to cut the true residual 10x, or produces a non-finite value,
  * is followed by plain GMRES (info.pc_fallback = 1). */
 int rte_pc_attach(rte_ctx* ctx, const float* weights_dev, int hidden, int layers, int factor);
 

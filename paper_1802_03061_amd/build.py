@@ -25,8 +25,8 @@ FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]
 
-SOURCES = ["apply2d.hip", "apply3d.hip", "spectra.hip", "krylov.hip", "rte_api.hip", "nn.hip", "batched.hip",
-           "scatter.hip"]
+SOURCES = ["apply2d.hip", "apply2d_bm.hip", "apply3d.hip", "spectra.hip", "krylov.hip", "rte_api.hip", "nn.hip",
+           "batched.hip", "scatter.hip"]
 
 
 def units():

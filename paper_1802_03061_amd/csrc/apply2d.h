@@ -1,5 +1,6 @@
 // Host-side interface of the 2D FFT apply kernels.
 #pragma once
+#include "../../include/rte.h"
 #include "common.h"
 
 namespace rte {
@@ -7,7 +8,7 @@ namespace rte {
 enum { APPLY_A = 0, APPLY_KT = 1, APPLY_RESID = 2 };
 
 struct ChanScale {
-    double s[2 * 8 + 1];   // per-channel factor applied in pass A (D for operator A, 1 for K~)
+    double s[2 * RTE_MAX_L + 1];   // per-channel factor applied in pass A (D for operator A, 1 for K~)
 };
 
 template <typename T>
@@ -19,6 +20,7 @@ struct Apply2DArgs {
     const cx<T>* twx;          // exp(-2 pi i q/PX), q < PX
     const cx<T>* twy;          // exp(-2 pi i q/PY), q < PY
     hipStream_t stream;
+    const cx<T>* twm = nullptr;   // L > 8: stage twiddles of the mode-axis FFT (length mode_fft_len(L))
     int pack = 0;              // 1: x-frequencies 0 and PX/2 share column 0 of the work buffer
     int var[3] = {0, 0, 0};    // kernel variant of passes A, B, C (see apply2d_variant_count)
     // The input's channels other than channel 0 are zero and pass A ran for channel 0 alone, so

@@ -471,7 +471,7 @@ int apply2d_variant_count(int pass, int L, int PX, int PY) {
         case 7: return pass_b_variants_L7<T>(PY);
         case 8: return pass_b_variants_L8<T>(PY);
     }
-    return 0;
+    return L <= RTE_MAX_L ? 2 : 0;   // mode-axis FFT or direct coupling
 }
 template int apply2d_variant_count<float>(int, int, int, int);
 template int apply2d_variant_count<double>(int, int, int, int);
@@ -494,7 +494,7 @@ int apply2d_pass_b(const Apply2DArgs<T>& a, int nbatch) {
         case 7: return pass_b_L7<T>(a, nbatch);
         case 8: return pass_b_L8<T>(a, nbatch);
     }
-    return -1;
+    return pass_b_large<T>(a, nbatch);
 }
 template <typename T>
 bool apply2d_needs_work2(int L, int PY) {
@@ -509,7 +509,7 @@ bool apply2d_needs_work2(int L, int PY) {
         case 7: return pass_b_split_L7<T>(PY);
         case 8: return pass_b_split_L8<T>(PY);
     }
-    return true;
+    return true;   // L > 8: split form
 }
 template bool apply2d_needs_work2<float>(int, int);
 template bool apply2d_needs_work2<double>(int, int);
@@ -526,7 +526,7 @@ bool apply2d_unpacked(int L, int PY, int var_b) {
         case 7: return pass_b_unpacked_L7<T>(PY, var_b);
         case 8: return pass_b_unpacked_L8<T>(PY, var_b);
     }
-    return false;
+    return true;   // L > 8: split form over unpacked columns
 }
 template bool apply2d_unpacked<float>(int, int, int);
 template bool apply2d_unpacked<double>(int, int, int);

@@ -17,6 +17,7 @@
 #include "apply2d.h"
 #include "apply2d_b.h"
 #include "fft.h"
+#include "passb_split.h"
 
 #ifndef RTE_PASSB_L
 #error "compile with -DRTE_PASSB_L=<L>"
@@ -416,24 +417,6 @@ __global__ __launch_bounds__(NTHR) void k_pass_b_batch(const BatchProb<T>* __res
 }
 #endif
 
-// Split form, step 1/3: forward y-FFT of one (channel, column) into a full-length buffer.
-template <typename T, int PY, int NTHR>
-__global__ __launch_bounds__(NTHR) void k_pass_b_fwd(const cx<T>* __restrict__ Tb, cx<T>* __restrict__ T2,
-                                                     const cx<T>* __restrict__ tw, int ny, int nkx) {
-    constexpr int LD = padded(PY);
-    __shared__ cx<T> buf[LD];
-    __shared__ cx<T> tws[PY];
-    const int tid = threadIdx.x;
-    const int kx = blockIdx.x, bc = blockIdx.y;
-    stage_twiddles<T, PY, NTHR>(tws, tw, tid);
-    const cx<T>* src = Tb + ((size_t)bc * nkx + kx) * ny;
-    for (int y = tid; y < PY; y += NTHR) buf[sw(y)] = y < ny ? src[y] : mk((T)0, (T)0);
-    __syncthreads();
-    block_fft<T, PY, 1, LD, NTHR, false>(buf, tws, tid);
-    cx<T>* dst = T2 + ((size_t)bc * nkx + kx) * PY;
-    for (int y = tid; y < PY; y += NTHR) dst[y] = buf[sw(y)];
-}
-
 // Split form, step 2/3: pointwise coupling over all (kx, ky).
 template <typename T, int PY, int L>
 __global__ __launch_bounds__(256) void k_pass_b_couple(cx<T>* __restrict__ T2, const cx<T>* __restrict__ Q,
@@ -467,24 +450,6 @@ __global__ __launch_bounds__(256) void k_pass_b_couple(cx<T>* __restrict__ T2, c
     couple_modes<T, L>(v, Q, qs, (size_t)kx * KH + fy, flip);
 #pragma unroll
     for (int c = 0; c < C; ++c) p[c * cstride + f] = v[c];
-}
-
-// Split form, step 3/3: inverse y-FFT and crop back into the work buffer.
-template <typename T, int PY, int NTHR>
-__global__ __launch_bounds__(NTHR) void k_pass_b_inv(cx<T>* __restrict__ Tb, const cx<T>* __restrict__ T2,
-                                                     const cx<T>* __restrict__ tw, int ny, int nkx) {
-    constexpr int LD = padded(PY);
-    __shared__ cx<T> buf[LD];
-    __shared__ cx<T> tws[PY];
-    const int tid = threadIdx.x;
-    const int kx = blockIdx.x, bc = blockIdx.y;
-    stage_twiddles<T, PY, NTHR>(tws, tw, tid);
-    const cx<T>* src = T2 + ((size_t)bc * nkx + kx) * PY;
-    for (int y = tid; y < PY; y += NTHR) buf[sw(y)] = src[y];
-    __syncthreads();
-    block_fft<T, PY, 1, LD, NTHR, true>(buf, tws, tid);
-    cx<T>* dst = Tb + ((size_t)bc * nkx + kx) * ny;
-    for (int y = tid; y < ny; y += NTHR) dst[y] = buf[sw(y)];
 }
 
 constexpr int lds_budget() { return 160 * 1024; }
@@ -559,17 +524,13 @@ static int launch_py(const Apply2DArgs<T>& a, int nbatch) {
         return 0;
     } else {
         if (!a.work2) return -2;
-        constexpr int NT = PY >= 256 ? 256 : (PY < 64 ? 64 : PY);
         if (a.single_in && nbatch != 1) return -3;
-        dim3 g1(nkx, nbatch * C);
-        dim3 g1f(nkx, a.single_in ? 1 : nbatch * C);   // single_in: channel 0 only
-        hipLaunchKernelGGL((k_pass_b_fwd<T, PY, NT>), g1f, dim3(NT), 0, a.stream, a.work, a.work2, a.twy, a.ny,
-                           nkx);
+        const size_t nseq = (size_t)nbatch * C * nkx;
+        split_fft<T, PY, false>(a.work, a.work2, a.twy, a.ny, a.single_in ? (size_t)nkx : nseq, a.stream);  // single_in: channel 0 only
         dim3 g2((unsigned)(((size_t)nkx * PY + 255) / 256), nbatch);
         hipLaunchKernelGGL((k_pass_b_couple<T, PY, L>), g2, dim3(256), 0, a.stream, a.work2, a.Q, nkx, nkq,
                            a.pack, a.single_in);
-        hipLaunchKernelGGL((k_pass_b_inv<T, PY, NT>), g1, dim3(NT), 0, a.stream, a.work, a.work2, a.twy, a.ny,
-                           nkx);
+        split_fft<T, PY, true>(a.work, a.work2, a.twy, a.ny, nseq, a.stream);
         return 0;
     }
 }

@@ -23,6 +23,9 @@ struct rte_ctx {
     double* Q3d = nullptr;
     rte::cx<float>* twf[3] = {nullptr, nullptr, nullptr};
     rte::cx<double>* twd[3] = {nullptr, nullptr, nullptr};
+    // 2D with L > 8: stage twiddles of the FFT along the mode axis (pass-B coupling)
+    rte::cx<float>* twmf = nullptr;
+    rte::cx<double>* twmd = nullptr;
     // FFT work buffers (2D: T and the split pass-B buffer; 3D: T1 and T2)
     rte::cx<float>* wf = nullptr;
     rte::cx<float>* wf2 = nullptr;

@@ -1218,6 +1218,7 @@ int rte_pc_attach(rte_ctx* c, const float* weights, int hidden, int layers, int 
     pc_free(c);
     if (!weights) return RTE_OK;
     if (c->dim != 2) return set_error(RTE_EUNSUPPORTED, "the learned preconditioner is 2D only");
+    if (c->C > 17) return set_error(RTE_EUNSUPPORTED, "the learned preconditioner takes up to 17 channels (L <= 8)");
     if (!valid_net(c->C, hidden, layers)) return set_error(RTE_EINVAL, "bad network shape");
     if (factor < 1 || c->nx % factor || c->ny % factor) return set_error(RTE_EINVAL, "factor must divide n_x and n_y");
     if (c->nx > 512) return set_error(RTE_EUNSUPPORTED, "grid too wide for the restriction kernel");

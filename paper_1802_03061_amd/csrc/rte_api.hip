@@ -24,6 +24,7 @@
 
 #include "../../include/rte.h"
 #include "apply2d.h"
+#include "apply2d_b.h"
 #include "apply3d.h"
 #include "sh3d.h"
 #include "ctx.h"
@@ -105,6 +106,8 @@ static void free_ctx(rte_ctx* c) {
         dfree(c->twf[a]);
         dfree(c->twd[a]);
     }
+    dfree(c->twmf);
+    dfree(c->twmd);
     dfree(c->wf);
     dfree(c->wf2);
     dfree(c->wd);
@@ -213,12 +216,14 @@ static Apply2DArgs<T> args2d(const rte_ctx* c);
 template <>
 Apply2DArgs<float> args2d<float>(const rte_ctx* c) {
     Apply2DArgs<float> a{c->nx, c->ny, c->PX, c->PY, c->L, c->C, c->wf, c->wf2, c->Qf, c->twf[0], c->twf[1], c->stream};
+    a.twm = c->twmf;
     for (int p = 0; p < 3; ++p) a.var[p] = c->varf[p];
     return a;
 }
 template <>
 Apply2DArgs<double> args2d<double>(const rte_ctx* c) {
     Apply2DArgs<double> a{c->nx, c->ny, c->PX, c->PY, c->L, c->C, c->wd, c->wd2, c->Qd, c->twd[0], c->twd[1], c->stream};
+    a.twm = c->twmd;
     for (int p = 0; p < 3; ++p) a.var[p] = c->vard[p];
     return a;
 }
@@ -769,9 +774,11 @@ int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const 
     hipError_t e = hipGetDevice(&c->device);
     if (e != hipSuccess) { free_ctx(c); return set_hip_error(e, "hipGetDevice", __FILE__, __LINE__); }
 
-    // twiddles
-    const int Ps[3] = {c->PX, c->PY, c->PZ};
-    for (int a = 0; a < c->dim; ++a) {
+    // twiddles of the grid axes, and of the mode axis when pass B couples the modes by an FFT
+    const bool mode_fft = c->dim == 2 && c->L > PASSB_FUSED_MAX_L;
+    const int Ps[4] = {c->PX, c->PY, c->PZ, mode_fft ? mode_fft_len(c->L) : 0};
+    for (int a = 0; a < 4; ++a) {
+        if (a >= c->dim && !(a == 3 && mode_fft)) continue;
         std::vector<double> re, im;
         twiddles(Ps[a], re, im);
         std::vector<cx<double>> td(Ps[a]);
@@ -780,9 +787,11 @@ int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const 
             td[q] = mk(re[q], im[q]);
             tf[q] = mk((float)re[q], (float)im[q]);
         }
-        if ((rc = dalloc(&c->twd[a], Ps[a])) || (rc = dalloc(&c->twf[a], Ps[a]))) { free_ctx(c); return rc; }
-        e = hipMemcpy(c->twd[a], td.data(), Ps[a] * sizeof(cx<double>), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(c->twf[a], tf.data(), Ps[a] * sizeof(cx<float>), hipMemcpyHostToDevice);
+        cx<double>*& dd = a < 3 ? c->twd[a] : c->twmd;
+        cx<float>*& ff = a < 3 ? c->twf[a] : c->twmf;
+        if ((rc = dalloc(&dd, Ps[a])) || (rc = dalloc(&ff, Ps[a]))) { free_ctx(c); return rc; }
+        e = hipMemcpy(dd, td.data(), Ps[a] * sizeof(cx<double>), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(ff, tf.data(), Ps[a] * sizeof(cx<float>), hipMemcpyHostToDevice);
         if (e != hipSuccess) { free_ctx(c); return set_hip_error(e, "twiddle upload", __FILE__, __LINE__); }
     }
     const bool f32 = prec == RTE_PREC_FP32;

@@ -101,7 +101,11 @@ extern "C" int rte_scattering_term(rte_ctx* c, int layout, const void* u, int nt
 #define RTE_SC_CASE(LL) \
     case LL: launch_scatter<LL>((const double*)u, modes, c->ncell, ntheta, cf, S, c->stream); break;
         RTE_SC_CASE(0) RTE_SC_CASE(1) RTE_SC_CASE(2) RTE_SC_CASE(3) RTE_SC_CASE(4) RTE_SC_CASE(5) RTE_SC_CASE(6)
-        RTE_SC_CASE(7) RTE_SC_CASE(8)
+        RTE_SC_CASE(7) RTE_SC_CASE(8) RTE_SC_CASE(9) RTE_SC_CASE(10) RTE_SC_CASE(11) RTE_SC_CASE(12)
+        RTE_SC_CASE(13) RTE_SC_CASE(14) RTE_SC_CASE(15) RTE_SC_CASE(16) RTE_SC_CASE(17) RTE_SC_CASE(18)
+        RTE_SC_CASE(19) RTE_SC_CASE(20) RTE_SC_CASE(21) RTE_SC_CASE(22) RTE_SC_CASE(23) RTE_SC_CASE(24)
+        RTE_SC_CASE(25) RTE_SC_CASE(26) RTE_SC_CASE(27) RTE_SC_CASE(28) RTE_SC_CASE(29) RTE_SC_CASE(30)
+        RTE_SC_CASE(31) RTE_SC_CASE(32)
 #undef RTE_SC_CASE
         default: return set_error(RTE_EUNSUPPORTED, "L = %d", c->L);
     }

@@ -19,7 +19,7 @@ RTE_EINVAL, RTE_ENOMEM, RTE_EDEVICE, RTE_ENUMERIC, RTE_EUNSUPPORTED = -1, -2, -3
 PREC_FP32, PREC_FP64 = 0, 1
 OP_A, OP_KT = 0, 1
 LAYOUT_MODES, LAYOUT_CHANNELS = 0, 1
-MAX_L = 8
+MAX_L = 32
 MAX_L3 = 3          # RTE_MAX_L3: largest spherical-harmonic degree of a 3D context
 MAX_RHS = 64        # RTE_MAX_RHS: right-hand sides of one rte_solve_multi call
 NN_SCRATCH_BYTES = 32 << 20      # RTE_NN_SCRATCH_BYTES of rte_nn.h

@@ -49,7 +49,7 @@ def _grid(rte, dim=2, n=(16, 16, 1), h=1 / 16):
 
 @pytest.mark.parametrize("case", [
     dict(dim=4), dict(n=(1, 16, 1)), dict(h=0.0), dict(h=-1.0), dict(mu_a=-0.1), dict(mu_s=-1.0),
-    dict(mu_a=0.0, mu_s=0.0), dict(L=-1), dict(L=9), dict(prec=7), dict(sigma=[0.5, 0.2], L=1),
+    dict(mu_a=0.0, mu_s=0.0), dict(L=-1), dict(L=33), dict(prec=7), dict(sigma=[0.5, 0.2], L=1),
     dict(sigma=[1.0, 1.5], L=1), dict(sigma=None, L=2),
 ])
 def test_setup_rejects_invalid_arguments(lib, case):

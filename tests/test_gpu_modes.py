@@ -1,0 +1,169 @@
+"""Many angular modes in 2D (L = 9..32, up to 65 modes) against the CPU oracle through the C ABI.
+
+Above L = 8 pass B couples the modes at each frequency either by a convolution along the mode axis
+computed with FFTs (the kernel depends on k' - k only, Sec. 3.3.1) or by the direct Toeplitz sum;
+both variants are checked: the apply on small ragged grids against the oracle's direct double sum,
+sampled rows of a 128^2 apply against the oracle's row sums, solves against dense LU, a 256^2
+solve whose true residual the oracle's FFT apply confirms, and the size limits.  Bars: FP64 path
+1e-12 (apply) / 1e-10 (solve); FP32 path 1e-6, as for few modes (the FP32 FFTs along the grid axes
+and the mode axis add a few units of 6e-8 per stage; up to 256 along the mode axis adds one
+stage over the direct sum)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import dev, host, relerr, say
+from oracle import krylov as kr
+from oracle import operator2d as op2
+import oracle_ref
+from paper_1802_03061_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+TOL32 = 1e-6
+
+
+@pytest.fixture(scope="module")
+def rte():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1802_03061_amd import rte as r
+    r.load()
+    return r
+
+
+def _to_ch(u, L):
+    """Channels of conjugate-symmetric modes: W_0, then sqrt2 Re W_k, sqrt2 Im W_k for k = 1..L."""
+    out = [u[L].real]
+    for k in range(1, L + 1):
+        out += [np.sqrt(2) * u[L + k].real, np.sqrt(2) * u[L + k].imag]
+    return np.stack(out)
+
+
+def _ctx(rte, nx, ny, L, prec, mu_a=0.1, mu_s=2.0, g=0.7):
+    sh = inputs.hg_sigma_hat(g, L)
+    h = 1.0 / max(nx, ny)
+    return rte.Context((nx, ny), h=h, mu_a=mu_a, mu_s=mu_s, sigma_hat=sh, L=L, prec=prec), sh, h
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("L,ny,nx", [(9, 5, 7), (15, 8, 8), (16, 3, 12), (24, 6, 5), (31, 4, 4), (32, 5, 6)])
+def test_apply_small_vs_direct(rte, prec, L, ny, nx):
+    """Random complex modes (operators A and K~) and random real channels, both pass-B variants."""
+    say("modes apply small", L, ny, nx, "prec", prec)
+    rng = np.random.default_rng(100 * L + ny)
+    ctx, sh, h = _ctx(rte, nx, ny, L, prec)
+    M = 2 * L + 1
+    assert ctx.modes == M and ctx.channels == M
+    u = rng.standard_normal((M, ny, nx)) + 1j * rng.standard_normal((M, ny, nx))
+    ref = {name: op2.apply_direct(u, L, h, 2.1, 2.0, sh, name) for name in ("A", "KT")}
+    g = inputs.random_conj_symmetric_modes(rng, L, max(nx, ny))[:, :ny, :nx].copy()
+    refc = _to_ch(op2.apply_direct(g, L, h, 2.1, 2.0, sh, "A"), L)
+    _, nv = ctx.get_variant(prec, 1)
+    assert nv == 2
+    bar = TOL64 if prec == 1 else TOL32
+    for v in range(nv):
+        ctx.set_variant(prec, 1, v)
+        for op, name in ((rte.OP_A, "A"), (rte.OP_KT, "KT")):
+            y = host(ctx.apply(dev(u), op=op, prec=prec))
+            e = relerr(y, ref[name])
+            say(f"  variant {v} op {name} modes relerr {e:.2e}")
+            assert e <= bar
+        yc = host(ctx.apply(dev(_to_ch(g, L)), op=rte.OP_A, prec=prec, layout=rte.LAYOUT_CHANNELS))
+        e = relerr(yc, refc)
+        say(f"  variant {v} channels relerr {e:.2e}")
+        assert e <= bar
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_rhs_large_L_vs_oracle(rte, prec):
+    n, L = 9, 20
+    ctx, sh, h = _ctx(rte, n, n, L, prec)
+    f = inputs.gaussian_mixture_source(n, inputs.gaussian_mixture_params(np.random.default_rng(4), 2))
+    b = host(ctx.rhs(dev(f)))
+    ref = op2.rhs(f, L, h, 2.1, method="direct")
+    e = relerr(b, ref)
+    say("modes rhs L", L, "prec", prec, "relerr", e)
+    assert e <= TOL64     # the right-hand side is formed by the FP64 apply
+    ctx.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("L,prec", [(24, 1), (24, 0), (12, 0)])
+def test_apply_128_sampled_vs_row_sums(rte, L, prec):
+    """128^2 (256^2 padded): sampled output cells (corners, edges, interior) against the oracle's
+    row sums over every cell and mode, for both pass-B variants."""
+    n = 128
+    ctx, sh, h = _ctx(rte, n, n, L, prec, mu_a=0.05, mu_s=5.0, g=0.8)
+    M = 2 * L + 1
+    rng = np.random.default_rng(7 + L)
+    u = rng.standard_normal((M, n, n)) + 1j * rng.standard_normal((M, n, n))
+    cells = [(0, 0), (127, 127), (0, 127), (64, 64), (31, 100), (127, 3)]
+    ref = op2.apply_sampled(u, cells, L, h, 5.05, 5.0, sh)
+    for v in range(2):
+        ctx.set_variant(prec, 1, v)
+        say("modes apply 128 sampled L", L, "prec", prec, "variant", v)
+        y = host(ctx.apply(dev(u), prec=prec))
+        got = np.array([y[:, iy, ix] for iy, ix in cells])
+        e = float(np.abs(got - ref).max() / np.abs(ref).max())
+        say(f"  sampled max relerr {e:.2e}")
+        assert e <= (1e-11 if prec == 1 else 1e-6)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("L,n,mu_s", [(12, 6, 4.0), (32, 4, 8.0)])
+def test_solve_large_L_vs_lu(rte, prec, L, n, mu_s):
+    say("modes solve small", L, n, mu_s, "prec", prec)
+    mu_a = 0.1
+    ctx, sh, h = _ctx(rte, n, n, L, prec, mu_a=mu_a, mu_s=mu_s, g=0.8)
+    f = np.random.default_rng(n + L).random((n, n))
+    for v in range(2):
+        ctx.set_variant(prec, 1, v)
+        u, info = ctx.solve(dev(f), tol=1e-11)
+        say("  variant", v, "info", info)
+        A = op2.dense_A(n, n, L, h, mu_a + mu_s, mu_s, sh)
+        b = op2.rhs(f, L, h, mu_a + mu_s, method="direct")
+        ref = kr.solve_dense(A, b.reshape(-1)).reshape(b.shape)
+        e = relerr(host(u), ref)
+        say("  relerr vs LU", e)
+        assert e <= (1e-10 if prec == 1 else 1e-6)
+    ctx.close()
+
+
+@pytest.mark.timeout(900)
+def test_solve_256_L16_true_residual(rte):
+    """256^2, L = 16 (33 modes), HG g = 0.9, mu_a = 0.05, mu_s = 10, two-Gaussian source: the FP32
+    apply with FP64 Krylov to 1e-8 after autotuning; the oracle's FP64 FFT apply confirms the true
+    residual of the GPU solution, and the density is positive."""
+    n, L = 256, 16
+    mu_a, mu_s = 0.05, 10.0
+    sh = inputs.hg_sigma_hat(0.9, L)
+    f = inputs.paper_sources(n)["f1"]
+    ctx = rte.Context(n, mu_a=mu_a, mu_s=mu_s, sigma_hat=sh, L=L, prec=rte.PREC_FP32)
+    ctx.autotune()
+    say("modes solve 256 L16, pass-B variant", ctx.get_variant(rte.PREC_FP32, 1))
+    u, info = ctx.solve(dev(f), tol=1e-8)
+    say("  info", info)
+    uu = host(u)
+    ctx.close()
+    h = 1.0 / n
+    sp = op2.kernel_spectra(n, n, L, h, mu_a + mu_s, workers=oracle_ref.WORKERS)
+    b = op2.rhs(f, L, h, mu_a + mu_s, spectra=sp, workers=oracle_ref.WORKERS)
+    r = b - op2.apply_fft(uu, L, h, mu_a + mu_s, mu_s, sh, spectra=sp, workers=oracle_ref.WORKERS)
+    rr = float(np.linalg.norm(r) / np.linalg.norm(b))
+    say("  oracle true residual", rr)
+    assert rr <= 1.5e-8
+    assert uu[L].real.min() >= -1e-7 * np.abs(uu[L]).max()
+
+
+def test_limits(rte):
+    with pytest.raises(rte.RteError) as ei:
+        rte.Context(8, mu_a=0.1, mu_s=1.0, L=33, sigma_hat=inputs.hg_sigma_hat(0.5, 33))
+    assert ei.value.code == rte.RTE_EINVAL
+    ctx = rte.Context(8, mu_a=0.1, mu_s=1.0, L=9, sigma_hat=inputs.hg_sigma_hat(0.5, 9))
+    with pytest.raises(rte.RteError) as ei:
+        ctx.attach_pc(torch.zeros(100000, dtype=torch.float32, device="cuda"), hidden=32, layers=5, factor=2)
+    assert ei.value.code == rte.RTE_EUNSUPPORTED
+    ctx.close()

@@ -33,7 +33,7 @@ def _to_ch(u, L):
 
 @pytest.mark.parametrize("L,ny,nx,ntheta", [(0, 9, 7, 5), (2, 12, 10, 1), (3, 16, 16, 64), (8, 11, 13, 100),
                                             (4, 5, 21, 130), (1, 3, 300, 7), (5, 4, 6, 9), (6, 2, 2, 3),
-                                            (7, 7, 3, 64)])
+                                            (7, 7, 3, 64), (12, 6, 5, 17), (32, 4, 3, 65)])
 def test_scattering_term_small_vs_oracle(rte, L, ny, nx, ntheta):
     say("scattering", L, ny, nx, ntheta)
     rng = np.random.default_rng(L * 31 + ny)

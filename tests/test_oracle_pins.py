@@ -25,7 +25,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 # ---------------------------------------------------------------- self-cell integrals ----------
 
 @pytest.mark.parametrize("mu_t", [0.0, 1.1, 10.1, 50.01])
-@pytest.mark.parametrize("m", [0, 2, 4, 8, 16])
+@pytest.mark.parametrize("m", [0, 2, 4, 8, 16, 36, 64])
 def test_self_cell_2d_vs_polar_brute_force(mu_t, m):
     """Exact cell integral vs adaptive 2D quadrature with the radial integral done numerically
     over the whole circle (no use of the square's 8-fold symmetry or of the 1D reduction)."""
@@ -46,7 +46,9 @@ def test_self_cell_2d_vs_polar_brute_force(mu_t, m):
     if m % 4:
         assert got == 0.0 and abs(re) < 1e-15
     else:
-        assert abs(got - re) <= 1e-12 * abs(re)
+        # for large m the integral is a cancellation of terms of size h, so the rounding floor of
+        # both evaluations is absolute, a few units of 1e-16 h
+        assert abs(got - re) <= 1e-12 * abs(re) + 1e-14 * h
 
 
 @pytest.mark.parametrize("mu_t", [0.5, 20.0])
@@ -126,10 +128,11 @@ def test_aniso_kernel_J_hermitian_not_hermitian():
     assert np.abs(lhs - Kd).max() > 1e-3 * np.abs(Kd).max()
 
 
-def test_fft_apply_equals_direct_sum():
-    """Circulant embedding (Sec. 2.3.1, 3.3.1) reproduces the direct double sum, ragged grid."""
+@pytest.mark.parametrize("L,ny,nx", [(2, 7, 10), (16, 4, 5)])
+def test_fft_apply_equals_direct_sum(L, ny, nx):
+    """Circulant embedding (Sec. 2.3.1, 3.3.1) reproduces the direct double sum, ragged grid, few
+    and many modes."""
     rng = np.random.default_rng(1)
-    ny, nx, L = 7, 10, 2
     h, mu_t, mu_s = 0.1, 2.3, 1.9
     sh = inputs.hg_sigma_hat(0.6, L)
     u = rng.standard_normal((2 * L + 1, ny, nx)) + 1j * rng.standard_normal((2 * L + 1, ny, nx))
@@ -140,8 +143,9 @@ def test_fft_apply_equals_direct_sum():
     A = op2.dense_A(ny, nx, L, h, mu_t, mu_s, sh)
     y3 = (A @ u.reshape(-1)).reshape(u.shape)
     assert np.linalg.norm(y3 - op2.apply_direct(u, L, h, mu_t, mu_s, sh)) <= 1e-14 * np.linalg.norm(y3)
-    ys = op2.apply_sampled(u, [(0, 0), (6, 9), (3, 4)], L, h, mu_t, mu_s, sh)
-    for c, (iy, ix) in enumerate([(0, 0), (6, 9), (3, 4)]):
+    cells = [(0, 0), (ny - 1, nx - 1), (ny // 2, nx // 2)]
+    ys = op2.apply_sampled(u, cells, L, h, mu_t, mu_s, sh)
+    for c, (iy, ix) in enumerate(cells):
         assert np.abs(ys[c] - y3[:, iy, ix]).max() <= 1e-14 * np.abs(y3).max()
 
 
