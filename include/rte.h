@@ -257,7 +257,7 @@ int rte_autotune(rte_ctx* ctx, int reps);
 int rte_set_variant(rte_ctx* ctx, int prec, int pass, int variant);
 int rte_get_variant(const rte_ctx* ctx, int prec, int pass, int* variant, int* count);
 
-/* Sizes: *channels = 2L+1 (3D: 1), *modes = 2L+1, *cells = n_x n_y (n_z). */
+/* Sizes: *channels = *modes = 2L+1 (2D) or (L+1)^2 (3D), *cells = n_x n_y (n_z). */
 int rte_query(const rte_ctx* ctx, int* channels, int* modes, long long* cells);
 
 /* Pack complex modes (must be conjugate-symmetric) into channels, and back. FP64, asynchronous. */
