@@ -144,7 +144,7 @@ __device__ __forceinline__ void couple_packed_pair(PF p, PM pm, const cx<T>* __r
 // Fused pass B: NCOL columns x C channels per block, spectra resident in LDS.
 // base: the batch entry's [C][nkx][ny] work buffer; nkx = its columns, nkq = columns of the kernel
 // table (PX/2 + 1); kx0 = the block's first column.
-template <typename T, int PY, int L, int NCOL, int NTHR, int GV = 0>
+template <typename T, int PY, int L, int NCOL, int NTHR, int GV = 0, int SCH = 0>
 __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T>* __restrict__ Q, int ny, int nkx,
                                             int nkq, int pack, int kx0, cx<T>* spec, const cx<T>* tws,
                                             cx<T>* pairtmp, int tid, int single = 0) {
@@ -159,7 +159,7 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
     // Rows y >= ny (<= PY/2) are zero padding, so the first Stockham stage (radix R0, no twiddles)
     // is done in registers straight from the loads: butterfly j takes inputs y = j + r PY/R0, of
     // which only r < R0/2 can be non-zero, and writes its R0 outputs at j R0 + r.
-    constexpr int R0 = fft_radix(PY, 1);
+    constexpr int R0 = fft_radix(PY, 1, SCH);
     constexpr int NB0 = PY / R0;
     constexpr int NBT = NF * NB0;
     constexpr int IT = (NBT + NTHR - 1) / NTHR;
@@ -192,13 +192,19 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
     }
     __syncthreads();
     // at most ~3 radix-8 butterflies per thread and stage, or groups of GV transforms if given
-    constexpr int G0 = (3 * NTHR * 8) / PY >= NF ? NF : ((3 * NTHR * 8) / PY < 1 ? 1 : (3 * NTHR * 8) / PY);
+    // (the radix-32 schedule transforms every sequence at once)
+    constexpr int G0 = SCH == 1 ? NF
+                                : ((3 * NTHR * 8) / PY >= NF ? NF : ((3 * NTHR * 8) / PY < 1 ? 1 : (3 * NTHR * 8) / PY));
     constexpr int G = GV > 0 ? (GV < NF ? GV : NF) : G0;
-    block_fft_grouped_range<T, PY, NF, G, LD, NTHR, false, R0, PY>(spec, tws, tid);
+    block_fft_grouped_range<T, PY, NF, G, LD, NTHR, false, R0, PY, SCH>(spec, tws, tid);
     const size_t qs = (size_t)nkq * KH;
+    // Frequencies are visited in the order [0, PY/4), [3PY/4, PY), [PY/4, 3PY/4): with PY/2 threads
+    // a frequency and its mirror PY - f, which read the same quarter-table entries, fall in the
+    // same sweep, so the second read finds the entries in L2.
 #pragma unroll 1
     for (int idx = tid; idx < NCOL * PY; idx += NTHR) {
-        const int f = idx % PY, col = idx / PY;
+        const int fi = idx % PY, col = idx / PY;
+        const int f = fi < PY / 4 ? fi : (fi < PY / 2 ? fi + PY / 2 : fi - PY / 4);
         const int kx = kx0 + col;
         if (kx >= nkx) continue;
         cx<T>* sp = spec + col * C * LD;
@@ -232,10 +238,10 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
     __syncthreads();
     // Inverse y-FFT: every stage but the last in LDS; the last stage (sub-length NSL, radix RL) goes
     // straight to memory, where only its outputs y = j + r NSL < ny are kept.
-    constexpr int NSL = fft_last_ns(PY);
+    constexpr int NSL = fft_last_ns(PY, SCH);
     constexpr int RL = PY / NSL;
-    block_fft_grouped_range<T, PY, NF, G, LD, NTHR, true, 1, NSL>(spec, tws, tid);
-    constexpr int TWL = stage_tw_offset(PY, NSL);
+    block_fft_grouped_range<T, PY, NF, G, LD, NTHR, true, 1, NSL, SCH>(spec, tws, tid);
+    constexpr int TWL = stage_tw_offset(PY, NSL, SCH);
     for (int idx = tid; idx < NF * NSL; idx += NTHR) {
         const int j = idx % NSL, fc = idx / NSL;
         const int col = fc / C, c = fc % C;
@@ -262,7 +268,7 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
     }
 }
 
-template <typename T, int PY, int L, int NCOL, int NTHR, int GV>
+template <typename T, int PY, int L, int NCOL, int NTHR, int GV, int SCH = 0>
 __global__ __launch_bounds__(NTHR) void k_pass_b_lds(cx<T>* __restrict__ Tb, const cx<T>* __restrict__ Q,
                                                      const cx<T>* __restrict__ tw, int ny, int nkx, int nkq,
                                                      int pack, int single) {
@@ -272,7 +278,7 @@ __global__ __launch_bounds__(NTHR) void k_pass_b_lds(cx<T>* __restrict__ Tb, con
     __shared__ cx<T> pairtmp[2 * C];   // Q of the two self-mirrored frequencies of a packed column
     const int tid = threadIdx.x;
     stage_twiddles<T, PY, NTHR>(tws, tw, tid);
-    pass_b_cols<T, PY, L, NCOL, NTHR, GV>(Tb + (size_t)blockIdx.y * C * nkx * ny, Q, ny, nkx, nkq, pack,
+    pass_b_cols<T, PY, L, NCOL, NTHR, GV, SCH>(Tb + (size_t)blockIdx.y * C * nkx * ny, Q, ny, nkx, nkq, pack,
                                           blockIdx.x * NCOL, spec, tws, pairtmp, tid, single);
 }
 
@@ -481,18 +487,23 @@ constexpr bool reg_variant() {   // the register-resident form as an FP32 varian
 }
 
 template <typename T, int PY, int L>
-constexpr int fused_variants() {
+constexpr int fused_variants_base() {
     constexpr int C = 2 * L + 1;
     constexpr int NF = ncol_for<T, PY, L>() * C * PY;
     if (PY < 128) return 1;
     return reg_variant<T, PY, L>() ? 4 : ((sizeof(T) == 4 && NF / 8 >= 1024) ? 3 : 2);
 }
+// The radix-32 schedule (fft.h, schedule 1) as the last variant, for padded y >= 256.
+template <typename T, int PY, int L>
+constexpr bool sched_variant() { return PY >= 256; }
+template <typename T, int PY, int L>
+constexpr int fused_variants() { return fused_variants_base<T, PY, L>() + (sched_variant<T, PY, L>() ? 1 : 0); }
 
-template <typename T, int PY, int L, int NCOL, int NT, int GV>
+template <typename T, int PY, int L, int NCOL, int NT, int GV, int SCH = 0>
 static void launch_fused(const Apply2DArgs<T>& a, int nbatch, int nkx, int nkq) {
     dim3 grid((nkx + NCOL - 1) / NCOL, nbatch);
-    hipLaunchKernelGGL((k_pass_b_lds<T, PY, L, NCOL, NT, GV>), grid, dim3(NT), 0, a.stream, a.work, a.Q, a.twy, a.ny,
-                       nkx, nkq, a.pack, a.single_in);
+    hipLaunchKernelGGL((k_pass_b_lds<T, PY, L, NCOL, NT, GV, SCH>), grid, dim3(NT), 0, a.stream, a.work, a.Q,
+                       SCH == 1 ? a.twy1 : a.twy, a.ny, nkx, nkq, a.pack, a.single_in);
 }
 
 template <typename T, int PY>
@@ -504,7 +515,14 @@ static int launch_py(const Apply2DArgs<T>& a, int nbatch) {
     if constexpr (fused_fits<T, PY, L>()) {
         constexpr int NCOL = ncol_for<T, PY, L>();
         constexpr int NT = nthr_for<T, NCOL * C * PY>();
-        constexpr int NV = fused_variants<T, PY, L>();
+        constexpr int NV = fused_variants_base<T, PY, L>();
+        if constexpr (sched_variant<T, PY, L>()) {
+            if (a.var[1] == NV) {
+                if (!a.twy1) return -5;
+                launch_fused<T, PY, L, NCOL, NT, 0, 1>(a, nbatch, nkx, nkq);
+                return 0;
+            }
+        }
         if constexpr (reg_variant<T, PY, L>()) {
             if (a.var[1] == 3) {   // the work buffer is unpacked for this variant (apply2d_pack)
                 if (a.pack) return -4;

@@ -22,19 +22,24 @@ namespace rte {
 __device__ __forceinline__ int sw(int i) { return i + (i >> 4); }
 constexpr int padded(int P) { return P + P / 16; }
 
-constexpr int fft_radix(int P, int Ns) {
-    // r = log2 of what remains to be combined: radix 8 stages, led by one radix-16 stage when
-    // r = 1 (mod 3) and r >= 4 (2 when r = 1), or one radix-4 stage when r = 2 (mod 3)
-    return (ilog2(P) - ilog2(Ns)) % 3 == 1 ? ((ilog2(P) - ilog2(Ns)) >= 4 ? 16 : 2)
-                                           : ((ilog2(P) - ilog2(Ns)) % 3 == 2 ? 4 : 8);
+// Radix schedules: S = 0 (default) and S = 1 (radix 32: two stages at length 1024, fewer LDS
+// round trips per transform at the price of more registers per butterfly).
+constexpr int fft_radix(int P, int Ns, int S = 0) {
+    // r = log2 of what remains to be combined.
+    // S = 0: radix 8 stages, led by one radix-16 stage when r = 1 (mod 3) and r >= 4 (2 when
+    // r = 1), or one radix-4 stage when r = 2 (mod 3).
+    // S = 1: radix 32 stages, led by one stage of radix 2^(r mod 5) when r is not a multiple of 5.
+    return S == 1 ? ((ilog2(P) - ilog2(Ns)) % 5 == 0 ? 32 : (1 << ((ilog2(P) - ilog2(Ns)) % 5)))
+                  : ((ilog2(P) - ilog2(Ns)) % 3 == 1 ? ((ilog2(P) - ilog2(Ns)) >= 4 ? 16 : 2)
+                                                     : ((ilog2(P) - ilog2(Ns)) % 3 == 2 ? 4 : 8));
 }
 
 // Offset of the twiddles of the stage with sub-transform length NS (> 1) in the per-stage table;
 // the table holds sum over those stages of NS (R - 1) = P - (first radix) entries.
-constexpr int stage_tw_offset(int P, int NS) {
+constexpr int stage_tw_offset(int P, int NS, int S = 0) {
     int off = 0, ns = 1;
     while (ns < NS) {
-        const int R = fft_radix(P, ns);
+        const int R = fft_radix(P, ns, S);
         if (ns > 1) off += ns * (R - 1);
         ns *= R;
     }
@@ -87,6 +92,38 @@ __device__ __forceinline__ void dft_small(cx<T>* v) {
 #pragma unroll
             for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
         }
+    } else if constexpr (R == 32) {
+        // 32 = 8 x 4: v[8 n1 + n2] -> A[n2][k1] = DFT4 over n1, times W32^(n2 k1), then
+        // X[k1 + 4 k2] = DFT8 over n2.  W32^q = cos(pi q/16) -+ i sin(pi q/16), q = n2 k1 <= 21.
+        const T c1 = (T)0.98078528040323044912618223613424, s1 = (T)0.19509032201612826784828486847702;
+        const T c2 = (T)0.92387953251128675612818318939679, s2 = (T)0.38268343236508977172845998403040;
+        const T c3 = (T)0.83146961230254523707878837761791, s3 = (T)0.55557023301960222474283081394853;
+        const T rh = (T)0.70710678118654752440084436210485;
+        const T wr[22] = {(T)1, c1, c2, c3, rh, s3, s2, s1, (T)0, -s1, -s2, -s3, -rh, -c3, -c2, -c1,
+                          (T)-1, -c1, -c2, -c3, -rh, -s3};
+        const T wi[22] = {(T)0, s1, s2, s3, rh, c3, c2, c1, (T)1, c1, c2, c3, rh, s3, s2, s1,
+                          (T)0, -s1, -s2, -s3, -rh, -c3};   // sin(pi q / 16)
+        cx<T> a[8][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < 4; ++n1) a[n2][n1] = v[8 * n1 + n2];
+            dft_small<T, 4, INV>(a[n2]);
+#pragma unroll
+            for (int k1 = 1; k1 < 4; ++k1) {
+                if (n2 == 0) continue;
+                const int q = n2 * k1;
+                const cx<T> w = mk(wr[q], INV ? wi[q] : -wi[q]);
+                a[n2][k1] = a[n2][k1] * w;
+            }
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            cx<T> b[8] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1], a[4][k1], a[5][k1], a[6][k1], a[7][k1]};
+            dft_small<T, 8, INV>(b);
+#pragma unroll
+            for (int k2 = 0; k2 < 8; ++k2) v[k1 + 4 * k2] = b[k2];
+        }
     } else {  // R == 8: two 4-point DFTs on the even and odd samples, then W8^q
         cx<T> e[4] = {v[0], v[2], v[4], v[6]};
         cx<T> o[4] = {v[1], v[3], v[5], v[7]};
@@ -111,13 +148,13 @@ __device__ __forceinline__ void dft_small(cx<T>* v) {
 }
 
 // One in-place Stockham stage over NFFT transforms of length P at buf + f*LD (swizzled).
-template <typename T, int P, int NFFT, int LD, int NTHR, int R, int NS, bool INV>
+template <typename T, int P, int NFFT, int LD, int NTHR, int R, int NS, bool INV, int SCH = 0>
 __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* tw, int tid) {
     constexpr int NB = P / R;
     constexpr int TOTAL = NB * NFFT;
     constexpr int ITEMS = (TOTAL + NTHR - 1) / NTHR;
     constexpr int S = NS * R;
-    constexpr int TWOFF = stage_tw_offset(P, NS);
+    constexpr int TWOFF = stage_tw_offset(P, NS, SCH);
     cx<T> v[ITEMS][R];
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
@@ -155,60 +192,60 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* tw, int tid) 
     __syncthreads();
 }
 
-template <typename T, int P, int NFFT, int LD, int NTHR, bool INV, int NS>
+template <typename T, int P, int NFFT, int LD, int NTHR, bool INV, int NS, int SCH = 0>
 __device__ __forceinline__ void fft_stages(cx<T>* buf, const cx<T>* tw, int tid) {
     if constexpr (NS < P) {
-        constexpr int R = fft_radix(P, NS);
-        fft_stage<T, P, NFFT, LD, NTHR, R, NS, INV>(buf, tw, tid);
-        fft_stages<T, P, NFFT, LD, NTHR, INV, NS * R>(buf, tw, tid);
+        constexpr int R = fft_radix(P, NS, SCH);
+        fft_stage<T, P, NFFT, LD, NTHR, R, NS, INV, SCH>(buf, tw, tid);
+        fft_stages<T, P, NFFT, LD, NTHR, INV, NS * R, SCH>(buf, tw, tid);
     }
 }
 
 // Unnormalised DFT (INV=false: exp(-2 pi i jk/P); INV=true: exp(+2 pi i jk/P)) of NFFT
 // transforms held in LDS at buf + f*LD, element i at sw(i); LD >= padded(P).  tw is the
 // twiddle table (LDS or global).  Must be called by all NTHR threads; ends with a barrier.
-template <typename T, int P, int NFFT, int LD, int NTHR, bool INV>
+template <typename T, int P, int NFFT, int LD, int NTHR, bool INV, int SCH = 0>
 __device__ __forceinline__ void block_fft(cx<T>* buf, const cx<T>* tw, int tid) {
     static_assert(is_pow2(P) && P >= 2, "FFT length must be a power of two");
     static_assert(LD >= P + P / 16, "LD must hold the padded transform");
-    fft_stages<T, P, NFFT, LD, NTHR, INV, 1>(buf, tw, tid);
+    fft_stages<T, P, NFFT, LD, NTHR, INV, 1, SCH>(buf, tw, tid);
 }
 
 // The same over NFFT transforms processed in groups of at most G (fewer butterflies held in
 // registers per stage, at the price of more barriers).
-template <typename T, int P, int NFFT, int G, int LD, int NTHR, bool INV>
+template <typename T, int P, int NFFT, int G, int LD, int NTHR, bool INV, int SCH = 0>
 __device__ __forceinline__ void block_fft_grouped(cx<T>* buf, const cx<T>* tw, int tid) {
     if constexpr (NFFT <= G) {
-        block_fft<T, P, NFFT, LD, NTHR, INV>(buf, tw, tid);
+        block_fft<T, P, NFFT, LD, NTHR, INV, SCH>(buf, tw, tid);
     } else {
-        block_fft<T, P, G, LD, NTHR, INV>(buf, tw, tid);
-        block_fft_grouped<T, P, NFFT - G, G, LD, NTHR, INV>(buf + G * LD, tw, tid);
+        block_fft<T, P, G, LD, NTHR, INV, SCH>(buf, tw, tid);
+        block_fft_grouped<T, P, NFFT - G, G, LD, NTHR, INV, SCH>(buf + G * LD, tw, tid);
     }
 }
 
 // The stages with sub-transform length in [NS, NSEND) only (for transforms whose first stage is
 // fused into the load or whose last stage is fused into the store by the caller).
-template <typename T, int P, int NFFT, int LD, int NTHR, bool INV, int NS, int NSEND>
+template <typename T, int P, int NFFT, int LD, int NTHR, bool INV, int NS, int NSEND, int SCH = 0>
 __device__ __forceinline__ void fft_stages_range(cx<T>* buf, const cx<T>* tw, int tid) {
     if constexpr (NS < NSEND) {
-        constexpr int R = fft_radix(P, NS);
-        fft_stage<T, P, NFFT, LD, NTHR, R, NS, INV>(buf, tw, tid);
-        fft_stages_range<T, P, NFFT, LD, NTHR, INV, NS * R, NSEND>(buf, tw, tid);
+        constexpr int R = fft_radix(P, NS, SCH);
+        fft_stage<T, P, NFFT, LD, NTHR, R, NS, INV, SCH>(buf, tw, tid);
+        fft_stages_range<T, P, NFFT, LD, NTHR, INV, NS * R, NSEND, SCH>(buf, tw, tid);
     }
 }
-template <typename T, int P, int NFFT, int G, int LD, int NTHR, bool INV, int NS, int NSEND>
+template <typename T, int P, int NFFT, int G, int LD, int NTHR, bool INV, int NS, int NSEND, int SCH = 0>
 __device__ __forceinline__ void block_fft_grouped_range(cx<T>* buf, const cx<T>* tw, int tid) {
     if constexpr (NFFT <= G) {
-        fft_stages_range<T, P, NFFT, LD, NTHR, INV, NS, NSEND>(buf, tw, tid);
+        fft_stages_range<T, P, NFFT, LD, NTHR, INV, NS, NSEND, SCH>(buf, tw, tid);
     } else {
-        fft_stages_range<T, P, G, LD, NTHR, INV, NS, NSEND>(buf, tw, tid);
-        block_fft_grouped_range<T, P, NFFT - G, G, LD, NTHR, INV, NS, NSEND>(buf + G * LD, tw, tid);
+        fft_stages_range<T, P, G, LD, NTHR, INV, NS, NSEND, SCH>(buf, tw, tid);
+        block_fft_grouped_range<T, P, NFFT - G, G, LD, NTHR, INV, NS, NSEND, SCH>(buf + G * LD, tw, tid);
     }
 }
 // Sub-transform length of the last stage of a length-P transform.
-constexpr int fft_last_ns(int P) {
+constexpr int fft_last_ns(int P, int S = 0) {
     int ns = 1;
-    while (ns * fft_radix(P, ns) < P) ns *= fft_radix(P, ns);
+    while (ns * fft_radix(P, ns, S) < P) ns *= fft_radix(P, ns, S);
     return ns;
 }
 
@@ -217,18 +254,18 @@ constexpr int fft_last_ns(int P) {
 // zero past the data), and written to buf; the remaining stages run in LDS.  Ends with a barrier.
 // Split in two so that a caller can issue the loads of its next group early:
 // fft_padded_load fills the registers (PaddedIn), fft_padded_from_regs does the rest.
-template <typename T, int P, int NFFT, int NTHR>
+template <typename T, int P, int NFFT, int NTHR, int SCH = 0>
 struct PaddedIn {
-    static constexpr int R0 = fft_radix(P, 1);
+    static constexpr int R0 = fft_radix(P, 1, SCH);
     static constexpr int NB0 = P / R0;
     static constexpr int NBT = NFFT * NB0;
     static constexpr int IT = (NBT + NTHR - 1) / NTHR;
     cx<T> v[IT][R0 / 2];
 };
 
-template <typename T, int P, int NFFT, int NTHR, typename Ld>
-__device__ __forceinline__ void fft_padded_load(PaddedIn<T, P, NFFT, NTHR>& in, int tid, Ld ld) {
-    using PI = PaddedIn<T, P, NFFT, NTHR>;
+template <typename T, int P, int NFFT, int NTHR, int SCH = 0, typename Ld>
+__device__ __forceinline__ void fft_padded_load(PaddedIn<T, P, NFFT, NTHR, SCH>& in, int tid, Ld ld) {
+    using PI = PaddedIn<T, P, NFFT, NTHR, SCH>;
 #pragma unroll
     for (int it = 0; it < PI::IT; ++it) {
         const int idx = tid + it * NTHR;
@@ -239,10 +276,10 @@ __device__ __forceinline__ void fft_padded_load(PaddedIn<T, P, NFFT, NTHR>& in, 
     }
 }
 
-template <typename T, int P, int NFFT, int LD, int NTHR>
+template <typename T, int P, int NFFT, int LD, int NTHR, int SCH = 0>
 __device__ __forceinline__ void fft_padded_from_regs(cx<T>* buf, const cx<T>* tws, int tid,
-                                                     const PaddedIn<T, P, NFFT, NTHR>& in) {
-    using PI = PaddedIn<T, P, NFFT, NTHR>;
+                                                     const PaddedIn<T, P, NFFT, NTHR, SCH>& in) {
+    using PI = PaddedIn<T, P, NFFT, NTHR, SCH>;
     constexpr int R0 = PI::R0;
 #pragma unroll
     for (int it = 0; it < PI::IT; ++it) {
@@ -258,25 +295,25 @@ __device__ __forceinline__ void fft_padded_from_regs(cx<T>* buf, const cx<T>* tw
         }
     }
     __syncthreads();
-    fft_stages_range<T, P, NFFT, LD, NTHR, false, R0, P>(buf, tws, tid);
+    fft_stages_range<T, P, NFFT, LD, NTHR, false, R0, P, SCH>(buf, tws, tid);
 }
 
-template <typename T, int P, int NFFT, int LD, int NTHR, typename Ld>
+template <typename T, int P, int NFFT, int LD, int NTHR, int SCH = 0, typename Ld>
 __device__ __forceinline__ void fft_forward_padded(cx<T>* buf, const cx<T>* tws, int tid, Ld ld) {
-    PaddedIn<T, P, NFFT, NTHR> in;
-    fft_padded_load<T, P, NFFT, NTHR>(in, tid, ld);
-    fft_padded_from_regs<T, P, NFFT, LD, NTHR>(buf, tws, tid, in);
+    PaddedIn<T, P, NFFT, NTHR, SCH> in;
+    fft_padded_load<T, P, NFFT, NTHR, SCH>(in, tid, ld);
+    fft_padded_from_regs<T, P, NFFT, LD, NTHR, SCH>(buf, tws, tid, in);
 }
 
 // Inverse transforms of the NFFT sequences in buf of which only outputs y < P/2 are wanted: every
 // stage but the last in LDS, the last in registers, handing y = j + r NSL (r < RL/2) to
 // st(f, y, value) (the functor skips y past the data).  No barrier at the end.
-template <typename T, int P, int NFFT, int LD, int NTHR, typename St>
+template <typename T, int P, int NFFT, int LD, int NTHR, int SCH = 0, typename St>
 __device__ __forceinline__ void fft_inverse_cropped(cx<T>* buf, const cx<T>* tws, int tid, St st) {
-    constexpr int NSL = fft_last_ns(P);
+    constexpr int NSL = fft_last_ns(P, SCH);
     constexpr int RL = P / NSL;
-    fft_stages_range<T, P, NFFT, LD, NTHR, true, 1, NSL>(buf, tws, tid);
-    constexpr int TWL = stage_tw_offset(P, NSL);
+    fft_stages_range<T, P, NFFT, LD, NTHR, true, 1, NSL, SCH>(buf, tws, tid);
+    constexpr int TWL = stage_tw_offset(P, NSL, SCH);
     for (int idx = tid; idx < NFFT * NSL; idx += NTHR) {
         const int j = idx % NSL, f = idx / NSL;
         cx<T> v[RL];

@@ -10,8 +10,8 @@
 // 8; BF16 operands, FP32 accumulation.  The input tile with its one-cell halo is staged in LDS as
 // BF16.  The data gradient is the same convolution with the weights flipped in space and
 // transposed in channels, masked by the ReLU derivative of the previous layer.  Weight and bias
-// gradients are FP32 reductions over the batch, one block per (output, input) channel pair, in a
-// fixed order.
+// gradients are one more GEMM on MFMA (BF16 operands, FP32 accumulation) over the batch's pixels,
+// reduced across blocks in a fixed order.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -61,14 +61,25 @@ __global__ __launch_bounds__(256) void k_conv3x3(const float* __restrict__ in, c
     const int b = bid / tiles_y;
     const int x0 = tx * TW, y0 = ty * ROWS;
     const float sc = in_scale ? *in_scale : 1.0f;
-    for (int idx = threadIdx.x; idx < CIN * (ROWS + 2) * (TW + 2); idx += 256) {
-        const int c = idx / ((ROWS + 2) * (TW + 2));
-        const int rem = idx % ((ROWS + 2) * (TW + 2));
-        const int r = rem / (TW + 2), q = rem % (TW + 2);
-        const int y = y0 + r - 1, x = x0 + q - 1;
-        float v = 0.f;
-        if (y >= 0 && y < H && x >= 0 && x < W) v = in[((size_t)(b * CIN + c) * H + y) * W + x] * sc;
-        patch[c][r][q] = f2bf(v);
+    constexpr int NP = CIN * (ROWS + 2) * (TW + 2);
+    unsigned short* pf = &patch[0][0][0];
+    // loads in batches of 8 so that their latencies overlap, then the conversions
+    for (int base = 0; base < NP; base += 8 * 256) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * 256 + threadIdx.x;
+            const int c = idx / ((ROWS + 2) * (TW + 2));
+            const int rem = idx % ((ROWS + 2) * (TW + 2));
+            const int y = y0 + rem / (TW + 2) - 1, x = x0 + rem % (TW + 2) - 1;
+            const bool in_img = idx < NP && y >= 0 && y < H && x >= 0 && x < W;
+            v[u] = in_img ? in[((size_t)(b * CIN + c) * H + y) * W + x] * sc : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * 256 + threadIdx.x;
+            if (idx < NP) pf[idx] = f2bf(v[u]);
+        }
     }
     __syncthreads();
     f32x16 acc;
@@ -110,42 +121,117 @@ __global__ __launch_bounds__(256) void k_conv3x3(const float* __restrict__ in, c
     }
 }
 
-// gW[o][c][t] = sum_{b,p} gy[b][o][p] x[b][c][p + off_t]; gb[o] = sum gy[b][o][p] (block c == 0).
+// Weight and bias gradients as one GEMM on MFMA: G[o][k] = sum_p gy[o][p] X[p][k] over every pixel
+// p of the batch, with X[p][k] = x[c][p + off_t] for k = c*9 + t < Cin*9 and X[p][Cin*9] = 1 (so
+// G[o][Cin*9] is the bias gradient); BF16 operands, FP32 accumulation, as in the forward.  Block
+// (tile, group) takes one tile of 256 pixels of one sample (WG_ROWS x WG_TW, or 16 x 16 when W <= 16),
+// stages the tile's input with its halo and the output gradient in LDS as BF16, and its wave w
+// accumulates the 32-column tile kt = 4 group + w of G over the tile's pixels, 8 at a time.  Each
+// block writes its 32 x 32 sums to part[tile][32][NKT*32]; k_wgrad_reduce adds the tiles in order.
+// The staging loads are issued in batches of 8 so that their latencies overlap.
+constexpr int WG_ROWS = 8, WG_TW = 32, WG_MAXCIN = 32;
+
+__host__ __device__ constexpr int wgrad_ktiles(int cin) { return (cin * 9 + 1 + 31) / 32; }
+__host__ __device__ constexpr int wgrad_tw(int W) { return W <= 16 ? 16 : WG_TW; }
+__host__ __device__ inline int wgrad_tiles(int B, int H, int W) {
+    const int tw = wgrad_tw(W), rows = 256 / tw;
+    return B * ((H + rows - 1) / rows) * ((W + tw - 1) / tw);
+}
+
 __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const float* __restrict__ x, const float* __restrict__ gy,
-                                                       float* __restrict__ gW, float* __restrict__ gb, int B,
-                                                       int Cin, int Cout, int H, int W) {
-    __shared__ float sh[4][10];
-    const int o = blockIdx.x / Cin, c = blockIdx.x % Cin;
-    float acc[10];
+                                                       float* __restrict__ part, int B, int Cin, int Cout, int H,
+                                                       int W) {
+    __shared__ unsigned short xs[WG_MAXCIN * (WG_ROWS + 2) * (WG_TW + 2)];
+    __shared__ __align__(16) unsigned short gs[32 * 256];
+    const int TW = wgrad_tw(W), ROWS = 256 / TW, PW = TW + 2, PH = ROWS + 2;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int NKT = wgrad_ktiles(Cin), K = Cin * 9;
+    const int kt = blockIdx.y * 4 + wave;
+    const int tiles_x = (W + TW - 1) / TW, tiles_y = (H + ROWS - 1) / ROWS;
+    const int tile = blockIdx.x;
+    const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y, b = tile / (tiles_x * tiles_y);
+    const int x0 = tx * TW, y0 = ty * ROWS;
+    const int NX = Cin * PH * PW, NG = 32 * 256;
+    for (int base = 0; base < NX; base += 8 * 256) {
+        float v[8];
 #pragma unroll
-    for (int t = 0; t < 10; ++t) acc[t] = 0.f;
-    const int HW = H * W;
-    for (int p = threadIdx.x; p < B * HW; p += 256) {
-        const int b = p / HW, yx = p % HW;
-        const int y = yx / W, xx = yx % W;
-        const float g = gy[(size_t)(b * Cout + o) * HW + yx];
-        const float* xc = x + (size_t)(b * Cin + c) * HW;
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int yy = y + t / 3 - 1, xq = xx + t % 3 - 1;
-            if (yy >= 0 && yy < H && xq >= 0 && xq < W) acc[t] += g * xc[yy * W + xq];
+        for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * 256 + threadIdx.x;
+            const int c = idx / (PH * PW), rem = idx % (PH * PW);
+            const int yy = y0 + rem / PW - 1, xx = x0 + rem % PW - 1;
+            const bool in = idx < NX && yy >= 0 && yy < H && xx >= 0 && xx < W;
+            v[u] = in ? x[((size_t)(b * Cin + c) * H + yy) * W + xx] : 0.f;
         }
-        acc[9] += g;
-    }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int t = 0; t < 10; ++t) {
-        float v = acc[t];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-        if (lane == 0) sh[wid][t] = v;
+        for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * 256 + threadIdx.x;
+            if (idx < NX) xs[idx] = f2bf(v[u]);
+        }
+    }
+#pragma unroll
+    for (int base = 0; base < NG; base += 8 * 256) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = base + u * 256 + threadIdx.x;
+            const int o = idx / 256, pr = idx % 256;
+            const int yy = y0 + pr / TW, xx = x0 + pr % TW;
+            v[u] = (o < Cout && yy < H && xx < W) ? gy[((size_t)(b * Cout + o) * H + yy) * W + xx] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) gs[base + u * 256 + threadIdx.x] = f2bf(v[u]);
     }
     __syncthreads();
-    if (threadIdx.x < 10) {
-        const int t = threadIdx.x;
-        const float v = sh[0][t] + sh[1][t] + sh[2][t] + sh[3][t];
-        if (t < 9) gW[((size_t)o * Cin + c) * 9 + t] = v;
-        else if (c == 0 && gb) gb[o] = v;
+    if (kt >= NKT) return;
+    const int h = lane >> 5, li = lane & 31;
+    // this lane's column of X: an input tap (read from xs), the bias's ones, or zero padding
+    const int kcol = kt * 32 + li;
+    const int kind = kcol < K ? 0 : (kcol == K ? 1 : 2);
+    const int xoff = kcol < K ? (kcol / 9) * PH * PW + ((kcol % 9) / 3) * PW + (kcol % 9) % 3 : 0;
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    const int spr = TW / 8;   // pixel steps per row
+#pragma unroll 4
+    for (int step = 0; step < 32; ++step) {
+        const int row = step / spr, cg = (step % spr) * 8 + 4 * h;
+        const bf16x4 a = *reinterpret_cast<const bf16x4*>(gs + li * 256 + row * TW + cg);
+        bf16x4 bv;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            bv[r] = kind == 0 ? (short)xs[xoff + row * PW + cg + r] : (kind == 1 ? (short)0x3f80 : (short)0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bv, acc, 0, 0, 0);
     }
+    const int KT32 = NKT * 32;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = 8 * (r >> 2) + 4 * h + (r & 3);
+        part[((size_t)tile * 32 + i) * KT32 + kt * 32 + li] = acc[r];
+    }
+}
+
+// gW[o][k] = sum over tiles of part[tile][o][k] (k < Cin*9, the layout of W[o][c][t]); gb[o] from
+// the ones column k = Cin*9.  Eight independent loads per step, added in tile order.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int ntiles, int Cin, int Cout,
+                                                      float* __restrict__ gW, float* __restrict__ gb) {
+    const int K = Cin * 9, KT32 = wgrad_ktiles(Cin) * 32;
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= Cout * (K + 1)) return;
+    const int o = idx / (K + 1), k = idx % (K + 1);
+    const float* p = part + (size_t)o * KT32 + k;
+    const size_t st = (size_t)32 * KT32;
+    float s = 0.f;
+    int g = 0;
+    for (; g + 8 <= ntiles; g += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(size_t)(g + u) * st];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; g < ntiles; ++g) s += p[(size_t)g * st];
+    if (k < K) gW[(size_t)o * K + k] = s;
+    else if (gb) gb[o] = s;
 }
 
 // diff = y - t; gout = 2 w_b diff / B; lossb[b] = w_b ||diff||^2 / B.  One block per sample.
@@ -207,24 +293,42 @@ __global__ void k_pack(const float* __restrict__ W, int Cin, int Cout, unsigned 
 
 // ------------------------------------------------------------------ coarse grid helpers ------
 // out[c][I][J] = mean over the F x F block of (a - b - d) (b, d optional), FP64 in, FP32 out.
-__global__ void k_pool(const double* __restrict__ a, const double* __restrict__ bsub, const double* __restrict__ dsub,
-                       float* __restrict__ out, int C, int ny, int nx, int F) {
+// One block per (chunk of CW columns, coarse row I, channel c), CW a multiple of F: the 256 threads
+// split into 256 / CW row groups, each summing its rows of the block's F fine rows for one column
+// (coalesced along x), then the F x F sums of the chunk's coarse cells are formed from LDS in a
+// fixed order.
+__host__ __device__ constexpr int pool_chunk(int F) { return F <= 64 ? F * (64 / F) : F; }
+
+__global__ __launch_bounds__(256) void k_pool(const double* __restrict__ a, const double* __restrict__ bsub,
+                                              const double* __restrict__ dsub, float* __restrict__ out, int C, int ny,
+                                              int nx, int F) {
+    __shared__ double part[256];
+    const int CW = pool_chunk(F);
+    const int NRG = 256 / CW;
     const int Hc = ny / F, Wc = nx / F;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= C * Hc * Wc) return;
-    const int c = idx / (Hc * Wc), rem = idx % (Hc * Wc);
-    const int I = rem / Wc, J = rem % Wc;
+    const int x0 = blockIdx.x * CW, I = blockIdx.y, c = blockIdx.z;
+    const int ncols = min(CW, nx - x0);
+    const int rg = threadIdx.x / CW, col = threadIdx.x % CW;
     double s = 0.0;
-    for (int u = 0; u < F; ++u) {
-        const size_t row = ((size_t)c * ny + I * F + u) * nx + J * F;
-        for (int v = 0; v < F; ++v) {
-            double val = a[row + v];
-            if (bsub) val -= bsub[row + v];
-            if (dsub) val -= dsub[row + v];
+    if (rg < NRG && col < ncols) {
+        const size_t base = ((size_t)c * ny + (size_t)I * F) * nx + x0 + col;
+        for (int u = rg; u < F; u += NRG) {
+            const size_t o = base + (size_t)u * nx;
+            double val = a[o];
+            if (bsub) val -= bsub[o];
+            if (dsub) val -= dsub[o];
             s += val;
         }
     }
-    out[idx] = (float)(s / ((double)F * F));
+    part[threadIdx.x] = s;
+    __syncthreads();
+    const int ncells = ncols / F;
+    for (int J = threadIdx.x; J < ncells; J += 256) {
+        double t = 0.0;
+        for (int g = 0; g < NRG; ++g)
+            for (int q = 0; q < F; ++q) t += part[g * CW + J * F + q];
+        out[((size_t)c * Hc + I) * Wc + x0 / F + J] = (float)(t / ((double)F * F));
+    }
 }
 
 // One block per (channel, coarse row): column sums over the F fine rows, then F-wide groups into
@@ -930,6 +1034,8 @@ struct rte_nn {
     size_t cap = 0;                    // activation capacity in floats per tensor
     std::vector<float*> act, pre;      // act[l]: input of layer l (act[0] unused), pre[l]: pre-activation
     float *gA = nullptr, *gB = nullptr;
+    float* wpart = nullptr;            // per-tile partial weight gradients (k_conv3x3_wgrad)
+    size_t wpart_cap = 0;              // its capacity in floats
     double* lossb = nullptr;
     int lossb_cap = 0;
 };
@@ -1328,7 +1434,7 @@ void rte_nn_destroy(rte_nn* nn) {
     nfree(nn->p); nfree(nn->g); nfree(nn->m); nfree(nn->v); nfree(nn->wf); nfree(nn->wb);
     for (auto& a : nn->act) nfree(a);
     for (auto& a : nn->pre) nfree(a);
-    nfree(nn->gA); nfree(nn->gB); nfree(nn->lossb);
+    nfree(nn->gA); nfree(nn->gB); nfree(nn->lossb); nfree(nn->wpart);
     delete nn;
 }
 
@@ -1398,13 +1504,25 @@ int rte_nn_loss_grad(rte_nn* nn, const float* x, const float* t, const float* w,
         return rc;
     const int per = sh.C * H * W;
     hipLaunchKernelGGL(k_loss, dim3(B), dim3(256), 0, st, nn->act[sh.layers], t, w, nn->gA, nn->lossb, per, B);
+    const size_t wneed = (size_t)wgrad_tiles(B, H, W) * 32 * wgrad_ktiles(WG_MAXCIN) * 32;
+    if (wneed > nn->wpart_cap) {
+        nfree(nn->wpart);
+        nn->wpart_cap = 0;
+        if ((rc = nalloc(&nn->wpart, wneed))) return rc;
+        nn->wpart_cap = wneed;
+    }
     // backward: gA holds dLoss/d(output of layer l)
     float* gcur = nn->gA;
     float* gnext = nn->gB;
     for (int l = sh.layers - 1; l >= 0; --l) {
         const float* a_in = l == 0 ? x : nn->act[l];
-        hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(sh.cout[l] * sh.cin[l]), dim3(256), 0, st, a_in, gcur,
-                           nn->g + sh.woff[l], nn->g + sh.boff[l], B, sh.cin[l], sh.cout[l], H, W);
+        const int ntiles = wgrad_tiles(B, H, W);
+        const dim3 wg((unsigned)ntiles, (unsigned)((wgrad_ktiles(sh.cin[l]) + 3) / 4));
+        hipLaunchKernelGGL(k_conv3x3_wgrad, wg, dim3(256), 0, st, a_in, gcur, nn->wpart, B, sh.cin[l], sh.cout[l], H,
+                           W);
+        const int nout = sh.cout[l] * (sh.cin[l] * 9 + 1);
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3((nout + 255) / 256), dim3(256), 0, st, nn->wpart, ntiles, sh.cin[l],
+                           sh.cout[l], nn->g + sh.woff[l], nn->g + sh.boff[l]);
         if (l > 0) {   // data gradient, masked by the ReLU of layer l-1
             if (conv_launch(sh.cout[l], gcur, nn->wb + sh.pb_off[l], nullptr, sh.cin[l], gnext, nullptr, nn->pre[l - 1],
                             false, nullptr, B, H, W, st))
@@ -1441,6 +1559,7 @@ int rte_pc_make_pairs(rte_ctx* c, const double* b, const double* xs, const doubl
                       float* to, float* wo) {
     if (!c || !b || !xs || !xit || !xo || !to || !wo || count < 0) return set_error(RTE_EINVAL, "bad argument");
     if (c->dim != 2 || F < 1 || c->nx % F || c->ny % F) return set_error(RTE_EINVAL, "factor must divide n_x and n_y");
+    if (F > 256) return set_error(RTE_EUNSUPPORTED, "coarsening factor above 256");
     const size_t n = c->nvec;
     const int Hc = c->ny / F, Wc = c->nx / F;
     const int nco = c->C * Hc * Wc;
@@ -1455,10 +1574,11 @@ int rte_pc_make_pairs(rte_ctx* c, const double* b, const double* xs, const doubl
         krylov_dots(c->rv, n, 1, c->rv, n, c->partial, c->dsmall + 1, false, st);
         float* xr = xo + (size_t)j * nco;
         float* xt = to + (size_t)j * nco;
-        hipLaunchKernelGGL(k_pool, dim3((nco + 255) / 256), dim3(256), 0, st, c->rv, (const double*)nullptr,
-                           (const double*)nullptr, xr, c->C, c->ny, c->nx, F);
-        hipLaunchKernelGGL(k_pool, dim3((nco + 255) / 256), dim3(256), 0, st, c->t1, c->rv, (const double*)nullptr, xt,
+        const dim3 pg((unsigned)((c->nx + pool_chunk(F) - 1) / pool_chunk(F)), (unsigned)Hc, (unsigned)c->C);
+        hipLaunchKernelGGL(k_pool, pg, dim3(256), 0, st, c->rv, (const double*)nullptr, (const double*)nullptr, xr,
                            c->C, c->ny, c->nx, F);
+        hipLaunchKernelGGL(k_pool, pg, dim3(256), 0, st, c->t1, c->rv, (const double*)nullptr, xt, c->C, c->ny, c->nx,
+                           F);
         hipLaunchKernelGGL(k_pair_finish, dim3(1), dim3(256), 0, st, xr, xt, nco, c->dsmall + 1, (double)n, c->dsmall,
                            wo + j, F);
     }

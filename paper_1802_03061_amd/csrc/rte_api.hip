@@ -108,6 +108,8 @@ static void free_ctx(rte_ctx* c) {
     }
     dfree(c->twmf);
     dfree(c->twmd);
+    dfree(c->twy1f);
+    dfree(c->twy1d);
     dfree(c->wf);
     dfree(c->wf2);
     dfree(c->wd);
@@ -217,6 +219,7 @@ template <>
 Apply2DArgs<float> args2d<float>(const rte_ctx* c) {
     Apply2DArgs<float> a{c->nx, c->ny, c->PX, c->PY, c->L, c->C, c->wf, c->wf2, c->Qf, c->twf[0], c->twf[1], c->stream};
     a.twm = c->twmf;
+    a.twy1 = c->twy1f;
     for (int p = 0; p < 3; ++p) a.var[p] = c->varf[p];
     return a;
 }
@@ -224,6 +227,7 @@ template <>
 Apply2DArgs<double> args2d<double>(const rte_ctx* c) {
     Apply2DArgs<double> a{c->nx, c->ny, c->PX, c->PY, c->L, c->C, c->wd, c->wd2, c->Qd, c->twd[0], c->twd[1], c->stream};
     a.twm = c->twmd;
+    a.twy1 = c->twy1d;
     for (int p = 0; p < 3; ++p) a.var[p] = c->vard[p];
     return a;
 }
@@ -776,19 +780,20 @@ int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const 
 
     // twiddles of the grid axes, and of the mode axis when pass B couples the modes by an FFT
     const bool mode_fft = c->dim == 2 && c->L > PASSB_FUSED_MAX_L;
-    const int Ps[4] = {c->PX, c->PY, c->PZ, mode_fft ? mode_fft_len(c->L) : 0};
-    for (int a = 0; a < 4; ++a) {
-        if (a >= c->dim && !(a == 3 && mode_fft)) continue;
+    // (index 4: the y axis in the radix-32 schedule, for the pass-B variant that uses it)
+    const int Ps[5] = {c->PX, c->PY, c->PZ, mode_fft ? mode_fft_len(c->L) : 0, c->PY};
+    for (int a = 0; a < 5; ++a) {
+        if (a >= c->dim && !(a == 3 && mode_fft) && !(a == 4 && c->dim == 2)) continue;
         std::vector<double> re, im;
-        twiddles(Ps[a], re, im);
+        twiddles(Ps[a], re, im, a == 4 ? 1 : 0);
         std::vector<cx<double>> td(Ps[a]);
         std::vector<cx<float>> tf(Ps[a]);
         for (int q = 0; q < Ps[a]; ++q) {
             td[q] = mk(re[q], im[q]);
             tf[q] = mk((float)re[q], (float)im[q]);
         }
-        cx<double>*& dd = a < 3 ? c->twd[a] : c->twmd;
-        cx<float>*& ff = a < 3 ? c->twf[a] : c->twmf;
+        cx<double>*& dd = a < 3 ? c->twd[a] : (a == 3 ? c->twmd : c->twy1d);
+        cx<float>*& ff = a < 3 ? c->twf[a] : (a == 3 ? c->twmf : c->twy1f);
         if ((rc = dalloc(&dd, Ps[a])) || (rc = dalloc(&ff, Ps[a]))) { free_ctx(c); return rc; }
         e = hipMemcpy(dd, td.data(), Ps[a] * sizeof(cx<double>), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(ff, tf.data(), Ps[a] * sizeof(cx<float>), hipMemcpyHostToDevice);

@@ -8,7 +8,7 @@ namespace rte {
 
 double self_cell_2d(int m, double h, double mu_t);
 double self_cell_3d(double h, double mu_t);
-void twiddles(int P, std::vector<double>& re, std::vector<double>& im);
+void twiddles(int P, std::vector<double>& re, std::vector<double>& im, int sched = 0);
 
 struct SpectraArgs2D {
     int nx, ny, PX, PY, L;

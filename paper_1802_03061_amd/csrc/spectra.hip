@@ -127,18 +127,18 @@ void self_cell_3d_pairs(int L, double h, double mu_t, std::vector<double>& c) {
                 }
 }
 
-// The twiddle table of the length-P LDS FFT (fft.h), in its per-stage layout: for every Stockham
-// stage after the first (sub-transform length NS, radix R), the factors exp(-2 pi i k r / (NS R))
-// for k < NS, r = 1..R-1 at stage_tw_offset(P, NS) + k (R - 1) + (r - 1).  The angle is computed
+// The twiddle table of the length-P LDS FFT (fft.h) with radix schedule `sched`, in its per-stage
+// layout: for every Stockham stage after the first (sub-transform length NS, radix R), the factors
+// exp(-2 pi i k r / (NS R)) for k < NS, r = 1..R-1 at stage_tw_offset(P, NS, sched) + k (R - 1) + (r - 1).  The angle is computed
 // in long double from the exact integer fraction (k r mod NS R) / (NS R), rounded to FP64, with
 // the quarter points exact.
-void twiddles(int P, std::vector<double>& re, std::vector<double>& im) {
+void twiddles(int P, std::vector<double>& re, std::vector<double>& im, int sched) {
     re.assign(P, 0.0);
     im.assign(P, 0.0);
     const long double pi = 3.141592653589793238462643383279502884L;
     int ns = 1, off = 0;
     while (ns < P) {
-        const int R = fft_radix(P, ns);
+        const int R = fft_radix(P, ns, sched);
         if (ns > 1) {
             const int S = ns * R;
             for (int k = 0; k < ns; ++k)

@@ -70,8 +70,9 @@ def bf16(a):
 
 def emulated_grads(x, t, w, params):
     """The oracle's convolutions applied to the operands the GPU kernels use: BF16-rounded layer
-    inputs and weights in the forward and data-gradient convolutions, FP32-level weight gradients
-    from the unrounded activations."""
+    inputs and weights in the forward and data-gradient convolutions, and BF16-rounded layer inputs
+    and output gradients in the weight and bias gradients (all three are BF16 GEMMs with FP32
+    accumulation on the GPU)."""
     acts, pre = [x], []
     a = x
     for l, (W, b) in enumerate(params):
@@ -83,7 +84,7 @@ def emulated_grads(x, t, w, params):
     g = 2.0 * (acts[-1] - t) * (w / B)[:, None, None, None]
     grads = [None] * len(params)
     for l in range(len(params) - 1, -1, -1):
-        _, gW, gb = cn.conv3x3_backward(acts[l], params[l][0], g)
+        _, gW, gb = cn.conv3x3_backward(bf16(acts[l]), params[l][0], bf16(g))
         grads[l] = (gW, gb)
         if l > 0:
             gx, _, _ = cn.conv3x3_backward(acts[l], bf16(params[l][0]), bf16(g))
