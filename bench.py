@@ -1,6 +1,7 @@
 """Benchmark of the RTE solver on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload hg512|batched|iso3d|diff256|iso32]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload hg512|batched|iso3d|diff256|iso32|sh3d|modes|multi]
 
 Default workload (hg512): solve time to relative residual 1e-8 on the 512^2, L = 8
 Henyey-Greenstein problem.  One step = one full solve (right-hand side b = K~ g by an FP64 apply,
@@ -21,6 +22,13 @@ Other workloads (same JSON shape):
            mu_a = 0.01)
   iso32    the small isotropic problem (32^2, mu_a = 0.1, mu_s = 1, centred Gaussian), FP64
            throughout, tol 1e-10 (latency-bound)
+  sh3d     one step = one solve of the 3D anisotropic problem in real spherical harmonics to
+           degree 2 (9 modes), 64^3, HG g = 0.5, mu_a = 0.05, mu_s = 10, tol 1e-8
+  modes    one step = one solve of a 2D problem with many modes (L = 16, 33 modes; the split
+           pass B with the mode-axis FFT or the direct coupling, as tuned), 256^2, HG g = 0.9,
+           mu_a = 0.05, mu_s = 10, tol 1e-8
+  multi    one step = one rte_solve_multi call for 16 sources sharing one 256^2, L = 4 medium
+           (HG g = 0.5, mu_a = 0.1, mu_s = 10), tol 1e-8 per source; value counts sources solved
 
 Also reported: operator applies/s, per-pass apply times from HIP events on the context stream with
 the HBM roofline of the dominant kernel, the measured copy bandwidth, the error of the GPU solution
@@ -119,6 +127,11 @@ def traffic_for(dom: str, variants):
     return p["traffic_bytes"] if p else None
 
 
+def log(*a):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def padded(n: int) -> int:
     P = 16
     while P < 2 * n - 1:
@@ -153,6 +166,37 @@ def apply3d_pass_bytes(n: int) -> dict:
     t2 = 8 * H * P * n
     q = 4 * H * (P // 2 + 1) * (P // 2 + 1)
     return {"A": 8 * N + t1, "B": t1 + t2, "C": 2 * t2 + q, "D": t2 + t1, "E": t1 + 16 * N}
+
+
+def apply_split_bytes(n: int, L: int, vbytes: int = 8, cbytes: int = 8) -> dict:
+    """As apply_pass_bytes for the split pass B of many modes (L > 8): the x-spectrum has P/2+1
+    unpacked columns, and pass B is three kernels over the full-length buffer [C][P/2+1][P]: the
+    forward y-FFTs (read the spectrum, write the buffer), the mode coupling (read and write the
+    buffer, read the quarter kernel spectra), the inverse y-FFTs (read the buffer, write the
+    spectrum)."""
+    C = 2 * L + 1
+    N = n * n
+    P = padded(n)
+    NK = P // 2 + 1
+    spec = cbytes * C * NK * n
+    full = cbytes * C * NK * P
+    kern = cbytes * C * NK * (P // 2 + 1)
+    return {"A": vbytes * C * N + spec, "B": (spec + full) + (2 * full + kern) + (full + spec),
+            "C": spec + 2 * vbytes * C * N}
+
+
+def apply3d_sh_pass_bytes(n: int, L: int) -> dict:
+    """Algorithmic HBM bytes of one FP32 3D apply with spherical harmonics to degree L: the
+    isotropic passes for each of the M = (L+1)^2 channels, and in the z pass the real octant
+    spectra of the M(M+1)/2 mode pairs."""
+    M = (L + 1) ** 2
+    iso = apply3d_pass_bytes(n)
+    P = padded(n)
+    H = P // 2 + 1
+    q = 4 * H * (P // 2 + 1) * (P // 2 + 1)
+    out = {k: M * v for k, v in iso.items()}
+    out["C"] = M * (iso["C"] - q) + (M * (M + 1) // 2) * q
+    return out
 
 
 def copy_peak_gbs(torch, mib: int = 1024, reps: int = 10) -> float:
@@ -225,6 +269,7 @@ def oracle_2d(w, tol: float, gpu_u: dict) -> tuple:
     n, L = w["n"], w["L"]
     h, mu_t = 1.0 / n, w["mu_a"] + w["mu_s"]
     nt = oracle_threads()
+    log("oracle: CPU baseline solve and reference solve", f"n={n} L={L}")
     t0 = time.perf_counter()
     spectra = op2.kernel_spectra(n, n, L, h, mu_t, workers=nt)
     t_pre = time.perf_counter() - t0
@@ -233,6 +278,7 @@ def oracle_2d(w, tol: float, gpu_u: dict) -> tuple:
     b = op2.rhs(w["f"], L, h, mu_t, spectra=spectra, workers=nt)
     x, hist = kr.gmres(apply, b, tol, 1000)
     t_sol = time.perf_counter() - t0
+    log(f"oracle: baseline solve {t_sol:.1f} s, {len(hist) - 1} iterations; reference solve to 1e-13")
     t0 = time.perf_counter()
     apply(x, 1)
     t_apply1 = time.perf_counter() - t0
@@ -263,6 +309,7 @@ def oracle_3d(w, tol: float, gpu_u: dict) -> tuple:
     n = w["n"]
     h, mu_t = 1.0 / n, w["mu_a"] + w["mu_s"]
     nt = oracle_threads()
+    log("oracle: CPU baseline solve and reference solve", f"n={n}")
     t0 = time.perf_counter()
     spec = op3.kernel_spectrum(n, n, n, h, mu_t, workers=nt)
     t_pre = time.perf_counter() - t0
@@ -271,6 +318,7 @@ def oracle_3d(w, tol: float, gpu_u: dict) -> tuple:
     b = op3.apply_fft(w["f"], h, mu_t, 0.0, "KT", spectrum=spec, workers=nt)
     x, hist = kr.gmres(apply, b, tol, 1000)
     t_sol = time.perf_counter() - t0
+    log(f"oracle: baseline solve {t_sol:.1f} s, {len(hist) - 1} iterations; reference solve to 1e-13")
     t0 = time.perf_counter()
     apply(x, 1)
     t_apply1 = time.perf_counter() - t0
@@ -285,6 +333,41 @@ def oracle_3d(w, tol: float, gpu_u: dict) -> tuple:
            "t_pre_s": t_pre, "t_sol_s": t_sol, "iterations": len(hist) - 1,
            "relres_true": float(np.linalg.norm(b - apply(x)) / nb),
            "single_thread_apply_s": t_apply1, "host": host_cpu()}
+    err = {"reference": {"what": "oracle FP64 GMRES over the FFT apply to 1e-13", "iterations": len(rhist) - 1,
+                         "relres_true": float(np.linalg.norm(b - apply(ref)) / nb), "seconds": t_ref},
+           "seed0_cpu_solve": relerr(x, ref)}
+    for k, u in gpu_u.items():
+        err[k] = relerr(u, ref)
+    return cpu, err
+
+
+def oracle_3d_sh(w, tol: float, gpu_u: dict) -> tuple:
+    """As oracle_2d for the 3D problem in spherical harmonics (oracle.operator3d_sh)."""
+    from oracle import krylov as kr
+    from oracle import operator3d_sh as o3s
+    n, L = w["n"], w["L"]
+    h, mu_t = 1.0 / n, w["mu_a"] + w["mu_s"]
+    nt = oracle_threads()
+    log("oracle: CPU baseline solve and reference solve", f"n={n} L={L}")
+    t0 = time.perf_counter()
+    sp = o3s.kernel_spectra(n, n, n, L, h, mu_t, workers=nt)
+    t_pre = time.perf_counter() - t0
+    apply = lambda u, k=nt: o3s.apply_fft(u, L, h, mu_t, w["mu_s"], w["sigma_hat"], "A", spectra=sp, workers=k)
+    t0 = time.perf_counter()
+    b = o3s.rhs(w["f"], L, h, mu_t, spectra=sp, workers=nt)
+    x, hist = kr.gmres(apply, b, tol, 1000)
+    t_sol = time.perf_counter() - t0
+    log(f"oracle: baseline solve {t_sol:.1f} s, {len(hist) - 1} iterations; reference solve to 1e-13")
+    t0 = time.perf_counter()
+    ref, rhist = kr.gmres(apply, b, 1e-13, 1000)
+    t_ref = time.perf_counter() - t0
+    nb = np.linalg.norm(b)
+    cpu = {"value": 1.0 / t_sol, "unit": "solves/s", "cores": nt, "kind": "oracle",
+           "sample": (f"one FP64 solve of the seed-0 source to relative residual {tol:g} "
+                      f"(oracle.krylov.gmres over oracle.operator3d_sh.apply_fft, {nt} threads): "
+                      f"{len(hist) - 1} iterations, {t_sol:.2f} s; kernel spectra {t_pre:.2f} s excluded"),
+           "t_pre_s": t_pre, "t_sol_s": t_sol, "iterations": len(hist) - 1,
+           "relres_true": float(np.linalg.norm(b - apply(x)) / nb), "host": host_cpu()}
     err = {"reference": {"what": "oracle FP64 GMRES over the FFT apply to 1e-13", "iterations": len(rhist) - 1,
                          "relres_true": float(np.linalg.norm(b - apply(ref)) / nb), "seconds": t_ref},
            "seed0_cpu_solve": relerr(x, ref)}
@@ -537,6 +620,135 @@ def bench_iso3d(args, torch, rte, mu_s):
     return out, ctx, w, sols
 
 
+def bench_sh3d(args, torch, rte, mu_s):
+    """3D anisotropic scattering in real spherical harmonics (degree 2, 9 modes), 64^3."""
+    from paper_1802_03061_amd import inputs
+    w = inputs.workload("sh3d", seed=0, mu_s=mu_s)
+    n, L = w["n"], w["L"]
+    ctx = rte.Context(n, dim=3, mu_a=w["mu_a"], mu_s=w["mu_s"], sigma_hat=w["sigma_hat"], L=L, prec=rte.PREC_FP32)
+    fs = [torch.from_numpy(inputs.workload("sh3d", seed=s, mu_s=mu_s)["f"]).cuda() for s in range(max(args.steps, 1))]
+    torch.cuda.synchronize()
+    r = timed_solves(ctx, fs, args.steps, args.warmup, torch)
+    sols = {"gpu": seed0_solution(ctx, fs[0]).real}
+    pb = apply3d_sh_pass_bytes(n, L)
+    rf = roofline(ctx, rte, pb, args.apply_reps, ["A", "B", "C", "D", "E"])
+    out = {
+        "value": r["solves_per_s"], "unit": "solves/s", "ms_per_step": r["ms_per_solve"],
+        "dtype": "f32 apply + f64 krylov",
+        "config": {"workload": (f"3D anisotropic {n}^3, HG g=0.5, real spherical harmonics to degree {L} "
+                                f"({(L + 1) ** 2} modes), mu_a={w['mu_a']:g}, mu_s={mu_s:g}, Gaussian-mixture "
+                                f"sources, FP32 FFT on the {padded(n)}^3 padded grid, tol 1e-8"),
+                   "n": n, "L": L, "mu_s": mu_s},
+        "solve": r, "applies_per_s": 1000.0 / rf["ms_apply"],
+        "apply_ms": {"fp32_total": rf["ms_apply"], "fp32_passes": rf["passes"]},
+        "apply_hbm_fraction": rf["apply_hbm_fraction"], "apply_bytes": pb, "roofline": rf["roofline"],
+    }
+    return out, ctx, w, sols
+
+
+def bench_modes(args, torch, rte, mu_s):
+    """2D with many modes (L = 16, 33 modes; the split pass B with the autotuner's choice of the
+    mode-axis FFT or the direct coupling), 256^2."""
+    from paper_1802_03061_amd import inputs
+    w = inputs.workload("modes", seed=0, mu_s=mu_s)
+    n, L = w["n"], w["L"]
+    ctx = rte.Context(n, mu_a=w["mu_a"], mu_s=w["mu_s"], sigma_hat=w["sigma_hat"], L=L, prec=rte.PREC_FP32)
+    fs = [torch.from_numpy(inputs.workload("modes", seed=s, mu_s=mu_s)["f"]).cuda() for s in range(max(args.steps, 1))]
+    torch.cuda.synchronize()
+    r = timed_solves(ctx, fs, args.steps, args.warmup, torch)
+    sols = {"gpu": seed0_solution(ctx, fs[0])}
+    pb = apply_split_bytes(n, L)
+    rf = roofline(ctx, rte, pb, args.apply_reps, ["A", "B", "C"])
+    coupling = {}
+    vb, nvb = ctx.get_variant(rte.PREC_FP32, 1)
+    for v in range(nvb):
+        ctx.set_variant(rte.PREC_FP32, 1, v)
+        coupling[("mode-axis FFT", "direct")[v]] = ctx.time_apply(rte.OP_A, rte.PREC_FP32, reps=args.apply_reps)[1][1]
+    ctx.set_variant(rte.PREC_FP32, 1, vb)
+    out = {
+        "value": r["solves_per_s"], "unit": "solves/s", "ms_per_step": r["ms_per_solve"],
+        "dtype": "f32 apply + f64 krylov",
+        "config": {"workload": (f"2D HG g=0.9, L={L} ({2 * L + 1} modes), {n}^2 cells, mu_a={w['mu_a']:g}, "
+                                f"mu_s={mu_s:g}, seeded Gaussian-mixture sources, tol 1e-8"),
+                   "n": n, "L": L, "mu_s": mu_s},
+        "solve": r, "applies_per_s": 1000.0 / rf["ms_apply"],
+        "apply_ms": {"fp32_total": rf["ms_apply"], "fp32_passes": rf["passes"]},
+        "pass_b_ms_by_coupling": coupling, "pass_b_coupling_chosen": ("mode-axis FFT", "direct")[vb],
+        "apply_hbm_fraction": rf["apply_hbm_fraction"], "apply_bytes": pb, "roofline": rf["roofline"],
+    }
+    return out, ctx, w, sols
+
+
+def bench_multi(args, torch, rte, with_oracle: bool, mu_s, nrhs: int = 16):
+    """Several sources sharing one medium (rte_solve_multi: global GMRES on the stacked system, one
+    batched apply per iteration), 16 sources on 256^2, L = 4; the single-source solver beside it."""
+    from paper_1802_03061_amd import inputs
+    w = inputs.workload("multi", seed=0, mu_s=mu_s)
+    n, L = w["n"], w["L"]
+    ctx = rte.Context(n, mu_a=w["mu_a"], mu_s=w["mu_s"], sigma_hat=w["sigma_hat"], L=L, prec=rte.PREC_FP32)
+    srcs = [inputs.workload("multi", seed=s, mu_s=mu_s)["f"] for s in range(nrhs)]
+    fs = [torch.from_numpy(f).cuda() for f in srcs]
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        ctx.solve_multi(fs, tol=1e-8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        us, infos, _ = ctx.solve_multi(fs, tol=1e-8)
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / args.steps
+    single = timed_solves(ctx, fs, nrhs, 1, torch)
+    per = apply_pass_bytes(n, L)
+    C = 2 * L + 1
+    H = padded(n) // 2
+    kern = 8 * C * (H + 1) * (H + 1)
+    pb = {"A": nrhs * per["A"], "B": nrhs * (per["B"] - kern) + kern, "C": nrhs * per["C"]}
+    ms_apply, ms_pass = ctx.time_apply_multi(nrhs, rte.OP_A, rte.PREC_FP32, reps=max(5, args.apply_reps // 5))
+    dom = int(np.argmax(ms_pass[:3]))
+    ach = pb["ABC"[dom]] / (ms_pass[dom] * 1e-3) / 1e9
+    out = {
+        "value": nrhs * 1000.0 / ms, "unit": "solves/s", "ms_per_step": ms, "dtype": "f32 apply + f64 krylov",
+        "config": {"workload": (f"{nrhs} Gaussian-mixture sources sharing one 2D medium: {n}^2 cells, HG g=0.5, "
+                                f"L={L} ({C} modes), mu_a={w['mu_a']:g}, mu_s={mu_s:g}, tol 1e-8 per source"),
+                   "n": n, "L": L, "sources": nrhs, "mu_s": mu_s},
+        "solve": {"stacked_iterations": infos[0]["iterations"],
+                  "max_relres_true": max(i["relres_true"] for i in infos)},
+        "single_source_solver": {"ms_for_all": single["ms_per_solve"] * nrhs,
+                                 "solves_per_s": single["solves_per_s"], "iterations": single["iterations"]},
+        "batched_apply_ms": {"total": ms_apply, "passes": dict(zip("ABC", ms_pass[:3]))},
+        "roofline": {"bound": "hbm", "kernel": f"batched apply pass {'ABC'[dom]} ({nrhs} sources)", "achieved": ach,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": pb["ABC"[dom]], "ms_per_launch": ms_pass[dom]},
+        "apply_hbm_fraction": sum(pb.values()) / (ms_apply * 1e-3) / 1e9 / HBM_PEAK_GBS,
+    }
+    cpu = None
+    if with_oracle:
+        from oracle import krylov as kr
+        from oracle import operator2d as op2
+        h, mu_t = 1.0 / n, w["mu_a"] + w["mu_s"]
+        nt = oracle_threads()
+        sp = op2.kernel_spectra(n, n, L, h, mu_t, workers=nt)
+        apply = lambda u: op2.apply_fft(u, L, h, mu_t, w["mu_s"], w["sigma_hat"], "A", spectra=sp, workers=nt)
+        sample = [0, 1]
+        t_sol, its, errs = 0.0, [], {}
+        for s in sample:
+            b = op2.rhs(srcs[s], L, h, mu_t, spectra=sp, workers=nt)
+            t0 = time.perf_counter()
+            x, hist = kr.gmres(apply, b, 1e-8, 1000)
+            t_sol += time.perf_counter() - t0
+            its.append(len(hist) - 1)
+            ref, _ = kr.gmres(apply, b, 1e-13, 1000)
+            errs[str(s)] = relerr(us[s].cpu().numpy(), ref)
+        cpu = {"value": len(sample) / t_sol, "unit": "solves/s", "cores": nt, "kind": "oracle",
+               "sample": (f"sources {sample} of the {nrhs}, each an FP64 oracle solve to 1e-8 (oracle.krylov.gmres "
+                          f"over oracle.operator2d.apply_fft, {nt} threads): {t_sol:.2f} s, {sum(its)} iterations; "
+                          f"kernel spectra excluded"), "t_sol_s": t_sol, "host": host_cpu()}
+        out["error_vs_oracle"] = {"reference": "oracle FP64 GMRES over the FFT apply to 1e-13, per source",
+                                  "sources": errs, "max": max(errs.values())}
+    ctx.close()
+    return out, cpu
+
+
 def bench_iso32(args, torch, rte, with_oracle: bool):
     """The small isotropic problem in FP64 to 1e-10: every step solves the same deterministic
     source; the reference is the oracle's dense LU solution."""
@@ -587,7 +799,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="hg512", choices=["hg512", "batched", "iso3d", "diff256", "iso32"])
+    ap.add_argument("--workload", default="hg512",
+                    choices=["hg512", "batched", "iso3d", "diff256", "iso32", "sh3d", "modes", "multi"])
     ap.add_argument("--mu-s", type=float, default=None)
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true",
@@ -631,6 +844,18 @@ def main():
         out, cpu = bench_batched(args, torch, rte, oracle_on)
     elif args.workload == "iso32":
         out, cpu = bench_iso32(args, torch, rte, oracle_on)
+    elif args.workload == "multi":
+        out, cpu = bench_multi(args, torch, rte, oracle_on, args.mu_s if args.mu_s is not None else 10.0)
+    elif args.workload == "sh3d":
+        out, ctx, w, sols = bench_sh3d(args, torch, rte, args.mu_s if args.mu_s is not None else 10.0)
+        ctx.close()
+        if oracle_on:
+            cpu, out["error_vs_oracle"] = oracle_3d_sh(w, 1e-8, sols)
+    elif args.workload == "modes":
+        out, ctx, w, sols = bench_modes(args, torch, rte, args.mu_s if args.mu_s is not None else 10.0)
+        ctx.close()
+        if oracle_on:
+            cpu, out["error_vs_oracle"] = oracle_2d(w, 1e-8, sols)
     else:
         out, ctx, w, sols = bench_iso3d(args, torch, rte, args.mu_s if args.mu_s is not None else 10.0)
         ctx.close()

@@ -233,6 +233,11 @@ int rte_pc_attach(rte_ctx* ctx, const float* weights_dev, int hidden, int layers
  * 3D: five passes; unused entries 0).  Input/output are internal buffers. */
 int rte_time_apply(rte_ctx* ctx, int op, int prec, int reps, double* ms_total, double* ms_pass);
 
+/* As rte_time_apply for the batched apply of nrhs stacked channel vectors that rte_solve_multi runs
+ * every iteration (each pass one launch over all nrhs right-hand sides; nrhs in 1..RTE_MAX_RHS).
+ * Grows the work buffers to nrhs right-hand sides as rte_solve_multi does.  Synchronises. */
+int rte_time_apply_multi(rte_ctx* ctx, int nrhs, int op, int prec, int reps, double* ms_total, double* ms_pass);
+
 /* Time the batched apply of one inner iteration of rte_solve_batched over the same contexts (in
  * the same order; a batch plan must exist, i.e. rte_solve_batched ran on them): every problem
  * active, one launch per pass (A, B, C) and padded grid size, `reps` times, each launch bracketed

@@ -95,68 +95,83 @@ __device__ __forceinline__ cx<T> times_i_pow(cx<T> v, int q) {   // v i^q, q in 
     return q == 0 ? v : q == 1 ? mul_i(v) : q == 2 ? mk(-v.re, -v.im) : mul_mi(v);
 }
 
-// Pass C with the mode coupling: per (kx, ky) column, the z-FFT of all CH channels in LDS, then per
-// frequency kz (one thread each)
+// Pass C with the mode coupling.  A block takes the column pair (kx, fy) and (kx, PY - fy), which
+// read the same octant entries (fy = 0 and PY/2 are single columns): the z-FFT of all CH channels of
+// both columns in LDS, then per frequency kz (one thread each, both columns)
 //     w'_b = i^(l_b) s_b w_b,   y'_a = sum_b R_ab w'_b,   y_a = i^(-l_a) s_a y'_a,
 // s_a = the parities of Y_a for the reflections that map (ky, kz) into the stored octant, which
-// equals y_a = sum_b F_ab w_b; R_ba = (-1)^(l_a + l_b) R_ab supplies the lower triangle.  Then the
-// inverse z-FFT of every channel.
+// equals y_a = sum_b F_ab w_b; R_ba = (-1)^(l_a + l_b) R_ab supplies the lower triangle, and every
+// R value read serves both columns.  Then the inverse z-FFT of every channel of both columns.
 template <typename T, int PZ, int CH, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_pass3_c_sh(cx<T>* __restrict__ T2, const T* __restrict__ Q,
                                                      const cx<T>* __restrict__ tw, int nz, int PY, size_t t2sz,
                                                      size_t noct) {
     constexpr int LD = padded(PZ) + 1;
-    __shared__ cx<T> buf[CH * LD];
+    __shared__ cx<T> buf[2 * CH * LD];
     __shared__ cx<T> tws[PZ];
     const int tid = threadIdx.x;
-    const int col = blockIdx.x;                        // kx * PY + ky
-    const int kx = col / PY, ky = col % PY;
     const int HY = PY / 2 + 1, HZ = PZ / 2 + 1;
+    const int kx = blockIdx.x / HY, fy = blockIdx.x % HY;
+    const bool pair = fy > 0 && fy < PY / 2;
+    const size_t col0 = (size_t)kx * PY + fy, col1 = (size_t)kx * PY + (PY - fy);
     stage_twiddles<T, PZ, NTHR>(tws, tw, tid);
     __syncthreads();
-    fft_forward_padded<T, PZ, CH, LD, NTHR>(buf, tws, tid, [&](int c, int z) {
-        return z < nz ? T2[c * t2sz + (size_t)col * nz + z] : mk((T)0, (T)0);
+    // transforms 0..CH-1: column (kx, fy); CH..2CH-1: column (kx, PY - fy), zero when single
+    fft_forward_padded<T, PZ, 2 * CH, LD, NTHR>(buf, tws, tid, [&](int t, int z) {
+        const int c = t % CH;
+        const bool second = t >= CH;
+        return (z < nz && (!second || pair)) ? T2[c * t2sz + (second ? col1 : col0) * nz + z] : mk((T)0, (T)0);
     });
-    const bool negy = ky > PY / 2;
-    const int fy = negy ? PY - ky : ky;
     const T* Qc = Q + ((size_t)kx * HY + fy) * HZ;
     for (int kz = tid; kz < PZ; kz += NTHR) {
         const bool negz = kz > PZ / 2;
         const int fz = negz ? PZ - kz : kz;
-        cx<T> w[CH], y[CH];
+        cx<T> w0[CH], y0[CH], w1[CH], y1[CH];
 #pragma unroll
         for (int b = 0; b < CH; ++b) {
+            // first column: ky = fy <= PY/2 (no y reflection); second: ky = PY - fy (reflected)
             cx<T> v = buf[b * LD + sw(kz)];
-            const bool flip = (kShNegY[b] && negy) != (kShNegZ[b] && negz);
-            if (flip) v = mk(-v.re, -v.im);
-            w[b] = times_i_pow(v, kShDeg[b] & 3);
-            y[b] = mk((T)0, (T)0);
+            if (kShNegZ[b] && negz) v = mk(-v.re, -v.im);
+            w0[b] = times_i_pow(v, kShDeg[b] & 3);
+            cx<T> u = buf[(CH + b) * LD + sw(kz)];
+            if (kShNegY[b] != (kShNegZ[b] && negz)) u = mk(-u.re, -u.im);
+            w1[b] = times_i_pow(u, kShDeg[b] & 3);
+            y0[b] = mk((T)0, (T)0);
+            y1[b] = mk((T)0, (T)0);
         }
 #pragma unroll
         for (int a = 0; a < CH; ++a) {
 #pragma unroll
             for (int b = a; b < CH; ++b) {
                 const T r = Qc[(size_t)(a * CH - a * (a - 1) / 2 + (b - a)) * noct + fz];
-                y[a].re = fma(r, w[b].re, y[a].re);
-                y[a].im = fma(r, w[b].im, y[a].im);
+                y0[a].re = fma(r, w0[b].re, y0[a].re);
+                y0[a].im = fma(r, w0[b].im, y0[a].im);
+                y1[a].re = fma(r, w1[b].re, y1[a].re);
+                y1[a].im = fma(r, w1[b].im, y1[a].im);
                 if (b != a) {
                     const T rb = ((kShDeg[a] + kShDeg[b]) & 1) ? -r : r;
-                    y[b].re = fma(rb, w[a].re, y[b].re);
-                    y[b].im = fma(rb, w[a].im, y[b].im);
+                    y0[b].re = fma(rb, w0[a].re, y0[b].re);
+                    y0[b].im = fma(rb, w0[a].im, y0[b].im);
+                    y1[b].re = fma(rb, w1[a].re, y1[b].re);
+                    y1[b].im = fma(rb, w1[a].im, y1[b].im);
                 }
             }
         }
 #pragma unroll
         for (int a = 0; a < CH; ++a) {
-            cx<T> v = times_i_pow(y[a], (4 - (kShDeg[a] & 3)) & 3);
-            const bool flip = (kShNegY[a] && negy) != (kShNegZ[a] && negz);
-            if (flip) v = mk(-v.re, -v.im);
+            cx<T> v = times_i_pow(y0[a], (4 - (kShDeg[a] & 3)) & 3);
+            if (kShNegZ[a] && negz) v = mk(-v.re, -v.im);
             buf[a * LD + sw(kz)] = v;
+            cx<T> u = times_i_pow(y1[a], (4 - (kShDeg[a] & 3)) & 3);
+            if (kShNegY[a] != (kShNegZ[a] && negz)) u = mk(-u.re, -u.im);
+            buf[(CH + a) * LD + sw(kz)] = u;
         }
     }
     __syncthreads();
-    fft_inverse_cropped<T, PZ, CH, LD, NTHR>(buf, tws, tid, [&](int c, int z, cx<T> v) {
-        if (z < nz) T2[c * t2sz + (size_t)col * nz + z] = v;
+    fft_inverse_cropped<T, PZ, 2 * CH, LD, NTHR>(buf, tws, tid, [&](int t, int z, cx<T> v) {
+        const int c = t % CH;
+        const bool second = t >= CH;
+        if (z < nz && (!second || pair)) T2[c * t2sz + (second ? col1 : col0) * nz + z] = v;
     });
 }
 
@@ -218,11 +233,13 @@ static int launch3_c(const Apply3DArgs<T>& a) {
     } else {
     const size_t t2sz = ncol * a.nz;
     const size_t noct = (size_t)(a.PX / 2 + 1) * (a.PY / 2 + 1) * (PZ / 2 + 1);
+    const unsigned npairs = (unsigned)((a.PX / 2 + 1) * (a.PY / 2 + 1));   // blocks: (kx, fy) column pairs
+    constexpr int NT = PZ >= 256 ? 256 : (PZ < 64 ? 64 : PZ);
     switch (a.C) {
 #define RTE_CSH(CHN)                                                                                              \
     case CHN:                                                                                                     \
-        hipLaunchKernelGGL((k_pass3_c_sh<T, PZ, CHN, 256>), dim3((unsigned)ncol), dim3(256), 0, a.stream, a.T2, a.Q3, \
-                           a.twz, a.nz, a.PY, t2sz, noct);                                                        \
+        hipLaunchKernelGGL((k_pass3_c_sh<T, PZ, CHN, NT>), dim3(npairs), dim3(NT), 0, a.stream, a.T2, a.Q3, a.twz,   \
+                           a.nz, a.PY, t2sz, noct);                                                               \
         return 0;
         RTE_CSH(4) RTE_CSH(9) RTE_CSH(16)
 #undef RTE_CSH

@@ -1063,6 +1063,22 @@ int rte_solve_source(rte_ctx* c, const void* g, int layout, double tol, int max_
     return rc;
 }
 
+// Work buffers for nrhs right-hand sides and the stacked solution, residual and right-hand side.
+static int ensure_multi(rte_ctx* c, int nrhs) {
+    int rc = ensure_work(c, nrhs);
+    if (rc) return rc;
+    if (c->multi_nb < nrhs) {
+        dfree(c->xm);
+        dfree(c->rm);
+        dfree(c->bm);
+        c->multi_nb = 0;
+        const size_t n = (size_t)nrhs * c->nvec;
+        if ((rc = dalloc(&c->xm, n)) || (rc = dalloc(&c->rm, n)) || (rc = dalloc(&c->bm, n))) return rc;
+        c->multi_nb = nrhs;
+    }
+    return RTE_OK;
+}
+
 // Several right-hand sides sharing the context's operator, solved as one GMRES on the stacked
 // block-diagonal system diag(A, ..., A) [x_1; ...; x_B] = [b_1; ...; b_B] with each b_s scaled to
 // unit norm (global GMRES): every iteration is one batched apply over all B vectors and one
@@ -1078,17 +1094,8 @@ int rte_solve_multi(rte_ctx* c, int nrhs, const double* const* f, double tol, in
         if (!f[s] || !u[s]) return set_error(RTE_EINVAL, "source or output %d is NULL", s);
     const double t0 = now_ms();
     const size_t nv = c->nvec;
-    int rc = ensure_work(c, nrhs);
+    int rc = ensure_multi(c, nrhs);
     if (rc) return rc;
-    if (c->multi_nb < nrhs) {
-        dfree(c->xm);
-        dfree(c->rm);
-        dfree(c->bm);
-        c->multi_nb = 0;
-        const size_t n = (size_t)nrhs * nv;
-        if ((rc = dalloc(&c->xm, n)) || (rc = dalloc(&c->rm, n)) || (rc = dalloc(&c->bm, n))) return rc;
-        c->multi_nb = nrhs;
-    }
     hipStream_t st = c->stream;
     // right-hand sides and their norms
     std::vector<double> bn(nrhs);
@@ -1173,19 +1180,19 @@ int rte_solve_rhs(rte_ctx* c, const double* b, double tol, int max_iter, double*
     return solve_core(c, b, tol, max_iter, x, info, x_iterates, max_record, n_recorded);
 }
 
-int rte_time_apply(rte_ctx* c, int op, int prec, int reps, double* ms_total, double* ms_pass) {
-    if (!c || reps < 1) return set_error(RTE_EINVAL, "bad argument");
+// Per-pass event timing of `reps` applies of nb stacked channel vectors x -> y.
+static int time_apply_impl(rte_ctx* c, int op, int prec, int reps, int nb, const double* x, double* y,
+                           double* ms_total, double* ms_pass) {
     if (prec == RTE_PREC_FP32 && c->prec != RTE_PREC_FP32) return set_error(RTE_EINVAL, "FP32 apply needs an FP32 context");
     const int mode = op == RTE_OP_A ? APPLY_A : APPLY_KT;
     const int nev = c->dim == 2 ? 4 : 6;
     hipEvent_t ev[6];
     for (int i = 0; i < nev; ++i) RTE_HIP_TRY(hipEventCreate(&ev[i]));
     std::vector<double> acc(nev, 0.0);
-    vec_fill(c->t0, 1.0, c->nvec, c->stream);
     int rc = RTE_OK;
     for (int r = 0; r < reps && !rc; ++r) {
-        rc = prec == RTE_PREC_FP32 ? apply_t<float>(c, mode, c->t0, nullptr, c->t1, 1, ev)
-                                   : apply_t<double>(c, mode, c->t0, nullptr, c->t1, 1, ev);
+        rc = prec == RTE_PREC_FP32 ? apply_t<float>(c, mode, x, nullptr, y, nb, ev)
+                                   : apply_t<double>(c, mode, x, nullptr, y, nb, ev);
         if (rc) break;
         RTE_HIP_TRY(hipEventSynchronize(ev[nev - 1]));
         for (int i = 1; i < nev; ++i) {
@@ -1204,6 +1211,21 @@ int rte_time_apply(rte_ctx* c, int op, int prec, int reps, double* ms_total, dou
         for (int i = 1; i < nev; ++i) ms_pass[i - 1] = acc[i] / reps;
     }
     return RTE_OK;
+}
+
+int rte_time_apply(rte_ctx* c, int op, int prec, int reps, double* ms_total, double* ms_pass) {
+    if (!c || reps < 1) return set_error(RTE_EINVAL, "bad argument");
+    vec_fill(c->t0, 1.0, c->nvec, c->stream);
+    return time_apply_impl(c, op, prec, reps, 1, c->t0, c->t1, ms_total, ms_pass);
+}
+
+int rte_time_apply_multi(rte_ctx* c, int nrhs, int op, int prec, int reps, double* ms_total, double* ms_pass) {
+    if (!c || reps < 1 || nrhs < 1) return set_error(RTE_EINVAL, "bad argument");
+    if (nrhs > RTE_MAX_RHS) return set_error(RTE_EINVAL, "nrhs = %d exceeds %d", nrhs, RTE_MAX_RHS);
+    int rc = ensure_multi(c, nrhs);
+    if (rc) return rc;
+    vec_fill(c->xm, 1.0, (size_t)nrhs * c->nvec, c->stream);
+    return time_apply_impl(c, op, prec, reps, nrhs, c->xm, c->rm, ms_total, ms_pass);
 }
 
 }  // extern "C"

@@ -150,4 +150,19 @@ def workload(name: str, seed: int = 0, mu_s: float | None = None, n: int | None 
         p = gaussian_mixture_params(rng, 2)
         return dict(dim=2, n=nn, L=4, mu_a=0.01, mu_s=50.0 if mu_s is None else mu_s,
                     sigma_hat=hg_sigma_hat(0.3, 4), f=gaussian_mixture_source(nn, p))
+    if name == "sh3d":             # 3D anisotropic, HG g=0.5, spherical harmonics to degree 2, 64^3
+        nn = n or 64
+        p = gaussian_mixture_params(rng, 3)
+        return dict(dim=3, n=nn, L=2, mu_a=0.05, mu_s=10.0 if mu_s is None else mu_s,
+                    sigma_hat=hg_sigma_hat(0.5, 2), f=gaussian_mixture_source(nn, p, 3))
+    if name == "modes":            # 2D, strongly forward-peaked HG g=0.9, L=16 (33 modes), 256^2
+        nn = n or 256
+        p = gaussian_mixture_params(rng, 2)
+        return dict(dim=2, n=nn, L=16, mu_a=0.05, mu_s=10.0 if mu_s is None else mu_s,
+                    sigma_hat=hg_sigma_hat(0.9, 16), f=gaussian_mixture_source(nn, p))
+    if name == "multi":            # one 256^2 medium (HG g=0.5, L=4) for many sources
+        nn = n or 256
+        p = gaussian_mixture_params(rng, 2)
+        return dict(dim=2, n=nn, L=4, mu_a=0.1, mu_s=10.0 if mu_s is None else mu_s,
+                    sigma_hat=hg_sigma_hat(0.5, 4), f=gaussian_mixture_source(nn, p))
     raise KeyError(name)

@@ -88,6 +88,7 @@ def load():
         "rte_pc_make_pairs": (I, [P, P, P, P, I, I, P, P, P]),
         "rte_pc_apply": (I, [P, P, P]),
         "rte_time_apply": (I, [P, I, I, I, C.POINTER(D), C.POINTER(D)]),
+        "rte_time_apply_multi": (I, [P, I, I, I, I, C.POINTER(D), C.POINTER(D)]),
         "rte_time_batched_apply": (I, [I, C.POINTER(P), I, C.POINTER(D), I, C.POINTER(I), C.POINTER(D),
                                        C.POINTER(I), C.POINTER(I), C.POINTER(I)]),
         "rte_query": (I, [P, C.POINTER(I), C.POINTER(I), C.POINTER(C.c_longlong)]),
@@ -296,6 +297,14 @@ class Context:
         tot = C.c_double()
         passes = (C.c_double * 5)()
         _check(load().rte_time_apply(self._h, op, prec, reps, C.byref(tot), passes))
+        return tot.value, list(passes)
+
+    def time_apply_multi(self, nrhs, op=OP_A, prec=None, reps=20):
+        """Per-pass timing of the batched apply over nrhs stacked right-hand sides."""
+        prec = self.prec if prec is None else prec
+        tot = C.c_double()
+        passes = (C.c_double * 5)()
+        _check(load().rte_time_apply_multi(self._h, int(nrhs), op, prec, reps, C.byref(tot), passes))
         return tot.value, list(passes)
 
     def autotune(self, reps=5):

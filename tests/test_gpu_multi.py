@@ -120,3 +120,18 @@ def test_multi_bad_arguments(rte):
     nul = (P * 1)(None)
     assert lib.rte_solve_multi(ctx._h, 1, nul, 1e-8, 10, up, None) == rte.RTE_EINVAL
     ctx.close()
+
+
+def test_time_apply_multi(rte):
+    """The batched apply timing over stacked right-hand sides: every pass timed, more sources take
+    longer, and out-of-range counts are refused."""
+    ctx = rte.Context(256, mu_a=0.1, mu_s=2.0, L=2, sigma_hat=[1, .5, .25], prec=rte.PREC_FP32)
+    t1, p1 = ctx.time_apply_multi(1, reps=5)
+    t16, p16 = ctx.time_apply_multi(16, reps=5)
+    say("time_apply_multi 1:", t1, p1[:3], "16:", t16, p16[:3])
+    assert all(x > 0 for x in p1[:3]) and all(x > 0 for x in p16[:3])
+    assert t16 > 2 * t1          # sixteen times the vector traffic at a size well past launch latency
+    with pytest.raises(rte.RteError) as ei:
+        ctx.time_apply_multi(rte.MAX_RHS + 1, reps=1)
+    assert ei.value.code == rte.RTE_EINVAL
+    ctx.close()
