@@ -250,14 +250,16 @@ int rte_time_apply_multi(rte_ctx* ctx, int nrhs, int op, int prec, int reps, dou
 int rte_time_batched_apply(int count, rte_ctx* const* ctxs, int reps, double* ms_total, int max_launch,
                            int* n_launch, double* ms_launch, int* launch_pass, int* launch_px, int* launch_py);
 
-/* Kernel variants of the 2D apply (pass 0 = A, 1 = B, 2 = C; prec = RTE_PREC_FP32 or
- * RTE_PREC_FP64 apply).  Variants differ only in tiling (row tiles, thread counts, FFT grouping):
- * the same arithmetic, equal results up to rounding.  rte_setup of a 2D context with n_x or n_y >= 128 picks the
- * fastest variant of every pass by timing them on the context's buffers, once per (precision,
- * L, n_x, n_y) per process (environment RTE_AUTOTUNE=0: keep variant 0).  rte_autotune re-times
- * them (`reps` launches each; synchronises the stream); rte_set_variant forces one
- * (RTE_EINVAL if out of range); rte_get_variant reports the current one and how many exist.
- * 3D contexts: RTE_EUNSUPPORTED (get_variant reports variant 0 of 1). */
+/* Kernel variants of the apply (prec = RTE_PREC_FP32 or RTE_PREC_FP64 apply).  2D: pass 0 = A,
+ * 1 = B, 2 = C; 3D: pass 0 = A (x-FFT), 1 = B (y-FFT), 2 = C (z-FFT with the spectrum or the mode
+ * coupling), 3 = D (inverse y-FFT), 4 = E (inverse x-FFT).  Variants differ only in tiling (row
+ * tiles, z-rows or columns per block, thread counts, FFT grouping, radix schedule, the coupling
+ * method for many modes): the same arithmetic, equal results up to rounding.  rte_setup of a 2D
+ * context with n_x or n_y >= 128, or of a 3D context with a side >= 64, picks the fastest variant of
+ * every pass by timing them on the context's buffers, once per (precision, L, grid) per process
+ * (environment RTE_AUTOTUNE=0: keep variant 0).  rte_autotune re-times them (`reps` launches each;
+ * synchronises the stream); rte_set_variant forces one (RTE_EINVAL if the pass or variant is out of
+ * range); rte_get_variant reports the current one and how many exist. */
 int rte_autotune(rte_ctx* ctx, int reps);
 int rte_set_variant(rte_ctx* ctx, int prec, int pass, int variant);
 int rte_get_variant(const rte_ctx* ctx, int prec, int pass, int* variant, int* count);

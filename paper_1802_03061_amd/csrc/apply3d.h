@@ -22,7 +22,14 @@ struct Apply3DArgs {
     const cx<T>* twz;
     ChanScale3 sc;             // factor per channel on the pass-B load
     hipStream_t stream;
+    int var[3] = {0, 0, 0};    // kernel variants of passes B, C, D (apply3d_variant_count)
 };
+
+// Kernel variants of the 3D passes B, C, D (which = 1, 2, 3), same arithmetic, different tiling:
+// B and D take 8, 4 or 16 z-rows per block; the isotropic C takes 2048/PZ, half or twice as many
+// columns per block; the spherical-harmonic C has one form.
+template <typename T>
+int apply3d_variant_count(int which, int C, int PZ);
 
 // which = 1: y-FFT with transposed store; 2: z-FFT, spectrum multiply (C > 1: the mode coupling),
 // inverse z-FFT; 3: inverse y-FFT back to T1.

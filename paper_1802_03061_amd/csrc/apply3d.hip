@@ -200,13 +200,11 @@ __global__ __launch_bounds__(NTHR) void k_pass3_d(cx<T>* __restrict__ T1, const 
     });
 }
 
-// z-rows per block of the y-passes: eight in both precisions (in FP32, 16 and 4 rows were slower
-// at 128^3: 15.1 / 22.3 and 19.4 / 27.0 us for the forward / inverse pass against 13.4 / 21.1)
-template <typename T> constexpr int tz_rows() { return 8; }
-
-template <typename T, int PY>
-static void launch3_bd(const Apply3DArgs<T>& a, bool inverse) {
-    constexpr int TZ = tz_rows<T>();
+// z-rows per block of the y-passes: 8 (variant 0), 4 or 16 (variants 1, 2).  At 128^3 in FP32, 16
+// and 4 rows were slower than 8: 15.1 / 22.3 and 19.4 / 27.0 us for the forward / inverse pass
+// against 13.4 / 21.1.
+template <typename T, int PY, int TZ>
+static void launch3_bd_tz(const Apply3DArgs<T>& a, bool inverse) {
     const int nkx = a.PX / 2 + 1;
     const size_t t1sz = (size_t)a.nz * nkx * a.ny, t2sz = (size_t)nkx * a.PY * a.nz;
     dim3 grid(nkx, (a.nz + TZ - 1) / TZ, a.C);
@@ -218,14 +216,28 @@ static void launch3_bd(const Apply3DArgs<T>& a, bool inverse) {
                            nkx, t1sz, t2sz);
 }
 
+template <typename T, int PY>
+static void launch3_bd(const Apply3DArgs<T>& a, bool inverse) {
+    const int v = a.var[inverse ? 2 : 0];
+    if (v == 1) launch3_bd_tz<T, PY, 4>(a, inverse);
+    else if (v == 2) launch3_bd_tz<T, PY, 16>(a, inverse);
+    else launch3_bd_tz<T, PY, 8>(a, inverse);
+}
+
+template <typename T, int PZ, int NC>
+static void launch3_c_iso(const Apply3DArgs<T>& a, size_t ncol) {
+    dim3 grid((unsigned)((ncol + NC - 1) / NC));
+    hipLaunchKernelGGL((k_pass3_c<T, PZ, NC, 256>), grid, dim3(256), 0, a.stream, a.T2, a.Q3, a.twz, a.nz, a.PY, ncol);
+}
+
 template <typename T, int PZ>
 static int launch3_c(const Apply3DArgs<T>& a) {
     const size_t ncol = (size_t)(a.PX / 2 + 1) * a.PY;
     if (a.C == 1) {
         constexpr int NC = PZ >= 2048 ? 1 : 2048 / PZ;
-        dim3 grid((unsigned)((ncol + NC - 1) / NC));
-        hipLaunchKernelGGL((k_pass3_c<T, PZ, NC, 256>), grid, dim3(256), 0, a.stream, a.T2, a.Q3, a.twz, a.nz, a.PY,
-                           ncol);
+        if (a.var[1] == 1) launch3_c_iso<T, PZ, (NC > 1 ? NC / 2 : 1)>(a, ncol);
+        else if (a.var[1] == 2) launch3_c_iso<T, PZ, 2 * NC>(a, ncol);
+        else launch3_c_iso<T, PZ, NC>(a, ncol);
         return 0;
     }
     if constexpr (PZ > 256) {
@@ -263,6 +275,16 @@ int apply3d_pass(const Apply3DArgs<T>& a, int which) {
     }
     return -1;
 }
+
+template <typename T>
+int apply3d_variant_count(int which, int C, int PZ) {
+    (void)PZ;
+    if (which == 1 || which == 3) return 3;
+    if (which == 2) return C == 1 ? 3 : 1;
+    return 0;
+}
+template int apply3d_variant_count<float>(int, int, int);
+template int apply3d_variant_count<double>(int, int, int);
 
 template int apply3d_pass<float>(const Apply3DArgs<float>&, int);
 template int apply3d_pass<double>(const Apply3DArgs<double>&, int);

@@ -68,6 +68,9 @@ struct rte_ctx {
     // kernel variants of the 2D apply passes A, B, C (FP32 and FP64 applies), set by the autotuner
     int varf[3] = {0, 0, 0};
     int vard[3] = {0, 0, 0};
+    // 3D: variants of passes A (x-FFT row tiles), B, C, D, E (inverse x-FFT row tiles)
+    int var3f[5] = {0, 0, 0, 0, 0};
+    int var3d[5] = {0, 0, 0, 0, 0};
     // learned preconditioner (see nn.hip)
     bool pc_attached = false;
     int pc_hidden = 0, pc_layers = 0, pc_factor = 1;

@@ -252,6 +252,10 @@ static int apply_t(rte_ctx* c, int mode, const TV* x, const double* b, TV* y, in
         a.C = 1;
         a.L = 0;
         a.pack = 0;
+        const int* v3 = sizeof(T) == 4 ? c->var3f : c->var3d;
+        a.var[0] = v3[0];
+        a.var[1] = 0;
+        a.var[2] = v3[4];
         ChanScale ones;
         for (int i = 0; i < 2 * RTE_MAX_L + 1; ++i) ones.s[i] = 1.0;
         Apply3DArgs<T> a3;
@@ -260,6 +264,7 @@ static int apply_t(rte_ctx* c, int mode, const TV* x, const double* b, TV* y, in
         a3.L = c->L;
         a3.sc = channel_scale3(c, mode);
         a3.stream = c->stream;
+        for (int p = 0; p < 3; ++p) a3.var[p] = v3[p + 1];
         const size_t t1sz = (size_t)c->C * c->nz * (c->PX / 2 + 1) * c->ny;   // one batch entry
         if constexpr (sizeof(T) == 4) {
             a3.T1 = c->wf; a3.T2 = c->wf2; a3.Q3 = c->Q3f; a3.twy = c->twf[1]; a3.twz = c->twf[2];
@@ -706,6 +711,86 @@ int solve_core(rte_ctx* c, const double* b, double tol, int max_iter, double* x,
 
 using namespace rte;
 
+// Per-pass event timing of `reps` applies of nb stacked channel vectors x -> y.
+static int time_apply_impl(rte_ctx* c, int op, int prec, int reps, int nb, const double* x, double* y,
+                           double* ms_total, double* ms_pass) {
+    if (prec == RTE_PREC_FP32 && c->prec != RTE_PREC_FP32) return set_error(RTE_EINVAL, "FP32 apply needs an FP32 context");
+    const int mode = op == RTE_OP_A ? APPLY_A : APPLY_KT;
+    const int nev = c->dim == 2 ? 4 : 6;
+    hipEvent_t ev[6];
+    for (int i = 0; i < nev; ++i) RTE_HIP_TRY(hipEventCreate(&ev[i]));
+    std::vector<double> acc(nev, 0.0);
+    int rc = RTE_OK;
+    for (int r = 0; r < reps && !rc; ++r) {
+        rc = prec == RTE_PREC_FP32 ? apply_t<float>(c, mode, x, nullptr, y, nb, ev)
+                                   : apply_t<double>(c, mode, x, nullptr, y, nb, ev);
+        if (rc) break;
+        RTE_HIP_TRY(hipEventSynchronize(ev[nev - 1]));
+        for (int i = 1; i < nev; ++i) {
+            float ms = 0.f;
+            RTE_HIP_TRY(hipEventElapsedTime(&ms, ev[i - 1], ev[i]));
+            acc[i] += ms;
+        }
+    }
+    for (int i = 0; i < nev; ++i) (void)hipEventDestroy(ev[i]);
+    if (rc) return rc;
+    double tot = 0.0;
+    for (int i = 1; i < nev; ++i) tot += acc[i];
+    if (ms_total) *ms_total = tot / reps;
+    if (ms_pass) {
+        for (int i = 0; i < 5; ++i) ms_pass[i] = 0.0;
+        for (int i = 1; i < nev; ++i) ms_pass[i - 1] = acc[i] / reps;
+    }
+    return RTE_OK;
+}
+
+
+// 3D: passes 0 and 4 are the 2D x-passes (row-tile variants), 1..3 the y-, z- and inverse y-passes.
+template <typename T>
+static int variant_count3(const rte_ctx* c, int pass) {
+    if (pass == 0 || pass == 4) return apply2d_variant_count<T>(pass == 0 ? 0 : 2, 0, c->PX, c->PY);
+    return apply3d_variant_count<T>(pass, c->C, c->PZ);
+}
+
+// The 3D tuner: each pass's variants timed in turn (the others at their current choice) from the
+// per-pass events of `reps` applies, the fastest kept; cached per (precision, L, n) for the process.
+template <typename T>
+static int tune3_t(rte_ctx* c, int* var, int reps, bool use_cache) {
+    const std::vector<int> key = {3, (int)sizeof(T), c->L, c->nx, c->ny, c->nz};
+    if (use_cache) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            for (int p = 0; p < 5; ++p) var[p] = it->second[p];
+            return RTE_OK;
+        }
+    }
+    const int prec = sizeof(T) == 4 ? RTE_PREC_FP32 : RTE_PREC_FP64;
+    vec_fill(c->t0, 1.0, c->nvec, c->stream);
+    for (int pass = 0; pass < 5; ++pass) {
+        const int nv = variant_count3<T>(c, pass);
+        int best = var[pass];
+        double best_ms = 1e30;
+        for (int v = 0; v < nv; ++v) {
+            var[pass] = v;
+            double tot = 0.0, ms[5] = {0, 0, 0, 0, 0};
+            int rc = time_apply_impl(c, RTE_OP_A, prec, reps, 1, c->t0, c->t1, &tot, ms);
+            if (rc) return rc;
+            if (ms[pass] < best_ms) { best_ms = ms[pass]; best = v; }
+        }
+        var[pass] = best;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = std::vector<int>(var, var + 5);
+    return RTE_OK;
+}
+
+static int autotune_3d(rte_ctx* c, int reps, bool use_cache) {
+    int rc = tune3_t<double>(c, c->var3d, reps, use_cache);
+    if (!rc && c->prec == RTE_PREC_FP32) rc = tune3_t<float>(c, c->var3f, reps, use_cache);
+    return rc;
+}
+
 // ------------------------------------------------------------------ C ABI --------------------
 
 extern "C" {
@@ -857,6 +942,9 @@ int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const 
     if (c->dim == 2 && std::max(c->nx, c->ny) >= 128 && !(at && at[0] == '0')) {
         if ((rc = autotune_2d(c, 5, true))) { free_ctx(c); return rc; }
     }
+    if (c->dim == 3 && std::max(c->nx, std::max(c->ny, c->nz)) >= 64 && !(at && at[0] == '0')) {
+        if ((rc = autotune_3d(c, 3, true))) { free_ctx(c); return rc; }
+    }
     c->t_setup_ms = now_ms() - t0;
     *out = c;
     return RTE_OK;
@@ -864,27 +952,35 @@ int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const 
 
 int rte_autotune(rte_ctx* c, int reps) {
     if (!c || reps < 1) return set_error(RTE_EINVAL, "bad argument");
-    if (c->dim != 2) return set_error(RTE_EUNSUPPORTED, "variants exist for 2D contexts only");
-    return autotune_2d(c, reps, false);
+    return c->dim == 2 ? autotune_2d(c, reps, false) : autotune_3d(c, reps, false);
+}
+
+static int variant_count(const rte_ctx* c, int prec, int pass) {
+    const bool f = prec == RTE_PREC_FP32;
+    if (c->dim == 3) return f ? variant_count3<float>(c, pass) : variant_count3<double>(c, pass);
+    return f ? apply2d_variant_count<float>(pass, c->L, c->PX, c->PY)
+             : apply2d_variant_count<double>(pass, c->L, c->PX, c->PY);
 }
 
 int rte_set_variant(rte_ctx* c, int prec, int pass, int variant) {
-    if (!c || pass < 0 || pass > 2 || (prec != RTE_PREC_FP32 && prec != RTE_PREC_FP64)) return set_error(RTE_EINVAL, "bad argument");
-    if (c->dim != 2) return set_error(RTE_EUNSUPPORTED, "variants exist for 2D contexts only");
-    const int nv = prec == RTE_PREC_FP32 ? apply2d_variant_count<float>(pass, c->L, c->PX, c->PY)
-                                         : apply2d_variant_count<double>(pass, c->L, c->PX, c->PY);
+    if (!c || (prec != RTE_PREC_FP32 && prec != RTE_PREC_FP64)) return set_error(RTE_EINVAL, "bad argument");
+    const int npass = c->dim == 2 ? 3 : 5;
+    if (pass < 0 || pass >= npass) return set_error(RTE_EINVAL, "pass %d out of range (%d passes)", pass, npass);
+    const int nv = variant_count(c, prec, pass);
     if (variant < 0 || variant >= nv) return set_error(RTE_EINVAL, "variant %d out of range (%d variants)", variant, nv);
-    (prec == RTE_PREC_FP32 ? c->varf : c->vard)[pass] = variant;
+    if (c->dim == 2) (prec == RTE_PREC_FP32 ? c->varf : c->vard)[pass] = variant;
+    else (prec == RTE_PREC_FP32 ? c->var3f : c->var3d)[pass] = variant;
     return RTE_OK;
 }
 
 int rte_get_variant(const rte_ctx* c, int prec, int pass, int* variant, int* count) {
-    if (!c || pass < 0 || pass > 2 || (prec != RTE_PREC_FP32 && prec != RTE_PREC_FP64)) return set_error(RTE_EINVAL, "bad argument");
-    if (variant) *variant = c->dim == 2 ? (prec == RTE_PREC_FP32 ? c->varf : c->vard)[pass] : 0;
-    if (count)
-        *count = c->dim != 2 ? 1
-                 : prec == RTE_PREC_FP32 ? apply2d_variant_count<float>(pass, c->L, c->PX, c->PY)
-                                         : apply2d_variant_count<double>(pass, c->L, c->PX, c->PY);
+    if (!c || (prec != RTE_PREC_FP32 && prec != RTE_PREC_FP64)) return set_error(RTE_EINVAL, "bad argument");
+    const int npass = c->dim == 2 ? 3 : 5;
+    if (pass < 0 || pass >= npass) return set_error(RTE_EINVAL, "pass %d out of range (%d passes)", pass, npass);
+    if (variant)
+        *variant = c->dim == 2 ? (prec == RTE_PREC_FP32 ? c->varf : c->vard)[pass]
+                               : (prec == RTE_PREC_FP32 ? c->var3f : c->var3d)[pass];
+    if (count) *count = variant_count(c, prec, pass);
     return RTE_OK;
 }
 
@@ -1178,39 +1274,6 @@ int rte_solve_rhs(rte_ctx* c, const double* b, double tol, int max_iter, double*
             return set_error(RTE_EINVAL, "x_iterates overlaps x or b");
     }
     return solve_core(c, b, tol, max_iter, x, info, x_iterates, max_record, n_recorded);
-}
-
-// Per-pass event timing of `reps` applies of nb stacked channel vectors x -> y.
-static int time_apply_impl(rte_ctx* c, int op, int prec, int reps, int nb, const double* x, double* y,
-                           double* ms_total, double* ms_pass) {
-    if (prec == RTE_PREC_FP32 && c->prec != RTE_PREC_FP32) return set_error(RTE_EINVAL, "FP32 apply needs an FP32 context");
-    const int mode = op == RTE_OP_A ? APPLY_A : APPLY_KT;
-    const int nev = c->dim == 2 ? 4 : 6;
-    hipEvent_t ev[6];
-    for (int i = 0; i < nev; ++i) RTE_HIP_TRY(hipEventCreate(&ev[i]));
-    std::vector<double> acc(nev, 0.0);
-    int rc = RTE_OK;
-    for (int r = 0; r < reps && !rc; ++r) {
-        rc = prec == RTE_PREC_FP32 ? apply_t<float>(c, mode, x, nullptr, y, nb, ev)
-                                   : apply_t<double>(c, mode, x, nullptr, y, nb, ev);
-        if (rc) break;
-        RTE_HIP_TRY(hipEventSynchronize(ev[nev - 1]));
-        for (int i = 1; i < nev; ++i) {
-            float ms = 0.f;
-            RTE_HIP_TRY(hipEventElapsedTime(&ms, ev[i - 1], ev[i]));
-            acc[i] += ms;
-        }
-    }
-    for (int i = 0; i < nev; ++i) (void)hipEventDestroy(ev[i]);
-    if (rc) return rc;
-    double tot = 0.0;
-    for (int i = 1; i < nev; ++i) tot += acc[i];
-    if (ms_total) *ms_total = tot / reps;
-    if (ms_pass) {
-        for (int i = 0; i < 5; ++i) ms_pass[i] = 0.0;
-        for (int i = 1; i < nev; ++i) ms_pass[i - 1] = acc[i] / reps;
-    }
-    return RTE_OK;
 }
 
 int rte_time_apply(rte_ctx* c, int op, int prec, int reps, double* ms_total, double* ms_pass) {

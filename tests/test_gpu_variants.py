@@ -63,3 +63,49 @@ def test_variants_match_oracle(rte, n, L, prec):
     y = host(ctx.apply(x, op=rte.OP_A))
     assert relerr(y, ref) <= (1e-6 if prec == rte.PREC_FP32 else 1e-12)
     ctx.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("n,L,prec", [(40, 0, 0), (33, 0, 1), (20, 2, 0), (12, 3, 1)])
+def test_variants_3d_match_oracle(rte, n, L, prec):
+    """3D: every variant of each of the five passes (x-pass row tiles, y-pass z-rows, z-pass
+    columns), the others at variant 0, against the oracle's FP64 FFT apply; then the tuner."""
+    from oracle import operator3d as op3
+    from oracle import operator3d_sh as o3s
+    say("variants 3d", n, L, prec)
+    mu_a, mu_s, h = 0.1, 2.0, 1.0 / n
+    sh = inputs.hg_sigma_hat(0.5, L)
+    ctx = rte.Context((n, n, n), h=h, mu_a=mu_a, mu_s=mu_s, sigma_hat=sh, L=L, prec=prec)
+    M = (L + 1) ** 2
+    rng = np.random.default_rng(n + 7 * L)
+    u = rng.standard_normal((M, n, n, n))
+    if L == 0:
+        ref = op3.apply_fft(u[0], h, mu_a + mu_s, mu_s, "A", workers=16)[None]
+    else:
+        ref = o3s.apply_fft(u, L, h, mu_a + mu_s, mu_s, sh, "A", workers=16)
+    x = dev(u)
+    precs = [prec] if prec == rte.PREC_FP64 else [rte.PREC_FP32, rte.PREC_FP64]
+    for p in precs:
+        bar = 1e-6 if p == rte.PREC_FP32 else 1e-12
+        counts = [ctx.get_variant(p, q)[1] for q in range(5)]
+        assert counts[1] == 3 and counts[3] == 3 and counts[2] == (3 if L == 0 else 1)
+        for q in range(5):
+            for v in range(counts[q]):
+                for qq in range(5):
+                    ctx.set_variant(p, qq, v if qq == q else 0)
+                y = host(ctx.apply(x, op=rte.OP_A, prec=p, layout=rte.LAYOUT_CHANNELS))
+                e = relerr(y.reshape(ref.shape), ref)
+                say(f"  prec {p} pass {q} variant {v} of {counts[q]}: relerr vs oracle {e:.2e}")
+                assert e <= bar
+        with pytest.raises(rte.RteError):
+            ctx.set_variant(p, 5, 0)
+        for qq in range(5):
+            ctx.set_variant(p, qq, 0)
+    ctx.autotune(reps=2)
+    for p in precs:
+        for q in range(5):
+            v, nv = ctx.get_variant(p, q)
+            assert 0 <= v < nv
+    y = host(ctx.apply(x, op=rte.OP_A, layout=rte.LAYOUT_CHANNELS))
+    assert relerr(y.reshape(ref.shape), ref) <= (1e-6 if prec == rte.PREC_FP32 else 1e-12)
+    ctx.close()
