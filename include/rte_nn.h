@@ -69,6 +69,21 @@ int rte_nn_loss_grad(rte_nn* nn, const float* x_dev, const float* t_dev, const f
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the last gradient. */
 int rte_nn_adam_step(rte_nn* nn, float lr);
 
+/* Minibatch gather for training: dst[i] = src[idx[i]] for i < count, rows of row_len floats
+ * (device arrays; idx: device int32, each in [0, nrows); dst may not overlap src).  An index out
+ * of range is not checked on the device: the caller draws them in range.  Asynchronous on
+ * `hip_stream` (NULL = default stream). */
+int rte_nn_gather_rows(const float* src_dev, long long nrows, long long row_len, const int* idx_dev, int count,
+                       float* dst_dev, void* hip_stream);
+
+/* Bilinear upsampling of FP64 fields [count][C][hc][wc] to [count][C][ny][nx] at cell centres,
+ * used to make the multiscale random fields of the training pairs: the source coordinate of fine
+ * cell (y, x) is ((y + 1/2) hc / ny - 1/2, (x + 1/2) wc / nx - 1/2), clamped below at 0, and the
+ * value interpolates linearly between the two nearest coarse cells (the upper index clamped to
+ * the last cell).  Asynchronous on `hip_stream`. */
+int rte_nn_upsample_bilinear(const double* coarse_dev, int count, int C, int hc, int wc, int ny, int nx,
+                             double* fine_dev, void* hip_stream);
+
 /* Training pairs from `count` iterates x_j of a solve of A x = b with solution x_star (all FP64
  * channel vectors of the context): r_j = b - A x_j (FP64 apply), e_j = x_star - x_j, written as
  * coarse inputs x_out[j] = R r_j / s_j, targets t_out[j] = R (e_j - r_j) / s_j ([count][C][Hc][Wc],

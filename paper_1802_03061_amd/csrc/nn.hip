@@ -291,6 +291,37 @@ __global__ void k_pack(const float* __restrict__ W, int Cin, int Cout, unsigned 
     }
 }
 
+// ------------------------------------------------------------------ training data ------------
+// dst[i][k] = src[idx[i]][k] (grid-stride over count * row_len).
+__global__ __launch_bounds__(256) void k_gather_rows(const float* __restrict__ src, long long row_len,
+                                                     const int* __restrict__ idx, long long total,
+                                                     float* __restrict__ dst) {
+    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
+        const long long i = t / row_len, k = t % row_len;
+        dst[t] = src[(long long)idx[i] * row_len + k];
+    }
+}
+
+// Bilinear upsampling at cell centres (source coordinate (d + 1/2) in/out - 1/2, clamped at 0;
+// the upper neighbour clamped to the last cell), one fine cell per thread (grid-stride).
+__global__ __launch_bounds__(256) void k_upsample_bilinear(const double* __restrict__ cz, int hc, int wc, int ny,
+                                                           int nx, long long total, double* __restrict__ fine) {
+    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
+        const int x = (int)(t % nx);
+        const int y = (int)((t / nx) % ny);
+        const long long plane = t / ((long long)nx * ny);
+        const double sy = fmax(((double)y + 0.5) * hc / ny - 0.5, 0.0);
+        const double sx = fmax(((double)x + 0.5) * wc / nx - 0.5, 0.0);
+        const int y0 = min((int)sy, hc - 1), x0 = min((int)sx, wc - 1);
+        const int y1 = min(y0 + 1, hc - 1), x1 = min(x0 + 1, wc - 1);
+        const double ay = sy - y0, ax = sx - x0;
+        const double* p = cz + plane * hc * wc;
+        const double top = (1.0 - ax) * p[y0 * wc + x0] + ax * p[y0 * wc + x1];
+        const double bot = (1.0 - ax) * p[y1 * wc + x0] + ax * p[y1 * wc + x1];
+        fine[t] = (1.0 - ay) * top + ay * bot;
+    }
+}
+
 // ------------------------------------------------------------------ coarse grid helpers ------
 // out[c][I][J] = mean over the F x F block of (a - b - d) (b, d optional), FP64 in, FP32 out.
 // One block per (chunk of CW columns, coarse row I, channel c), CW a multiple of F: the 256 threads
@@ -1553,6 +1584,32 @@ int rte_nn_adam_step(rte_nn* nn, float lr) {
                        lr, b1, b2, c1, c2, 1e-8f);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? RTE_OK : set_hip_error(e, "rte_nn_adam_step", __FILE__, __LINE__);
+}
+
+int rte_nn_gather_rows(const float* src, long long nrows, long long row_len, const int* idx, int count, float* dst,
+                       void* hip_stream) {
+    if (!src || !idx || !dst || nrows < 1 || row_len < 1 || count < 0) return set_error(RTE_EINVAL, "bad argument");
+    const float* src_end = src + nrows * row_len;
+    if (dst < src_end && src < dst + (long long)count * row_len) return set_error(RTE_EINVAL, "dst overlaps src");
+    if (count == 0) return RTE_OK;
+    const long long total = (long long)count * row_len;
+    const unsigned nb = (unsigned)std::min<long long>((total + 255) / 256, 65535LL * 8);
+    hipLaunchKernelGGL(k_gather_rows, dim3(nb), dim3(256), 0, (hipStream_t)hip_stream, src, row_len, idx, total, dst);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RTE_OK : set_hip_error(e, "rte_nn_gather_rows", __FILE__, __LINE__);
+}
+
+int rte_nn_upsample_bilinear(const double* coarse, int count, int C, int hc, int wc, int ny, int nx, double* fine,
+                             void* hip_stream) {
+    if (!coarse || !fine || count < 0 || C < 1 || hc < 1 || wc < 1 || ny < 1 || nx < 1)
+        return set_error(RTE_EINVAL, "bad argument");
+    const long long total = (long long)count * C * ny * nx;
+    if (total == 0) return RTE_OK;
+    const unsigned nb = (unsigned)std::min<long long>((total + 255) / 256, 65535LL * 8);
+    hipLaunchKernelGGL(k_upsample_bilinear, dim3(nb), dim3(256), 0, (hipStream_t)hip_stream, coarse, hc, wc, ny, nx,
+                       total, fine);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RTE_OK : set_hip_error(e, "rte_nn_upsample_bilinear", __FILE__, __LINE__);
 }
 
 int rte_pc_make_pairs(rte_ctx* c, const double* b, const double* xs, const double* xit, int count, int F, float* xo,

@@ -24,14 +24,15 @@ from . import inputs, rte
 
 
 def multiscale_fields(shape, count, gen, scales=(2, 4, 8, 16, 32, 64)):
-    """Seeded random fields at every scale: coarse Gaussian noise on an m x m grid, bilinearly
-    upsampled to the fine grid, for m cycling through `scales` (input generation only)."""
+    """Seeded random fields at every scale: coarse Gaussian noise on an m x m grid (the random
+    numbers drawn by torch), bilinearly upsampled to the fine grid by the library, for m cycling
+    through `scales`."""
     C, ny, nx = shape
     out = torch.empty((count, C, ny, nx), dtype=torch.float64, device="cuda")
     for i in range(count):
         m = scales[i % len(scales)]
         c = torch.randn((1, C, min(m, ny), min(m, nx)), dtype=torch.float64, device="cuda", generator=gen)
-        out[i] = torch.nn.functional.interpolate(c, size=(ny, nx), mode="bilinear", align_corners=False)[0]
+        out[i] = rte.upsample_bilinear(c, ny, nx)[0]
     return out
 
 
@@ -40,7 +41,9 @@ def generate_pairs(ctx: "rte.Context", sources, factor: int, rec_tol: float = 1e
                    seed: int = 0):
     """Pairs from plain GMRES iterates of the given sources, plus pairs (r, e) = (A u, u) that need
     no solve: noise_ratio times as many for white-noise u (rough inputs need little correction)
-    and multiscale_ratio times as many for random fields at every scale."""
+    and multiscale_ratio times as many for random fields at every scale.  The synthetic pairs pass
+    the drawn field itself as the "iterate" (so e = -u, r = -A u): the draws are symmetric, so
+    this is the same distribution of pairs."""
     xs, ts, ws = [], [], []
     gen = torch.Generator(device="cuda").manual_seed(seed)
     zero = torch.zeros(ctx.channel_shape, dtype=torch.float64, device="cuda")
@@ -56,12 +59,12 @@ def generate_pairs(ctx: "rte.Context", sources, factor: int, rec_tol: float = 1e
         k = int(round(noise_ratio * rec.shape[0]))
         if k > 0:
             u = torch.randn((k,) + tuple(ctx.channel_shape), dtype=torch.float64, device="cuda", generator=gen)
-            x, t, w = ctx.make_pairs(zero, zero, (-u).contiguous(), factor)
+            x, t, w = ctx.make_pairs(zero, zero, u, factor)
             xs.append(x); ts.append(t); ws.append(w)
         k = int(round(multiscale_ratio * rec.shape[0]))
         if k > 0:
             u = multiscale_fields(tuple(ctx.channel_shape), k, gen)
-            x, t, w = ctx.make_pairs(zero, zero, (-u).contiguous(), factor)
+            x, t, w = ctx.make_pairs(zero, zero, u, factor)
             xs.append(x); ts.append(t); ws.append(w)
     return torch.cat(xs), torch.cat(ts), torch.cat(ws)
 
@@ -74,8 +77,8 @@ def train(x, t, w, channels, hidden=32, layers=5, steps=2000, batch=32, lr=1e-3,
     g = torch.Generator(device="cpu").manual_seed(seed)
     hist = []
     for step in range(steps):
-        idx = torch.randint(0, n, (min(batch, n),), generator=g).cuda()
-        xb, tb, wb = x[idx].contiguous(), t[idx].contiguous(), w[idx].contiguous()
+        idx = torch.randint(0, n, (min(batch, n),), generator=g, dtype=torch.int32).cuda()
+        xb, tb, wb = rte.gather_rows(x, idx), rte.gather_rows(t, idx), rte.gather_rows(w, idx)
         loss = net.loss_grad(xb, tb, wb)
         net.adam_step(lr)
         if log_every and step % log_every == 0:

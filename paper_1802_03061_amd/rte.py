@@ -85,6 +85,8 @@ def load():
         "rte_nn_forward_noalloc": (I, [P, P, I, I, I, P]),
         "rte_nn_loss_grad": (I, [P, P, P, P, I, I, I, C.POINTER(D), P]),
         "rte_nn_adam_step": (I, [P, C.c_float]),
+        "rte_nn_gather_rows": (I, [P, C.c_longlong, C.c_longlong, P, I, P, P]),
+        "rte_nn_upsample_bilinear": (I, [P, I, I, I, I, I, I, P, P]),
         "rte_pc_make_pairs": (I, [P, P, P, P, I, I, P, P, P]),
         "rte_pc_apply": (I, [P, P, P]),
         "rte_time_apply": (I, [P, I, I, I, C.POINTER(D), C.POINTER(D)]),
@@ -390,6 +392,33 @@ def time_batched_apply(ctxs, reps=20):
     ps, px, py = (C.c_int * cap)(), (C.c_int * cap)(), (C.c_int * cap)()
     _check(load().rte_time_batched_apply(n, hs, int(reps), C.byref(tot), cap, C.byref(nl), ms, ps, px, py))
     return tot.value, [(ps[i], px[i], py[i], ms[i]) for i in range(min(nl.value, cap))]
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def gather_rows(src, idx):
+    """dst[i] = src[idx[i]] over the first axis (float32 device tensor, int32 device indices)."""
+    src = src.contiguous()
+    idx = idx.to(torch.int32).contiguous()
+    dst = torch.empty((idx.shape[0],) + tuple(src.shape[1:]), dtype=torch.float32, device=src.device)
+    row = 1
+    for d in src.shape[1:]:
+        row *= int(d)
+    _check(load().rte_nn_gather_rows(_ptr(src, torch.float32), src.shape[0], row, C.c_void_p(idx.data_ptr()),
+                                     int(idx.shape[0]), C.c_void_p(dst.data_ptr()), _stream()))
+    return dst
+
+
+def upsample_bilinear(coarse, ny, nx):
+    """Bilinear upsampling at cell centres of FP64 fields [count][C][hc][wc] to [count][C][ny][nx]."""
+    coarse = coarse.contiguous()
+    n, Cc, hc, wc = coarse.shape
+    fine = torch.empty((n, Cc, ny, nx), dtype=torch.float64, device=coarse.device)
+    _check(load().rte_nn_upsample_bilinear(_ptr(coarse, torch.float64), n, Cc, hc, wc, ny, nx,
+                                           C.c_void_p(fine.data_ptr()), _stream()))
+    return fine
 
 
 class Net:

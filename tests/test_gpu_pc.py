@@ -408,3 +408,29 @@ def test_fgmres_iterates_match_oracle(rte, prec, n, basis32):
         assert d_oracle <= 3e-2
     ctx.close()
     net.close()
+
+
+def test_gather_rows_and_upsample_match_torch_cpu(rte):
+    """The two training-data kernels against PyTorch CPU references: the minibatch gather against
+    indexing, and the bilinear upsampling at cell centres against F.interpolate (bilinear,
+    align_corners=False), including non-integer ratios and a 1-cell source."""
+    rng = np.random.default_rng(5)
+    src = rng.standard_normal((10, 3, 4, 5)).astype(np.float32)
+    idx = np.array([3, 0, 9, 3, 7], dtype=np.int32)
+    got = host(rte.gather_rows(dev(src), dev(idx)))
+    assert np.array_equal(got, src[idx])
+    lib = rte.load()
+    import ctypes
+    s = dev(src)
+    i = dev(idx)
+    p = ctypes.c_void_p(s.data_ptr())
+    assert lib.rte_nn_gather_rows(p, 10, 60, ctypes.c_void_p(i.data_ptr()), 5, ctypes.c_void_p(s.data_ptr() + 64),
+                                  None) == rte.RTE_EINVAL      # dst overlaps src
+    import torch.nn.functional as Fn
+    for (hc, wc, ny, nx) in [(4, 6, 16, 24), (4, 6, 9, 13), (1, 1, 5, 7), (8, 8, 8, 8), (3, 5, 64, 32)]:
+        c = rng.standard_normal((2, 3, hc, wc))
+        ref = Fn.interpolate(torch.from_numpy(c), size=(ny, nx), mode="bilinear", align_corners=False).numpy()
+        got = host(rte.upsample_bilinear(dev(c), ny, nx))
+        e = float(np.abs(got - ref).max())
+        say("upsample", hc, wc, ny, nx, "max abs err", e)
+        assert e <= 1e-14
