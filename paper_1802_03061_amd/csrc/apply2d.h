@@ -22,6 +22,7 @@ struct Apply2DArgs {
     hipStream_t stream;
     const cx<T>* twm = nullptr;   // L > 8: stage twiddles of the mode-axis FFT (length mode_fft_len(L))
     const cx<T>* twy1 = nullptr;  // y twiddles in the radix-32 schedule (fft.h, schedule 1)
+    const cx<T>* twyh = nullptr;  // stage twiddles of length PY/2 (pass B split in halves)
     int pack = 0;              // 1: x-frequencies 0 and PX/2 share column 0 of the work buffer
     int var[3] = {0, 0, 0};    // kernel variant of passes A, B, C (see apply2d_variant_count)
     // The input's channels other than channel 0 are zero and pass A ran for channel 0 alone, so

@@ -458,6 +458,115 @@ __global__ __launch_bounds__(256) void k_pass_b_couple(cx<T>* __restrict__ T2, c
     for (int c = 0; c < C; ++c) p[c * cstride + f] = v[c];
 }
 
+// Pass B split in halves (for columns whose spectra do not fit LDS at once: FP64 with many modes).
+// The first decimation-in-frequency stage splits the length-PY y-transform of a column into its
+// even and odd frequencies, the length-PH = PY/2 transforms of x[n] and x[n] W^n (W =
+// exp(-2 pi i / PY); x[n] = 0 for n >= ny, and ny <= PH).  A block takes one column and runs the two
+// halves one after the other with one half's spectra of every channel in LDS: forward transform,
+// the mode coupling at that half's frequencies f = 2k + h, inverse transform.  The inverse of the
+// whole column is e[n] + W^-n o[n] (e, o the inverse transforms of the even and odd halves): the
+// even half's e goes to the scratch buffer E ([batch][C][columns][ny], like the work buffer), and
+// the odd half adds its part and writes the column.  HBM: the column is read twice and e written
+// and read once, against three passes over a full-length buffer in the split form.
+template <typename T, int PY, int L, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_pass_b_half(cx<T>* __restrict__ Tb, cx<T>* __restrict__ E,
+                                                      const cx<T>* __restrict__ Q, const cx<T>* __restrict__ twh,
+                                                      int ny, int nkx, int nkq, int pack, int single) {
+    constexpr int C = 2 * L + 1;
+    constexpr int PH = PY / 2;
+    constexpr int LD = padded(PH);
+    constexpr int KH = PY / 2 + 1;
+    constexpr int HY = PY / 2;
+    constexpr int G = (3 * NTHR * 8) / PH >= C ? C : ((3 * NTHR * 8) / PH < 1 ? 1 : (3 * NTHR * 8) / PH);
+    __shared__ cx<T> spec[C * LD];
+    __shared__ cx<T> tws[PH];
+    __shared__ cx<T> pairtmp[2 * C];   // Q of the two self-mirrored frequencies of a packed column
+    const int tid = threadIdx.x;
+    const int kx = blockIdx.x, b = blockIdx.y;
+    const size_t cstride = (size_t)nkx * ny;
+    cx<T>* base = Tb + (size_t)b * C * cstride + (size_t)kx * ny;
+    cx<T>* ebase = E + (size_t)b * C * cstride + (size_t)kx * ny;
+    const size_t qs = (size_t)nkq * KH;
+    stage_twiddles<T, PH, NTHR>(tws, twh, tid);
+    for (int h = 0; h < 2; ++h) {
+        for (int n = tid; n < PH; n += NTHR) {
+            cx<T> w = mk((T)1, (T)0);
+            if (h == 1) {
+                double sn, cs;
+                sincospi(-2.0 * (double)n / (double)PY, &sn, &cs);
+                w = mk((T)cs, (T)sn);
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const cx<T> v = (n < ny && (!single || c == 0)) ? base[c * cstride + n] : mk((T)0, (T)0);
+                spec[c * LD + sw(n)] = h ? v * w : v;
+            }
+        }
+        __syncthreads();
+        block_fft_grouped<T, PH, C, G, LD, NTHR, false>(spec, tws, tid);
+        if (pack && kx == 0) {
+            // column 0 packs the x-frequencies 0 and PX/2: split each frequency pair (f, PY - f), both
+            // in this half, into the two real sequences' spectra, couple each with its kernel column
+            for (int k = tid; k < PH; k += NTHR) {
+                const int f = 2 * k + h;
+                if (f > HY) continue;
+                const int fm = (PY - f) & (PY - 1);
+                const int km = (fm - h) / 2;
+                const bool self = fm == f;
+                cx<T>* zf = spec + sw(k);
+                cx<T>* zq = self ? pairtmp + (f == 0 ? 0 : C) : spec + sw(km);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const cx<T> z = zf[c * LD], w = conj(self ? z : zq[c * LD]);
+                    zf[c * LD] = scale(z + w, (T)0.5);
+                    zq[c * (self ? 1 : LD)] = scale(mul_mi(z - w), (T)0.5);
+                }
+                couple_inplace<T, L>(zf, LD, Q, qs, (size_t)f, false);
+                couple_inplace<T, L>(zq, self ? 1 : LD, Q, qs, (size_t)(nkq - 1) * KH + f, false);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const cx<T> d = zf[c * LD], q = zq[c * (self ? 1 : LD)];
+                    zf[c * LD] = d + mul_i(q);
+                    if (!self) zq[c * LD] = conj(d) + mul_i(conj(q));
+                }
+            }
+        } else {
+            // frequencies in the order [0, PH/4), [3PH/4, PH), [PH/4, 3PH/4): a frequency and its
+            // mirror, which read the same quarter-table entries, fall in the same sweep
+            for (int ki = tid; ki < PH; ki += NTHR) {
+                const int k = ki < PH / 4 ? ki : (ki < PH / 2 ? ki + PH / 2 : ki - PH / 4);
+                const int f = 2 * k + h;
+                const bool flip = f > HY;
+                couple_inplace<T, L>(spec + sw(k), LD, Q, qs, (size_t)kx * KH + (flip ? PY - f : f), flip);
+            }
+        }
+        __syncthreads();
+        block_fft_grouped<T, PH, C, G, LD, NTHR, true>(spec, tws, tid);
+        for (int n = tid; n < ny; n += NTHR) {
+            cx<T> w = mk((T)1, (T)0);
+            if (h == 1) {
+                double sn, cs;
+                sincospi(2.0 * (double)n / (double)PY, &sn, &cs);
+                w = mk((T)cs, (T)sn);
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const cx<T> v = spec[c * LD + sw(n)];
+                if (h == 0) ebase[c * cstride + n] = v;
+                else base[c * cstride + n] = ebase[c * cstride + n] + v * w;
+            }
+        }
+        __syncthreads();   // the next half overwrites the spectra
+    }
+}
+
+template <typename T, int PY, int L>
+constexpr bool half_fits() {
+    // LDS of k_pass_b_half: one half of the column's spectra, the half-length twiddles, the pair scratch
+    return PY >= 64 && ((long)(2 * L + 1) * padded(PY / 2) + PY / 2 + 2 * (2 * L + 1)) * (long)sizeof(cx<T>) <=
+                           160 * 1024;
+}
+
 constexpr int lds_budget() { return 160 * 1024; }
 
 template <typename T, int PY, int L>
@@ -543,6 +652,15 @@ static int launch_py(const Apply2DArgs<T>& a, int nbatch) {
     } else {
         if (!a.work2) return -2;
         if (a.single_in && nbatch != 1) return -3;
+        if constexpr (half_fits<T, PY, L>()) {
+            if (a.var[1] == 1) {   // split in halves
+                if (!a.twyh) return -5;
+                dim3 grid(nkx, nbatch);
+                hipLaunchKernelGGL((k_pass_b_half<T, PY, L, 256>), grid, dim3(256), 0, a.stream, a.work, a.work2, a.Q,
+                                   a.twyh, a.ny, nkx, nkq, a.pack, a.single_in);
+                return 0;
+            }
+        }
         const size_t nseq = (size_t)nbatch * C * nkx;
         split_fft<T, PY, false>(a.work, a.work2, a.twy, a.ny, a.single_in ? (size_t)nkx : nseq, a.stream);  // single_in: channel 0 only
         dim3 g2((unsigned)(((size_t)nkx * PY + 255) / 256), nbatch);
@@ -556,7 +674,7 @@ static int launch_py(const Apply2DArgs<T>& a, int nbatch) {
 template <typename T, int PY>
 static int variants_py() {
     if constexpr (fused_fits<T, PY, RTE_PASSB_L>()) return fused_variants<T, PY, RTE_PASSB_L>();
-    return 1;
+    return half_fits<T, PY, RTE_PASSB_L>() ? 2 : 1;   // split form; split in halves
 }
 
 template <typename T>

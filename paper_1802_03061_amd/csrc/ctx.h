@@ -23,9 +23,11 @@ struct rte_ctx {
     double* Q3d = nullptr;
     rte::cx<float>* twf[3] = {nullptr, nullptr, nullptr};
     rte::cx<double>* twd[3] = {nullptr, nullptr, nullptr};
-    // 2D: y twiddles in the radix-32 schedule (pass-B variant)
+    // 2D: y twiddles in the radix-32 schedule (pass-B variant), and of length PY/2 (pass B in halves)
     rte::cx<float>* twy1f = nullptr;
     rte::cx<double>* twy1d = nullptr;
+    rte::cx<float>* twyhf = nullptr;
+    rte::cx<double>* twyhd = nullptr;
     // 2D with L > 8: stage twiddles of the FFT along the mode axis (pass-B coupling)
     rte::cx<float>* twmf = nullptr;
     rte::cx<double>* twmd = nullptr;

@@ -110,6 +110,8 @@ static void free_ctx(rte_ctx* c) {
     dfree(c->twmd);
     dfree(c->twy1f);
     dfree(c->twy1d);
+    dfree(c->twyhf);
+    dfree(c->twyhd);
     dfree(c->wf);
     dfree(c->wf2);
     dfree(c->wd);
@@ -220,6 +222,7 @@ Apply2DArgs<float> args2d<float>(const rte_ctx* c) {
     Apply2DArgs<float> a{c->nx, c->ny, c->PX, c->PY, c->L, c->C, c->wf, c->wf2, c->Qf, c->twf[0], c->twf[1], c->stream};
     a.twm = c->twmf;
     a.twy1 = c->twy1f;
+    a.twyh = c->twyhf;
     for (int p = 0; p < 3; ++p) a.var[p] = c->varf[p];
     return a;
 }
@@ -228,6 +231,7 @@ Apply2DArgs<double> args2d<double>(const rte_ctx* c) {
     Apply2DArgs<double> a{c->nx, c->ny, c->PX, c->PY, c->L, c->C, c->wd, c->wd2, c->Qd, c->twd[0], c->twd[1], c->stream};
     a.twm = c->twmd;
     a.twy1 = c->twy1d;
+    a.twyh = c->twyhd;
     for (int p = 0; p < 3; ++p) a.var[p] = c->vard[p];
     return a;
 }
@@ -865,10 +869,11 @@ int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const 
 
     // twiddles of the grid axes, and of the mode axis when pass B couples the modes by an FFT
     const bool mode_fft = c->dim == 2 && c->L > PASSB_FUSED_MAX_L;
-    // (index 4: the y axis in the radix-32 schedule, for the pass-B variant that uses it)
-    const int Ps[5] = {c->PX, c->PY, c->PZ, mode_fft ? mode_fft_len(c->L) : 0, c->PY};
-    for (int a = 0; a < 5; ++a) {
-        if (a >= c->dim && !(a == 3 && mode_fft) && !(a == 4 && c->dim == 2)) continue;
+    // (index 4: the y axis in the radix-32 schedule, for the pass-B variant that uses it; index 5:
+    // length PY/2, for pass B split in halves)
+    const int Ps[6] = {c->PX, c->PY, c->PZ, mode_fft ? mode_fft_len(c->L) : 0, c->PY, c->PY / 2};
+    for (int a = 0; a < 6; ++a) {
+        if (a >= c->dim && !(a == 3 && mode_fft) && !(a >= 4 && c->dim == 2)) continue;
         std::vector<double> re, im;
         twiddles(Ps[a], re, im, a == 4 ? 1 : 0);
         std::vector<cx<double>> td(Ps[a]);
@@ -877,8 +882,8 @@ int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const 
             td[q] = mk(re[q], im[q]);
             tf[q] = mk((float)re[q], (float)im[q]);
         }
-        cx<double>*& dd = a < 3 ? c->twd[a] : (a == 3 ? c->twmd : c->twy1d);
-        cx<float>*& ff = a < 3 ? c->twf[a] : (a == 3 ? c->twmf : c->twy1f);
+        cx<double>*& dd = a < 3 ? c->twd[a] : (a == 3 ? c->twmd : (a == 4 ? c->twy1d : c->twyhd));
+        cx<float>*& ff = a < 3 ? c->twf[a] : (a == 3 ? c->twmf : (a == 4 ? c->twy1f : c->twyhf));
         if ((rc = dalloc(&dd, Ps[a])) || (rc = dalloc(&ff, Ps[a]))) { free_ctx(c); return rc; }
         e = hipMemcpy(dd, td.data(), Ps[a] * sizeof(cx<double>), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(ff, tf.data(), Ps[a] * sizeof(cx<float>), hipMemcpyHostToDevice);
