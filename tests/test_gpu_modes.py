@@ -167,3 +167,30 @@ def test_limits(rte):
         ctx.attach_pc(torch.zeros(100000, dtype=torch.float32, device="cuda"), hidden=32, layers=5, factor=2)
     assert ei.value.code == rte.RTE_EUNSUPPORTED
     ctx.close()
+
+
+@pytest.mark.timeout(900)
+def test_apply_max_size_sampled(rte):
+    """The largest 2D problem the library takes: 512^2 with L = 32 (65 modes, 1024^2 padded, the
+    mode-axis FFT of length 256), FP32 and FP64 applies, both couplings, sampled output cells
+    against the oracle's row sums."""
+    n, L = 512, 32
+    sh = inputs.hg_sigma_hat(0.8, L)
+    h = 1.0 / n
+    ctx = rte.Context(n, mu_a=0.05, mu_s=5.0, sigma_hat=sh, L=L, prec=rte.PREC_FP32)
+    M = 2 * L + 1
+    rng = np.random.default_rng(99)
+    u = rng.standard_normal((M, n, n)) + 1j * rng.standard_normal((M, n, n))
+    cells = [(0, 0), (511, 511), (0, 511), (256, 200), (33, 470)]
+    ref = op2.apply_sampled(u, cells, L, h, 5.05, 5.0, sh)
+    x = dev(u)
+    for prec in (0, 1):
+        for v in range(2):
+            ctx.set_variant(prec, 1, v)
+            say("max size apply prec", prec, "variant", v)
+            y = host(ctx.apply(x, prec=prec))
+            got = np.array([y[:, iy, ix] for iy, ix in cells])
+            e = float(np.abs(got - ref).max() / np.abs(ref).max())
+            say(f"  sampled max relerr {e:.2e}")
+            assert e <= (1e-11 if prec == 1 else 1e-6)
+    ctx.close()
