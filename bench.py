@@ -517,11 +517,11 @@ def bench_batched(args, torch, rte, with_oracle: bool):
     # bytes of the problems each launch covers (FP32 apply, FP64 basis vectors)
     ms_tot, launches = rte.time_batched_apply(ctxs, reps=args.apply_reps)
     lrows = []
-    for ps, px, py, lms in launches:
+    for ps, px, py, lms, var in launches:
         members = [p for p in probs if padded(p["n"]) == px]
         nbytes = sum(apply_pass_bytes(p["n"], 0)["ABC"[ps]] for p in members)
-        lrows.append({"pass": "ABC"[ps], "padded": px, "problems": len(members), "ms": lms, "bytes": nbytes,
-                      "GBs": nbytes / (lms * 1e-3) / 1e9})
+        lrows.append({"pass": "ABC"[ps], "padded": px, "problems": len(members), "variant": var, "ms": lms,
+                      "bytes": nbytes, "GBs": nbytes / (lms * 1e-3) / 1e9})
     dom = max(lrows, key=lambda r: r["ms"])
     total_bytes = sum(r["bytes"] for r in lrows)
     out = {

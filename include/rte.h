@@ -243,12 +243,25 @@ int rte_time_apply_multi(rte_ctx* ctx, int nrhs, int op, int prec, int reps, dou
  * active, one launch per pass (A, B, C) and padded grid size, `reps` times, each launch bracketed
  * by HIP events on the batch stream.  Outputs: *ms_total the average time of the whole batched
  * apply; for launch i < min(*n_launch, max_launch): ms_launch[i] its average time, launch_pass[i]
- * (0 = A, 1 = B, 2 = C) and launch_px[i], launch_py[i] the padded grid of the problems it covers.
- * Launches are ordered pass A over the size classes, then B, then C; size classes in the order
- * their first problem appears.  Overwrites the first two basis columns of each problem.
+ * (0 = A, 1 = B, 2 = C), launch_px[i], launch_py[i] the padded grid of the problems it covers and
+ * launch_var[i] the kernel variant it runs (rte_set_batched_variant); any output array may be
+ * NULL.  Launches are ordered pass A over the size classes, then B, then C; size classes in the
+ * order their first problem appears.  Overwrites the first two basis columns of each problem.
  * RTE_EINVAL without a plan for these contexts.  Synchronises the batch stream. */
 int rte_time_batched_apply(int count, rte_ctx* const* ctxs, int reps, double* ms_total, int max_launch,
-                           int* n_launch, double* ms_launch, int* launch_pass, int* launch_px, int* launch_py);
+                           int* n_launch, double* ms_launch, int* launch_pass, int* launch_px, int* launch_py,
+                           int* launch_var);
+
+/* Kernel variants of the batched apply, per padded grid size of a batch (same arithmetic, equal
+ * results up to rounding).  pass 0: the row tile of passes A and C (4 variants for a padded x >= 128,
+ * as the single-problem row tiles); pass 1: the columns per block of pass B (the default columns and
+ * threads, half the threads, twice or half the columns; padded y >= 128).  When rte_solve_batched
+ * builds the plan of a new list of contexts it times the variants of every size class on all of
+ * its problems and keeps the fastest (environment RTE_AUTOTUNE=0: variant 0).  This call forces
+ * `variant` (0..3; a size class with fewer variants takes variant 0) or restores tuning (-1) for
+ * plans built afterwards, and drops the cached plans.  The setting is process-wide.  RTE_EINVAL if
+ * pass or variant is out of range. */
+int rte_set_batched_variant(int pass, int variant);
 
 /* Kernel variants of the apply (prec = RTE_PREC_FP32 or RTE_PREC_FP64 apply).  2D: pass 0 = A,
  * 1 = B, 2 = C; 3D: pass 0 = A (x-FFT), 1 = B (y-FFT), 2 = C (z-FFT with the spectrum or the mode

@@ -65,22 +65,29 @@ struct BatchProb {
 };
 
 // Batched passes over a list of (problem index, tile) items whose problems all have this PX
-// (passes A, C: tiles of apply2d_batch_rows() rows) or this PY (pass B: groups of
-// apply2d_batch_cols() columns).  act[p] == 0 skips problem p (act may be NULL); dj (may be NULL)
-// points to the Krylov column index j.
+// (passes A, C: tiles of apply2d_batch_rows(var) rows) or this PY (pass B: groups of
+// apply2d_batch_cols(PY, var) columns).  act[p] == 0 skips problem p (act may be NULL); dj (may be
+// NULL) points to the Krylov column index j.  Variants (same arithmetic, different tiling; -1 when
+// var is out of range): passes A and C share the row tile (the single-problem row tiles, padded
+// x >= 128); pass B takes the fused form's columns per block with its threads or half of them, or
+// twice or half the columns (padded y >= 128).
 template <typename T>
-int apply2d_batch_rows();
+int apply2d_batch_row_variants(int PX);
 template <typename T>
-int apply2d_batch_cols(int PY);
+int apply2d_batch_rows(int var);
+template <typename T>
+int apply2d_batch_col_variants(int PY);
+template <typename T>
+int apply2d_batch_cols(int PY, int var);
 template <typename T>
 int apply2d_batch_pass_a(int PX, const BatchProb<T>* probs, const int2* items, int nitems, const int* act,
-                         const int* dj, hipStream_t st);
+                         const int* dj, int var, hipStream_t st);
 template <typename T>
-int apply2d_batch_pass_b(int PY, const BatchProb<T>* probs, const int2* items, int nitems, const int* act,
+int apply2d_batch_pass_b(int PY, const BatchProb<T>* probs, const int2* items, int nitems, const int* act, int var,
                          hipStream_t st);
 template <typename T>
 int apply2d_batch_pass_c(int PX, const BatchProb<T>* probs, const int2* items, int nitems, const int* act,
-                         const int* dj, int mode, hipStream_t st);
+                         const int* dj, int mode, int var, hipStream_t st);
 
 // y = x - K~ D x (APPLY_A), K~ x (APPLY_KT) or b - (x - K~ D x) (APPLY_RESID) on nbatch channel
 // vectors [nbatch][C][ny][nx] stored as TV (float64, or float32 with T = float; b is float64),

@@ -537,44 +537,75 @@ int apply2d_pass_c(const Apply2DArgs<T>& a, const TV* x, const double* b, TV* y,
     return 0;
 }
 
-template <typename T, int PX>
-static void launch_a_batch(const BatchProb<T>* probs, const int2* items, int nitems, const int* act, const int* dj,
-                           hipStream_t st) {
+// Row tile of batched variant v (shared by passes A and C): the default, half, twice or a quarter
+// of it, as the single-problem variants; padded x >= 128 only.
+template <typename T>
+int apply2d_batch_row_variants(int PX) { return PX >= 128 ? 4 : 1; }
+template <typename T>
+int apply2d_batch_rows(int var) {
     constexpr int TR = tile_rows<T>();
+    return var == 1 ? TR / 2 : var == 2 ? TR * 2 : var == 3 ? TR / 4 : TR;
+}
+template <typename T, int PX, int TR>
+static void launch_a_batch_tr(const BatchProb<T>* probs, const int2* items, int nitems, const int* act, const int* dj,
+                              hipStream_t st) {
     hipLaunchKernelGGL((k_pass_a_batch<T, PX, TR, 256>), dim3(nitems), dim3(256), 0, st, probs, items, act, dj);
 }
 template <typename T, int PX>
-static void launch_c_batch(const BatchProb<T>* probs, const int2* items, int nitems, const int* act, const int* dj,
-                           int mode, hipStream_t st) {
+static void launch_a_batch(const BatchProb<T>* probs, const int2* items, int nitems, const int* act, const int* dj,
+                           int var, hipStream_t st) {
     constexpr int TR = tile_rows<T>();
+    if constexpr (PX >= 128) {
+        if (var == 1) return launch_a_batch_tr<T, PX, TR / 2>(probs, items, nitems, act, dj, st);
+        if (var == 2) return launch_a_batch_tr<T, PX, TR * 2>(probs, items, nitems, act, dj, st);
+        if (var == 3) return launch_a_batch_tr<T, PX, TR / 4>(probs, items, nitems, act, dj, st);
+    }
+    launch_a_batch_tr<T, PX, TR>(probs, items, nitems, act, dj, st);
+}
+template <typename T, int PX, int TR>
+static void launch_c_batch_tr(const BatchProb<T>* probs, const int2* items, int nitems, const int* act, const int* dj,
+                              int mode, hipStream_t st) {
     hipLaunchKernelGGL((k_pass_c_batch<T, PX, TR, 256>), dim3(nitems), dim3(256), 0, st, probs, items, act, dj, mode);
 }
-template <typename T>
-int apply2d_batch_rows() { return tile_rows<T>(); }
+template <typename T, int PX>
+static void launch_c_batch(const BatchProb<T>* probs, const int2* items, int nitems, const int* act, const int* dj,
+                           int mode, int var, hipStream_t st) {
+    constexpr int TR = tile_rows<T>();
+    if constexpr (PX >= 128) {
+        if (var == 1) return launch_c_batch_tr<T, PX, TR / 2>(probs, items, nitems, act, dj, mode, st);
+        if (var == 2) return launch_c_batch_tr<T, PX, TR * 2>(probs, items, nitems, act, dj, mode, st);
+        if (var == 3) return launch_c_batch_tr<T, PX, TR / 4>(probs, items, nitems, act, dj, mode, st);
+    }
+    launch_c_batch_tr<T, PX, TR>(probs, items, nitems, act, dj, mode, st);
+}
 template <typename T>
 int apply2d_batch_pass_a(int PX, const BatchProb<T>* probs, const int2* items, int nitems, const int* act,
-                         const int* dj, hipStream_t st) {
+                         const int* dj, int var, hipStream_t st) {
     if (nitems <= 0) return 0;
-    RTE_P_SWITCH(PX, launch_a_batch, probs, items, nitems, act, dj, st);
+    if (var < 0 || var >= apply2d_batch_row_variants<T>(PX)) return -1;
+    RTE_P_SWITCH(PX, launch_a_batch, probs, items, nitems, act, dj, var, st);
     return 0;
 }
 template <typename T>
 int apply2d_batch_pass_c(int PX, const BatchProb<T>* probs, const int2* items, int nitems, const int* act,
-                         const int* dj, int mode, hipStream_t st) {
+                         const int* dj, int mode, int var, hipStream_t st) {
     if (nitems <= 0) return 0;
-    RTE_P_SWITCH(PX, launch_c_batch, probs, items, nitems, act, dj, mode, st);
+    if (var < 0 || var >= apply2d_batch_row_variants<T>(PX)) return -1;
+    RTE_P_SWITCH(PX, launch_c_batch, probs, items, nitems, act, dj, mode, var, st);
     return 0;
 }
-template int apply2d_batch_rows<float>();
-template int apply2d_batch_rows<double>();
-template int apply2d_batch_pass_a<float>(int, const BatchProb<float>*, const int2*, int, const int*, const int*,
+template int apply2d_batch_row_variants<float>(int);
+template int apply2d_batch_row_variants<double>(int);
+template int apply2d_batch_rows<float>(int);
+template int apply2d_batch_rows<double>(int);
+template int apply2d_batch_pass_a<float>(int, const BatchProb<float>*, const int2*, int, const int*, const int*, int,
                                          hipStream_t);
-template int apply2d_batch_pass_a<double>(int, const BatchProb<double>*, const int2*, int, const int*, const int*,
+template int apply2d_batch_pass_a<double>(int, const BatchProb<double>*, const int2*, int, const int*, const int*, int,
                                           hipStream_t);
 template int apply2d_batch_pass_c<float>(int, const BatchProb<float>*, const int2*, int, const int*, const int*, int,
-                                         hipStream_t);
+                                         int, hipStream_t);
 template int apply2d_batch_pass_c<double>(int, const BatchProb<double>*, const int2*, int, const int*, const int*, int,
-                                          hipStream_t);
+                                          int, hipStream_t);
 
 template <typename T, typename TV>
 int apply2d(const Apply2DArgs<T>& a, const TV* x, const double* b, TV* y, int mode,

@@ -694,38 +694,80 @@ static int launch_pass_b_impl(const Apply2DArgs<T>& a, int nbatch) {
 #define RTE_CAT2(a, b) a##b
 #define RTE_CAT(a, b) RTE_CAT2(a, b)
 #if RTE_PASSB_L == 0
+// Batched pass-B variants (padded y >= 128): 0 = the fused form's columns per block and threads;
+// 1 = the same columns with half the threads; 2 = twice the columns; 3 = half the columns.
+template <typename T, int PY, int NCOL>
+constexpr bool batch_b_fits() {
+    return ((long)NCOL * padded(PY) + PY + 2) * (long)sizeof(cx<T>) <= lds_budget();
+}
 template <typename T, int PY>
-static void launch_b_batch(const BatchProb<T>* probs, const int2* items, int nitems, const int* act, hipStream_t st) {
+constexpr int batch_b_variants() {
+    return PY < 128 ? 1 : (batch_b_fits<T, PY, 2 * ncol_for<T, PY, 0>()>() ? 4 : 2);
+}
+template <typename T, int PY, int NCOL, int NT>
+static void launch_b_batch_nc(const BatchProb<T>* probs, const int2* items, int nitems, const int* act,
+                              hipStream_t st) {
+    static_assert(batch_b_fits<T, PY, NCOL>(), "batched pass-B columns exceed the LDS budget");
+    hipLaunchKernelGGL((k_pass_b_batch<T, PY, NCOL, NT>), dim3(nitems), dim3(NT), 0, st, probs, items, act);
+}
+template <typename T, int PY>
+static void launch_b_batch(const BatchProb<T>* probs, const int2* items, int nitems, const int* act, int var,
+                           hipStream_t st) {
     static_assert(fused_fits<T, PY, 0>(), "isotropic pass B is always fused");
     constexpr int NCOL = ncol_for<T, PY, 0>();
     constexpr int NT = nthr_for<T, NCOL * PY>();
-    hipLaunchKernelGGL((k_pass_b_batch<T, PY, NCOL, NT>), dim3(nitems), dim3(NT), 0, st, probs, items, act);
+    if constexpr (batch_b_variants<T, PY>() >= 2) {
+        if (var == 1) return launch_b_batch_nc<T, PY, NCOL, (NT / 2 > 64 ? NT / 2 : 64)>(probs, items, nitems, act, st);
+    }
+    if constexpr (batch_b_variants<T, PY>() >= 4) {
+        if (var == 2) return launch_b_batch_nc<T, PY, 2 * NCOL, nthr_for<T, 2 * NCOL * PY>()>(probs, items, nitems,
+                                                                                            act, st);
+        if (var == 3) return launch_b_batch_nc<T, PY, NCOL / 2, nthr_for<T, NCOL / 2 * PY>()>(probs, items, nitems,
+                                                                                            act, st);
+    }
+    launch_b_batch_nc<T, PY, NCOL, NT>(probs, items, nitems, act, st);
 }
 template <typename T>
-int apply2d_batch_cols(int PY) {
-    (void)PY;
-    return ncol_for<T, 1024, 0>();
+int apply2d_batch_col_variants(int PY) {
+    switch (PY) {
+        case 128: return batch_b_variants<T, 128>();
+        case 256: return batch_b_variants<T, 256>();
+        case 512: return batch_b_variants<T, 512>();
+        case 1024: return batch_b_variants<T, 1024>();
+        default: return 1;
+    }
 }
 template <typename T>
-int apply2d_batch_pass_b(int PY, const BatchProb<T>* probs, const int2* items, int nitems, const int* act,
+int apply2d_batch_cols(int PY, int var) {
+    constexpr int NCOL = ncol_for<T, 1024, 0>();   // the same for every PY when C = 1
+    if (var < 0 || var >= apply2d_batch_col_variants<T>(PY)) return 0;
+    return var == 2 ? 2 * NCOL : var == 3 ? NCOL / 2 : NCOL;
+}
+template <typename T>
+int apply2d_batch_pass_b(int PY, const BatchProb<T>* probs, const int2* items, int nitems, const int* act, int var,
                          hipStream_t st) {
     if (nitems <= 0) return 0;
+    if (var < 0 || var >= apply2d_batch_col_variants<T>(PY)) return -1;
     switch (PY) {
-        case 16: launch_b_batch<T, 16>(probs, items, nitems, act, st); break;
-        case 32: launch_b_batch<T, 32>(probs, items, nitems, act, st); break;
-        case 64: launch_b_batch<T, 64>(probs, items, nitems, act, st); break;
-        case 128: launch_b_batch<T, 128>(probs, items, nitems, act, st); break;
-        case 256: launch_b_batch<T, 256>(probs, items, nitems, act, st); break;
-        case 512: launch_b_batch<T, 512>(probs, items, nitems, act, st); break;
-        case 1024: launch_b_batch<T, 1024>(probs, items, nitems, act, st); break;
+        case 16: launch_b_batch<T, 16>(probs, items, nitems, act, var, st); break;
+        case 32: launch_b_batch<T, 32>(probs, items, nitems, act, var, st); break;
+        case 64: launch_b_batch<T, 64>(probs, items, nitems, act, var, st); break;
+        case 128: launch_b_batch<T, 128>(probs, items, nitems, act, var, st); break;
+        case 256: launch_b_batch<T, 256>(probs, items, nitems, act, var, st); break;
+        case 512: launch_b_batch<T, 512>(probs, items, nitems, act, var, st); break;
+        case 1024: launch_b_batch<T, 1024>(probs, items, nitems, act, var, st); break;
         default: return -1;
     }
     return 0;
 }
-template int apply2d_batch_cols<float>(int);
-template int apply2d_batch_cols<double>(int);
-template int apply2d_batch_pass_b<float>(int, const BatchProb<float>*, const int2*, int, const int*, hipStream_t);
-template int apply2d_batch_pass_b<double>(int, const BatchProb<double>*, const int2*, int, const int*, hipStream_t);
+template int apply2d_batch_col_variants<float>(int);
+template int apply2d_batch_col_variants<double>(int);
+template int apply2d_batch_cols<float>(int, int);
+template int apply2d_batch_cols<double>(int, int);
+template int apply2d_batch_pass_b<float>(int, const BatchProb<float>*, const int2*, int, const int*, int,
+                                         hipStream_t);
+template int apply2d_batch_pass_b<double>(int, const BatchProb<double>*, const int2*, int, const int*, int,
+                                          hipStream_t);
 #endif
 
 // Whether pass B takes the work buffer unpacked (x-frequencies 0 and PX/2 in columns of their own)

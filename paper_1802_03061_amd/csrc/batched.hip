@@ -9,6 +9,8 @@
 //     column groups of all its problems), then the Krylov kernels over a global list of 4096-element
 //     chunks of all problems' vectors, Givens rotations with one thread per problem, and a tick that
 //     advances the column index j kept in device memory;
+//   * the tiling of each size class's passes (row tiles of A and C, column groups of B) is chosen
+//     when the plan is built, by timing the variants on all of the class's problems;
 //   * that sequence is captured once into a HIP graph and replayed; a problem whose estimate meets
 //     its target (or that reaches the restart length) clears its active flag on the device and its
 //     blocks exit at once in later replays;
@@ -21,6 +23,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -348,9 +351,11 @@ __global__ __launch_bounds__(BT) void kb_combine(const Chunk* __restrict__ ch, c
 
 struct SizeClass {
     int PX, PY;
+    std::vector<int> probs;    // problems of this padded size, in order
     std::vector<int2> ac, b;   // (problem, row tile) and (problem, column group)
-    int2* dac = nullptr;
+    int2* dac = nullptr;       // device lists, room for the most items of any variant
     int2* db = nullptr;
+    int vr = 0, vb = 0;        // variants: row tiles of passes A and C, column groups of pass B
 };
 
 template <typename T>
@@ -370,11 +375,11 @@ template <typename T>
 int apply_batch(const std::vector<SizeClass>& cls, const BatchProb<T>* probs, const int* mask, const int* dj, int mode,
                 hipStream_t st) {
     for (const auto& k : cls)
-        if (apply2d_batch_pass_a<T>(k.PX, probs, k.dac, (int)k.ac.size(), mask, dj, st)) return -1;
+        if (apply2d_batch_pass_a<T>(k.PX, probs, k.dac, (int)k.ac.size(), mask, dj, k.vr, st)) return -1;
     for (const auto& k : cls)
-        if (apply2d_batch_pass_b<T>(k.PY, probs, k.db, (int)k.b.size(), mask, st)) return -1;
+        if (apply2d_batch_pass_b<T>(k.PY, probs, k.db, (int)k.b.size(), mask, k.vb, st)) return -1;
     for (const auto& k : cls)
-        if (apply2d_batch_pass_c<T>(k.PX, probs, k.dac, (int)k.ac.size(), mask, dj, mode, st)) return -1;
+        if (apply2d_batch_pass_c<T>(k.PX, probs, k.dac, (int)k.ac.size(), mask, dj, mode, k.vr, st)) return -1;
     return 0;
 }
 
@@ -456,11 +461,116 @@ X* carve(char* base, size_t& used, size_t n) {
     return reinterpret_cast<X*>(base + off);
 }
 
+// The (problem, row tile) and (problem, column group) items of size class k for row tiles of tr
+// rows and groups of nc columns, in XCD order.
+void fill_items(SizeClass& k, rte_ctx* const* ctxs, int tr, int nc) {
+    k.ac.clear();
+    k.b.clear();
+    for (int p : k.probs) {
+        for (int t = 0; t < (ctxs[p]->ny + tr - 1) / tr; ++t) k.ac.push_back(make_int2(p, t));
+        for (int t = 0; t < (ctxs[p]->PX / 2 + nc - 1) / nc; ++t) k.b.push_back(make_int2(p, t));
+    }
+    k.ac = xcd_order(k.ac);
+    k.b = xcd_order(k.b);
+}
+
+// Item-list room of size class k over every variant of precision T (the smallest tiles give the
+// most items).
+template <typename T>
+std::pair<size_t, size_t> item_room(const SizeClass& k, rte_ctx* const* ctxs) {
+    int tr = 1 << 30, nc = 1 << 30;
+    for (int v = 0; v < apply2d_batch_row_variants<T>(k.PX); ++v) tr = std::min(tr, apply2d_batch_rows<T>(v));
+    for (int v = 0; v < apply2d_batch_col_variants<T>(k.PY); ++v) nc = std::min(nc, apply2d_batch_cols<T>(k.PY, v));
+    size_t nac = 0, nb = 0;
+    for (int p : k.probs) {
+        nac += (size_t)(ctxs[p]->ny + tr - 1) / tr;
+        nb += (size_t)(ctxs[p]->PX / 2 + nc - 1) / nc;
+    }
+    return {nac, nb};
+}
+
+// Variants forced by rte_set_batched_variant (-1: tuned); guarded by g_plan_mu.
+int g_force[2] = {-1, -1};
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// Choose the row-tile variant (passes A and C together) and the column-group variant (pass B) of
+// every size class of the iteration's item lists: the fastest (best of 3 runs of 5 launches) over
+// all of the class's problems (every problem active, basis column 0 in, column 1 out) on the plan stream,
+// unless forced by rte_set_batched_variant or disabled by RTE_AUTOTUNE=0 (variant 0).  Leaves the
+// chosen lists on the device.
+template <typename T>
+int tune_plan(Plan& pl, rte_ctx* const* ctxs) {
+    hipStream_t st = pl.st;
+    const char* at = std::getenv("RTE_AUTOTUNE");
+    const bool tune = !(at && at[0] == '0');
+    constexpr int reps = 5, trials = 3;
+    const BatchProb<T>* probs = (const BatchProb<T>*)pl.d_it;
+    std::vector<int> ones(pl.P, 1);
+    const int j0[2] = {0, 0};
+    BK_TRY(hipMemcpyAsync(pl.d_act, ones.data(), sizeof(int) * pl.P, hipMemcpyHostToDevice, st));
+    BK_TRY(hipMemcpyAsync(pl.d_j, j0, sizeof(int), hipMemcpyHostToDevice, st));
+    BK_TRY(hipStreamSynchronize(st));
+    EventPair ev;
+    BK_TRY(hipEventCreate(&ev.a));
+    BK_TRY(hipEventCreate(&ev.b));
+    auto upload = [&](const SizeClass& k) -> int {
+        BK_TRY(hipMemcpyAsync(k.dac, k.ac.data(), sizeof(int2) * k.ac.size(), hipMemcpyHostToDevice, st));
+        BK_TRY(hipMemcpyAsync(k.db, k.b.data(), sizeof(int2) * k.b.size(), hipMemcpyHostToDevice, st));
+        BK_TRY(hipStreamSynchronize(st));
+        return RTE_OK;
+    };
+    auto launch = [&](const SizeClass& k, int which) {
+        if (which == 1) return apply2d_batch_pass_b<T>(k.PY, probs, k.db, (int)k.b.size(), pl.d_act, k.vb, st);
+        if (apply2d_batch_pass_a<T>(k.PX, probs, k.dac, (int)k.ac.size(), pl.d_act, pl.d_j, k.vr, st)) return -1;
+        return apply2d_batch_pass_c<T>(k.PX, probs, k.dac, (int)k.ac.size(), pl.d_act, pl.d_j, APPLY_A, k.vr, st);
+    };
+    auto timed = [&](SizeClass& k, int which, double* ms) -> int {
+        fill_items(k, ctxs, apply2d_batch_rows<T>(k.vr), apply2d_batch_cols<T>(k.PY, k.vb));
+        if (int rc = upload(k)) return rc;
+        if (launch(k, which)) return set_error(RTE_EUNSUPPORTED, "batched apply: unsupported size");   // warm-up
+        for (int trial = 0; trial < trials; ++trial) {   // the best of a few runs of `reps` launches
+            BK_TRY(hipEventRecord(ev.a, st));
+            for (int r = 0; r < reps; ++r) (void)launch(k, which);
+            BK_TRY(hipEventRecord(ev.b, st));
+            BK_TRY(hipEventSynchronize(ev.b));
+            float t = 0.f;
+            BK_TRY(hipEventElapsedTime(&t, ev.a, ev.b));
+            if (trial == 0 || t < *ms) *ms = t;
+        }
+        return RTE_OK;
+    };
+    for (auto& k : pl.cls) {
+        const int nv[2] = {apply2d_batch_row_variants<T>(k.PX), apply2d_batch_col_variants<T>(k.PY)};
+        int* var[2] = {&k.vr, &k.vb};
+        for (int w = 0; w < 2; ++w) *var[w] = g_force[w] >= 0 && g_force[w] < nv[w] ? g_force[w] : 0;
+        for (int w = 0; w < 2; ++w) {
+            if (!tune || g_force[w] >= 0 || nv[w] < 2) continue;
+            double best = 0.0;
+            int bv = 0;
+            for (int v = 0; v < nv[w]; ++v) {
+                *var[w] = v;
+                double ms = 0.0;
+                if (int rc = timed(k, w, &ms)) return rc;
+                if (v == 0 || ms < best) { best = ms; bv = v; }
+            }
+            *var[w] = bv;
+        }
+        fill_items(k, ctxs, apply2d_batch_rows<T>(k.vr), apply2d_batch_cols<T>(k.PY, k.vb));
+        if (int rc = upload(k)) return rc;
+    }
+    return RTE_OK;
+}
+
 template <typename T>
 int build_plan(Plan& pl, int P, rte_ctx* const* ctxs) {
     const int m = pl.m;
-    const int TRf = apply2d_batch_rows<T>(), TRd = apply2d_batch_rows<double>();
-    const int NCf = apply2d_batch_cols<T>(0), NCd = apply2d_batch_cols<double>(0);
     std::map<std::pair<int, int>, int> cls_index;
     pl.kp.assign(P, KryProb{});
     for (int p = 0; p < P; ++p) {
@@ -478,26 +588,18 @@ int build_plan(Plan& pl, int P, rte_ctx* const* ctxs) {
             sc.PY = c->PY;
             pl.cls.push_back(sc);
         }
+        pl.cls[cls_index[key]].probs.push_back(p);
     }
-    // the iteration uses precision T, the right-hand side and residual FP64: separate item lists
+    // the iteration uses precision T (its variants tuned below), the right-hand side and residual
+    // FP64 with variant 0: separate item lists
     pl.cls_d = pl.cls;
-    for (int p = 0; p < P; ++p) {
-        const rte_ctx* c = ctxs[p];
-        const int ci = cls_index[std::make_pair(c->PX, c->PY)];
-        for (int t = 0; t < (c->ny + TRf - 1) / TRf; ++t) pl.cls[ci].ac.push_back(make_int2(p, t));
-        for (int t = 0; t < (c->PX / 2 + NCf - 1) / NCf; ++t) pl.cls[ci].b.push_back(make_int2(p, t));
-        for (int t = 0; t < (c->ny + TRd - 1) / TRd; ++t) pl.cls_d[ci].ac.push_back(make_int2(p, t));
-        for (int t = 0; t < (c->PX / 2 + NCd - 1) / NCd; ++t) pl.cls_d[ci].b.push_back(make_int2(p, t));
-    }
-    for (auto* list : {&pl.cls, &pl.cls_d})
-        for (auto& k : *list) {
-            k.ac = xcd_order(k.ac);
-            k.b = xcd_order(k.b);
-        }
+    for (auto& k : pl.cls_d) fill_items(k, ctxs, apply2d_batch_rows<double>(0), apply2d_batch_cols<double>(k.PY, 0));
+    std::vector<std::pair<size_t, size_t>> room;
+    for (auto& k : pl.cls) room.push_back(item_room<T>(k, ctxs));
     const int NCH = pl.NCH = (int)pl.chunks.size();
     const size_t S = pl.S = (size_t)(m + 1) * m + 4 * (size_t)m + 2;   // Arnoldi slab per problem
     size_t items = 0;
-    for (auto& k : pl.cls) items += k.ac.size() + k.b.size();
+    for (auto& r : room) items += r.first + r.second;
     for (auto& k : pl.cls_d) items += k.ac.size() + k.b.size();
     const size_t ntake = 16 + 4 * pl.cls.size();
     const size_t cap = 256 * ntake + sizeof(Chunk) * NCH + sizeof(KryProb) * P + sizeof(BState) * P +
@@ -517,7 +619,10 @@ int build_plan(Plan& pl, int P, rte_ctx* const* ctxs) {
     pl.d_part2 = carve<double>(a, used, NCH);
     pl.d_rn2 = carve<double>(a, used, P);
     pl.d_slab = carve<double>(a, used, S * P);
-    for (auto& k : pl.cls) { k.dac = carve<int2>(a, used, k.ac.size()); k.db = carve<int2>(a, used, k.b.size()); }
+    for (size_t i = 0; i < pl.cls.size(); ++i) {
+        pl.cls[i].dac = carve<int2>(a, used, room[i].first);
+        pl.cls[i].db = carve<int2>(a, used, room[i].second);
+    }
     for (auto& k : pl.cls_d) { k.dac = carve<int2>(a, used, k.ac.size()); k.db = carve<int2>(a, used, k.b.size()); }
     pl.d_it = carve<BatchProb<T>>(a, used, P);
     pl.d_res = carve<BatchProb<double>>(a, used, P);
@@ -549,16 +654,12 @@ int build_plan(Plan& pl, int P, rte_ctx* const* ctxs) {
     BK_TRY(hipMemcpyAsync(pl.d_ch, pl.chunks.data(), sizeof(Chunk) * NCH, hipMemcpyHostToDevice, st));
     BK_TRY(hipMemcpyAsync(pl.d_it, it.data(), sizeof(BatchProb<T>) * P, hipMemcpyHostToDevice, st));
     BK_TRY(hipMemcpyAsync(pl.d_res, res.data(), sizeof(BatchProb<double>) * P, hipMemcpyHostToDevice, st));
-    for (size_t i = 0; i < pl.cls.size(); ++i) {
-        auto up = [&](int2* d, const std::vector<int2>& h) {
-            return hipMemcpyAsync(d, h.data(), sizeof(int2) * h.size(), hipMemcpyHostToDevice, st);
-        };
-        BK_TRY(up(pl.cls[i].dac, pl.cls[i].ac));
-        BK_TRY(up(pl.cls[i].db, pl.cls[i].b));
-        BK_TRY(up(pl.cls_d[i].dac, pl.cls_d[i].ac));
-        BK_TRY(up(pl.cls_d[i].db, pl.cls_d[i].b));
+    for (const auto& k : pl.cls_d) {
+        BK_TRY(hipMemcpyAsync(k.dac, k.ac.data(), sizeof(int2) * k.ac.size(), hipMemcpyHostToDevice, st));
+        BK_TRY(hipMemcpyAsync(k.db, k.b.data(), sizeof(int2) * k.b.size(), hipMemcpyHostToDevice, st));
     }
     BK_TRY(hipStreamSynchronize(st));   // host staging vectors go out of scope
+    if (int rc = tune_plan<T>(pl, ctxs)) return rc;
     // pinned host staging; the active count is written by the tick kernel straight into it
     const size_t pin_bytes = sizeof(BState) * P + sizeof(int) * 2 * P + 8 + sizeof(double) * P + sizeof(int) * (m + 1) + 64;
     BK_TRY(hipHostMalloc(&pl.pinned, pin_bytes, hipHostMallocMapped | hipHostMallocCoherent));
@@ -777,7 +878,7 @@ int solve_batched_t(int P, rte_ctx* const* ctxs, const double* const* f, const d
 // one launch per pass and padded size, each bracketed by events on the plan's stream.
 template <typename T>
 int time_plan(Plan& pl, int reps, double* ms_total, int max_launch, int* n_launch, double* ms_launch, int* launch_pass,
-              int* launch_px, int* launch_py) {
+              int* launch_px, int* launch_py, int* launch_var) {
     hipStream_t st = pl.st;
     const int P = pl.P, ncls = (int)pl.cls.size(), nl = 3 * ncls;
     std::vector<int> ones(P, 1);
@@ -795,10 +896,12 @@ int time_plan(Plan& pl, int reps, double* ms_total, int max_launch, int* n_launc
         if (hipEventRecord(ev[0], st) != hipSuccess) { rc = set_error(RTE_EDEVICE, "hipEventRecord failed"); break; }
         for (int pass = 0; pass < 3 && !rc; ++pass)
             for (const auto& k : pl.cls) {
-                int bad = pass == 0 ? apply2d_batch_pass_a<T>(k.PX, probs, k.dac, (int)k.ac.size(), pl.d_act, pl.d_j, st)
-                        : pass == 1 ? apply2d_batch_pass_b<T>(k.PY, probs, k.db, (int)k.b.size(), pl.d_act, st)
-                                    : apply2d_batch_pass_c<T>(k.PX, probs, k.dac, (int)k.ac.size(), pl.d_act, pl.d_j,
-                                                              APPLY_A, st);
+                int bad = pass == 0
+                              ? apply2d_batch_pass_a<T>(k.PX, probs, k.dac, (int)k.ac.size(), pl.d_act, pl.d_j, k.vr, st)
+                          : pass == 1
+                              ? apply2d_batch_pass_b<T>(k.PY, probs, k.db, (int)k.b.size(), pl.d_act, k.vb, st)
+                              : apply2d_batch_pass_c<T>(k.PX, probs, k.dac, (int)k.ac.size(), pl.d_act, pl.d_j,
+                                                        APPLY_A, k.vr, st);
                 if (bad) { rc = set_error(RTE_EUNSUPPORTED, "batched apply: unsupported size"); break; }
                 if (hipEventRecord(ev[++q], st) != hipSuccess) { rc = set_error(RTE_EDEVICE, "hipEventRecord failed"); break; }
             }
@@ -822,6 +925,7 @@ int time_plan(Plan& pl, int reps, double* ms_total, int max_launch, int* n_launc
         if (launch_pass) launch_pass[i] = i / ncls;
         if (launch_px) launch_px[i] = pl.cls[i % ncls].PX;
         if (launch_py) launch_py[i] = pl.cls[i % ncls].PY;
+        if (launch_var) launch_var[i] = i / ncls == 1 ? pl.cls[i % ncls].vb : pl.cls[i % ncls].vr;
     }
     return RTE_OK;
 }
@@ -829,7 +933,7 @@ int time_plan(Plan& pl, int reps, double* ms_total, int max_launch, int* n_launc
 }  // namespace
 
 int time_batched_impl(int count, rte_ctx* const* ctxs, int reps, double* ms_total, int max_launch, int* n_launch,
-                      double* ms_launch, int* launch_pass, int* launch_px, int* launch_py) {
+                      double* ms_launch, int* launch_pass, int* launch_px, int* launch_py, int* launch_var) {
     if (count < 1 || !ctxs || reps < 1 || max_launch < 0) return set_error(RTE_EINVAL, "bad argument");
     for (int i = 0; i < count; ++i)
         if (!ctxs[i]) return set_error(RTE_EINVAL, "problem %d: NULL context", i);
@@ -845,12 +949,22 @@ int time_batched_impl(int count, rte_ctx* const* ctxs, int reps, double* ms_tota
         if (q->ids == ids && q->m == ctxs[0]->opts.restart && q->prec == ctxs[0]->prec && q->bufs == bufs) {
             return q->prec == RTE_PREC_FP32
                        ? time_plan<float>(*q, reps, ms_total, max_launch, n_launch, ms_launch, launch_pass, launch_px,
-                                          launch_py)
+                                          launch_py, launch_var)
                        : time_plan<double>(*q, reps, ms_total, max_launch, n_launch, ms_launch, launch_pass, launch_px,
-                                           launch_py);
+                                           launch_py, launch_var);
         }
     }
     return set_error(RTE_EINVAL, "no batch plan for these contexts: call rte_solve_batched on them first");
+}
+
+// Force the batched variants of every later plan (pass 0: row tiles of passes A and C, 1: column
+// groups of pass B; -1: tuned) and drop the cached plans.
+int batched_set_variant(int pass, int variant) {
+    if (pass < 0 || pass > 1 || variant < -1 || variant > 3) return set_error(RTE_EINVAL, "bad batched variant");
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    g_force[pass] = variant;
+    plans().clear();
+    return RTE_OK;
 }
 
 // A context is going away: drop every cached batch plan that refers to it.

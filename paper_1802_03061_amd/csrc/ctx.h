@@ -118,6 +118,7 @@ namespace rte {
 int solve_batched_impl(int count, rte_ctx* const* ctxs, const double* const* f, const double* tol, int max_iter,
                        void* const* u, rte_solve_info* infos);
 int time_batched_impl(int count, rte_ctx* const* ctxs, int reps, double* ms_total, int max_launch, int* n_launch,
-                      double* ms_launch, int* launch_pass, int* launch_px, int* launch_py);
+                      double* ms_launch, int* launch_pass, int* launch_px, int* launch_py, int* launch_var);
+int batched_set_variant(int pass, int variant);
 void batched_forget(unsigned long long id);
 }  // namespace rte

@@ -1305,7 +1305,9 @@ extern "C" int rte_solve_batched(int count, rte_ctx* const* ctxs, const double* 
 
 extern "C" int rte_time_batched_apply(int count, rte_ctx* const* ctxs, int reps, double* ms_total, int max_launch,
                                       int* n_launch, double* ms_launch, int* launch_pass, int* launch_px,
-                                      int* launch_py) {
+                                      int* launch_py, int* launch_var) {
     return rte::time_batched_impl(count, ctxs, reps, ms_total, max_launch, n_launch, ms_launch, launch_pass,
-                                  launch_px, launch_py);
+                                  launch_px, launch_py, launch_var);
 }
+
+extern "C" int rte_set_batched_variant(int pass, int variant) { return rte::batched_set_variant(pass, variant); }

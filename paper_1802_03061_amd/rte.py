@@ -92,7 +92,8 @@ def load():
         "rte_time_apply": (I, [P, I, I, I, C.POINTER(D), C.POINTER(D)]),
         "rte_time_apply_multi": (I, [P, I, I, I, I, C.POINTER(D), C.POINTER(D)]),
         "rte_time_batched_apply": (I, [I, C.POINTER(P), I, C.POINTER(D), I, C.POINTER(I), C.POINTER(D),
-                                       C.POINTER(I), C.POINTER(I), C.POINTER(I)]),
+                                       C.POINTER(I), C.POINTER(I), C.POINTER(I), C.POINTER(I)]),
+        "rte_set_batched_variant": (I, [I, I]),
         "rte_query": (I, [P, C.POINTER(I), C.POINTER(I), C.POINTER(C.c_longlong)]),
         "rte_autotune": (I, [P, I]),
         "rte_set_variant": (I, [P, I, I, I]),
@@ -382,16 +383,22 @@ def solve_batched(ctxs, fs, tols, max_iter=1000, allow_not_converged=False):
 
 def time_batched_apply(ctxs, reps=20):
     """Per-launch times of the batched apply (rte_time_batched_apply); needs a prior solve_batched
-    on the same contexts.  Returns (ms_total, [(pass, PX, PY, ms), ...])."""
+    on the same contexts.  Returns (ms_total, [(pass, PX, PY, ms, variant), ...])."""
     n = len(ctxs)
     hs = (C.c_void_p * n)(*[c._h for c in ctxs])
     cap = 64
     tot = C.c_double()
     nl = C.c_int()
     ms = (C.c_double * cap)()
-    ps, px, py = (C.c_int * cap)(), (C.c_int * cap)(), (C.c_int * cap)()
-    _check(load().rte_time_batched_apply(n, hs, int(reps), C.byref(tot), cap, C.byref(nl), ms, ps, px, py))
-    return tot.value, [(ps[i], px[i], py[i], ms[i]) for i in range(min(nl.value, cap))]
+    ps, px, py, pv = (C.c_int * cap)(), (C.c_int * cap)(), (C.c_int * cap)(), (C.c_int * cap)()
+    _check(load().rte_time_batched_apply(n, hs, int(reps), C.byref(tot), cap, C.byref(nl), ms, ps, px, py, pv))
+    return tot.value, [(ps[i], px[i], py[i], ms[i], pv[i]) for i in range(min(nl.value, cap))]
+
+
+def set_batched_variant(pass_, variant):
+    """Force a kernel variant of the batched apply for plans built afterwards (rte_set_batched_variant):
+    pass 0 = row tiles of passes A and C, 1 = column groups of pass B; -1 restores tuning."""
+    _check(load().rte_set_batched_variant(int(pass_), int(variant)))
 
 
 def _stream():

@@ -101,6 +101,10 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.rte_scattering_term(None, 0, None, 8, None) == rte.RTE_EINVAL
     assert lib.rte_set_variant(None, 0, 0, 0) == rte.RTE_EINVAL
     assert lib.rte_get_variant(None, 0, 0, None, None) == rte.RTE_EINVAL
+    for pass_, var in ((2, 0), (-1, 0), (0, 4), (1, -2)):
+        assert lib.rte_set_batched_variant(pass_, var) == rte.RTE_EINVAL
+    assert lib.rte_set_batched_variant(0, -1) == rte.RTE_OK
+    assert lib.rte_set_batched_variant(1, -1) == rte.RTE_OK
     lib.rte_destroy(None)
     assert b"gfx950" in lib.rte_version()
 

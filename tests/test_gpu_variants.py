@@ -109,3 +109,48 @@ def test_variants_3d_match_oracle(rte, n, L, prec):
     y = host(ctx.apply(x, op=rte.OP_A, layout=rte.LAYOUT_CHANNELS))
     assert relerr(y.reshape(ref.shape), ref) <= (1e-6 if prec == rte.PREC_FP32 else 1e-12)
     ctx.close()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", [1, 0])
+def test_batched_variants_match_oracle(rte, prec):
+    """The batched solver under every forced row-tile variant (passes A and C) and every column-group
+    variant (pass B): problems of five padded sizes (64 .. 1024, ragged tiles), each batched
+    solution against the oracle's FP64 reference solve of its own problem; then the tuned plan,
+    whose reported variants must be in range."""
+    import oracle_ref
+    say("batched variants prec", prec)
+    rng = np.random.default_rng(31 + prec)
+    sizes = (20, 64, 100, 150, 300, 64)
+    probs = [dict(n=n, mu_s=float(rng.uniform(0.5, 8.0)), mu_a=float(rng.uniform(0.05, 0.5)),
+                  params=inputs.gaussian_mixture_params(rng, 2)) for n in sizes]
+    srcs = [inputs.gaussian_mixture_source(p["n"], p["params"]) for p in probs]
+    refs = [oracle_ref.Ref2D(f, p["n"], 0, p["mu_a"], p["mu_s"], np.ones(1)) for p, f in zip(probs, srcs)]
+    tol, bar = (1e-8, 1e-6) if prec == rte.PREC_FP32 else (1e-11, 1e-9)
+    ctxs = [rte.Context(p["n"], mu_a=p["mu_a"], mu_s=p["mu_s"], L=0, prec=prec) for p in probs]
+    fs = [dev(f) for f in srcs]
+    combos = [(v, 0) for v in range(4)] + [(3, v) for v in range(4)] + [(-1, -1)]
+    try:
+        for vr, vb in combos:
+            rte.set_batched_variant(0, vr)
+            rte.set_batched_variant(1, vb)
+            us, infos, rc = rte.solve_batched(ctxs, fs, [tol] * len(ctxs))
+            assert rc == rte.RTE_OK
+            _, launches = rte.time_batched_apply(ctxs, reps=2)
+            used = {(ps, px): var for ps, px, py, ms, var in launches}
+            for (ps, px), var in used.items():
+                if px < 128:
+                    assert var == 0
+                elif vr >= 0:
+                    assert var == (vb if ps == 1 else vr)
+                else:
+                    assert 0 <= var < 4
+            worst = max(relerr(host(u), r.u) for u, r in zip(us, refs))
+            say(f"  forced ({vr}, {vb}): launches {sorted(used.items())} worst relerr vs oracle {worst:.2e}")
+            assert worst <= bar
+            assert max(i["relres_true"] for i in infos) <= tol
+    finally:
+        rte.set_batched_variant(0, -1)
+        rte.set_batched_variant(1, -1)
+        for c in ctxs:
+            c.close()
