@@ -480,7 +480,6 @@ __global__ __launch_bounds__(NTHR) void k_pass_b_half(cx<T>* __restrict__ Tb, cx
     constexpr int G = (3 * NTHR * 8) / PH >= C ? C : ((3 * NTHR * 8) / PH < 1 ? 1 : (3 * NTHR * 8) / PH);
     __shared__ cx<T> spec[C * LD];
     __shared__ cx<T> tws[PH];
-    __shared__ cx<T> pairtmp[2 * C];   // Q of the two self-mirrored frequencies of a packed column
     const int tid = threadIdx.x;
     const int kx = blockIdx.x, b = blockIdx.y;
     const size_t cstride = (size_t)nkx * ny;
@@ -489,6 +488,7 @@ __global__ __launch_bounds__(NTHR) void k_pass_b_half(cx<T>* __restrict__ Tb, cx
     const size_t qs = (size_t)nkq * KH;
     stage_twiddles<T, PH, NTHR>(tws, twh, tid);
     for (int h = 0; h < 2; ++h) {
+#pragma unroll 1
         for (int n = tid; n < PH; n += NTHR) {
             cx<T> w = mk((T)1, (T)0);
             if (h == 1) {
@@ -506,26 +506,47 @@ __global__ __launch_bounds__(NTHR) void k_pass_b_half(cx<T>* __restrict__ Tb, cx
         block_fft_grouped<T, PH, C, G, LD, NTHR, false>(spec, tws, tid);
         if (pack && kx == 0) {
             // column 0 packs the x-frequencies 0 and PX/2: split each frequency pair (f, PY - f), both
-            // in this half, into the two real sequences' spectra, couple each with its kernel column
+            // in this half, into the two real sequences' spectra (D kept at f, Q moved to PY - f),
+            // couple each with its kernel column, recombine.  The Q of the two self-mirrored
+            // frequencies (0 and PY/2) go to the slots 16 and 33 of each channel row, which the
+            // swizzle sw() never uses, so that every coupling has the channel stride LD.
+#pragma unroll 1
             for (int k = tid; k < PH; k += NTHR) {
                 const int f = 2 * k + h;
                 if (f > HY) continue;
                 const int fm = (PY - f) & (PY - 1);
-                const int km = (fm - h) / 2;
                 const bool self = fm == f;
                 cx<T>* zf = spec + sw(k);
-                cx<T>* zq = self ? pairtmp + (f == 0 ? 0 : C) : spec + sw(km);
+                cx<T>* zq = spec + (self ? (f == 0 ? 16 : 33) : sw((fm - h) / 2));
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
                     const cx<T> z = zf[c * LD], w = conj(self ? z : zq[c * LD]);
                     zf[c * LD] = scale(z + w, (T)0.5);
-                    zq[c * (self ? 1 : LD)] = scale(mul_mi(z - w), (T)0.5);
+                    zq[c * LD] = scale(mul_mi(z - w), (T)0.5);
                 }
-                couple_inplace<T, L>(zf, LD, Q, qs, (size_t)f, false);
-                couple_inplace<T, L>(zq, self ? 1 : LD, Q, qs, (size_t)(nkq - 1) * KH + f, false);
+            }
+            __syncthreads();
+#pragma unroll 1
+            for (int it = tid; it < 2 * PH; it += NTHR) {
+                const int k = it >> 1, f = 2 * k + h;
+                if (f > HY) continue;
+                const int fm = (PY - f) & (PY - 1);
+                const bool self = fm == f, isq = it & 1;
+                cx<T>* z = spec + (!isq ? sw(k) : (self ? (f == 0 ? 16 : 33) : sw((fm - h) / 2)));
+                couple_inplace<T, L>(z, LD, Q, qs, isq ? (size_t)(nkq - 1) * KH + f : (size_t)f, false);
+            }
+            __syncthreads();
+#pragma unroll 1
+            for (int k = tid; k < PH; k += NTHR) {
+                const int f = 2 * k + h;
+                if (f > HY) continue;
+                const int fm = (PY - f) & (PY - 1);
+                const bool self = fm == f;
+                cx<T>* zf = spec + sw(k);
+                cx<T>* zq = spec + (self ? (f == 0 ? 16 : 33) : sw((fm - h) / 2));
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    const cx<T> d = zf[c * LD], q = zq[c * (self ? 1 : LD)];
+                    const cx<T> d = zf[c * LD], q = zq[c * LD];
                     zf[c * LD] = d + mul_i(q);
                     if (!self) zq[c * LD] = conj(d) + mul_i(conj(q));
                 }
@@ -533,6 +554,7 @@ __global__ __launch_bounds__(NTHR) void k_pass_b_half(cx<T>* __restrict__ Tb, cx
         } else {
             // frequencies in the order [0, PH/4), [3PH/4, PH), [PH/4, 3PH/4): a frequency and its
             // mirror, which read the same quarter-table entries, fall in the same sweep
+#pragma unroll 1
             for (int ki = tid; ki < PH; ki += NTHR) {
                 const int k = ki < PH / 4 ? ki : (ki < PH / 2 ? ki + PH / 2 : ki - PH / 4);
                 const int f = 2 * k + h;
@@ -542,6 +564,7 @@ __global__ __launch_bounds__(NTHR) void k_pass_b_half(cx<T>* __restrict__ Tb, cx
         }
         __syncthreads();
         block_fft_grouped<T, PH, C, G, LD, NTHR, true>(spec, tws, tid);
+#pragma unroll 1
         for (int n = tid; n < ny; n += NTHR) {
             cx<T> w = mk((T)1, (T)0);
             if (h == 1) {
@@ -562,9 +585,8 @@ __global__ __launch_bounds__(NTHR) void k_pass_b_half(cx<T>* __restrict__ Tb, cx
 
 template <typename T, int PY, int L>
 constexpr bool half_fits() {
-    // LDS of k_pass_b_half: one half of the column's spectra, the half-length twiddles, the pair scratch
-    return PY >= 64 && ((long)(2 * L + 1) * padded(PY / 2) + PY / 2 + 2 * (2 * L + 1)) * (long)sizeof(cx<T>) <=
-                           160 * 1024;
+    // LDS of k_pass_b_half: one half of the column's spectra and the half-length twiddles
+    return PY >= 64 && ((long)(2 * L + 1) * padded(PY / 2) + PY / 2) * (long)sizeof(cx<T>) <= 160 * 1024;
 }
 
 constexpr int lds_budget() { return 160 * 1024; }
