@@ -92,10 +92,12 @@ typedef struct {
 typedef struct {
     int restart;         /* Krylov dimension per cycle, 1..RTE_MAX_RESTART (default 64) */
     int max_cycles;      /* refinement cycles (default 8) */
-    double inner_tol;    /* per-cycle relative reduction for the FP32 inner solve (default 3e-5,
-                            which at 512^2, L = 8 splits the iterations most evenly between the
-                            two refinement cycles; ignored for RTE_PREC_FP64, whose cycles run to
-                            the requested tol) */
+    double inner_tol;    /* per-cycle relative reduction for the FP32 inner solve (default 3e-4:
+                            both refinement cycles stay short, and a step's Gram-Schmidt cost
+                            grows with its position in the cycle; rte_solve_batched takes at most
+                            3e-5, since its problems advance in lockstep and a third cycle for a
+                            few of them costs the whole batch; ignored for RTE_PREC_FP64, whose
+                            cycles run to the requested tol) */
     int reorth;          /* classical Gram-Schmidt passes: 0 = one pass (default; each restart
                             cycle ends with an FP64 true-residual check), 1 = a second pass when
                             the norm drops below 1/sqrt(2) of its value, 2 = always two passes.

@@ -860,7 +860,7 @@ int rte_setup(rte_ctx** out, const rte_grid* g, double mu_a, double mu_s, const 
     c->nvec = (size_t)c->C * c->ncell;
     c->opts.restart = 64;
     c->opts.max_cycles = 8;
-    c->opts.inner_tol = 3e-5;
+    c->opts.inner_tol = 3e-4;
     c->opts.reorth = 0;
     c->opts.use_pc = 1;
     c->opts.basis_fp32 = 0;
@@ -1004,7 +1004,7 @@ int rte_set_solve_opts(rte_ctx* c, const rte_solve_opts* o) {
     rte_solve_opts d;
     d.restart = 64;
     d.max_cycles = 8;
-    d.inner_tol = 3e-5;
+    d.inner_tol = 3e-4;
     d.reorth = 0;
     d.use_pc = 1;
     d.basis_fp32 = 0;

@@ -226,7 +226,7 @@ class Context:
         _check(load().rte_scattering_term(self._h, layout, up, int(ntheta), sp))
         return out
 
-    def set_opts(self, restart=64, max_cycles=8, inner_tol=3e-5, reorth=0, use_pc=1, basis_fp32=0):
+    def set_opts(self, restart=64, max_cycles=8, inner_tol=3e-4, reorth=0, use_pc=1, basis_fp32=0):
         o = SolveOpts(restart, max_cycles, inner_tol, reorth, use_pc, basis_fp32)
         _check(load().rte_set_solve_opts(self._h, C.byref(o)))
 
