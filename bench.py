@@ -794,6 +794,30 @@ def bench_iso32(args, torch, rte, with_oracle: bool):
     return out, cpu
 
 
+def solves_only(args, torch, rte):
+    """Preconditioned solves alone, after a pause that separates them from the setup in a trace."""
+    from paper_1802_03061_amd import inputs, pc_train
+    if args.workload not in ("hg512", "diff256"):
+        raise SystemExit("--solves-only takes --workload hg512 or diff256")
+    mu_s = args.mu_s if args.mu_s is not None else (10.0 if args.workload == "hg512" else 50.0)
+    w = inputs.workload(args.workload, seed=0, mu_s=mu_s)
+    n, L = w["n"], w["L"]
+    ctx = rte.Context(n, mu_a=w["mu_a"], mu_s=w["mu_s"], sigma_hat=w["sigma_hat"], L=L, prec=rte.PREC_FP32)
+    fs = [torch.from_numpy(inputs.workload(args.workload, seed=s, mu_s=mu_s)["f"]).cuda()
+          for s in range(max(args.steps, 2))]
+    F = pc_train.coarse_factor(n)
+    net, meta = pc_train.train_for(ctx, range(10000, 10012), args.workload, F, steps=args.train_steps, mu_s=mu_s)
+    ctx.attach_pc(net.params(), hidden=meta["hidden"], layers=meta["layers"], factor=F)
+    for i in range(2):
+        ctx.solve(fs[i])
+    torch.cuda.synchronize()
+    time.sleep(0.3)
+    r = timed_solves(ctx, fs, args.steps, 0, torch)
+    ctx.close()
+    net.close()
+    return {"workload": args.workload, "solves": args.steps, **r}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -814,6 +838,10 @@ def main():
     ap.add_argument("--variants", default=None, help="JSON list of [variant, count] for passes A, B, C")
     ap.add_argument("--force-variants", default=None,
                     help="JSON list of the FP32 kernel variants of passes A, B, C to use instead of the tuned ones")
+    ap.add_argument("--solves-only", action="store_true",
+                    help="hg512 / diff256 for a kernel trace of the solves alone: train the preconditioner, "
+                         "run 2 untimed solves, pause 0.3 s (a gap that marks the timed region in the trace), "
+                         "then --steps timed preconditioned solves; prints their time and exits")
     args = ap.parse_args()
     if args.pmc_summary:
         t = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], json.loads(args.variants) if args.variants else None)
@@ -834,6 +862,9 @@ def main():
     rank = int(os.environ.get("RANK", "0"))
     oracle_on = rank == 0 and not args.no_cpu_baseline
     cpu = None
+    if args.solves_only:
+        print(json.dumps(solves_only(args, torch, rte)), flush=True)
+        return
     if args.workload in ("hg512", "diff256"):
         mu_s = args.mu_s if args.mu_s is not None else (10.0 if args.workload == "hg512" else 50.0)
         out, ctx, base, sols = bench_pc_workload(args, torch, rte, args.workload, mu_s)

@@ -226,8 +226,9 @@ int rte_solve_batched(int count, rte_ctx* const* ctxs, const double* const* f_de
  * the coarse cell centres, s: RMS of v, N: `layers` 3x3 convolutions C -> hidden -> ... -> C with ReLU
  * between, C = 2L+1).  weights_dev: packed float32 parameters (layout in rte_nn.h); the context
  * keeps a BF16 copy.  factor must divide n_x and n_y.  NULL detaches.  2D contexts with L <= 8
- * only (3D, or L > 8: RTE_EUNSUPPORTED).  A preconditioned cycle that fails to cut the true residual 10x, or produces a non-finite value,
- * is followed by plain GMRES (info.pc_fallback = 1). */
+ * only (3D, or L > 8: RTE_EUNSUPPORTED).  A preconditioned cycle that does not end the solve and
+ * fails to cut the true residual 10x (or to reach twice its own target, when that asks for less),
+ * or that produces a non-finite value, is followed by plain GMRES (info.pc_fallback = 1). */
 int rte_pc_attach(rte_ctx* ctx, const float* weights_dev, int hidden, int layers, int factor);
 
 /* Time `reps` back-to-back applies (op, RTE_LAYOUT_CHANNELS, prec) on the context stream with

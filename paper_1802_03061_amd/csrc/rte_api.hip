@@ -685,8 +685,10 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
             return set_error(RTE_ENUMERIC, "non-finite true residual");
         }
         rn = std::sqrt(rn2);
-        // the preconditioned cycle must cut the residual at least 10x, else continue without it
-        if (pc_live && rn > 0.1 * cycle_start_rn) {
+        // the preconditioned cycle must cut the residual at least 10x (or reach twice its own
+        // target, when that asks for less), else the solve continues without it; a cycle that
+        // ends the solve is not judged
+        if (pc_live && rn > tol * bn && rn > std::max(0.1 * cycle_start_rn, 2.0 * target)) {
             pc_live = false;
             inf.pc_fallback = 1;
         }
