@@ -458,6 +458,153 @@ __global__ __launch_bounds__(256) void k_pass_b_couple(cx<T>* __restrict__ T2, c
     for (int c = 0; c < C; ++c) p[c * cstride + f] = v[c];
 }
 
+// Split form, steps 2 and 3 fused, by groups of output channels.  The coupling of one column at
+// one frequency needs every input channel, so the column's spectra (2L+1 channels of PY entries)
+// stay in the full-length buffer; a block takes a column and a group of output channels (modes 0
+// and 1, then the pairs of modes 2g and 2g + 1: at most 4 channels), couples those channels at
+// every frequency into LDS and runs their inverse y-FFTs, writing the kept rows.  Against the
+// separate coupling and inverse kernels this skips one write and one read of the full-length
+// buffer; the groups of a column run on one XCD, so the re-reads of its spectra and of its kernel
+// column hit L2.
+template <int L>
+constexpr int couple_groups() { return (L + 2) / 2; }
+template <int L, int G>
+struct CGroup {
+    static constexpr int klo = G == 0 ? 0 : 2 * G;                         // modes klo .. khi
+    static constexpr int khi = (G == 0 ? 1 : 2 * G + 1) > L ? L : (G == 0 ? 1 : 2 * G + 1);
+    static constexpr int ch0 = klo == 0 ? 0 : 2 * klo - 1;                // channels ch0 .. 2 khi
+    static constexpr int nch = 2 * khi + 1 - ch0;
+};
+
+// The output channels of group G of the mode coupling at one frequency (conventions of
+// couple_modes: V_k = sum_m Khat_m W_{k+m}, Khat_{-m} = (-1)^m conj Khat_m) from the 2L+1 input
+// channels v; out[i] is channel ch0 + i.
+template <typename T, int L, int G>
+__device__ __forceinline__ void couple_group(const cx<T>* v, cx<T>* out, const cx<T>* __restrict__ Q,
+                                             size_t qstride_m, size_t qoff, bool flip) {
+    using CG = CGroup<L, G>;
+    constexpr int C = 2 * L + 1;
+    constexpr int KH = CG::khi;
+    const T r2 = (T)0.70710678118654752440084436210485;
+    cx<T> W[C];   // complex modes k' = -L..L at index k' + L
+    W[L] = v[0];
+#pragma unroll
+    for (int k = 1; k <= L; ++k) {
+        const cx<T> a = v[2 * k - 1], bb = v[2 * k];
+        W[L + k] = scale(a + mul_i(bb), r2);
+        W[L - k] = scale(a - mul_i(bb), r2);
+    }
+    cx<T> V[2 * KH + 1];   // modes k = -khi..khi at index k + khi (|k| >= klo used)
+#pragma unroll
+    for (int k = 0; k < 2 * KH + 1; ++k) V[k] = mk((T)0, (T)0);
+#pragma unroll
+    for (int m = 0; m <= KH + L; ++m) {
+        cx<T> K = Q[m * qstride_m + qoff];
+        if (flip) { K.im = -K.im; if (m & 1) { K.re = -K.re; K.im = -K.im; } }
+        cx<T> Kn = conj(K);
+        if (m & 1) { Kn.re = -Kn.re; Kn.im = -Kn.im; }
+#pragma unroll
+        for (int k = -KH; k <= KH; ++k) {
+            if (k > -CG::klo && k < CG::klo) continue;
+            if (k + m >= -L && k + m <= L) cmac(V[k + KH], K, W[k + m + L]);
+            if (m > 0 && k - m >= -L && k - m <= L) cmac(V[k + KH], Kn, W[k - m + L]);
+        }
+    }
+#pragma unroll
+    for (int k = CG::klo; k <= KH; ++k) {
+        if (k == 0) {
+            out[0] = V[KH];
+        } else {
+            out[2 * k - 1 - CG::ch0] = scale(V[KH + k] + V[KH - k], r2);
+            out[2 * k - CG::ch0] = scale(mul_mi(V[KH + k] - V[KH - k]), r2);
+        }
+    }
+}
+
+// The coupled output channels of group G at frequency f of column kx into spec (channel i of the
+// group at spec[i * LD + sw(f)]).  Column 0 of a packed buffer holds z = d + i q: its D and Q
+// spectra at f are formed from Z(f) and Z(PY - f) and coupled with the first and the last kernel
+// column, one after the other (Z'(f) = D'(f) + i Q'(f)).
+template <typename T, int PY, int L, int G, int LD>
+__device__ __forceinline__ void couple_group_at(const cx<T>* __restrict__ col, size_t cstride, cx<T>* spec,
+                                                const cx<T>* __restrict__ Q, size_t qs, int kx, int nkq, int f,
+                                                bool packed, bool single) {
+    constexpr int C = 2 * L + 1;
+    constexpr int NCH = CGroup<L, G>::nch;
+    constexpr int KH = PY / 2 + 1;
+    const bool flip = f > PY / 2;
+    const int fy = flip ? PY - f : f;
+    const cx<T> zero = mk((T)0, (T)0);
+    cx<T> v[C], o[NCH];
+    if (!packed) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = (single && c > 0) ? zero : col[c * cstride + f];
+        couple_group<T, L, G>(v, o, Q, qs, (size_t)kx * KH + fy, flip);
+    } else {
+        // D (s = 0) then Q (s = 1), through one coupling body so that only one is live
+        const int fm = (PY - f) & (PY - 1);
+#pragma unroll
+        for (int i = 0; i < NCH; ++i) o[i] = zero;
+#pragma unroll 1
+        for (int s = 0; s < 2; ++s) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const bool in = !single || c == 0;
+                const cx<T> z = in ? col[c * cstride + f] : zero, w = in ? conj(col[c * cstride + fm]) : zero;
+                v[c] = scale(s ? mul_mi(z - w) : z + w, (T)0.5);
+            }
+            cx<T> os[NCH];
+            couple_group<T, L, G>(v, os, Q, qs, (s ? (size_t)(nkq - 1) * KH : (size_t)0) + fy, flip);
+#pragma unroll
+            for (int i = 0; i < NCH; ++i) o[i] = o[i] + (s ? mul_i(os[i]) : os[i]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NCH; ++i) spec[i * LD + sw(f)] = o[i];
+}
+
+template <typename T, int PY, int L, int NTHR>
+__global__ __launch_bounds__(NTHR, 2) void k_pass_b_couple_inv(cx<T>* __restrict__ Tb, const cx<T>* __restrict__ T2,
+                                                                const cx<T>* __restrict__ Q,
+                                                                const cx<T>* __restrict__ tw, int ny, int nkx,
+                                                                int nkq, int pack, int single) {
+    constexpr int C = 2 * L + 1;
+    constexpr int NG = couple_groups<L>();
+    constexpr int GM = 4;                 // channels of the largest group
+    constexpr int LD = padded(PY);
+    __shared__ cx<T> spec[GM * LD];
+    // block b runs on XCD b % 8: the NG groups of column kx take the blocks
+    // 8 (NG (kx / 8) + g) + kx % 8, all on the XCD of kx % 8
+    const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+    const int kx = (slot / NG) * 8 + xcd, g = slot % NG;
+    if (kx >= nkx) return;   // the whole block
+    const int b = blockIdx.y, tid = threadIdx.x;
+    const size_t cstride = (size_t)nkx * PY;
+    const cx<T>* col = T2 + (size_t)b * C * cstride + (size_t)kx * PY;
+    const size_t qs = (size_t)nkq * (PY / 2 + 1);
+    const bool packed = pack && kx == 0;
+    for (int i = tid; i < GM * LD; i += NTHR) spec[i] = mk((T)0, (T)0);   // the unused channels
+    __syncthreads();
+#pragma unroll 1
+    for (int f = tid; f < PY; f += NTHR) {
+        switch (g) {
+            case 0: couple_group_at<T, PY, L, 0, LD>(col, cstride, spec, Q, qs, kx, nkq, f, packed, single); break;
+            case 1: if constexpr (NG > 1) couple_group_at<T, PY, L, 1, LD>(col, cstride, spec, Q, qs, kx, nkq, f, packed, single); break;
+            case 2: if constexpr (NG > 2) couple_group_at<T, PY, L, 2, LD>(col, cstride, spec, Q, qs, kx, nkq, f, packed, single); break;
+            case 3: if constexpr (NG > 3) couple_group_at<T, PY, L, 3, LD>(col, cstride, spec, Q, qs, kx, nkq, f, packed, single); break;
+            default: if constexpr (NG > 4) couple_group_at<T, PY, L, 4, LD>(col, cstride, spec, Q, qs, kx, nkq, f, packed, single); break;
+        }
+    }
+    __syncthreads();
+    const int ch0 = g == 0 ? 0 : 4 * g - 1;
+    const int nch = (g == 0 ? 3 : 4) < C - ch0 ? (g == 0 ? 3 : 4) : C - ch0;
+    cx<T>* dst = Tb + (size_t)b * C * nkx * ny + (size_t)kx * ny;
+    const size_t ostride = (size_t)nkx * ny;
+    fft_inverse_cropped<T, PY, GM, LD, NTHR>(spec, tw, tid, [&](int fl, int y, cx<T> v) {
+        if (fl < nch && y < ny) dst[(size_t)(ch0 + fl) * ostride + y] = v;
+    });
+}
+
 // Pass B split in halves (for columns whose spectra do not fit LDS at once: FP64 with many modes).
 // The first decimation-in-frequency stage splits the length-PY y-transform of a column into its
 // even and odd frequencies, the length-PH = PY/2 transforms of x[n] and x[n] W^n (W =
@@ -685,6 +832,15 @@ static int launch_py(const Apply2DArgs<T>& a, int nbatch) {
         }
         const size_t nseq = (size_t)nbatch * C * nkx;
         split_fft<T, PY, false>(a.work, a.work2, a.twy, a.ny, a.single_in ? (size_t)nkx : nseq, a.stream);  // single_in: channel 0 only
+        if constexpr (L >= 1) {
+            if (a.var[1] == (half_fits<T, PY, L>() ? 2 : 1)) {   // coupling fused with the inverse
+                constexpr int NG = couple_groups<L>();
+                dim3 g3((unsigned)(((nkx + 7) / 8) * 8 * NG), nbatch);
+                hipLaunchKernelGGL((k_pass_b_couple_inv<T, PY, L, 256>), g3, dim3(256), 0, a.stream, a.work,
+                                   a.work2, a.Q, a.twy, a.ny, nkx, nkq, a.pack, a.single_in);
+                return 0;
+            }
+        }
         dim3 g2((unsigned)(((size_t)nkx * PY + 255) / 256), nbatch);
         hipLaunchKernelGGL((k_pass_b_couple<T, PY, L>), g2, dim3(256), 0, a.stream, a.work2, a.Q, nkx, nkq,
                            a.pack, a.single_in);
@@ -696,7 +852,8 @@ static int launch_py(const Apply2DArgs<T>& a, int nbatch) {
 template <typename T, int PY>
 static int variants_py() {
     if constexpr (fused_fits<T, PY, RTE_PASSB_L>()) return fused_variants<T, PY, RTE_PASSB_L>();
-    return half_fits<T, PY, RTE_PASSB_L>() ? 2 : 1;   // split form; split in halves
+    // split form; split in halves; the coupling fused with the inverse y-FFTs
+    return (half_fits<T, PY, RTE_PASSB_L>() ? 2 : 1) + (RTE_PASSB_L >= 1 ? 1 : 0);
 }
 
 template <typename T>

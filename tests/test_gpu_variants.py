@@ -22,7 +22,8 @@ def rte():
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("n,L,prec", [(200, 2, 0), (256, 8, 0), (150, 1, 1), (512, 8, 0), (96, 4, 0)])
+@pytest.mark.parametrize("n,L,prec", [(200, 2, 0), (256, 8, 0), (150, 1, 1), (512, 8, 0), (96, 4, 0), (128, 6, 1),
+                                      (72, 7, 0), (40, 5, 1)])
 def test_variants_match_oracle(rte, n, L, prec):
     say("variants", n, L, prec)
     mu_a, mu_s = 0.1, 2.0
