@@ -269,8 +269,9 @@ int rte_set_batched_variant(int pass, int variant);
 /* Kernel variants of the apply (prec = RTE_PREC_FP32 or RTE_PREC_FP64 apply).  2D: pass 0 = A,
  * 1 = B, 2 = C; 3D: pass 0 = A (x-FFT), 1 = B (y-FFT), 2 = C (z-FFT with the spectrum or the mode
  * coupling), 3 = D (inverse y-FFT), 4 = E (inverse x-FFT).  Variants differ only in tiling (row
- * tiles, z-rows or columns per block, thread counts, FFT grouping, radix schedule, the coupling
- * method for many modes): the same arithmetic, equal results up to rounding.  rte_setup of a 2D
+ * tiles, z-rows or columns per block, thread counts, FFT grouping, radix schedule, how the FP64
+ * pass B with many modes stages its full-length spectra, the coupling method for many modes): the
+ * same arithmetic, equal results up to rounding.  rte_setup of a 2D
  * context with n_x or n_y >= 128, or of a 3D context with a side >= 64, picks the fastest variant of
  * every pass by timing them on the context's buffers, once per (precision, L, grid) per process
  * (environment RTE_AUTOTUNE=0: keep variant 0).  rte_autotune re-times them (`reps` launches each;
