@@ -833,7 +833,10 @@ static int launch_py(const Apply2DArgs<T>& a, int nbatch) {
         const size_t nseq = (size_t)nbatch * C * nkx;
         split_fft<T, PY, false>(a.work, a.work2, a.twy, a.ny, a.single_in ? (size_t)nkx : nseq, a.stream);  // single_in: channel 0 only
         if constexpr (L >= 1) {
-            if (a.var[1] == (half_fits<T, PY, L>() ? 2 : 1)) {   // coupling fused with the inverse
+            // the coupling fused with the inverse: the tuned choice, and always for a single input
+            // channel (the right-hand side K~ f), where it reads one channel of the full-length
+            // buffer instead of writing and reading all of them
+            if (a.var[1] == (half_fits<T, PY, L>() ? 2 : 1) || a.single_in) {
                 constexpr int NG = couple_groups<L>();
                 dim3 g3((unsigned)(((nkx + 7) / 8) * 8 * NG), nbatch);
                 hipLaunchKernelGGL((k_pass_b_couple_inv<T, PY, L, 256>), g3, dim3(256), 0, a.stream, a.work,

@@ -114,7 +114,7 @@ def test_apply_full_size_sampled(rte, prec):
     ctx.close()
 
 
-@pytest.mark.parametrize("L,n", [(0, 32), (3, 24), (8, 32), (6, 40)])
+@pytest.mark.parametrize("L,n", [(0, 32), (3, 24), (8, 32), (6, 40), (8, 200), (5, 77)])
 def test_rhs_vs_oracle(rte, L, n):
     say("rhs", L, n)
     w = inputs.workload("hg512", seed=3, n=n)
