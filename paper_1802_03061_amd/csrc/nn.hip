@@ -1181,6 +1181,16 @@ size_t pc_coarse_len(const rte_ctx* c) {
     return (size_t)c->C * (c->ny / c->pc_factor) * (c->nx / c->pc_factor);
 }
 
+// p[0..3] = (a, b, c, d), in stream order (no host staging to keep alive, no wait on the host).
+__global__ void k_set_floats4(float* __restrict__ p, float a, float b, float c, float d) {
+    if (threadIdx.x == 0) {
+        p[0] = a;
+        p[1] = b;
+        p[2] = c;
+        p[3] = d;
+    }
+}
+
 int pc_begin_solve(rte_ctx* c, int m) {
     const size_t nco = pc_coarse_len(c);
     if (c->pc_slots < m + 1) {
@@ -1191,9 +1201,9 @@ int pc_begin_solve(rte_ctx* c, int m) {
         c->pc_slots = m + 1;
     }
     // s = RMS of a unit-norm vector = 1 / sqrt(nvec); the combine slot is pc_Y[m + 1]
-    const float st[4] = {(float)(1.0 / std::sqrt((double)c->nvec)), (float)std::sqrt((double)c->nvec), 0.f, 0.f};
-    hipError_t e = hipMemcpyAsync(c->pc_st, st, sizeof(st), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);   // st lives on the host stack
+    hipLaunchKernelGGL(k_set_floats4, dim3(1), dim3(64), 0, c->stream, c->pc_st,
+                       (float)(1.0 / std::sqrt((double)c->nvec)), (float)std::sqrt((double)c->nvec), 0.f, 0.f);
+    const hipError_t e = hipGetLastError();
     return e == hipSuccess ? RTE_OK : set_hip_error(e, "pc_begin_solve", __FILE__, __LINE__);
 }
 
