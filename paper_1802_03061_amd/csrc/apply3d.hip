@@ -70,13 +70,23 @@ __global__ __launch_bounds__(NTHR) void k_pass3_c(cx<T>* __restrict__ T2, const 
         qrow[tid] = (col < (int)ncol) ? (kx * HY + fy) * HZ : -1;
     }
     __syncthreads();
-    for (int idx = tid; idx < NC * PZ; idx += NTHR) {
+    // the spectrum values of the thread's entries are loaded first, all in flight together
+    constexpr int PERQ = (NC * PZ + NTHR - 1) / NTHR;
+    T qv[PERQ];
+#pragma unroll
+    for (int u = 0; u < PERQ; ++u) {
+        const int idx = tid + u * NTHR;
         const int c = idx / PZ, kz = idx % PZ;
-        const int q = qrow[c];
-        if (q >= 0) {
-            const int fz = kz <= PZ / 2 ? kz : PZ - kz;
-            buf[c * LD + sw(kz)] = scale(buf[c * LD + sw(kz)], Q3[(size_t)q + fz]);
-        }
+        const int q = ((NC * PZ) % NTHR == 0 || idx < NC * PZ) ? qrow[c] : -1;
+        const int fz = kz <= PZ / 2 ? kz : PZ - kz;
+        qv[u] = q >= 0 ? Q3[(size_t)q + fz] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < PERQ; ++u) {
+        const int idx = tid + u * NTHR;
+        const int c = idx / PZ, kz = idx % PZ;
+        if (((NC * PZ) % NTHR == 0 || idx < NC * PZ) && qrow[c] >= 0)
+            buf[c * LD + sw(kz)] = scale(buf[c * LD + sw(kz)], qv[u]);
     }
     __syncthreads();
     fft_inverse_cropped<T, PZ, NC, LD, NTHR>(buf, tws, tid, [&](int c, int z, cx<T> v) {
@@ -187,10 +197,21 @@ __global__ __launch_bounds__(NTHR) void k_pass3_d(cx<T>* __restrict__ T1, const 
     T1 += ch * t1sz;
     T2 += ch * t2sz;
     stage_twiddles<T, PY, NTHR>(tws, tw, tid);
-    for (int idx = tid; idx < TZ * PY; idx += NTHR) {
+    // every load of the tile is issued before the first LDS store, so their latencies overlap
+    constexpr int PER = (TZ * PY + NTHR - 1) / NTHR;
+    cx<T> v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = tid + u * NTHR;
         const int zl = idx % TZ, ky = idx / TZ;
         const int z = z0 + zl;
-        buf[zl * LD + sw(ky)] = z < nz ? T2[((size_t)kx * PY + ky) * nz + z] : mk((T)0, (T)0);
+        v[u] = ((TZ * PY) % NTHR == 0 || idx < TZ * PY) && z < nz ? T2[((size_t)kx * PY + ky) * nz + z]
+                                                                   : mk((T)0, (T)0);
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = tid + u * NTHR;
+        if ((TZ * PY) % NTHR == 0 || idx < TZ * PY) buf[(idx % TZ) * LD + sw(idx / TZ)] = v[u];
     }
     __syncthreads();
     // only rows y < ny are kept: the last inverse stage writes them directly
