@@ -333,10 +333,22 @@ __device__ __forceinline__ void fft_inverse_cropped(cx<T>* buf, const cx<T>* tws
     }
 }
 
-// Copy the P-entry twiddle table into LDS (all threads; followed by the caller's barrier).
+// Copy the P-entry twiddle table into LDS (all threads; followed by the caller's barrier).  Every
+// load is issued before the first LDS store, so the copy costs one load latency, not P / NTHR.
 template <typename T, int P, int NTHR>
 __device__ __forceinline__ void stage_twiddles(cx<T>* tws, const cx<T>* __restrict__ tw, int tid) {
-    for (int q = tid; q < P; q += NTHR) tws[q] = tw[q];
+    constexpr int K = (P + NTHR - 1) / NTHR;
+    cx<T> v[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int q = tid + u * NTHR;
+        v[u] = (P % NTHR == 0 || q < P) ? tw[q] : mk((T)0, (T)0);
+    }
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int q = tid + u * NTHR;
+        if (P % NTHR == 0 || q < P) tws[q] = v[u];
+    }
 }
 
 }  // namespace rte

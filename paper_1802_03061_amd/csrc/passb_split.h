@@ -47,8 +47,19 @@ __global__ __launch_bounds__(NTHR) void k_pass_b_inv(cx<T>* __restrict__ Tb, con
     const int live = (int)min((size_t)NSEQ, (size_t)nseq - s0);
     stage_twiddles<T, PY, NTHR>(tws, tw, tid);
     const cx<T>* src = T2 + s0 * PY;
-    for (int idx = tid; idx < NSEQ * PY; idx += NTHR)
-        buf[(idx / PY) * LD + sw(idx % PY)] = idx < live * PY ? src[idx] : mk((T)0, (T)0);
+    // every load of the block's sequences is issued before the first LDS store
+    constexpr int PER = (NSEQ * PY + NTHR - 1) / NTHR;
+    cx<T> v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = tid + u * NTHR;
+        v[u] = ((NSEQ * PY) % NTHR == 0 || idx < NSEQ * PY) && idx < live * PY ? src[idx] : mk((T)0, (T)0);
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int idx = tid + u * NTHR;
+        if ((NSEQ * PY) % NTHR == 0 || idx < NSEQ * PY) buf[(idx / PY) * LD + sw(idx % PY)] = v[u];
+    }
     __syncthreads();
     cx<T>* dst = Tb + s0 * ny;
     fft_inverse_cropped<T, PY, NSEQ, LD, NTHR>(buf, tws, tid, [&](int f, int y, cx<T> v) {
