@@ -45,13 +45,24 @@ __device__ __forceinline__ void load_modes(cx<T>* a, const cx<T>* __restrict__ T
         a[f * LD + sw(p)] = mk((T)0, (T)0);
     }
     __syncthreads();
-    for (int idx = tid; idx < F * C; idx += NTHR) {
-        const int f = idx % F, c = idx / F;
-        const int ky = ky0 + f;
-        if (ky >= PY || (single && c > 0)) continue;
-        const cx<T> v = T2c[(size_t)c * cstride + ky];
-        const int p = c == 0 ? L : ((c & 1) ? L + (c + 1) / 2 : L - c / 2);
-        a[f * LD + sw(p)] = v;
+    constexpr int U = 4;   // U entries per thread at a time, loads first
+    for (int base = tid; base < F * C; base += U * NTHR) {
+        cx<T> v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * NTHR;
+            const int f = idx % F, c = idx / F;
+            const bool ok = idx < F * C && ky0 + f < PY && !(single && c > 0);
+            v[u] = ok ? T2c[(size_t)c * cstride + ky0 + f] : mk((T)0, (T)0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * NTHR;
+            const int f = idx % F, c = idx / F;
+            if (idx >= F * C || ky0 + f >= PY || (single && c > 0)) continue;
+            const int p = c == 0 ? L : ((c & 1) ? L + (c + 1) / 2 : L - c / 2);
+            a[f * LD + sw(p)] = v[u];
+        }
     }
     __syncthreads();
     const T r2 = (T)0.70710678118654752440084436210485;
@@ -108,17 +119,29 @@ __global__ __launch_bounds__(NTHR) void k_couple_modefft(cx<T>* __restrict__ T2,
         g[f * LD + sw(p)] = mk((T)0, (T)0);
     }
     load_modes<T, F, LD, NTHR>(a, T2c, cstride, ky0, PY, C, L, PM, single, tid);   // ends with a barrier
-    for (int idx = tid; idx < F * (2 * L + 1); idx += NTHR) {
-        const int f = idx % F, m = idx / F;
-        const int ky = ky0 + f;
-        if (ky >= PY) continue;
-        const bool flip = ky > PY / 2;
-        const cx<T> K = khat(Q, qs, KH, kx, flip ? PY - ky : ky, flip, m);
-        g[f * LD + sw((PM - m) & (PM - 1))] = K;
-        if (m > 0) {
-            cx<T> Kn = conj(K);
-            if (m & 1) { Kn.re = -Kn.re; Kn.im = -Kn.im; }
-            g[f * LD + sw(m)] = Kn;
+    constexpr int UK = 4;   // UK spectrum entries per thread at a time, loads first
+    for (int base = tid; base < F * (2 * L + 1); base += UK * NTHR) {
+        cx<T> Kv[UK];
+#pragma unroll
+        for (int u = 0; u < UK; ++u) {
+            const int idx = base + u * NTHR;
+            const int f = idx % F, m = idx / F;
+            const int ky = ky0 + f;
+            const bool flip = ky > PY / 2;
+            Kv[u] = (idx < F * (2 * L + 1) && ky < PY) ? khat(Q, qs, KH, kx, flip ? PY - ky : ky, flip, m)
+                                                         : mk((T)0, (T)0);
+        }
+#pragma unroll
+        for (int u = 0; u < UK; ++u) {
+            const int idx = base + u * NTHR;
+            const int f = idx % F, m = idx / F;
+            if (idx >= F * (2 * L + 1) || ky0 + f >= PY) continue;
+            g[f * LD + sw((PM - m) & (PM - 1))] = Kv[u];
+            if (m > 0) {
+                cx<T> Kn = conj(Kv[u]);
+                if (m & 1) { Kn.re = -Kn.re; Kn.im = -Kn.im; }
+                g[f * LD + sw(m)] = Kn;
+            }
         }
     }
     __syncthreads();
@@ -160,23 +183,37 @@ __global__ __launch_bounds__(NTHR) void k_couple_direct(cx<T>* __restrict__ T2, 
     cx<T>* T2c = T2 + (size_t)b * C * cstride + (size_t)kx * PY;
     for (int idx = tid; idx < F * S; idx += nthr) sm[idx] = mk((T)0, (T)0);
     __syncthreads();
-    for (int idx = tid; idx < F * C; idx += nthr) {
-        const int f = idx % F, m = idx / F;       // m = 0..2L; idx also walks the channels c = m
-        const int ky = ky0 + f;
-        if (ky >= PY) continue;
-        cx<T>* rec = sm + f * S;
-        const bool flip = ky > PY / 2;
-        const cx<T> K = khat(Q, qs, KH, kx, flip ? PY - ky : ky, flip, m);
-        rec[KOFF + m] = K;
-        if (m > 0) {                              // Khat_{-m} = (-1)^m conj Khat_m
-            cx<T> Kn = conj(K);
-            if (m & 1) { Kn.re = -Kn.re; Kn.im = -Kn.im; }
-            rec[KOFF - m] = Kn;
+    // U entries per thread at a time, their loads all issued before the LDS stores
+    constexpr int U = 4;
+    for (int base = tid; base < F * C; base += U * nthr) {
+        cx<T> Kv[U], Wv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * nthr;
+            const int f = idx % F, m = idx / F;   // m = 0..2L; idx also walks the channels c = m
+            const int ky = ky0 + f;
+            const bool ok = idx < F * C && ky < PY;
+            const bool flip = ky > PY / 2;
+            Kv[u] = ok ? khat(Q, qs, KH, kx, flip ? PY - ky : ky, flip, m) : mk((T)0, (T)0);
+            Wv[u] = ok && !(single && m > 0) ? T2c[(size_t)m * cstride + ky] : mk((T)0, (T)0);
         }
-        const int c = m;
-        if (single && c > 0) continue;
-        const int p = c == 0 ? L : ((c & 1) ? L + (c + 1) / 2 : L - c / 2);   // parked as in the mode FFT
-        rec[AOFF + p] = T2c[(size_t)c * cstride + ky];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * nthr;
+            const int f = idx % F, m = idx / F;
+            if (idx >= F * C || ky0 + f >= PY) continue;
+            cx<T>* rec = sm + f * S;
+            rec[KOFF + m] = Kv[u];
+            if (m > 0) {                          // Khat_{-m} = (-1)^m conj Khat_m
+                cx<T> Kn = conj(Kv[u]);
+                if (m & 1) { Kn.re = -Kn.re; Kn.im = -Kn.im; }
+                rec[KOFF - m] = Kn;
+            }
+            const int c = m;
+            if (single && c > 0) continue;
+            const int p = c == 0 ? L : ((c & 1) ? L + (c + 1) / 2 : L - c / 2);   // parked as in the mode FFT
+            rec[AOFF + p] = Wv[u];
+        }
     }
     __syncthreads();
     const T r2 = (T)0.70710678118654752440084436210485;
