@@ -100,6 +100,7 @@ __global__ __launch_bounds__(BT) void kb_dots(const Chunk* __restrict__ ch, cons
         const int e = tid + u * BT;
         wv[u] = e < c.len ? w[e] : 0.0;
     }
+#pragma unroll 2   // the next vector's loads go out while this one is summed
     for (int i = 0; i <= j; ++i) {
         const double* v = k.V + (size_t)i * k.nvec + c.off;
         double s = 0.0;
@@ -151,6 +152,7 @@ __global__ __launch_bounds__(BT) void kb_update(const Chunk* __restrict__ ch, co
         const int e = tid + u * BT;
         wv[u] = e < c.len ? w[e] : 0.0;
     }
+#pragma unroll 2   // the next vector's loads go out while this one is subtracted
     for (int i = 0; i <= j; ++i) {
         const double hi = h[i];
         const double* v = k.V + (size_t)i * k.nvec + c.off;
