@@ -141,6 +141,14 @@ __device__ __forceinline__ void couple_packed_pair(PF p, PM pm, const cx<T>* __r
     }
 }
 
+// Default group size of the fused pass's y-transforms: at most ~3 radix-8 butterflies per thread
+// and stage.  Fewer groups mean fewer barriers but more live registers per thread.
+template <int PY, int NF, int NTHR>
+constexpr int default_group() {
+    constexpr int g = (3 * NTHR * 8) / PY;
+    return g >= NF ? NF : (g < 1 ? 1 : g);
+}
+
 // Fused pass B: NCOL columns x C channels per block, spectra resident in LDS.
 // base: the batch entry's [C][nkx][ny] work buffer; nkx = its columns, nkq = columns of the kernel
 // table (PX/2 + 1); kx0 = the block's first column.
@@ -191,10 +199,9 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
         }
     }
     __syncthreads();
-    // at most ~3 radix-8 butterflies per thread and stage, or groups of GV transforms if given
-    // (the radix-32 schedule transforms every sequence at once)
-    constexpr int G0 = SCH == 1 ? NF
-                                : ((3 * NTHR * 8) / PY >= NF ? NF : ((3 * NTHR * 8) / PY < 1 ? 1 : (3 * NTHR * 8) / PY));
+    // the default groups, or groups of GV transforms if given (the radix-32 schedule transforms
+    // every sequence at once)
+    constexpr int G0 = SCH == 1 ? NF : default_group<PY, NF, NTHR>();
     constexpr int G = GV > 0 ? (GV < NF ? GV : NF) : G0;
     block_fft_grouped_range<T, PY, NF, G, LD, NTHR, false, R0, PY, SCH>(spec, tws, tid);
     const size_t qs = (size_t)nkq * KH;
@@ -771,11 +778,21 @@ constexpr int fused_variants_base() {
     if (PY < 128) return 1;
     return reg_variant<T, PY, L>() ? 4 : ((sizeof(T) == 4 && NF / 8 >= 1024) ? 3 : 2);
 }
-// The radix-32 schedule (fft.h, schedule 1) as the last variant, for padded y >= 256.
+// The radix-32 schedule (fft.h, schedule 1) as the next variant, for padded y >= 256.
 template <typename T, int PY, int L>
 constexpr bool sched_variant() { return PY >= 256; }
+// All of a block's transforms in one group, as the last variant, where the default grouping
+// splits them (FP32 at padded y = 1024 and L >= 6: 12 + 5 transforms at L = 8).
 template <typename T, int PY, int L>
-constexpr int fused_variants() { return fused_variants_base<T, PY, L>() + (sched_variant<T, PY, L>() ? 1 : 0); }
+constexpr bool onegroup_variant() {
+    constexpr int NF = ncol_for<T, PY, L>() * (2 * L + 1);
+    return default_group<PY, NF, nthr_for<T, NF * PY>()>() < NF;
+}
+template <typename T, int PY, int L>
+constexpr int fused_variants() {
+    return fused_variants_base<T, PY, L>() + (sched_variant<T, PY, L>() ? 1 : 0) +
+           (onegroup_variant<T, PY, L>() ? 1 : 0);
+}
 
 template <typename T, int PY, int L, int NCOL, int NT, int GV, int SCH = 0>
 static void launch_fused(const Apply2DArgs<T>& a, int nbatch, int nkx, int nkq) {
@@ -815,6 +832,12 @@ static int launch_py(const Apply2DArgs<T>& a, int nbatch) {
         }
         if constexpr (NV >= 2) {
             if (a.var[1] == 2) { launch_fused<T, PY, L, NCOL, 256, 0>(a, nbatch, nkx, nkq); return 0; }
+        }
+        if constexpr (onegroup_variant<T, PY, L>()) {
+            if (a.var[1] == NV + (sched_variant<T, PY, L>() ? 1 : 0)) {
+                launch_fused<T, PY, L, NCOL, NT, NCOL * C>(a, nbatch, nkx, nkq);
+                return 0;
+            }
         }
         launch_fused<T, PY, L, NCOL, NT, 0>(a, nbatch, nkx, nkq);
         return 0;
