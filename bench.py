@@ -57,7 +57,8 @@ METRIC = "solve time to rel-res 1e-8 (512^2, L=8 HG), learned-PC vs plain; appli
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "hbm_traffic_hg512_L8.json")
 # sources of the 2D apply kernels: counter readings are only reported while these are unchanged
 APPLY_SOURCES = ["paper_1802_03061_amd/csrc/" + f for f in
-                 ("apply2d.hip", "apply2d_b.hip", "apply2d.h", "apply2d_b.h", "passb_split.h", "fft.h", "common.h")]
+                 ("apply2d.hip", "apply2d_b.hip", "apply2d.h", "apply2d_b.h", "apply2d_tile.h", "passb_split.h", "fft.h",
+                  "common.h")]
 
 
 def sources_digest() -> str:

@@ -228,7 +228,10 @@ int rte_solve_batched(int count, rte_ctx* const* ctxs, const double* const* f_de
  * keeps a BF16 copy.  factor must divide n_x and n_y.  NULL detaches.  2D contexts with L <= 8
  * only (3D, or L > 8: RTE_EUNSUPPORTED).  A preconditioned cycle that does not end the solve and
  * fails to cut the true residual 10x (or to reach twice its own target, when that asks for less),
- * or that produces a non-finite value, is followed by plain GMRES (info.pc_fallback = 1). */
+ * or that produces a non-finite value, is followed by plain GMRES (info.pc_fallback = 1).  With
+ * the FP32 apply (padded x 128..1024) each Arnoldi step runs the next apply's x-transforms beside
+ * the network and adds the correction's x-spectrum in the y-pass instead (the same z up to FP32
+ * rounding); environment RTE_PC_EARLY_A=0 keeps the correction in the x-pass. */
 int rte_pc_attach(rte_ctx* ctx, const float* weights_dev, int hidden, int layers, int factor);
 
 /* Time `reps` back-to-back applies (op, RTE_LAYOUT_CHANNELS, prec) on the context stream with

@@ -11,6 +11,20 @@ struct ChanScale {
     double s[2 * RTE_MAX_L + 1];   // per-channel factor applied in pass A (D for operator A, 1 for K~)
 };
 
+// The coarse correction added in pass B instead of pass A (FP32 fused pass B, L <= 8).  Pass A
+// has transformed the vector alone; pass B adds, to every column before its y-FFT, the
+// x-spectrum of the correction cs P y scaled as pass A scales its input.  P is separable (an
+// x- then a y-interpolation), so the x-spectrum of row yy of P y_c is (1 - a) G_c[r0] + a G_c[r1],
+// with (r0, r1, a) the y-interpolation of row yy and G_c[R](kx) = sum_X y_c[R][X] phi[X][kx],
+// phi[X] being the x-spectrum of the fine row of interpolation weights of coarse column X (its
+// column 0 holds (phi(0), phi(PX/2)) when the work buffer is packed).
+struct CorrB {
+    const float* y = nullptr;       // coarse field [C][Hc][Wc]
+    const void* phi = nullptr;      // cx<float> [Wc][nkx], nkx = columns of the work buffer
+    const float* coef = nullptr;    // [C] in device memory: pass A's factor of channel c times cs
+    int Hc = 0, Wc = 0, F = 1;
+};
+
 template <typename T>
 struct Apply2DArgs {
     int nx, ny, PX, PY, L, C;
@@ -35,6 +49,9 @@ struct Apply2DArgs {
     const float* corr = nullptr;
     int cF = 1;
     double cs = 0.0;
+    // Set (bcorr.y non-null): pass B adds the correction's x-spectrum (see CorrB); pass A is not
+    // run by apply2d_from_b.
+    CorrB bcorr;
 };
 
 // Kernel variants (same arithmetic, different tiling; results agree up to rounding):
@@ -113,5 +130,13 @@ bool apply2d_unpacked(int L, int PY, int var_b);
 template <typename T, typename TV>
 int apply2d_pass_c(const Apply2DArgs<T>& a, const TV* x, const double* b, TV* y, int mode,
                    int nbatch);
+// Whether pass B of this (precision, L, PY, pass-B variant) can add the coarse correction
+// (CorrB): the FP32 fused form in LDS, not the register-resident variant.
+template <typename T>
+bool apply2d_b_corr_ok(int L, int PY, int var_b);
+// Passes B and C of y = A (x + cs P y) for one batch entry, pass A having already written the
+// x-spectrum of the scaled x alone into a.work; a.bcorr and a.corr describe the correction.
+template <typename T, typename TV>
+int apply2d_from_b(const Apply2DArgs<T>& a, const TV* x, TV* y);
 
 }  // namespace rte

@@ -16,6 +16,7 @@
 // with Khat read from the quarter table (see apply2d.hip for the symmetries).
 #include "apply2d.h"
 #include "apply2d_b.h"
+#include "apply2d_tile.h"
 #include "fft.h"
 #include "passb_split.h"
 
@@ -152,10 +153,10 @@ constexpr int default_group() {
 // Fused pass B: NCOL columns x C channels per block, spectra resident in LDS.
 // base: the batch entry's [C][nkx][ny] work buffer; nkx = its columns, nkq = columns of the kernel
 // table (PX/2 + 1); kx0 = the block's first column.
-template <typename T, int PY, int L, int NCOL, int NTHR, int GV = 0, int SCH = 0>
+template <typename T, int PY, int L, int NCOL, int NTHR, int GV = 0, int SCH = 0, bool CORR = false>
 __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T>* __restrict__ Q, int ny, int nkx,
                                             int nkq, int pack, int kx0, cx<T>* spec, const cx<T>* tws,
-                                            cx<T>* pairtmp, int tid, int single = 0) {
+                                            cx<T>* pairtmp, int tid, int single = 0, const CorrB* cb = nullptr) {
     // single: only channel 0 of the input is non-zero; the other channels are not read
     constexpr int C = 2 * L + 1;
     constexpr int NF = NCOL * C;
@@ -171,6 +172,67 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
     constexpr int NB0 = PY / R0;
     constexpr int NBT = NF * NB0;
     constexpr int IT = (NBT + NTHR - 1) / NTHR;
+    // The coarse correction's x-spectrum (CorrB): G[fc][R] = coef_c sum_X y_c[R][X] phi[X][kx] for
+    // the block's columns, held in spec (with a table of the rows' y-interpolation) until the first
+    // stage's writes, then interpolated in y onto every loaded row.  A thread's first G item has its (L2-resident) loads issued before the
+    // column loads, so that their latency hides behind those.
+    //   When a wave's transform index is the same for all its lanes (NB0 a multiple of 64) and the
+    // same rows recur at every step it, each wave computes the G values of its own transforms
+    // into private slots among the pad slots of spec (never written by the transforms, see sw)
+    // and reads them back after a wave-level fence: no block barrier, so the waves' column loads
+    // still overlap one another's first stage.  Otherwise G goes through spec with two barriers.
+    constexpr int GU = 16;
+    constexpr bool WAVEG = CORR && NB0 % 64 == 0 && NTHR % NB0 == 0 && NTHR <= NF * (PY / 16);
+    T gy[CORR ? GU : 1];
+    cx<T> gp[CORR ? GU : 1];
+    int Hc = 1, Wc = 1;
+    bool wg = false;
+    const cx<T>* phi = nullptr;
+    const int wave = tid >> 6, lane = tid & 63;
+    // pad slot e (< 64) of this wave
+    auto gslot = [&](int e) -> cx<T>* {
+        const int q = wave * 64 + e;
+        return spec + (q / (PY / 16)) * LD + 17 * (q % (PY / 16)) + 16;
+    };
+    if constexpr (CORR) {
+        Hc = cb->Hc;
+        Wc = cb->Wc;
+        phi = reinterpret_cast<const cx<T>*>(cb->phi);
+        wg = WAVEG && IT * Hc <= 64;
+        int fc, R;
+        bool ok;
+        if (wg) {   // lane = it Hc + R
+            const int itl = lane / Hc;
+            R = lane % Hc;
+            fc = (64 * wave + itl * NTHR) / NB0;
+            ok = itl < IT && fc < NF;
+        } else {
+            fc = tid / Hc;
+            R = tid % Hc;
+            ok = tid < NF * Hc;
+        }
+        const int kx = kx0 + fc / C;
+        ok = ok && kx < nkx;
+        const float* yr = cb->y + ((size_t)(fc % C) * Hc + R) * Wc;
+        // each lane reads its own coarse row: 16-byte loads when rows are whole float4s (the
+        // field is 16-byte aligned), so an instruction touches a quarter of the cache lines
+        if (Wc % 4 == 0) {
+            const float4* y4 = reinterpret_cast<const float4*>(yr);
+#pragma unroll
+            for (int q = 0; q < GU / 4; ++q) {
+                const float4 t = (ok && 4 * q < Wc) ? y4[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+                gy[4 * q] = (T)t.x;
+                gy[4 * q + 1] = (T)t.y;
+                gy[4 * q + 2] = (T)t.z;
+                gy[4 * q + 3] = (T)t.w;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < GU; ++u) gy[u] = (ok && u < Wc) ? (T)yr[u] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < GU; ++u) gp[u] = (ok && u < Wc) ? phi[(size_t)u * nkx + kx] : mk((T)0, (T)0);
+    }
     cx<T> ld[IT][R0 / 2];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -184,6 +246,115 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
             const int y = j + r * NB0;
             ld[it][r] = (ok && y < ny) ? base[c * cstride + (size_t)kx * ny + y] : mk((T)0, (T)0);
         }
+    }
+    if (CORR && wg) {
+        const int itl = lane / Hc, R = lane % Hc;
+        const int fc = (64 * wave + itl * NTHR) / NB0;
+        const int kx = kx0 + fc / C;
+        T gr = 0, gi = 0;
+        if (itl < IT && fc < NF && kx < nkx) {
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                gr += gy[u] * gp[u].re;
+                gi += gy[u] * gp[u].im;
+            }
+            const float* yr = cb->y + ((size_t)(fc % C) * Hc + R) * Wc;
+            for (int X = GU; X < Wc; ++X) {
+                const T yv = (T)yr[X];
+                const cx<T> ph = phi[(size_t)X * nkx + kx];
+                gr += yv * ph.re;
+                gi += yv * ph.im;
+            }
+            const T k = (T)cb->coef[fc % C];
+            gr *= k;
+            gi *= k;
+        }
+        *gslot(lane) = mk(gr, gi);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // this thread's rows (the same at every it): lower coarse row and weight of the upper one
+        const int j = tid % NB0;
+        const float invF = 1.f / (float)cb->F;
+        int rlo[R0 / 2];
+        T wt[R0 / 2];
+#pragma unroll
+        for (int r = 0; r < R0 / 2; ++r) {
+            const float yi = ((float)(j + r * NB0) + 0.5f) * invF - 0.5f;
+            const float f0 = floorf(yi);
+            const int i0 = (int)f0;
+            rlo[r] = min(max(i0, 0), Hc - 1);
+            wt[r] = (i0 < 0 || i0 >= Hc - 1) ? (T)0 : (T)(yi - f0);
+        }
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int idx = tid + it * NTHR;
+            const int kx = kx0 + (idx / NB0) / C;
+            const bool ok = (NBT % NTHR == 0 || idx < NBT) && kx < nkx;
+#pragma unroll
+            for (int r = 0; r < R0 / 2; ++r) {
+                if (ok && j + r * NB0 < ny) {
+                    const cx<T> g0 = *gslot(it * Hc + rlo[r]), g1 = *gslot(it * Hc + min(rlo[r] + 1, Hc - 1));
+                    ld[it][r].re += g0.re + wt[r] * (g1.re - g0.re);
+                    ld[it][r].im += g0.im + wt[r] * (g1.im - g0.im);
+                }
+            }
+        }
+    } else if constexpr (CORR) {
+        for (int idx = tid; idx < NF * Hc; idx += NTHR) {
+            const int fc = idx / Hc, R = idx % Hc;
+            const int c = fc % C;
+            const int kx = kx0 + fc / C;
+            T gr = 0, gi = 0;
+            if (kx < nkx) {
+                if (idx == tid) {
+#pragma unroll
+                    for (int u = 0; u < GU; ++u) {
+                        gr += gy[u] * gp[u].re;
+                        gi += gy[u] * gp[u].im;
+                    }
+                }
+                const float* yr = cb->y + ((size_t)c * Hc + R) * Wc;
+                for (int X = idx == tid ? GU : 0; X < Wc; ++X) {
+                    const T yv = (T)yr[X];
+                    const cx<T> ph = phi[(size_t)X * nkx + kx];
+                    gr += yv * ph.re;
+                    gi += yv * ph.im;
+                }
+            }
+            const T k = (T)cb->coef[c];
+            spec[idx] = mk(k * gr, k * gi);
+        }
+        // the y-interpolation of every row (lerp_at) after G: (weight of the upper row, lower row);
+        // rows clamped to one coarse row get weight 0
+        cx<T>* rt = spec + NF * Hc;
+        for (int y = tid; y < ny; y += NTHR) {
+            int r0, r1;
+            float ay;
+            lerp_at(y, cb->F, Hc, r0, r1, ay);
+            rt[y] = mk(r1 == r0 ? (T)0 : (T)ay, (T)r0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int idx = tid + it * NTHR;
+            const int j = idx % NB0, fc = idx / NB0;
+            const int kx = kx0 + fc / C;
+            const bool ok = (NBT % NTHR == 0 || idx < NBT) && kx < nkx;
+            const cx<T>* g = spec + fc * Hc;
+#pragma unroll
+            for (int r = 0; r < R0 / 2; ++r) {
+                const int y = j + r * NB0;
+                if (ok && y < ny) {
+                    const cx<T> t = rt[y];
+                    const int r0 = (int)t.im;
+                    const cx<T> g0 = g[r0], g1 = g[min(r0 + 1, Hc - 1)];
+                    ld[it][r].re += g0.re + t.re * (g1.re - g0.re);
+                    ld[it][r].im += g0.im + t.re * (g1.im - g0.im);
+                }
+            }
+        }
+        __syncthreads();   // G is read before the first stage overwrites spec
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -275,18 +446,18 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
     }
 }
 
-template <typename T, int PY, int L, int NCOL, int NTHR, int GV, int SCH = 0>
+template <typename T, int PY, int L, int NCOL, int NTHR, int GV, int SCH = 0, bool CORR = false>
 __global__ __launch_bounds__(NTHR) void k_pass_b_lds(cx<T>* __restrict__ Tb, const cx<T>* __restrict__ Q,
                                                      const cx<T>* __restrict__ tw, int ny, int nkx, int nkq,
-                                                     int pack, int single) {
+                                                     int pack, int single, CorrB cb) {
     constexpr int C = 2 * L + 1;
     __shared__ cx<T> spec[NCOL * C * padded(PY)];
     __shared__ cx<T> tws[PY];
     __shared__ cx<T> pairtmp[2 * C];   // Q of the two self-mirrored frequencies of a packed column
     const int tid = threadIdx.x;
     stage_twiddles<T, PY, NTHR>(tws, tw, tid);
-    pass_b_cols<T, PY, L, NCOL, NTHR, GV, SCH>(Tb + (size_t)blockIdx.y * C * nkx * ny, Q, ny, nkx, nkq, pack,
-                                          blockIdx.x * NCOL, spec, tws, pairtmp, tid, single);
+    pass_b_cols<T, PY, L, NCOL, NTHR, GV, SCH, CORR>(Tb + (size_t)blockIdx.y * C * nkx * ny, Q, ny, nkx, nkq, pack,
+                                                blockIdx.x * NCOL, spec, tws, pairtmp, tid, single, &cb);
 }
 
 // Register-resident form (unpacked work buffer: x-frequencies 0 and PX/2 in columns of their
@@ -797,14 +968,31 @@ constexpr int fused_variants() {
 template <typename T, int PY, int L, int NCOL, int NT, int GV, int SCH = 0>
 static void launch_fused(const Apply2DArgs<T>& a, int nbatch, int nkx, int nkq) {
     dim3 grid((nkx + NCOL - 1) / NCOL, nbatch);
+    if constexpr (sizeof(T) == 4) {
+        if (a.bcorr.y) {
+            hipLaunchKernelGGL((k_pass_b_lds<T, PY, L, NCOL, NT, GV, SCH, true>), grid, dim3(NT), 0, a.stream, a.work,
+                               a.Q, SCH == 1 ? a.twy1 : a.twy, a.ny, nkx, nkq, a.pack, 0, a.bcorr);
+            return;
+        }
+    }
     hipLaunchKernelGGL((k_pass_b_lds<T, PY, L, NCOL, NT, GV, SCH>), grid, dim3(NT), 0, a.stream, a.work, a.Q,
-                       SCH == 1 ? a.twy1 : a.twy, a.ny, nkx, nkq, a.pack, a.single_in);
+                       SCH == 1 ? a.twy1 : a.twy, a.ny, nkx, nkq, a.pack, a.single_in, a.bcorr);
+}
+
+// Whether pass B of this (precision, PY, variant) adds the coarse correction (CorrB): the FP32
+// fused forms in LDS.
+template <typename T, int PY>
+static bool corr_ok_py(int var) {
+    constexpr int L = RTE_PASSB_L;
+    if constexpr (sizeof(T) == 4 && fused_fits<T, PY, L>()) return !(reg_variant<T, PY, L>() && var == 3);
+    else return false;
 }
 
 template <typename T, int PY>
 static int launch_py(const Apply2DArgs<T>& a, int nbatch) {
     constexpr int L = RTE_PASSB_L;
     constexpr int C = 2 * L + 1;
+    if (a.bcorr.y && (!corr_ok_py<T, PY>(a.var[1]) || a.single_in)) return -6;
     const int nkq = a.PX / 2 + 1;
     const int nkx = a.pack ? a.PX / 2 : nkq;
     if constexpr (fused_fits<T, PY, L>()) {
@@ -998,6 +1186,22 @@ bool RTE_CAT(pass_b_unpacked_L, RTE_PASSB_L)(int PY, int var) {
 }
 template bool RTE_CAT(pass_b_unpacked_L, RTE_PASSB_L)<float>(int, int);
 template bool RTE_CAT(pass_b_unpacked_L, RTE_PASSB_L)<double>(int, int);
+
+template <typename T>
+bool RTE_CAT(pass_b_corr_ok_L, RTE_PASSB_L)(int PY, int var) {
+    switch (PY) {
+        case 16: return corr_ok_py<T, 16>(var);
+        case 32: return corr_ok_py<T, 32>(var);
+        case 64: return corr_ok_py<T, 64>(var);
+        case 128: return corr_ok_py<T, 128>(var);
+        case 256: return corr_ok_py<T, 256>(var);
+        case 512: return corr_ok_py<T, 512>(var);
+        case 1024: return corr_ok_py<T, 1024>(var);
+    }
+    return false;
+}
+template bool RTE_CAT(pass_b_corr_ok_L, RTE_PASSB_L)<float>(int, int);
+template bool RTE_CAT(pass_b_corr_ok_L, RTE_PASSB_L)<double>(int, int);
 
 #define RTE_PASSB_FN RTE_CAT(pass_b_L, RTE_PASSB_L)
 #define RTE_PASSB_VARIANTS RTE_CAT(pass_b_variants_L, RTE_PASSB_L)

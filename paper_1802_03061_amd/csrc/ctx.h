@@ -91,6 +91,14 @@ struct rte_ctx {
     int pc_nbias = 0;
     float* pc_Y = nullptr;             // coarse network outputs of the current cycle (+ a combine slot)
     int pc_slots = 0;
+    // x-spectra of the prolongation's weight rows [Wc][nkx] (FP32 apply, work buffer packed as
+    // pc_phi_pack), for the coarse correction added in pass B
+    rte::cx<float>* pc_phi = nullptr;
+    int pc_phi_pack = -1;
+    // the correction's per-channel factors (pass A's factor times 1/sqrt(nvec)), device, and the
+    // host copy they were made from
+    float* pc_coef = nullptr;
+    float pc_coef_host[17] = {};
 };
 
 namespace rte {

@@ -20,6 +20,7 @@
 
 #include "../../include/rte_nn.h"
 #include "apply2d.h"
+#include "apply2d_tile.h"
 #include "ctx.h"
 #include "arnoldi_dev.h"
 #include "krylov.h"
@@ -806,6 +807,71 @@ __global__ __launch_bounds__(NET_THREADS) void k_rescale_net(ArnoldiArgs t, TV* 
     for (size_t i = wb * NET_THREADS + threadIdx.x; i < n; i += stride) w[i] = (TV)((double)w[i] * inv);
 }
 
+// k_rescale_net with the next apply's pass A beside the network.  The next Krylov vector's
+// preconditioned form z = v + s P Y needs Y, the network's output, but the x-transform is linear:
+// the blocks other than 0 (the column's bookkeeping) and 1 (the network) transform v alone, and
+// pass B adds the x-spectrum of the correction (CorrB).  Those blocks take row tiles of PA_TR rows,
+// one per 256-thread quarter, in a loop that every block runs the same number of times (a tile
+// past the end loads only in-range addresses and stores nothing).  When the device finds the
+// stored vector's norm off, each quarter folds the factor into pass A's scale and then rescales
+// its own tile's rows, after the barrier that ends the tile, so no other thread still reads them.
+constexpr int PA_TR = 4;
+constexpr int PA_NQ = NET_THREADS / 256;
+struct PassAJob {
+    const cx<float>* twx;   // x twiddles of the FP32 apply
+    cx<float>* work;        // its work buffer [C][NKS][ny]
+    ChanScale sc;           // pass A's per-channel factors (operator A)
+    int nx, ny, C, pack;
+};
+template <int PX>
+constexpr size_t pass_a_job_lds() {
+    return (size_t)(PX + PA_NQ * (PA_TR / 2) * (padded(PX) + 1)) * sizeof(cx<float>);
+}
+template <int HID, typename TV, int PX>
+__global__ __launch_bounds__(NET_THREADS) void k_rescale_net_pa(ArnoldiArgs t, TV* __restrict__ w,
+                                                                const double* __restrict__ partial, int nblk,
+                                                                const float* __restrict__ in,
+                                                                const float* __restrict__ in_scale,
+                                                                const unsigned short* __restrict__ wn, int nwn,
+                                                                const float* __restrict__ bias_all, int nbias,
+                                                                const int* __restrict__ meta, int layers, int C,
+                                                                int Hc, int Wc, float* __restrict__ out, PassAJob pj) {
+    const double inv = arnoldi_stage1_in_rescale(t, partial, nblk);   // bookkeeping in block 0 only
+    if (blockIdx.x == 1) {
+        net_fused_block<HID>(in, in_scale, wn, nwn, bias_all, nbias, meta, layers, C, Hc, Wc, out,
+                             inv < 0.0 ? 1.0f : (float)inv);
+        return;
+    }
+    if (blockIdx.x == 0) return;
+    constexpr int LD = padded(PX) + 1;
+    extern __shared__ __attribute__((aligned(16))) unsigned short lds[];
+    cx<float>* tws = reinterpret_cast<cx<float>*>(lds);
+    const int q = threadIdx.x >> 8, ltid = threadIdx.x & 255;
+    cx<float>* buf = tws + PX + q * (PA_TR / 2) * LD;
+    stage_twiddles<float, PX, NET_THREADS>(tws, pj.twx, threadIdx.x);
+    const int nx = pj.nx, ny = pj.ny;
+    const int NKS = pj.pack ? PX / 2 : PX / 2 + 1;
+    const int ntr = (ny + PA_TR - 1) / PA_TR;
+    const int ntiles = pj.C * ntr;
+    const int G = gridDim.x - 2, b = blockIdx.x - 2;
+    const int rounds = (ntiles + PA_NQ * G - 1) / (PA_NQ * G);
+    const double f = inv < 0.0 ? 1.0 : inv;
+    for (int k = 0; k < rounds; ++k) {
+        const int tile = (k * G + b) * PA_NQ + q;
+        const bool live = tile < ntiles;
+        const int bc = live ? tile / ntr : 0;
+        const int y0 = live ? (tile % ntr) * PA_TR : ny;
+        pass_a_tile<float, PX, PA_TR, 256, TV, false>(w + (size_t)bc * ny * nx, pj.work + (size_t)bc * NKS * ny, nx,
+                                                       ny, pj.sc.s[bc] * f, pj.pack, y0, buf, tws, ltid);
+        __syncthreads();   // this tile's LDS reads end before the next tile's writes
+        if (inv >= 0.0 && live) {
+            TV* wr = w + (size_t)bc * ny * nx + (size_t)y0 * nx;
+            const int cnt = min(PA_TR, ny - y0) * nx;
+            for (int e = ltid; e < cnt; e += 256) wr[e] = (TV)((double)wr[e] * inv);
+        }
+    }
+}
+
 // The single Gram-Schmidt pass of the preconditioned Arnoldi step with its normalisation and the
 // network's restriction fused: w = a (w - sum_v V[v] h[v]) (h = st0.st, a computed here by
 // arnoldi_stage0_in_update, block 0 also running stage 0 of the column), the F x F block means of
@@ -1140,6 +1206,10 @@ void pc_free(rte_ctx* c) {
     c->pc_nbias = 0;
     nfree(c->pc_Y);
     c->pc_slots = 0;
+    nfree(c->pc_phi);
+    c->pc_phi_pack = -1;
+    nfree(c->pc_coef);
+    for (float& v : c->pc_coef_host) v = 0.f;
     c->pc_attached = false;
 }
 
@@ -1287,12 +1357,68 @@ int pc_rescale_net(rte_ctx* c, const ArnoldiArgs& t, TV* w, const double* partia
     return e == hipSuccess ? RTE_OK : set_hip_error(e, "pc_rescale_net", __FILE__, __LINE__);
 }
 
+bool pc_rescale_net_pa_ok(const rte_ctx* c) {
+    if (!pc_rescale_net_ok(c) || c->dim != 2) return false;
+    if (c->PX != 128 && c->PX != 256 && c->PX != 512 && c->PX != 1024) return false;
+    NetShape sh;
+    sh.init(c->C, c->pc_hidden, c->pc_layers);
+    const size_t pa = pass_a_job_lds<1024>();   // the largest instantiation
+    return std::max(fused_net_lds(sh, c->ny / c->pc_factor, c->nx / c->pc_factor), pa) + RESCALE_NET_STATIC_LDS <=
+           160 * 1024;
+}
+
+template <int HID, typename TV, int PX>
+static void launch_rescale_net_pa(rte_ctx* c, const ArnoldiArgs& t, TV* w, const double* partial, int nblk,
+                                  int nwn, int layers, int Hc, int Wc, float* out, const PassAJob& pj, size_t lds) {
+    lds = std::max(lds, pass_a_job_lds<PX>());
+    // one block per CU: blocks 0 and 1 plus 254 pass-A blocks
+    hipLaunchKernelGGL((k_rescale_net_pa<HID, TV, PX>), dim3(256), dim3(NET_THREADS), lds, c->stream, t, w, partial,
+                       nblk, c->pc_coarse, c->pc_st + 1, c->pc_wn, nwn, c->pc_bn, c->pc_nbias, c->pc_meta, layers,
+                       c->C, Hc, Wc, out, pj);
+}
+
+template <typename TV>
+int pc_rescale_net_pa(rte_ctx* c, const ArnoldiArgs& t, TV* w, const double* partial, int slot,
+                      const ChanScale& sc, int pack) {
+    NetShape sh;
+    sh.init(c->C, c->pc_hidden, c->pc_layers);
+    const int F = c->pc_factor;
+    const int Hc = c->ny / F, Wc = c->nx / F;
+    const size_t lds = fused_net_lds(sh, Hc, Wc);
+    const int nwn = (int)c->pc_wn_len;
+    float* out = c->pc_Y + (size_t)slot * pc_coarse_len(c);
+    const int nblk = pc_update_pool_blocks(c);
+    PassAJob pj;
+    pj.twx = c->twf[0];
+    pj.work = c->wf;
+    pj.sc = sc;
+    pj.nx = c->nx;
+    pj.ny = c->ny;
+    pj.C = c->C;
+    pj.pack = pack;
+#define RTE_PA_CASE(PXV)                                                                                         \
+    case PXV:                                                                                                    \
+        if (c->pc_hidden == 32)                                                                                  \
+            launch_rescale_net_pa<32, TV, PXV>(c, t, w, partial, nblk, nwn, sh.layers, Hc, Wc, out, pj, lds);    \
+        else                                                                                                     \
+            launch_rescale_net_pa<16, TV, PXV>(c, t, w, partial, nblk, nwn, sh.layers, Hc, Wc, out, pj, lds);    \
+        break;
+    switch (c->PX) {
+        RTE_PA_CASE(128) RTE_PA_CASE(256) RTE_PA_CASE(512) RTE_PA_CASE(1024)
+        default: return set_error(RTE_EUNSUPPORTED, "pc_rescale_net_pa: padded x %d", c->PX);
+    }
+#undef RTE_PA_CASE
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RTE_OK : set_hip_error(e, "pc_rescale_net_pa", __FILE__, __LINE__);
+}
+
 #define RTE_PC_INST(TV)                                                                                           \
     template void pc_scale_pool<double, TV>(rte_ctx*, const double*, TV*, const double*, double, double*, int,    \
                                             double, int*, int);                                                 \
     template void pc_rescale_pool_arn1<TV>(rte_ctx*, const ArnoldiArgs&, TV*, const double*);                    \
     template void pc_update_pool<TV>(rte_ctx*, TV*, const TV*, int, double*, double*, const ArnoldiArgs&);       \
-    template int pc_rescale_net<TV>(rte_ctx*, const ArnoldiArgs&, TV*, const double*, int);
+    template int pc_rescale_net<TV>(rte_ctx*, const ArnoldiArgs&, TV*, const double*, int);                     \
+    template int pc_rescale_net_pa<TV>(rte_ctx*, const ArnoldiArgs&, TV*, const double*, int, const ChanScale&, int);
 RTE_PC_INST(float)
 RTE_PC_INST(double)
 #undef RTE_PC_INST

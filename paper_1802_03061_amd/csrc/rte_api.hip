@@ -16,6 +16,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <complex>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -330,6 +331,97 @@ static int apply_basis_pc(rte_ctx* c, const TV* v, TV* y, const float* Y) {
     else return c->prec == RTE_PREC_FP32 ? apply_pc_t<float>(c, v, y, Y) : apply_pc_t<double>(c, v, y, Y);
 }
 
+// The x-spectra of the bilinear prolongation's weight rows (CorrB): phi[X][kx] = sum over fine
+// columns x < nx of w_X(x) exp(-2 pi i kx x / PX), w_X(x) the weight of coarse column X at x as
+// lerp_at computes it; with the packed work buffer, column 0 holds (phi(0), phi(PX/2)).  Built on
+// the host in FP64 once per context and packing.
+static int pc_phi_prepare(rte_ctx* c, int pack) {
+    if (c->pc_phi && c->pc_phi_pack == pack) return RTE_OK;
+    const int F = c->pc_factor, Wc = c->nx / F, PX = c->PX, H = PX / 2;
+    const int nkx = pack ? H : H + 1;
+    std::vector<std::complex<double>> tw(PX), ph((size_t)Wc * nkx);
+    std::vector<double> alt(Wc, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int q = 0; q < PX; ++q) tw[q] = std::polar(1.0, -2.0 * pi * q / PX);
+    for (int x = 0; x < c->nx; ++x) {
+        const float xi = ((float)x + 0.5f) / (float)F - 0.5f;
+        const float f0 = std::floor(xi);
+        const float a = xi - f0;
+        const int i0 = (int)f0;
+        const int lo = std::min(std::max(i0, 0), Wc - 1), hi = std::min(std::max(i0 + 1, 0), Wc - 1);
+        const double wl = (double)(1.f - a), wh = (double)a;
+        for (int k = 0; k < nkx; ++k) {
+            const std::complex<double> e = tw[(size_t)k * x % PX];
+            ph[(size_t)lo * nkx + k] += wl * e;
+            ph[(size_t)hi * nkx + k] += wh * e;
+        }
+        const double sg = (x & 1) ? -1.0 : 1.0;
+        alt[lo] += wl * sg;
+        alt[hi] += wh * sg;
+    }
+    std::vector<cx<float>> hst((size_t)Wc * nkx);
+    for (int X = 0; X < Wc; ++X)
+        for (int k = 0; k < nkx; ++k) {
+            std::complex<double> v = ph[(size_t)X * nkx + k];
+            if (pack && k == 0) v = std::complex<double>(v.real(), alt[X]);
+            hst[(size_t)X * nkx + k] = cx<float>{(float)v.real(), (float)v.imag()};
+        }
+    if (c->pc_phi) (void)hipFree(c->pc_phi);
+    c->pc_phi = nullptr;
+    c->pc_phi_pack = -1;
+    int rc = dalloc(&c->pc_phi, hst.size());
+    if (rc) return rc;
+    RTE_HIP_TRY(hipMemcpy(c->pc_phi, hst.data(), hst.size() * sizeof(cx<float>), hipMemcpyHostToDevice));
+    c->pc_phi_pack = pack;
+    return RTE_OK;
+}
+
+// Whether a preconditioned solve runs the next apply's pass A inside the stage-1 launch, beside
+// the network (FP32 2D apply with a pass B that can add the correction); RTE_PC_EARLY_A=0 turns
+// it off.  Prepares the correction's x-spectra.
+static bool early_a_ok(rte_ctx* c) {
+    if (c->dim != 2 || c->prec != RTE_PREC_FP32 || c->L > 8 || c->C > 17) return false;
+    const char* env = std::getenv("RTE_PC_EARLY_A");
+    if (env && env[0] == '0') return false;
+    if (!pc_rescale_net_pa_ok(c)) return false;
+    const Apply2DArgs<float> a = args2d<float>(c);
+    if (!apply2d_b_corr_ok<float>(c->L, c->PY, a.var[1])) return false;
+    if (pc_phi_prepare(c, pack_for(a)) != RTE_OK) return false;
+    // the per-channel factors, uploaded again only when the medium changed
+    const ChanScale sc = channel_scale(c, APPLY_A);
+    const double cs = 1.0 / std::sqrt((double)c->nvec);
+    float k[17] = {};
+    for (int ch = 0; ch < c->C; ++ch) k[ch] = (float)(sc.s[ch] * cs);
+    if (c->pc_coef && std::memcmp(k, c->pc_coef_host, sizeof(k)) == 0) return true;
+    if (!c->pc_coef && dalloc(&c->pc_coef, 17) != RTE_OK) return false;
+    if (hipMemcpy(c->pc_coef, k, sizeof(k), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    std::memcpy(c->pc_coef_host, k, sizeof(k));
+    return true;
+}
+
+// y = A (v + s P Y) after the stage-1 launch has run pass A on v alone (early_a_ok): passes B,
+// adding the correction's x-spectrum, and C.
+template <typename TV>
+static int apply_basis_pc_from_b(rte_ctx* c, const TV* v, TV* y, const float* Y) {
+    Apply2DArgs<float> a = args2d<float>(c);
+    a.pack = pack_for(a);
+    a.corr = Y;
+    a.cF = c->pc_factor;
+    a.cs = 1.0 / std::sqrt((double)c->nvec);
+    a.bcorr.y = Y;
+    a.bcorr.phi = c->pc_phi;
+    a.bcorr.F = c->pc_factor;
+    a.bcorr.Hc = c->ny / c->pc_factor;
+    a.bcorr.Wc = c->nx / c->pc_factor;
+    a.bcorr.coef = c->pc_coef;
+    if (apply2d_from_b<float>(a, v, y)) return set_error(RTE_EUNSUPPORTED, "apply: unsupported size");
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? RTE_OK : set_hip_error(e, "apply launch", __FILE__, __LINE__);
+}
+
 // ------------------------------------------------------------------ autotuning -----------------
 // Every pass of the 2D apply has a few kernel variants with the same arithmetic (different row
 // tiles, thread counts, FFT grouping).  The tuner times each variant of each pass on the
@@ -487,6 +579,7 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
     const bool fused = c->opts.reorth == 0 &&
                        (!use_pc || (size_t)pc_update_pool_blocks(c) <= (size_t)(m + 3) * RTE_KRYLOV_NBLK);
     const bool rescale_net = fused && use_pc && pc_rescale_net_ok(c);
+    const bool early_a = rescale_net && early_a_ok(c);
 
     double* dH = c->arn;
     double* dcs = dH + (size_t)(m + 1) * m;
@@ -517,6 +610,7 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
         int jd = 0;           // columns of this cycle that are valid
         int launched = 0;
         bool net_ready = false;   // the network output of the next step is already being computed
+        bool a_ready = false;     // and pass A of its apply (early_a)
         bool stop = false, bad = false;
         for (int j = 0; j < m && it + launched < max_iter && !stop; ++j) {
             TV* vj = V + (size_t)j * n;
@@ -525,7 +619,9 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
             if (pc_live) {
                 if (!net_ready && (rc = pc_net_slot(c, j))) return rc;   // else the last launch ran it
                 net_ready = false;
-                if ((rc = apply_basis_pc(c, vj, w, pc_slot(c, j)))) return rc;
+                rc = a_ready ? apply_basis_pc_from_b(c, vj, w, pc_slot(c, j)) : apply_basis_pc(c, vj, w, pc_slot(c, j));
+                a_ready = false;
+                if (rc) return rc;
             } else if ((rc = apply_basis(c, vj, w, nb))) {
                 return rc;
             }
@@ -562,8 +658,16 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
                 at.est_out = c->hpipe_dev + j;
                 at.flags_out = c->hpipe_flags_dev + 2 * j;
                 if (pc_live && j + 1 < m && rescale_net) {
-                    // stage 1 and the next step's network in one launch
-                    if ((rc = pc_rescale_net(c, at, w, c->partial, j + 1))) return rc;
+                    // stage 1 and the next step's network in one launch (with the next apply's
+                    // pass A on the other blocks when early_a)
+                    if (early_a) {
+                        const Apply2DArgs<float> a = args2d<float>(c);
+                        if ((rc = pc_rescale_net_pa(c, at, w, c->partial, j + 1, channel_scale(c, APPLY_A), pack_for(a))))
+                            return rc;
+                        a_ready = true;
+                    } else if ((rc = pc_rescale_net(c, at, w, c->partial, j + 1))) {
+                        return rc;
+                    }
                     net_ready = true;
                 } else if (pc_live) {
                     pc_rescale_pool_arn1(c, at, w, c->partial);

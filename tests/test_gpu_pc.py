@@ -410,6 +410,57 @@ def test_fgmres_iterates_match_oracle(rte, prec, n, basis32):
     net.close()
 
 
+@pytest.mark.parametrize("n,L,F,basis32", [(64, 2, 4, 0), (64, 2, 4, 1), (64, 8, 8, 0), (160, 2, 8, 0),
+                                           (512, 8, 32, 0)])
+def test_early_pass_a_matches_oracle(rte, monkeypatch, n, L, F, basis32):
+    """FP32 apply: the stage-1 launch of each preconditioned Arnoldi step also runs the next apply's
+    pass A on v_{j+1} alone, and pass B adds the x-spectrum of the coarse correction (the x-FFT is
+    linear, and the bilinear prolongation separates into x and y parts), so the apply still takes
+    z_j = v_j + s P N(R v_j / s).  The first iterates agree with the path that adds the correction
+    before pass A (RTE_PC_EARLY_A=0) to FP32 rounding and follow the oracle's flexible GMRES within
+    the BF16 network's accuracy; full solves of both paths agree with each other.  Padded x 128,
+    512 (n = 160, 20^2 coarse grid) and 1024 (n = 512, where each wave of pass B forms the
+    correction of its own transforms); L = 8 takes 17 channels."""
+    k = 4
+    mu_a, mu_s = 0.1, 4.0
+    h, mu_t = 1.0 / n, mu_a + mu_s
+    sh = inputs.hg_sigma_hat(0.5, L)
+    f = inputs.gaussian_mixture_source(n, inputs.gaussian_mixture_params(np.random.default_rng(13), 2))
+    ctx = rte.Context(n, mu_a=mu_a, mu_s=mu_s, sigma_hat=sh, L=L, prec=0)
+    net = rte.Net(ctx.channels, 32, 5, seed=9, use_bias=False)
+    w = net.params() * 0.3
+    params = unpack(host(w), ctx.channels, 32, 5)
+    ctx.attach_pc(w, factor=F)
+    ctx.set_opts(basis_fp32=basis32)
+    b = op2.rhs(f, L, h, mu_t, method="fft")
+    bc = _to_ch(b, L)
+    recs, sols = {}, {}
+    for early in ("1", "0"):
+        monkeypatch.setenv("RTE_PC_EARLY_A", early)
+        say("early pass A", early, "n", n, "L", L, "F", F, "basis32", basis32)
+        _, info, rec = ctx.solve_rhs(dev(bc), tol=1e-11, record=k)
+        assert info["pc_used"] == 1 and info["pc_fallback"] == 0 and rec.shape[0] == k
+        recs[early] = host(rec)
+        u, info = ctx.solve_rhs(dev(bc), tol=1e-10)[:2]
+        say("  solve", info["iterations"], info["relres_true"])
+        assert info["pc_fallback"] == 0 and info["relres_true"] <= 1e-10
+        sols[early] = host(u)
+    spectra = op2.kernel_spectra(n, n, L, h, mu_t)
+    matvec = lambda v: _to_ch(op2.apply_fft(_to_modes(v, L), L, h, mu_t, mu_s, sh, spectra=spectra), L)
+    xs = _oracle_fgmres_iterates(matvec, lambda v: cn.precondition(v, params, F), bc, k)
+    for i in range(k):
+        d_paths = relerr(recs["1"][i], recs["0"][i])
+        d_oracle = relerr(recs["1"][i], xs[i])
+        say("  iterate", i + 1, "early vs late", d_paths, "vs oracle", d_oracle)
+        assert d_paths <= 1e-4
+        assert d_oracle <= 3e-2
+    d = relerr(sols["1"], sols["0"])
+    say("  solutions early vs late", d)
+    assert d <= 1e-8
+    ctx.close()
+    net.close()
+
+
 def test_gather_rows_and_upsample_match_torch_cpu(rte):
     """The two training-data kernels against PyTorch CPU references: the minibatch gather against
     indexing, and the bilinear upsampling at cell centres against F.interpolate (bilinear,
