@@ -19,7 +19,7 @@ struct ChanScale {
 // phi[X] being the x-spectrum of the fine row of interpolation weights of coarse column X (its
 // column 0 holds (phi(0), phi(PX/2)) when the work buffer is packed).
 struct CorrB {
-    const float* y = nullptr;       // coarse field [C][Hc][Wc]
+    const float* y = nullptr;       // coarse field [C][Hc][Wc], 16-byte aligned, Wc a multiple of 4
     const void* phi = nullptr;      // cx<float> [Wc][nkx], nkx = columns of the work buffer
     const float* coef = nullptr;    // [C] in device memory: pass A's factor of channel c times cs
     int Hc = 0, Wc = 0, F = 1;

@@ -213,25 +213,22 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
         }
         const int kx = kx0 + fc / C;
         ok = ok && kx < nkx;
-        const float* yr = cb->y + ((size_t)(fc % C) * Hc + R) * Wc;
-        // each lane reads its own coarse row: 16-byte loads when rows are whole float4s (the
-        // field is 16-byte aligned), so an instruction touches a quarter of the cache lines
-        if (Wc % 4 == 0) {
-            const float4* y4 = reinterpret_cast<const float4*>(yr);
+        // Each lane reads its own coarse row as 16-byte loads (rows are whole float4s, CorrB), an
+        // instruction touching a quarter of the cache lines that single floats would.  Every load
+        // takes a clamped in-range index instead of a branch, and the out-of-range values are
+        // zeroed afterwards: per-load branches made the compiler wait for these loads before
+        // issuing the column loads.
+        const float4* y4 = reinterpret_cast<const float4*>(cb->y + (ok ? ((size_t)(fc % C) * Hc + R) * Wc : 0));
 #pragma unroll
-            for (int q = 0; q < GU / 4; ++q) {
-                const float4 t = (ok && 4 * q < Wc) ? y4[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-                gy[4 * q] = (T)t.x;
-                gy[4 * q + 1] = (T)t.y;
-                gy[4 * q + 2] = (T)t.z;
-                gy[4 * q + 3] = (T)t.w;
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < GU; ++u) gy[u] = (ok && u < Wc) ? (T)yr[u] : (T)0;
+        for (int q = 0; q < GU / 4; ++q) {
+            const float4 t = y4[4 * q < Wc ? q : 0];
+            gy[4 * q] = (T)t.x;
+            gy[4 * q + 1] = (T)t.y;
+            gy[4 * q + 2] = (T)t.z;
+            gy[4 * q + 3] = (T)t.w;
         }
 #pragma unroll
-        for (int u = 0; u < GU; ++u) gp[u] = (ok && u < Wc) ? phi[(size_t)u * nkx + kx] : mk((T)0, (T)0);
+        for (int u = 0; u < GU; ++u) gp[u] = phi[(ok && u < Wc) ? (size_t)u * nkx + kx : 0];
     }
     cx<T> ld[IT][R0 / 2];
 #pragma unroll
@@ -241,12 +238,19 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
         const int col = fc / C, c = fc % C;
         const int kx = kx0 + col;
         const bool ok = (NBT % NTHR == 0 || idx < NBT) && kx < nkx && (!single || c == 0);
+        // every load takes a clamped in-range index instead of a branch, and the values out of
+        // range are zeroed where they are first used (the first stage below): behind per-load
+        // branches, or with a product right after each load, the compiler waited for the first
+        // loads before issuing the rest
 #pragma unroll
         for (int r = 0; r < R0 / 2; ++r) {
             const int y = j + r * NB0;
-            ld[it][r] = (ok && y < ny) ? base[c * cstride + (size_t)kx * ny + y] : mk((T)0, (T)0);
+            ld[it][r] = base[(ok && y < ny) ? c * cstride + (size_t)kx * ny + y : 0];
         }
     }
+    // keep the column loads issued ahead of the correction's arithmetic, which waits on its own
+    // (earlier) loads only
+    if constexpr (CORR) __builtin_amdgcn_sched_barrier(0);
     if (CORR && wg) {
         const int itl = lane / Hc, R = lane % Hc;
         const int fc = (64 * wave + itl * NTHR) / NB0;
@@ -255,8 +259,9 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
         if (itl < IT && fc < NF && kx < nkx) {
 #pragma unroll
             for (int u = 0; u < GU; ++u) {
-                gr += gy[u] * gp[u].re;
-                gi += gy[u] * gp[u].im;
+                const T yv = u < Wc ? gy[u] : (T)0;
+                gr += yv * gp[u].re;
+                gi += yv * gp[u].im;
             }
             const float* yr = cb->y + ((size_t)(fc % C) * Hc + R) * Wc;
             for (int X = GU; X < Wc; ++X) {
@@ -310,8 +315,9 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
                 if (idx == tid) {
 #pragma unroll
                     for (int u = 0; u < GU; ++u) {
-                        gr += gy[u] * gp[u].re;
-                        gi += gy[u] * gp[u].im;
+                        const T yv = u < Wc ? gy[u] : (T)0;
+                        gr += yv * gp[u].re;
+                        gi += yv * gp[u].im;
                     }
                 }
                 const float* yr = cb->y + ((size_t)c * Hc + R) * Wc;
@@ -361,9 +367,12 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
         const int idx = tid + it * NTHR;
         if (NBT % NTHR == 0 || idx < NBT) {
             const int j = idx % NB0, fc = idx / NB0;
+            const int c = fc % C, kx = kx0 + fc / C;
+            const bool ok = kx < nkx && (!single || c == 0);
             cx<T> v[R0];
 #pragma unroll
-            for (int r = 0; r < R0; ++r) v[r] = r < R0 / 2 ? ld[it][r] : mk((T)0, (T)0);
+            for (int r = 0; r < R0; ++r)
+                v[r] = (r < R0 / 2 && ok && j + r * NB0 < ny) ? ld[it][r] : mk((T)0, (T)0);
             dft_small<T, R0, false>(v);
 #pragma unroll
             for (int r = 0; r < R0; ++r) spec[fc * LD + sw(j * R0 + r)] = v[r];

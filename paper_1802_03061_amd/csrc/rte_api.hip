@@ -381,6 +381,7 @@ static int pc_phi_prepare(rte_ctx* c, int pack) {
 // it off.  Prepares the correction's x-spectra.
 static bool early_a_ok(rte_ctx* c) {
     if (c->dim != 2 || c->prec != RTE_PREC_FP32 || c->L > 8 || c->C > 17) return false;
+    if ((c->nx / c->pc_factor) % 4) return false;   // pass B reads the coarse rows as float4s
     const char* env = std::getenv("RTE_PC_EARLY_A");
     if (env && env[0] == '0') return false;
     if (!pc_rescale_net_pa_ok(c)) return false;
