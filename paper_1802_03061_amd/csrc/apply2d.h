@@ -57,8 +57,9 @@ struct Apply2DArgs {
 // Kernel variants (same arithmetic, different tiling; results agree up to rounding):
 //   passes A and C (PX >= 128): row tiles of 16, 8, 32 or 4 rows (FP32) / 8, 4, 16 or 2 rows (FP64)
 //   pass B, fused form (PY >= 128): default threads and FFT grouping, 1024 threads with groups of
-//   4 transforms (FP32 only), 256 threads, the register-resident form (FP32, 5+ channels), and
-//   the radix-32 schedule (PY >= 256)
+//   4 transforms (FP32 only), 256 threads, the register-resident form (FP32, 5+ channels), the
+//   radix-32 schedule (PY >= 256), and all of a block's transforms in one FFT stage group where
+//   the default grouping splits them (FP32, PY = 1024, L >= 6)
 //   pass B, split form (FP64 with L > 4): three kernels through the full-length buffer, the
 //   column split in halves, or the coupling fused with the inverse y-FFTs by channel groups
 //   pass B, L > 8: the coupling as a mode-axis FFT or as a register-blocked direct sum
