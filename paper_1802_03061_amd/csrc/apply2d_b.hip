@@ -173,14 +173,15 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
     constexpr int NBT = NF * NB0;
     constexpr int IT = (NBT + NTHR - 1) / NTHR;
     // The coarse correction's x-spectrum (CorrB): G[fc][R] = coef_c sum_X y_c[R][X] phi[X][kx] for
-    // the block's columns, held in spec (with a table of the rows' y-interpolation) until the first
-    // stage's writes, then interpolated in y onto every loaded row.  A thread's first G item has its (L2-resident) loads issued before the
-    // column loads, so that their latency hides behind those.
+    // the block's columns, interpolated in y onto every loaded row.  A thread's first G item has
+    // its (L2-resident) loads issued before the column loads, so that their latency hides behind
+    // those.
     //   When a wave's transform index is the same for all its lanes (NB0 a multiple of 64) and the
     // same rows recur at every step it, each wave computes the G values of its own transforms
     // into private slots among the pad slots of spec (never written by the transforms, see sw)
     // and reads them back after a wave-level fence: no block barrier, so the waves' column loads
-    // still overlap one another's first stage.  Otherwise G goes through spec with two barriers.
+    // still overlap one another's first stage.  Otherwise G and a table of the rows'
+    // y-interpolation go through spec, behind two barriers.
     constexpr int GU = 16;
     constexpr bool WAVEG = CORR && NB0 % 64 == 0 && NTHR % NB0 == 0 && NTHR <= NF * (PY / 16);
     T gy[CORR ? GU : 1];
@@ -215,9 +216,9 @@ __device__ __forceinline__ void pass_b_cols(cx<T>* __restrict__ base, const cx<T
         ok = ok && kx < nkx;
         // Each lane reads its own coarse row as 16-byte loads (rows are whole float4s, CorrB), an
         // instruction touching a quarter of the cache lines that single floats would.  Every load
-        // takes a clamped in-range index instead of a branch, and the out-of-range values are
-        // zeroed afterwards: per-load branches made the compiler wait for these loads before
-        // issuing the column loads.
+        // takes a clamped in-range index instead of a branch, and the sums below skip the values
+        // out of range: per-load branches made the compiler wait for these loads before issuing
+        // the column loads.
         const float4* y4 = reinterpret_cast<const float4*>(cb->y + (ok ? ((size_t)(fc % C) * Hc + R) * Wc : 0));
 #pragma unroll
         for (int q = 0; q < GU / 4; ++q) {
