@@ -574,6 +574,10 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
     double rn = bn;
     int it = 0, cycles = 0, status = RTE_NOT_CONVERGED;
     double est = bn;
+    // the output step ran after the last change of x: it is enqueued with a cycle's true residual
+    // only when that cycle can end the solve (its target within 100x of the tolerance), else once
+    // after the last cycle
+    bool finish_fresh = false;
     bool pc_live = use_pc;
     // single-pass Gram-Schmidt with the normalisation (and the network's restriction) fused into the
     // update; the preconditioned form needs one partial sum per pooling block in c->partial
@@ -597,6 +601,7 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
         ++cycles;
         double target = 0.5 * tol * bn;
         if (mixed) target = std::max(target, c->opts.inner_tol * rn);
+        const bool may_end = target <= 100.0 * tol * bn;
         // v_0 = r / rn (with the pooled coarse input of the network when preconditioning)
         if (pc_live) {   // with g = (rn, 0, ...) and the flags cleared in the same launch
             pc_scale_pool(c, (const double*)rv, V, nullptr, 1.0 / rn, dg, m + 1, rn, dfl, 4);
@@ -727,7 +732,11 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
             if ((rc = apply_channels(c, APPLY_RESID, RTE_PREC_FP64, x, b, rv, nb))) return rc;
             ++inf.applies;
             dot_enqueue(c, rv, rv, n);
-            if (finish && finish->fn) finish->fn(c, finish->arg);   // runs while the host waits
+            finish_fresh = false;
+            if (finish && finish->fn && may_end) {   // runs while the host waits
+                finish->fn(c, finish->arg);
+                finish_fresh = true;
+            }
         }
         // settle the last enqueued iteration
         if (launched > 0 && (rc = wait_slot(c, hp + (launched - 1)))) return rc;
@@ -750,6 +759,7 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
                 inf.pc_fallback = 1;
                 continue;
             }
+            if (finish && finish->fn && !finish_fresh) finish->fn(c, finish->arg);
             inf.iterations = it;
             inf.cycles = cycles;
             inf.status = RTE_ENUMERIC;
@@ -778,11 +788,16 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
             if ((rc = apply_channels(c, APPLY_RESID, RTE_PREC_FP64, x, b, rv, nb))) return rc;
             ++inf.applies;
             dot_enqueue(c, rv, rv, n);
-            if (finish && finish->fn) finish->fn(c, finish->arg);   // runs while the host waits
+            finish_fresh = false;
+            if (finish && finish->fn && may_end) {   // runs while the host waits
+                finish->fn(c, finish->arg);
+                finish_fresh = true;
+            }
         }
         double rn2;
         if ((rc = dot_wait(c, &rn2))) return rc;
         if (!std::isfinite(rn2)) {
+            if (finish && finish->fn && !finish_fresh) finish->fn(c, finish->arg);
             inf.iterations = it;
             inf.cycles = cycles;
             inf.status = RTE_ENUMERIC;
@@ -798,6 +813,7 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
             inf.pc_fallback = 1;
         }
     }
+    if (finish && finish->fn && !finish_fresh) finish->fn(c, finish->arg);
     RTE_HIP_TRY(hipStreamSynchronize(st));
     inf.iterations = it;
     inf.cycles = cycles;

@@ -227,15 +227,18 @@ def test_solve_gram_schmidt_variants_vs_lu(rte, reorth, prec, basis32):
     ctx.close()
 
 
-@pytest.mark.parametrize("reorth", [0, 1])
-def test_solve_no_scattering_is_one_step(rte, reorth):
+@pytest.mark.parametrize("reorth,prec", [(0, 1), (1, 1), (0, 0)])
+def test_solve_no_scattering_is_one_step(rte, reorth, prec):
     """mu_s = 0 makes A the identity: the first Arnoldi column breaks down (w = v_0), and the
-    solution is the right-hand side b = K f, which the KT apply gives directly."""
+    solution is the right-hand side b = K f, which the KT apply gives directly.  With the FP32
+    apply the first cycle's target (3e-4 of the residual) is far above the tolerance, so the
+    output conversion is not queued with its true residual; the solve still converges in that
+    cycle, and the conversion runs at its end."""
     L, n = 2, 16
     rng = np.random.default_rng(3)
     f = rng.random((n, n))
     sh = inputs.hg_sigma_hat(0.5, L)
-    ctx = rte.Context(n, mu_a=1.5, mu_s=0.0, sigma_hat=sh, L=L, prec=rte.PREC_FP64)
+    ctx = rte.Context(n, mu_a=1.5, mu_s=0.0, sigma_hat=sh, L=L, prec=prec)
     ctx.set_opts(reorth=reorth)
     u, info = ctx.solve(dev(f), tol=1e-12)
     say("  info", info)
