@@ -231,7 +231,9 @@ int rte_solve_batched(int count, rte_ctx* const* ctxs, const double* const* f_de
  * or that produces a non-finite value, is followed by plain GMRES (info.pc_fallback = 1).  With
  * the FP32 apply (padded x 128..1024) each Arnoldi step runs the next apply's x-transforms beside
  * the network and adds the correction's x-spectrum in the y-pass instead (the same z up to FP32
- * rounding); environment RTE_PC_EARLY_A=0 keeps the correction in the x-pass. */
+ * rounding); environment RTE_PC_EARLY_A=0 keeps the correction in the x-pass.  Environment
+ * RTE_RENORM_TOL overrides the tolerance on |v_{j+1}|^2 - 1 beyond which a solve rescales the new
+ * Krylov vector (default 1e-8 with the FP32 apply, 1e-10 with FP64; negative: every step). */
 int rte_pc_attach(rte_ctx* ctx, const float* weights_dev, int hidden, int layers, int factor);
 
 /* Time `reps` back-to-back applies (op, RTE_LAYOUT_CHANNELS, prec) on the context stream with

@@ -585,6 +585,10 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
                        (!use_pc || (size_t)pc_update_pool_blocks(c) <= (size_t)(m + 3) * RTE_KRYLOV_NBLK);
     const bool rescale_net = fused && use_pc && pc_rescale_net_ok(c);
     const bool early_a = rescale_net && early_a_ok(c);
+    // tolerance on |v_{j+1}|^2 - 1 beyond which the stored vector is rescaled; RTE_RENORM_TOL
+    // overrides it (a negative value rescales at every step, which tests use)
+    const char* renorm_env = std::getenv("RTE_RENORM_TOL");
+    const double renorm_tol = renorm_env ? std::atof(renorm_env) : (mixed ? 1e-8 : 1e-10);
 
     double* dH = c->arn;
     double* dcs = dH + (size_t)(m + 1) * m;
@@ -640,7 +644,7 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
             at.m = m;
             at.reorth = c->opts.reorth;
             at.fused = fused ? 1 : 0;
-            at.renorm_tol = mixed ? 1e-8 : 1e-10;
+            at.renorm_tol = renorm_tol;
             at.st = sd;
             at.H = dH;
             at.cs = dcs;

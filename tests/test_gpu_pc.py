@@ -410,9 +410,10 @@ def test_fgmres_iterates_match_oracle(rte, prec, n, basis32):
     net.close()
 
 
-@pytest.mark.parametrize("n,L,F,basis32", [(64, 2, 4, 0), (64, 2, 4, 1), (64, 8, 8, 0), (160, 2, 8, 0),
-                                           (512, 8, 32, 0)])
-def test_early_pass_a_matches_oracle(rte, monkeypatch, n, L, F, basis32):
+@pytest.mark.parametrize("n,L,F,basis32,rescale", [(64, 2, 4, 0, 0), (64, 2, 4, 1, 0), (64, 8, 8, 0, 0),
+                                                   (160, 2, 8, 0, 0), (512, 8, 32, 0, 0), (64, 2, 4, 0, 1),
+                                                   (512, 8, 32, 0, 1)])
+def test_early_pass_a_matches_oracle(rte, monkeypatch, n, L, F, basis32, rescale):
     """FP32 apply: the stage-1 launch of each preconditioned Arnoldi step also runs the next apply's
     pass A on v_{j+1} alone, and pass B adds the x-spectrum of the coarse correction (the x-FFT is
     linear, and the bilinear prolongation separates into x and y parts), so the apply still takes
@@ -420,7 +421,9 @@ def test_early_pass_a_matches_oracle(rte, monkeypatch, n, L, F, basis32):
     before pass A (RTE_PC_EARLY_A=0) to FP32 rounding and follow the oracle's flexible GMRES within
     the BF16 network's accuracy; full solves of both paths agree with each other.  Padded x 128,
     512 (n = 160, 20^2 coarse grid) and 1024 (n = 512, where each wave of pass B forms the
-    correction of its own transforms); L = 8 takes 17 channels."""
+    correction of its own transforms); L = 8 takes 17 channels.  rescale: RTE_RENORM_TOL=-1 makes
+    every step rescale its new vector, so the stage-1 launch folds the factor into pass A and
+    rescales each tile after transforming it."""
     k = 4
     mu_a, mu_s = 0.1, 4.0
     h, mu_t = 1.0 / n, mu_a + mu_s
@@ -434,6 +437,8 @@ def test_early_pass_a_matches_oracle(rte, monkeypatch, n, L, F, basis32):
     ctx.set_opts(basis_fp32=basis32)
     b = op2.rhs(f, L, h, mu_t, method="fft")
     bc = _to_ch(b, L)
+    if rescale:
+        monkeypatch.setenv("RTE_RENORM_TOL", "-1")
     recs, sols = {}, {}
     for early in ("1", "0"):
         monkeypatch.setenv("RTE_PC_EARLY_A", early)
