@@ -35,11 +35,12 @@ template <typename TV>
 int pc_rescale_net(rte_ctx* c, const ArnoldiArgs& t, TV* w, const double* partial, int slot);
 // The same launch with the next apply's pass A (FP32, 2D) on its other blocks: the x-transform of
 // w alone, scaled per channel by sc, into the FP32 work buffer (packed as `pack`); the apply of
-// w is then finished by passes B (adding the coarse correction, CorrB) and C.  Usable when
-// pc_rescale_net_pa_ok(c).
+// w is then finished by passes B (adding the coarse correction, CorrB) and C.  With t NULL (the
+// first step of a cycle, w = v_0 and its block means already pooled) there is no stage 1: the
+// network of v_0 beside its pass A.  Usable when pc_rescale_net_pa_ok(c).
 bool pc_rescale_net_pa_ok(const rte_ctx* c);
 template <typename TV>
-int pc_rescale_net_pa(rte_ctx* c, const ArnoldiArgs& t, TV* w, const double* partial, int slot,
+int pc_rescale_net_pa(rte_ctx* c, const ArnoldiArgs* t, TV* w, const double* partial, int slot,
                       const ChanScale& sc, int pack);
 int pc_update_pool_blocks(const rte_ctx* c);
 int pc_net_slot(rte_ctx* c, int j);                    // Y_j = N(pooled v_j / s)

@@ -827,7 +827,9 @@ template <int PX>
 constexpr size_t pass_a_job_lds() {
     return (size_t)(PX + PA_NQ * (PA_TR / 2) * (padded(PX) + 1)) * sizeof(cx<float>);
 }
-template <int HID, typename TV, int PX>
+// ST1 false: the first step of a cycle, with no Arnoldi column to finish: the network of v_0's
+// block means beside pass A of v_0, no rescale.
+template <int HID, typename TV, int PX, bool ST1>
 __global__ __launch_bounds__(NET_THREADS) void k_rescale_net_pa(ArnoldiArgs t, TV* __restrict__ w,
                                                                 const double* __restrict__ partial, int nblk,
                                                                 const float* __restrict__ in,
@@ -836,7 +838,8 @@ __global__ __launch_bounds__(NET_THREADS) void k_rescale_net_pa(ArnoldiArgs t, T
                                                                 const float* __restrict__ bias_all, int nbias,
                                                                 const int* __restrict__ meta, int layers, int C,
                                                                 int Hc, int Wc, float* __restrict__ out, PassAJob pj) {
-    const double inv = arnoldi_stage1_in_rescale(t, partial, nblk);   // bookkeeping in block 0 only
+    double inv = -1.0;
+    if constexpr (ST1) inv = arnoldi_stage1_in_rescale(t, partial, nblk);   // bookkeeping in block 0 only
     if (blockIdx.x == 1) {
         net_fused_block<HID>(in, in_scale, wn, nwn, bias_all, nbias, meta, layers, C, Hc, Wc, out,
                              inv < 0.0 ? 1.0f : (float)inv);
@@ -1368,17 +1371,22 @@ bool pc_rescale_net_pa_ok(const rte_ctx* c) {
 }
 
 template <int HID, typename TV, int PX>
-static void launch_rescale_net_pa(rte_ctx* c, const ArnoldiArgs& t, TV* w, const double* partial, int nblk,
+static void launch_rescale_net_pa(rte_ctx* c, const ArnoldiArgs* t, TV* w, const double* partial, int nblk,
                                   int nwn, int layers, int Hc, int Wc, float* out, const PassAJob& pj, size_t lds) {
     lds = std::max(lds, pass_a_job_lds<PX>());
     // one block per CU: blocks 0 and 1 plus 254 pass-A blocks
-    hipLaunchKernelGGL((k_rescale_net_pa<HID, TV, PX>), dim3(256), dim3(NET_THREADS), lds, c->stream, t, w, partial,
-                       nblk, c->pc_coarse, c->pc_st + 1, c->pc_wn, nwn, c->pc_bn, c->pc_nbias, c->pc_meta, layers,
-                       c->C, Hc, Wc, out, pj);
+    if (t)
+        hipLaunchKernelGGL((k_rescale_net_pa<HID, TV, PX, true>), dim3(256), dim3(NET_THREADS), lds, c->stream, *t, w,
+                           partial, nblk, c->pc_coarse, c->pc_st + 1, c->pc_wn, nwn, c->pc_bn, c->pc_nbias,
+                           c->pc_meta, layers, c->C, Hc, Wc, out, pj);
+    else
+        hipLaunchKernelGGL((k_rescale_net_pa<HID, TV, PX, false>), dim3(256), dim3(NET_THREADS), lds, c->stream,
+                           ArnoldiArgs{}, w, partial, nblk, c->pc_coarse, c->pc_st + 1, c->pc_wn, nwn, c->pc_bn,
+                           c->pc_nbias, c->pc_meta, layers, c->C, Hc, Wc, out, pj);
 }
 
 template <typename TV>
-int pc_rescale_net_pa(rte_ctx* c, const ArnoldiArgs& t, TV* w, const double* partial, int slot,
+int pc_rescale_net_pa(rte_ctx* c, const ArnoldiArgs* t, TV* w, const double* partial, int slot,
                       const ChanScale& sc, int pack) {
     NetShape sh;
     sh.init(c->C, c->pc_hidden, c->pc_layers);
@@ -1418,7 +1426,7 @@ int pc_rescale_net_pa(rte_ctx* c, const ArnoldiArgs& t, TV* w, const double* par
     template void pc_rescale_pool_arn1<TV>(rte_ctx*, const ArnoldiArgs&, TV*, const double*);                    \
     template void pc_update_pool<TV>(rte_ctx*, TV*, const TV*, int, double*, double*, const ArnoldiArgs&);       \
     template int pc_rescale_net<TV>(rte_ctx*, const ArnoldiArgs&, TV*, const double*, int);                     \
-    template int pc_rescale_net_pa<TV>(rte_ctx*, const ArnoldiArgs&, TV*, const double*, int, const ChanScale&, int);
+    template int pc_rescale_net_pa<TV>(rte_ctx*, const ArnoldiArgs*, TV*, const double*, int, const ChanScale&, int);
 RTE_PC_INST(float)
 RTE_PC_INST(double)
 #undef RTE_PC_INST

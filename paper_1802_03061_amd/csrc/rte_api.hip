@@ -627,7 +627,14 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
             TV* w = V + (size_t)(j + 1) * n;
             // flexible GMRES: w = A z_j with z_j = v_j + s P Y_j formed inside the apply
             if (pc_live) {
-                if (!net_ready && (rc = pc_net_slot(c, j))) return rc;   // else the last launch ran it
+                if (!net_ready && early_a && j == 0) {   // v_0's network beside its pass A
+                    const Apply2DArgs<float> a = args2d<float>(c);
+                    if ((rc = pc_rescale_net_pa<TV>(c, nullptr, vj, c->partial, 0, channel_scale(c, APPLY_A), pack_for(a))))
+                        return rc;
+                    a_ready = true;
+                } else if (!net_ready && (rc = pc_net_slot(c, j))) {   // else the last launch ran it
+                    return rc;
+                }
                 net_ready = false;
                 rc = a_ready ? apply_basis_pc_from_b(c, vj, w, pc_slot(c, j)) : apply_basis_pc(c, vj, w, pc_slot(c, j));
                 a_ready = false;
@@ -672,7 +679,7 @@ static int solve_core_t(rte_ctx* c, const double* b, double tol, int max_iter, d
                     // pass A on the other blocks when early_a)
                     if (early_a) {
                         const Apply2DArgs<float> a = args2d<float>(c);
-                        if ((rc = pc_rescale_net_pa(c, at, w, c->partial, j + 1, channel_scale(c, APPLY_A), pack_for(a))))
+                        if ((rc = pc_rescale_net_pa(c, &at, w, c->partial, j + 1, channel_scale(c, APPLY_A), pack_for(a))))
                             return rc;
                         a_ready = true;
                     } else if ((rc = pc_rescale_net(c, at, w, c->partial, j + 1))) {
